@@ -1,0 +1,300 @@
+"""Seeded synthetic workloads for the MDP domain-decomposition hot path.
+
+This module only *describes* problems: subdomain rectangles, wavenumbers,
+grid sizes, boundary-condition kinds, the exact test solutions and their
+boundary samples.  It holds none of the method's arithmetic (no stencil, no
+auxiliary-problem solve, no extension, no Chebyshev expansion, no least
+squares), so both the CPU oracle and the GPU path can draw their inputs from
+here without sharing any of the computation they are compared on.
+
+Geometry conventions (paper Sec. 3.3-3.4):
+  * a subdomain is an axis-aligned rectangle [x0, x0+lx] x [y0, y0+ly] with a
+    constant wavenumber k (Sec. 3.1 assumes k constant on every subdomain);
+  * its four sides are numbered 0 = bottom (y = y0), 1 = top (y = y0+ly),
+    2 = left (x = x0), 3 = right (x = x0+lx);
+  * a side is either an outer boundary carrying alpha*u + beta*du/dn = phi
+    (eq. helmholtz_robin, outward normal n) or an interface shared with one
+    side of a neighbouring subdomain (Sec. 3.3.2);
+  * the auxiliary grid has n cells per direction.
+
+Test solutions (all homogeneous, f = 0):
+  * plane wave exp(i k (x cos(theta) + y sin(theta)));
+  * the piecewise plane wave of Appendix A: in strip i,
+    a_i exp(i k_i x) + b_i exp(-i k_i x), amplitudes fixed by continuity of u
+    and u_x at every interface with a_1 = 1 (incident wave) and b_N = 0 (no
+    reflection from the right end).  The closed form for two strips printed in
+    the appendix (eq. R_T_solved) does not satisfy its own derivative
+    condition; the amplitudes here come from solving the appendix's linear
+    system directly, which for two strips gives R = (k1-k2)/(k1+k2) and
+    T = 2 k1/(k1+k2).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Tuple
+
+import numpy as np
+
+BOTTOM, TOP, LEFT, RIGHT = 0, 1, 2, 3
+SIDE_NAMES = ("bottom", "top", "left", "right")
+BOUNDARY, INTERFACE = 0, 1
+
+
+@dataclass
+class Subdomain:
+    x0: float
+    y0: float
+    lx: float
+    ly: float
+    k: float
+    n: int
+
+
+@dataclass
+class Side:
+    kind: int                 # BOUNDARY or INTERFACE
+    alpha: float = 0.0        # boundary: alpha*u + beta*du/dn = phi
+    beta: float = 0.0
+    nbr: int = -1             # interface: neighbour subdomain index
+    nbr_side: int = -1        # interface: neighbour's side index
+
+
+@dataclass
+class Workload:
+    name: str
+    subdomains: List[Subdomain]
+    sides: List[List[Side]]   # sides[i][s]
+    m_star: int
+    exact: Callable           # exact(x, y) -> complex ndarray
+    exact_grad: Callable      # exact_grad(x, y) -> (u_x, u_y) complex ndarrays
+    precision: str = "c128"   # compute precision of the AP solves: c128 | c64 | c64r
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+# ----------------------------------------------------------------- solutions
+def plane_wave(k: float, theta: float):
+    c, s = math.cos(theta), math.sin(theta)
+
+    def u(x, y):
+        return np.exp(1j * k * (np.asarray(x) * c + np.asarray(y) * s))
+
+    def grad(x, y):
+        v = u(x, y)
+        return 1j * k * c * v, 1j * k * s * v
+
+    return u, grad
+
+
+def piecewise_amplitudes(interfaces: List[float], ks: List[float]) -> Tuple[np.ndarray, np.ndarray]:
+    """Amplitudes (a_i, b_i) of a_i e^{i k_i x} + b_i e^{-i k_i x} on N strips.
+
+    Unknowns: b_1, a_2, b_2, ..., a_{N-1}, b_{N-1}, a_N (2N-2 of them) with
+    a_1 = 1 and b_N = 0; equations: continuity of u and of u_x at the N-1
+    interfaces x_1 < ... < x_{N-1} (Appendix A, four-strip system and its
+    N-strip generalisation).
+    """
+    N = len(ks)
+    assert len(interfaces) == N - 1
+    if N == 1:
+        return np.array([1.0 + 0j]), np.array([0.0 + 0j])
+    nunk = 2 * N - 2
+
+    def col(i, which):  # which 0 -> a_i, 1 -> b_i ; returns unknown index or None
+        if i == 0 and which == 0:
+            return None
+        if i == N - 1 and which == 1:
+            return None
+        return 2 * i - 1 + which  # b_1 -> 0, a_2 -> 1, b_2 -> 2, ...
+
+    A = np.zeros((nunk, nunk), dtype=complex)
+    rhs = np.zeros(nunk, dtype=complex)
+    for j, xj in enumerate(interfaces):
+        left, right = j, j + 1
+        for row, deriv in ((2 * j, False), (2 * j + 1, True)):
+            for strip, sgn in ((left, 1.0), (right, -1.0)):
+                k = ks[strip]
+                for which, e in ((0, np.exp(1j * k * xj)), (1, np.exp(-1j * k * xj))):
+                    coef = sgn * e
+                    if deriv:
+                        coef *= (1j * k) if which == 0 else (-1j * k)
+                    c = col(strip, which)
+                    if c is None:
+                        if strip == 0 and which == 0:
+                            rhs[row] -= coef  # a_1 = 1 known
+                    else:
+                        A[row, c] += coef
+    sol = np.linalg.solve(A, rhs)
+    a = np.zeros(N, dtype=complex)
+    b = np.zeros(N, dtype=complex)
+    a[0] = 1.0
+    for i in range(N):
+        for which in (0, 1):
+            c = col(i, which)
+            if c is not None:
+                (a if which == 0 else b)[i] = sol[c]
+    return a, b
+
+
+def piecewise_plane_wave(interfaces: List[float], ks: List[float]):
+    a, b = piecewise_amplitudes(interfaces, ks)
+    edges = np.asarray(interfaces, dtype=float)
+    kk = np.asarray(ks, dtype=float)
+
+    def strip_of(x):
+        return np.searchsorted(edges, np.asarray(x, dtype=float), side="right")
+
+    def u(x, y):
+        x = np.asarray(x, dtype=float)
+        i = strip_of(x)
+        return a[i] * np.exp(1j * kk[i] * x) + b[i] * np.exp(-1j * kk[i] * x) + 0 * np.asarray(y)
+
+    def grad(x, y):
+        x = np.asarray(x, dtype=float)
+        i = strip_of(x)
+        ux = 1j * kk[i] * (a[i] * np.exp(1j * kk[i] * x) - b[i] * np.exp(-1j * kk[i] * x))
+        return ux + 0 * np.asarray(y), 0 * ux + 0 * np.asarray(y)
+
+    return u, grad, a, b
+
+
+# ----------------------------------------------------------------- topology
+def grid_topology(nx: int, ny: int, x0: float, y0: float, lx: float, ly: float,
+                  ks: List[float], n: List[int] | int,
+                  bc: Callable[[int, int, int], Tuple[float, float]]):
+    """nx*ny rectangles of size lx*ly, row-major from (x0, y0) (index = iy*nx + ix).
+
+    bc(ix, iy, side) -> (alpha, beta) for the sides on the outer boundary.
+    """
+    subs, sides = [], []
+    for iy in range(ny):
+        for ix in range(nx):
+            i = iy * nx + ix
+            nn = n[i] if isinstance(n, (list, tuple, np.ndarray)) else n
+            subs.append(Subdomain(x0 + ix * lx, y0 + iy * ly, lx, ly, float(ks[i]), int(nn)))
+            ss = []
+            for s in range(4):
+                nb = {BOTTOM: (ix, iy - 1, TOP), TOP: (ix, iy + 1, BOTTOM),
+                      LEFT: (ix - 1, iy, RIGHT), RIGHT: (ix + 1, iy, LEFT)}[s]
+                jx, jy, js = nb
+                if 0 <= jx < nx and 0 <= jy < ny:
+                    ss.append(Side(INTERFACE, nbr=jy * nx + jx, nbr_side=js))
+                else:
+                    a, b = bc(ix, iy, s)
+                    ss.append(Side(BOUNDARY, alpha=a, beta=b))
+            sides.append(ss)
+    return subs, sides
+
+
+def side_points(sd: Subdomain, s: int, t: np.ndarray):
+    """Physical points on side s at affine parameter t in [-1, 1].
+
+    The parameter increases with global x on horizontal sides and with global
+    y on vertical sides, so the two subdomains sharing an interface agree on it.
+    """
+    t = np.asarray(t, dtype=float)
+    if s in (BOTTOM, TOP):
+        x = sd.x0 + 0.5 * (t + 1.0) * sd.lx
+        y = np.full_like(x, sd.y0 if s == BOTTOM else sd.y0 + sd.ly)
+    else:
+        y = sd.y0 + 0.5 * (t + 1.0) * sd.ly
+        x = np.full_like(y, sd.x0 if s == LEFT else sd.x0 + sd.lx)
+    return x, y
+
+
+def outward_normal(s: int) -> Tuple[float, float]:
+    return {BOTTOM: (0.0, -1.0), TOP: (0.0, 1.0), LEFT: (-1.0, 0.0), RIGHT: (1.0, 0.0)}[s]
+
+
+def boundary_samples(w: Workload, i: int, s: int, t: np.ndarray) -> np.ndarray:
+    """phi = alpha*u + beta*du/dn of the exact solution at side parameters t."""
+    sd = w.subdomains[i]
+    side = w.sides[i][s]
+    assert side.kind == BOUNDARY
+    x, y = side_points(sd, s, t)
+    ux, uy = w.exact_grad(x, y)
+    nx, ny = outward_normal(s)
+    return side.alpha * w.exact(x, y) + side.beta * (nx * ux + ny * uy)
+
+
+# ----------------------------------------------------------------- workloads
+def config_two_rect(n: int = 64, k: float = 10.0, m_star: int = 16, precision: str = "c128") -> Workload:
+    """Unit square as 2x1 rectangles [0,.5]x[0,1] and [.5,1]x[0,1]; Dirichlet
+    data of the plane wave at angle pi/6 on the six outer sides."""
+    subs, sides = grid_topology(2, 1, 0.0, 0.0, 0.5, 1.0, [k, k], n, lambda ix, iy, s: (1.0, 0.0))
+    u, g = plane_wave(k, math.pi / 6)
+    return Workload("two_rect_k10_n%d" % n, subs, sides, m_star, u, g, precision,
+                    notes="2x1 rectangles, k=%g, n=%d, M*=%d, Dirichlet, plane wave pi/6" % (k, n, m_star))
+
+
+def config_cross_point(n: int = 256, k: float = 50.0, m_star: int = 32, seed: int = 2,
+                       precision: str = "c64r") -> Workload:
+    """Unit square as 2x2 squares of side 0.5 (one interior cross-point);
+    Dirichlet on the x = 0 and x = 1 sides, Neumann on y = 0 and y = 1; plane
+    wave at a seed-drawn angle theta = 2*pi*U[0,1)."""
+    rng = np.random.default_rng(seed)
+    theta = 2.0 * math.pi * float(rng.random())
+
+    def bc(ix, iy, s):
+        return (1.0, 0.0) if s in (LEFT, RIGHT) else (0.0, 1.0)
+
+    subs, sides = grid_topology(2, 2, 0.0, 0.0, 0.5, 0.5, [k] * 4, n, bc)
+    u, g = plane_wave(k, theta)
+    w = Workload("cross_point_k50_n%d" % n, subs, sides, m_star, u, g, precision,
+                 notes="2x2 squares, k=%g, n=%d, M*=%d, mixed Dirichlet/Neumann, theta=%.6f (seed %d)"
+                 % (k, n, m_star, theta, seed))
+    w.extra["theta"] = theta
+    return w
+
+
+def config_transmission(n: int = 1024, ks=(20.0, 200.0, 20.0, 200.0), m_star: int = 64,
+                        precision: str = "c64r") -> Workload:
+    """Unit square as 4 vertical strips [i/4,(i+1)/4]x[0,1] with alternating
+    wavenumbers; exact piecewise plane wave; Dirichlet data on the outer sides."""
+    N = len(ks)
+    subs, sides = grid_topology(N, 1, 0.0, 0.0, 1.0 / N, 1.0, list(ks), n, lambda ix, iy, s: (1.0, 0.0))
+    u, g, a, b = piecewise_plane_wave([(i + 1) / N for i in range(N - 1)], list(ks))
+    w = Workload("transmission_%dstrips_n%d" % (N, n), subs, sides, m_star, u, g, precision,
+                 notes="%d strips, k=%s, n=%d, M*=%d, Dirichlet, piecewise plane wave" % (N, list(ks), n, m_star))
+    w.extra["a"], w.extra["b"] = a, b
+    return w
+
+
+def config_paper_base(n: int = 64, k: float = 13.0, m_star: int = 40) -> Workload:
+    """Single square of side 2 centred at the origin, Robin alpha = beta = 1,
+    plane wave exp(i k (x+y)/sqrt 2) (the single-subdomain base case of Sec. 4.1)."""
+    subs, sides = grid_topology(1, 1, -1.0, -1.0, 2.0, 2.0, [k], n, lambda ix, iy, s: (1.0, 1.0))
+    u, g = plane_wave(k, math.pi / 4)
+    return Workload("paper_base_n%d" % n, subs, sides, m_star, u, g, "c128")
+
+
+def config_paper_two(n: int = 64, k: float = 13.0, m_star: int = 40) -> Workload:
+    """Two squares of side 2: the first centred at the origin, the second to its
+    right (interface at x = 1); Robin alpha = beta = 1; plane wave at pi/4."""
+    subs, sides = grid_topology(2, 1, -1.0, -1.0, 2.0, 2.0, [k, k], n, lambda ix, iy, s: (1.0, 1.0))
+    u, g = plane_wave(k, math.pi / 4)
+    return Workload("paper_two_n%d" % n, subs, sides, m_star, u, g, "c128")
+
+
+def config_paper_jump(n: int = 64, k1: float = 5.0, k2: float = 13.0, m_star: int = 40) -> Workload:
+    """Two squares of side 2 (interface at x = 1) with k1 | k2, incident wave
+    e^{i k1 x}, Dirichlet data (the two-subdomain transmission case of Sec. 4.2)."""
+    subs, sides = grid_topology(2, 1, -1.0, -1.0, 2.0, 2.0, [k1, k2], n, lambda ix, iy, s: (1.0, 0.0))
+    u, g, a, b = piecewise_plane_wave([1.0], [k1, k2])
+    return Workload("paper_jump_%g_%g_n%d" % (k1, k2, n), subs, sides, m_star, u, g, "c128")
+
+
+WORKLOADS = {
+    "two_rect": config_two_rect,
+    "cross_point": config_cross_point,
+    "transmission": config_transmission,
+}
+
+
+def random_rhs(shape, seed: int, complex_: bool = True) -> np.ndarray:
+    """Seeded standard-normal test data (real or complex)."""
+    rng = np.random.default_rng(seed)
+    if complex_:
+        return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    return rng.standard_normal(shape)
