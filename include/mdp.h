@@ -1,0 +1,184 @@
+/*
+ * mdp.h -- C-ABI of the MI355X (gfx950) library for the hot path of the
+ * Method of Difference Potentials (MDP) applied to non-overlapping domain
+ * decomposition of the Helmholtz equation
+ *     Delta u + k^2 u = f  in Omega,   alpha u + beta du/dn = phi  on dOmega
+ * (North, Tsynkov & Turkel, Sec. 3, eq. helmholtz_physical), here with f = 0.
+ *
+ * The three calls follow the algorithm summary of Sec. 3.5:
+ *   step 1b  mdp_build_projector  -- Q^(i) = [(P_gamma - I) Ex Psi_j], one
+ *                                    auxiliary-problem (AP) solve per column;
+ *   step 2   mdp_solve_interface  -- boundary and interface conditions
+ *                                    eliminated in coefficient space, least
+ *                                    squares for the coefficients c;
+ *   step 3   mdp_reconstruct      -- u = P_{N+} Ex(c) on each subdomain.
+ * mdp_ap_solve exposes G^(h), the AP solve itself (Sec. 3.2.1), on a batch of
+ * right-hand sides.
+ *
+ * Conventions common to every call
+ *   - Every function returns an mdp_status (0 = success).  On failure nothing
+ *     has been launched and mdp_last_error(ctx) describes the cause; no C++
+ *     exception crosses this interface.
+ *   - "device" pointers are HIP device allocations on the context's device;
+ *     "host" pointers are ordinary host memory.  Output buffers are owned by
+ *     the caller; handles (mdp_ctx, mdp_projector) are owned by the library.
+ *   - stream is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  Work is enqueued asynchronously on it unless stated otherwise.
+ *   - Complex numbers are interleaved (re, im) FP64 pairs.
+ *   - Grids: n cells per direction of the auxiliary square (n even, n >= 8);
+ *     node (m, q), m, q = 0..n, sits at x = xa + m h, y = ya + q h with
+ *     h = side/n.  A grid function is stored as (n+1)*(n+1) values, index
+ *     m*(n+1) + q (x-major, y fastest).
+ *   - Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef MDP_H
+#define MDP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } mdp_c128;
+
+typedef enum {
+    MDP_OK = 0,
+    MDP_ERR_ARG = -1,        /* invalid argument (sizes, null pointers, topology) */
+    MDP_ERR_HIP = -2,        /* a HIP runtime call failed */
+    MDP_ERR_OOM = -3,        /* device allocation failed */
+    MDP_ERR_SINGULAR = -4,   /* an AP mode pivot or the interface factor broke down */
+    MDP_ERR_NONFINITE = -5,  /* non-finite input data */
+    MDP_ERR_NODEVICE = -6    /* no HIP device / bad device index */
+} mdp_status;
+
+/* Arithmetic of the AP solves.  The interface least squares is FP64 always. */
+typedef enum {
+    MDP_C128 = 0,         /* complex FP64 throughout */
+    MDP_C64 = 1,          /* complex FP32 AP solves (FP32 MFMA, FP32 accumulation) */
+    MDP_C64_REFINED = 2   /* FP32 solve + one FP64 residual and FP32 correction solve */
+} mdp_precision;
+
+/* One subdomain: the rectangle [x0, x0+lx] x [y0, y0+ly] with constant
+ * wavenumber k (Sec. 3.1 assumes k constant on every subdomain).  Its
+ * auxiliary domain is the square of side 1.1*max(lx, ly) centred on it, with
+ * u = 0 on its top and bottom sides and the Sommerfeld-type conditions
+ * u_x +- i k u = 0 on its left and right sides (eq. auxiliary_problem). */
+typedef struct {
+    double x0, y0, lx, ly;
+    double k;
+    int n;
+} mdp_subdomain;
+
+/* One side of one subdomain; sides are numbered 0 bottom, 1 top, 2 left, 3 right. */
+typedef struct {
+    int kind;              /* 0 = outer boundary, 1 = interface */
+    double alpha, beta;    /* boundary: alpha u + beta du/dn = phi, (alpha, beta) != (0, 0)
+                              (eq. helmholtz_robin, Sec. 3.3.1; n = outward normal) */
+    const mdp_c128* d;     /* boundary: host, M* Chebyshev coefficients of phi in the side
+                              parameter t (see mdp_cheb_coeffs); ignored for interfaces */
+    int nbr, nbr_side;     /* interface: neighbouring subdomain and its side (Sec. 3.3.2);
+                              the two sides must be the same segment */
+} mdp_side;
+
+typedef struct mdp_ctx mdp_ctx;
+typedef struct mdp_projector mdp_projector;
+
+/* Create a context on HIP device `device`.  *ctx receives the handle.
+ * Errors: MDP_ERR_NODEVICE, MDP_ERR_HIP, MDP_ERR_ARG (ctx == NULL). */
+int mdp_create(mdp_ctx** ctx, int device);
+
+/* Destroy a context, its workspaces and its projector cache (projectors
+ * still held by the caller stay valid until released). NULL is a no-op. */
+void mdp_destroy(mdp_ctx* ctx);
+
+/* Message of the last failure on ctx (or of the last mdp_create failure when
+ * ctx is NULL).  Valid until the next call on the same context. */
+const char* mdp_last_error(const mdp_ctx* ctx);
+
+/* Step 1b of Sec. 3.5: Q = [(P_gamma - I) Ex Psi^(0)_1..4M*, (P_gamma - I) Ex Psi^(1)_1..4M*]
+ * (eq. Q_construction), where Psi_j are Chebyshev polynomials T_0..T_{M*-1}
+ * on each side (Sec. 3.2.4, eq. Psi_def) and Ex is the equation-based
+ * extension through rho^4 (Sec. 3.2.3, eqs. general_extension, cartesian_extension).
+ * Column col = kind*4M* + side*M* + j (kind 0 Dirichlet, 1 Neumann).
+ * Each column costs one AP solve (P_gamma is applied as
+ * (P_gamma - I) xi = -Tr_gamma G^(h)(L^(h) w |_{M+}), eqs. Potential_def, def_Pgamma).
+ * All 8M* solves run as one batch on `stream`.
+ * Projectors are cached in the context by (lx, ly, n, k, M*, precision) and
+ * reference counted: a cache hit returns the same handle with its count
+ * raised (Sec. 3.5: Q is computed once per distinct wavenumber).
+ * Errors: MDP_ERR_ARG (n odd or < 8, M* < 1, lx/ly <= 0, subdomain not inside
+ * its AP interior), MDP_ERR_NONFINITE (k not finite or <= 0), MDP_ERR_SINGULAR
+ * (an AP mode factor breaks down), MDP_ERR_OOM, MDP_ERR_HIP. */
+int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int precision,
+                        void* stream, mdp_projector** out);
+
+/* Read-only view of a projector.  n_gamma = |gamma|; gamma_mq (host, 2*n_gamma
+ * ints) lists gamma nodes as (m, q) pairs in increasing lexicographic (m, q)
+ * order; q_dev (device, n_gamma x 8M* complex, column-major, leading
+ * dimension n_gamma) is Q.  Any output pointer may be NULL.  The views stay
+ * valid while the projector is held.  Errors: MDP_ERR_ARG (P == NULL). */
+int mdp_projector_info(const mdp_projector* P, int* n_gamma, const int** gamma_mq,
+                       const mdp_c128** q_dev);
+
+/* Drop one reference; the projector is freed with its last reference (the
+ * context's cache holds one of its own until mdp_destroy). NULL is a no-op. */
+void mdp_projector_release(mdp_projector* P);
+
+/* Step 2 of Sec. 3.5.  subs (host, n_sub) are the subdomains; P[i] is
+ * subdomain i's projector, built for a rectangle of the same size, n and k
+ * (entries may alias: Q does not depend on the position of the rectangle);
+ * sides is a host array of 4*n_sub entries, sides[4*i + s].  The boundary
+ * conditions (eq. BC_coefficients) and interface conditions
+ * (eq. transmission_coefficients) are resolved by elimination (Sec. 3.3.3),
+ * giving the reduced system Qbar c = Fbar with sum|gamma_i| rows and
+ * 4*n_sub*M* columns, which is solved in the least-squares sense (steps
+ * 2b-2c) in FP64 on the device.
+ * c_out (device, caller-owned, 8M* complex per subdomain, subdomain-major, each
+ * in the column order of Q) receives every coefficient, known and solved.
+ * rel_residual_out (host, may be NULL) = ||Qbar c - Fbar|| / ||Fbar||;
+ * cond_estimate_out (host, may be NULL) estimates the 2-norm condition number
+ * of the column-equilibrated Qbar.  The call synchronises `stream` because it
+ * returns host scalars.
+ * Errors: MDP_ERR_ARG (inconsistent topology, mismatched interface segments,
+ * alpha = beta = 0, M* or rectangle different from the projectors', null d),
+ * MDP_ERR_NONFINITE, MDP_ERR_SINGULAR (the factor of Qbar broke down), MDP_ERR_OOM, MDP_ERR_HIP. */
+int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs,
+                        const mdp_projector* const* P, const mdp_side* sides, int m_star, void* stream,
+                        mdp_c128* c_out, double* rel_residual_out, double* cond_estimate_out);
+
+/* Step 3 of Sec. 3.5 for n_sub subdomains: xi_gamma = Ex(sum_j c_j Psi_j) and
+ * u = P_{N+} xi_gamma = w - G^(h)(L^(h) w |_{M+}) (eqs. Potential_def,
+ * potential_solution_homo).  c (device) holds 8M* coefficients per subdomain
+ * as written by mdp_solve_interface; u_out (device, caller-owned) receives
+ * subdomain i's grid function at offset sum_{l<i} (n_l+1)^2 (complex); it is
+ * the solution on N+ and the difference potential elsewhere.  Subdomains
+ * sharing a projector are solved in one batch.
+ * Errors: MDP_ERR_ARG, MDP_ERR_OOM, MDP_ERR_HIP. */
+int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P,
+                    const mdp_c128* c, void* stream, mdp_c128* u_out);
+
+/* G^(h) of Sec. 3.2.1 on `batch` right-hand sides: solves the discrete AP
+ * (eq. discrete_AP: the compact scheme at interior nodes, u = 0 on q = 0, n,
+ * fourth-order Sommerfeld-type rows at m = 0, n with zero right-hand side)
+ * for g (device, batch grid functions; only interior nodes 1 <= m, q <= n-1
+ * are read) into u (device, batch grid functions, zero on q = 0, n).
+ * h = grid step, k = wavenumber.  Errors: MDP_ERR_ARG, MDP_ERR_NONFINITE,
+ * MDP_ERR_SINGULAR, MDP_ERR_OOM, MDP_ERR_HIP. */
+int mdp_ap_solve(mdp_ctx* ctx, int n, double h, double k, int precision, int batch,
+                 const mdp_c128* g, mdp_c128* u, void* stream);
+
+/* Host helper (Sec. 3.3.1: phi expanded in the same basis): t[i] =
+ * cos(pi (i + 1/2)/M*), i = 0..M*-1, the sample points of mdp_cheb_coeffs. */
+int mdp_cheb_points(int m_star, double* t);
+
+/* Host helper: coefficients d_j (j = 0..M*-1) of the polynomial of degree < M*
+ * interpolating samples[i] = phi(t_i) at the points of mdp_cheb_points,
+ * d_j = (2 - delta_j0)/M* sum_i phi(t_i) T_j(t_i).  Errors: MDP_ERR_ARG. */
+int mdp_cheb_coeffs(int m_star, const mdp_c128* samples, mdp_c128* d);
+
+/* Library version string (static). */
+const char* mdp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDP_H */

@@ -1,0 +1,149 @@
+// Internal declarations of the MDP library (host orchestration + HIP kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mdp.h"
+
+namespace mdp {
+
+// ----------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define MDP_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            throw ::mdp::Error(e_ == hipErrorOutOfMemory ? MDP_ERR_OOM : MDP_ERR_HIP,        \
+                               std::string(#call) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+// ----------------------------------------------------------------- device buffer
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t b) { alloc(b); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t b) {
+        release();
+        if (b == 0) return;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error(MDP_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+        }
+        bytes = b;
+    }
+    // grow-only reallocation (contents are not preserved)
+    void reserve(size_t b) { if (b > bytes) alloc(b); }
+    void release() { if (p) (void)hipFree(p); p = nullptr; bytes = 0; }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ----------------------------------------------------------------- geometry (host)
+// Auxiliary grid of one subdomain and its grid sets (paper Sec. 3.2.2).
+struct Geometry {
+    double x0, y0, lx, ly;      // subdomain rectangle
+    int n;                      // cells per direction of the auxiliary square
+    double L, h, xa, ya;        // side, step, lower-left corner of the AP square
+    int m_lo, m_hi, q_lo, q_hi; // M+ = [m_lo, m_hi] x [q_lo, q_hi] (inclusive)
+    int n_gamma;
+    std::vector<int> gm, gq;    // gamma nodes, increasing (m, q)
+    std::vector<int> side;      // side of each gamma node (0 bottom, 1 top, 2 left, 3 right)
+    std::vector<double> rho;    // signed distance to that side (> 0 outside)
+    std::vector<double> t;      // side parameter in [-1, 1] (unclamped)
+    std::vector<double> slen;   // side length
+    std::vector<int> gmq;       // interleaved (m, q) pairs, for the public view
+};
+
+Geometry make_geometry(double x0, double y0, double lx, double ly, int n);
+
+// Extension matrix E = Ex^(H) Psi (|gamma| x 8M*, column-major, real FP64).
+std::vector<double> extension_matrix(const Geometry& g, double k, int m_star);
+
+// ----------------------------------------------------------------- folded sine layout
+// For even n = 2p the type-I sine transform splits by the parity of the mode j:
+// S(n-q, j) = (-1)^(j+1) S(q, j).  A grid row of n-1 interior values is stored
+// "folded" as two column blocks:
+//   block 1 (width P1 >= p):   e_q = g_q + g_{n-q} (q < p), e_p = g_p   <-> odd modes  j = 2c+1
+//   block 2 (width P2 >= p-1): o_q = g_q - g_{n-q} (q < p)              <-> even modes j = 2(c-P1)+2
+// and the transform is a block-diagonal product of the two blocks with the
+// corresponding sine sub-matrices.  Padding columns are zero.
+struct Fold {
+    int n = 0, p = 0, P1 = 0, P2 = 0, W = 0;
+    static Fold make(int n);
+};
+
+// ----------------------------------------------------------------- kernel launchers (kernels_*.hip)
+struct StencilCoef { double c0, ce, cc; };
+struct EndRowCoef { double wD, wD2, wA, wA2, k; };
+
+struct APDevPlan;  // forward
+
+// RHS sources of an AP batch (all evaluated in FP64)
+enum class Src { GRID = 0, STENCIL_GRID = 1, STENCIL_E = 2 };
+
+struct SrcDesc {
+    Src kind;
+    const double* grid;   // GRID / STENCIL_GRID: complex interleaved grids, (n+1)^2 each, stride grid_stride (complex elems)
+    long grid_stride;
+    const double* E;      // STENCIL_E: column-major |gamma| x ncols real
+    int ldE;
+    int col0;             // STENCIL_E: first column of this batch
+    const int* gidx;      // (n+1)^2 map node -> gamma index or -1
+    int m_lo, m_hi, q_lo, q_hi;  // M+ box (STENCIL_*)
+};
+
+template <class T>
+void launch_fold_rhs(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, bool cplx, T* out,
+                     hipStream_t st);
+template <class T>
+void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st);
+template <class T>
+void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* colc, int n, const Fold& f, int R,
+                    hipStream_t st);
+void launch_residual(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, EndRowCoef ec, int R, bool cplx_src,
+                     const float* u32, float* r_out, hipStream_t st);
+template <class T>
+void launch_gather_q(const T* u, const float* du, int n, const Fold& f, const int* gm, const int* gq, int ng, int R,
+                     double* Q, int ldq, int col0, hipStream_t st);
+template <class T>
+void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, int R, const double* w, long w_stride,
+                        double* out, long out_stride, hipStream_t st);
+void launch_extend_density(const double* E, int ng, int ncol, const double* c, int R, const int* gm,
+                           const int* gq, int n, double* w, long w_stride, hipStream_t st);
+
+// interface least squares
+void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const double2* A, int lda,
+                  const double2* B, int ldb, double2 beta, double2* C, int ldc, DevBuf& ws, hipStream_t st);
+void launch_chol_block(const double2* G, int ldg, int nb, double shift, double2* L, int ldl, double2* Linv, int ldi,
+                       int* info, int base, hipStream_t st);
+void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
+                          const int4* colmap, const double2* coefs, int ncol, double2* Qbar, int ldq, hipStream_t st);
+void launch_known_rhs(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
+                      const int* kcol, const double2* kval, const int* koff, double2* F, hipStream_t st);
+void launch_col_norms(const double2* A, int m, int n, int lda, double* out, hipStream_t st);
+void launch_scale_cols(double2* A, int m, int n, int lda, const double* s, int invert, hipStream_t st);
+void launch_fill(double* p, long n, double v, hipStream_t st);
+
+}  // namespace mdp

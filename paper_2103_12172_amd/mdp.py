@@ -1,0 +1,251 @@
+"""Thin Python binding of libmdp (include/mdp.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts Python
+arguments to the C-ABI's plain pointers and sizes.  Device buffers are torch
+tensors on the GPU (their data_ptr() is passed through), streams are torch
+streams.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdp.so")
+
+MDP_OK, MDP_ERR_ARG, MDP_ERR_HIP, MDP_ERR_OOM, MDP_ERR_SINGULAR, MDP_ERR_NONFINITE, MDP_ERR_NODEVICE = 0, -1, -2, -3, -4, -5, -6
+MDP_C128, MDP_C64, MDP_C64_REFINED = 0, 1, 2
+PRECISIONS = {"c128": MDP_C128, "c64": MDP_C64, "c64r": MDP_C64_REFINED}
+
+STATUS_NAMES = {0: "MDP_OK", -1: "MDP_ERR_ARG", -2: "MDP_ERR_HIP", -3: "MDP_ERR_OOM", -4: "MDP_ERR_SINGULAR",
+                -5: "MDP_ERR_NONFINITE", -6: "MDP_ERR_NODEVICE"}
+
+EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector", "mdp_projector_info",
+            "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
+            "mdp_cheb_coeffs", "mdp_version"]
+
+
+class MdpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class C128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Subdomain(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("lx", ctypes.c_double),
+                ("ly", ctypes.c_double), ("k", ctypes.c_double), ("n", ctypes.c_int)]
+
+
+class Side(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("d", ctypes.POINTER(C128)), ("nbr", ctypes.c_int), ("nbr_side", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmdp.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libmdp.so not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.mdp_create.argtypes = [ctypes.POINTER(vp), ip]
+    lib.mdp_create.restype = ip
+    lib.mdp_destroy.argtypes = [vp]
+    lib.mdp_destroy.restype = None
+    lib.mdp_last_error.argtypes = [vp]
+    lib.mdp_last_error.restype = ctypes.c_char_p
+    lib.mdp_build_projector.argtypes = [vp, ctypes.POINTER(Subdomain), ip, ip, vp, ctypes.POINTER(vp)]
+    lib.mdp_build_projector.restype = ip
+    lib.mdp_projector_info.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ctypes.POINTER(ip)), ctypes.POINTER(vp)]
+    lib.mdp_projector_info.restype = ip
+    lib.mdp_projector_release.argtypes = [vp]
+    lib.mdp_projector_release.restype = None
+    lib.mdp_solve_interface.argtypes = [vp, ip, ctypes.POINTER(Subdomain), ctypes.POINTER(vp), ctypes.POINTER(Side),
+                                        ip, vp, vp, ctypes.POINTER(dp), ctypes.POINTER(dp)]
+    lib.mdp_solve_interface.restype = ip
+    lib.mdp_reconstruct.argtypes = [vp, ip, ctypes.POINTER(vp), vp, vp, vp]
+    lib.mdp_reconstruct.restype = ip
+    lib.mdp_ap_solve.argtypes = [vp, ip, dp, dp, ip, ip, vp, vp, vp]
+    lib.mdp_ap_solve.restype = ip
+    lib.mdp_cheb_points.argtypes = [ip, ctypes.POINTER(dp)]
+    lib.mdp_cheb_points.restype = ip
+    lib.mdp_cheb_coeffs.argtypes = [ip, ctypes.POINTER(C128), ctypes.POINTER(C128)]
+    lib.mdp_cheb_coeffs.restype = ip
+    lib.mdp_version.argtypes = []
+    lib.mdp_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Context:
+    """Owns an mdp_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        rc = lib.mdp_create(ctypes.byref(h), device)
+        if rc != MDP_OK:
+            raise MdpError(rc, lib.mdp_last_error(None).decode())
+        self.handle = h
+        self.lib = lib
+        self.device = device
+
+    def check(self, rc: int):
+        if rc != MDP_OK:
+            raise MdpError(rc, self.lib.mdp_last_error(self.handle).decode())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.mdp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceArray:
+    """__cuda_array_interface__ view of library-owned device memory."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "version": 3, "strides": None}
+
+
+class Projector:
+    """A reference to a cached mdp_projector (released on close/garbage collection)."""
+
+    def __init__(self, ctx: Context, handle: ctypes.c_void_p, m_star: int):
+        self.ctx, self.handle, self.m_star = ctx, handle, m_star
+
+    def info(self):
+        ng = ctypes.c_int()
+        gmq = ctypes.POINTER(ctypes.c_int)()
+        q = ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.mdp_projector_info(self.handle, ctypes.byref(ng), ctypes.byref(gmq),
+                                                       ctypes.byref(q)))
+        n = ng.value
+        mq = np.ctypeslib.as_array(gmq, shape=(2 * n,)).reshape(n, 2).copy()
+        return n, mq, q.value
+
+    def q_tensor(self):
+        """Q as a torch complex128 tensor (n_gamma x 8M*), copied from the library's buffer."""
+        import torch
+        n, _, ptr = self.info()
+        view = _DeviceArray(ptr, (8 * self.m_star, n), "<c16")
+        t = torch.as_tensor(view, device="cuda:%d" % self.ctx.device)
+        return t.T.clone()
+
+    def release(self):
+        if self.handle:
+            self.ctx.lib.mdp_projector_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def mdp_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def mdp_build_projector(ctx: Context, sd: Subdomain, m_star: int, precision, stream=None) -> Projector:
+    prec = PRECISIONS.get(precision, precision)
+    h = ctypes.c_void_p()
+    ctx.check(ctx.lib.mdp_build_projector(ctx.handle, ctypes.byref(sd), m_star, prec,
+                                          ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
+    return Projector(ctx, h, m_star)
+
+
+def make_sides(sides: Sequence[Side], d_arrays: Sequence[Optional[np.ndarray]]):
+    """Side structs with their boundary coefficient arrays attached (kept alive by the returned holder)."""
+    arr = (Side * len(sides))()
+    keep = []
+    for i, (s, d) in enumerate(zip(sides, d_arrays)):
+        arr[i] = s
+        if d is not None:
+            buf = (C128 * len(d))(*[C128(float(v.real), float(v.imag)) for v in d])
+            keep.append(buf)
+            arr[i].d = ctypes.cast(buf, ctypes.POINTER(C128))
+        else:
+            arr[i].d = ctypes.POINTER(C128)()
+    return arr, keep
+
+
+def mdp_solve_interface(ctx: Context, subs: Sequence[Subdomain], projectors: Sequence[Projector], sides,
+                        d_arrays, m_star: int, c_out, stream=None, want_cond: bool = True):
+    n = len(subs)
+    sub_arr = (Subdomain * n)(*subs)
+    parr = (ctypes.c_void_p * n)(*[p.handle.value for p in projectors])
+    side_arr, keep = make_sides(sides, d_arrays)
+    rel = ctypes.c_double()
+    cond = ctypes.c_double()
+    ctx.check(ctx.lib.mdp_solve_interface(ctx.handle, n, sub_arr, parr, side_arr, m_star,
+                                          ctypes.c_void_p(_stream_ptr(stream)), ctypes.c_void_p(c_out.data_ptr()),
+                                          ctypes.byref(rel), ctypes.byref(cond) if want_cond else None))
+    del keep
+    return rel.value, (cond.value if want_cond else None)
+
+
+def mdp_reconstruct(ctx: Context, projectors: Sequence[Projector], c, u_out, stream=None):
+    n = len(projectors)
+    parr = (ctypes.c_void_p * n)(*[p.handle.value for p in projectors])
+    ctx.check(ctx.lib.mdp_reconstruct(ctx.handle, n, parr, ctypes.c_void_p(c.data_ptr()),
+                                      ctypes.c_void_p(_stream_ptr(stream)), ctypes.c_void_p(u_out.data_ptr())))
+
+
+def mdp_ap_solve(ctx: Context, n: int, h: float, k: float, precision, g, u, stream=None):
+    prec = PRECISIONS.get(precision, precision)
+    batch = g.numel() // ((n + 1) * (n + 1))
+    ctx.check(ctx.lib.mdp_ap_solve(ctx.handle, n, float(h), float(k), prec, batch, ctypes.c_void_p(g.data_ptr()),
+                                   ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def mdp_cheb_points(m_star: int) -> np.ndarray:
+    lib = load()
+    t = (ctypes.c_double * m_star)()
+    rc = lib.mdp_cheb_points(m_star, t)
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_cheb_points")
+    return np.array(t[:])
+
+
+def mdp_cheb_coeffs(samples: np.ndarray) -> np.ndarray:
+    lib = load()
+    m = len(samples)
+    s = (C128 * m)(*[C128(float(v.real), float(v.imag)) for v in samples])
+    d = (C128 * m)()
+    rc = lib.mdp_cheb_coeffs(m, s, d)
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_cheb_coeffs")
+    return np.array([complex(v.re, v.im) for v in d])
+
+
+def version() -> str:
+    return load().mdp_version().decode()
