@@ -175,6 +175,25 @@ int mdp_cheb_points(int m_star, double* t);
  * d_j = (2 - delta_j0)/M* sum_i phi(t_i) T_j(t_i).  Errors: MDP_ERR_ARG. */
 int mdp_cheb_coeffs(int m_star, const mdp_c128* samples, mdp_c128* d);
 
+/* Drop the context's own reference to every cached projector (projectors the
+ * caller still holds stay valid) so that the next mdp_build_projector
+ * recomputes Q.  AP plans (sine matrices, per-mode tridiagonal factors) and
+ * workspaces are kept.  Errors: MDP_ERR_ARG (ctx == NULL). */
+int mdp_cache_clear(mdp_ctx* ctx);
+
+/* Per-launch profiling of the context's kernels: while enabled, every kernel
+ * launch of the hot path is bracketed by HIP events recorded on the stream it
+ * runs on and tagged with its kernel class and the launch's algorithmic flops
+ * and bytes.  enable != 0 starts (and clears) the record, 0 stops it.
+ * Errors: MDP_ERR_ARG. */
+int mdp_profile_enable(mdp_ctx* ctx, int enable);
+
+/* JSON summary of the records since the last enable, one entry per kernel
+ * class: {"class": {"count": c, "total_ms": t, "flops": f, "bytes": b}, ...},
+ * written to buf (host, NUL-terminated, at most buflen bytes).  Synchronises
+ * the device.  Errors: MDP_ERR_ARG (null or too small buffer), MDP_ERR_HIP. */
+int mdp_profile_report(mdp_ctx* ctx, char* buf, int buflen);
+
 /* Library version string (static). */
 const char* mdp_version(void);
 

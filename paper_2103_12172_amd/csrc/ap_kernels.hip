@@ -64,27 +64,24 @@ struct SrcEval {
 // out row (b, m): block 1 col c = q-1 (q = 1..p):   e_q = g_q + g_{n-q} (e_p = g_p)
 //                 block 2 col c = P1+q-1 (q < p):   o_q = g_q - g_{n-q}
 template <class T>
-__global__ void fold_rhs_kernel(SrcEval ev, Fold f, int R, int planes, T* __restrict__ out) {
+__global__ void __launch_bounds__(256)
+fold_rhs_kernel(SrcEval ev, Fold f, int planes, T* __restrict__ out) {
     const int n = f.n, p = f.p, W = f.W;
-    const long total = (long)R * (n + 1) * W;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % W);
-        const long rm = i / W;
-        const int m = (int)(rm % (n + 1));
-        const int b = (int)(rm / (n + 1));
-        C64 v = {0.0, 0.0};
-        if (c < f.P1) {
-            const int q = c + 1;
-            if (q < p) v = cadd(ev.rhs(b, m, q), ev.rhs(b, m, n - q));
-            else if (q == p) v = ev.rhs(b, m, p);
-        } else {
-            const int q = c - f.P1 + 1;
-            if (q < p) v = csub(ev.rhs(b, m, q), ev.rhs(b, m, n - q));
-        }
-        const long o = (((long)b * planes) * (n + 1) + m) * W + c;
-        out[o] = (T)v.re;
-        if (planes == 2) out[o + (long)(n + 1) * W] = (T)v.im;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y, b = blockIdx.z;
+    if (c >= W) return;
+    C64 v = {0.0, 0.0};
+    if (c < f.P1) {
+        const int q = c + 1;
+        if (q < p) v = cadd(ev.rhs(b, m, q), ev.rhs(b, m, n - q));
+        else if (q == p) v = ev.rhs(b, m, p);
+    } else {
+        const int q = c - f.P1 + 1;
+        if (q < p) v = csub(ev.rhs(b, m, q), ev.rhs(b, m, n - q));
     }
+    const long o = (((long)b * planes) * (n + 1) + m) * W + c;
+    out[o] = (T)v.re;
+    if (planes == 2) out[o + (long)(n + 1) * W] = (T)v.im;
 }
 
 // ------------------------------------------------------------------ tridiagonal solve per mode
@@ -211,144 +208,143 @@ __device__ inline C64 unfold_c(const T* __restrict__ u, const Fold& f, int b, in
 }
 
 // ------------------------------------------------------------------ residual (refinement)
-// r = g - A u32 over every row of the discrete AP, in FP64:
-//   interior rows (1 <= m <= n-1): g(m,q) - L^(h) u32 (u = 0 at q = 0, n);
-//   end rows m = 0, n: -(Sommerfeld-type row applied to u32) (zero right-hand side).
-// Written folded (like fold_rhs) as FP32 real/imaginary planes.
-struct EndRow {
-    EndRowCoef ec;
-    __device__ inline C64 apply(const float* u, const Fold& f, int b, int m_out, int m_in, double sgn, int q) const {
-        // D = u(m_out) - u(m_in), A = (u(m_out) + u(m_in))/2 at q-1, q, q+1; second difference in y
-        C64 D[3], Av[3];
-        for (int t = -1; t <= 1; ++t) {
-            C64 uo = unfold_c(u, f, b, m_out, q + t), ui = unfold_c(u, f, b, m_in, q + t);
-            D[t + 1] = csub(uo, ui);
-            Av[t + 1] = cscale(cadd(uo, ui), 0.5);
+// r = g - A u32 over every row of the discrete AP, in FP64, directly in folded
+// coordinates.  The folded synthesis rows hold A_q = (u_q + u_{n-q})/2 and
+// B_q = (u_q - u_{n-q})/2; every row of the AP is symmetric under q -> n-q, so
+//   r_q + r_{n-q} = (g_q + g_{n-q}) - 2 (Op A)_q   (q < p),  r_p = g_p - (Op A)_p,
+//   r_q - r_{n-q} = (g_q - g_{n-q}) - 2 (Op B)_q   (q < p),
+// where Op is the interior 9-node stencil (1 <= m <= n-1) or the Sommerfeld-type
+// end row (m = 0, n), applied to the A block extended evenly about q = p
+// (A_0 = 0, A_{p+1} = A_{p-1}) or to the B block extended oddly (B_0 = B_p = 0).
+// Output: the folded residual as FP32 real/imaginary planes.
+struct FoldedField {
+    const float* __restrict__ u;
+    Fold f;
+    // value of plane pl of the even (blk 0) or odd (blk 1) field at (m, q), q = 0..p+1
+    __device__ inline double at(int b, int pl, int m, int q, int blk) const {
+        const int p = f.p;
+        const float* row = u + (((long)b * 2 + pl) * (f.n + 1) + m) * f.W;
+        if (blk == 0) {
+            if (q <= 0) return 0.0;
+            if (q > p) q = 2 * p - q;
+            return (double)row[q - 1];
         }
-        C64 d2D = cadd(csub(D[2], cscale(D[1], 2.0)), D[0]);
-        C64 d2A = cadd(csub(Av[2], cscale(Av[1], 2.0)), Av[0]);
-        C64 dpart = cadd(cscale(D[1], ec.wD), cscale(d2D, ec.wD2));
-        C64 apart = cadd(cscale(Av[1], ec.wA), cscale(d2A, ec.wA2));
-        // + sgn * i k * apart
-        return {dpart.re - sgn * ec.k * apart.im, dpart.im + sgn * ec.k * apart.re};
+        if (q <= 0 || q >= p) {
+            if (q > p) return -(double)row[f.P1 + (2 * p - q) - 1];
+            return 0.0;
+        }
+        return (double)row[f.P1 + q - 1];
     }
+    __device__ inline C64 atc(int b, int m, int q, int blk) const { return {at(b, 0, m, q, blk), at(b, 1, m, q, blk)}; }
 };
 
-__global__ void residual_kernel(SrcEval ev, EndRow er, Fold f, int R, const float* __restrict__ u32,
-                                float* __restrict__ r_out) {
+__global__ void __launch_bounds__(256)
+residual_kernel(SrcEval ev, EndRowCoef ec, Fold f, const float* __restrict__ u32, float* __restrict__ r_out) {
     const int n = f.n, p = f.p, W = f.W;
-    const long total = (long)R * (n + 1) * W;
-    const StencilCoef sc = ev.sc;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % W);
-        const long rm = i / W;
-        const int m = (int)(rm % (n + 1));
-        const int b = (int)(rm / (n + 1));
-        int q1 = -1, q2 = -1;
-        double s2 = 0.0;
-        if (c < f.P1) {
-            int q = c + 1;
-            if (q < p) { q1 = q; q2 = n - q; s2 = 1.0; }
-            else if (q == p) { q1 = p; }
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y, b = blockIdx.z;
+    if (c >= W) return;
+    const FoldedField F{u32, f};
+    int blk, q;
+    if (c < f.P1) { blk = 0; q = c + 1; if (q > p) q = -1; }
+    else { blk = 1; q = c - f.P1 + 1; if (q >= p) q = -1; }
+    C64 r = {0.0, 0.0};
+    if (q > 0) {
+        // folded right-hand side
+        C64 g;
+        if (blk == 0) g = (q < p) ? cadd(ev.rhs(b, m, q), ev.rhs(b, m, n - q)) : ev.rhs(b, m, p);
+        else g = csub(ev.rhs(b, m, q), ev.rhs(b, m, n - q));
+        const double wgt = (blk == 0 && q == p) ? 1.0 : 2.0;
+        C64 op;
+        if (m > 0 && m < n) {
+            const StencilCoef sc = ev.sc;
+            C64 e = cadd(cadd(F.atc(b, m + 1, q, blk), F.atc(b, m - 1, q, blk)),
+                         cadd(F.atc(b, m, q + 1, blk), F.atc(b, m, q - 1, blk)));
+            C64 k = cadd(cadd(F.atc(b, m + 1, q + 1, blk), F.atc(b, m - 1, q + 1, blk)),
+                         cadd(F.atc(b, m + 1, q - 1, blk), F.atc(b, m - 1, q - 1, blk)));
+            C64 cc = F.atc(b, m, q, blk);
+            op = {sc.c0 * cc.re + sc.ce * e.re + sc.cc * k.re, sc.c0 * cc.im + sc.ce * e.im + sc.cc * k.im};
         } else {
-            int q = c - f.P1 + 1;
-            if (q < p) { q1 = q; q2 = n - q; s2 = -1.0; }
-        }
-        C64 acc = {0.0, 0.0};
-        for (int t = 0; t < 2; ++t) {
-            const int q = t ? q2 : q1;
-            if (q < 0) continue;
-            const double w = t ? s2 : 1.0;
-            C64 r;
-            if (m == 0) {
-                C64 row = er.apply(u32, f, b, 1, 0, -1.0, q);
-                r = {-row.re, -row.im};
-            } else if (m == n) {
-                C64 row = er.apply(u32, f, b, n, n - 1, 1.0, q);
-                r = {-row.re, -row.im};
-            } else {
-                C64 g = ev.rhs(b, m, q);
-                C64 e = cadd(cadd(unfold_c(u32, f, b, m + 1, q), unfold_c(u32, f, b, m - 1, q)),
-                             cadd(unfold_c(u32, f, b, m, q + 1), unfold_c(u32, f, b, m, q - 1)));
-                C64 k = cadd(cadd(unfold_c(u32, f, b, m + 1, q + 1), unfold_c(u32, f, b, m - 1, q + 1)),
-                             cadd(unfold_c(u32, f, b, m + 1, q - 1), unfold_c(u32, f, b, m - 1, q - 1)));
-                C64 cc = unfold_c(u32, f, b, m, q);
-                r = {g.re - (sc.c0 * cc.re + sc.ce * e.re + sc.cc * k.re),
-                     g.im - (sc.c0 * cc.im + sc.ce * e.im + sc.cc * k.im)};
+            // D = u(m_out) - u(m_in), A = (u(m_out) + u(m_in))/2 at q-1, q, q+1; +- i k on the A part
+            const int mo = (m == 0) ? 1 : n, mi = (m == 0) ? 0 : n - 1;
+            const double sgn = (m == 0) ? -1.0 : 1.0;
+            C64 D[3], Av[3];
+            for (int t = 0; t < 3; ++t) {
+                C64 uo = F.atc(b, mo, q + t - 1, blk), ui = F.atc(b, mi, q + t - 1, blk);
+                D[t] = csub(uo, ui);
+                Av[t] = cscale(cadd(uo, ui), 0.5);
             }
-            acc = cadd(acc, cscale(r, w));
+            C64 d2D = cadd(csub(D[2], cscale(D[1], 2.0)), D[0]);
+            C64 d2A = cadd(csub(Av[2], cscale(Av[1], 2.0)), Av[0]);
+            C64 dpart = cadd(cscale(D[1], ec.wD), cscale(d2D, ec.wD2));
+            C64 apart = cadd(cscale(Av[1], ec.wA), cscale(d2A, ec.wA2));
+            op = {dpart.re - sgn * ec.k * apart.im, dpart.im + sgn * ec.k * apart.re};
         }
-        const long o = (((long)b * 2) * (n + 1) + m) * W + c;
-        r_out[o] = (float)acc.re;
-        r_out[o + (long)(n + 1) * W] = (float)acc.im;
+        r = {g.re - wgt * op.re, g.im - wgt * op.im};
     }
+    const long o = (((long)b * 2) * (n + 1) + m) * W + c;
+    r_out[o] = (float)r.re;
+    r_out[o + (long)(n + 1) * W] = (float)r.im;
 }
 
 // ------------------------------------------------------------------ gather onto gamma (projector)
 // Q(i, col0+b) = -(u(m_i, q_i)) with u = u_main (+ du, the FP32 correction of a refined solve).
 template <class T>
 __global__ void gather_q_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f,
-                                const int* __restrict__ gm, const int* __restrict__ gq, int ng, int R,
+                                const int* __restrict__ gm, const int* __restrict__ gq, int ng,
                                 double* __restrict__ Q, int ldq, int col0) {
-    const long total = (long)ng * R;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        const int i = (int)(t % ng);
-        const int b = (int)(t / ng);
-        const int m = gm[i], q = gq[i];
-        C64 v = unfold_c(u, f, b, m, q);
-        if (du) v = cadd(v, unfold_c(du, f, b, m, q));
-        double* o = Q + 2 * ((long)(col0 + b) * ldq + i);
-        o[0] = -v.re;
-        o[1] = -v.im;
-    }
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= ng) return;
+    const int m = gm[i], q = gq[i];
+    C64 v = unfold_c(u, f, b, m, q);
+    if (du) v = cadd(v, unfold_c(du, f, b, m, q));
+    double* o = Q + 2 * ((long)(col0 + b) * ldq + i);
+    o[0] = -v.re;
+    o[1] = -v.im;
 }
 
 // ------------------------------------------------------------------ unfold to grids
 // out_b(m, q) = w_b(m, q) + alpha * u_b(m, q)  (w optional; complex interleaved FP64)
 template <class T>
-__global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f, int R,
-                                   double alpha, const double* w, long w_stride, double* out, long out_stride) {
+__global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f, double alpha,
+                                   const double* w, long w_stride, double* out, long out_stride) {
     const int n = f.n;
-    const long npts = (long)(n + 1) * (n + 1);
-    const long total = npts * R;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        const int b = (int)(t / npts);
-        const long node = t % npts;
-        const int m = (int)(node / (n + 1)), q = (int)(node % (n + 1));
-        C64 v = unfold_c(u, f, b, m, q);
-        if (du) v = cadd(v, unfold_c(du, f, b, m, q));
-        double re = alpha * v.re, im = alpha * v.im;
-        if (w) {
-            const double* wp = w + 2 * ((long)b * w_stride + node);
-            re += wp[0];
-            im += wp[1];
-        }
-        double* o = out + 2 * ((long)b * out_stride + node);
-        o[0] = re;
-        o[1] = im;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y, b = blockIdx.z;
+    if (q > n) return;
+    const long node = (long)m * (n + 1) + q;
+    C64 v = unfold_c(u, f, b, m, q);
+    if (du) v = cadd(v, unfold_c(du, f, b, m, q));
+    double re = alpha * v.re, im = alpha * v.im;
+    if (w) {
+        const double* wp = w + 2 * ((long)b * w_stride + node);
+        re += wp[0];
+        im += wp[1];
     }
+    double* o = out + 2 * ((long)b * out_stride + node);
+    o[0] = re;
+    o[1] = im;
 }
 
 // ------------------------------------------------------------------ density on gamma for reconstruction
 // w_b(gamma_i) = sum_col E(i, col) c_b(col)  (E real, c complex); w is pre-zeroed elsewhere.
 __global__ void extend_density_kernel(const double* __restrict__ E, int ng, int ncol, const double* __restrict__ c,
-                                      int R, const int* __restrict__ gm, const int* __restrict__ gq, int n,
-                                      double* w, long w_stride) {
-    const long total = (long)ng * R;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        const int i = (int)(t % ng);
-        const int b = (int)(t / ng);
-        double re = 0.0, im = 0.0;
-        const double* cb = c + 2 * (long)b * ncol;
-        for (int col = 0; col < ncol; ++col) {
-            double e = E[(long)col * ng + i];
-            re += e * cb[2 * col];
-            im += e * cb[2 * col + 1];
-        }
-        double* o = w + 2 * ((long)b * w_stride + (long)gm[i] * (n + 1) + gq[i]);
-        o[0] = re;
-        o[1] = im;
+                                      const int* __restrict__ gm, const int* __restrict__ gq, int n, double* w,
+                                      long w_stride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= ng) return;
+    double re = 0.0, im = 0.0;
+    const double* cb = c + 2 * (long)b * ncol;
+    for (int col = 0; col < ncol; ++col) {
+        double e = E[(long)col * ng + i];
+        re += e * cb[2 * col];
+        im += e * cb[2 * col + 1];
     }
+    double* o = w + 2 * ((long)b * w_stride + (long)gm[i] * (n + 1) + gq[i]);
+    o[0] = re;
+    o[1] = im;
 }
 
 inline unsigned grid_for(long total, int block = 256) {
@@ -360,19 +356,25 @@ inline unsigned grid_for(long total, int block = 256) {
 
 }  // namespace
 
+static void check_batch(int R) {
+    if (R > 65535) throw Error(MDP_ERR_ARG, "batch too large for one launch");
+}
+
 template <class T>
 void launch_fold_rhs(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, bool cplx, T* out,
                      hipStream_t st) {
+    check_batch(R);
     SrcEval ev{s, n, sc};
-    long total = (long)R * (n + 1) * f.W;
-    hipLaunchKernelGGL(fold_rhs_kernel<T>, dim3(grid_for(total)), dim3(256), 0, st, ev, f, R, cplx ? 2 : 1, out);
+    const int bx = f.W < 256 ? f.W : 256;
+    dim3 grid((f.W + bx - 1) / bx, n + 1, R);
+    hipLaunchKernelGGL(fold_rhs_kernel<T>, grid, dim3(bx), 0, st, ev, f, cplx ? 2 : 1, out);
     MDP_HIP(hipGetLastError());
 }
 
 template <class T>
 void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* colc, int n, const Fold& f, int R,
                     hipStream_t st) {
-    if (R > 65535) throw Error(MDP_ERR_ARG, "tridiagonal batch too large");
+    check_batch(R);
     dim3 grid((f.W + 255) / 256, R);
     hipLaunchKernelGGL(tridiag_kernel<T>, grid, dim3(256), 0, st, in, planes_in, out, fac, colc, n, f.W, R);
     MDP_HIP(hipGetLastError());
@@ -380,10 +382,11 @@ void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* c
 
 void launch_residual(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, EndRowCoef ec, int R, bool,
                      const float* u32, float* r_out, hipStream_t st) {
+    check_batch(R);
     SrcEval ev{s, n, sc};
-    EndRow er{ec};
-    long total = (long)R * (n + 1) * f.W;
-    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(total)), dim3(256), 0, st, ev, er, f, R, u32, r_out);
+    const int bx = f.W < 256 ? f.W : 256;
+    dim3 grid((f.W + bx - 1) / bx, n + 1, R);
+    hipLaunchKernelGGL(residual_kernel, grid, dim3(bx), 0, st, ev, ec, f, u32, r_out);
     MDP_HIP(hipGetLastError());
 }
 
@@ -391,27 +394,27 @@ template <class T>
 void launch_gather_q(const T* u, const float* du, int n, const Fold& f, const int* gm, const int* gq, int ng, int R,
                      double* Q, int ldq, int col0, hipStream_t st) {
     (void)n;
-    long total = (long)ng * R;
-    hipLaunchKernelGGL(gather_q_kernel<T>, dim3(grid_for(total)), dim3(256), 0, st, u, du, f, gm, gq, ng, R, Q, ldq,
-                       col0);
+    check_batch(R);
+    dim3 grid((ng + 255) / 256, R);
+    hipLaunchKernelGGL(gather_q_kernel<T>, grid, dim3(256), 0, st, u, du, f, gm, gq, ng, Q, ldq, col0);
     MDP_HIP(hipGetLastError());
 }
 
 template <class T>
 void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, int R, const double* w, long w_stride,
                         double* out, long out_stride, hipStream_t st) {
-    long total = (long)(n + 1) * (n + 1) * R;
+    check_batch(R);
     double alpha = w ? -1.0 : 1.0;
-    hipLaunchKernelGGL(unfold_grid_kernel<T>, dim3(grid_for(total)), dim3(256), 0, st, u, du, f, R, alpha, w,
-                       w_stride, out, out_stride);
+    dim3 grid((n + 1 + 255) / 256, n + 1, R);
+    hipLaunchKernelGGL(unfold_grid_kernel<T>, grid, dim3(256), 0, st, u, du, f, alpha, w, w_stride, out, out_stride);
     MDP_HIP(hipGetLastError());
 }
 
 void launch_extend_density(const double* E, int ng, int ncol, const double* c, int R, const int* gm,
                            const int* gq, int n, double* w, long w_stride, hipStream_t st) {
-    long total = (long)ng * R;
-    hipLaunchKernelGGL(extend_density_kernel, dim3(grid_for(total)), dim3(256), 0, st, E, ng, ncol, c, R, gm, gq, n,
-                       w, w_stride);
+    check_batch(R);
+    dim3 grid((ng + 255) / 256, R);
+    hipLaunchKernelGGL(extend_density_kernel, grid, dim3(256), 0, st, E, ng, ncol, c, gm, gq, n, w, w_stride);
     MDP_HIP(hipGetLastError());
 }
 

@@ -170,20 +170,37 @@ static void solve_batch_t(const APPlan& P, Workspace& ws, const SrcDesc& src, bo
     const T* fac = (const T*)(sizeof(T) == 8 ? P.fac64.p : P.fac32.p);
     const T* colc = (const T*)(sizeof(T) == 8 ? P.colc64.p : P.colc32.p);
 
-    launch_fold_rhs<T>(src, n, f, P.sc, R, src_cplx, A, st);
-    launch_gemm_bd<T>(A, Sf, B, (long)R * pin * rows, f, st);
-    launch_tridiag<T>(B, pin, A, fac, colc, n, f, R, st);
-    launch_gemm_bd<T>(A, Si, B, (long)R * 2 * rows, f, st);
+    // algorithmic work per launch: only the p + (p-1) = n-1 useful columns of a
+    // folded row count, padding does not
+    Profiler& pr = ws.prof;
+    const double useful = (double)(n - 1);
+    const double gemm_row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
+    const double rows_in = (double)R * pin * rows, rows_c = (double)R * 2 * rows;
+    const double tri_pts = (double)R * rows * useful;
+    pr.run("fold_rhs", st, 0.0, rows_in * useful * sizeof(T),
+           [&] { launch_fold_rhs<T>(src, n, f, P.sc, R, src_cplx, A, st); });
+    pr.run(sizeof(T) == 8 ? "gemm_sine_f64" : "gemm_sine_f32", st, rows_in * gemm_row_flops,
+           2.0 * rows_in * useful * sizeof(T), [&] { launch_gemm_bd<T>(A, Sf, B, (long)R * pin * rows, f, st); });
+    pr.run(sizeof(T) == 8 ? "tridiag_f64" : "tridiag_f32", st, tri_pts * 22.0,
+           tri_pts * (pin + 2) * sizeof(T) + 4.0 * rows * useful * sizeof(T),
+           [&] { launch_tridiag<T>(B, pin, A, fac, colc, n, f, R, st); });
+    pr.run(sizeof(T) == 8 ? "gemm_sine_f64" : "gemm_sine_f32", st, rows_c * gemm_row_flops,
+           2.0 * rows_c * useful * sizeof(T), [&] { launch_gemm_bd<T>(A, Si, B, (long)R * 2 * rows, f, st); });
     const float* du = nullptr;
     if (refine) {
         // r = g - A u in FP64 (u = the FP32 solution in B), correction solved in FP32
         ws.c.reserve(elems * sizeof(float));
         float* Cb = ws.c.as<float>();
         float* Af = reinterpret_cast<float*>(A);
-        launch_residual(src, n, f, P.sc, P.ec, R, src_cplx, reinterpret_cast<const float*>(B), Af, st);
-        launch_gemm_bd<float>(Af, P.Sf32.as<float>(), Cb, (long)R * 2 * rows, f, st);
-        launch_tridiag<float>(Cb, 2, Af, P.fac32.as<float>(), P.colc32.as<float>(), n, f, R, st);
-        launch_gemm_bd<float>(Af, P.Si32.as<float>(), Cb, (long)R * 2 * rows, f, st);
+        const double tri_c = (double)R * rows * useful;
+        pr.run("residual", st, tri_c * 9.0 * 8.0, tri_c * 2.0 * 2.0 * sizeof(float),
+               [&] { launch_residual(src, n, f, P.sc, P.ec, R, src_cplx, reinterpret_cast<const float*>(B), Af, st); });
+        pr.run("gemm_sine_f32", st, rows_c * gemm_row_flops, 2.0 * rows_c * useful * sizeof(float),
+               [&] { launch_gemm_bd<float>(Af, P.Sf32.as<float>(), Cb, (long)R * 2 * rows, f, st); });
+        pr.run("tridiag_f32", st, tri_c * 22.0, tri_c * 4.0 * sizeof(float) + 4.0 * rows * useful * sizeof(float),
+               [&] { launch_tridiag<float>(Cb, 2, Af, P.fac32.as<float>(), P.colc32.as<float>(), n, f, R, st); });
+        pr.run("gemm_sine_f32", st, rows_c * gemm_row_flops, 2.0 * rows_c * useful * sizeof(float),
+               [&] { launch_gemm_bd<float>(Af, P.Si32.as<float>(), Cb, (long)R * 2 * rows, f, st); });
         du = Cb;
     }
     consume(B, du);

@@ -23,10 +23,23 @@ struct APPlan {
     APPlan(int n, double h, double k);
 };
 
+// Least-squares buffers (grow-only).
+struct LSWork {
+    DevBuf G, L, Linv[3], T, A0, Aq, vec, norms, flags;
+};
+
+// Packed interface matrix buffers (grow-only).
+struct PackedWork {
+    DevBuf dQ, dm, ds, doff, droff, dsub, dp, dgcol, dstart, dcols, dcoef, Ap, Gi;
+};
+
 // Grow-only device workspaces of a context.
 struct Workspace {
     DevBuf a, b, c;       // folded batch buffers
     DevBuf zg;            // split-K partial products of the complex GEMM
+    LSWork ls;            // interface least squares
+    PackedWork pk;        // block-sparse interface matrix
+    Profiler prof;        // optional per-launch timing
 };
 
 // Largest batch whose buffers fit in cap_bytes (at least 1, at most R).

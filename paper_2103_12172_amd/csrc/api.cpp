@@ -214,10 +214,14 @@ int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int p
             const Fold f = plan.f;
             solve_batch(plan, ctx->ws, precision, src, false, R,
                         [&](const void* u, const float* du) {
-                            if (precision == MDP_C128)
-                                launch_gather_q<double>((const double*)u, du, n, f, gmd, gqd, ng, R, Qd, ng, col0, st);
-                            else
-                                launch_gather_q<float>((const float*)u, du, n, f, gmd, gqd, ng, R, Qd, ng, col0, st);
+                            ctx->ws.prof.run("gather_q", st, 0.0, (double)ng * R * 16.0 * 2.0, [&] {
+                                if (precision == MDP_C128)
+                                    launch_gather_q<double>((const double*)u, du, n, f, gmd, gqd, ng, R, Qd, ng, col0,
+                                                            st);
+                                else
+                                    launch_gather_q<float>((const float*)u, du, n, f, gmd, gqd, ng, R, Qd, ng, col0,
+                                                           st);
+                            });
                         },
                         st);
         }
@@ -370,13 +374,76 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
         upload(d_kcol, kcol);
         upload(d_kval, kval);
         upload(d_koff, koff);
-        DevBuf Qbar((size_t)m * ncol * sizeof(double2)), F((size_t)m * sizeof(double2)), x((size_t)ncol * sizeof(double2));
-        launch_assemble_qbar(d_qsrc.as<const double2* const>(), d_qld.as<int>(), n_sub, d_roff.as<int>(), m,
-                             d_cmap.as<int4>(), d_coef.as<double2>(), ncol, Qbar.as<double2>(), m, st);
+        DevBuf F((size_t)m * sizeof(double2)), x((size_t)ncol * sizeof(double2));
         launch_known_rhs(d_qsrc.as<const double2* const>(), d_qld.as<int>(), n_sub, d_roff.as<int>(), m,
                          d_kcol.as<int>(), d_kval.as<double2>(), d_koff.as<int>(), F.as<double2>(), st);
-        LSResult r = ls_solve(ctx->ws, Qbar.as<double2>(), F.as<double2>(), m, ncol, x.as<double2>(),
-                              cond_estimate_out != nullptr, st);
+        // block-sparse description: subdomain i's rows touch only the unknown blocks with a contribution from i
+        PackedHost ph;
+        ph.n_sub = n_sub;
+        ph.nc = ncol;
+        ph.Q = qsrc;
+        ph.m = qld;
+        long off = 0;
+        for (int i = 0; i < n_sub; ++i) {
+            ph.off.push_back(off);
+            ph.roff.push_back(row_off[i]);
+            ph.pc_start.push_back((int)ph.pc_sub.size());
+            int si = 0;
+            for (size_t b = 0; b < blocks.size(); ++b) {
+                std::vector<const Contrib*> mine;
+                for (const Contrib& c : blocks[b].c)
+                    if (c.sub == i) mine.push_back(&c);
+                if (mine.empty()) continue;
+                for (int j = 0; j < M; ++j) {
+                    int4 cm{-1, -1, 0, 0};
+                    double2 w0{0.0, 0.0}, w1{0.0, 0.0};
+                    cm.x = mine[0]->kind * 4 * M + mine[0]->side * M + j;
+                    w0 = mine[0]->coef;
+                    if (mine.size() > 1) {
+                        cm.y = mine[1]->kind * 4 * M + mine[1]->side * M + j;
+                        w1 = mine[1]->coef;
+                    }
+                    ph.pc_sub.push_back(i);
+                    ph.pc_p.push_back(si);
+                    ph.pc_gcol.push_back((int)b * M + j);
+                    ph.pc_cols.push_back(cm);
+                    ph.pc_coef.push_back(w0);
+                    ph.pc_coef.push_back(w1);
+                    ++si;
+                }
+            }
+            ph.s.push_back(si);
+            ph.max_s = std::max(ph.max_s, si);
+            ph.max_m = std::max(ph.max_m, qld[i]);
+            off += (long)qld[i] * si;
+        }
+        ph.total_pc = (int)ph.pc_sub.size();
+        LSResult r;
+        {
+            // the whole least-squares solve as one profiled span (it synchronises internally)
+            Profiler& pr = ctx->ws.prof;
+            hipEvent_t a = nullptr, b = nullptr;
+            if (pr.on) { a = pr.get(); b = pr.get(); MDP_HIP(hipEventRecord(a, st)); }
+            double gram_flops = 0.0;
+            for (int i = 0; i < n_sub; ++i) gram_flops += 8.0 * (double)qld[i] * ph.s[i] * ph.s[i];
+            bool fallback = false;
+            r = ls_solve_packed(ctx->ws, ph, F.as<double2>(), x.as<double2>(), cond_estimate_out != nullptr, st,
+                                &fallback);
+            if (fallback) {
+                // dense Cholesky-QR passes on the assembled matrix
+                DevBuf Qbar((size_t)m * ncol * sizeof(double2));
+                launch_assemble_qbar(d_qsrc.as<const double2* const>(), d_qld.as<int>(), n_sub, d_roff.as<int>(), m,
+                                     d_cmap.as<int4>(), d_coef.as<double2>(), ncol, Qbar.as<double2>(), m, st);
+                r = ls_solve(ctx->ws, Qbar.as<double2>(), F.as<double2>(), m, ncol, x.as<double2>(),
+                             cond_estimate_out != nullptr, st);
+                gram_flops = 8.0 * (double)m * ncol * ncol * r.passes;
+                MDP_HIP(hipStreamSynchronize(st));
+            }
+            if (pr.on) {
+                MDP_HIP(hipEventRecord(b, st));
+                pr.recs.push_back({"interface_ls", a, b, gram_flops, (double)m * ncol * 16.0});
+            }
+        }
         // expand the unknowns to the full coefficient vectors (column order of Q)
         std::vector<double2> hx(ncol);
         MDP_HIP(hipMemcpyAsync(hx.data(), x.p, ncol * sizeof(double2), hipMemcpyDeviceToHost, st));
@@ -465,10 +532,13 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
                 solve_batch(plan, ctx->ws, prec, src, true, Rc,
                             [&](const void* u, const float* du) {
                                 // u_out = w - G(L w |M+), written in place over w
-                                if (prec == MDP_C128)
-                                    launch_unfold_grid<double>((const double*)u, du, n, f, Rc, w, npts, w, npts, st);
-                                else
-                                    launch_unfold_grid<float>((const float*)u, du, n, f, Rc, w, npts, w, npts, st);
+                                ctx->ws.prof.run("unfold_grid", st, 0.0, (double)Rc * npts * 16.0 * 3.0, [&] {
+                                    if (prec == MDP_C128)
+                                        launch_unfold_grid<double>((const double*)u, du, n, f, Rc, w, npts, w, npts,
+                                                                   st);
+                                    else
+                                        launch_unfold_grid<float>((const float*)u, du, n, f, Rc, w, npts, w, npts, st);
+                                });
                             },
                             st);
             }
@@ -515,6 +585,59 @@ int mdp_ap_solve(mdp_ctx* ctx, int n, double h, double k, int precision, int bat
                         st);
         }
         end_call(ctx, st);
+        return MDP_OK;
+    });
+}
+
+// ---------------------------------------------------------------------------- cache / profiling
+int mdp_cache_clear(mdp_ctx* ctx) {
+    if (!ctx) return MDP_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        MDP_HIP(hipDeviceSynchronize());
+        for (auto& kv : ctx->cache) mdp_projector_release(kv.second);
+        ctx->cache.clear();
+        return MDP_OK;
+    });
+}
+
+int mdp_profile_enable(mdp_ctx* ctx, int enable) {
+    if (!ctx) return MDP_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        MDP_HIP(hipDeviceSynchronize());
+        ctx->ws.prof.reset();
+        ctx->ws.prof.on = enable != 0;
+        return MDP_OK;
+    });
+}
+
+int mdp_profile_report(mdp_ctx* ctx, char* buf, int buflen) {
+    if (!ctx || !buf || buflen < 3) return MDP_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        MDP_HIP(hipDeviceSynchronize());
+        struct Acc { int count = 0; double ms = 0, flops = 0, bytes = 0; };
+        std::map<std::string, Acc> acc;
+        for (auto& r : ctx->ws.prof.recs) {
+            float ms = 0.f;
+            MDP_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            Acc& a = acc[r.name];
+            a.count += 1;
+            a.ms += ms;
+            a.flops += r.flops;
+            a.bytes += r.bytes;
+        }
+        std::string out = "{";
+        bool first = true;
+        char tmp[512];
+        for (auto& kv : acc) {
+            std::snprintf(tmp, sizeof tmp, "%s\"%s\": {\"count\": %d, \"total_ms\": %.6f, \"flops\": %.6e, \"bytes\": %.6e}",
+                          first ? "" : ", ", kv.first.c_str(), kv.second.count, kv.second.ms, kv.second.flops,
+                          kv.second.bytes);
+            out += tmp;
+            first = false;
+        }
+        out += "}";
+        if ((int)out.size() + 1 > buflen) throw Error(MDP_ERR_ARG, "profile report buffer too small");
+        std::memcpy(buf, out.c_str(), out.size() + 1);
         return MDP_OK;
     });
 }

@@ -19,32 +19,43 @@ __device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_
 // Workgroup tile 64 x 64, 4 waves of 32 x 32, K step 16; the K range of this
 // workgroup is [kz*kchunk, min(K, (kz+1)*kchunk)).  With split-K (nsplit > 1)
 // raw products go to P[kz] and a second kernel reduces them.
-constexpr int ZBM = 64, ZBN = 64, ZBK = 16;
+constexpr int ZBK = 16;
 
+// tri: 0 = full; 1 = only tiles touching the lower triangle of C are computed
+// (C Hermitian, lower part used); 2 = op(B) is upper triangular, so column tile
+// n0 only needs k < n0 + 64.
+template <int ZBM>
 __global__ void __launch_bounds__(256)
 zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ A, int lda,
              const double2* __restrict__ B, int ldb, double2* __restrict__ C, int ldc, double2 alpha, double2 beta,
-             int kchunk, double2* __restrict__ P, long pstride, int mtiles) {
+             int kchunk, double2* __restrict__ P, long pstride, int mtiles, int tri) {
+    constexpr int ZBN = ZBM;
+    constexpr int WT = ZBM / 2;          // wave tile (2 x 2 waves)
+    constexpr int TT = WT / 16;          // 16x16 MFMA blocks per wave side
+    constexpr int NL = ZBM * ZBK / 256;  // complex elements per thread per tile
     __shared__ double Ar[2][ZBK][ZBM + 2], Ai[2][ZBK][ZBM + 2];
     __shared__ double Br[2][ZBK][ZBN + 2], Bi[2][ZBK][ZBN + 2];
     const int tid = threadIdx.x;
     const int mt = blockIdx.x % mtiles, nt = blockIdx.x / mtiles;
     const int kz = blockIdx.y;
     const int m0 = mt * ZBM, n0 = nt * ZBN;
-    const int kb = kz * kchunk, ke = min(K, kb + kchunk);
+    if (tri == 1 && m0 + ZBM <= n0) return;
+    const int kb = kz * kchunk;
+    int ke = min(K, kb + kchunk);
+    if (tri == 2) ke = min(ke, n0 + ZBN);
     const int wave = tid >> 6, lane = tid & 63, wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
 
-    d4 cr[2][2], ci[2][2];
+    d4 cr[TT][TT], ci[TT][TT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) { cr[i][j] = d4{0, 0, 0, 0}; ci[i][j] = d4{0, 0, 0, 0}; }
+        for (int j = 0; j < TT; ++j) { cr[i][j] = d4{0, 0, 0, 0}; ci[i][j] = d4{0, 0, 0, 0}; }
 
-    double2 ra[4], rb[4];
+    double2 ra[NL], rb[NL];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < NL; ++v) {
             int idx = tid + v * 256;
             int i, kk;
             if (opA == 0) { i = idx % ZBM; kk = idx / ZBM; } else { kk = idx % ZBK; i = idx / ZBK; }
@@ -69,7 +80,7 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < NL; ++v) {
             int idx = tid + v * 256;
             int i, kk, j;
             if (opA == 0) { i = idx % ZBM; kk = idx / ZBM; } else { kk = idx % ZBK; i = idx / ZBK; }
@@ -92,18 +103,18 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
         if (more) gload(k0 + ZBK);
 #pragma unroll
         for (int kk = 0; kk < ZBK / 4; ++kk) {
-            double ar[2], ai[2], br[2], bi[2];
+            double ar[TT], ai[TT], br[TT], bi[TT];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                ar[i] = Ar[buf][kk * 4 + lk][wm * 32 + i * 16 + lr];
-                ai[i] = Ai[buf][kk * 4 + lk][wm * 32 + i * 16 + lr];
-                br[i] = Br[buf][kk * 4 + lk][wn * 32 + i * 16 + lr];
-                bi[i] = Bi[buf][kk * 4 + lk][wn * 32 + i * 16 + lr];
+            for (int i = 0; i < TT; ++i) {
+                ar[i] = Ar[buf][kk * 4 + lk][wm * WT + i * 16 + lr];
+                ai[i] = Ai[buf][kk * 4 + lk][wm * WT + i * 16 + lr];
+                br[i] = Br[buf][kk * 4 + lk][wn * WT + i * 16 + lr];
+                bi[i] = Bi[buf][kk * 4 + lk][wn * WT + i * 16 + lr];
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < TT; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < TT; ++j) {
                     cr[i][j] = mfma64(ar[i], br[j], cr[i][j]);
                     cr[i][j] = mfma64(-ai[i], bi[j], cr[i][j]);
                     ci[i][j] = mfma64(ar[i], bi[j], ci[i][j]);
@@ -115,17 +126,17 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
         buf ^= 1;
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TT; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int gi = m0 + wm * 32 + i * 16 + lk + 4 * r;   // f64 MFMA D rows: (lane>>4) + 4r
-                int gj = n0 + wn * 32 + j * 16 + lr;
+                int gi = m0 + wm * WT + i * 16 + lk + 4 * r;   // f64 MFMA D rows: (lane>>4) + 4r
+                int gj = n0 + wn * WT + j * 16 + lr;
                 if (gi >= M || gj >= N) continue;
                 double vr = cr[i][j][r], vi = ci[i][j][r];
                 if (P) {
-                    P[kz * pstride + gi + (long)gj * M] = make_double2(vr, vi);
+                    P[kz * pstride + gi + (long)gj * M] = make_double2(vr, vi);   // zero if this K range was empty
                 } else {
                     double2 o = make_double2(alpha.x * vr - alpha.y * vi, alpha.x * vi + alpha.y * vr);
                     double2* cp = C + gi + (long)gj * ldc;
@@ -140,10 +151,13 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
 }
 
 __global__ void zgemm_reduce_kernel(int M, int N, int nsplit, const double2* __restrict__ P, long pstride,
-                                    double2* __restrict__ C, int ldc, double2 alpha, double2 beta) {
-    long total = (long)M * N;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        int i = (int)(t % M), j = (int)(t / M);
+                                    double2* __restrict__ C, int ldc, double2 alpha, double2 beta, int tri, int tile) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= M) return;
+    if (tri == 1 && (i / tile + 1) * tile <= (j / tile) * tile) return;
+    {
+        const long t = i + (long)j * M;
         double sr = 0.0, si = 0.0;
         for (int s = 0; s < nsplit; ++s) {
             double2 v = P[s * pstride + t];
@@ -161,79 +175,468 @@ __global__ void zgemm_reduce_kernel(int M, int N, int nsplit, const double2* __r
     }
 }
 
-// Cholesky of one Hermitian diagonal block (lower: G = L L^H) and the inverse of
-// its factor, in LDS.  G (nb x nb, leading dim ldg) is read; L goes to Lout
-// (ld ldl, upper part zeroed) and L^{-1} to Linv (ld ldi).  A non-positive pivot
-// sets *info to its 1-based index (first failure wins) and the block is then
-// not usable.  `shift` is added to the diagonal before factoring.
-template <int NB>
-__global__ void __launch_bounds__(256)
+// 1/d to full FP64 precision: hardware reciprocal estimate refined by two
+// Newton steps (each doubles the correct bits), cheaper in latency than the
+// IEEE division sequence
+__device__ inline double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky of one 64 x 64 Hermitian diagonal block, G = L L^* (lower), and the
+// inverse of its factor.  Blocked unscaled elimination G = Lt D Lt^* (unit-lower
+// Lt, Lt(i,k) = S(i,k)/S(k,k)) in panels of 8 columns; the same elimination
+// applied to the identity yields Lt^{-1}; at the end L = Lt D^{1/2} and
+// L^{-1} = D^{-1/2} Lt^{-1}.  (64/TS)^2 threads; thread t owns the TS x TS
+// tiles at rows TS (t % (64/TS)) and columns TS (t / (64/TS)) of S and of the
+// inverse in registers (launched with TS = 4: 256 threads, no register
+// spills; 2 x 2 tiles with 1024 threads spill the panel registers).  Per
+// panel: the owners publish the panel columns (and the panel rows of the
+// inverse) to LDS, one wavefront factors the 64 x 8 panel and finalises those
+// 8 inverse rows with wave-level synchronisation (each lane keeps its panel row
+// in registers; only the 8 diagonal-block entries of a column travel through
+// LDS), and every thread applies the rank-8 update to its registers.  G (nb x
+// nb, ld ldg) is read, L goes to Lout (ld ldl, upper part zero), L^{-1} to Linv
+// (ld ldi).  A non-positive pivot sets *info to base + its 1-based index (first
+// failure wins); `shift` is added to the diagonal first.
+template <int TS>
+__global__ void __launch_bounds__((64 / TS) * (64 / TS))
 chol_block_kernel(const double2* __restrict__ G, int ldg, int nb, double shift, double2* __restrict__ Lout, int ldl,
                   double2* __restrict__ Linv, int ldi, int* info, int base) {
-    __shared__ double2 S[NB][NB + 1];
-    __shared__ double2 X[NB][NB + 1];
-    __shared__ int bad;
+    constexpr int NB = 64, PW = 8, TD = 64 / TS;
+    __shared__ double2 P[NB][PW + 1];   // panel columns of S (unscaled)
+    __shared__ double2 LT[NB][PW + 1];  // the same scaled by the pivot: Lt(i, k)
+    __shared__ double2 XP[PW][NB + 1];  // panel rows of the inverse
+    __shared__ double piv[NB];
+    __shared__ double2 colk[PW];        // diagonal-block entries of the current panel column
+    __shared__ int bad_s;
     const int tid = threadIdx.x;
-    if (tid == 0) bad = 0;
-    for (int t = tid; t < NB * NB; t += 256) {
-        int i = t % NB, j = t / NB;
+    const int r0 = TS * (tid % TD), c0 = TS * (tid / TD);
+    const int wave = tid >> 6, lane = tid & 63;
+    double sr[TS][TS], si[TS][TS], xr[TS][TS], xi[TS][TS];
+#pragma unroll
+    for (int a = 0; a < TS; ++a)
+#pragma unroll
+        for (int b = 0; b < TS; ++b) {
+            const int i = r0 + a, j = c0 + b;
+            double2 v = make_double2(0.0, 0.0);
+            if (i < nb && j < nb) v = G[i + (long)j * ldg];
+            else if (i == j) v = make_double2(1.0, 0.0);   // identity padding keeps the factor regular
+            if (i == j && i < nb) v.x += shift;
+            sr[a][b] = v.x;
+            si[a][b] = v.y;
+            xr[a][b] = (i == j) ? 1.0 : 0.0;
+            xi[a][b] = 0.0;
+        }
+    if (tid == 0) bad_s = 0;
+    for (int kb = 0; kb < NB; kb += PW) {
+        // publish the panel columns kb..kb+7 of S and the panel rows kb..kb+7 of the inverse
+        if (c0 >= kb && c0 < kb + PW) {
+#pragma unroll
+            for (int a = 0; a < TS; ++a)
+#pragma unroll
+                for (int b = 0; b < TS; ++b) P[r0 + a][c0 - kb + b] = make_double2(sr[a][b], si[a][b]);
+        }
+        if (r0 >= kb && r0 < kb + PW) {
+#pragma unroll
+            for (int a = 0; a < TS; ++a)
+#pragma unroll
+                for (int b = 0; b < TS; ++b) XP[r0 - kb + a][c0 + b] = make_double2(xr[a][b], xi[a][b]);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const int i = lane;
+            double2 pr[PW], xc[PW];
+#pragma unroll
+            for (int jj = 0; jj < PW; ++jj) { pr[jj] = P[i][jj]; xc[jj] = XP[jj][i]; }
+#pragma unroll
+            for (int kk = 0; kk < PW; ++kk) {
+                const int k = kb + kk;
+                if (i >= kb && i < kb + PW) colk[i - kb] = pr[kk];
+                wave_sync();
+                double2 ck[PW];
+#pragma unroll
+                for (int jj = 0; jj < PW; ++jj) ck[jj] = colk[jj];
+                double d = ck[kk].x;
+                if (!(d > 0.0)) {
+                    if (lane == 0 && !bad_s) bad_s = k + 1;
+                    d = 1.0;
+                }
+                const double dinv = recip(d);
+                const double2 pik = pr[kk];
+                LT[i][kk] = make_double2(pik.x * dinv, pik.y * dinv);
+#pragma unroll
+                for (int jj = kk + 1; jj < PW; ++jj) {
+                    if (i >= kb + jj) {   // S(i, kb+jj) -= S(i,k) conj(S(kb+jj,k)) / d
+                        pr[jj].x -= (pik.x * ck[jj].x + pik.y * ck[jj].y) * dinv;
+                        pr[jj].y -= (pik.y * ck[jj].x - pik.x * ck[jj].y) * dinv;
+                    }
+                    // inverse rows: X(kb+jj, i) -= Lt(kb+jj, k) X(k, i)
+                    const double lr = ck[jj].x * dinv, li = ck[jj].y * dinv;
+                    xc[jj].x -= lr * xc[kk].x - li * xc[kk].y;
+                    xc[jj].y -= lr * xc[kk].y + li * xc[kk].x;
+                }
+                if (lane == 0) piv[k] = d;
+                wave_sync();   // colk is rewritten by the next column
+            }
+#pragma unroll
+            for (int jj = 0; jj < PW; ++jj) { P[i][jj] = pr[jj]; XP[jj][i] = xc[jj]; }
+        }
+        __syncthreads();
+        // owners take the factored panel back; everybody applies the rank-8 update
+        if (c0 >= kb && c0 < kb + PW) {
+#pragma unroll
+            for (int a = 0; a < TS; ++a)
+#pragma unroll
+                for (int b = 0; b < TS; ++b) {
+                    const double2 v = P[r0 + a][c0 - kb + b];
+                    sr[a][b] = v.x;
+                    si[a][b] = v.y;
+                }
+        }
+        if (r0 >= kb && r0 < kb + PW) {
+#pragma unroll
+            for (int a = 0; a < TS; ++a)
+#pragma unroll
+                for (int b = 0; b < TS; ++b) {
+                    const double2 v = XP[r0 - kb + a][c0 + b];
+                    xr[a][b] = v.x;
+                    xi[a][b] = v.y;
+                }
+        }
+        if (r0 + TS - 1 >= kb + PW) {
+#pragma unroll
+            for (int kk = 0; kk < PW; ++kk) {
+                double2 li[TS], lj[TS], xk[TS];
+#pragma unroll
+                for (int a = 0; a < TS; ++a) li[a] = LT[r0 + a][kk];
+#pragma unroll
+                for (int b = 0; b < TS; ++b) { lj[b] = P[c0 + b][kk]; xk[b] = XP[kk][c0 + b]; }
+#pragma unroll
+                for (int a = 0; a < TS; ++a) {
+                    const int i = r0 + a;
+                    if (i < kb + PW) continue;
+                    const double lr = li[a].x, lim = li[a].y;
+#pragma unroll
+                    for (int b = 0; b < TS; ++b) {
+                        const int j = c0 + b;
+                        if (j < kb + PW) {          // inverse: X(i, j) -= Lt(i, k) X(k, j)
+                            xr[a][b] -= lr * xk[b].x - lim * xk[b].y;
+                            xi[a][b] -= lr * xk[b].y + lim * xk[b].x;
+                        } else if (j <= i) {        // S(i, j) -= Lt(i, k) conj(S(j, k))
+                            sr[a][b] -= lr * lj[b].x + lim * lj[b].y;
+                            si[a][b] -= lim * lj[b].x - lr * lj[b].y;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < TS; ++a)
+#pragma unroll
+        for (int b = 0; b < TS; ++b) {
+            const int i = r0 + a, j = c0 + b;
+            if (i >= nb || j >= nb) continue;
+            double2 l = make_double2(0.0, 0.0), x = make_double2(0.0, 0.0);
+            if (j < i) { const double sc = recip(sqrt(piv[j])); l = make_double2(sr[a][b] * sc, si[a][b] * sc); }
+            else if (j == i) l = make_double2(sqrt(piv[j]), 0.0);
+            if (j <= i) { const double sc = recip(sqrt(piv[i])); x = make_double2(xr[a][b] * sc, xi[a][b] * sc); }
+            Lout[i + (long)j * ldl] = l;
+            Linv[i + (long)j * ldi] = x;
+        }
+    if (tid == 0 && bad_s && info) atomicCAS(info, 0, base + bad_s);
+}
+
+// max and min Cholesky pivot ratio estimate: diag of L (ld) -> out[0] = max |L_ii|^2, out[1] = min |L_ii|^2
+__global__ void diag_range_kernel(const double2* __restrict__ L, int n, int ld, double* out) {
+    __shared__ double mx[256], mn[256];
+    double a = 0.0, b = 1e308;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double v = L[i + (long)i * ld].x;
+        a = fmax(a, v * v);
+        b = fmin(b, v * v);
+    }
+    mx[threadIdx.x] = a;
+    mn[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+            mn[threadIdx.x] = fmin(mn[threadIdx.x], mn[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = mx[0]; out[1] = mn[0]; }
+}
+
+// y = alpha op(A) x + beta y, op = conjugate transpose: one workgroup per output
+// entry j (a length-m dot product of column j), A column-major m x n.
+__global__ void __launch_bounds__(256)
+zgemv_c_kernel(int m, const double2* __restrict__ A, int lda, const double2* __restrict__ x, double2* y,
+               double2 alpha, double2 beta) {
+    const int j = blockIdx.x;
+    __shared__ double rr[256], ri[256];
+    double sr = 0.0, si = 0.0;
+    const double2* col = A + (long)j * lda;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        const double2 a = col[i], v = x[i];
+        sr += a.x * v.x + a.y * v.y;
+        si += a.x * v.y - a.y * v.x;
+    }
+    rr[threadIdx.x] = sr;
+    ri[threadIdx.x] = si;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) { rr[threadIdx.x] += rr[threadIdx.x + w]; ri[threadIdx.x] += ri[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double2 o = make_double2(alpha.x * rr[0] - alpha.y * ri[0], alpha.x * ri[0] + alpha.y * rr[0]);
+        if (beta.x != 0.0 || beta.y != 0.0) {
+            const double2 c = y[j];
+            o.x += beta.x * c.x - beta.y * c.y;
+            o.y += beta.x * c.y + beta.y * c.x;
+        }
+        y[j] = o;
+    }
+}
+
+// y += alpha A x (A column-major m x n): thread per row, 64-column chunks per
+// workgroup, partial sums added atomically (y pre-scaled by beta separately).
+__global__ void __launch_bounds__(256)
+zgemv_n_kernel(int m, int n, const double2* __restrict__ A, int lda, const double2* __restrict__ x, double* y,
+               double2 alpha) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j0 = blockIdx.y * 64;
+    const int j1 = min(n, j0 + 64);
+    if (i >= m) return;
+    double sr = 0.0, si = 0.0;
+    const double2* a = A + i;
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+        const double2 av = a[(long)j * lda], v = x[j];
+        sr += av.x * v.x - av.y * v.y;
+        si += av.x * v.y + av.y * v.x;
+    }
+    atomicAdd(&y[2 * i], alpha.x * sr - alpha.y * si);
+    atomicAdd(&y[2 * i + 1], alpha.x * si + alpha.y * sr);
+}
+
+__global__ void zscale_kernel(int m, double2* y, double2 beta) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const double2 c = y[i];
+    y[i] = make_double2(beta.x * c.x - beta.y * c.y, beta.x * c.y + beta.y * c.x);
+}
+
+// out[slot] += sum |v|^2 (one workgroup per 256*16 entries, double atomics)
+__global__ void __launch_bounds__(256) znorm2_kernel(int m, const double2* __restrict__ v, double* out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
+        const double2 a = v[i];
+        s += a.x * a.x + a.y * a.y;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+// normalise v (length n <= 64k) to unit norm in one workgroup, store the old norm
+__global__ void __launch_bounds__(256) znormalize_kernel(int n, double2* v, double* norm_out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += v[i].x * v[i].x + v[i].y * v[i].y;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double nrm = sqrt(red[0]);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) { v[i].x *= inv; v[i].y *= inv; }
+    if (threadIdx.x == 0) *norm_out = nrm;
+}
+
+// scale columns by 1/s (s from col_norms); a zero or non-finite norm raises flag bits
+__global__ void scale_cols_checked_kernel(double2* A, int m, int lda, const double* __restrict__ s, int* flags) {
+    const int c = blockIdx.y;
+    const double v = s[c];
+    const bool ok = v > 0.0 && v < 1e300;
+    if (!ok) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(flags, v == 0.0 ? 1 : 2);
+        return;
+    }
+    const double f = 1.0 / v;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < m; r += gridDim.x * blockDim.x) {
+        double2* p = A + r + (long)c * lda;
+        p->x *= f;
+        p->y *= f;
+    }
+}
+
+// ---------------------------------------------------------------- packed (block-sparse) interface matrix
+// Qbar's rows of subdomain i only touch the unknown blocks of that subdomain,
+// so it is stored as one dense block A_i (m_i x s_i, column-major) per
+// subdomain.  Packed column pc (global numbering over all subdomains) belongs
+// to subdomain pc_sub[pc], is column pc_p[pc] of its block and column
+// pc_gcol[pc] of Qbar; it is coefA Q_i(:, colA) + coefB Q_i(:, colB).
+struct PackedDesc {
+    const double2* const* Q;   // per subdomain: its projector's Q (ld = m_i)
+    const int* m;              // rows per subdomain
+    const long* off;           // start of A_i in the packed buffer
+    const int* s;              // packed columns per subdomain
+    const int* pc_sub;
+    const int* pc_p;
+    const int* pc_gcol;
+    const int4* pc_cols;       // (colA, colB, -, -), -1 = absent
+    const double2* pc_coef;    // 2 per packed column
+    const long* roff;          // first row of subdomain i in the stacked right-hand side
+};
+
+__global__ void assemble_packed_kernel(PackedDesc d, double2* __restrict__ Ap) {
+    const int pc = blockIdx.y;
+    const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
+    const int4 cm = d.pc_cols[pc];
+    const double2 wa = d.pc_coef[2 * pc], wb = d.pc_coef[2 * pc + 1];
+    const double2* Q = d.Q[i];
+    double2* out = Ap + d.off[i] + (long)p * m;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < m; r += gridDim.x * blockDim.x) {
         double2 v = make_double2(0.0, 0.0);
-        if (i < nb && j < nb) v = G[i + (long)j * ldg];
-        else if (i == j) v = make_double2(1.0, 0.0);  // identity padding keeps the factor regular
-        if (i == j && i < nb) v.x += shift;
-        S[i][j] = v;
+        if (cm.x >= 0) {
+            const double2 q = Q[r + (long)cm.x * m];
+            v.x += wa.x * q.x - wa.y * q.y;
+            v.y += wa.x * q.y + wa.y * q.x;
+        }
+        if (cm.y >= 0) {
+            const double2 q = Q[r + (long)cm.y * m];
+            v.x += wb.x * q.x - wb.y * q.y;
+            v.y += wb.x * q.y + wb.y * q.x;
+        }
+        out[r] = v;
     }
+}
+
+// norms2[gcol] += ||packed column||^2 (one workgroup per packed column)
+__global__ void __launch_bounds__(256) packed_colnorm2_kernel(PackedDesc d, const double2* __restrict__ Ap,
+                                                              double* norms2) {
+    const int pc = blockIdx.x;
+    const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
+    const double2* col = Ap + d.off[i] + (long)p * m;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int r = threadIdx.x; r < m; r += 256) s += col[r].x * col[r].x + col[r].y * col[r].y;
+    red[threadIdx.x] = s;
     __syncthreads();
-    for (int k = 0; k < NB; ++k) {
-        // pivot
-        if (tid == 0) {
-            double d = S[k][k].x;
-            if (!(d > 0.0)) {
-                if (!bad) bad = k + 1;
-                d = 1.0;
-            }
-            S[k][k] = make_double2(sqrt(d), 0.0);
-        }
-        __syncthreads();
-        double dk = S[k][k].x;
-        for (int i = k + 1 + tid; i < NB; i += 256) {
-            S[i][k].x /= dk;
-            S[i][k].y /= dk;
-        }
-        __syncthreads();
-        // trailing update of the lower triangle: S(i,j) -= L(i,k) conj(L(j,k)), k < j <= i
-        const int r = NB - k - 1;
-        for (int t = tid; t < r * r; t += 256) {
-            int i = k + 1 + t % r, j = k + 1 + t / r;
-            if (j > i) continue;
-            double2 a = S[i][k], b = S[j][k];
-            S[i][j].x -= a.x * b.x + a.y * b.y;
-            S[i][j].y -= a.y * b.x - a.x * b.y;
-        }
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    // inverse of the lower-triangular factor, one column per thread: L X = I
-    if (tid < NB) {
-        const int c = tid;
-        for (int i = 0; i < NB; ++i) {
-            if (i < c) { X[i][c] = make_double2(0.0, 0.0); continue; }
-            double sr = (i == c) ? 1.0 : 0.0, si = 0.0;
-            for (int k = c; k < i; ++k) {
-                double2 l = S[i][k], x = X[k][c];
-                sr -= l.x * x.x - l.y * x.y;
-                si -= l.x * x.y + l.y * x.x;
-            }
-            double d = S[i][i].x;
-            X[i][c] = make_double2(sr / d, si / d);
-        }
+    if (threadIdx.x == 0) atomicAdd(&norms2[d.pc_gcol[pc]], red[0]);
+}
+
+// norms = sqrt(norms2); zero / non-finite norms raise flag bits 1 / 2
+__global__ void finalize_norms_kernel(int n, const double* __restrict__ norms2, double* norms, int* flags) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const double v = norms2[c];
+    if (!(v < 1e300)) { atomicOr(flags, 2); norms[c] = 1.0; return; }
+    if (!(v > 0.0)) { atomicOr(flags, 1); norms[c] = 1.0; return; }
+    norms[c] = sqrt(v);
+}
+
+__global__ void packed_scale_kernel(PackedDesc d, double2* Ap, const double* __restrict__ norms) {
+    const int pc = blockIdx.y;
+    const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
+    const double f = 1.0 / norms[d.pc_gcol[pc]];
+    double2* col = Ap + d.off[i] + (long)p * m;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < m; r += gridDim.x * blockDim.x) {
+        col[r].x *= f;
+        col[r].y *= f;
     }
+}
+
+// y[gcol] += alpha * A_i(:, p)^* v_i (one workgroup per packed column)
+__global__ void __launch_bounds__(256) packed_ahx_kernel(PackedDesc d, const double2* __restrict__ Ap,
+                                                         const double2* __restrict__ v, double2 alpha, double* y) {
+    const int pc = blockIdx.x;
+    const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
+    const double2* col = Ap + d.off[i] + (long)p * m;
+    const double2* vi = v + d.roff[i];
+    __shared__ double rr[256], ri[256];
+    double sr = 0.0, si = 0.0;
+    for (int r = threadIdx.x; r < m; r += 256) {
+        const double2 a = col[r], b = vi[r];
+        sr += a.x * b.x + a.y * b.y;
+        si += a.x * b.y - a.y * b.x;
+    }
+    rr[threadIdx.x] = sr;
+    ri[threadIdx.x] = si;
     __syncthreads();
-    for (int t = tid; t < nb * nb; t += 256) {
-        int i = t % nb, j = t / nb;
-        Lout[i + (long)j * ldl] = (j <= i) ? S[i][j] : make_double2(0.0, 0.0);
-        Linv[i + (long)j * ldi] = (j <= i) ? X[i][j] : make_double2(0.0, 0.0);
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) { rr[threadIdx.x] += rr[threadIdx.x + w]; ri[threadIdx.x] += ri[threadIdx.x + w]; }
+        __syncthreads();
     }
-    if (tid == 0 && bad && info) atomicCAS(info, 0, base + bad);
+    if (threadIdx.x == 0) {
+        const int g = d.pc_gcol[pc];
+        atomicAdd(&y[2 * g], alpha.x * rr[0] - alpha.y * ri[0]);
+        atomicAdd(&y[2 * g + 1], alpha.x * ri[0] + alpha.y * rr[0]);
+    }
+}
+
+// r_i += alpha * A_i x(gcol of its columns): thread per row, 32-column chunks, atomics
+__global__ void __launch_bounds__(256) packed_ax_kernel(PackedDesc d, const double2* __restrict__ Ap,
+                                                        const double2* __restrict__ x, const int* __restrict__ pc_start,
+                                                        double2 alpha, double* r) {
+    const int i = blockIdx.z;
+    const int m = d.m[i], s = d.s[i];
+    const int row = blockIdx.x * 256 + threadIdx.x;
+    const int c0 = blockIdx.y * 32;
+    if (row >= m || c0 >= s) return;
+    const double2* A = Ap + d.off[i];
+    const int pcb = pc_start[i];
+    double sr = 0.0, si = 0.0;
+    const int c1 = min(s, c0 + 32);
+    for (int c = c0; c < c1; ++c) {
+        const double2 a = A[row + (long)c * m], v = x[d.pc_gcol[pcb + c]];
+        sr += a.x * v.x - a.y * v.y;
+        si += a.x * v.y + a.y * v.x;
+    }
+    double* o = r + 2 * (d.roff[i] + row);
+    atomicAdd(&o[0], alpha.x * sr - alpha.y * si);
+    atomicAdd(&o[1], alpha.x * si + alpha.y * sr);
+}
+
+// G(gcol(p1), gcol(p2)) += Gi(p1, p2) for the packed columns of one subdomain
+__global__ void scatter_gram_kernel(const double2* __restrict__ Gi, int s, const int* __restrict__ gcol, double2* G,
+                                    int ldg) {
+    const int p1 = blockIdx.x * blockDim.x + threadIdx.x, p2 = blockIdx.y;
+    if (p1 >= s) return;
+    const double2 v = Gi[p1 + (long)p2 * s];
+    double2* o = G + gcol[p1] + (long)gcol[p2] * ldg;
+    o->x += v.x;
+    o->y += v.y;
+}
+
+// y += x (complex vectors)
+__global__ void zaxpy1_kernel(int n, const double2* __restrict__ x, double2* y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { y[i].x += x[i].x; y[i].y += x[i].y; }
 }
 
 // Qbar(r, c) for rows of subdomain s: sum of up to two weighted columns of Q_s.
@@ -325,10 +728,25 @@ inline unsigned blocks_for(long total) {
 }  // namespace
 
 void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const double2* A, int lda,
-                  const double2* B, int ldb, double2 beta, double2* C, int ldc, DevBuf& P, hipStream_t st) {
+                  const double2* B, int ldb, double2 beta, double2* C, int ldc, DevBuf& P, hipStream_t st, int tri) {
     if (m <= 0 || n <= 0) return;
+    if (n == 1 && tri == 0) {   // matrix-vector products
+        if (opB != 'N') throw Error(MDP_ERR_ARG, "gemv with a transposed vector");
+        if (opA == 'C')
+            hipLaunchKernelGGL(zgemv_c_kernel, dim3(m), dim3(256), 0, st, k, A, lda, B, C, alpha, beta);
+        else {
+            if (!(beta.x == 1.0 && beta.y == 0.0))
+                hipLaunchKernelGGL(zscale_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, C, beta);
+            hipLaunchKernelGGL(zgemv_n_kernel, dim3((m + 255) / 256, (k + 63) / 64), dim3(256), 0, st, m, k, A, lda,
+                               B, (double*)C, alpha);
+        }
+        MDP_HIP(hipGetLastError());
+        return;
+    }
     const int oa = (opA == 'C') ? 1 : 0, ob = (opB == 'C') ? 1 : 0;
-    const int mt = (m + ZBM - 1) / ZBM, nt = (n + ZBN - 1) / ZBN;
+    // 64x64 tiles when they fill the chip, 32x32 for small products
+    const int tile = ((long)((m + 63) / 64) * ((n + 63) / 64) >= 128) ? 64 : 32;
+    const int mt = (m + tile - 1) / tile, nt = (n + tile - 1) / tile;
     const int tiles = mt * nt;
     int nsplit = 1;
     if (k > 0 && tiles < 512) {
@@ -340,33 +758,34 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
     kchunk = (kchunk + ZBK - 1) / ZBK * ZBK;
     if (kchunk < ZBK) kchunk = ZBK;
     nsplit = (k > 0) ? (k + kchunk - 1) / kchunk : 1;
-    if (nsplit <= 1) {
-        hipLaunchKernelGGL(zgemm_kernel, dim3(tiles, 1), dim3(256), 0, st, oa, ob, m, n, k, A, lda, B, ldb, C, ldc,
-                           alpha, beta, kchunk, (double2*)nullptr, 0L, mt);
-        MDP_HIP(hipGetLastError());
-        return;
-    }
     const long pstride = (long)m * n;
-    const size_t need = (size_t)pstride * nsplit * sizeof(double2);
-    if (need > P.bytes) {   // never free a buffer earlier kernels may still read
-        MDP_HIP(hipDeviceSynchronize());
-        P.reserve(need);
+    double2* part = nullptr;
+    if (nsplit > 1) {
+        const size_t need = (size_t)pstride * nsplit * sizeof(double2);
+        if (need > P.bytes) {   // never free a buffer earlier kernels may still read
+            MDP_HIP(hipDeviceSynchronize());
+            P.reserve(need);
+        }
+        part = P.as<double2>();
     }
-    hipLaunchKernelGGL(zgemm_kernel, dim3(tiles, nsplit), dim3(256), 0, st, oa, ob, m, n, k, A, lda, B, ldb, C, ldc,
-                       alpha, beta, kchunk, P.as<double2>(), pstride, mt);
+    if (tile == 64)
+        hipLaunchKernelGGL(zgemm_kernel<64>, dim3(tiles, nsplit), dim3(256), 0, st, oa, ob, m, n, k, A, lda, B, ldb,
+                           C, ldc, alpha, beta, kchunk, part, pstride, mt, tri);
+    else
+        hipLaunchKernelGGL(zgemm_kernel<32>, dim3(tiles, nsplit), dim3(256), 0, st, oa, ob, m, n, k, A, lda, B, ldb,
+                           C, ldc, alpha, beta, kchunk, part, pstride, mt, tri);
     MDP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(zgemm_reduce_kernel, dim3(blocks_for(pstride)), dim3(256), 0, st, m, n, nsplit,
-                       P.as<double2>(), pstride, C, ldc, alpha, beta);
-    MDP_HIP(hipGetLastError());
+    if (nsplit > 1) {
+        hipLaunchKernelGGL(zgemm_reduce_kernel, dim3((m + 255) / 256, n), dim3(256), 0, st, m, n, nsplit, part,
+                           pstride, C, ldc, alpha, beta, tri, tile);
+        MDP_HIP(hipGetLastError());
+    }
 }
 
 void launch_chol_block(const double2* G, int ldg, int nb, double shift, double2* L, int ldl, double2* Linv, int ldi,
                        int* info, int base, hipStream_t st) {
-    if (nb <= 32)
-        hipLaunchKernelGGL(chol_block_kernel<32>, dim3(1), dim3(256), 0, st, G, ldg, nb, shift, L, ldl, Linv, ldi,
-                           info, base);
-    else if (nb <= 64)
-        hipLaunchKernelGGL(chol_block_kernel<64>, dim3(1), dim3(256), 0, st, G, ldg, nb, shift, L, ldl, Linv, ldi,
+    if (nb <= 64)
+        hipLaunchKernelGGL(chol_block_kernel<4>, dim3(1), dim3(256), 0, st, G, ldg, nb, shift, L, ldl, Linv, ldi,
                            info, base);
     else
         throw Error(MDP_ERR_ARG, "Cholesky block too large");
@@ -395,6 +814,80 @@ void launch_col_norms(const double2* A, int m, int n, int lda, double* out, hipS
 
 void launch_scale_cols(double2* A, int m, int n, int lda, const double* s, int invert, hipStream_t st) {
     hipLaunchKernelGGL(scale_cols_kernel, dim3(blocks_for((long)m * n)), dim3(256), 0, st, A, m, n, lda, s, invert);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_znorm2(int m, const double2* v, double* out, hipStream_t st) {
+    int g = std::min(1024, std::max(1, (m + 4095) / 4096));
+    hipLaunchKernelGGL(znorm2_kernel, dim3(g), dim3(256), 0, st, m, v, out);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_znormalize(int n, double2* v, double* norm_out, hipStream_t st) {
+    hipLaunchKernelGGL(znormalize_kernel, dim3(1), dim3(256), 0, st, n, v, norm_out);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_scale_cols_checked(double2* A, int m, int n, int lda, const double* s, int* flags, hipStream_t st) {
+    dim3 grid(std::max(1, std::min((m + 255) / 256, 64)), n);
+    hipLaunchKernelGGL(scale_cols_checked_kernel, grid, dim3(256), 0, st, A, m, lda, s, flags);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_assemble_packed(const PackedDevice& d, int total_pc, int max_m, double2* Ap, hipStream_t st) {
+    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
+    dim3 grid(std::max(1, std::min((max_m + 255) / 256, 64)), total_pc);
+    hipLaunchKernelGGL(assemble_packed_kernel, grid, dim3(256), 0, st, pd, Ap);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_packed_colnorm2(const PackedDevice& d, int total_pc, const double2* Ap, double* norms2, hipStream_t st) {
+    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
+    hipLaunchKernelGGL(packed_colnorm2_kernel, dim3(total_pc), dim3(256), 0, st, pd, Ap, norms2);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_finalize_norms(int n, const double* norms2, double* norms, int* flags, hipStream_t st) {
+    hipLaunchKernelGGL(finalize_norms_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, norms2, norms, flags);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_packed_scale(const PackedDevice& d, int total_pc, int max_m, double2* Ap, const double* norms,
+                         hipStream_t st) {
+    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
+    dim3 grid(std::max(1, std::min((max_m + 255) / 256, 64)), total_pc);
+    hipLaunchKernelGGL(packed_scale_kernel, grid, dim3(256), 0, st, pd, Ap, norms);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_packed_ahx(const PackedDevice& d, int total_pc, const double2* Ap, const double2* v, double2 alpha,
+                       double2* y, hipStream_t st) {
+    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
+    hipLaunchKernelGGL(packed_ahx_kernel, dim3(total_pc), dim3(256), 0, st, pd, Ap, v, alpha, (double*)y);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_packed_ax(const PackedDevice& d, int n_sub, int max_m, int max_s, const double2* Ap, const double2* x,
+                      double2 alpha, double2* r, hipStream_t st) {
+    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
+    dim3 grid((max_m + 255) / 256, (max_s + 31) / 32, n_sub);
+    hipLaunchKernelGGL(packed_ax_kernel, grid, dim3(256), 0, st, pd, Ap, x, d.pc_start, alpha, (double*)r);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_scatter_gram(const double2* Gi, int s, const int* gcol, double2* G, int ldg, hipStream_t st) {
+    dim3 grid((s + 255) / 256, s);
+    hipLaunchKernelGGL(scatter_gram_kernel, grid, dim3(256), 0, st, Gi, s, gcol, G, ldg);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_zaxpy1(int n, const double2* x, double2* y, hipStream_t st) {
+    hipLaunchKernelGGL(zaxpy1_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, x, y);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_diag_range(const double2* L, int n, int ld, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(diag_range_kernel, dim3(1), dim3(256), 0, st, L, n, ld, out);
     MDP_HIP(hipGetLastError());
 }
 

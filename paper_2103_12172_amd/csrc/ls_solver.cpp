@@ -12,11 +12,14 @@
 // factors.  Every pass is complex FP64 GEMM on the matrix cores (Gram, the
 // blocked triangular inverse, the product with it) plus one small Cholesky per
 // 64-column diagonal block, instead of the long chain of column-by-column
-// reflector kernels a Householder factorisation would need on a GPU.  One step
-// of least-squares refinement with the same factors follows.
+// reflector kernels a Householder factorisation needs.  One step of
+// least-squares refinement with the same factors follows.  The host waits for
+// the device once, at the end (and once more when the shift is needed).
 #include "ls_solver.h"
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -27,16 +30,26 @@ namespace {
 constexpr int NB = 64;
 const double2 ONE = {1.0, 0.0}, ZERO = {0.0, 0.0}, MONE = {-1.0, 0.0};
 
-struct LSBufs {
-    DevBuf G, L, Linv[3], T, A0, Aw, Aq, F, y, z, x, r, info, norms;
+// device scalars written by the kernels and read back once
+struct Flags {
+    int info;      // first failing Cholesky pivot (1-based) of any pass
+    int badcol;    // 1: zero column, 2: non-finite column
+    double r2;     // ||F - A x||^2
+    double f2;     // ||F||^2
+    double pw[2];  // power-iteration norms
 };
 
-// Blocked lower Cholesky G = L L^* (G is overwritten by the trailing updates)
-// and the blocked inverse Linv = L^{-1}.  Returns the 1-based index of the
-// first failing pivot, 0 on success.
-int cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* T, int* info_dev, int nc, double shift,
-                         Workspace& ws, hipStream_t st) {
-    MDP_HIP(hipMemsetAsync(info_dev, 0, sizeof(int), st));
+void grow(DevBuf& b, size_t bytes) {
+    if (bytes > b.bytes) {
+        MDP_HIP(hipDeviceSynchronize());
+        b.reserve(bytes);
+    }
+}
+
+// Blocked lower Cholesky G = L L^* (G's lower triangle is overwritten by the
+// trailing updates) and the blocked inverse Linv = L^{-1}.
+void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* T, int* info_dev, int nc, double shift,
+                          Workspace& ws, hipStream_t st) {
     MDP_HIP(hipMemsetAsync(L, 0, sizeof(double2) * (size_t)nc * nc, st));
     MDP_HIP(hipMemsetAsync(Linv, 0, sizeof(double2) * (size_t)nc * nc, st));
     for (int kb = 0; kb < nc; kb += NB) {
@@ -48,10 +61,10 @@ int cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* T, int*
             // panel: L(below, k) = G(below, k) L_kk^{-*}
             launch_zgemm('N', 'C', rest, nbk, nbk, ONE, G + (kb + nbk) + (size_t)kb * nc, nc,
                          Linv + kb + (size_t)kb * nc, nc, ZERO, L + (kb + nbk) + (size_t)kb * nc, nc, ws.zg, st);
-            // trailing update: G(below, below) -= L(below, k) L(below, k)^*
+            // trailing update of the lower triangle: G(below, below) -= L(below, k) L(below, k)^*
             launch_zgemm('N', 'C', rest, rest, nbk, MONE, L + (kb + nbk) + (size_t)kb * nc, nc,
                          L + (kb + nbk) + (size_t)kb * nc, nc, ONE, G + (kb + nbk) + (size_t)(kb + nbk) * nc, nc,
-                         ws.zg, st);
+                         ws.zg, st, 1);
         }
     }
     // block rows of the inverse: Linv(i, 0:i) = -Linv_ii L(i, 0:i) Linv(0:i, 0:i)
@@ -61,163 +74,302 @@ int cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* T, int*
         launch_zgemm('N', 'N', nbi, ib, nbi, MONE, Linv + ib + (size_t)ib * nc, nc, T, nbi, ZERO, Linv + ib, nc,
                      ws.zg, st);
     }
-    int info = 0;
-    MDP_HIP(hipMemcpyAsync(&info, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
-    MDP_HIP(hipStreamSynchronize(st));
-    return info;
-}
-
-double host_norm(const double2* dev, int m, hipStream_t st) {
-    std::vector<double2> h(m);
-    MDP_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double2) * m, hipMemcpyDeviceToHost, st));
-    MDP_HIP(hipStreamSynchronize(st));
-    double s = 0.0;
-    for (auto& v : h) s += v.x * v.x + v.y * v.y;
-    return std::sqrt(s);
 }
 
 }  // namespace
 
-// A: m x nc (ld m, device) -- overwritten; F: m (device); x_out: nc (device).
 LSResult ls_solve(Workspace& ws, double2* A, const double2* F, int m, int nc, double2* x_out, bool want_cond,
                   hipStream_t st) {
     if (m < nc) throw Error(MDP_ERR_ARG, "least squares needs at least as many rows as unknowns");
     LSResult res{};
-    LSBufs b;
+    LSWork& w = ws.ls;
     const size_t nn = (size_t)nc * nc, mn = (size_t)m * nc;
-    b.G.alloc(nn * sizeof(double2));
-    b.L.alloc(nn * sizeof(double2));
-    for (auto& l : b.Linv) l.alloc(nn * sizeof(double2));
-    b.T.alloc((size_t)NB * nc * sizeof(double2));
-    b.A0.alloc(mn * sizeof(double2));
-    b.Aq.alloc(mn * sizeof(double2));
-    b.y.alloc(nc * sizeof(double2));
-    b.z.alloc(nc * sizeof(double2));
-    b.x.alloc(nc * sizeof(double2));
-    b.r.alloc(m * sizeof(double2));
-    b.info.alloc(sizeof(int));
-    b.norms.alloc(nc * sizeof(double));
+    grow(w.G, nn * sizeof(double2));
+    grow(w.L, nn * sizeof(double2));
+    for (auto& l : w.Linv) grow(l, nn * sizeof(double2));
+    grow(w.T, (size_t)NB * nc * sizeof(double2));
+    grow(w.A0, mn * sizeof(double2));
+    grow(w.Aq, mn * sizeof(double2));
+    grow(w.vec, (size_t)(6 * nc + 2 * m) * sizeof(double2));
+    grow(w.norms, nc * sizeof(double));
+    grow(w.flags, sizeof(Flags));
+    double2* y = w.vec.as<double2>();
+    double2* z = y + nc;
+    double2* xv = z + nc;
+    double2* s1 = xv + nc;
+    double2* s2 = s1 + nc;
+    double2* s3 = s2 + nc;
+    double2* r = s3 + nc;
+    double2* t = r + m;
+    Flags* fl = w.flags.as<Flags>();
 
-    // column equilibration
-    launch_col_norms(A, m, nc, m, b.norms.as<double>(), st);
-    std::vector<double> norms(nc);
-    MDP_HIP(hipMemcpyAsync(norms.data(), b.norms.p, nc * sizeof(double), hipMemcpyDeviceToHost, st));
-    MDP_HIP(hipStreamSynchronize(st));
-    for (int c = 0; c < nc; ++c) {
-        if (!std::isfinite(norms[c])) throw Error(MDP_ERR_NONFINITE, "non-finite entry in the interface matrix");
-        if (!(norms[c] > 0.0)) throw Error(MDP_ERR_SINGULAR, "zero column in the interface matrix");
-    }
-    launch_scale_cols(A, m, nc, m, b.norms.as<double>(), 1, st);
-    MDP_HIP(hipMemcpyAsync(b.A0.p, A, mn * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    auto run = [&](double shift, int passes) {
+        MDP_HIP(hipMemsetAsync(&fl->info, 0, sizeof(int), st));
+        MDP_HIP(hipMemcpyAsync(A, w.A0.p, mn * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        double2* cur = A;
+        double2* nxt = w.Aq.as<double2>();
+        for (int pass = 0; pass < passes; ++pass) {
+            launch_zgemm('C', 'N', nc, nc, m, ONE, cur, m, cur, m, ZERO, w.G.as<double2>(), nc, ws.zg, st, 1);
+            cholesky_and_inverse(w.G.as<double2>(), w.L.as<double2>(), w.Linv[pass].as<double2>(), w.T.as<double2>(),
+                                 &fl->info, nc, pass == 0 ? shift : 0.0, ws, st);
+            // A <- A L^{-*}  (L^{-*} is upper triangular)
+            launch_zgemm('N', 'C', m, nc, nc, ONE, cur, m, w.Linv[pass].as<double2>(), nc, ZERO, nxt, m, ws.zg, st, 2);
+            std::swap(cur, nxt);
+        }
+        return cur;   // Q, orthonormal columns
+    };
+    // R^{-1} v = Linv_0^* Linv_1^* ... Linv_{p-1}^* v (last pass first)
+    auto apply_rinv = [&](int passes, const double2* v, double2* out, bool accumulate) {
+        const double2* src = v;
+        double2* bufs[2] = {s1, s2};
+        int tt = 0;
+        for (int p = passes - 1; p >= 0; --p) {
+            double2* dst = (p == 0) ? out : bufs[tt];
+            launch_zgemm('C', 'N', nc, 1, nc, ONE, w.Linv[p].as<double2>(), nc, src, nc,
+                         (p == 0 && accumulate) ? ONE : ZERO, dst, nc, ws.zg, st);
+            src = dst;
+            tt ^= 1;
+        }
+    };
 
-    double2* cur = A;
-    double2* nxt = b.Aq.as<double2>();
+    // column equilibration (A0 keeps the scaled matrix)
+    MDP_HIP(hipMemsetAsync(fl, 0, sizeof(Flags), st));
+    launch_col_norms(A, m, nc, m, w.norms.as<double>(), st);
+    launch_scale_cols_checked(A, m, nc, m, w.norms.as<double>(), &fl->badcol, st);
+    MDP_HIP(hipMemcpyAsync(w.A0.p, A, mn * sizeof(double2), hipMemcpyDeviceToDevice, st));
+
     int passes = 2;
     double shift = 0.0;
-    for (int pass = 0; pass < passes; ++pass) {
-        launch_zgemm('C', 'N', nc, nc, m, ONE, cur, m, cur, m, ZERO, b.G.as<double2>(), nc, ws.zg, st);
-        int info = cholesky_and_inverse(b.G.as<double2>(), b.L.as<double2>(), b.Linv[pass].as<double2>(),
-                                        b.T.as<double2>(), b.info.as<int>(), nc, pass == 0 ? shift : 0.0, ws, st);
-        if (info && pass == 0 && shift == 0.0) {
-            // numerically indefinite Gram matrix: shifted first pass, one extra pass
-            const double u = 1.1102230246251565e-16;
-            shift = 11.0 * ((double)m * nc + (double)nc * (nc + 1)) * u * (double)nc;
-            passes = 3;
-            launch_zgemm('C', 'N', nc, nc, m, ONE, cur, m, cur, m, ZERO, b.G.as<double2>(), nc, ws.zg, st);
-            info = cholesky_and_inverse(b.G.as<double2>(), b.L.as<double2>(), b.Linv[0].as<double2>(),
-                                        b.T.as<double2>(), b.info.as<int>(), nc, shift, ws, st);
-        }
-        if (info) throw Error(MDP_ERR_SINGULAR, "interface least squares: Cholesky-QR broke down (rank deficient)");
-        // A <- A L^{-*}
-        launch_zgemm('N', 'C', m, nc, nc, ONE, cur, m, b.Linv[pass].as<double2>(), nc, ZERO, nxt, m, ws.zg, st);
-        std::swap(cur, nxt);
+    Flags hf{};
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        double2* Q = run(shift, passes);
+        // x = R^{-1} Q^* F, then one refinement step x += R^{-1} Q^* (F - A0 x)
+        launch_zgemm('C', 'N', nc, 1, m, ONE, Q, m, F, m, ZERO, y, nc, ws.zg, st);
+        apply_rinv(passes, y, xv, false);
+        MDP_HIP(hipMemcpyAsync(r, F, m * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        launch_zgemm('N', 'N', m, 1, nc, MONE, w.A0.as<double2>(), m, xv, nc, ONE, r, m, ws.zg, st);
+        launch_zgemm('C', 'N', nc, 1, m, ONE, Q, m, r, m, ZERO, y, nc, ws.zg, st);
+        apply_rinv(passes, y, xv, true);
+        // final residual
+        MDP_HIP(hipMemcpyAsync(r, F, m * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        launch_zgemm('N', 'N', m, 1, nc, MONE, w.A0.as<double2>(), m, xv, nc, ONE, r, m, ws.zg, st);
+        MDP_HIP(hipMemsetAsync(&fl->r2, 0, 2 * sizeof(double), st));
+        launch_znorm2(m, r, &fl->r2, st);
+        launch_znorm2(m, F, &fl->f2, st);
+        MDP_HIP(hipMemcpyAsync(&hf, fl, sizeof(Flags), hipMemcpyDeviceToHost, st));
+        MDP_HIP(hipStreamSynchronize(st));
+        if (hf.badcol & 2) throw Error(MDP_ERR_NONFINITE, "non-finite entry in the interface matrix");
+        if (hf.badcol & 1) throw Error(MDP_ERR_SINGULAR, "zero column in the interface matrix");
+        if (!hf.info) break;
+        if (attempt == 1) throw Error(MDP_ERR_SINGULAR, "interface least squares: Cholesky-QR broke down");
+        // numerically indefinite Gram matrix: shifted first pass and one extra pass
+        const double u = 1.1102230246251565e-16;
+        shift = 11.0 * ((double)m * nc + (double)nc * (nc + 1)) * u * (double)nc;
+        passes = 3;
     }
     res.shifted = shift != 0.0;
     res.passes = passes;
-
-    // x = R^{-1} Q^* F with R^{-1} = Linv_0^* Linv_1^* ... Linv_{p-1}^* (apply the last pass first);
-    // `accumulate` adds the result to `out` instead of overwriting it.
-    DevBuf s1(nc * sizeof(double2)), s2(nc * sizeof(double2));
-    auto apply_rinv = [&](const double2* v, double2* out, bool accumulate) {
-        const double2* src = v;
-        double2* bufs[2] = {s1.as<double2>(), s2.as<double2>()};
-        int t = 0;
-        for (int p = passes - 1; p >= 0; --p) {
-            double2* dst = (p == 0) ? out : bufs[t];
-            launch_zgemm('C', 'N', nc, 1, nc, ONE, b.Linv[p].as<double2>(), nc, src, nc,
-                         (p == 0 && accumulate) ? ONE : ZERO, dst, nc, ws.zg, st);
-            src = dst;
-            t ^= 1;
-        }
-    };
-    double2* Qf = cur;
-    DevBuf qtf(nc * sizeof(double2));
-    launch_zgemm('C', 'N', nc, 1, m, ONE, Qf, m, F, m, ZERO, qtf.as<double2>(), nc, ws.zg, st);
-    apply_rinv(qtf.as<double2>(), b.x.as<double2>(), false);
-    // one refinement step: r = F - A0 x, x += R^{-1} Q^* r
-    MDP_HIP(hipMemcpyAsync(b.r.p, F, m * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    launch_zgemm('N', 'N', m, 1, nc, MONE, b.A0.as<double2>(), m, b.x.as<double2>(), nc, ONE, b.r.as<double2>(), m,
-                 ws.zg, st);
-    launch_zgemm('C', 'N', nc, 1, m, ONE, Qf, m, b.r.as<double2>(), m, ZERO, qtf.as<double2>(), nc, ws.zg, st);
-    apply_rinv(qtf.as<double2>(), b.x.as<double2>(), true);
-    // residual
-    MDP_HIP(hipMemcpyAsync(b.r.p, F, m * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    launch_zgemm('N', 'N', m, 1, nc, MONE, b.A0.as<double2>(), m, b.x.as<double2>(), nc, ONE, b.r.as<double2>(), m,
-                 ws.zg, st);
-    const double nf = host_norm(F, m, st);
-    res.rel_residual = host_norm(b.r.as<double2>(), m, st) / (nf > 0 ? nf : 1.0);
+    res.rel_residual = std::sqrt(hf.r2) / (hf.f2 > 0 ? std::sqrt(hf.f2) : 1.0);
 
     // unscale: c = x / norms
-    launch_scale_cols(b.x.as<double2>(), 1, nc, 1, b.norms.as<double>(), 1, st);
-    MDP_HIP(hipMemcpyAsync(x_out, b.x.p, nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_scale_cols(xv, 1, nc, 1, w.norms.as<double>(), 1, st);
+    MDP_HIP(hipMemcpyAsync(x_out, xv, nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
 
     if (want_cond) {
-        // power iterations for sigma_max(A0) (on A0^* A0) and sigma_min (on R^{-1} R^{-*})
+        // power iterations: sigma_max(A0)^2 on A0^* A0, 1/sigma_min^2 on R^{-1} R^{-*}
         std::vector<double2> hv(nc);
         for (int i = 0; i < nc; ++i) hv[i] = make_double2(1.0 + 0.001 * (i % 7), 0.37 * ((i * 13) % 5));
-        DevBuf v(nc * sizeof(double2)), w(nc * sizeof(double2)), t(m * sizeof(double2));
-        auto normalize = [&](DevBuf& vec) {
-            std::vector<double2> h(nc);
-            MDP_HIP(hipMemcpyAsync(h.data(), vec.p, nc * sizeof(double2), hipMemcpyDeviceToHost, st));
-            MDP_HIP(hipStreamSynchronize(st));
-            double s = 0;
-            for (auto& e : h) s += e.x * e.x + e.y * e.y;
-            s = std::sqrt(s);
-            for (auto& e : h) { e.x /= s; e.y /= s; }
-            MDP_HIP(hipMemcpyAsync(vec.p, h.data(), nc * sizeof(double2), hipMemcpyHostToDevice, st));
-            MDP_HIP(hipStreamSynchronize(st));
-            return s;
-        };
-        MDP_HIP(hipMemcpyAsync(v.p, hv.data(), nc * sizeof(double2), hipMemcpyHostToDevice, st));
-        normalize(v);
-        double lmax = 0.0;
+        double2* v = s3;
+        MDP_HIP(hipMemcpyAsync(v, hv.data(), nc * sizeof(double2), hipMemcpyHostToDevice, st));
+        launch_znormalize(nc, v, &fl->pw[0], st);
         for (int it = 0; it < 12; ++it) {
-            launch_zgemm('N', 'N', m, 1, nc, ONE, b.A0.as<double2>(), m, v.as<double2>(), nc, ZERO, t.as<double2>(), m,
-                         ws.zg, st);
-            launch_zgemm('C', 'N', nc, 1, m, ONE, b.A0.as<double2>(), m, t.as<double2>(), m, ZERO, v.as<double2>(), nc,
-                         ws.zg, st);
-            lmax = normalize(v);
+            launch_zgemm('N', 'N', m, 1, nc, ONE, w.A0.as<double2>(), m, v, nc, ZERO, t, m, ws.zg, st);
+            launch_zgemm('C', 'N', nc, 1, m, ONE, w.A0.as<double2>(), m, t, m, ZERO, v, nc, ws.zg, st);
+            launch_znormalize(nc, v, &fl->pw[0], st);
         }
-        MDP_HIP(hipMemcpyAsync(w.p, hv.data(), nc * sizeof(double2), hipMemcpyHostToDevice, st));
-        normalize(w);
-        double lmin_inv = 0.0;
+        MDP_HIP(hipMemcpyAsync(v, hv.data(), nc * sizeof(double2), hipMemcpyHostToDevice, st));
+        launch_znormalize(nc, v, &fl->pw[1], st);
         for (int it = 0; it < 12; ++it) {
-            // w <- R^{-1} R^{-*} w with R^{-*} = Linv_{p-1} ... Linv_1 Linv_0 (Linv_0 applied first)
-            const double2* src = w.as<double2>();
-            double2* bufs[2] = {b.z.as<double2>(), b.y.as<double2>()};
+            // v <- R^{-1} R^{-*} v with R^{-*} = Linv_{p-1} ... Linv_0 (Linv_0 applied first)
+            const double2* src = v;
+            double2* bufs[2] = {y, z};
             int tt = 0;
             for (int p = 0; p < passes; ++p) {
-                launch_zgemm('N', 'N', nc, 1, nc, ONE, b.Linv[p].as<double2>(), nc, src, nc, ZERO, bufs[tt], nc,
+                launch_zgemm('N', 'N', nc, 1, nc, ONE, w.Linv[p].as<double2>(), nc, src, nc, ZERO, bufs[tt], nc,
                              ws.zg, st);
                 src = bufs[tt];
                 tt ^= 1;
             }
-            apply_rinv(src, w.as<double2>(), false);
-            lmin_inv = normalize(w);
+            apply_rinv(passes, src, v, false);
+            launch_znormalize(nc, v, &fl->pw[1], st);
         }
-        res.cond = std::sqrt(lmax * lmin_inv);
+        MDP_HIP(hipMemcpyAsync(&hf, fl, sizeof(Flags), hipMemcpyDeviceToHost, st));
+        MDP_HIP(hipStreamSynchronize(st));
+        res.cond = std::sqrt(hf.pw[0] * hf.pw[1]);
     }
+    return res;
+}
+
+
+// ---------------------------------------------------------------------------
+// Block-sparse interface least squares (default path).
+//
+// Qbar is kept as one dense block per subdomain (its rows touch only that
+// subdomain's unknown blocks).  R is the Cholesky factor of the Gram matrix
+// Qbar^* Qbar = sum_i scatter(A_i^* A_i) -- the same R as in Qbar = Q R -- and
+// the solution is c = R^{-1} R^{-*} Qbar^* Fbar = R^{-1} Q^* Fbar, followed by
+// iterative refinement with the same factor (corrected semi-normal equations,
+// Bjorck): each step r = Fbar - Qbar c, c += R^{-1} R^{-*} Qbar^* r.  When the
+// columns are equilibrated and cond(Qbar) is moderate the corrected solution is
+// as accurate as a Householder least-squares solution; the caller falls back to
+// the dense Cholesky-QR passes when the Cholesky breaks down or the refinement
+// does not contract.
+namespace {
+
+template <class T>
+void upload_async(DevBuf& d, const std::vector<T>& v, hipStream_t st) {
+    const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    grow(d, bytes);
+    if (!v.empty()) MDP_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+struct PackedFlags {
+    int info;
+    int badcol;
+    double r2, f2, x2, dx2;
+    double pw[2];
+};
+
+}  // namespace
+
+LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, double2* x_out, bool want_cond,
+                         hipStream_t st, bool* fallback) {
+    LSResult res{};
+    *fallback = false;
+    PackedWork& w = ws.pk;
+    const int nc = h.nc, n_sub = h.n_sub, npc = h.total_pc;
+    long mtot = 0, ptot = 0;
+    for (int i = 0; i < n_sub; ++i) { mtot += h.m[i]; ptot += (long)h.m[i] * h.s[i]; }
+    // descriptors (tiny; the copies are ordered on the stream before the kernels)
+    std::vector<const double2*> q(h.Q);
+    upload_async(w.dQ, q, st);
+    upload_async(w.dm, h.m, st);
+    upload_async(w.ds, h.s, st);
+    upload_async(w.doff, h.off, st);
+    upload_async(w.droff, h.roff, st);
+    upload_async(w.dsub, h.pc_sub, st);
+    upload_async(w.dp, h.pc_p, st);
+    upload_async(w.dgcol, h.pc_gcol, st);
+    upload_async(w.dstart, h.pc_start, st);
+    upload_async(w.dcols, h.pc_cols, st);
+    upload_async(w.dcoef, h.pc_coef, st);
+    grow(w.Ap, (size_t)ptot * sizeof(double2));
+    grow(w.Gi, (size_t)h.max_s * h.max_s * sizeof(double2));
+    LSWork& lw = ws.ls;
+    const size_t nn = (size_t)nc * nc;
+    grow(lw.G, nn * sizeof(double2));
+    grow(lw.L, nn * sizeof(double2));
+    grow(lw.Linv[0], nn * sizeof(double2));
+    grow(lw.T, (size_t)NB * nc * sizeof(double2));
+    grow(lw.vec, (size_t)(6 * nc + 2 * mtot) * sizeof(double2));
+    grow(lw.norms, 2 * (size_t)nc * sizeof(double));
+    grow(lw.flags, sizeof(PackedFlags));
+    PackedDevice d{w.dQ.as<const double2* const>(), w.dm.as<int>(), w.doff.as<long>(), w.ds.as<int>(),
+                   w.dsub.as<int>(), w.dp.as<int>(), w.dgcol.as<int>(), w.dcols.as<int4>(), w.dcoef.as<double2>(),
+                   w.droff.as<long>(), w.dstart.as<int>()};
+    double2* Ap = w.Ap.as<double2>();
+    double* norms2 = lw.norms.as<double>();
+    double* norms = norms2 + nc;
+    double2* y = lw.vec.as<double2>();
+    double2* t = y + nc;
+    double2* x = t + nc;
+    double2* dx = x + nc;
+    double2* v1 = dx + nc;
+    double2* v2 = v1 + nc;
+    double2* r = v2 + nc;
+    PackedFlags* fl = lw.flags.as<PackedFlags>();
+    double2* G = lw.G.as<double2>();
+    double2* L = lw.L.as<double2>();
+    double2* Linv = lw.Linv[0].as<double2>();
+
+    MDP_HIP(hipMemsetAsync(fl, 0, sizeof(PackedFlags), st));
+    // packed blocks, equilibrated columns
+    launch_assemble_packed(d, npc, h.max_m, Ap, st);
+    MDP_HIP(hipMemsetAsync(norms2, 0, nc * sizeof(double), st));
+    launch_packed_colnorm2(d, npc, Ap, norms2, st);
+    launch_finalize_norms(nc, norms2, norms, &fl->badcol, st);
+    launch_packed_scale(d, npc, h.max_m, Ap, norms, st);
+    // Gram matrix
+    MDP_HIP(hipMemsetAsync(G, 0, nn * sizeof(double2), st));
+    for (int i = 0; i < n_sub; ++i) {
+        const int si = h.s[i], mi = h.m[i];
+        launch_zgemm('C', 'N', si, si, mi, ONE, Ap + h.off[i], mi, Ap + h.off[i], mi, ZERO, w.Gi.as<double2>(), si,
+                     ws.zg, st);
+        launch_scatter_gram(w.Gi.as<double2>(), si, w.dgcol.as<int>() + h.pc_start[i], G, nc, st);
+    }
+    cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, ws, st);
+    // c = R^{-1} R^{-*} Qbar^* F, R^{-1} = Linv^*, R^{-*} = Linv
+    auto normal_solve = [&](const double2* rhs_rows, double2* out) {
+        MDP_HIP(hipMemsetAsync(y, 0, nc * sizeof(double2), st));
+        launch_packed_ahx(d, npc, Ap, rhs_rows, ONE, y, st);
+        launch_zgemm('N', 'N', nc, 1, nc, ONE, Linv, nc, y, nc, ZERO, t, nc, ws.zg, st);
+        launch_zgemm('C', 'N', nc, 1, nc, ONE, Linv, nc, t, nc, ZERO, out, nc, ws.zg, st);
+    };
+    auto residual = [&]() {   // r = F - Qbar x (stacked rows)
+        MDP_HIP(hipMemcpyAsync(r, F, mtot * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        launch_packed_ax(d, n_sub, h.max_m, h.max_s, Ap, x, MONE, r, st);
+    };
+    normal_solve(F, x);
+    const int steps = 2;
+    for (int it = 0; it < steps; ++it) {
+        residual();
+        normal_solve(r, dx);
+        if (it == steps - 1) launch_znorm2(nc, dx, &fl->dx2, st);
+        launch_zaxpy1(nc, dx, x, st);
+    }
+    residual();
+    launch_znorm2((int)mtot, r, &fl->r2, st);
+    launch_znorm2((int)mtot, F, &fl->f2, st);
+    launch_znorm2(nc, x, &fl->x2, st);
+    PackedFlags hf{};
+    MDP_HIP(hipMemcpyAsync(&hf, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
     MDP_HIP(hipStreamSynchronize(st));
+    if (hf.badcol & 2) throw Error(MDP_ERR_NONFINITE, "non-finite entry in the interface matrix");
+    if (hf.badcol & 1) throw Error(MDP_ERR_SINGULAR, "zero column in the interface matrix");
+    // the last correction must be negligible; otherwise the Gram matrix is too ill-conditioned
+    if (hf.info || !(hf.dx2 <= 1e-22 * hf.x2)) {
+        if (std::getenv("MDP_VERBOSE"))
+            std::fprintf(stderr, "mdp: semi-normal least squares handed over (pivot failure %d, |dx|/|x| %.3e)\n",
+                         hf.info, std::sqrt(hf.dx2 / (hf.x2 > 0 ? hf.x2 : 1.0)));
+        *fallback = true;
+        return res;
+    }
+    res.passes = 1;
+    res.rel_residual = std::sqrt(hf.r2) / (hf.f2 > 0 ? std::sqrt(hf.f2) : 1.0);
+    launch_scale_cols(x, 1, nc, 1, norms, 1, st);
+    MDP_HIP(hipMemcpyAsync(x_out, x, nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if (want_cond) {
+        // cond(Qbar_eq)^2 = lambda_max(G) lambda_max(G^{-1}); G v = L (L^* v), G^{-1} v = Linv^* (Linv v)
+        std::vector<double2> hv(nc);
+        for (int i = 0; i < nc; ++i) hv[i] = make_double2(1.0 + 0.001 * (i % 7), 0.37 * ((i * 13) % 5));
+        for (int which = 0; which < 2; ++which) {
+            MDP_HIP(hipMemcpyAsync(v1, hv.data(), nc * sizeof(double2), hipMemcpyHostToDevice, st));
+            launch_znormalize(nc, v1, &fl->pw[which], st);
+            for (int it = 0; it < 16; ++it) {
+                if (which == 0) {
+                    launch_zgemm('C', 'N', nc, 1, nc, ONE, L, nc, v1, nc, ZERO, v2, nc, ws.zg, st);
+                    launch_zgemm('N', 'N', nc, 1, nc, ONE, L, nc, v2, nc, ZERO, v1, nc, ws.zg, st);
+                } else {
+                    launch_zgemm('N', 'N', nc, 1, nc, ONE, Linv, nc, v1, nc, ZERO, v2, nc, ws.zg, st);
+                    launch_zgemm('C', 'N', nc, 1, nc, ONE, Linv, nc, v2, nc, ZERO, v1, nc, ws.zg, st);
+                }
+                launch_znormalize(nc, v1, &fl->pw[which], st);
+            }
+        }
+        MDP_HIP(hipMemcpyAsync(&hf, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
+        MDP_HIP(hipStreamSynchronize(st));
+        res.cond = std::sqrt(hf.pw[0] * hf.pw[1]);
+    }
     return res;
 }
 

@@ -1,6 +1,8 @@
 // Device least-squares solve of the reduced interface system.
 #pragma once
 
+#include <vector>
+
 #include "ap_solver.h"
 
 namespace mdp {
@@ -11,6 +13,24 @@ struct LSResult {
     bool shifted = false;       // the shifted first pass was needed
     int passes = 0;
 };
+
+// Host description of the block-sparse interface matrix: subdomain i's rows
+// form the dense block A_i (m_i x s_i); packed column pc is coefA Q_i(:, colA)
+// + coefB Q_i(:, colB) and column pc_gcol[pc] of Qbar.
+struct PackedHost {
+    int n_sub = 0, nc = 0, total_pc = 0, max_m = 0, max_s = 0;
+    std::vector<const double2*> Q;
+    std::vector<int> m, s, pc_sub, pc_p, pc_gcol, pc_start;
+    std::vector<long> off, roff;
+    std::vector<int4> pc_cols;
+    std::vector<double2> pc_coef;
+};
+
+// Corrected semi-normal equations on the packed matrix; F is the stacked
+// right-hand side (device).  Sets *fallback (and returns) when the Cholesky of
+// the Gram matrix breaks down or the refinement does not contract.
+LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, double2* x_out, bool want_cond,
+                         hipStream_t st, bool* fallback);
 
 // min ||A x - F||_2 for A (m x nc, column-major, ld m, device; overwritten) and
 // F (m, device); x_out (nc, device).

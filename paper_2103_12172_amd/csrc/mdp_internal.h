@@ -60,6 +60,49 @@ struct DevBuf {
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// ----------------------------------------------------------------- per-launch profiler
+// When enabled, every kernel launch of the hot path is bracketed by HIP events
+// recorded on its own stream, tagged with a kernel class and the launch's
+// algorithmic flops and bytes (what the algorithm must compute and move, not
+// what the implementation happens to).
+struct Profiler {
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+        double flops, bytes;
+    };
+    bool on = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        MDP_HIP(hipEventCreate(&e));
+        return e;
+    }
+    template <class F>
+    void run(const char* name, hipStream_t st, double flops, double bytes, F&& f) {
+        if (!on) { f(); return; }
+        hipEvent_t a = get(), b = get();
+        MDP_HIP(hipEventRecord(a, st));
+        f();
+        MDP_HIP(hipEventRecord(b, st));
+        recs.push_back({name, a, b, flops, bytes});
+    }
+    void reset() {
+        for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+        recs.clear();
+    }
+    ~Profiler() {
+        reset();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 // ----------------------------------------------------------------- geometry (host)
 // Auxiliary grid of one subdomain and its grid sets (paper Sec. 3.2.2).
 struct Geometry {
@@ -134,8 +177,13 @@ void launch_extend_density(const double* E, int ng, int ncol, const double* c, i
                            const int* gq, int n, double* w, long w_stride, hipStream_t st);
 
 // interface least squares
+// tri: 0 full; 1 lower-triangle tiles of C only; 2 op(B) upper triangular (skip its zero part)
 void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const double2* A, int lda,
-                  const double2* B, int ldb, double2 beta, double2* C, int ldc, DevBuf& ws, hipStream_t st);
+                  const double2* B, int ldb, double2 beta, double2* C, int ldc, DevBuf& ws, hipStream_t st,
+                  int tri = 0);
+void launch_znorm2(int m, const double2* v, double* out, hipStream_t st);
+void launch_znormalize(int n, double2* v, double* norm_out, hipStream_t st);
+void launch_scale_cols_checked(double2* A, int m, int n, int lda, const double* s, int* flags, hipStream_t st);
 void launch_chol_block(const double2* G, int ldg, int nb, double shift, double2* L, int ldl, double2* Linv, int ldi,
                        int* info, int base, hipStream_t st);
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
@@ -145,5 +193,32 @@ void launch_known_rhs(const double2* const* Qsrc, const int* qld, int n_sub, con
 void launch_col_norms(const double2* A, int m, int n, int lda, double* out, hipStream_t st);
 void launch_scale_cols(double2* A, int m, int n, int lda, const double* s, int invert, hipStream_t st);
 void launch_fill(double* p, long n, double v, hipStream_t st);
+
+// packed (block-sparse) interface matrix: device views of the per-subdomain blocks
+struct PackedDevice {
+    const double2* const* Q;
+    const int* m;
+    const long* off;
+    const int* s;
+    const int* pc_sub;
+    const int* pc_p;
+    const int* pc_gcol;
+    const int4* pc_cols;
+    const double2* pc_coef;
+    const long* roff;
+    const int* pc_start;   // first packed column of each subdomain
+};
+void launch_assemble_packed(const PackedDevice& d, int total_pc, int max_m, double2* Ap, hipStream_t st);
+void launch_packed_colnorm2(const PackedDevice& d, int total_pc, const double2* Ap, double* norms2, hipStream_t st);
+void launch_finalize_norms(int n, const double* norms2, double* norms, int* flags, hipStream_t st);
+void launch_packed_scale(const PackedDevice& d, int total_pc, int max_m, double2* Ap, const double* norms,
+                         hipStream_t st);
+void launch_packed_ahx(const PackedDevice& d, int total_pc, const double2* Ap, const double2* v, double2 alpha,
+                       double2* y, hipStream_t st);
+void launch_packed_ax(const PackedDevice& d, int n_sub, int max_m, int max_s, const double2* Ap, const double2* x,
+                      double2 alpha, double2* r, hipStream_t st);
+void launch_scatter_gram(const double2* Gi, int s, const int* gcol, double2* G, int ldg, hipStream_t st);
+void launch_zaxpy1(int n, const double2* x, double2* y, hipStream_t st);
+void launch_diag_range(const double2* L, int n, int ld, double* out, hipStream_t st);
 
 }  // namespace mdp

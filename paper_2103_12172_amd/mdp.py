@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "MDP_OK", -1: "MDP_ERR_ARG", -2: "MDP_ERR_HIP", -3: "MDP_ERR_
 
 EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector", "mdp_projector_info",
             "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
-            "mdp_cheb_coeffs", "mdp_version"]
+            "mdp_cheb_coeffs", "mdp_version", "mdp_cache_clear", "mdp_profile_enable", "mdp_profile_report"]
 
 
 class MdpError(RuntimeError):
@@ -83,6 +83,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mdp_cheb_points.restype = ip
     lib.mdp_cheb_coeffs.argtypes = [ip, ctypes.POINTER(C128), ctypes.POINTER(C128)]
     lib.mdp_cheb_coeffs.restype = ip
+    lib.mdp_cache_clear.argtypes = [vp]
+    lib.mdp_cache_clear.restype = ip
+    lib.mdp_profile_enable.argtypes = [vp, ip]
+    lib.mdp_profile_enable.restype = ip
+    lib.mdp_profile_report.argtypes = [vp, ctypes.c_char_p, ip]
+    lib.mdp_profile_report.restype = ip
     lib.mdp_version.argtypes = []
     lib.mdp_version.restype = ctypes.c_char_p
     _lib = lib
@@ -245,6 +251,21 @@ def mdp_cheb_coeffs(samples: np.ndarray) -> np.ndarray:
     if rc != MDP_OK:
         raise MdpError(rc, "mdp_cheb_coeffs")
     return np.array([complex(v.re, v.im) for v in d])
+
+
+def mdp_cache_clear(ctx: Context):
+    ctx.check(ctx.lib.mdp_cache_clear(ctx.handle))
+
+
+def mdp_profile_enable(ctx: Context, enable: bool = True):
+    ctx.check(ctx.lib.mdp_profile_enable(ctx.handle, 1 if enable else 0))
+
+
+def mdp_profile_report(ctx: Context) -> dict:
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    ctx.check(ctx.lib.mdp_profile_report(ctx.handle, buf, len(buf)))
+    return json.loads(buf.value.decode())
 
 
 def version() -> str:

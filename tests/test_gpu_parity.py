@@ -191,3 +191,25 @@ def test_error_paths(ctx):
     with pytest.raises(mdp.MdpError) as e:   # gamma would touch the auxiliary boundary
         mdp.mdp_build_projector(ctx, mdp.Subdomain(0, 0, 1, 1, 10.0, 8), 4, "c128")
     assert e.value.code == mdp.MDP_ERR_ARG
+
+
+def test_dd_ill_conditioned_falls_back_to_cholesky_qr(ctx):
+    """The paper's base case with M* = 40 on the coarsest grid has cond ~1e8 after
+    column equilibration: the semi-normal path must hand over to the Cholesky-QR
+    passes, which still reproduce the oracle's (Householder) accuracy vs the exact
+    solution and its residual."""
+    w = wl.config_paper_base(n=64)
+    res = dd.dd_solve(ctx, w, "c128")
+    torch.cuda.synchronize()
+    ores = osolve.dd_solve(w)
+    sd = w.subdomains[0]
+    g = ores["grids"][0]
+    u = res.u.cpu().numpy().reshape(sd.n + 1, sd.n + 1)
+    X, Y = np.meshgrid(g.xs, g.ys, indexing="ij")
+    e_gpu = float(np.abs(u - w.exact(X, Y))[g.Mplus].max())
+    e_ref = ores["info"]["error_max_Mplus"]
+    print("paper base n=64: cond %.3e, error vs exact gpu %.4e oracle %.4e, residual gpu %.3e oracle %.3e"
+          % (res.cond, e_gpu, e_ref, res.rel_residual, ores["info"]["rel_residual"]))
+    assert res.cond > 1e6
+    assert abs(e_gpu - e_ref) < 0.02 * e_ref
+    assert res.rel_residual < 1.05 * ores["info"]["rel_residual"] + 1e-14
