@@ -57,6 +57,22 @@ typedef enum {
     MDP_C64_REFINED = 2   /* FP32 solve + one FP64 residual and FP32 correction solve */
 } mdp_precision;
 
+/* How mdp_build_projector computes Q.  Both routes give the same Q up to
+ * rounding order.
+ * MDP_PATH_AUTO: for MDP_C128, the support-in / gamma-out route: the
+ *   right-hand side L^(h) w |_{M+} lives on the two outer rings of M+ and
+ *   only Tr_gamma of the AP solution is needed (eq. def_Pgamma), so only the
+ *   four dense RHS rows and the four full gamma rows go through the sine
+ *   GEMM; the other rows are transformed and synthesised inside one fused
+ *   tridiagonal sweep that keeps the columns on chip.  Other precisions, and
+ *   M+ boxes not symmetric about the AP centre line, use the dense route.
+ * MDP_PATH_DENSE: every column is a full AP solve (sine GEMM of every grid
+ *   row, tridiagonal solve, inverse GEMM) followed by the gather onto gamma. */
+typedef enum {
+    MDP_PATH_AUTO = 0,
+    MDP_PATH_DENSE = 1
+} mdp_projector_path;
+
 /* One subdomain: the rectangle [x0, x0+lx] x [y0, y0+ly] with constant
  * wavenumber k (Sec. 3.1 assumes k constant on every subdomain).  Its
  * auxiliary domain is the square of side 1.1*max(lx, ly) centred on it, with
@@ -89,6 +105,10 @@ int mdp_create(mdp_ctx** ctx, int device);
 /* Destroy a context, its workspaces and its projector cache (projectors
  * still held by the caller stay valid until released). NULL is a no-op. */
 void mdp_destroy(mdp_ctx* ctx);
+
+/* Select the projector route of later mdp_build_projector calls on ctx
+ * (projectors already cached are not rebuilt).  Errors: MDP_ERR_ARG. */
+int mdp_set_projector_path(mdp_ctx* ctx, int path);
 
 /* Message of the last failure on ctx (or of the last mdp_create failure when
  * ctx is NULL).  Valid until the next call on the same context. */

@@ -433,4 +433,352 @@ template void launch_unfold_grid<double>(const double*, const float*, int, const
 template void launch_unfold_grid<float>(const float*, const float*, int, const Fold&, int, const double*, long,
                                         double*, long, hipStream_t);
 
+
+// ============================================================================
+// Projector build, support-in / gamma-out form (FP64).
+//
+// For a projector column the right-hand side g = L^(h) w |_{M+} (w on gamma)
+// lives on the two outermost rings of the M+ box [m_lo, m_hi] x [q_lo, q_hi],
+// and Q needs the solution only on gamma.  With the box symmetric in y
+// (q_hi = n - q_lo):
+//   * rows m_lo, m_lo+1, m_hi-1, m_hi ("special input rows") are dense in q:
+//     their folded rows go through the MFMA sine GEMM (4 rows per RHS);
+//   * every other row has g only at q_lo, q_lo+1, q_hi-1, q_hi, i.e. two
+//     entries per folded block: its transform is two multiply-adds per mode,
+//     done on the fly inside the tridiagonal sweep;
+//   * on gamma, rows m_lo-1, m_lo, m_hi, m_hi+1 are full: the sweep writes
+//     their mode-space values to a compact buffer for a small inverse GEMM;
+//     every other gamma row needs u only at q_lo-1, q_lo and their mirrors,
+//     i.e. the folded synthesis values A, B at q_lo-1 and q_lo, which are sums
+//     over the modes: reduced across the wavefront as the sweep produces them.
+// The tridiagonal sweep keeps nothing of the column in HBM: the forward pass
+// stores y only at the end of every K-row segment, and the backward pass
+// recomputes each segment's y in registers before walking back through it.
+// ============================================================================
+namespace {
+
+struct RingGeom {
+    int m_lo, m_hi, q_lo, q_hi;
+};
+
+__device__ inline int special_in(const RingGeom& r, int m) {
+    if (m == r.m_lo) return 0;
+    if (m == r.m_lo + 1) return 1;
+    if (m == r.m_hi - 1) return 2;
+    if (m == r.m_hi) return 3;
+    return -1;
+}
+__device__ inline int special_out(const RingGeom& r, int m) {
+    if (m == r.m_lo - 1) return 0;
+    if (m == r.m_lo) return 1;
+    if (m == r.m_hi) return 2;
+    if (m == r.m_hi + 1) return 3;
+    return -1;
+}
+
+// gc[b][m][4] = (g_lo + g_hi, g_lo1 + g_hi1, g_lo - g_hi, g_lo1 - g_hi1) for
+// every row m = 0..n, with g_lo = g(m, q_lo), g_lo1 = g(m, q_lo+1),
+// g_hi1 = g(m, q_hi-1), g_hi = g(m, q_hi): the folded ring entries of a
+// non-special box row (zero on the special rows and outside the box);
+// spec[b][s][W] = folded special input row s.
+// Work item t of RHS b: t <= n a gc row, otherwise one folded special entry.
+__global__ void __launch_bounds__(256)
+fold_ring_kernel(SrcEval ev, Fold f, RingGeom rg, double* __restrict__ gc, double* __restrict__ spec) {
+    const int n = f.n, p = f.p, W = f.W, b = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= n) {
+        const int m = t;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+        if (m >= rg.m_lo && m <= rg.m_hi && special_in(rg, m) < 0) {
+            v0 = ev.rhs(b, m, rg.q_lo).re;
+            v1 = ev.rhs(b, m, rg.q_lo + 1).re;
+            v2 = ev.rhs(b, m, rg.q_hi - 1).re;
+            v3 = ev.rhs(b, m, rg.q_hi).re;
+        }
+        double* o = gc + ((long)b * (n + 1) + m) * 4;
+        o[0] = v0 + v3;
+        o[1] = v1 + v2;
+        o[2] = v0 - v3;
+        o[3] = v1 - v2;
+        return;
+    }
+    const int i = t - (n + 1);
+    if (i >= 4 * W) return;
+    const int s = i / W, c = i - s * W;
+    const int m = (s == 0) ? rg.m_lo : (s == 1) ? rg.m_lo + 1 : (s == 2) ? rg.m_hi - 1 : rg.m_hi;
+    double v = 0.0;
+    if (c < f.P1) {
+        const int q = c + 1;
+        if (q < p) v = ev.rhs(b, m, q).re + ev.rhs(b, m, n - q).re;
+        else if (q == p) v = ev.rhs(b, m, p).re;
+    } else {
+        const int q = c - f.P1 + 1;
+        if (q < p) v = ev.rhs(b, m, q).re - ev.rhs(b, m, n - q).re;
+    }
+    spec[((long)b * 4 + s) * W + c] = v;
+}
+
+// One step of a butterfly reduce-scatter over the wavefront: the lanes with
+// `bit` set keep the upper half of v[0..2H), the others the lower half, and
+// each adds its partner's copy of the half it keeps.
+template <int H>
+__device__ inline void reduce_half(double* v, int lane, int bit) {
+    const bool hi = (lane & bit) != 0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const double keep = hi ? v[H + j] : v[j];
+        const double send = hi ? v[j] : v[H + j];
+        v[j] = keep + __shfl_xor(send, bit, 64);
+    }
+}
+
+// Sums over the 64 lanes of the 32 values v[i*4 + t] (8 rows x 4 products);
+// afterwards lanes 2j and 2j+1 hold the total of value j in v[0].
+__device__ inline void reduce_32(double* v, int lane) {
+    reduce_half<16>(v, lane, 32);
+    reduce_half<8>(v, lane, 16);
+    reduce_half<4>(v, lane, 8);
+    reduce_half<2>(v, lane, 4);
+    reduce_half<1>(v, lane, 2);
+    v[0] += __shfl_xor(v[0], 1, 64);
+}
+
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+// Index of the special input row m (0..3), 4 for any other row.
+__device__ inline int special_slot(const RingGeom& r, int m) {
+    const int s = special_in(r, m);
+    return s < 0 ? 4 : s;
+}
+
+// One wavefront per (64 consecutive folded mode columns, right-hand side b).
+// Per column c (sine mode j): forward transform of the RHS rows, Thomas
+// elimination (y_m = ghat_m - l_m y_{m-1}, x_m = r_m (y_m - s_m x_{m+1})),
+// then per row the synthesis partial sums x_m(c) * sin(pi j q / n) at
+// q = q_lo-1, q_lo (into thin) and the full gamma rows into xs.
+// gc[b][n+1][4] ring table, lf/rf[(n+1)][W] complex factors l_m, r_m,
+// ckpt[b][seg][2][W], xs[b][2][4][W], thin[b][wblk][nseg*K][4].
+// LDS: the wave's (n+1) ring pairs and the 4 special-row values per lane.
+template <int K>
+__global__ void __launch_bounds__(64)
+proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec_hat,
+                  const double* __restrict__ Sf, const double* __restrict__ Si, Fold f, RingGeom rg,
+                  const dv2* __restrict__ lf, const dv2* __restrict__ rf, const double* __restrict__ colc,
+                  double* __restrict__ ckpt, double* __restrict__ xs, double* __restrict__ thin, int nseg) {
+    static_assert(K % 8 == 0, "segments are reduced 8 rows at a time");
+    extern __shared__ double2 lds_g[];  // [n+1] ring pairs, then [5][64] special values
+    const int n = f.n, W = f.W;
+    const int lane = threadIdx.x, wblk = blockIdx.x, b = blockIdx.y;
+    const int c = wblk * 64 + lane;
+    const bool odd = c < f.P1;  // uniform over the wavefront (P1 is a multiple of 64)
+    const int base = odd ? 0 : f.P1;
+    double* lds_sp = reinterpret_cast<double*>(lds_g + (n + 1));
+    {
+        const double* g = gc + (long)b * (n + 1) * 4 + (odd ? 0 : 2);
+        for (int m = lane; m <= n; m += 64) lds_g[m] = make_double2(g[(long)m * 4], g[(long)m * 4 + 1]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) lds_sp[s * 64 + lane] = spec_hat[((long)b * 4 + s) * W + c];
+        lds_sp[4 * 64 + lane] = 0.0;
+    }
+    __syncthreads();
+    const double s1 = Sf[(long)(base + rg.q_lo - 1) * W + c];
+    const double s2 = Sf[(long)(base + rg.q_lo) * W + c];
+    const double t1 = Si[(long)c * W + base + rg.q_lo - 2];
+    const double t2 = Si[(long)c * W + base + rg.q_lo - 1];
+    const double a = colc[c], s0r = colc[W + c], s0i = colc[2 * W + c];
+    const dv2* lcol = lf + c;
+    const dv2* rcol = rf + c;
+    double* ck = ckpt + (long)b * nseg * 2 * W + c;
+
+    auto ghat = [&](int m) -> double {
+        const double2 g = lds_g[m];
+        return g.x * s1 + g.y * s2 + lds_sp[special_slot(rg, m) * 64 + lane];
+    };
+    // factor rows of segment s (rows past n read row n; their results are unused)
+    auto load_f = [&](dv2* F, const dv2* col, int s) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) F[i] = col[(long)min(s * K + i, n) * W];
+    };
+
+    // forward elimination, checkpointing y at the end of every full segment
+    double yr = 0.0, yi = 0.0;
+    {
+        dv2 Lc[K], Ln[K];
+        load_f(Lc, lcol, 0);
+        for (int s = 0; s < nseg - 1; ++s) {
+            load_f(Ln, lcol, s + 1);
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const double fr = ghat(s * K + i);
+                const double nr = fr - (Lc[i].x * yr - Lc[i].y * yi);
+                const double ni = -(Lc[i].x * yi + Lc[i].y * yr);
+                yr = nr;
+                yi = ni;
+            }
+            ck[(long)s * 2 * W] = yr;
+            ck[(long)(s * 2 + 1) * W] = yi;
+#pragma unroll
+            for (int i = 0; i < K; ++i) Lc[i] = Ln[i];
+        }
+    }
+
+    // back substitution segment by segment: recompute the segment's y from
+    // the checkpoint before it, then walk back through it
+    double xr = 0.0, xi = 0.0;
+    double* xs_re = xs + (long)b * 8 * W + c;
+    double* xs_im = xs_re + 4 * W;
+    double* th = thin + ((long)b * (W / 64) + wblk) * ((long)nseg * K) * 4;
+    dv2 Lc[K], Ln[K], Rc[K];
+    load_f(Lc, lcol, nseg - 1);
+    for (int s = nseg - 1; s >= 0; --s) {
+        double pr = 0.0, pi = 0.0;
+        load_f(Rc, rcol, s);
+        if (s > 0) {
+            pr = ck[(long)(s - 1) * 2 * W];
+            pi = ck[(long)((s - 1) * 2 + 1) * W];
+            load_f(Ln, lcol, s - 1);
+        }
+        double vr[K], vi[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int m = min(s * K + i, n);
+            const double fr = ghat(m);
+            const double nr = fr - (Lc[i].x * pr - Lc[i].y * pi);
+            const double ni = -(Lc[i].x * pi + Lc[i].y * pr);
+            pr = nr;
+            pi = ni;
+            vr[i] = pr;
+            vi[i] = pi;
+        }
+#pragma unroll
+        for (int i = K - 1; i >= 0; --i) {
+            const int m = s * K + i;
+            if (m <= n) {
+                const double offr = (m == 0) ? s0r : a, offi = (m == 0) ? s0i : 0.0;
+                const double tr = vr[i] - (offr * xr - offi * xi);
+                const double ti = vi[i] - (offr * xi + offi * xr);
+                xr = Rc[i].x * tr - Rc[i].y * ti;
+                xi = Rc[i].x * ti + Rc[i].y * tr;
+                const int so = special_out(rg, m);
+                if (so >= 0) {
+                    xs_re[(long)so * W] = xr;
+                    xs_im[(long)so * W] = xi;
+                }
+                vr[i] = xr;
+                vi[i] = xi;
+            } else {
+                vr[i] = 0.0;
+                vi[i] = 0.0;
+            }
+        }
+        // synthesis partial sums of the gamma rows met by this segment
+        if (s * K <= rg.m_hi + 1 && s * K + K - 1 >= rg.m_lo - 1) {
+#pragma unroll
+            for (int h8 = 0; h8 < K; h8 += 8) {
+                double v[32];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    v[4 * i + 0] = vr[h8 + i] * t1;
+                    v[4 * i + 1] = vi[h8 + i] * t1;
+                    v[4 * i + 2] = vr[h8 + i] * t2;
+                    v[4 * i + 3] = vi[h8 + i] * t2;
+                }
+                reduce_32(v, lane);
+                if ((lane & 1) == 0) th[(long)(s * K + h8) * 4 + (lane >> 1)] = v[0];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) Lc[i] = Ln[i];
+    }
+}
+
+// Q(i, col0+b) = -u(m_i, q_i): the full gamma rows from the synthesis rows us
+// ([b][plane][4][W], output of the inverse sine GEMM of xs), the others from
+// the thin partial sums (odd-mode blocks give A, even-mode blocks B).
+__global__ void gather_q_fused_kernel(const double* __restrict__ us, const double* __restrict__ thin, Fold f,
+                                      RingGeom rg, int rows_pad, const int* __restrict__ gm,
+                                      const int* __restrict__ gq, int ng, double* __restrict__ Q, int ldq,
+                                      int col0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= ng) return;
+    const int m = gm[i], q = gq[i], n = f.n, p = f.p, W = f.W;
+    double vre, vim;
+    const int so = special_out(rg, m);
+    if (so >= 0) {
+        double v[2];
+        for (int pl = 0; pl < 2; ++pl) {
+            const double* row = us + (((long)b * 2 + pl) * 4 + so) * W;
+            double u;
+            if (q <= 0 || q >= n) u = 0.0;
+            else if (q == p) u = row[p - 1];
+            else if (q < p) u = row[q - 1] + row[f.P1 + q - 1];
+            else u = row[n - q - 1] - row[f.P1 + n - q - 1];
+            v[pl] = u;
+        }
+        vre = v[0];
+        vim = v[1];
+    } else {
+        const int qq = (q <= p) ? q : n - q;
+        const double sgn = (q <= p) ? 1.0 : -1.0;
+        const int k2 = (qq == rg.q_lo - 1) ? 0 : 2;
+        const int nb = W / 64, nb1 = f.P1 / 64;
+        double A0 = 0.0, A1 = 0.0, B0 = 0.0, B1 = 0.0;
+        for (int w = 0; w < nb; ++w) {
+            const double* t = thin + (((long)b * nb + w) * rows_pad + m) * 4 + k2;
+            if (w < nb1) { A0 += t[0]; A1 += t[1]; }
+            else { B0 += t[0]; B1 += t[1]; }
+        }
+        vre = A0 + sgn * B0;
+        vim = A1 + sgn * B1;
+    }
+    double* o = Q + 2 * ((long)(col0 + b) * ldq + i);
+    o[0] = -vre;
+    o[1] = -vim;
+}
+
+}  // namespace
+
+bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi) {
+    return q_hi == f.n - q_lo && q_lo >= 2 && q_lo <= f.p - 2 && m_lo >= 2 && m_hi <= f.n - 2 && m_hi - m_lo >= 3 &&
+           f.W % 64 == 0 && f.P1 % 64 == 0;
+}
+
+int fused_segments(int n) { return (n + 1 + FUSED_K - 1) / FUSED_K; }
+
+void launch_fold_ring(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, double* gc, double* spec,
+                      hipStream_t st) {
+    check_batch(R);
+    SrcEval ev{s, n, sc};
+    RingGeom rg{s.m_lo, s.m_hi, s.q_lo, s.q_hi};
+    const int items = n + 1 + 4 * f.W;
+    hipLaunchKernelGGL(fold_ring_kernel, dim3((items + 255) / 256, R), dim3(256), 0, st, ev, f, rg, gc, spec);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_proj_fused(const double* gc, const double* spec_hat, const double* Sf, const double* Si, const Fold& f,
+                       int m_lo, int m_hi, int q_lo, int q_hi, const double* lf, const double* rf, const double* colc,
+                       double* ckpt, double* xs, double* thin, int R, hipStream_t st) {
+    check_batch(R);
+    if (!fused_projector_supported(f, m_lo, m_hi, q_lo, q_hi)) throw Error(MDP_ERR_ARG, "fused projector geometry");
+    RingGeom rg{m_lo, m_hi, q_lo, q_hi};
+    const int nseg = fused_segments(f.n);
+    const size_t lds = (size_t)(f.n + 1) * sizeof(double2) + 5 * 64 * sizeof(double);
+    hipLaunchKernelGGL(proj_fused_kernel<FUSED_K>, dim3(f.W / 64, R), dim3(64), lds, st, gc, spec_hat, Sf, Si, f, rg,
+                       reinterpret_cast<const dv2*>(lf), reinterpret_cast<const dv2*>(rf), colc, ckpt, xs,
+                       thin, nseg);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_gather_q_fused(const double* us, const double* thin, const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi,
+                           const int* gm, const int* gq, int ng, int R, double* Q, int ldq, int col0, hipStream_t st) {
+    check_batch(R);
+    RingGeom rg{m_lo, m_hi, q_lo, q_hi};
+    const int rows_pad = fused_segments(f.n) * FUSED_K;
+    dim3 grid((ng + 255) / 256, R);
+    hipLaunchKernelGGL(gather_q_fused_kernel, grid, dim3(256), 0, st, us, thin, f, rg, rows_pad, gm, gq, ng, Q, ldq,
+                       col0);
+    MDP_HIP(hipGetLastError());
+}
+
 }  // namespace mdp

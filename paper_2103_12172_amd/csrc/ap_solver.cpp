@@ -147,6 +147,15 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
     upload<double>(fac64, fac);
     upload<float>(fac32, fac);
     upload<double>(colc64, colc);
+    std::vector<double> lf(2 * plane), rf(2 * plane);
+    for (size_t e = 0; e < plane; ++e) {
+        lf[2 * e] = fac[e];
+        lf[2 * e + 1] = fac[plane + e];
+        rf[2 * e] = fac[2 * plane + e];
+        rf[2 * e + 1] = fac[3 * plane + e];
+    }
+    upload<double>(lf64, lf);
+    upload<double>(rf64, rf);
     upload<float>(colc32, colc);
 }
 

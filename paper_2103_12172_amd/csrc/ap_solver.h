@@ -20,6 +20,7 @@ struct APPlan {
     double min_pivot_ratio;  // smallest |pivot| / row scale over all modes (host check)
     DevBuf Sf64, Si64, Sf32, Si32;     // block-diagonal sine matrices (W x W)
     DevBuf fac64, fac32, colc64, colc32;  // tridiagonal LU factors per mode
+    DevBuf lf64, rf64;    // the same l_m and r_m as interleaved complex [(n+1)][W] (fused projector sweep)
     APPlan(int n, double h, double k);
 };
 

@@ -39,6 +39,7 @@ struct mdp_ctx {
     std::map<ProjKey, mdp_projector*> cache;
     Workspace ws;
     size_t ws_cap = (size_t)24 << 30;
+    int projector_path = MDP_PATH_AUTO;
     hipEvent_t last = nullptr;   // end of the previous call's work (workspaces are shared)
     hipStream_t last_stream = nullptr;
     bool have_last = false;
@@ -115,6 +116,71 @@ void prepare_ws(mdp_ctx* ctx, const APPlan& P, int precision, int R) {
     }
 }
 
+
+// Q by the support-in / gamma-out route (FP64): per chunk of columns, the
+// ring RHS and the folded special rows, their sine GEMM, the fused sweep with
+// the gamma-row reductions, the inverse GEMM of the four full gamma rows and
+// the gather into Q.
+void build_q_fused(mdp_ctx* ctx, const APPlan& plan, mdp_projector* P, hipStream_t st) {
+    const Geometry& G = P->g;
+    const Fold& f = plan.f;
+    const int n = G.n, W = f.W, ng = G.n_gamma, ncol = 8 * P->m_star;
+    const int nseg = fused_segments(n), rows_pad = nseg * FUSED_K, nb = W / 64;
+    const size_t per_a = (size_t)nseg * 2 * W + (size_t)nb * rows_pad * 4;      // ckpt + thin
+    const size_t per_b = (size_t)(n + 1) * 4 + (size_t)(4 + 4 + 8 + 8) * W;       // gc, spec, spec_hat, xs, us
+    size_t chunk = ctx->ws_cap / ((per_a + per_b) * sizeof(double));
+    chunk = std::max<size_t>(1, std::min<size_t>({chunk, (size_t)65535, (size_t)ncol}));
+    const size_t need_a = chunk * per_a * sizeof(double), need_b = chunk * per_b * sizeof(double);
+    if (need_a > ctx->ws.a.bytes || need_b > ctx->ws.b.bytes) {
+        MDP_HIP(hipDeviceSynchronize());
+        ctx->ws.a.reserve(need_a);
+        ctx->ws.b.reserve(need_b);
+    }
+    Profiler& pr = ctx->ws.prof;
+    const double elems_useful = (double)(n + 1) * (n - 1);
+    const double gemm_row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
+    const int box_rows = G.m_hi - G.m_lo + 3;
+    for (int col0 = 0; col0 < ncol; col0 += (int)chunk) {
+        const int R = std::min((int)chunk, ncol - col0);
+        double* ckpt = ctx->ws.a.as<double>();
+        double* thin = ckpt + (size_t)R * nseg * 2 * W;
+        double* gc = ctx->ws.b.as<double>();
+        double* spec = gc + (size_t)R * (n + 1) * 4;
+        double* spec_hat = spec + (size_t)R * 4 * W;
+        double* xs = spec_hat + (size_t)R * 4 * W;
+        double* us = xs + (size_t)R * 8 * W;
+        SrcDesc src{};
+        src.kind = Src::STENCIL_E;
+        src.E = P->E.as<double>();
+        src.ldE = ng;
+        src.col0 = col0;
+        src.gidx = P->gidx.as<int>();
+        src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
+        pr.run("fold_ring", st, 0.0, (double)R * ((n + 1) * 4.0 + 4.0 * (n - 1)) * 8.0,
+               [&] { launch_fold_ring(src, n, f, plan.sc, R, gc, spec, st); });
+        pr.run("gemm_sine_f64", st, 4.0 * R * gemm_row_flops, 2.0 * 4.0 * R * (n - 1) * 8.0,
+               [&] { launch_gemm_bd<double>(spec, plan.Sf64.as<double>(), spec_hat, (long)R * 4, f, st); });
+        // algorithmic flops per column element: forward elimination 7, back substitution 10, ring transform 3
+        // (box rows), synthesis products and sums 8 (gamma rows)
+        pr.run("ap_fused_f64", st,
+               (double)R * (elems_useful * 17.0 + (double)(G.m_hi - G.m_lo + 1) * (n - 1) * 3.0 +
+                            (double)box_rows * (n - 1) * 8.0),
+               (double)R * ((G.m_hi - G.m_lo + 1) * 32.0 + 4.0 * (n - 1) * 8.0 + 8.0 * (n - 1) * 8.0 +
+                            (double)box_rows * 4 * 8.0),
+               [&] {
+                   launch_proj_fused(gc, spec_hat, plan.Sf64.as<double>(), plan.Si64.as<double>(), f, G.m_lo,
+                                     G.m_hi, G.q_lo, G.q_hi, plan.lf64.as<double>(), plan.rf64.as<double>(),
+                                     plan.colc64.as<double>(), ckpt, xs, thin, R, st);
+               });
+        pr.run("gemm_sine_f64", st, 8.0 * R * gemm_row_flops, 2.0 * 8.0 * R * (n - 1) * 8.0,
+               [&] { launch_gemm_bd<double>(xs, plan.Si64.as<double>(), us, (long)R * 8, f, st); });
+        pr.run("gather_q", st, 0.0, (double)ng * R * 16.0 * 2.0, [&] {
+            launch_gather_q_fused(us, thin, f, G.m_lo, G.m_hi, G.q_lo, G.q_hi, P->gm.as<int>(), P->gq.as<int>(), ng,
+                                  R, P->Q.as<double>(), ng, col0, st);
+        });
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -157,6 +223,13 @@ void mdp_destroy(mdp_ctx* ctx) {
     delete ctx;
 }
 
+int mdp_set_projector_path(mdp_ctx* ctx, int path) {
+    if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
+    if (path != MDP_PATH_AUTO && path != MDP_PATH_DENSE) return fail(ctx, MDP_ERR_ARG, "unknown projector path");
+    ctx->projector_path = path;
+    return MDP_OK;
+}
+
 const char* mdp_last_error(const mdp_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
 int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int precision, void* stream,
@@ -196,6 +269,16 @@ int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int p
         const Geometry& G = P->g;
 
         begin_call(ctx, st);
+        if (precision == MDP_C128 && ctx->projector_path == MDP_PATH_AUTO &&
+            fused_projector_supported(plan.f, G.m_lo, G.m_hi, G.q_lo, G.q_hi)) {
+            build_q_fused(ctx, plan, P.get(), st);
+            end_call(ctx, st);
+            mdp_projector* raw = P.release();
+            raw->refs.store(2);
+            ctx->cache[key] = raw;
+            *out = raw;
+            return MDP_OK;
+        }
         const int chunk = chunk_size(plan, precision, ctx->ws_cap, ncol);
         prepare_ws(ctx, plan, precision, chunk);
         for (int col0 = 0; col0 < ncol; col0 += chunk) {

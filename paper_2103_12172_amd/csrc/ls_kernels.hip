@@ -191,166 +191,123 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Cholesky of one 64 x 64 Hermitian diagonal block, G = L L^* (lower), and the
-// inverse of its factor.  Blocked unscaled elimination G = Lt D Lt^* (unit-lower
-// Lt, Lt(i,k) = S(i,k)/S(k,k)) in panels of 8 columns; the same elimination
-// applied to the identity yields Lt^{-1}; at the end L = Lt D^{1/2} and
-// L^{-1} = D^{-1/2} Lt^{-1}.  (64/TS)^2 threads; thread t owns the TS x TS
-// tiles at rows TS (t % (64/TS)) and columns TS (t / (64/TS)) of S and of the
-// inverse in registers (launched with TS = 4: 256 threads, no register
-// spills; 2 x 2 tiles with 1024 threads spill the panel registers).  Per
-// panel: the owners publish the panel columns (and the panel rows of the
-// inverse) to LDS, one wavefront factors the 64 x 8 panel and finalises those
-// 8 inverse rows with wave-level synchronisation (each lane keeps its panel row
-// in registers; only the 8 diagonal-block entries of a column travel through
-// LDS), and every thread applies the rank-8 update to its registers.  G (nb x
-// nb, ld ldg) is read, L goes to Lout (ld ldl, upper part zero), L^{-1} to Linv
-// (ld ldi).  A non-positive pivot sets *info to base + its 1-based index (first
-// failure wins); `shift` is added to the diagonal first.
-template <int TS>
-__global__ void __launch_bounds__((64 / TS) * (64 / TS))
-chol_block_kernel(const double2* __restrict__ G, int ldg, int nb, double shift, double2* __restrict__ Lout, int ldl,
-                  double2* __restrict__ Linv, int ldi, int* info, int base) {
-    constexpr int NB = 64, PW = 8, TD = 64 / TS;
-    __shared__ double2 P[NB][PW + 1];   // panel columns of S (unscaled)
-    __shared__ double2 LT[NB][PW + 1];  // the same scaled by the pivot: Lt(i, k)
-    __shared__ double2 XP[PW][NB + 1];  // panel rows of the inverse
-    __shared__ double piv[NB];
-    __shared__ double2 colk[PW];        // diagonal-block entries of the current panel column
+// Cholesky factor and inverse of one Hermitian positive definite diagonal
+// block of order nb <= 64: G (lower triangle read, ld ldg) = L L^*, L to Lout
+// (ld ldl, lower triangle written), L^{-1} to Linv (ld ldi, lower triangle
+// written); the caller zeroes the strict upper triangles.  `shift` is added
+// to the diagonal first; orders below 64 are padded with the identity.
+// Right-looking, one column per step: with S the Schur complement and X the
+// inverse of the unit lower factor (both unscaled), step k takes the pivot
+// d_k = S(k,k) and updates S(i,j) -= S(i,k) conj(S(j,k)) / d_k (j > k) and
+// X(i,j) -= S(i,k) X(k,j) / d_k (i > k); then L(i,j) = S(i,j)/sqrt(d_j) and
+// L^{-1}(i,j) = X(i,j)/sqrt(d_i).  Column k of S and row k of X are broadcast
+// through LDS (double-buffered: one barrier per step).  The 136 4x4 tiles of
+// the lower triangle are spread 34 per wavefront; a tile's S and X entries
+// stay in registers.  A non-positive pivot sets *info to base + its 1-based
+// index (first failure wins).
+__global__ void __launch_bounds__(256)
+chol64_kernel(const double2* __restrict__ G, int ldg, int nb, double shift, double2* __restrict__ Lout, int ldl,
+              double2* __restrict__ Linv, int ldi, int* info, int base) {
+    __shared__ double2 colS[2][64];
+    __shared__ double2 rowX[2][64];
+    __shared__ double piv[64];
     __shared__ int bad_s;
     const int tid = threadIdx.x;
-    const int r0 = TS * (tid % TD), c0 = TS * (tid / TD);
-    const int wave = tid >> 6, lane = tid & 63;
-    double sr[TS][TS], si[TS][TS], xr[TS][TS], xi[TS][TS];
+    const int lane = tid & 63;
+    const bool act = lane < 34;
+    // tile number t -> (ti, tj) with t = ti (ti + 1) / 2 + tj, tj <= ti
+    const int t = (tid >> 6) * 34 + (act ? lane : 0);
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    const int tj = t - ti * (ti + 1) / 2;
+    const int r0 = 4 * ti, c0 = 4 * tj;
+    double sr[4][4], si[4][4], xr[4][4], xi[4][4];
 #pragma unroll
-    for (int a = 0; a < TS; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < TS; ++b) {
+        for (int b = 0; b < 4; ++b) {
             const int i = r0 + a, j = c0 + b;
             double2 v = make_double2(0.0, 0.0);
-            if (i < nb && j < nb) v = G[i + (long)j * ldg];
-            else if (i == j) v = make_double2(1.0, 0.0);   // identity padding keeps the factor regular
-            if (i == j && i < nb) v.x += shift;
+            if (act && j <= i) {
+                if (i < nb) v = G[i + (long)j * ldg];
+                else if (i == j) v = make_double2(1.0, 0.0);
+                if (i == j && i < nb) v.x += shift;
+            }
             sr[a][b] = v.x;
             si[a][b] = v.y;
             xr[a][b] = (i == j) ? 1.0 : 0.0;
             xi[a][b] = 0.0;
         }
     if (tid == 0) bad_s = 0;
-    for (int kb = 0; kb < NB; kb += PW) {
-        // publish the panel columns kb..kb+7 of S and the panel rows kb..kb+7 of the inverse
-        if (c0 >= kb && c0 < kb + PW) {
+    for (int kt = 0; kt < 16; ++kt) {
 #pragma unroll
-            for (int a = 0; a < TS; ++a)
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * kt + kk, buf = kk & 1;
+            if (act && tj == kt) {
 #pragma unroll
-                for (int b = 0; b < TS; ++b) P[r0 + a][c0 - kb + b] = make_double2(sr[a][b], si[a][b]);
-        }
-        if (r0 >= kb && r0 < kb + PW) {
-#pragma unroll
-            for (int a = 0; a < TS; ++a)
-#pragma unroll
-                for (int b = 0; b < TS; ++b) XP[r0 - kb + a][c0 + b] = make_double2(xr[a][b], xi[a][b]);
-        }
-        __syncthreads();
-        if (wave == 0) {
-            const int i = lane;
-            double2 pr[PW], xc[PW];
-#pragma unroll
-            for (int jj = 0; jj < PW; ++jj) { pr[jj] = P[i][jj]; xc[jj] = XP[jj][i]; }
-#pragma unroll
-            for (int kk = 0; kk < PW; ++kk) {
-                const int k = kb + kk;
-                if (i >= kb && i < kb + PW) colk[i - kb] = pr[kk];
-                wave_sync();
-                double2 ck[PW];
-#pragma unroll
-                for (int jj = 0; jj < PW; ++jj) ck[jj] = colk[jj];
-                double d = ck[kk].x;
-                if (!(d > 0.0)) {
-                    if (lane == 0 && !bad_s) bad_s = k + 1;
-                    d = 1.0;
-                }
-                const double dinv = recip(d);
-                const double2 pik = pr[kk];
-                LT[i][kk] = make_double2(pik.x * dinv, pik.y * dinv);
-#pragma unroll
-                for (int jj = kk + 1; jj < PW; ++jj) {
-                    if (i >= kb + jj) {   // S(i, kb+jj) -= S(i,k) conj(S(kb+jj,k)) / d
-                        pr[jj].x -= (pik.x * ck[jj].x + pik.y * ck[jj].y) * dinv;
-                        pr[jj].y -= (pik.y * ck[jj].x - pik.x * ck[jj].y) * dinv;
-                    }
-                    // inverse rows: X(kb+jj, i) -= Lt(kb+jj, k) X(k, i)
-                    const double lr = ck[jj].x * dinv, li = ck[jj].y * dinv;
-                    xc[jj].x -= lr * xc[kk].x - li * xc[kk].y;
-                    xc[jj].y -= lr * xc[kk].y + li * xc[kk].x;
-                }
-                if (lane == 0) piv[k] = d;
-                wave_sync();   // colk is rewritten by the next column
+                for (int a = 0; a < 4; ++a) colS[buf][r0 + a] = make_double2(sr[a][kk], si[a][kk]);
             }
+            if (act && ti == kt) {
 #pragma unroll
-            for (int jj = 0; jj < PW; ++jj) { P[i][jj] = pr[jj]; XP[jj][i] = xc[jj]; }
-        }
-        __syncthreads();
-        // owners take the factored panel back; everybody applies the rank-8 update
-        if (c0 >= kb && c0 < kb + PW) {
+                for (int b = 0; b < 4; ++b) rowX[buf][c0 + b] = make_double2(xr[kk][b], xi[kk][b]);
+            }
+            __syncthreads();
+            double d = colS[buf][k].x;
+            if (!(d > 0.0)) {
+                if (tid == 0 && !bad_s) bad_s = k + 1;
+                d = 1.0;
+            }
+            if (tid == 0) piv[k] = d;
+            const double dinv = recip(d);
+            if (act && r0 + 3 > k) {
+                double2 ci[4], cj[4], xk[4];
 #pragma unroll
-            for (int a = 0; a < TS; ++a)
+                for (int a = 0; a < 4; ++a) ci[a] = colS[buf][r0 + a];
 #pragma unroll
-                for (int b = 0; b < TS; ++b) {
-                    const double2 v = P[r0 + a][c0 - kb + b];
-                    sr[a][b] = v.x;
-                    si[a][b] = v.y;
+                for (int b = 0; b < 4; ++b) cj[b] = colS[buf][c0 + b];
+                const bool xupd = tj <= kt, supd = c0 + 3 > k;
+                if (xupd) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) xk[b] = rowX[buf][c0 + b];
                 }
-        }
-        if (r0 >= kb && r0 < kb + PW) {
 #pragma unroll
-            for (int a = 0; a < TS; ++a)
-#pragma unroll
-                for (int b = 0; b < TS; ++b) {
-                    const double2 v = XP[r0 - kb + a][c0 + b];
-                    xr[a][b] = v.x;
-                    xi[a][b] = v.y;
-                }
-        }
-        if (r0 + TS - 1 >= kb + PW) {
-#pragma unroll
-            for (int kk = 0; kk < PW; ++kk) {
-                double2 li[TS], lj[TS], xk[TS];
-#pragma unroll
-                for (int a = 0; a < TS; ++a) li[a] = LT[r0 + a][kk];
-#pragma unroll
-                for (int b = 0; b < TS; ++b) { lj[b] = P[c0 + b][kk]; xk[b] = XP[kk][c0 + b]; }
-#pragma unroll
-                for (int a = 0; a < TS; ++a) {
+                for (int a = 0; a < 4; ++a) {
                     const int i = r0 + a;
-                    if (i < kb + PW) continue;
-                    const double lr = li[a].x, lim = li[a].y;
+                    if (i <= k) continue;
+                    const double lr = ci[a].x * dinv, li = ci[a].y * dinv;
 #pragma unroll
-                    for (int b = 0; b < TS; ++b) {
+                    for (int b = 0; b < 4; ++b) {
                         const int j = c0 + b;
-                        if (j < kb + PW) {          // inverse: X(i, j) -= Lt(i, k) X(k, j)
-                            xr[a][b] -= lr * xk[b].x - lim * xk[b].y;
-                            xi[a][b] -= lr * xk[b].y + lim * xk[b].x;
-                        } else if (j <= i) {        // S(i, j) -= Lt(i, k) conj(S(j, k))
-                            sr[a][b] -= lr * lj[b].x + lim * lj[b].y;
-                            si[a][b] -= lim * lj[b].x - lr * lj[b].y;
+                        if (supd && j > k && j <= i) {
+                            sr[a][b] -= lr * cj[b].x + li * cj[b].y;
+                            si[a][b] -= li * cj[b].x - lr * cj[b].y;
+                        }
+                        if (xupd) {
+                            xr[a][b] -= lr * xk[b].x - li * xk[b].y;
+                            xi[a][b] -= lr * xk[b].y + li * xk[b].x;
                         }
                     }
                 }
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
+    if (!act) return;
 #pragma unroll
-    for (int a = 0; a < TS; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < TS; ++b) {
+        for (int b = 0; b < 4; ++b) {
             const int i = r0 + a, j = c0 + b;
-            if (i >= nb || j >= nb) continue;
-            double2 l = make_double2(0.0, 0.0), x = make_double2(0.0, 0.0);
-            if (j < i) { const double sc = recip(sqrt(piv[j])); l = make_double2(sr[a][b] * sc, si[a][b] * sc); }
-            else if (j == i) l = make_double2(sqrt(piv[j]), 0.0);
-            if (j <= i) { const double sc = recip(sqrt(piv[i])); x = make_double2(xr[a][b] * sc, xi[a][b] * sc); }
+            if (i >= nb || j > i) continue;
+            double2 l, x;
+            if (j < i) {
+                const double sc = recip(sqrt(piv[j]));
+                l = make_double2(sr[a][b] * sc, si[a][b] * sc);
+            } else {
+                l = make_double2(sqrt(piv[j]), 0.0);
+            }
+            const double sx = recip(sqrt(piv[i]));
+            x = make_double2(xr[a][b] * sx, xi[a][b] * sx);
             Lout[i + (long)j * ldl] = l;
             Linv[i + (long)j * ldi] = x;
         }
@@ -784,11 +741,8 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
 
 void launch_chol_block(const double2* G, int ldg, int nb, double shift, double2* L, int ldl, double2* Linv, int ldi,
                        int* info, int base, hipStream_t st) {
-    if (nb <= 64)
-        hipLaunchKernelGGL(chol_block_kernel<4>, dim3(1), dim3(256), 0, st, G, ldg, nb, shift, L, ldl, Linv, ldi,
-                           info, base);
-    else
-        throw Error(MDP_ERR_ARG, "Cholesky block too large");
+    if (nb < 1 || nb > 64) throw Error(MDP_ERR_ARG, "Cholesky block order must be 1..64");
+    hipLaunchKernelGGL(chol64_kernel, dim3(1), dim3(256), 0, st, G, ldg, nb, shift, L, ldl, Linv, ldi, info, base);
     MDP_HIP(hipGetLastError());
 }
 

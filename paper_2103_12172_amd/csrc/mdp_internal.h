@@ -176,6 +176,20 @@ void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, int R
 void launch_extend_density(const double* E, int ng, int ncol, const double* c, int R, const int* gm,
                            const int* gq, int n, double* w, long w_stride, hipStream_t st);
 
+// projector build, support-in / gamma-out form (FP64)
+constexpr int FUSED_K = 8;   // rows per recomputed segment of the fused tridiagonal sweep
+bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi);
+int fused_segments(int n);   // segments of FUSED_K rows covering m = 0..n
+// gc: [R][n+1][4] ring table, spec: [R][4][W] folded special rows
+void launch_fold_ring(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, double* gc, double* spec,
+                      hipStream_t st);
+// lf, rf: [(n+1)][W] interleaved complex Thomas factors l_m and r_m = 1/d_m
+void launch_proj_fused(const double* gc, const double* spec_hat, const double* Sf, const double* Si, const Fold& f,
+                       int m_lo, int m_hi, int q_lo, int q_hi, const double* lf, const double* rf, const double* colc,
+                       double* ckpt, double* xs, double* thin, int R, hipStream_t st);
+void launch_gather_q_fused(const double* us, const double* thin, const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi,
+                           const int* gm, const int* gq, int ng, int R, double* Q, int ldq, int col0, hipStream_t st);
+
 // interface least squares
 // tri: 0 full; 1 lower-triangle tiles of C only; 2 op(B) upper triangular (skip its zero part)
 void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const double2* A, int lda,

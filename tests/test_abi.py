@@ -1,0 +1,63 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/mdp.h declares, and its host-only helpers work.  mdp_create reports
+MDP_ERR_NODEVICE when no HIP device is visible (nothing is computed here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2103_12172_amd import mdp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mdp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_three_steps():
+    names = _declared()
+    for f in ("mdp_build_projector", "mdp_solve_interface", "mdp_reconstruct"):
+        assert f in names
+
+
+def test_library_exports_every_declared_function():
+    lib = mdp.load()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(mdp.EXPORTED) == _declared()
+
+
+def test_host_helpers():
+    assert mdp.version().startswith("mdp-gfx950")
+    m = 9
+    t = mdp.mdp_cheb_points(m)
+    assert np.allclose(t, np.cos(np.pi * (np.arange(m) + 0.5) / m))
+    # interpolation of a polynomial of degree < M* is exact: phi = T_3 + 2i T_0
+    phi = np.cos(3 * np.arccos(t)) + 2j
+    d = mdp.mdp_cheb_coeffs(phi)
+    ref = np.zeros(m, complex)
+    ref[0], ref[3] = 2j, 1.0
+    assert np.abs(d - ref).max() < 1e-13
+
+
+def test_argument_errors_without_device():
+    lib = mdp.load()
+    assert lib.mdp_cheb_points(0, None) == mdp.MDP_ERR_ARG
+    assert lib.mdp_set_projector_path(None, 0) == mdp.MDP_ERR_ARG
+    assert lib.mdp_cache_clear(None) == mdp.MDP_ERR_ARG
+
+
+def test_create_without_device_fails_loudly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    lib = mdp.load()
+    h = ctypes.c_void_p()
+    rc = lib.mdp_create(ctypes.byref(h), 0)
+    assert rc == mdp.MDP_ERR_NODEVICE
+    assert b"device" in lib.mdp_last_error(None)

@@ -108,6 +108,35 @@ def test_projector_cross_point_matches_oracle(ctx, prec):
     assert colerr.max() < TOL[prec]
 
 
+@pytest.mark.parametrize("geom", [(0.0, 0.0, 0.3, 0.7, 25.0, 128, 8), (0.1, 0.2, 0.5, 0.5, 50.0, 256, 32),
+                                  (0.0, 0.0, 1.0, 0.45, 12.0, 96, 12)])
+def test_projector_fused_route_matches_dense_and_oracle(ctx, geom):
+    """The support-in / gamma-out route (default for complex128) against the
+    dense route (full AP solve per column) and against oracle columns."""
+    x0, y0, lx, ly, k, n, m_star = geom
+    sd = mdp.Subdomain(x0, y0, lx, ly, k, n)
+    mdp.mdp_cache_clear(ctx)
+    P = mdp.mdp_build_projector(ctx, sd, m_star, "c128")
+    Qf = P.q_tensor().cpu().numpy()
+    mdp.mdp_set_projector_path(ctx, "dense")
+    mdp.mdp_cache_clear(ctx)
+    try:
+        Pd = mdp.mdp_build_projector(ctx, sd, m_star, "c128")
+        Qd = Pd.q_tensor().cpu().numpy()
+    finally:
+        mdp.mdp_set_projector_path(ctx, "auto")
+        mdp.mdp_cache_clear(ctx)
+    g = ogrid.APGrid(x0, y0, lx, ly, n)
+    _check_gamma(P, g)
+    cols = np.unique(np.array([0, 1, m_star, 3 * m_star - 1, 4 * m_star, 8 * m_star - 1]))
+    solver = scheme.make_solver(n, g.h, k, "separable" if n > 128 else "auto")
+    Qref = oprojector.build_projector(g, k, m_star, solver, cols=cols)
+    e_dense = np.linalg.norm(Qf - Qd, axis=0) / np.linalg.norm(Qd, axis=0)
+    e_orc = np.linalg.norm(Qf[:, cols] - Qref, axis=0) / np.linalg.norm(Qref, axis=0)
+    print("fused vs dense %.3e, fused vs oracle %.3e" % (e_dense.max(), e_orc.max()))
+    assert e_dense.max() < 1e-10 and e_orc.max() < 1e-10
+
+
 def test_projector_cache_and_release(ctx):
     sd = mdp.Subdomain(0.0, 0.0, 0.5, 1.0, 10.0, 64)
     P1 = mdp.mdp_build_projector(ctx, sd, 16, "c128")
