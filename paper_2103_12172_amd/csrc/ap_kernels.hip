@@ -109,81 +109,75 @@ tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, con
     const T* r_im = fac + 3 * plane + c;
     const T a = colc[c], s0r = colc[W + c], s0i = colc[2 * W + c];
 
-    // forward sweep
-    T yr = fin_re[0], yi = fin_im ? fin_im[0] : T(0);
-    o_re[0] = yr;
-    o_im[0] = yi;
-    constexpr int U = 4;
-    int m = 1;
-    for (; m + U - 1 <= n; m += U) {
-        T fr[U], fi[U], lr[U], li[U];
+    // forward sweep, rows in groups of U with the next group's loads in flight
+    constexpr int U = 8;
+    T yr = T(0), yi = T(0);
+    T fr[U], fi[U], lr[U], li[U], nfr[U], nfi[U], nlr[U], nli[U];
+    auto load_fwd = [&](int m0, T* F, T* Fi, T* Lr, T* Li) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            long off = (long)(m + u) * W;
-            fr[u] = fin_re[off];
-            fi[u] = fin_im ? fin_im[off] : T(0);
-            lr[u] = l_re[off];
-            li[u] = l_im[off];
+            const long off = (long)min(m0 + u, n) * W;
+            F[u] = fin_re[off];
+            Fi[u] = fin_im ? fin_im[off] : T(0);
+            Lr[u] = l_re[off];
+            Li[u] = l_im[off];
         }
+    };
+    load_fwd(0, fr, fi, lr, li);
+    for (int m0 = 0; m0 <= n; m0 += U) {
+        if (m0 + U <= n) load_fwd(m0 + U, nfr, nfi, nlr, nli);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            T nr = fr[u] - (lr[u] * yr - li[u] * yi);
-            T ni = fi[u] - (lr[u] * yi + li[u] * yr);
+            const int m = m0 + u;
+            if (m > n) break;
+            const T nr = fr[u] - (lr[u] * yr - li[u] * yi);   // l_0 = 0
+            const T ni = fi[u] - (lr[u] * yi + li[u] * yr);
             yr = nr;
             yi = ni;
-            long off = (long)(m + u) * W;
-            o_re[off] = yr;
-            o_im[off] = yi;
+            o_re[(long)m * W] = yr;
+            o_im[(long)m * W] = yi;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            fr[u] = nfr[u];
+            fi[u] = nfi[u];
+            lr[u] = nlr[u];
+            li[u] = nli[u];
         }
     }
-    for (; m <= n; ++m) {
-        long off = (long)m * W;
-        T fr = fin_re[off], fi = fin_im ? fin_im[off] : T(0);
-        T lr = l_re[off], li = l_im[off];
-        T nr = fr - (lr * yr - li * yi);
-        T ni = fi - (lr * yi + li * yr);
-        yr = nr;
-        yi = ni;
-        o_re[off] = yr;
-        o_im[off] = yi;
-    }
-    // backward sweep
-    {
-        long off = (long)n * W;
-        T rr = r_re[off], ri = r_im[off];
-        T xr = rr * yr - ri * yi, xi = rr * yi + ri * yr;
-        o_re[off] = xr;
-        o_im[off] = xi;
-        m = n - 1;
-        for (; m - U + 1 >= 1; m -= U) {
-            T y_r[U], y_i[U], q_r[U], q_i[U];
+    // backward sweep over the same groups, last group first; y comes back from out
+    T xr = T(0), xi = T(0);
+    const int last = (n / U) * U;
+    auto load_bwd = [&](int m0, T* Yr, T* Yi, T* Qr, T* Qi) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                long o2 = (long)(m - u) * W;
-                y_r[u] = o_re[o2];
-                y_i[u] = o_im[o2];
-                q_r[u] = r_re[o2];
-                q_i[u] = r_im[o2];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                T tr = y_r[u] - a * xr, ti = y_i[u] - a * xi;
-                xr = q_r[u] * tr - q_i[u] * ti;
-                xi = q_r[u] * ti + q_i[u] * tr;
-                long o2 = (long)(m - u) * W;
-                o_re[o2] = xr;
-                o_im[o2] = xi;
-            }
+        for (int u = 0; u < U; ++u) {
+            const long off = (long)min(m0 + u, n) * W;
+            Yr[u] = o_re[off];
+            Yi[u] = o_im[off];
+            Qr[u] = r_re[off];
+            Qi[u] = r_im[off];
         }
-        for (; m >= 0; --m) {
-            long o2 = (long)m * W;
-            T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);
-            T tr = o_re[o2] - (sr * xr - si * xi), ti = o_im[o2] - (sr * xi + si * xr);
-            T q_r = r_re[o2], q_i = r_im[o2];
-            xr = q_r * tr - q_i * ti;
-            xi = q_r * ti + q_i * tr;
-            o_re[o2] = xr;
-            o_im[o2] = xi;
+    };
+    load_bwd(last, fr, fi, lr, li);
+    for (int m0 = last; m0 >= 0; m0 -= U) {
+        if (m0 >= U) load_bwd(m0 - U, nfr, nfi, nlr, nli);
+#pragma unroll
+        for (int u = U - 1; u >= 0; --u) {
+            const int m = m0 + u;
+            if (m > n) continue;
+            const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);   // x_{n+1} = 0
+            const T tr = fr[u] - (sr * xr - si * xi), ti = fi[u] - (sr * xi + si * xr);
+            xr = lr[u] * tr - li[u] * ti;
+            xi = lr[u] * ti + li[u] * tr;
+            o_re[(long)m * W] = xr;
+            o_im[(long)m * W] = xi;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            fr[u] = nfr[u];
+            fi[u] = nfi[u];
+            lr[u] = nlr[u];
+            li[u] = nli[u];
         }
     }
 }
@@ -330,21 +324,80 @@ __global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restr
 // ------------------------------------------------------------------ density on gamma for reconstruction
 // w_b(gamma_i) = sum_col E(i, col) c_b(col)  (E real, c complex); w is pre-zeroed elsewhere.
 __global__ void extend_density_kernel(const double* __restrict__ E, int ng, int ncol, const double* __restrict__ c,
-                                      const int* __restrict__ gm, const int* __restrict__ gq, int n, double* w,
-                                      long w_stride) {
+                                      const int* __restrict__ gm, const int* __restrict__ gq,
+                                      const int* __restrict__ gside, int n, double* w, long w_stride) {
+    // row i of E is nonzero only in its side's Dirichlet and Neumann columns
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= ng) return;
+    const int M = ncol / 8, s = gside[i];
     double re = 0.0, im = 0.0;
     const double* cb = c + 2 * (long)b * ncol;
-    for (int col = 0; col < ncol; ++col) {
-        double e = E[(long)col * ng + i];
-        re += e * cb[2 * col];
-        im += e * cb[2 * col + 1];
+    for (int kind = 0; kind < 2; ++kind) {
+        const int col0 = kind * 4 * M + s * M;
+#pragma unroll 8
+        for (int j = 0; j < M; ++j) {
+            const double e = E[(long)(col0 + j) * ng + i];
+            re += e * cb[2 * (col0 + j)];
+            im += e * cb[2 * (col0 + j) + 1];
+        }
     }
     double* o = w + 2 * ((long)b * w_stride + (long)gm[i] * (n + 1) + gq[i]);
     o[0] = re;
     o[1] = im;
+}
+
+// Extension matrix E = Ex Psi (Sec. 3.2.3-3.2.4, eqs. general_extension,
+// cartesian_extension, Psi_def): column-major |gamma| x 8M*, zero outside the
+// node's side.  For gamma node i on side s, at signed distance rho from the
+// side line and side parameter t, with psi = T_j(t) and tangential derivatives
+// psi^(p) = (2 / side length)^p T_j^(p)(t):
+//   Dirichlet column s M* + j:       psi + rho^2/2 (-psi_tt - k^2 psi)
+//                                    + rho^4/24 (psi_tttt + 2 k^2 psi_tt + k^4 psi)
+//   Neumann column 4M* + s M* + j:   rho psi + rho^3/6 (-psi_tt - k^2 psi)
+// (the Taylor expansion in rho of a Helmholtz solution with u = psi, du/dn = 0
+// resp. u = 0, du/dn = psi on the side, normal derivatives replaced through the
+// equation).  T_j^(p) by the differentiated recurrence
+// T_{j+1}^(p) = 2 t T_j^(p) + 2 p T_j^(p-1) - T_{j-1}^(p), one thread per node.
+// The other 6M* entries of the row are left as they are (the caller zeroes E).
+__global__ void extension_kernel(const int* __restrict__ side, const double* __restrict__ rho,
+                                 const double* __restrict__ tpar, const double* __restrict__ slen, int ng, double k,
+                                 int M, double* __restrict__ E) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ng) return;
+    const int s = side[i];
+    const double t = tpar[i], r = rho[i];
+    const double sc = 2.0 / slen[i], sc2 = sc * sc, sc4 = sc2 * sc2;
+    const double k2 = k * k, k4 = k2 * k2;
+    const double r2 = r * r, r3 = r2 * r, r4 = r2 * r2;
+    double cur[5] = {1.0, 0.0, 0.0, 0.0, 0.0};    // T_j^(p), p = 0..4
+    double prev[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // T_{j-1}^(p)
+    for (int j = 0; j < M; ++j) {
+        const double p0 = cur[0], p2 = sc2 * cur[2], p4 = sc4 * cur[4];
+        E[(long)(s * M + j) * ng + i] = p0 + 0.5 * r2 * (-p2 - k2 * p0) + (r4 / 24.0) * (p4 + 2.0 * k2 * p2 + k4 * p0);
+        E[(long)(4 * M + s * M + j) * ng + i] = r * p0 + (r3 / 6.0) * (-p2 - k2 * p0);
+        double nxt[5];
+        if (j == 0) {
+            nxt[0] = t;
+            nxt[1] = 1.0;
+            nxt[2] = nxt[3] = nxt[4] = 0.0;
+        } else {
+#pragma unroll
+            for (int p = 0; p < 5; ++p) nxt[p] = 2.0 * t * cur[p] - prev[p] + (p ? 2.0 * p * cur[p - 1] : 0.0);
+        }
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            prev[p] = cur[p];
+            cur[p] = nxt[p];
+        }
+    }
+}
+
+// gidx[gm[i] (n+1) + gq[i]] = i (the map was filled with -1)
+__global__ void gamma_index_kernel(const int* __restrict__ gm, const int* __restrict__ gq, int ng, int n,
+                                   int* __restrict__ gidx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ng) gidx[gm[i] * (n + 1) + gq[i]] = i;
 }
 
 inline unsigned grid_for(long total, int block = 256) {
@@ -411,10 +464,12 @@ void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, int R
 }
 
 void launch_extend_density(const double* E, int ng, int ncol, const double* c, int R, const int* gm,
-                           const int* gq, int n, double* w, long w_stride, hipStream_t st) {
+                           const int* gq, const int* gside, int n, double* w, long w_stride, hipStream_t st) {
     check_batch(R);
+    if (ncol % 8) throw Error(MDP_ERR_ARG, "extension matrix width must be 8 M*");
     dim3 grid((ng + 255) / 256, R);
-    hipLaunchKernelGGL(extend_density_kernel, grid, dim3(256), 0, st, E, ng, ncol, c, gm, gq, n, w, w_stride);
+    hipLaunchKernelGGL(extend_density_kernel, grid, dim3(256), 0, st, E, ng, ncol, c, gm, gq, gside, n, w,
+                       w_stride);
     MDP_HIP(hipGetLastError());
 }
 
@@ -738,6 +793,20 @@ __global__ void gather_q_fused_kernel(const double* __restrict__ us, const doubl
 }
 
 }  // namespace
+
+void launch_extension(const int* side, const double* rho, const double* t, const double* slen, int ng, double k,
+                      int m_star, double* E, hipStream_t st) {
+    if (ng <= 0) return;
+    hipLaunchKernelGGL(extension_kernel, dim3((ng + 255) / 256), dim3(256), 0, st, side, rho, t, slen, ng, k, m_star,
+                       E);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_gamma_index(const int* gm, const int* gq, int ng, int n, int* gidx, hipStream_t st) {
+    if (ng <= 0) return;
+    hipLaunchKernelGGL(gamma_index_kernel, dim3((ng + 255) / 256), dim3(256), 0, st, gm, gq, ng, n, gidx);
+    MDP_HIP(hipGetLastError());
+}
 
 bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi) {
     return q_hi == f.n - q_lo && q_lo >= 2 && q_lo <= f.p - 2 && m_lo >= 2 && m_hi <= f.n - 2 && m_hi - m_lo >= 3 &&

@@ -34,12 +34,19 @@ struct PackedWork {
     DevBuf dQ, dm, ds, doff, droff, dsub, dp, dgcol, dstart, dcols, dcoef, Ap, Gi;
 };
 
+// Interface assembly and reconstruction buffers (grow-only).
+struct CallWork {
+    DevBuf qsrc, qld, roff, cmap, coef, kcol, kval, koff, F, x;   // mdp_solve_interface
+    DevBuf rc_c, rc_w;                                          // mdp_reconstruct
+};
+
 // Grow-only device workspaces of a context.
 struct Workspace {
     DevBuf a, b, c;       // folded batch buffers
     DevBuf zg;            // split-K partial products of the complex GEMM
     LSWork ls;            // interface least squares
     PackedWork pk;        // block-sparse interface matrix
+    CallWork cw;          // per-call temporaries
     Profiler prof;        // optional per-launch timing
 };
 

@@ -22,7 +22,10 @@ struct mdp_projector {
     DevBuf Q;      // n_gamma x 8M* complex, column-major
     DevBuf E;      // n_gamma x 8M* real
     DevBuf gidx;   // (n+1)^2 node -> gamma index
-    DevBuf gm, gq; // gamma nodes
+    DevBuf meta;   // gamma nodes: gm, gq, side (int), then rho, t, side length (double)
+    std::vector<char> meta_host;  // host copy the upload reads from
+    const int *gm = nullptr, *gq = nullptr, *gside = nullptr;
+    const double *grho = nullptr, *gt = nullptr, *gslen = nullptr;
 };
 
 namespace {
@@ -102,6 +105,23 @@ void upload(DevBuf& d, const std::vector<T>& v) {
     if (!v.empty()) MDP_HIP(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
+// Grow a workspace buffer (after the device has drained, since earlier work
+// may still use the old allocation; contents are not kept).
+void ensure(DevBuf& d, size_t bytes) {
+    if (bytes > d.bytes) {
+        MDP_HIP(hipDeviceSynchronize());
+        d.reserve(bytes);
+    }
+}
+
+// Copy a host vector into a grow-only workspace buffer on the stream.  The
+// host vector must stay alive until the stream has consumed it.
+template <class T>
+void upload_ws(DevBuf& d, const std::vector<T>& v, hipStream_t st) {
+    ensure(d, std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (!v.empty()) MDP_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
 // Grow the batch workspaces before a solve so that no buffer is freed while
 // earlier work may still use it.
 void prepare_ws(mdp_ctx* ctx, const APPlan& P, int precision, int R) {
@@ -175,7 +195,7 @@ void build_q_fused(mdp_ctx* ctx, const APPlan& plan, mdp_projector* P, hipStream
         pr.run("gemm_sine_f64", st, 8.0 * R * gemm_row_flops, 2.0 * 8.0 * R * (n - 1) * 8.0,
                [&] { launch_gemm_bd<double>(xs, plan.Si64.as<double>(), us, (long)R * 8, f, st); });
         pr.run("gather_q", st, 0.0, (double)ng * R * 16.0 * 2.0, [&] {
-            launch_gather_q_fused(us, thin, f, G.m_lo, G.m_hi, G.q_lo, G.q_hi, P->gm.as<int>(), P->gq.as<int>(), ng,
+            launch_gather_q_fused(us, thin, f, G.m_lo, G.m_hi, G.q_lo, G.q_hi, P->gm, P->gq, ng,
                                   R, P->Q.as<double>(), ng, col0, st);
         });
     }
@@ -257,18 +277,39 @@ int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int p
         P->m_star = m_star;
         P->precision = precision;
         const int ng = g.n_gamma, ncol = 8 * m_star;
-        std::vector<double> E = extension_matrix(g, sd->k, m_star);
-        std::vector<int> gidx((size_t)(g.n + 1) * (g.n + 1), -1);
-        for (int i = 0; i < ng; ++i) gidx[(size_t)g.gm[i] * (g.n + 1) + g.gq[i]] = i;
-        upload(P->E, E);
-        upload(P->gidx, gidx);
-        upload(P->gm, g.gm);
-        upload(P->gq, g.gq);
+        begin_call(ctx, st);
+        // gamma node lists in one upload; E and the node -> gamma map are built on the device
+        const size_t ints = ((3 * (size_t)ng + 1) / 2) * 2, meta_bytes = ints * sizeof(int) + 3 * (size_t)ng * sizeof(double);
+        P->meta_host.assign(meta_bytes, 0);
+        int* hi = reinterpret_cast<int*>(P->meta_host.data());
+        double* hd = reinterpret_cast<double*>(hi + ints);
+        std::copy(g.gm.begin(), g.gm.end(), hi);
+        std::copy(g.gq.begin(), g.gq.end(), hi + ng);
+        std::copy(g.side.begin(), g.side.end(), hi + 2 * ng);
+        std::copy(g.rho.begin(), g.rho.end(), hd);
+        std::copy(g.t.begin(), g.t.end(), hd + ng);
+        std::copy(g.slen.begin(), g.slen.end(), hd + 2 * ng);
+        P->meta.alloc(meta_bytes);
+        MDP_HIP(hipMemcpyAsync(P->meta.p, P->meta_host.data(), meta_bytes, hipMemcpyHostToDevice, st));
+        const int* di = P->meta.as<int>();
+        const double* dd = reinterpret_cast<const double*>(di + ints);
+        P->gm = di;
+        P->gq = di + ng;
+        P->gside = di + 2 * ng;
+        P->grho = dd;
+        P->gt = dd + ng;
+        P->gslen = dd + 2 * ng;
+        P->E.alloc((size_t)ng * ncol * sizeof(double));
+        MDP_HIP(hipMemsetAsync(P->E.p, 0, (size_t)ng * ncol * sizeof(double), st));
+        launch_extension(P->gside, P->grho, P->gt, P->gslen, ng, sd->k, m_star, P->E.as<double>(), st);
+        const size_t nodes = (size_t)(g.n + 1) * (g.n + 1);
+        P->gidx.alloc(nodes * sizeof(int));
+        MDP_HIP(hipMemsetAsync(P->gidx.p, 0xff, nodes * sizeof(int), st));   // -1 everywhere
+        launch_gamma_index(P->gm, P->gq, ng, g.n, P->gidx.as<int>(), st);
         P->Q.alloc((size_t)ng * ncol * 2 * sizeof(double));
         P->g = std::move(g);
         const Geometry& G = P->g;
 
-        begin_call(ctx, st);
         if (precision == MDP_C128 && ctx->projector_path == MDP_PATH_AUTO &&
             fused_projector_supported(plan.f, G.m_lo, G.m_hi, G.q_lo, G.q_hi)) {
             build_q_fused(ctx, plan, P.get(), st);
@@ -291,8 +332,8 @@ int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int p
             src.gidx = P->gidx.as<int>();
             src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
             double* Qd = P->Q.as<double>();
-            const int* gmd = P->gm.as<int>();
-            const int* gqd = P->gq.as<int>();
+            const int* gmd = P->gm;
+            const int* gqd = P->gq;
             const int n = G.n;
             const Fold f = plan.f;
             solve_batch(plan, ctx->ws, precision, src, false, R,
@@ -448,16 +489,19 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
         std::vector<const double2*> qsrc(n_sub);
         std::vector<int> qld(n_sub);
         for (int i = 0; i < n_sub; ++i) { qsrc[i] = P[i]->Q.as<const double2>(); qld[i] = P[i]->g.n_gamma; }
-        DevBuf d_qsrc, d_qld, d_roff, d_cmap, d_coef, d_kcol, d_kval, d_koff;
-        upload(d_qsrc, qsrc);
-        upload(d_qld, qld);
-        upload(d_roff, row_off);
-        upload(d_cmap, colmap);
-        upload(d_coef, coefs);
-        upload(d_kcol, kcol);
-        upload(d_kval, kval);
-        upload(d_koff, koff);
-        DevBuf F((size_t)m * sizeof(double2)), x((size_t)ncol * sizeof(double2));
+        CallWork& cw = ctx->ws.cw;
+        DevBuf &d_qsrc = cw.qsrc, &d_qld = cw.qld, &d_roff = cw.roff, &d_cmap = cw.cmap, &d_coef = cw.coef,
+               &d_kcol = cw.kcol, &d_kval = cw.kval, &d_koff = cw.koff, &F = cw.F, &x = cw.x;
+        upload_ws(d_qsrc, qsrc, st);
+        upload_ws(d_qld, qld, st);
+        upload_ws(d_roff, row_off, st);
+        upload_ws(d_cmap, colmap, st);
+        upload_ws(d_coef, coefs, st);
+        upload_ws(d_kcol, kcol, st);
+        upload_ws(d_kval, kval, st);
+        upload_ws(d_koff, koff, st);
+        ensure(F, (size_t)m * sizeof(double2));
+        ensure(x, (size_t)ncol * sizeof(double2));
         launch_known_rhs(d_qsrc.as<const double2* const>(), d_qld.as<int>(), n_sub, d_roff.as<int>(), m,
                          d_kcol.as<int>(), d_kval.as<double2>(), d_koff.as<int>(), F.as<double2>(), st);
         // block-sparse description: subdomain i's rows touch only the unknown blocks with a contribution from i
@@ -593,13 +637,16 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
             const int n = G.n, ng = G.n_gamma, ncol = 8 * Pi->m_star, R = (int)grp.size();
             const long npts = (long)(n + 1) * (n + 1);
             APPlan& plan = get_plan(ctx, n, G.h, Pi->k);
-            DevBuf cb((size_t)R * ncol * sizeof(mdp_c128)), wb((size_t)R * npts * sizeof(mdp_c128));
+            DevBuf& cb = ctx->ws.cw.rc_c;
+            DevBuf& wb = ctx->ws.cw.rc_w;
+            ensure(cb, (size_t)R * ncol * sizeof(mdp_c128));
+            ensure(wb, (size_t)R * npts * sizeof(mdp_c128));
             for (int r = 0; r < R; ++r)
                 MDP_HIP(hipMemcpyAsync(cb.as<mdp_c128>() + (size_t)r * ncol, c + (size_t)grp[r] * ncol,
                                        ncol * sizeof(mdp_c128), hipMemcpyDeviceToDevice, st));
-            MDP_HIP(hipMemsetAsync(wb.p, 0, wb.bytes, st));
-            launch_extend_density(Pi->E.as<double>(), ng, ncol, cb.as<double>(), R, Pi->gm.as<int>(), Pi->gq.as<int>(),
-                                  n, wb.as<double>(), npts, st);
+            MDP_HIP(hipMemsetAsync(wb.p, 0, (size_t)R * npts * sizeof(mdp_c128), st));
+            launch_extend_density(Pi->E.as<double>(), ng, ncol, cb.as<double>(), R, Pi->gm, Pi->gq, Pi->gside, n,
+                                  wb.as<double>(), npts, st);
             const int chunk = chunk_size(plan, Pi->precision, ctx->ws_cap, R);
             prepare_ws(ctx, plan, Pi->precision, chunk);
             for (int r0 = 0; r0 < R; r0 += chunk) {
@@ -628,7 +675,6 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
             for (int r = 0; r < R; ++r)
                 MDP_HIP(hipMemcpyAsync(u_out + off[grp[r]], wb.as<mdp_c128>() + (size_t)r * npts,
                                        npts * sizeof(mdp_c128), hipMemcpyDeviceToDevice, st));
-            MDP_HIP(hipStreamSynchronize(st));  // temporaries are freed on return
         }
         end_call(ctx, st);
         return MDP_OK;

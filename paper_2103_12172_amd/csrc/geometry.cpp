@@ -80,44 +80,4 @@ Geometry make_geometry(double x0, double y0, double lx, double ly, int n) {
     return g;
 }
 
-// E(i, col) for gamma node i on side s, at signed distance rho, side parameter t:
-//   Dirichlet column (xi0 = psi, xi1 = 0):
-//     psi + rho^2/2 (-psi'' - k^2 psi) + rho^4/24 (psi'''' + 2 k^2 psi'' + k^4 psi)
-//   Neumann column (xi0 = 0, xi1 = psi):
-//     rho psi + rho^3/6 (-psi'' - k^2 psi)
-// with psi = T_j(t) and tangential derivatives psi^(p) = (2/side length)^p T_j^(p)(t).
-// T_j^(p) from the three-term recurrence differentiated p times:
-//   T_{j+1}^(p) = 2 t T_j^(p) + 2 p T_j^(p-1) - T_{j-1}^(p).
-std::vector<double> extension_matrix(const Geometry& g, double k, int m_star) {
-    const int ng = g.n_gamma;
-    std::vector<double> E((size_t)ng * 8 * m_star, 0.0);
-    std::vector<double> T(5 * (size_t)m_star);
-    const double k2 = k * k, k4 = k2 * k2;
-    for (int i = 0; i < ng; ++i) {
-        const double t = g.t[i];
-        for (int p = 0; p <= 4; ++p) {
-            double* Tp = &T[(size_t)p * m_star];
-            const double* Tq = p ? &T[(size_t)(p - 1) * m_star] : nullptr;
-            if (m_star > 0) Tp[0] = (p == 0) ? 1.0 : 0.0;
-            if (m_star > 1) Tp[1] = (p == 0) ? t : (p == 1 ? 1.0 : 0.0);
-            for (int j = 1; j + 1 < m_star; ++j) {
-                double v = 2.0 * t * Tp[j] - Tp[j - 1];
-                if (p) v += 2.0 * p * Tq[j];
-                Tp[j + 1] = v;
-            }
-        }
-        const double sc = 2.0 / g.slen[i], sc2 = sc * sc, sc4 = sc2 * sc2;
-        const double r = g.rho[i], r2 = r * r, r3 = r2 * r, r4 = r2 * r2;
-        const int s = g.side[i];
-        for (int j = 0; j < m_star; ++j) {
-            double p0 = T[j], p2 = sc2 * T[2 * (size_t)m_star + j], p4 = sc4 * T[4 * (size_t)m_star + j];
-            double dcol = p0 + 0.5 * r2 * (-p2 - k2 * p0) + (r4 / 24.0) * (p4 + 2.0 * k2 * p2 + k4 * p0);
-            double ncol = r * p0 + (r3 / 6.0) * (-p2 - k2 * p0);
-            E[(size_t)(s * m_star + j) * ng + i] = dcol;
-            E[(size_t)(4 * m_star + s * m_star + j) * ng + i] = ncol;
-        }
-    }
-    return E;
-}
-
 }  // namespace mdp

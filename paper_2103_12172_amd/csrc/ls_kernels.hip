@@ -191,37 +191,43 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// pivot used by the elimination: a non-positive (or NaN) one is replaced by 1
+__device__ inline double unit_if_bad(double d) { return d > 0.0 ? d : 1.0; }
+
 // Cholesky factor and inverse of one Hermitian positive definite diagonal
 // block of order nb <= 64: G (lower triangle read, ld ldg) = L L^*, L to Lout
-// (ld ldl, lower triangle written), L^{-1} to Linv (ld ldi, lower triangle
-// written); the caller zeroes the strict upper triangles.  `shift` is added
-// to the diagonal first; orders below 64 are padded with the identity.
-// Right-looking, one column per step: with S the Schur complement and X the
-// inverse of the unit lower factor (both unscaled), step k takes the pivot
-// d_k = S(k,k) and updates S(i,j) -= S(i,k) conj(S(j,k)) / d_k (j > k) and
-// X(i,j) -= S(i,k) X(k,j) / d_k (i > k); then L(i,j) = S(i,j)/sqrt(d_j) and
-// L^{-1}(i,j) = X(i,j)/sqrt(d_i).  Column k of S and row k of X are broadcast
-// through LDS (double-buffered: one barrier per step).  The 136 4x4 tiles of
-// the lower triangle are spread 34 per wavefront; a tile's S and X entries
-// stay in registers.  A non-positive pivot sets *info to base + its 1-based
-// index (first failure wins).
-__global__ void __launch_bounds__(256)
+// (ld ldl) and L^{-1} to Linv (ld ldi), lower triangles written (the caller
+// zeroes the strict upper triangles).  `shift` is added to the diagonal
+// first; orders below 64 are padded with the identity.
+//
+// Unscaled right-looking elimination of [S | I]: step k takes the pivot
+// d_k = S(k,k), Lt(i,k) = S(i,k)/d_k, and for every row i > k updates
+//   S(i,j) -= Lt(i,k) conj(S(j,k))   for k < j <= i   (Schur complement),
+//   X(i,j) -= Lt(i,k) X(k,j)         for j <= k       (X = unit factor^-1).
+// Row i's lower entries j <= i are exactly one of the two at every step, so
+// one array M holds S right of the eliminated columns and X left of them, and
+// the step is the single update M(i,j) -= Lt(i,k) v_j with v_j = conj(S(j,k))
+// for j > k, v_j = X(k,j) for j < k and v_k = d_k + 1 (which turns M(i,k) =
+// S(i,k) into X(i,k) = -Lt(i,k)).  Column k of S is kept in LDS for L; at the
+// end L(i,j) = S(i,j)/sqrt(d_j), L^{-1}(i,j) = X(i,j)/sqrt(d_i).
+// Threads: the 136 4x4 tiles of the lower triangle, one per thread (3
+// wavefronts); each step is one barrier, its update branch-free.  A
+// non-positive pivot sets *info to base + its 1-based index (first failure
+// wins).
+__global__ void __launch_bounds__(192)
 chol64_kernel(const double2* __restrict__ G, int ldg, int nb, double shift, double2* __restrict__ Lout, int ldl,
               double2* __restrict__ Linv, int ldi, int* info, int base) {
-    __shared__ double2 colS[2][64];
-    __shared__ double2 rowX[2][64];
+    __shared__ double2 Ls[64][64];   // Ls[k][i] = S(i,k) at step k (i > k)
+    __shared__ double2 vb[2][64];    // v of the step (double-buffered)
     __shared__ double piv[64];
-    __shared__ int bad_s;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const bool act = lane < 34;
-    // tile number t -> (ti, tj) with t = ti (ti + 1) / 2 + tj, tj <= ti
-    const int t = (tid >> 6) * 34 + (act ? lane : 0);
+    const bool act = tid < 136;
     int ti = 0;
+    const int t = act ? tid : 0;
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     const int tj = t - ti * (ti + 1) / 2;
     const int r0 = 4 * ti, c0 = 4 * tj;
-    double sr[4][4], si[4][4], xr[4][4], xi[4][4];
+    double mr[4][4], mi[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -233,85 +239,98 @@ chol64_kernel(const double2* __restrict__ G, int ldg, int nb, double shift, doub
                 else if (i == j) v = make_double2(1.0, 0.0);
                 if (i == j && i < nb) v.x += shift;
             }
-            sr[a][b] = v.x;
-            si[a][b] = v.y;
-            xr[a][b] = (i == j) ? 1.0 : 0.0;
-            xi[a][b] = 0.0;
+            mr[a][b] = v.x;
+            mi[a][b] = v.y;
         }
-    if (tid == 0) bad_s = 0;
+    int bad = 0;
     for (int kt = 0; kt < 16; ++kt) {
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int k = 4 * kt + kk, buf = kk & 1;
-            if (act && tj == kt) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a) colS[buf][r0 + a] = make_double2(sr[a][kk], si[a][kk]);
-            }
-            if (act && ti == kt) {
-#pragma unroll
-                for (int b = 0; b < 4; ++b) rowX[buf][c0 + b] = make_double2(xr[kk][b], xi[kk][b]);
-            }
-            __syncthreads();
-            double d = colS[buf][k].x;
-            if (!(d > 0.0)) {
-                if (tid == 0 && !bad_s) bad_s = k + 1;
-                d = 1.0;
-            }
-            if (tid == 0) piv[k] = d;
-            const double dinv = recip(d);
-            if (act && r0 + 3 > k) {
-                double2 ci[4], cj[4], xk[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) ci[a] = colS[buf][r0 + a];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) cj[b] = colS[buf][c0 + b];
-                const bool xupd = tj <= kt, supd = c0 + 3 > k;
-                if (xupd) {
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) xk[b] = rowX[buf][c0 + b];
-                }
+            if (act && tj == kt) {   // column k: Lt source, v right of the pivot, the pivot
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     const int i = r0 + a;
-                    if (i <= k) continue;
-                    const double lr = ci[a].x * dinv, li = ci[a].y * dinv;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int j = c0 + b;
-                        if (supd && j > k && j <= i) {
-                            sr[a][b] -= lr * cj[b].x + li * cj[b].y;
-                            si[a][b] -= li * cj[b].x - lr * cj[b].y;
-                        }
-                        if (xupd) {
-                            xr[a][b] -= lr * xk[b].x - li * xk[b].y;
-                            xi[a][b] -= lr * xk[b].y + li * xk[b].x;
-                        }
+                    if (i > k) {
+                        Ls[k][i] = make_double2(mr[a][kk], mi[a][kk]);
+                        vb[buf][i] = make_double2(mr[a][kk], -mi[a][kk]);
+                    } else if (i == k) {
+                        piv[k] = mr[a][kk];
+                        vb[buf][k] = make_double2(mr[a][kk] + 1.0, 0.0);
                     }
                 }
             }
+            if (act && ti == kt) {   // row k of X left of the pivot
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int j = c0 + b;
+                    if (j < k) vb[buf][j] = make_double2(mr[kk][b], mi[kk][b]);
+                }
+            }
+            __syncthreads();
+            double d = piv[k];
+            if (!(d > 0.0)) {   // breakdown: reported, and the step continues with a unit pivot
+                if (!bad) bad = k + 1;
+                d = 1.0;
+            }
+            const double dinv = recip(d);
+            double lr[4], li[4], vr[4], vi[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const double2 c = Ls[k][r0 + a];   // rows <= k: not written this step, masked out
+                const bool live = r0 + a > k;
+                lr[a] = live ? c.x * dinv : 0.0;
+                li[a] = live ? c.y * dinv : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const double2 v = vb[buf][c0 + b];
+                vr[b] = v.x;
+                vi[b] = v.y;
+            }
+            // M -= Lt v, as two fused multiply-adds per component straight into the
+            // accumulators (32 independent chains)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    mr[a][b] = fma(-lr[a], vr[b], mr[a][b]);
+                    mi[a][b] = fma(-lr[a], vi[b], mi[a][b]);
+                }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    mr[a][b] = fma(li[a], vi[b], mr[a][b]);
+                    mi[a][b] = fma(-li[a], vr[b], mi[a][b]);
+                }
         }
     }
-    __syncthreads();
     if (!act) return;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+        const int i = r0 + a;
+        if (i >= nb) continue;
+        const double sdi = sqrt(unit_if_bad(piv[i])), rdi = recip(sdi);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int i = r0 + a, j = c0 + b;
-            if (i >= nb || j > i) continue;
+            const int j = c0 + b;
+            if (j > i) continue;
             double2 l, x;
             if (j < i) {
-                const double sc = recip(sqrt(piv[j]));
-                l = make_double2(sr[a][b] * sc, si[a][b] * sc);
+                const double2 sv = Ls[j][i];
+                const double sc = recip(sqrt(unit_if_bad(piv[j])));
+                l = make_double2(sv.x * sc, sv.y * sc);
+                x = make_double2(mr[a][b] * rdi, mi[a][b] * rdi);
             } else {
-                l = make_double2(sqrt(piv[j]), 0.0);
+                l = make_double2(sdi, 0.0);
+                x = make_double2(rdi, 0.0);
             }
-            const double sx = recip(sqrt(piv[i]));
-            x = make_double2(xr[a][b] * sx, xi[a][b] * sx);
             Lout[i + (long)j * ldl] = l;
             Linv[i + (long)j * ldi] = x;
         }
-    if (tid == 0 && bad_s && info) atomicCAS(info, 0, base + bad_s);
+    }
+    if (tid == 0 && bad && info) atomicCAS(info, 0, base + bad);
 }
 
 // max and min Cholesky pivot ratio estimate: diag of L (ld) -> out[0] = max |L_ii|^2, out[1] = min |L_ii|^2
@@ -389,9 +408,15 @@ zgemv_n_kernel(int m, int n, const double2* __restrict__ A, int lda, const doubl
     atomicAdd(&y[2 * i + 1], alpha.x * si + alpha.y * sr);
 }
 
+// y = beta y; beta = 0 overwrites y with zeros without reading it (y may hold
+// anything, NaN included, when the caller asks for y = A x)
 __global__ void zscale_kernel(int m, double2* y, double2 beta) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= m) return;
+    if (beta.x == 0.0 && beta.y == 0.0) {
+        y[i] = make_double2(0.0, 0.0);
+        return;
+    }
     const double2 c = y[i];
     y[i] = make_double2(beta.x * c.x - beta.y * c.y, beta.x * c.y + beta.y * c.x);
 }
@@ -624,24 +649,32 @@ __global__ void assemble_qbar_kernel(const double2* const* __restrict__ Qsrc, co
     }
 }
 
-// F(r) = -sum_k Q_s(rl, kcol[k]) * kval[k] over the known coefficients of subdomain s.
+// F(r) = -sum_k Q_s(rl, kcol[k]) * kval[k] over the known coefficients of subdomain s;
+// four lanes per row split the sum.
 __global__ void known_rhs_kernel(const double2* const* __restrict__ Qsrc, const int* __restrict__ qld, int n_sub,
                                  const int* __restrict__ row_off, const int* __restrict__ kcol,
                                  const double2* __restrict__ kval, const int* __restrict__ koff,
                                  double2* __restrict__ F) {
     const int total_rows = row_off[n_sub];
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < total_rows; r += gridDim.x * blockDim.x) {
+    const long gt = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int part = (int)(gt & 3);
+    const long r = gt >> 2;            // the 4 lanes of a row are adjacent in one wavefront
+    double sr = 0.0, si = 0.0;
+    if (r < total_rows) {
         int s = 0;
         while (r >= row_off[s + 1]) ++s;
-        const int rl = r - row_off[s];
-        double sr = 0.0, si = 0.0;
-        for (int k = koff[s]; k < koff[s + 1]; ++k) {
-            double2 q = Qsrc[s][rl + (long)kcol[k] * qld[s]], w = kval[k];
+        const int rl = (int)(r - row_off[s]);
+        for (int k = koff[s] + part; k < koff[s + 1]; k += 4) {
+            const double2 q = Qsrc[s][rl + (long)kcol[k] * qld[s]], w = kval[k];
             sr += w.x * q.x - w.y * q.y;
             si += w.x * q.y + w.y * q.x;
         }
-        F[r] = make_double2(-sr, -si);
     }
+    sr += __shfl_xor(sr, 1, 64);
+    si += __shfl_xor(si, 1, 64);
+    sr += __shfl_xor(sr, 2, 64);
+    si += __shfl_xor(si, 2, 64);
+    if (r < total_rows && part == 0) F[r] = make_double2(-sr, -si);
 }
 
 __global__ void col_norms_kernel(const double2* __restrict__ A, int m, int lda, double* __restrict__ out) {
@@ -742,7 +775,7 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
 void launch_chol_block(const double2* G, int ldg, int nb, double shift, double2* L, int ldl, double2* Linv, int ldi,
                        int* info, int base, hipStream_t st) {
     if (nb < 1 || nb > 64) throw Error(MDP_ERR_ARG, "Cholesky block order must be 1..64");
-    hipLaunchKernelGGL(chol64_kernel, dim3(1), dim3(256), 0, st, G, ldg, nb, shift, L, ldl, Linv, ldi, info, base);
+    hipLaunchKernelGGL(chol64_kernel, dim3(1), dim3(192), 0, st, G, ldg, nb, shift, L, ldl, Linv, ldi, info, base);
     MDP_HIP(hipGetLastError());
 }
 
@@ -756,8 +789,10 @@ void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub,
 
 void launch_known_rhs(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
                       const int* kcol, const double2* kval, const int* koff, double2* F, hipStream_t st) {
-    hipLaunchKernelGGL(known_rhs_kernel, dim3(blocks_for(total_rows)), dim3(256), 0, st, Qsrc, qld, n_sub, row_off,
-                       kcol, kval, koff, F);
+    const unsigned blocks = (unsigned)(((long)total_rows * 4 + 255) / 256);
+    if (total_rows <= 0) return;
+    hipLaunchKernelGGL(known_rhs_kernel, dim3(blocks), dim3(256), 0, st, Qsrc, qld, n_sub, row_off, kcol, kval, koff,
+                       F);
     MDP_HIP(hipGetLastError());
 }
 

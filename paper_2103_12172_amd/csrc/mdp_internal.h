@@ -121,8 +121,13 @@ struct Geometry {
 
 Geometry make_geometry(double x0, double y0, double lx, double ly, int n);
 
-// Extension matrix E = Ex^(H) Psi (|gamma| x 8M*, column-major, real FP64).
-std::vector<double> extension_matrix(const Geometry& g, double k, int m_star);
+// Extension matrix E = Ex^(H) Psi (|gamma| x 8M*, column-major, real FP64) on
+// the device from the gamma nodes' side, rho, t and side length; E must be
+// zeroed first (only each row's own-side columns are written).
+void launch_extension(const int* side, const double* rho, const double* t, const double* slen, int ng, double k,
+                      int m_star, double* E, hipStream_t st);
+// gidx[gm[i] (n+1) + gq[i]] = i over a map filled with -1 beforehand
+void launch_gamma_index(const int* gm, const int* gq, int ng, int n, int* gidx, hipStream_t st);
 
 // ----------------------------------------------------------------- folded sine layout
 // For even n = 2p the type-I sine transform splits by the parity of the mode j:
@@ -173,8 +178,9 @@ void launch_gather_q(const T* u, const float* du, int n, const Fold& f, const in
 template <class T>
 void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, int R, const double* w, long w_stride,
                         double* out, long out_stride, hipStream_t st);
+// w_b(gamma_i) = sum over the Dirichlet and Neumann columns of gamma_i's side of E(i, col) c_b(col)
 void launch_extend_density(const double* E, int ng, int ncol, const double* c, int R, const int* gm,
-                           const int* gq, int n, double* w, long w_stride, hipStream_t st);
+                           const int* gq, const int* gside, int n, double* w, long w_stride, hipStream_t st);
 
 // projector build, support-in / gamma-out form (FP64)
 constexpr int FUSED_K = 8;   // rows per recomputed segment of the fused tridiagonal sweep
