@@ -25,9 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAKS = {  # MI355X published dense peaks
+PEAKS = {  # MI355X published peaks
     "hbm": 8000.0,          # GB/s
-    "f64": 78.6,            # TFLOP/s (MFMA and vector)
+    "f64": 78.6,            # TFLOP/s: FP64 MFMA; FP64 vector = 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
     "f32": 157.3,           # TFLOP/s (MFMA)
 }
 ALGO = {
@@ -35,13 +35,89 @@ ALGO = {
     "gemm_sine_f64": ("mfma", "f64", "flops"),
     "gemm_sine_f32": ("mfma", "f32", "flops"),
     "interface_ls": ("mfma", "f64", "flops"),
+    "ap_fused_f64": ("alu", "f64", "flops"),
     "tridiag_f64": ("hbm", "hbm", "bytes"),
     "tridiag_f32": ("hbm", "hbm", "bytes"),
     "fold_rhs": ("hbm", "hbm", "bytes"),
+    "fold_ring": ("hbm", "hbm", "bytes"),
     "residual": ("hbm", "hbm", "bytes"),
     "gather_q": ("hbm", "hbm", "bytes"),
     "unfold_grid": ("hbm", "hbm", "bytes"),
 }
+# kernel class -> (part of its rocprofv3 kernel name, source file) for the PMC traffic summaries
+KERNELS = {
+    "ap_fused_f64": ("proj_fused_kernel", "paper_2103_12172_amd/csrc/ap_kernels.hip"),
+    "tridiag_f64": ("tridiag_kernel<double>", "paper_2103_12172_amd/csrc/ap_kernels.hip"),
+    "gemm_sine_f64": ("gemm_bd_kernel<double", "paper_2103_12172_amd/csrc/gemm_sine.hip"),
+    "gemm_sine_f32": ("gemm_bd_kernel<float", "paper_2103_12172_amd/csrc/gemm_sine.hip"),
+}
+COPY_BYTES = 1 << 30   # size of the calibration copy
+
+
+def source_sha(path):
+    import hashlib
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
+    (FETCH_SIZE + WRITE_SIZE scaled by the copy calibration), or None when there
+    is none or the kernel's source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if kernel not in KERNELS or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha") != source_sha(KERNELS[kernel][1]):
+        return None
+    return t["bytes_per_launch"]
+
+
+def _counter_kib(csv_path, name_part, counter):
+    """Per-dispatch values (KiB) of one counter for kernels whose name contains name_part."""
+    import csv
+    per = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            if name_part in row["Kernel_Name"] and row["Counter_Name"] == counter:
+                per[row["Dispatch_Id"]] = per.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+    return list(per.values())
+
+
+def write_traffic(kernel, workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
+    """profiles/traffic_<kernel>_<workload>.json from four rocprofv3 --pmc runs:
+    FETCH_SIZE and WRITE_SIZE of the kernel's dispatches, and of the calibration
+    copy of COPY_BYTES (bench.py --copy-calibration), which gives the scale."""
+    import statistics
+    name = KERNELS[kernel][0]
+    fetch = _counter_kib(fetch_csv, name, "FETCH_SIZE")
+    write = _counter_kib(write_csv, name, "WRITE_SIZE")
+    cal_f = max(_counter_kib(cal_fetch_csv, "copyBuffer", "FETCH_SIZE"))
+    cal_w = max(_counter_kib(cal_write_csv, "copyBuffer", "WRITE_SIZE"))
+    sf, sw = COPY_BYTES / (cal_f * 1024.0), COPY_BYTES / (cal_w * 1024.0)
+    fb = statistics.median(fetch) * 1024.0 * sf
+    wb = statistics.median(write) * 1024.0 * sw
+    out = {"kernel": kernel, "rocprof_name": name, "workload": workload, "dispatches": len(fetch),
+           "fetch_kib_median": statistics.median(fetch), "write_kib_median": statistics.median(write),
+           "copy_bytes": COPY_BYTES, "copy_fetch_kib": cal_f, "copy_write_kib": cal_w,
+           "scale_fetch": sf, "scale_write": sw, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+           "bytes_per_launch": fb + wb, "source_sha": source_sha(KERNELS[kernel][1])}
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def copy_calibration(reps=3):
+    """A plain device copy of COPY_BYTES (the scale of the PMC byte counters)."""
+    import torch
+    a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "reps": reps}))
 
 
 def ap_points_per_step(w) -> float:
@@ -56,7 +132,9 @@ def ap_points_per_step(w) -> float:
     return pts
 
 
-def roofline(report: dict):
+
+
+def roofline(report: dict, workload: str):
     # the dominant single kernel class ("interface_ls" is a span of many small kernels, reported separately)
     name = max((k for k in report if k != "interface_ls"), key=lambda k: report[k]["total_ms"])
     r = report[name]
@@ -71,8 +149,9 @@ def roofline(report: dict):
         unit = "GB/s"
     peak = PEAKS[peak_key]
     return name, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                  "frac": round(achieved / peak, 4), "traffic": None, "kernel": name,
-                  "avg_launch_ms": round(avg_ms, 5), "launches": r["count"]}
+                  "frac": round(achieved / peak, 4), "traffic": measured_traffic(name, workload), "kernel": name,
+                  "avg_launch_ms": round(avg_ms, 5), "launches": r["count"],
+                  "algorithmic_%s_per_launch" % what: per_launch}
 
 
 def run_steps(ctx, w, prec, sides, steps, warmup, profile):
@@ -120,22 +199,28 @@ def warm_ms(ctx, w, prec, sides, reps=5):
     return best * 1e3
 
 
-def cpu_baseline(w, pts):
-    """The CPU oracle, as it stands, on the same workload (one full DD solve)."""
-    import numpy as np
+
+
+def cpu_baseline(w, pts, min_seconds=10.0, max_reps=3):
+    """The CPU oracle, as it stands, on the same workload: full DD solves repeated
+    until about min_seconds of CPU work (at most max_reps)."""
     from oracle import solve as osolve
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    ores = osolve.dd_solve(w)
-    dt = time.perf_counter() - t0
+    reps, total, ores = 0, 0.0, None
+    while reps < max_reps and (reps == 0 or total < min_seconds):
+        t0 = time.perf_counter()
+        ores = osolve.dd_solve(w)
+        total += time.perf_counter() - t0
+        reps += 1
+    dt = total / reps
     return ores, {"value": pts / dt, "unit": "AP grid-points/s", "cores": int(threads), "kind": "oracle",
-                  "sample": "one full cold DD solve of the same workload (all projector columns by the separable "
-                            "sine + LAPACK tridiagonal route, Householder least squares, reconstruction): %.2f s"
-                            % dt}
+                  "sample": "%d full cold DD solve(s) of the same workload (every projector column by the separable "
+                            "sine + LAPACK banded tridiagonal route, Householder least squares, reconstruction), "
+                            "%.2f s each" % (reps, dt)}
 
 
 def main():
@@ -144,12 +229,19 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cross_point", choices=["two_rect", "cross_point", "transmission"])
-    ap.add_argument("--precision", default=None, help="c128 | c64 | c64r (default: the workload's)")
-    ap.add_argument("--compare", default="c128", help="second precision timed for comparison ('' = none)")
+    ap.add_argument("--precision", default="c128", help="c128 | c64 | c64r: precision of the reported value")
+    ap.add_argument("--compare", default="c64r,c64", help="precisions also timed, comma-separated ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run the copy that scales PMC counters")
+    ap.add_argument("--write-traffic", nargs=5,
+                    metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="reduce four rocprofv3 --pmc counter files to profiles/traffic_<kernel>_<workload>.json")
     args = ap.parse_args()
 
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.workload, *args.write_traffic[1:])
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
@@ -163,20 +255,25 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     w = wl.WORKLOADS[args.workload]()
-    prec = args.precision or w.precision
+    prec = args.precision
     ctx = mdp.mdp_create(0)
     sides = dd.side_structs(w, w.m_star)
     pts = ap_points_per_step(w)
 
     step_s, report, res = run_steps(ctx, w, prec, sides, args.steps, args.warmup, not args.no_profile)
     value = pts / step_s
-    extra = {}
-    if args.compare and args.compare != prec:
-        cstep, creport, _ = run_steps(ctx, w, args.compare, sides, max(2, args.steps // 2), 1, False)
-        extra["compare"] = {"precision": args.compare, "ms_per_step": round(cstep * 1e3, 4),
-                            "value": pts / cstep, "speedup_of_%s" % prec: round(cstep / step_s, 3)}
-    extra["dd_solve_warm_ms"] = round(warm_ms(ctx, w, prec, sides), 4)
+    results = {prec: res}
+    compare = {}
+    for cp in [c for c in args.compare.split(",") if c and c != prec]:
+        cstep, _, cres = run_steps(ctx, w, cp, sides, max(2, args.steps // 2), 1, False)
+        results[cp] = cres
+        compare[cp] = {"ms_per_step": round(cstep * 1e3, 4), "value": pts / cstep,
+                       "dd_solve_warm_ms": round(warm_ms(ctx, w, cp, sides), 4)}
+    warm = round(warm_ms(ctx, w, prec, sides), 4)
 
     line = {"metric": "AP grid-points/s (batched compact-4 Helmholtz) + DD solve ms, FP32 vs FP64",
             "value": value, "unit": "AP grid-points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -185,18 +282,20 @@ def main():
             "data": "synthetic",
             "config": {"workload": w.notes, "precision": prec, "ap_points_per_step": pts,
                        "subdomains": len(w.subdomains), "m_star": w.m_star,
-                       "interface_ls": "FP64 Cholesky-QR2 on device"}}
+                       "interface_ls": "FP64 on device (semi-normal equations with refinement, Cholesky-QR fallback)"},
+            "dd_solve_cold_ms": round(step_s * 1e3, 4), "dd_solve_warm_ms": warm}
     if report:
-        name, roof = roofline(report)
+        name, roof = roofline(report, args.workload)
         line["roofline"] = roof
         line["kernels"] = {k: {"count": v["count"], "total_ms": round(v["total_ms"], 4)} for k, v in report.items()}
-    line.update(extra)
+    if compare:
+        line["compare"] = compare
     if not args.no_cpu_baseline:
         ores, cb = cpu_baseline(w, pts)
         line["cpu_baseline"] = cb
-        c_gpu = res.c.cpu().numpy()
         c_ref = np.concatenate(ores["c"])
-        line["error_vs_oracle"] = {"c_rel": float(np.abs(c_gpu - c_ref).max() / np.abs(c_ref).max())}
+        line["error_vs_oracle"] = {p: {"c_rel": float(np.abs(r.c.cpu().numpy() - c_ref).max() / np.abs(c_ref).max())}
+                                   for p, r in results.items()}
         line["error_vs_exact"] = {"oracle": ores["info"]["error_max_Mplus"]}
     print(json.dumps(line))
     ctx.close()
