@@ -185,6 +185,13 @@ __device__ inline double recip(double d) {
     return r;
 }
 
+// 1/d from the hardware estimate and one Newton step (the estimate's error is
+// squared: full FP64 accuracy for the pivots of the block factorisation)
+__device__ inline double recip1(double d) {
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -194,143 +201,404 @@ __device__ inline void wave_sync() {
 // pivot used by the elimination: a non-positive (or NaN) one is replaced by 1
 __device__ inline double unit_if_bad(double d) { return d > 0.0 ? d : 1.0; }
 
-// Cholesky factor and inverse of one Hermitian positive definite diagonal
-// block of order nb <= 64: G (lower triangle read, ld ldg) = L L^*, L to Lout
-// (ld ldl) and L^{-1} to Linv (ld ldi), lower triangles written (the caller
-// zeroes the strict upper triangles).  `shift` is added to the diagonal
-// first; orders below 64 are padded with the identity.
-//
-// Unscaled right-looking elimination of [S | I]: step k takes the pivot
-// d_k = S(k,k), Lt(i,k) = S(i,k)/d_k, and for every row i > k updates
-//   S(i,j) -= Lt(i,k) conj(S(j,k))   for k < j <= i   (Schur complement),
-//   X(i,j) -= Lt(i,k) X(k,j)         for j <= k       (X = unit factor^-1).
-// Row i's lower entries j <= i are exactly one of the two at every step, so
-// one array M holds S right of the eliminated columns and X left of them, and
-// the step is the single update M(i,j) -= Lt(i,k) v_j with v_j = conj(S(j,k))
-// for j > k, v_j = X(k,j) for j < k and v_k = d_k + 1 (which turns M(i,k) =
-// S(i,k) into X(i,k) = -Lt(i,k)).  Column k of S is kept in LDS for L; at the
-// end L(i,j) = S(i,j)/sqrt(d_j), L^{-1}(i,j) = X(i,j)/sqrt(d_i).
-// Threads: the 136 4x4 tiles of the lower triangle, one per thread (3
-// wavefronts); each step is one barrier, its update branch-free.  A
-// non-positive pivot sets *info to base + its 1-based index (first failure
-// wins).
-__global__ void __launch_bounds__(192)
-chol64_kernel(const double2* __restrict__ G, int ldg, int nb, double shift, double2* __restrict__ Lout, int ldl,
-              double2* __restrict__ Linv, int ldi, int* info, int base) {
-    __shared__ double2 Ls[64][64];   // Ls[k][i] = S(i,k) at step k (i > k)
-    __shared__ double2 vb[2][64];    // v of the step (double-buffered)
-    __shared__ double piv[64];
-    const int tid = threadIdx.x;
-    const bool act = tid < 136;
-    int ti = 0;
-    const int t = act ? tid : 0;
-    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-    const int tj = t - ti * (ti + 1) / 2;
-    const int r0 = 4 * ti, c0 = 4 * tj;
-    double mr[4][4], mi[4][4];
+// LDS of one diagonal-block factorisation (rows padded to 65 entries)
+struct CholLds {
+    double2 S[64][65];     // Schur complement -> L (row-major, lower part)
+    double2 Z[64][65];     // inverse accumulation -> L^{-1} (row-major, lower part, zero upper part)
+    double2 Ls[16][16];    // sub-block elimination: column k of S at step k (Ls[k][r])
+    double2 Xr[16][16];    // sub-block elimination: row k of X at step k (Xr[k][j])
+    double piv[16];
+};
+
+// C(16x16 tile) accumulation for lane (row lane & 15, columns 4 (lane >> 4) + q):
+// acc += sum_k A(r, k) B(k, c) with A(r,k) = a(r,k), B(k,c) = b(k,c) read through the
+// functors, k = 0..15.
+template <class FA, class FB>
+__device__ inline void tile16_mac(double (&cr)[4], double (&ci)[4], FA a, FB b) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = r0 + a, j = c0 + b;
-            double2 v = make_double2(0.0, 0.0);
-            if (act && j <= i) {
-                if (i < nb) v = G[i + (long)j * ldg];
-                else if (i == j) v = make_double2(1.0, 0.0);
-                if (i == j && i < nb) v.x += shift;
-            }
-            mr[a][b] = v.x;
-            mi[a][b] = v.y;
-        }
-    int bad = 0;
-    for (int kt = 0; kt < 16; ++kt) {
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+        double2 x[4], y[4][4];   // one round of operands loaded before any arithmetic
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-            const int k = 4 * kt + kk, buf = kk & 1;
-            if (act && tj == kt) {   // column k: Lt source, v right of the pivot, the pivot
+            x[kk] = a(k0 + kk);
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int i = r0 + a;
-                    if (i > k) {
-                        Ls[k][i] = make_double2(mr[a][kk], mi[a][kk]);
-                        vb[buf][i] = make_double2(mr[a][kk], -mi[a][kk]);
-                    } else if (i == k) {
-                        piv[k] = mr[a][kk];
-                        vb[buf][k] = make_double2(mr[a][kk] + 1.0, 0.0);
+            for (int q = 0; q < 4; ++q) y[kk][q] = b(k0 + kk, q);
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                cr[q] = fma(x[kk].x, y[kk][q].x, fma(-x[kk].y, y[kk][q].y, cr[q]));
+                ci[q] = fma(x[kk].x, y[kk][q].y, fma(x[kk].y, y[kk][q].x, ci[q]));
+            }
+    }
+}
+
+// Cholesky factor and inverse of one Hermitian positive definite diagonal
+// block of order nb <= 64, by the whole workgroup (256 threads): G (lower
+// triangle read, ld ldg) + shift I = L L^*.  On return (after a barrier) s.Z
+// holds L^{-1} row-major with zero upper triangle and s.S holds L in its lower
+// triangle (orders below 64 padded with the identity); if Lout / Zout are set,
+// L and L^{-1} are also written there (lower triangles, ld ldl / ldz).
+// Returns the 1-based index of the first non-positive pivot (0 if none), the
+// same in every thread.
+//
+// Recursive blocking by 16 columns.  Sub-block s (rows/columns b0..b0+15):
+//  F  one wavefront factors the 16x16 diagonal block D = L_ss L_ss^* and its
+//     inverse by unscaled elimination of [D | I] (step k: pivot d_k, Lt(i,k) =
+//     D(i,k)/d_k, M(i,j) -= Lt(i,k) v_j over one array M holding D right of the
+//     eliminated columns and the unit factor's inverse X left of them, v_j =
+//     conj(D(j,k)) for j > k, X(k,j) for j < k, d_k + 1 for j = k), with
+//     wavefront-level synchronisation only;
+//  P  L(i,s) = S(i,s) L_ss^{-*} for the rows below, and Z(s,j) = L_ss^{-1} W(s,j)
+//     for the columns left of the block, W(s,j) = -sum_{l<s} L(s,l) Z(l,j) being
+//     what Z holds there;
+//  U  S(i,j) -= L(i,s) L(j,s)^* (trailing, lower) and W(i,j) -= L(i,s) Z(s,j)
+//     for the rows below (j up to the block, Z(s,s) = L_ss^{-1}).
+// P and U work on 16x16 tiles spread over the 4 wavefronts (4 entries per lane).
+__device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double shift, CholLds& s,
+                          double2* __restrict__ Lout, int ldl, double2* __restrict__ Zout, int ldz) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;   // tile row, column group (columns 4g..4g+3)
+    for (int e = tid; e < 64 * 64; e += blockDim.x) {
+        const int i = e >> 6, j = e & 63;
+        double2 v = make_double2(0.0, 0.0);
+        if (j <= i) {
+            if (i < nb) v = G[i + (long)j * ldg];
+            else if (i == j) v = make_double2(1.0, 0.0);
+            if (i == j && i < nb) v.x += shift;
+        }
+        s.S[i][j] = v;
+        s.Z[i][j] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    int bad = 0;
+    for (int sb = 0; sb < 4; ++sb) {
+        const int b0 = 16 * sb;
+        // ---- F: 16x16 diagonal block by wavefront 0
+        if (wave == 0) {
+            double mr[4], mi[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = 4 * g + q;
+                const double2 v = (c <= r) ? s.S[b0 + r][b0 + c] : make_double2(0.0, 0.0);
+                mr[q] = v.x;
+                mi[q] = v.y;
+            }
+            for (int k4 = 0; k4 < 4; ++k4) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * k4 + kk;
+                    if (g == k4) {            // column k of the block (all rows; only rows > k are used)
+                        s.Ls[k][r] = make_double2(mr[kk], mi[kk]);
+                        if (r == k) s.piv[k] = mr[kk];
+                    }
+                    // the pivot straight from its lane (row k, column group k4)
+                    const int pl = k + 16 * k4;
+                    const double dk = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mr[kk]), pl),
+                                                       __builtin_amdgcn_readlane(__double2loint(mr[kk]), pl));
+                    if (r == k) {             // row k of X (columns < k are used)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) s.Xr[k][4 * g + q] = make_double2(mr[q], mi[q]);
+                    }
+                    double d = dk;
+                    if (!(d > 0.0)) {
+                        if (!bad) bad = b0 + k + 1;
+                        d = 1.0;
+                    }
+                    const double dinv = recip1(d);
+                    wave_sync();
+                    const double2 cl = s.Ls[k][r];
+                    const bool live = r > k;
+                    const double lr = live ? cl.x * dinv : 0.0, li = live ? cl.y * dinv : 0.0;
+                    // v_j: both candidates loaded, then selected (no divergent branches)
+                    double2 cs[4], xs[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        cs[q] = s.Ls[k][4 * g + q];
+                        xs[q] = s.Xr[k][4 * g + q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = 4 * g + q;
+                        const double vx = (j > k) ? cs[q].x : ((j < k) ? xs[q].x : d + 1.0);
+                        const double vy = (j > k) ? -cs[q].y : ((j < k) ? xs[q].y : 0.0);
+                        mr[q] = fma(-lr, vx, fma(li, vy, mr[q]));
+                        mi[q] = fma(-lr, vy, fma(-li, vx, mi[q]));
                     }
                 }
             }
-            if (act && ti == kt) {   // row k of X left of the pivot
+            // L_ss into S, L_ss^{-1} into Z (lower parts; upper part of the Z block stays zero)
+            const double pr = s.piv[r];
+            const double sdr = sqrt(pr > 0.0 ? pr : 1.0), rdr = recip(sdr);
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int j = c0 + b;
-                    if (j < k) vb[buf][j] = make_double2(mr[kk][b], mi[kk][b]);
+            for (int q = 0; q < 4; ++q) {
+                const int c = 4 * g + q;
+                if (c < r) {
+                    const double pc = s.piv[c];
+                    const double sc = recip(sqrt(pc > 0.0 ? pc : 1.0));
+                    const double2 lv = s.Ls[c][r];
+                    s.S[b0 + r][b0 + c] = make_double2(lv.x * sc, lv.y * sc);
+                    s.Z[b0 + r][b0 + c] = make_double2(mr[q] * rdr, mi[q] * rdr);
+                } else if (c == r) {
+                    s.S[b0 + r][b0 + r] = make_double2(sdr, 0.0);
+                    s.Z[b0 + r][b0 + r] = make_double2(rdr, 0.0);
                 }
             }
-            __syncthreads();
-            double d = piv[k];
-            if (!(d > 0.0)) {   // breakdown: reported, and the step continues with a unit pivot
-                if (!bad) bad = k + 1;
-                d = 1.0;
+        }
+        __syncthreads();
+        // ---- P: panel below (tiles it = sb+1..3) and Z row block (tiles jt = 0..sb-1), into registers
+        const int np = 3 - sb, ntp = np + sb;
+        double pr_[4] = {}, pi_[4] = {};
+        int pt = -1;
+        for (int t = wave; t < ntp; t += 4) pt = t;   // each wavefront owns at most one tile (ntp <= 3)
+        if (pt >= 0) {
+            if (pt < np) {
+                const int i0 = b0 + 16 * (pt + 1);
+                tile16_mac(pr_, pi_, [&](int k) { return s.S[i0 + r][b0 + k]; },
+                           [&](int k, int q) { const double2 z = s.Z[b0 + 4 * g + q][b0 + k];
+                                               return make_double2(z.x, -z.y); });
+            } else {
+                const int j0 = 16 * (pt - np);
+                tile16_mac(pr_, pi_, [&](int k) { return s.Z[b0 + r][b0 + k]; },
+                           [&](int k, int q) { return s.Z[b0 + k][j0 + 4 * g + q]; });
             }
-            const double dinv = recip(d);
-            double lr[4], li[4], vr[4], vi[4];
+        }
+        __syncthreads();
+        if (pt >= 0) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const double2 c = Ls[k][r0 + a];   // rows <= k: not written this step, masked out
-                const bool live = r0 + a > k;
-                lr[a] = live ? c.x * dinv : 0.0;
-                li[a] = live ? c.y * dinv : 0.0;
+            for (int q = 0; q < 4; ++q) {
+                if (pt < np) s.S[b0 + 16 * (pt + 1) + r][b0 + 4 * g + q] = make_double2(pr_[q], pi_[q]);
+                else s.Z[b0 + r][16 * (pt - np) + 4 * g + q] = make_double2(pr_[q], pi_[q]);
             }
+        }
+        __syncthreads();
+        // ---- U: trailing lower tiles (sb < jt <= it) and W tiles (it > sb, jt <= sb)
+        const int ntr = np * (np + 1) / 2, nw = np * (sb + 1);
+        for (int t = wave; t < ntr + nw; t += 4) {
+            double cr[4] = {}, ci[4] = {};
+            if (t < ntr) {
+                int a = 0;
+                while ((a + 1) * (a + 2) / 2 <= t) ++a;
+                const int it = sb + 1 + a, jt = sb + 1 + (t - a * (a + 1) / 2);
+                tile16_mac(cr, ci, [&](int k) { return s.S[16 * it + r][b0 + k]; },
+                           [&](int k, int q) { const double2 l = s.S[16 * jt + 4 * g + q][b0 + k];
+                                               return make_double2(l.x, -l.y); });
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double2& o = s.S[16 * it + r][16 * jt + 4 * g + q];
+                    o.x -= cr[q];
+                    o.y -= ci[q];
+                }
+            } else {
+                const int u = t - ntr, it = sb + 1 + u % np, jt = u / np;
+                tile16_mac(cr, ci, [&](int k) { return s.S[16 * it + r][b0 + k]; },
+                           [&](int k, int q) { return s.Z[b0 + k][16 * jt + 4 * g + q]; });
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double2& o = s.Z[16 * it + r][16 * jt + 4 * g + q];
+                    o.x -= cr[q];
+                    o.y -= ci[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // the first failure (wavefront 0 saw every pivot), the same in every thread
+    __shared__ int bad_s;
+    if (tid == 0) bad_s = bad;
+    __syncthreads();
+    const int first = bad_s;
+    if (Lout || Zout) {
+        for (int e = tid; e < 64 * 64; e += blockDim.x) {
+            const int i = e >> 6, j = e & 63;
+            if (i >= nb || j > i) continue;
+            if (Lout) Lout[i + (long)j * ldl] = s.S[i][j];
+            if (Zout) Zout[i + (long)j * ldz] = s.Z[i][j];
+        }
+    }
+    return first;
+}
+
+// Block step of the blocked Cholesky factorisation and inverse of an order-nc
+// Hermitian positive definite matrix (G, lower triangle, ld nc), diagonal
+// block kb..kb+nbk-1.  Z = L^{-1} is built block row by block row:
+// W(i,j) accumulates -sum_l L(i,l) Z(l,j) over the eliminated blocks l, and
+// Z(k,j) = Z(k,k) W(k,j) once block row k's W is complete.
+// Workgroup roles (256 threads each, every one refactors the diagonal block
+// into LDS first):
+//   block 0:                     L(k,k), Z(k,k) to memory, breakdown to *info;
+//   blocks 1..np (32-row slabs): L(i,k) = G(i,k) Z(k,k)^*;
+//   the rest (32-column slabs j0 < kb): Z(k,j) = Z(k,k) W(k,j).
+// The slab operand is staged in the (no longer needed) S part of the LDS.
+// (one workgroup per CU by its LDS, so all 512 registers of a lane are allowed)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+chol_panel_kernel(const double2* __restrict__ G, int nc, int kb, int nbk, double shift, double2* __restrict__ L,
+                  double2* __restrict__ Z, const double2* __restrict__ W, int* info, int np) {
+    __shared__ CholLds s;
+    const int role = blockIdx.x, tid = threadIdx.x;
+    const long dk = kb + (long)kb * nc;
+    const bool diag = role == 0;
+    const int bad = chol64_lds(G + dk, nc, nbk, shift, s, diag ? L + dk : nullptr, nc, diag ? Z + dk : nullptr, nc);
+    if (diag) {
+        if (tid == 0 && bad && info) atomicCAS(info, 0, kb + bad);
+        return;
+    }
+    const int tr = tid >> 4, tc = tid & 15;   // 16 x 16 threads
+    if (role <= np) {
+        // rows i0..i0+31: S[r][k] = G(i0 + r, kb + k); thread rows 2tr + {0,1}, columns 4tc + {0..3}
+        const int i0 = kb + nbk + 32 * (role - 1);
+        for (int e = tid; e < 32 * 64; e += 256) {
+            const int rr = e >> 6, k = e & 63, i = i0 + rr;
+            s.S[rr][k] = (i < nc && k < nbk) ? G[i + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        double ar[2][4] = {}, ai[2][4] = {};
+        for (int k0 = 0; k0 < 64; k0 += 2) {
+            double2 gv[2][2], zv[2][4];   // L(i,c) = sum_k G(i,k) conj(Z(c,k)); operands of 2 k first
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a) gv[kk][a] = s.S[2 * tr + a][k0 + kk];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) zv[kk][b] = s.Z[4 * tc + b][k0 + kk];
+            }
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const double2 g = gv[kk][a], z = zv[kk][b];
+                        ar[a][b] = fma(g.x, z.x, fma(g.y, z.y, ar[a][b]));
+                        ai[a][b] = fma(g.y, z.x, fma(-g.x, z.y, ai[a][b]));
+                    }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int i = i0 + 2 * tr + a;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const double2 v = vb[buf][c0 + b];
-                vr[b] = v.x;
-                vi[b] = v.y;
+                const int c = 4 * tc + b;
+                if (i < nc && c < nbk) L[i + (long)(kb + c) * nc] = make_double2(ar[a][b], ai[a][b]);
             }
-            // M -= Lt v, as two fused multiply-adds per component straight into the
-            // accumulators (32 independent chains)
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    mr[a][b] = fma(-lr[a], vr[b], mr[a][b]);
-                    mi[a][b] = fma(-lr[a], vi[b], mi[a][b]);
-                }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    mr[a][b] = fma(li[a], vi[b], mr[a][b]);
-                    mi[a][b] = fma(-li[a], vr[b], mi[a][b]);
-                }
         }
+        return;
     }
-    if (!act) return;
+    // columns j0..j0+31 of block row k of Z: S[k][c] = W(kb + k, j0 + c); thread rows 4tr + {0..3},
+    // columns 2tc + {0,1}
+    const int j0 = 32 * (role - 1 - np);
+    for (int e = tid; e < 64 * 32; e += 256) {
+        const int k = e >> 5, c = e & 31;
+        s.S[k][c] = (k < nbk) ? W[kb + k + (long)(j0 + c) * nc] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double zr[4][2] = {}, zi[4][2] = {};
+    for (int k0 = 0; k0 < 64; k0 += 2) {
+        double2 wv[2][2], zv[2][4];   // operands of 2 k first
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) wv[kk][b] = s.S[k0 + kk][2 * tc + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) zv[kk][a] = s.Z[4 * tr + a][k0 + kk];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double2 z = zv[kk][a], w = wv[kk][b];
+                    zr[a][b] = fma(z.x, w.x, fma(-z.y, w.y, zr[a][b]));
+                    zi[a][b] = fma(z.x, w.y, fma(z.y, w.x, zi[a][b]));
+                }
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const int i = r0 + a;
-        if (i >= nb) continue;
-        const double sdi = sqrt(unit_if_bad(piv[i])), rdi = recip(sdi);
+        const int rr = 4 * tr + a;
+        if (rr >= nbk) continue;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int j = c0 + b;
-            if (j > i) continue;
-            double2 l, x;
-            if (j < i) {
-                const double2 sv = Ls[j][i];
-                const double sc = recip(sqrt(unit_if_bad(piv[j])));
-                l = make_double2(sv.x * sc, sv.y * sc);
-                x = make_double2(mr[a][b] * rdi, mi[a][b] * rdi);
-            } else {
-                l = make_double2(sdi, 0.0);
-                x = make_double2(rdi, 0.0);
-            }
-            Lout[i + (long)j * ldl] = l;
-            Linv[i + (long)j * ldi] = x;
+        for (int b = 0; b < 2; ++b) Z[kb + rr + (long)(j0 + 2 * tc + b) * nc] = make_double2(zr[a][b], zi[a][b]);
+    }
+}
+
+// Update after the block step kb..kb+nbk-1 (r0 = kb + nbk): 32 x 32 tiles of
+//   the trailing Schur complement  G(i,j) -= sum_k L(i,k) conj(L(j,k)),  r0 <= j <= i (tile-wise lower),
+//   the inverse accumulation       W(i,j) -= sum_k L(i,k) Z(k,j),        i >= r0, j < r0,
+// k over the block's columns (for j in the block, Z(k,j) is the block's own
+// inverse and W starts from zero).  Both operands staged in LDS; 2 x 2 entries
+// per thread.
+__global__ void __launch_bounds__(256)
+chol_update_kernel(double2* __restrict__ G, int nc, int kb, int nbk, const double2* __restrict__ L,
+                   const double2* __restrict__ Z, double2* __restrict__ W, int ntr) {
+    __shared__ double2 A[64][33];   // A[k][r] = L(i0 + r, kb + k)
+    __shared__ double2 B[64][33];   // B[k][c] = conj(L(j0 + c, kb + k)) or Z(kb + k, j0 + c)
+    const int r0 = kb + nbk, tid = threadIdx.x;
+    int t = blockIdx.x, i0, j0;
+    bool trail;
+    const int ntri = ntr * (ntr + 1) / 2;
+    if (t < ntri) {
+        int a = 0;
+        while ((a + 1) * (a + 2) / 2 <= t) ++a;
+        i0 = r0 + 32 * a;
+        j0 = r0 + 32 * (t - a * (a + 1) / 2);
+        trail = true;
+    } else {
+        t -= ntri;
+        i0 = r0 + 32 * (t % ntr);
+        j0 = 32 * (t / ntr);
+        trail = false;
+    }
+    for (int e = tid; e < 64 * 32; e += 256) {
+        const int k = e >> 5, r = e & 31;
+        const int i = i0 + r, j = j0 + r;
+        const bool kin = k < nbk;
+        A[k][r] = (kin && i < nc) ? L[i + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
+        if (trail) {
+            const double2 v = (kin && j < nc) ? L[j + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
+            B[k][r] = make_double2(v.x, -v.y);
+        } else {
+            B[k][r] = kin ? Z[kb + k + (long)j * nc] : make_double2(0.0, 0.0);
         }
     }
-    if (tid == 0 && bad && info) atomicCAS(info, 0, base + bad);
+    __syncthreads();
+    const int tr = tid >> 4, tc = tid & 15;
+    double cr[2][2] = {}, ci[2][2] = {};
+    for (int k0 = 0; k0 < 64; k0 += 4) {
+        double2 a[4][2], b[4][2];   // one round of operands loaded before any arithmetic
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                a[kk][u] = A[k0 + kk][2 * tr + u];
+                b[kk][u] = B[k0 + kk][2 * tc + u];
+            }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    cr[u][v] = fma(a[kk][u].x, b[kk][v].x, fma(-a[kk][u].y, b[kk][v].y, cr[u][v]));
+                    ci[u][v] = fma(a[kk][u].x, b[kk][v].y, fma(a[kk][u].y, b[kk][v].x, ci[u][v]));
+                }
+    }
+    double2* C = trail ? G : W;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = i0 + 2 * tr + u;
+        if (i >= nc) continue;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int j = j0 + 2 * tc + v;
+            if (j >= nc || (trail && j > i)) continue;
+            double2 c = C[i + (long)j * nc];
+            c.x -= cr[u][v];
+            c.y -= ci[u][v];
+            C[i + (long)j * nc] = c;
+        }
+    }
 }
 
 // max and min Cholesky pivot ratio estimate: diag of L (ld) -> out[0] = max |L_ii|^2, out[1] = min |L_ii|^2
@@ -772,11 +1040,21 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
     }
 }
 
-void launch_chol_block(const double2* G, int ldg, int nb, double shift, double2* L, int ldl, double2* Linv, int ldi,
-                       int* info, int base, hipStream_t st) {
-    if (nb < 1 || nb > 64) throw Error(MDP_ERR_ARG, "Cholesky block order must be 1..64");
-    hipLaunchKernelGGL(chol64_kernel, dim3(1), dim3(192), 0, st, G, ldg, nb, shift, L, ldl, Linv, ldi, info, base);
+void launch_chol_step(double2* G, int nc, int kb, int nbk, double shift, double2* L, double2* Z, double2* W,
+                      int* info, hipStream_t st) {
+    if (nbk < 1 || nbk > 64 || kb < 0 || kb % 64 || kb + nbk > nc) throw Error(MDP_ERR_ARG, "bad Cholesky block");
+    const int rest = nc - kb - nbk;
+    if (rest > 0 && nbk != 64) throw Error(MDP_ERR_ARG, "only the last Cholesky block may be short");
+    const int np = (rest + 31) / 32, nz = kb / 32;
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(1 + np + nz), dim3(256), 0, st, G, nc, kb, nbk, shift, L, Z, W, info,
+                       np);
     MDP_HIP(hipGetLastError());
+    const int nw = (kb + nbk) / 32;   // W column tiles, the diagonal block's included
+    const int tiles = np * (np + 1) / 2 + np * nw;
+    if (rest > 0) {
+        hipLaunchKernelGGL(chol_update_kernel, dim3(tiles), dim3(256), 0, st, G, nc, kb, nbk, L, Z, W, np);
+        MDP_HIP(hipGetLastError());
+    }
 }
 
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,

@@ -46,37 +46,22 @@ void grow(DevBuf& b, size_t bytes) {
     }
 }
 
-// Blocked lower Cholesky G = L L^* (G's lower triangle is overwritten by the
-// trailing updates) and the blocked inverse Linv = L^{-1}.
-void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* T, int* info_dev, int nc, double shift,
-                          Workspace& ws, hipStream_t st) {
+}  // namespace
+
+// Blocked Cholesky G + shift I = L L^* and Linv = L^{-1}, two launches per
+// 64-column block (diagonal factor + panel + inverse block row, then the
+// trailing and inverse updates); W (nc x nc) is the inverse's accumulator.
+// G's lower triangle is overwritten by the trailing updates.
+void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
+                          hipStream_t st) {
     MDP_HIP(hipMemsetAsync(L, 0, sizeof(double2) * (size_t)nc * nc, st));
     MDP_HIP(hipMemsetAsync(Linv, 0, sizeof(double2) * (size_t)nc * nc, st));
+    MDP_HIP(hipMemsetAsync(W, 0, sizeof(double2) * (size_t)nc * nc, st));
     for (int kb = 0; kb < nc; kb += NB) {
         const int nbk = std::min(NB, nc - kb);
-        launch_chol_block(G + kb + (size_t)kb * nc, nc, nbk, shift, L + kb + (size_t)kb * nc, nc,
-                          Linv + kb + (size_t)kb * nc, nc, info_dev, kb, st);
-        const int rest = nc - kb - nbk;
-        if (rest > 0) {
-            // panel: L(below, k) = G(below, k) L_kk^{-*}
-            launch_zgemm('N', 'C', rest, nbk, nbk, ONE, G + (kb + nbk) + (size_t)kb * nc, nc,
-                         Linv + kb + (size_t)kb * nc, nc, ZERO, L + (kb + nbk) + (size_t)kb * nc, nc, ws.zg, st);
-            // trailing update of the lower triangle: G(below, below) -= L(below, k) L(below, k)^*
-            launch_zgemm('N', 'C', rest, rest, nbk, MONE, L + (kb + nbk) + (size_t)kb * nc, nc,
-                         L + (kb + nbk) + (size_t)kb * nc, nc, ONE, G + (kb + nbk) + (size_t)(kb + nbk) * nc, nc,
-                         ws.zg, st, 1);
-        }
-    }
-    // block rows of the inverse: Linv(i, 0:i) = -Linv_ii L(i, 0:i) Linv(0:i, 0:i)
-    for (int ib = NB; ib < nc; ib += NB) {
-        const int nbi = std::min(NB, nc - ib);
-        launch_zgemm('N', 'N', nbi, ib, ib, ONE, L + ib, nc, Linv, nc, ZERO, T, nbi, ws.zg, st);
-        launch_zgemm('N', 'N', nbi, ib, nbi, MONE, Linv + ib + (size_t)ib * nc, nc, T, nbi, ZERO, Linv + ib, nc,
-                     ws.zg, st);
+        launch_chol_step(G, nc, kb, nbk, shift, L, Linv, W, info_dev, st);
     }
 }
-
-}  // namespace
 
 LSResult ls_solve(Workspace& ws, double2* A, const double2* F, int m, int nc, double2* x_out, bool want_cond,
                   hipStream_t st) {
@@ -87,7 +72,7 @@ LSResult ls_solve(Workspace& ws, double2* A, const double2* F, int m, int nc, do
     grow(w.G, nn * sizeof(double2));
     grow(w.L, nn * sizeof(double2));
     for (auto& l : w.Linv) grow(l, nn * sizeof(double2));
-    grow(w.T, (size_t)NB * nc * sizeof(double2));
+    grow(w.T, nn * sizeof(double2));
     grow(w.A0, mn * sizeof(double2));
     grow(w.Aq, mn * sizeof(double2));
     grow(w.vec, (size_t)(6 * nc + 2 * m) * sizeof(double2));
@@ -111,7 +96,7 @@ LSResult ls_solve(Workspace& ws, double2* A, const double2* F, int m, int nc, do
         for (int pass = 0; pass < passes; ++pass) {
             launch_zgemm('C', 'N', nc, nc, m, ONE, cur, m, cur, m, ZERO, w.G.as<double2>(), nc, ws.zg, st, 1);
             cholesky_and_inverse(w.G.as<double2>(), w.L.as<double2>(), w.Linv[pass].as<double2>(), w.T.as<double2>(),
-                                 &fl->info, nc, pass == 0 ? shift : 0.0, ws, st);
+                                 &fl->info, nc, pass == 0 ? shift : 0.0, st);
             // A <- A L^{-*}  (L^{-*} is upper triangular)
             launch_zgemm('N', 'C', m, nc, nc, ONE, cur, m, w.Linv[pass].as<double2>(), nc, ZERO, nxt, m, ws.zg, st, 2);
             std::swap(cur, nxt);
@@ -270,7 +255,7 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
     grow(lw.G, nn * sizeof(double2));
     grow(lw.L, nn * sizeof(double2));
     grow(lw.Linv[0], nn * sizeof(double2));
-    grow(lw.T, (size_t)NB * nc * sizeof(double2));
+    grow(lw.T, nn * sizeof(double2));
     grow(lw.vec, (size_t)(6 * nc + 2 * mtot) * sizeof(double2));
     grow(lw.norms, 2 * (size_t)nc * sizeof(double));
     grow(lw.flags, sizeof(PackedFlags));
@@ -307,7 +292,7 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
                      ws.zg, st);
         launch_scatter_gram(w.Gi.as<double2>(), si, w.dgcol.as<int>() + h.pc_start[i], G, nc, st);
     }
-    cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, ws, st);
+    cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st);
     // c = R^{-1} R^{-*} Qbar^* F, R^{-1} = Linv^*, R^{-*} = Linv
     auto normal_solve = [&](const double2* rhs_rows, double2* out) {
         MDP_HIP(hipMemsetAsync(y, 0, nc * sizeof(double2), st));

@@ -26,6 +26,13 @@ struct PackedHost {
     std::vector<double2> pc_coef;
 };
 
+// Blocked Cholesky G + shift I = L L^* and Linv = L^{-1} of an order-nc Hermitian
+// positive definite G (lower triangle read and overwritten, ld nc, device);
+// L and Linv (nc x nc, ld nc) get zero upper triangles; W is nc x nc scratch;
+// a breakdown sets *info_dev (first failing pivot, 1-based) if it is zero.
+void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
+                          hipStream_t st);
+
 // Corrected semi-normal equations on the packed matrix; F is the stacked
 // right-hand side (device).  Sets *fallback (and returns) when the Cholesky of
 // the Gram matrix breaks down or the refinement does not contract.

@@ -204,8 +204,11 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
 void launch_znorm2(int m, const double2* v, double* out, hipStream_t st);
 void launch_znormalize(int n, double2* v, double* norm_out, hipStream_t st);
 void launch_scale_cols_checked(double2* A, int m, int n, int lda, const double* s, int* flags, hipStream_t st);
-void launch_chol_block(const double2* G, int ldg, int nb, double shift, double2* L, int ldl, double2* Linv, int ldi,
-                       int* info, int base, hipStream_t st);
+// One block step (diagonal block kb..kb+nbk-1, nbk <= 64, kb a multiple of 64)
+// of the blocked Cholesky factorisation G + shift I = L L^* and of Z = L^{-1}
+// (W: nc x nc accumulator of the inverse, zero initially; L, Z zero initially).
+void launch_chol_step(double2* G, int nc, int kb, int nbk, double shift, double2* L, double2* Z, double2* W,
+                      int* info, hipStream_t st);
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
                           const int4* colmap, const double2* coefs, int ncol, double2* Qbar, int ldq, hipStream_t st);
 void launch_known_rhs(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
