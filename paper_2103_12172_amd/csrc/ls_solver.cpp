@@ -305,30 +305,53 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
         launch_packed_ax(d, n_sub, h.max_m, h.max_s, Ap, x, MONE, r, st);
     };
     normal_solve(F, x);
-    const int steps = 2;
-    for (int it = 0; it < steps; ++it) {
-        residual();
-        normal_solve(r, dx);
-        if (it == steps - 1) launch_znorm2(nc, dx, &fl->dx2, st);
-        launch_zaxpy1(nc, dx, x, st);
-    }
-    residual();
-    launch_znorm2((int)mtot, r, &fl->r2, st);
-    launch_znorm2((int)mtot, F, &fl->f2, st);
-    launch_znorm2(nc, x, &fl->x2, st);
+    // refinement steps; the last correction's norm and the solution's norm are
+    // measured so the host can judge convergence (each step contracts the error
+    // by about cond(Qbar)^2 u)
+    auto refine = [&](int steps) {
+        for (int it = 0; it < steps; ++it) {
+            residual();
+            normal_solve(r, dx);
+            if (it == steps - 1) {
+                MDP_HIP(hipMemsetAsync(&fl->x2, 0, 2 * sizeof(double), st));   // x2 and dx2 (adjacent)
+                launch_znorm2(nc, dx, &fl->dx2, st);
+            }
+            launch_zaxpy1(nc, dx, x, st);
+        }
+        launch_znorm2(nc, x, &fl->x2, st);
+    };
     PackedFlags hf{};
-    MDP_HIP(hipMemcpyAsync(&hf, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
-    MDP_HIP(hipStreamSynchronize(st));
-    if (hf.badcol & 2) throw Error(MDP_ERR_NONFINITE, "non-finite entry in the interface matrix");
-    if (hf.badcol & 1) throw Error(MDP_ERR_SINGULAR, "zero column in the interface matrix");
+    auto read_flags = [&]() {
+        MDP_HIP(hipMemcpyAsync(&hf, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
+        MDP_HIP(hipStreamSynchronize(st));
+        if (hf.badcol & 2) throw Error(MDP_ERR_NONFINITE, "non-finite entry in the interface matrix");
+        if (hf.badcol & 1) throw Error(MDP_ERR_SINGULAR, "zero column in the interface matrix");
+    };
+    auto converged = [&]() { return !hf.info && hf.dx2 <= 1e-22 * hf.x2; };
+    refine(2);
+    read_flags();
+    if (!hf.info && !converged()) {
+        // slower contraction (larger cond): continue while the corrections shrink
+        double prev = hf.dx2;
+        for (int round = 0; round < 3 && !converged(); ++round) {
+            refine(2);
+            read_flags();
+            if (!(hf.dx2 < 0.25 * prev)) break;   // not contracting: hand over
+            prev = hf.dx2;
+        }
+    }
     // the last correction must be negligible; otherwise the Gram matrix is too ill-conditioned
-    if (hf.info || !(hf.dx2 <= 1e-22 * hf.x2)) {
+    if (!converged()) {
         if (std::getenv("MDP_VERBOSE"))
             std::fprintf(stderr, "mdp: semi-normal least squares handed over (pivot failure %d, |dx|/|x| %.3e)\n",
                          hf.info, std::sqrt(hf.dx2 / (hf.x2 > 0 ? hf.x2 : 1.0)));
         *fallback = true;
         return res;
     }
+    residual();
+    launch_znorm2((int)mtot, r, &fl->r2, st);
+    launch_znorm2((int)mtot, F, &fl->f2, st);
+    read_flags();
     res.passes = 1;
     res.rel_residual = std::sqrt(hf.r2) / (hf.f2 > 0 ? std::sqrt(hf.f2) : 1.0);
     launch_scale_cols(x, 1, nc, 1, norms, 1, st);

@@ -186,6 +186,55 @@ def test_dd_cross_point(ctx, prec):
     assert e_gpu < 2 * e_ref
 
 
+def test_projector_transmission_full_size(ctx):
+    """Projector of a k = 200 strip at the full size of the transmission workload
+    (n = 1024, M* = 64: 512 columns in one launch), sampled columns vs the oracle."""
+    w = wl.config_transmission(n=1024)
+    sd = w.subdomains[1]
+    P = mdp.mdp_build_projector(ctx, mdp.Subdomain(sd.x0, sd.y0, sd.lx, sd.ly, sd.k, sd.n), w.m_star, "c128")
+    cols = np.array([0, 63, 64, 200, 300, 511])
+    g, Qref = _q_oracle(w, 1, w.m_star, cols=cols, kind="separable")
+    _check_gamma(P, g)
+    Q = P.q_tensor().cpu().numpy()[:, cols]
+    colerr = np.linalg.norm(Q - Qref, axis=0) / np.linalg.norm(Qref, axis=0)
+    print("projector transmission n=1024 k=200: max column rel err %.3e" % colerr.max())
+    assert colerr.max() < 1e-10
+
+
+def test_dd_transmission_reduced_matches_oracle(ctx):
+    """Four strips with a 4x wavenumber jump at a size the oracle finishes in
+    seconds (n = 256, k = 10 | 40, M* = 32)."""
+    w = wl.config_transmission(n=256, ks=(10.0, 40.0, 10.0, 40.0), m_star=32)
+    cerr, uerr, cond, e_gpu, e_ref = _dd_compare(ctx, w, "c128")
+    tol = 1e-10 * max(1.0, cond / 100.0)
+    assert cerr < tol and uerr < tol
+    assert abs(e_gpu - e_ref) <= 1e-3 * e_ref
+
+
+def test_dd_transmission_full_size_fourth_order(ctx):
+    """The transmission workload (k = 20 | 200, M* = 64) at n = 512 and at its full
+    size n = 1024: the error vs the exact piecewise plane wave on M+ falls by ~16
+    per halving (4th order) and the interface residual stays small."""
+    errs = []
+    for n in (512, 1024):
+        w = wl.config_transmission(n=n)
+        res = dd.dd_solve(ctx, w, "c128")
+        torch.cuda.synchronize()
+        u = res.u.cpu().numpy()
+        err = 0.0
+        for i, sd in enumerate(w.subdomains):
+            g = ogrid.APGrid(sd.x0, sd.y0, sd.lx, sd.ly, sd.n)
+            ui = u[res.offsets[i]:res.offsets[i + 1]].reshape(sd.n + 1, sd.n + 1)
+            X, Y = np.meshgrid(g.xs, g.ys, indexing="ij")
+            err = max(err, float(np.abs(ui - w.exact(X, Y))[g.Mplus].max()))
+        print("transmission n=%d: error vs exact %.3e, cond %.3e, residual %.3e" % (n, err, res.cond, res.rel_residual))
+        assert res.rel_residual < 1e-5
+        errs.append(err)
+        mdp.mdp_cache_clear(ctx)
+    assert 12.0 < errs[0] / errs[1] < 20.0
+    assert errs[1] < 2e-3
+
+
 def test_interface_least_squares_on_gpu_projectors(ctx):
     """The device assembly + least squares against the oracle's elimination and
     Householder QR applied to the same (GPU-built) Q matrices."""
