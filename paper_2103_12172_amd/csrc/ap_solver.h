@@ -31,7 +31,7 @@ struct LSWork {
 
 // Packed interface matrix buffers (grow-only).
 struct PackedWork {
-    DevBuf dQ, dm, ds, doff, droff, dsub, dp, dgcol, dstart, dcols, dcoef, Ap, Gi;
+    DevBuf dQ, dm, ds, doff, droff, dsub, dp, dgcol, dstart, dcols, dcoef, Ap, Gi, dzb;
 };
 
 // Interface assembly and reconstruction buffers (grow-only).

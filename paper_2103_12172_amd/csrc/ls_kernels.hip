@@ -24,12 +24,26 @@ constexpr int ZBK = 16;
 // tri: 0 = full; 1 = only tiles touching the lower triangle of C are computed
 // (C Hermitian, lower part used); 2 = op(B) is upper triangular, so column tile
 // n0 only needs k < n0 + 64.
+// With zb set, blockIdx.z selects a batch entry whose A (= B), sizes, K chunk and
+// split-K partial area replace the scalar arguments (Gram products A^* A).
 template <int ZBM>
 __global__ void __launch_bounds__(256)
 zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ A, int lda,
              const double2* __restrict__ B, int ldb, double2* __restrict__ C, int ldc, double2 alpha, double2 beta,
-             int kchunk, double2* __restrict__ P, long pstride, int mtiles, int tri) {
+             int kchunk, double2* __restrict__ P, long pstride, int mtiles, int tri, const ZBatch* __restrict__ zb) {
     constexpr int ZBN = ZBM;
+    if (zb) {
+        const ZBatch e = zb[blockIdx.z];
+        A = B = e.A;
+        M = N = e.n;
+        K = e.k;
+        lda = ldb = e.k;
+        kchunk = e.kchunk;
+        P += e.poff;
+        pstride = (long)e.n * e.n;
+        mtiles = (e.n + ZBM - 1) / ZBM;
+        if ((int)blockIdx.x >= mtiles * mtiles) return;
+    }
     constexpr int WT = ZBM / 2;          // wave tile (2 x 2 waves)
     constexpr int TT = WT / 16;          // 16x16 MFMA blocks per wave side
     constexpr int NL = ZBM * ZBK / 256;  // complex elements per thread per tile
@@ -872,6 +886,33 @@ __global__ void __launch_bounds__(256) packed_ax_kernel(PackedDesc d, const doub
     atomicAdd(&o[1], alpha.x * si + alpha.y * sr);
 }
 
+// G(gcol_b(p1), gcol_b(p2)) += sum over the K splits of Gi_b(p1, p2), p1 >= p2, for
+// every batch entry b (blockIdx.y): the batched Gram products reduced and
+// scattered into the lower triangle of G in one pass.  An entry of G receives at
+// most two contributions (a column block belongs to at most two subdomains) and
+// two-term sums do not depend on their order, so the atomics are deterministic.
+__global__ void gram_scatter_kernel(const ZBatch* __restrict__ zb, const double2* __restrict__ P, int nsplit,
+                                    const int* __restrict__ gcol_all, double2* G, int ldg) {
+    const ZBatch e = zb[blockIdx.y];
+    const int n = e.n;
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= (long)n * n) return;
+    const int p1 = (int)(t % n), p2 = (int)(t / n);
+    if (p1 < p2) return;
+    const double2* part = P + e.poff + t;
+    const long ps = (long)n * n;
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < nsplit; ++k) {
+        const double2 v = part[k * ps];
+        sr += v.x;
+        si += v.y;
+    }
+    const int* gcol = gcol_all + e.gcol_off;
+    double* o = reinterpret_cast<double*>(G + gcol[p1] + (long)gcol[p2] * ldg);
+    atomicAdd(&o[0], sr);
+    atomicAdd(&o[1], si);
+}
+
 // G(gcol(p1), gcol(p2)) += Gi(p1, p2) for the packed columns of one subdomain
 __global__ void scatter_gram_kernel(const double2* __restrict__ Gi, int s, const int* __restrict__ gcol, double2* G,
                                     int ldg) {
@@ -1028,10 +1069,10 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
     }
     if (tile == 64)
         hipLaunchKernelGGL(zgemm_kernel<64>, dim3(tiles, nsplit), dim3(256), 0, st, oa, ob, m, n, k, A, lda, B, ldb,
-                           C, ldc, alpha, beta, kchunk, part, pstride, mt, tri);
+                           C, ldc, alpha, beta, kchunk, part, pstride, mt, tri, nullptr);
     else
         hipLaunchKernelGGL(zgemm_kernel<32>, dim3(tiles, nsplit), dim3(256), 0, st, oa, ob, m, n, k, A, lda, B, ldb,
-                           C, ldc, alpha, beta, kchunk, part, pstride, mt, tri);
+                           C, ldc, alpha, beta, kchunk, part, pstride, mt, tri, nullptr);
     MDP_HIP(hipGetLastError());
     if (nsplit > 1) {
         hipLaunchKernelGGL(zgemm_reduce_kernel, dim3((m + 255) / 256, n), dim3(256), 0, st, m, n, nsplit, part,
@@ -1139,6 +1180,22 @@ void launch_packed_ax(const PackedDevice& d, int n_sub, int max_m, int max_s, co
     PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
     dim3 grid((max_m + 255) / 256, (max_s + 31) / 32, n_sub);
     hipLaunchKernelGGL(packed_ax_kernel, grid, dim3(256), 0, st, pd, Ap, x, d.pc_start, alpha, (double*)r);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int nsplit, double2* P, const int* gcol,
+                         double2* G, int ldg, hipStream_t st) {
+    if (nb <= 0) return;
+    const int tile = 32;
+    const int mt = (max_n + tile - 1) / tile;
+    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+    hipLaunchKernelGGL(zgemm_kernel<32>, dim3(mt * mt, nsplit, nb), dim3(256), 0, st, 1, 0, 0, 0, 0,
+                       (const double2*)nullptr, 0, (const double2*)nullptr, 0, (double2*)nullptr, 0, one, zero, 0, P,
+                       0L, 0, 1, zb_dev);
+    MDP_HIP(hipGetLastError());
+    (void)max_k;
+    hipLaunchKernelGGL(gram_scatter_kernel, dim3((unsigned)(((long)max_n * max_n + 255) / 256), nb), dim3(256), 0, st,
+                       zb_dev, P, nsplit, gcol, G, ldg);
     MDP_HIP(hipGetLastError());
 }
 

@@ -286,11 +286,26 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
     launch_packed_scale(d, npc, h.max_m, Ap, norms, st);
     // Gram matrix
     MDP_HIP(hipMemsetAsync(G, 0, nn * sizeof(double2), st));
-    for (int i = 0; i < n_sub; ++i) {
-        const int si = h.s[i], mi = h.m[i];
-        launch_zgemm('C', 'N', si, si, mi, ONE, Ap + h.off[i], mi, Ap + h.off[i], mi, ZERO, w.Gi.as<double2>(), si,
-                     ws.zg, st);
-        launch_scatter_gram(w.Gi.as<double2>(), si, w.dgcol.as<int>() + h.pc_start[i], G, nc, st);
+    std::vector<ZBatch> zb(n_sub);   // descriptors; alive until the stream is synchronised below
+    {
+        // all subdomains' A_i^* A_i in one split-K launch, reduced and scattered in a second
+        int max_m = 0, tiles = 0;
+        for (int i = 0; i < n_sub; ++i) {
+            max_m = std::max(max_m, h.m[i]);
+            tiles += ((h.s[i] + 31) / 32) * ((h.s[i] + 31) / 32);
+        }
+        int nsplit = std::max(1, std::min(std::min(2048 / std::max(tiles, 1), std::max(1, max_m / 128)), 64));
+        long poff = 0;
+        for (int i = 0; i < n_sub; ++i) {
+            int kchunk = (h.m[i] + nsplit - 1) / nsplit;
+            kchunk = std::max(16, (kchunk + 15) / 16 * 16);
+            zb[i] = ZBatch{Ap + h.off[i], h.s[i], h.m[i], kchunk, h.pc_start[i], poff};
+            poff += (long)nsplit * h.s[i] * h.s[i];
+        }
+        upload_async(w.dzb, zb, st);
+        grow(ws.zg, (size_t)std::max(poff, 1L) * sizeof(double2));
+        launch_gram_batched(w.dzb.as<ZBatch>(), n_sub, h.max_s, max_m, nsplit, ws.zg.as<double2>(),
+                            w.dgcol.as<int>(), G, nc, st);
     }
     cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st);
     // c = R^{-1} R^{-*} Qbar^* F, R^{-1} = Linv^*, R^{-*} = Linv

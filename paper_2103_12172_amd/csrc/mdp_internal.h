@@ -241,6 +241,18 @@ void launch_packed_ahx(const PackedDevice& d, int total_pc, const double2* Ap, c
 void launch_packed_ax(const PackedDevice& d, int n_sub, int max_m, int max_s, const double2* Ap, const double2* x,
                       double2 alpha, double2* r, hipStream_t st);
 void launch_scatter_gram(const double2* Gi, int s, const int* gcol, double2* G, int ldg, hipStream_t st);
+// One batch entry of the Gram products A_b^* A_b (A_b: k x n, column-major, ld k):
+// its split-K partials start at P + poff, its column map at gcol + gcol_off.
+struct ZBatch {
+    const double2* A;
+    int n, k, kchunk, gcol_off;
+    long poff;
+};
+// G(lower) += A_b^* A_b scattered through the column maps, all batch entries in
+// two launches (split-K products, then reduction + scatter); P holds
+// nsplit * sum_b n_b^2 partial entries; G must hold the other contributions or zero.
+void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int nsplit, double2* P, const int* gcol,
+                         double2* G, int ldg, hipStream_t st);
 void launch_zaxpy1(int n, const double2* x, double2* y, hipStream_t st);
 void launch_diag_range(const double2* L, int n, int ld, double* out, hipStream_t st);
 
