@@ -208,6 +208,12 @@ int mdp_cache_clear(mdp_ctx* ctx);
  * Errors: MDP_ERR_ARG. */
 int mdp_profile_enable(mdp_ctx* ctx, int enable);
 
+/* Restrict the per-launch profiling to the kernel classes named in `classes`
+ * (comma-separated, e.g. "chol_panel,ap_fused_f64,interface_ls"); NULL or ""
+ * records every class again.  Fewer records mean fewer event pairs on the
+ * stream while the profiled steps are timed.  Errors: MDP_ERR_ARG. */
+int mdp_profile_select(mdp_ctx* ctx, const char* classes);
+
 /* JSON summary of the records since the last enable, one entry per kernel
  * class: {"class": {"count": c, "total_ms": t, "flops": f, "bytes": b}, ...},
  * written to buf (host, NUL-terminated, at most buflen bytes).  Synchronises

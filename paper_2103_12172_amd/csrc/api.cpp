@@ -550,9 +550,10 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             // the whole least-squares solve as one profiled span (it synchronises internally)
             Profiler& pr = ctx->ws.prof;
             hipEvent_t a = nullptr, b = nullptr;
-            if (pr.on) { a = pr.get(); b = pr.get(); MDP_HIP(hipEventRecord(a, st)); }
-            double gram_flops = 0.0;
-            for (int i = 0; i < n_sub; ++i) gram_flops += 8.0 * (double)qld[i] * ph.s[i] * ph.s[i];
+            const bool span = pr.wants("interface_ls");
+            if (span) { a = pr.get(); b = pr.get(); MDP_HIP(hipEventRecord(a, st)); }
+            // algorithmic work of the least squares: a Householder QR of the m x ncol matrix
+            const double qr_flops = 8.0 * ((double)m * ncol * ncol - (double)ncol * ncol * ncol / 3.0);
             bool fallback = false;
             r = ls_solve_packed(ctx->ws, ph, F.as<double2>(), x.as<double2>(), cond_estimate_out != nullptr, st,
                                 &fallback);
@@ -563,12 +564,11 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
                                      d_cmap.as<int4>(), d_coef.as<double2>(), ncol, Qbar.as<double2>(), m, st);
                 r = ls_solve(ctx->ws, Qbar.as<double2>(), F.as<double2>(), m, ncol, x.as<double2>(),
                              cond_estimate_out != nullptr, st);
-                gram_flops = 8.0 * (double)m * ncol * ncol * r.passes;
                 MDP_HIP(hipStreamSynchronize(st));
             }
-            if (pr.on) {
+            if (span) {
                 MDP_HIP(hipEventRecord(b, st));
-                pr.recs.push_back({"interface_ls", a, b, gram_flops, (double)m * ncol * 16.0});
+                pr.recs.push_back({"interface_ls", a, b, qr_flops, (double)m * ncol * 16.0});
             }
         }
         // expand the unknowns to the full coefficient vectors (column order of Q)
@@ -735,6 +735,25 @@ int mdp_profile_enable(mdp_ctx* ctx, int enable) {
         MDP_HIP(hipDeviceSynchronize());
         ctx->ws.prof.reset();
         ctx->ws.prof.on = enable != 0;
+        return MDP_OK;
+    });
+}
+
+int mdp_profile_select(mdp_ctx* ctx, const char* classes) {
+    if (!ctx) return MDP_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        ctx->ws.prof.only.clear();
+        if (classes) {
+            std::string all(classes), cur;
+            for (char ch : all + ",") {
+                if (ch == ',') {
+                    if (!cur.empty()) ctx->ws.prof.only.push_back(cur);
+                    cur.clear();
+                } else if (ch != ' ') {
+                    cur += ch;
+                }
+            }
+        }
         return MDP_OK;
     });
 }

@@ -1081,8 +1081,8 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
     }
 }
 
-void launch_chol_step(double2* G, int nc, int kb, int nbk, double shift, double2* L, double2* Z, double2* W,
-                      int* info, hipStream_t st) {
+void launch_chol_panel(const double2* G, int nc, int kb, int nbk, double shift, double2* L, double2* Z,
+                       const double2* W, int* info, hipStream_t st) {
     if (nbk < 1 || nbk > 64 || kb < 0 || kb % 64 || kb + nbk > nc) throw Error(MDP_ERR_ARG, "bad Cholesky block");
     const int rest = nc - kb - nbk;
     if (rest > 0 && nbk != 64) throw Error(MDP_ERR_ARG, "only the last Cholesky block may be short");
@@ -1090,12 +1090,17 @@ void launch_chol_step(double2* G, int nc, int kb, int nbk, double shift, double2
     hipLaunchKernelGGL(chol_panel_kernel, dim3(1 + np + nz), dim3(256), 0, st, G, nc, kb, nbk, shift, L, Z, W, info,
                        np);
     MDP_HIP(hipGetLastError());
+}
+
+void launch_chol_update(double2* G, int nc, int kb, int nbk, const double2* L, const double2* Z, double2* W,
+                        hipStream_t st) {
+    const int rest = nc - kb - nbk;
+    if (rest <= 0) return;
+    const int np = (rest + 31) / 32;
     const int nw = (kb + nbk) / 32;   // W column tiles, the diagonal block's included
     const int tiles = np * (np + 1) / 2 + np * nw;
-    if (rest > 0) {
-        hipLaunchKernelGGL(chol_update_kernel, dim3(tiles), dim3(256), 0, st, G, nc, kb, nbk, L, Z, W, np);
-        MDP_HIP(hipGetLastError());
-    }
+    hipLaunchKernelGGL(chol_update_kernel, dim3(tiles), dim3(256), 0, st, G, nc, kb, nbk, L, Z, W, np);
+    MDP_HIP(hipGetLastError());
 }
 
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,

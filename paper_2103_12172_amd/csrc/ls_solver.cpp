@@ -53,13 +53,25 @@ void grow(DevBuf& b, size_t bytes) {
 // trailing and inverse updates); W (nc x nc) is the inverse's accumulator.
 // G's lower triangle is overwritten by the trailing updates.
 void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
-                          hipStream_t st) {
+                          hipStream_t st, Profiler* pr) {
     MDP_HIP(hipMemsetAsync(L, 0, sizeof(double2) * (size_t)nc * nc, st));
     MDP_HIP(hipMemsetAsync(Linv, 0, sizeof(double2) * (size_t)nc * nc, st));
     MDP_HIP(hipMemsetAsync(W, 0, sizeof(double2) * (size_t)nc * nc, st));
+    Profiler none;
+    Profiler& p = pr ? *pr : none;
     for (int kb = 0; kb < nc; kb += NB) {
         const int nbk = std::min(NB, nc - kb);
-        launch_chol_step(G, nc, kb, nbk, shift, L, Linv, W, info_dev, st);
+        const double b = nbk, rest = nc - kb - nbk;
+        // algorithmic flops (complex = 4 real multiply-adds): Cholesky and triangular inverse of
+        // the diagonal block (4/3 b^3 each), the panel of L (8 rest b^2), the block row of Z (8 kb b^2);
+        // then the trailing update (4 rest^2 b, lower half) and the inverse accumulation (8 rest (kb+b) b)
+        p.run("chol_panel", st, 8.0 / 3.0 * b * b * b + 8.0 * rest * b * b + 8.0 * kb * b * b,
+              16.0 * (b * b + rest * b + 2.0 * kb * b),
+              [&] { launch_chol_panel(G, nc, kb, nbk, shift, L, Linv, W, info_dev, st); });
+        if (rest > 0)
+            p.run("chol_update", st, 4.0 * rest * rest * b + 8.0 * rest * (kb + b) * b,
+                  16.0 * (rest * rest + 2.0 * rest * b + 2.0 * rest * (kb + b)),
+                  [&] { launch_chol_update(G, nc, kb, nbk, L, Linv, W, st); });
     }
 }
 
@@ -96,7 +108,7 @@ LSResult ls_solve(Workspace& ws, double2* A, const double2* F, int m, int nc, do
         for (int pass = 0; pass < passes; ++pass) {
             launch_zgemm('C', 'N', nc, nc, m, ONE, cur, m, cur, m, ZERO, w.G.as<double2>(), nc, ws.zg, st, 1);
             cholesky_and_inverse(w.G.as<double2>(), w.L.as<double2>(), w.Linv[pass].as<double2>(), w.T.as<double2>(),
-                                 &fl->info, nc, pass == 0 ? shift : 0.0, st);
+                                 &fl->info, nc, pass == 0 ? shift : 0.0, st, &ws.prof);
             // A <- A L^{-*}  (L^{-*} is upper triangular)
             launch_zgemm('N', 'C', m, nc, nc, ONE, cur, m, w.Linv[pass].as<double2>(), nc, ZERO, nxt, m, ws.zg, st, 2);
             std::swap(cur, nxt);
@@ -304,10 +316,17 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
         }
         upload_async(w.dzb, zb, st);
         grow(ws.zg, (size_t)std::max(poff, 1L) * sizeof(double2));
-        launch_gram_batched(w.dzb.as<ZBatch>(), n_sub, h.max_s, max_m, nsplit, ws.zg.as<double2>(),
-                            w.dgcol.as<int>(), G, nc, st);
+        double gram_flops = 0.0, gram_bytes = 0.0;
+        for (int i = 0; i < n_sub; ++i) {
+            gram_flops += 4.0 * h.m[i] * (double)h.s[i] * (h.s[i] + 1);   // lower half of A_i^* A_i
+            gram_bytes += 16.0 * h.m[i] * (double)h.s[i];
+        }
+        ws.prof.run("gram", st, gram_flops, gram_bytes, [&] {
+            launch_gram_batched(w.dzb.as<ZBatch>(), n_sub, h.max_s, max_m, nsplit, ws.zg.as<double2>(),
+                                w.dgcol.as<int>(), G, nc, st);
+        });
     }
-    cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st);
+    cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof);
     // c = R^{-1} R^{-*} Qbar^* F, R^{-1} = Linv^*, R^{-*} = Linv
     auto normal_solve = [&](const double2* rhs_rows, double2* out) {
         MDP_HIP(hipMemsetAsync(y, 0, nc * sizeof(double2), st));

@@ -30,8 +30,9 @@ struct PackedHost {
 // positive definite G (lower triangle read and overwritten, ld nc, device);
 // L and Linv (nc x nc, ld nc) get zero upper triangles; W is nc x nc scratch;
 // a breakdown sets *info_dev (first failing pivot, 1-based) if it is zero.
+// Per-launch timing goes to *pr when it is set and enabled.
 void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
-                          hipStream_t st);
+                          hipStream_t st, Profiler* pr = nullptr);
 
 // Corrected semi-normal equations on the packed matrix; F is the stacked
 // right-hand side (device).  Sets *fallback (and returns) when the Cholesky of

@@ -72,8 +72,16 @@ struct Profiler {
         double flops, bytes;
     };
     bool on = false;
+    std::vector<std::string> only;   // classes to record (all when empty)
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
+    bool wants(const char* name) const {
+        if (!on) return false;
+        if (only.empty()) return true;
+        for (const auto& o : only)
+            if (o == name) return true;
+        return false;
+    }
     hipEvent_t get() {
         if (!pool.empty()) {
             hipEvent_t e = pool.back();
@@ -86,7 +94,7 @@ struct Profiler {
     }
     template <class F>
     void run(const char* name, hipStream_t st, double flops, double bytes, F&& f) {
-        if (!on) { f(); return; }
+        if (!wants(name)) { f(); return; }
         hipEvent_t a = get(), b = get();
         MDP_HIP(hipEventRecord(a, st));
         f();
@@ -206,9 +214,13 @@ void launch_znormalize(int n, double2* v, double* norm_out, hipStream_t st);
 void launch_scale_cols_checked(double2* A, int m, int n, int lda, const double* s, int* flags, hipStream_t st);
 // One block step (diagonal block kb..kb+nbk-1, nbk <= 64, kb a multiple of 64)
 // of the blocked Cholesky factorisation G + shift I = L L^* and of Z = L^{-1}
-// (W: nc x nc accumulator of the inverse, zero initially; L, Z zero initially).
-void launch_chol_step(double2* G, int nc, int kb, int nbk, double shift, double2* L, double2* Z, double2* W,
-                      int* info, hipStream_t st);
+// (W: nc x nc accumulator of the inverse, zero initially; L, Z zero initially):
+// the diagonal factor, the panel of L and the block row of Z, then the
+// trailing Schur update and the inverse accumulation.
+void launch_chol_panel(const double2* G, int nc, int kb, int nbk, double shift, double2* L, double2* Z,
+                       const double2* W, int* info, hipStream_t st);
+void launch_chol_update(double2* G, int nc, int kb, int nbk, const double2* L, const double2* Z, double2* W,
+                        hipStream_t st);
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
                           const int4* colmap, const double2* coefs, int ncol, double2* Qbar, int ldq, hipStream_t st);
 void launch_known_rhs(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,

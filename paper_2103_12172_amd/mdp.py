@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "MDP_OK", -1: "MDP_ERR_ARG", -2: "MDP_ERR_HIP", -3: "MDP_ERR_
 EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector", "mdp_projector_info",
             "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
             "mdp_cheb_coeffs", "mdp_version", "mdp_cache_clear", "mdp_profile_enable", "mdp_profile_report",
-            "mdp_set_projector_path"]
+            "mdp_set_projector_path", "mdp_profile_select"]
 MDP_PATH_AUTO, MDP_PATH_DENSE = 0, 1
 PROJECTOR_PATHS = {"auto": MDP_PATH_AUTO, "dense": MDP_PATH_DENSE}
 
@@ -86,6 +86,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mdp_cheb_points.restype = ip
     lib.mdp_cheb_coeffs.argtypes = [ip, ctypes.POINTER(C128), ctypes.POINTER(C128)]
     lib.mdp_cheb_coeffs.restype = ip
+    lib.mdp_profile_select.argtypes = [vp, ctypes.c_char_p]
+    lib.mdp_profile_select.restype = ip
     lib.mdp_set_projector_path.argtypes = [vp, ip]
     lib.mdp_set_projector_path.restype = ip
     lib.mdp_cache_clear.argtypes = [vp]
@@ -270,6 +272,13 @@ def mdp_set_projector_path(ctx: Context, path):
 
 def mdp_profile_enable(ctx: Context, enable: bool = True):
     ctx.check(ctx.lib.mdp_profile_enable(ctx.handle, 1 if enable else 0))
+
+
+def mdp_profile_select(ctx: Context, classes=None):
+    """Record only these kernel classes (list or comma-separated string; None = all)."""
+    if classes is not None and not isinstance(classes, str):
+        classes = ",".join(classes)
+    ctx.check(ctx.lib.mdp_profile_select(ctx.handle, classes.encode() if classes else None))
 
 
 def mdp_profile_report(ctx: Context) -> dict:
