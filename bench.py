@@ -166,7 +166,7 @@ def roofline(report: dict, workload: str):
 
 
 def run_steps(ctx, w, prec, sides, steps, warmup, profile):
-    """Warm-up steps (the first profiled in full to find the dominant kernel class),
+    """Warm-up steps (the last profiled in full to find the dominant kernel class),
     then the timed steps with HIP events around the dominant class, the fused AP
     sweep and the interface span only."""
     import torch
@@ -174,13 +174,15 @@ def run_steps(ctx, w, prec, sides, steps, warmup, profile):
     import gc
     last = None
     selected = None
-    for it in range(max(warmup, 1 if profile else 0)):
-        if profile and it == 0:
+    nwarm = max(warmup, 1 if profile else 0)
+    for it in range(nwarm):
+        # the last warm-up step is profiled (the first one also pays one-time kernel loading)
+        if profile and it == nwarm - 1:
             mdp.mdp_profile_select(ctx, None)
             mdp.mdp_profile_enable(ctx, True)
         mdp.mdp_cache_clear(ctx)
         last = dd.dd_solve(ctx, w, prec, sides=sides, want_cond=False)
-        if profile and it == 0:
+        if profile and it == nwarm - 1:
             full = mdp.mdp_profile_report(ctx)
             mdp.mdp_profile_enable(ctx, False)
             dom = max((k for k in full if k != "interface_ls"), key=lambda k: full[k]["total_ms"])

@@ -156,8 +156,10 @@ void mdp_projector_release(mdp_projector* P);
  * in the column order of Q) receives every coefficient, known and solved.
  * rel_residual_out (host, may be NULL) = ||Qbar c - Fbar|| / ||Fbar||;
  * cond_estimate_out (host, may be NULL) estimates the 2-norm condition number
- * of the column-equilibrated Qbar.  The call synchronises `stream` because it
- * returns host scalars.
+ * of the column-equilibrated Qbar.  The call waits for the least-squares
+ * solve on `stream` (it returns host scalars); c_out is then written by work
+ * queued on `stream`, so readers of c_out order themselves after the call on
+ * `stream` (as mdp_reconstruct on the same stream does) or synchronise it.
  * Errors: MDP_ERR_ARG (inconsistent topology, mismatched interface segments,
  * alpha = beta = 0, M* or rectangle different from the projectors', null d),
  * MDP_ERR_NONFINITE, MDP_ERR_SINGULAR (the factor of Qbar broke down), MDP_ERR_OOM, MDP_ERR_HIP. */
@@ -170,8 +172,10 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs,
  * potential_solution_homo).  c (device) holds 8M* coefficients per subdomain
  * as written by mdp_solve_interface; u_out (device, caller-owned) receives
  * subdomain i's grid function at offset sum_{l<i} (n_l+1)^2 (complex); it is
- * the solution on N+ and the difference potential elsewhere.  Subdomains
- * sharing a projector are solved in one batch.
+ * the solution on N+, the difference potential at the other nodes of the grid
+ * rows m_lo-1..m_hi+1 that hold N+ (the auxiliary solve stops at those rows:
+ * its right-hand side vanishes outside them), and zero on the remaining rows.
+ * Subdomains sharing a projector are solved in one batch.
  * Errors: MDP_ERR_ARG, MDP_ERR_OOM, MDP_ERR_HIP. */
 int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P,
                     const mdp_c128* c, void* stream, mdp_c128* u_out);

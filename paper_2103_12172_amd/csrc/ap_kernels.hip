@@ -2,11 +2,12 @@
 // projector / reconstruction steps.
 //
 // Data layout in HBM (one batch of R right-hand sides, n even, p = n/2):
-//   folded rows  buf[((b*planes + pl)*(n+1) + m)*W + c]
-//     b = right-hand side, pl = 0 (real) / 1 (imaginary) plane, m = 0..n the
-//     x index, c the folded column (block 1: e_q or odd modes, block 2: o_q or
-//     even modes, see Fold).  Columns are contiguous, so a wavefront walking m
-//     for 64 consecutive columns reads 64 consecutive elements per step.
+//   folded rows  buf[((b*planes + pl)*nr + m - r0)*W + c]
+//     b = right-hand side, pl = 0 (real) / 1 (imaginary) plane, m = r0..r0+nr-1
+//     the x index (a band of rows, all n+1 of them for a full solve), c the
+//     folded column (block 1: e_q or odd modes, block 2: o_q or even modes, see
+//     Fold).  Columns are contiguous, so a wavefront walking m for 64
+//     consecutive columns reads 64 consecutive elements per step.
 //   grids        complex interleaved FP64, (n+1)^2 per function, index m*(n+1)+q.
 #include <hip/hip_complex.h>
 
@@ -28,7 +29,8 @@ struct SrcEval {
     StencilCoef sc;
 
     __device__ inline C64 wgrid(int b, int m, int q) const {   // density / grid value (complex)
-        const double* g = d.grid + 2 * ((long)b * d.grid_stride + (long)m * (n + 1) + q);
+        const long base = d.goff ? d.goff[b] : (long)b * d.grid_stride;
+        const double* g = d.grid + 2 * (base + (long)m * (n + 1) + q);
         return {g[0], g[1]};
     }
     __device__ inline double wE(int b, int m, int q) const {   // density of column col0+b (real)
@@ -65,10 +67,10 @@ struct SrcEval {
 //                 block 2 col c = P1+q-1 (q < p):   o_q = g_q - g_{n-q}
 template <class T>
 __global__ void __launch_bounds__(256)
-fold_rhs_kernel(SrcEval ev, Fold f, int planes, T* __restrict__ out) {
+fold_rhs_kernel(SrcEval ev, Fold f, int planes, Band bd, T* __restrict__ out) {
     const int n = f.n, p = f.p, W = f.W;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = blockIdx.y, b = blockIdx.z;
+    const int m = bd.r0 + blockIdx.y, b = blockIdx.z;
     if (c >= W) return;
     C64 v = {0.0, 0.0};
     if (c < f.P1) {
@@ -79,35 +81,42 @@ fold_rhs_kernel(SrcEval ev, Fold f, int planes, T* __restrict__ out) {
         const int q = c - f.P1 + 1;
         if (q < p) v = csub(ev.rhs(b, m, q), ev.rhs(b, m, n - q));
     }
-    const long o = (((long)b * planes) * (n + 1) + m) * W + c;
+    const long o = (((long)b * planes) * bd.nr + (m - bd.r0)) * W + c;
     out[o] = (T)v.re;
-    if (planes == 2) out[o + (long)(n + 1) * W] = (T)v.im;
+    if (planes == 2) out[o + (long)bd.nr * W] = (T)v.im;
 }
 
 // ------------------------------------------------------------------ tridiagonal solve per mode
-// For column c (one sine mode) and right-hand side b: rows m = 0..n,
-//   Thomas with precomputed factors: y_0 = f_0, y_m = f_m - l_m y_{m-1};
-//   x_n = r_n y_n, x_m = r_m (y_m - s_m x_{m+1}) with s_0 = sup0 (complex end
+// For column c (one sine mode) and right-hand side b, over the band of rows
+// m = r0..t (t = r0 + nr - 1), Thomas with precomputed factors:
+//   y_{r0-1} = 0, y_m = f_m - l_m y_{m-1};
+//   x_t = tw_t y_t, x_m = r_m (y_m - s_m x_{m+1}) with s_0 = sup0 (complex end
 //   row), s_m = a_c (interior off-diagonal) otherwise.
-// fac planes: [0] l.re [1] l.im [2] r.re [3] r.im, each (n+1) x W; colc: [0] a, [1] sup0.re, [2] sup0.im.
+// For the full system (r0 = 0, t = n) this is the plain LU solve (tw_n = r_n).
+// A band is exact when the right-hand side vanishes outside it: above it y is
+// zero, below it the rows are eliminated in advance by the twisted pivot tw_t.
+// fac planes: [0] l.re [1] l.im [2] r.re [3] r.im [4] tw.re [5] tw.im, each
+// (n+1) x W by absolute row; colc: [0] a, [1] sup0.re, [2] sup0.im.
 // y is kept in `out` between the sweeps.
 template <class T>
 __global__ void __launch_bounds__(256)
 tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, const T* __restrict__ fac,
-               const T* __restrict__ colc, int n, int W, int R) {
+               const T* __restrict__ colc, int n, int W, int R, Band bd) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (c >= W || b >= R) return;
-    const long plane = (long)(n + 1) * W;
-    const T* fin_re = in + (long)b * planes_in * plane + c;
+    const int r0 = bd.r0, t = bd.r0 + bd.nr - 1;
+    const long plane = (long)bd.nr * W, fplane = (long)(n + 1) * W;
+    const T* fin_re = in + (long)b * planes_in * plane + c - (long)r0 * W;   // indexed by absolute row
     const T* fin_im = (planes_in == 2) ? fin_re + plane : nullptr;
-    T* o_re = out + (long)b * 2 * plane + c;
+    T* o_re = out + (long)b * 2 * plane + c - (long)r0 * W;
     T* o_im = o_re + plane;
     const T* l_re = fac + c;
-    const T* l_im = fac + plane + c;
-    const T* r_re = fac + 2 * plane + c;
-    const T* r_im = fac + 3 * plane + c;
+    const T* l_im = fac + fplane + c;
+    const T* r_re = fac + 2 * fplane + c;
+    const T* r_im = fac + 3 * fplane + c;
     const T a = colc[c], s0r = colc[W + c], s0i = colc[2 * W + c];
+    const T twr = fac[4 * fplane + (long)t * W + c], twi = fac[5 * fplane + (long)t * W + c];
 
     // forward sweep, rows in groups of U with the next group's loads in flight
     constexpr int U = 8;
@@ -116,21 +125,21 @@ tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, con
     auto load_fwd = [&](int m0, T* F, T* Fi, T* Lr, T* Li) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const long off = (long)min(m0 + u, n) * W;
+            const long off = (long)min(m0 + u, t) * W;
             F[u] = fin_re[off];
             Fi[u] = fin_im ? fin_im[off] : T(0);
             Lr[u] = l_re[off];
             Li[u] = l_im[off];
         }
     };
-    load_fwd(0, fr, fi, lr, li);
-    for (int m0 = 0; m0 <= n; m0 += U) {
-        if (m0 + U <= n) load_fwd(m0 + U, nfr, nfi, nlr, nli);
+    load_fwd(r0, fr, fi, lr, li);
+    for (int m0 = r0; m0 <= t; m0 += U) {
+        if (m0 + U <= t) load_fwd(m0 + U, nfr, nfi, nlr, nli);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int m = m0 + u;
-            if (m > n) break;
-            const T nr = fr[u] - (lr[u] * yr - li[u] * yi);   // l_0 = 0
+            if (m > t) break;
+            const T nr = fr[u] - (lr[u] * yr - li[u] * yi);   // y_{r0-1} = 0 (and l_0 = 0)
             const T ni = fi[u] - (lr[u] * yi + li[u] * yr);
             yr = nr;
             yi = ni;
@@ -147,25 +156,26 @@ tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, con
     }
     // backward sweep over the same groups, last group first; y comes back from out
     T xr = T(0), xi = T(0);
-    const int last = (n / U) * U;
+    const int last = r0 + ((t - r0) / U) * U;
     auto load_bwd = [&](int m0, T* Yr, T* Yi, T* Qr, T* Qi) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const long off = (long)min(m0 + u, n) * W;
+            const int m = min(m0 + u, t);
+            const long off = (long)m * W;
             Yr[u] = o_re[off];
             Yi[u] = o_im[off];
-            Qr[u] = r_re[off];
-            Qi[u] = r_im[off];
+            Qr[u] = (m == t) ? twr : r_re[off];
+            Qi[u] = (m == t) ? twi : r_im[off];
         }
     };
     load_bwd(last, fr, fi, lr, li);
-    for (int m0 = last; m0 >= 0; m0 -= U) {
-        if (m0 >= U) load_bwd(m0 - U, nfr, nfi, nlr, nli);
+    for (int m0 = last; m0 >= r0; m0 -= U) {
+        if (m0 - U >= r0) load_bwd(m0 - U, nfr, nfi, nlr, nli);
 #pragma unroll
         for (int u = U - 1; u >= 0; --u) {
             const int m = m0 + u;
-            if (m > n) continue;
-            const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);   // x_{n+1} = 0
+            if (m > t) continue;
+            const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);   // x_{t+1} does not enter (xr = 0)
             const T tr = fr[u] - (sr * xr - si * xi), ti = fi[u] - (sr * xi + si * xr);
             xr = lr[u] * tr - li[u] * ti;
             xi = lr[u] * ti + li[u] * tr;
@@ -182,14 +192,182 @@ tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, con
     }
 }
 
+// The same solve cut into P row segments, one wavefront each (64 columns per
+// workgroup), for batches too small to fill the chip one column per thread.
+// Both sweeps are first-order linear recurrences,
+//   y_m = f_m - l_m y_{m-1},   x_m = rr_m y_m - rr_m s_m x_{m+1}   (rr_t = tw_t),
+// so each segment runs its recurrence from a zero start together with the
+// product of its coefficients (phi = prod(-l_m) forward, psi = prod(-rr_m s_m)
+// backward), one wavefront chains the P segment ends in order, and every
+// segment then adds phi (psi) times the value carried into it.  The rounding
+// is that of the sequential sweep: the same products of l (r s) multiply the
+// same terms, only grouped by segment.
+template <class T>
+struct PartLds {
+    T er[16][64], ei[16][64];   // segment end values (zero-start run)
+    T pr[16][64], pi[16][64];   // segment coefficient products
+    T cr[16][64], ci[16][64];   // values carried into the segments
+};
+
+template <class T>
+__global__ void __launch_bounds__(1024)
+tridiag_part_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, const T* __restrict__ fac,
+                    const T* __restrict__ colc, int n, int W, Band bd, int P, int Lseg) {
+    __shared__ PartLds<T> s;
+    const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane, b = blockIdx.y;
+    const bool act = c < W && p < P;
+    const int r0 = bd.r0, t = bd.r0 + bd.nr - 1;
+    const int ms = r0 + p * Lseg, me = min(ms + Lseg - 1, t);
+    const long plane = (long)bd.nr * W, fplane = (long)(n + 1) * W;
+    const int cc = min(c, W - 1);
+    const T* fin_re = in + (long)b * planes_in * plane + cc - (long)r0 * W;   // indexed by absolute row
+    const T* fin_im = (planes_in == 2) ? fin_re + plane : nullptr;
+    T* o_re = out + (long)b * 2 * plane + cc - (long)r0 * W;
+    T* o_im = o_re + plane;
+    const T* l_re = fac + cc;
+    const T* l_im = fac + fplane + cc;
+    const T* r_re = fac + 2 * fplane + cc;
+    const T* r_im = fac + 3 * fplane + cc;
+    const T a = colc[cc], s0r = colc[W + cc], s0i = colc[2 * W + cc];
+    const T twr = fac[4 * fplane + (long)t * W + cc], twi = fac[5 * fplane + (long)t * W + cc];
+    constexpr int U = 8;
+    T vr[U], vi[U], kr[U], ki[U];   // per row of a group: data value and recurrence coefficient
+
+    // forward group loads: data (from `src` planes) and -l_m
+    auto load_f = [&](int g0, const T* sre, const T* sim) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long off = (long)min(g0 + u, me) * W;
+            vr[u] = sre[off];
+            vi[u] = sim ? sim[off] : T(0);
+            kr[u] = -l_re[off];
+            ki[u] = -l_im[off];
+        }
+    };
+    // backward group loads: y_m and rr_m
+    auto load_b = [&](int g0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int m = min(g0 + u, me);
+            const long off = (long)m * W;
+            vr[u] = o_re[off];
+            vi[u] = o_im[off];
+            kr[u] = (m == t) ? twr : r_re[off];
+            ki[u] = (m == t) ? twi : r_im[off];
+        }
+    };
+    const int glast = ms + ((me - ms) / U) * U;
+
+    // A: forward run from zero and phi over the segment; the run goes to out
+    T yr = T(0), yi = T(0), fr = T(1), fi = T(0);
+    if (act) {
+        for (int g0 = ms; g0 <= me; g0 += U) {
+            load_f(g0, fin_re, fin_im);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (g0 + u > me) break;
+                const T nr = vr[u] + (kr[u] * yr - ki[u] * yi), ni = vi[u] + (kr[u] * yi + ki[u] * yr);
+                const T qr = kr[u] * fr - ki[u] * fi, qi = kr[u] * fi + ki[u] * fr;
+                yr = nr; yi = ni; fr = qr; fi = qi;
+                o_re[(long)(g0 + u) * W] = yr;
+                o_im[(long)(g0 + u) * W] = yi;
+            }
+        }
+        s.er[p][lane] = yr; s.ei[p][lane] = yi;
+        s.pr[p][lane] = fr; s.pi[p][lane] = fi;
+    }
+    __syncthreads();
+    if (p == 0) {   // y at the end of every segment, segment by segment
+        T Yr = T(0), Yi = T(0);
+        for (int q = 0; q < P; ++q) {
+            const T pr = s.pr[q][lane], pi = s.pi[q][lane];
+            const T nr = s.er[q][lane] + (pr * Yr - pi * Yi), ni = s.ei[q][lane] + (pr * Yi + pi * Yr);
+            Yr = nr; Yi = ni;
+            s.cr[q][lane] = Yr; s.ci[q][lane] = Yi;
+        }
+    }
+    __syncthreads();
+    // C: y_m = run_m + phi_m Y_in
+    if (act) {
+        const T Yr = (p > 0) ? s.cr[p - 1][lane] : T(0), Yi = (p > 0) ? s.ci[p - 1][lane] : T(0);
+        fr = T(1); fi = T(0);
+        for (int g0 = ms; g0 <= me; g0 += U) {
+            load_f(g0, o_re, o_im);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (g0 + u > me) break;
+                const T qr = kr[u] * fr - ki[u] * fi, qi = kr[u] * fi + ki[u] * fr;
+                fr = qr; fi = qi;
+                o_re[(long)(g0 + u) * W] = vr[u] + (fr * Yr - fi * Yi);
+                o_im[(long)(g0 + u) * W] = vi[u] + (fr * Yi + fi * Yr);
+            }
+        }
+    }
+    __syncthreads();
+    // D: backward run from zero and psi over the segment (the segment holding t starts with x_t = tw_t y_t)
+    T xr = T(0), xi = T(0), gr = T(1), gi = T(0);
+    if (act) {
+        for (int g0 = glast; g0 >= ms; g0 -= U) {
+            load_b(g0);
+#pragma unroll
+            for (int u = U - 1; u >= 0; --u) {
+                const int m = g0 + u;
+                if (m > me) continue;
+                const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);
+                const T tr = vr[u] - (sr * xr - si * xi), ti = vi[u] - (sr * xi + si * xr);
+                xr = kr[u] * tr - ki[u] * ti;
+                xi = kr[u] * ti + ki[u] * tr;
+                const T qr = -(kr[u] * sr - ki[u] * si), qi = -(kr[u] * si + ki[u] * sr);
+                const T hr = qr * gr - qi * gi, hi = qr * gi + qi * gr;
+                gr = hr; gi = hi;
+                o_re[(long)m * W] = xr;
+                o_im[(long)m * W] = xi;
+            }
+        }
+        s.er[p][lane] = xr; s.ei[p][lane] = xi;
+        s.pr[p][lane] = gr; s.pi[p][lane] = gi;
+    }
+    __syncthreads();
+    if (p == 0) {   // x at the start of every segment, last segment first
+        T Xr = T(0), Xi = T(0);
+        for (int q = P - 1; q >= 0; --q) {
+            const T pr = s.pr[q][lane], pi = s.pi[q][lane];
+            const T nr = s.er[q][lane] + (pr * Xr - pi * Xi), ni = s.ei[q][lane] + (pr * Xi + pi * Xr);
+            Xr = nr; Xi = ni;
+            s.cr[q][lane] = Xr; s.ci[q][lane] = Xi;
+        }
+    }
+    __syncthreads();
+    // F: x_m = run_m + psi_m X_in
+    if (act) {
+        const T Xr = (p + 1 < P) ? s.cr[p + 1][lane] : T(0), Xi = (p + 1 < P) ? s.ci[p + 1][lane] : T(0);
+        gr = T(1); gi = T(0);
+        for (int g0 = glast; g0 >= ms; g0 -= U) {
+            load_b(g0);   // vr/vi: the backward run
+#pragma unroll
+            for (int u = U - 1; u >= 0; --u) {
+                const int m = g0 + u;
+                if (m > me) continue;
+                const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);
+                const T qr = -(kr[u] * sr - ki[u] * si), qi = -(kr[u] * si + ki[u] * sr);
+                const T hr = qr * gr - qi * gi, hi = qr * gi + qi * gr;
+                gr = hr; gi = hi;
+                o_re[(long)m * W] = vr[u] + (gr * Xr - gi * Xi);
+                o_im[(long)m * W] = vi[u] + (gr * Xi + gi * Xr);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ unfold helpers
 // u(m, q) of right-hand side b, plane pl, from folded synthesis rows:
 //   u_q = A_q + B_q, u_{n-q} = A_q - B_q (q < p), u_p = A_p, zero at q = 0, n.
 template <class T>
-__device__ inline double unfold_at(const T* __restrict__ u, const Fold& f, int b, int pl, int m, int q) {
+__device__ inline double unfold_at(const T* __restrict__ u, const Fold& f, Band bd, int b, int pl, int m, int q) {
     const int n = f.n, p = f.p;
     if (q <= 0 || q >= n) return 0.0;
-    const T* row = u + (((long)b * 2 + pl) * (n + 1) + m) * f.W;
+    const T* row = u + (((long)b * 2 + pl) * bd.nr + (m - bd.r0)) * f.W;
     if (q == p) return (double)row[p - 1];
     if (q < p) return (double)row[q - 1] + (double)row[f.P1 + q - 1];
     const int qq = n - q;
@@ -197,8 +375,8 @@ __device__ inline double unfold_at(const T* __restrict__ u, const Fold& f, int b
 }
 
 template <class T>
-__device__ inline C64 unfold_c(const T* __restrict__ u, const Fold& f, int b, int m, int q) {
-    return {unfold_at(u, f, b, 0, m, q), unfold_at(u, f, b, 1, m, q)};
+__device__ inline C64 unfold_c(const T* __restrict__ u, const Fold& f, Band bd, int b, int m, int q) {
+    return {unfold_at(u, f, bd, b, 0, m, q), unfold_at(u, f, bd, b, 1, m, q)};
 }
 
 // ------------------------------------------------------------------ residual (refinement)
@@ -284,39 +462,41 @@ residual_kernel(SrcEval ev, EndRowCoef ec, Fold f, const float* __restrict__ u32
 // ------------------------------------------------------------------ gather onto gamma (projector)
 // Q(i, col0+b) = -(u(m_i, q_i)) with u = u_main (+ du, the FP32 correction of a refined solve).
 template <class T>
-__global__ void gather_q_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f,
+__global__ void gather_q_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f, Band bd,
                                 const int* __restrict__ gm, const int* __restrict__ gq, int ng,
                                 double* __restrict__ Q, int ldq, int col0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= ng) return;
     const int m = gm[i], q = gq[i];
-    C64 v = unfold_c(u, f, b, m, q);
-    if (du) v = cadd(v, unfold_c(du, f, b, m, q));
+    C64 v = unfold_c(u, f, bd, b, m, q);
+    if (du) v = cadd(v, unfold_c(du, f, bd, b, m, q));
     double* o = Q + 2 * ((long)(col0 + b) * ldq + i);
     o[0] = -v.re;
     o[1] = -v.im;
 }
 
 // ------------------------------------------------------------------ unfold to grids
-// out_b(m, q) = w_b(m, q) + alpha * u_b(m, q)  (w optional; complex interleaved FP64)
+// out_b(m, q) = w_b(m, q) + alpha * u_b(m, q) on the rows out_r0 + blockIdx.y (inside the
+// buffer's band bd; w optional; complex interleaved FP64)
 template <class T>
-__global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f, double alpha,
-                                   const double* w, long w_stride, double* out, long out_stride) {
+__global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f, Band bd,
+                                   int out_r0, double alpha, const double* w, long w_stride, double* out,
+                                   long out_stride, const long* __restrict__ boff) {
     const int n = f.n;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = blockIdx.y, b = blockIdx.z;
+    const int m = out_r0 + blockIdx.y, b = blockIdx.z;
     if (q > n) return;
     const long node = (long)m * (n + 1) + q;
-    C64 v = unfold_c(u, f, b, m, q);
-    if (du) v = cadd(v, unfold_c(du, f, b, m, q));
+    C64 v = unfold_c(u, f, bd, b, m, q);
+    if (du) v = cadd(v, unfold_c(du, f, bd, b, m, q));
     double re = alpha * v.re, im = alpha * v.im;
     if (w) {
-        const double* wp = w + 2 * ((long)b * w_stride + node);
+        const double* wp = w + 2 * ((boff ? boff[b] : (long)b * w_stride) + node);
         re += wp[0];
         im += wp[1];
     }
-    double* o = out + 2 * ((long)b * out_stride + node);
+    double* o = out + 2 * ((boff ? boff[b] : (long)b * out_stride) + node);
     o[0] = re;
     o[1] = im;
 }
@@ -324,15 +504,16 @@ __global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restr
 // ------------------------------------------------------------------ density on gamma for reconstruction
 // w_b(gamma_i) = sum_col E(i, col) c_b(col)  (E real, c complex); w is pre-zeroed elsewhere.
 __global__ void extend_density_kernel(const double* __restrict__ E, int ng, int ncol, const double* __restrict__ c,
-                                      const int* __restrict__ gm, const int* __restrict__ gq,
-                                      const int* __restrict__ gside, int n, double* w, long w_stride) {
+                                      const int* __restrict__ cidx, const int* __restrict__ gm,
+                                      const int* __restrict__ gq, const int* __restrict__ gside, int n, double* w,
+                                      long w_stride, const long* __restrict__ woff) {
     // row i of E is nonzero only in its side's Dirichlet and Neumann columns
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= ng) return;
     const int M = ncol / 8, s = gside[i];
     double re = 0.0, im = 0.0;
-    const double* cb = c + 2 * (long)b * ncol;
+    const double* cb = c + 2 * (long)(cidx ? cidx[b] : b) * ncol;
     for (int kind = 0; kind < 2; ++kind) {
         const int col0 = kind * 4 * M + s * M;
 #pragma unroll 8
@@ -342,7 +523,7 @@ __global__ void extend_density_kernel(const double* __restrict__ E, int ng, int 
             im += e * cb[2 * (col0 + j) + 1];
         }
     }
-    double* o = w + 2 * ((long)b * w_stride + (long)gm[i] * (n + 1) + gq[i]);
+    double* o = w + 2 * ((woff ? woff[b] : (long)b * w_stride) + (long)gm[i] * (n + 1) + gq[i]);
     o[0] = re;
     o[1] = im;
 }
@@ -413,23 +594,42 @@ static void check_batch(int R) {
     if (R > 65535) throw Error(MDP_ERR_ARG, "batch too large for one launch");
 }
 
+static void check_band(const Band& bd, int n) {
+    if (bd.r0 < 0 || bd.nr < 1 || bd.r0 + bd.nr > n + 1) throw Error(MDP_ERR_ARG, "row band outside the grid");
+}
+
 template <class T>
-void launch_fold_rhs(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, bool cplx, T* out,
+void launch_fold_rhs(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, bool cplx, Band bd, T* out,
                      hipStream_t st) {
     check_batch(R);
+    check_band(bd, n);
     SrcEval ev{s, n, sc};
     const int bx = f.W < 256 ? f.W : 256;
-    dim3 grid((f.W + bx - 1) / bx, n + 1, R);
-    hipLaunchKernelGGL(fold_rhs_kernel<T>, grid, dim3(bx), 0, st, ev, f, cplx ? 2 : 1, out);
+    dim3 grid((f.W + bx - 1) / bx, bd.nr, R);
+    hipLaunchKernelGGL(fold_rhs_kernel<T>, grid, dim3(bx), 0, st, ev, f, cplx ? 2 : 1, bd, out);
     MDP_HIP(hipGetLastError());
 }
 
 template <class T>
 void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* colc, int n, const Fold& f, int R,
-                    hipStream_t st) {
+                    Band bd, hipStream_t st) {
     check_batch(R);
-    dim3 grid((f.W + 255) / 256, R);
-    hipLaunchKernelGGL(tridiag_kernel<T>, grid, dim3(256), 0, st, in, planes_in, out, fac, colc, n, f.W, R);
+    check_band(bd, n);
+    // one column per thread while that gives a few thousand wavefronts; otherwise up to 16
+    // row segments of at least 8 rows per column
+    const long waves = (long)R * ((f.W + 63) / 64);
+    int P = (int)std::min<long>(16, (4096 + waves - 1) / waves);
+    P = std::min(P, (bd.nr + 7) / 8);
+    if (P <= 1) {
+        dim3 grid((f.W + 255) / 256, R);
+        hipLaunchKernelGGL(tridiag_kernel<T>, grid, dim3(256), 0, st, in, planes_in, out, fac, colc, n, f.W, R, bd);
+    } else {
+        const int Lseg = (bd.nr + P - 1) / P;
+        P = (bd.nr + Lseg - 1) / Lseg;
+        dim3 grid((f.W + 63) / 64, R);
+        hipLaunchKernelGGL(tridiag_part_kernel<T>, grid, dim3(64 * P), 0, st, in, planes_in, out, fac, colc, n, f.W,
+                           bd, P, Lseg);
+    }
     MDP_HIP(hipGetLastError());
 }
 
@@ -444,49 +644,56 @@ void launch_residual(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, End
 }
 
 template <class T>
-void launch_gather_q(const T* u, const float* du, int n, const Fold& f, const int* gm, const int* gq, int ng, int R,
-                     double* Q, int ldq, int col0, hipStream_t st) {
-    (void)n;
+void launch_gather_q(const T* u, const float* du, int n, const Fold& f, Band bd, const int* gm, const int* gq, int ng,
+                     int R, double* Q, int ldq, int col0, hipStream_t st) {
     check_batch(R);
+    check_band(bd, n);
     dim3 grid((ng + 255) / 256, R);
-    hipLaunchKernelGGL(gather_q_kernel<T>, grid, dim3(256), 0, st, u, du, f, gm, gq, ng, Q, ldq, col0);
+    hipLaunchKernelGGL(gather_q_kernel<T>, grid, dim3(256), 0, st, u, du, f, bd, gm, gq, ng, Q, ldq, col0);
     MDP_HIP(hipGetLastError());
 }
 
 template <class T>
-void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, int R, const double* w, long w_stride,
-                        double* out, long out_stride, hipStream_t st) {
+void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, Band bd, Band rows, int R, const double* w,
+                        long w_stride, double* out, long out_stride, const long* boff, hipStream_t st) {
     check_batch(R);
+    check_band(bd, n);
+    if (rows.r0 < bd.r0 || rows.nr < 1 || rows.r0 + rows.nr > bd.r0 + bd.nr)
+        throw Error(MDP_ERR_ARG, "output rows outside the solved band");
     double alpha = w ? -1.0 : 1.0;
-    dim3 grid((n + 1 + 255) / 256, n + 1, R);
-    hipLaunchKernelGGL(unfold_grid_kernel<T>, grid, dim3(256), 0, st, u, du, f, alpha, w, w_stride, out, out_stride);
+    dim3 grid((n + 1 + 255) / 256, rows.nr, R);
+    hipLaunchKernelGGL(unfold_grid_kernel<T>, grid, dim3(256), 0, st, u, du, f, bd, rows.r0, alpha, w, w_stride, out,
+                       out_stride, boff);
     MDP_HIP(hipGetLastError());
 }
 
-void launch_extend_density(const double* E, int ng, int ncol, const double* c, int R, const int* gm,
-                           const int* gq, const int* gside, int n, double* w, long w_stride, hipStream_t st) {
+void launch_extend_density(const double* E, int ng, int ncol, const double* c, const int* cidx, int R, const int* gm,
+                           const int* gq, const int* gside, int n, double* w, long w_stride, const long* woff,
+                           hipStream_t st) {
     check_batch(R);
     if (ncol % 8) throw Error(MDP_ERR_ARG, "extension matrix width must be 8 M*");
     dim3 grid((ng + 255) / 256, R);
-    hipLaunchKernelGGL(extend_density_kernel, grid, dim3(256), 0, st, E, ng, ncol, c, gm, gq, gside, n, w,
-                       w_stride);
+    hipLaunchKernelGGL(extend_density_kernel, grid, dim3(256), 0, st, E, ng, ncol, c, cidx, gm, gq, gside, n, w,
+                       w_stride, woff);
     MDP_HIP(hipGetLastError());
 }
 
-template void launch_fold_rhs<double>(const SrcDesc&, int, const Fold&, StencilCoef, int, bool, double*, hipStream_t);
-template void launch_fold_rhs<float>(const SrcDesc&, int, const Fold&, StencilCoef, int, bool, float*, hipStream_t);
-template void launch_tridiag<double>(const double*, int, double*, const double*, const double*, int, const Fold&, int,
+template void launch_fold_rhs<double>(const SrcDesc&, int, const Fold&, StencilCoef, int, bool, Band, double*,
+                                      hipStream_t);
+template void launch_fold_rhs<float>(const SrcDesc&, int, const Fold&, StencilCoef, int, bool, Band, float*,
                                      hipStream_t);
+template void launch_tridiag<double>(const double*, int, double*, const double*, const double*, int, const Fold&, int,
+                                     Band, hipStream_t);
 template void launch_tridiag<float>(const float*, int, float*, const float*, const float*, int, const Fold&, int,
-                                    hipStream_t);
-template void launch_gather_q<double>(const double*, const float*, int, const Fold&, const int*, const int*, int, int,
-                                      double*, int, int, hipStream_t);
-template void launch_gather_q<float>(const float*, const float*, int, const Fold&, const int*, const int*, int, int,
-                                     double*, int, int, hipStream_t);
-template void launch_unfold_grid<double>(const double*, const float*, int, const Fold&, int, const double*, long,
-                                         double*, long, hipStream_t);
-template void launch_unfold_grid<float>(const float*, const float*, int, const Fold&, int, const double*, long,
-                                        double*, long, hipStream_t);
+                                    Band, hipStream_t);
+template void launch_gather_q<double>(const double*, const float*, int, const Fold&, Band, const int*, const int*, int,
+                                      int, double*, int, int, hipStream_t);
+template void launch_gather_q<float>(const float*, const float*, int, const Fold&, Band, const int*, const int*, int,
+                                     int, double*, int, int, hipStream_t);
+template void launch_unfold_grid<double>(const double*, const float*, int, const Fold&, Band, Band, int,
+                                         const double*, long, double*, long, const long*, hipStream_t);
+template void launch_unfold_grid<float>(const float*, const float*, int, const Fold&, Band, Band, int, const double*,
+                                        long, double*, long, const long*, hipStream_t);
 
 
 // ============================================================================
@@ -611,26 +818,34 @@ __device__ inline int special_slot(const RingGeom& r, int m) {
 // elimination (y_m = ghat_m - l_m y_{m-1}, x_m = r_m (y_m - s_m x_{m+1})),
 // then per row the synthesis partial sums x_m(c) * sin(pi j q / n) at
 // q = q_lo-1, q_lo (into thin) and the full gamma rows into xs.
-// gc[b][n+1][4] ring table, lf/rf[(n+1)][W] complex factors l_m, r_m,
-// ckpt[b][seg][2][W], xs[b][2][4][W], thin[b][wblk][nseg*K][4].
-// LDS: the wave's (n+1) ring pairs and the 4 special-row values per lane.
+// Only the rows m0 = m_lo-1 .. t = m_hi+1 are swept: the right-hand side is
+// zero outside the box, so y vanishes above it, and below it the homogeneous
+// rows are eliminated from the bottom in advance (twisted factorisation at
+// row t: x_t = tw_t y_t with tw_t = 1/(d'_t - s_t sub_{t+1}/e_{t+1}), e the
+// pivots of the bottom-up elimination).
+// gc[b][n+1][4] ring table, lf/rf/tf[(n+1)][W] complex factors l_m, r_m, tw_m,
+// ckpt[b][seg][2][W], xs[b][2][4][W], thin[b][wblk][nseg*K][4] (rows from m0).
+// LDS: the wave's ring pairs of rows m0..t and the 4 special-row values per lane.
 template <int K>
 __global__ void __launch_bounds__(64)
 proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec_hat,
                   const double* __restrict__ Sf, const double* __restrict__ Si, Fold f, RingGeom rg,
-                  const dv2* __restrict__ lf, const dv2* __restrict__ rf, const double* __restrict__ colc,
-                  double* __restrict__ ckpt, double* __restrict__ xs, double* __restrict__ thin, int nseg) {
+                  const dv2* __restrict__ lf, const dv2* __restrict__ rf, const dv2* __restrict__ tf,
+                  const double* __restrict__ colc, double* __restrict__ ckpt, double* __restrict__ xs,
+                  double* __restrict__ thin, int nseg) {
     static_assert(K % 8 == 0, "segments are reduced 8 rows at a time");
-    extern __shared__ double2 lds_g[];  // [n+1] ring pairs, then [5][64] special values
+    extern __shared__ double2 lds_g[];  // [t-m0+1] ring pairs, then [5][64] special values
     const int n = f.n, W = f.W;
     const int lane = threadIdx.x, wblk = blockIdx.x, b = blockIdx.y;
     const int c = wblk * 64 + lane;
     const bool odd = c < f.P1;  // uniform over the wavefront (P1 is a multiple of 64)
     const int base = odd ? 0 : f.P1;
-    double* lds_sp = reinterpret_cast<double*>(lds_g + (n + 1));
+    const int m0 = rg.m_lo - 1, t = rg.m_hi + 1;
+    double* lds_sp = reinterpret_cast<double*>(lds_g + (t - m0 + 1));
     {
         const double* g = gc + (long)b * (n + 1) * 4 + (odd ? 0 : 2);
-        for (int m = lane; m <= n; m += 64) lds_g[m] = make_double2(g[(long)m * 4], g[(long)m * 4 + 1]);
+        for (int m = m0 + lane; m <= t; m += 64)
+            lds_g[m - m0] = make_double2(g[(long)m * 4], g[(long)m * 4 + 1]);
 #pragma unroll
         for (int s = 0; s < 4; ++s) lds_sp[s * 64 + lane] = spec_hat[((long)b * 4 + s) * W + c];
         lds_sp[4 * 64 + lane] = 0.0;
@@ -641,21 +856,22 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
     const double t1 = Si[(long)c * W + base + rg.q_lo - 2];
     const double t2 = Si[(long)c * W + base + rg.q_lo - 1];
     const double a = colc[c], s0r = colc[W + c], s0i = colc[2 * W + c];
+    const dv2 tw = tf[(long)t * W + c];
     const dv2* lcol = lf + c;
     const dv2* rcol = rf + c;
     double* ck = ckpt + (long)b * nseg * 2 * W + c;
 
     auto ghat = [&](int m) -> double {
-        const double2 g = lds_g[m];
+        const double2 g = lds_g[m - m0];
         return g.x * s1 + g.y * s2 + lds_sp[special_slot(rg, m) * 64 + lane];
     };
-    // factor rows of segment s (rows past n read row n; their results are unused)
+    // factor rows of segment s (rows past t read row t; their results are unused)
     auto load_f = [&](dv2* F, const dv2* col, int s) {
 #pragma unroll
-        for (int i = 0; i < K; ++i) F[i] = col[(long)min(s * K + i, n) * W];
+        for (int i = 0; i < K; ++i) F[i] = col[(long)min(m0 + s * K + i, t) * W];
     };
 
-    // forward elimination, checkpointing y at the end of every full segment
+    // forward elimination from row m0 (y_{m0-1} = 0), checkpointing y at the end of every full segment
     double yr = 0.0, yi = 0.0;
     {
         dv2 Lc[K], Ln[K];
@@ -664,7 +880,7 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
             load_f(Ln, lcol, s + 1);
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                const double fr = ghat(s * K + i);
+                const double fr = ghat(m0 + s * K + i);
                 const double nr = fr - (Lc[i].x * yr - Lc[i].y * yi);
                 const double ni = -(Lc[i].x * yi + Lc[i].y * yr);
                 yr = nr;
@@ -678,7 +894,7 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
     }
 
     // back substitution segment by segment: recompute the segment's y from
-    // the checkpoint before it, then walk back through it
+    // the checkpoint before it, then walk back through it (x_t = tw_t y_t)
     double xr = 0.0, xi = 0.0;
     double* xs_re = xs + (long)b * 8 * W + c;
     double* xs_im = xs_re + 4 * W;
@@ -696,7 +912,7 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
         double vr[K], vi[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const int m = min(s * K + i, n);
+            const int m = min(m0 + s * K + i, t);
             const double fr = ghat(m);
             const double nr = fr - (Lc[i].x * pr - Lc[i].y * pi);
             const double ni = -(Lc[i].x * pi + Lc[i].y * pr);
@@ -707,13 +923,14 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
         }
 #pragma unroll
         for (int i = K - 1; i >= 0; --i) {
-            const int m = s * K + i;
-            if (m <= n) {
+            const int m = m0 + s * K + i;
+            if (m <= t) {
                 const double offr = (m == 0) ? s0r : a, offi = (m == 0) ? s0i : 0.0;
                 const double tr = vr[i] - (offr * xr - offi * xi);
                 const double ti = vi[i] - (offr * xi + offi * xr);
-                xr = Rc[i].x * tr - Rc[i].y * ti;
-                xi = Rc[i].x * ti + Rc[i].y * tr;
+                const dv2 rm = (m == t) ? tw : Rc[i];
+                xr = rm.x * tr - rm.y * ti;
+                xi = rm.x * ti + rm.y * tr;
                 const int so = special_out(rg, m);
                 if (so >= 0) {
                     xs_re[(long)so * W] = xr;
@@ -726,21 +943,19 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
                 vi[i] = 0.0;
             }
         }
-        // synthesis partial sums of the gamma rows met by this segment
-        if (s * K <= rg.m_hi + 1 && s * K + K - 1 >= rg.m_lo - 1) {
+        // synthesis partial sums of the gamma rows of this segment
 #pragma unroll
-            for (int h8 = 0; h8 < K; h8 += 8) {
-                double v[32];
+        for (int h8 = 0; h8 < K; h8 += 8) {
+            double v[32];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    v[4 * i + 0] = vr[h8 + i] * t1;
-                    v[4 * i + 1] = vi[h8 + i] * t1;
-                    v[4 * i + 2] = vr[h8 + i] * t2;
-                    v[4 * i + 3] = vi[h8 + i] * t2;
-                }
-                reduce_32(v, lane);
-                if ((lane & 1) == 0) th[(long)(s * K + h8) * 4 + (lane >> 1)] = v[0];
+            for (int i = 0; i < 8; ++i) {
+                v[4 * i + 0] = vr[h8 + i] * t1;
+                v[4 * i + 1] = vi[h8 + i] * t1;
+                v[4 * i + 2] = vr[h8 + i] * t2;
+                v[4 * i + 3] = vi[h8 + i] * t2;
             }
+            reduce_32(v, lane);
+            if ((lane & 1) == 0) th[(long)(s * K + h8) * 4 + (lane >> 1)] = v[0];
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) Lc[i] = Ln[i];
@@ -780,7 +995,7 @@ __global__ void gather_q_fused_kernel(const double* __restrict__ us, const doubl
         const int nb = W / 64, nb1 = f.P1 / 64;
         double A0 = 0.0, A1 = 0.0, B0 = 0.0, B1 = 0.0;
         for (int w = 0; w < nb; ++w) {
-            const double* t = thin + (((long)b * nb + w) * rows_pad + m) * 4 + k2;
+            const double* t = thin + (((long)b * nb + w) * rows_pad + (m - rg.m_lo + 1)) * 4 + k2;
             if (w < nb1) { A0 += t[0]; A1 += t[1]; }
             else { B0 += t[0]; B1 += t[1]; }
         }
@@ -813,7 +1028,7 @@ bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int 
            f.W % 64 == 0 && f.P1 % 64 == 0;
 }
 
-int fused_segments(int n) { return (n + 1 + FUSED_K - 1) / FUSED_K; }
+int fused_segments(int m_lo, int m_hi) { return (m_hi - m_lo + 3 + FUSED_K - 1) / FUSED_K; }
 
 void launch_fold_ring(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, double* gc, double* spec,
                       hipStream_t st) {
@@ -826,16 +1041,16 @@ void launch_fold_ring(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, in
 }
 
 void launch_proj_fused(const double* gc, const double* spec_hat, const double* Sf, const double* Si, const Fold& f,
-                       int m_lo, int m_hi, int q_lo, int q_hi, const double* lf, const double* rf, const double* colc,
-                       double* ckpt, double* xs, double* thin, int R, hipStream_t st) {
+                       int m_lo, int m_hi, int q_lo, int q_hi, const double* lf, const double* rf, const double* tf,
+                       const double* colc, double* ckpt, double* xs, double* thin, int R, hipStream_t st) {
     check_batch(R);
     if (!fused_projector_supported(f, m_lo, m_hi, q_lo, q_hi)) throw Error(MDP_ERR_ARG, "fused projector geometry");
     RingGeom rg{m_lo, m_hi, q_lo, q_hi};
-    const int nseg = fused_segments(f.n);
-    const size_t lds = (size_t)(f.n + 1) * sizeof(double2) + 5 * 64 * sizeof(double);
+    const int nseg = fused_segments(m_lo, m_hi);
+    const size_t lds = (size_t)(m_hi - m_lo + 3) * sizeof(double2) + 5 * 64 * sizeof(double);
     hipLaunchKernelGGL(proj_fused_kernel<FUSED_K>, dim3(f.W / 64, R), dim3(64), lds, st, gc, spec_hat, Sf, Si, f, rg,
-                       reinterpret_cast<const dv2*>(lf), reinterpret_cast<const dv2*>(rf), colc, ckpt, xs,
-                       thin, nseg);
+                       reinterpret_cast<const dv2*>(lf), reinterpret_cast<const dv2*>(rf),
+                       reinterpret_cast<const dv2*>(tf), colc, ckpt, xs, thin, nseg);
     MDP_HIP(hipGetLastError());
 }
 
@@ -843,7 +1058,7 @@ void launch_gather_q_fused(const double* us, const double* thin, const Fold& f, 
                            const int* gm, const int* gq, int ng, int R, double* Q, int ldq, int col0, hipStream_t st) {
     check_batch(R);
     RingGeom rg{m_lo, m_hi, q_lo, q_hi};
-    const int rows_pad = fused_segments(f.n) * FUSED_K;
+    const int rows_pad = fused_segments(m_lo, m_hi) * FUSED_K;
     dim3 grid((ng + 255) / 256, R);
     hipLaunchKernelGGL(gather_q_fused_kernel, grid, dim3(256), 0, st, us, thin, f, rg, rows_pad, gm, gq, ng, Q, ldq,
                        col0);

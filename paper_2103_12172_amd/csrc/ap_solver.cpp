@@ -96,8 +96,14 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
     // with a = 1/h^2 - lambda/(6h^2) + k^2/12, b = k^2 - lambda (1/h^2 + k^2/12),
     // wD = 1/h - lambda/(24h) + k^2 h/24, wA = 1 - lambda/8 + k^2 h^2/8.
     // Thomas factors: d'_0 = diag_0, l_m = sub_m/d'_{m-1}, d'_m = diag_m - l_m sup_{m-1}; r_m = 1/d'_m.
+    // Twisted pivots (projector sweep over a band of rows m0..t with a zero right-hand side
+    // below t): with the bottom-up elimination e_n = diag_n, e_m = diag_m - sup_m sub_{m+1}/e_{m+1},
+    // row t reduces to gamma_t x_t = y_t, gamma_t = d'_t - sup_t sub_{t+1}/e_{t+1} (gamma_n = d'_n);
+    // tw_m = 1/gamma_m.
     const size_t plane = (size_t)(n + 1) * W;
-    std::vector<double> fac(4 * plane, 0.0), colc(3 * (size_t)W, 0.0);
+    std::vector<double> fac(6 * plane, 0.0), colc(3 * (size_t)W, 0.0), tw(2 * plane, 0.0);
+    std::vector<cd> dpiv(n + 1);
+    twist_ratio.assign(n + 1, 1e300);
     const double h2 = h * h, k2 = k * k;
     min_pivot_ratio = 1e300;
     for (int c = 0; c < W; ++c) {
@@ -122,6 +128,7 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
         };
         double minp = std::abs(dprev);
         put(0, 0.0, 1.0 / dprev);
+        dpiv[0] = dprev;
         for (int m = 1; m <= n; ++m) {
             cd sub = (m < n) ? cd(a) : subn;
             cd sup = (m - 1 == 0) ? sup0 : cd(a);
@@ -131,8 +138,26 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
             minp = std::min(minp, std::abs(d));
             put(m, l, 1.0 / d);
             dprev = d;
+            dpiv[m] = d;
         }
         min_pivot_ratio = std::min(min_pivot_ratio, minp / scale);
+        cd e = diagn;
+        for (int m = n; m >= 0; --m) {
+            cd gam = dpiv[m];
+            if (m < n) {
+                const cd sup = (m == 0) ? sup0 : cd(a);
+                const cd sub1 = (m + 1 < n) ? cd(a) : subn;
+                gam -= sup * sub1 / e;
+                const cd diag = (m == 0) ? diag0 : cd(b - 2 * a);
+                e = diag - sup * sub1 / e;
+            }
+            const cd r = 1.0 / gam;
+            tw[2 * ((size_t)m * W + c)] = r.real();
+            tw[2 * ((size_t)m * W + c) + 1] = r.imag();
+            fac[4 * plane + (size_t)m * W + c] = r.real();
+            fac[5 * plane + (size_t)m * W + c] = r.imag();
+            twist_ratio[m] = std::min(twist_ratio[m], std::abs(gam) / scale);
+        }
         colc[c] = a;
         colc[W + c] = sup0.real();
         colc[2 * (size_t)W + c] = sup0.imag();
@@ -156,6 +181,7 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
     }
     upload<double>(lf64, lf);
     upload<double>(rf64, rf);
+    upload<double>(tf64, tw);
     upload<float>(colc32, colc);
 }
 
@@ -164,10 +190,12 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
 // refined precision, the FP32 correction (du).
 template <class T>
 static void solve_batch_t(const APPlan& P, Workspace& ws, const SrcDesc& src, bool src_cplx, int R, bool refine,
-                          const std::function<void(const void*, const float*)>& consume, hipStream_t st) {
+                          Band bd, const std::function<void(const void*, const float*, Band)>& consume,
+                          hipStream_t st) {
     const Fold& f = P.f;
     const int n = P.n;
-    const size_t rows = (size_t)(n + 1);
+    if (refine) bd = Band{0, n + 1};   // the FP64 residual needs every row of the AP
+    const size_t rows = (size_t)bd.nr;
     const size_t elems = (size_t)R * 2 * rows * f.W;
     ws.a.reserve(elems * sizeof(T));
     ws.b.reserve(elems * sizeof(T));
@@ -187,12 +215,12 @@ static void solve_batch_t(const APPlan& P, Workspace& ws, const SrcDesc& src, bo
     const double rows_in = (double)R * pin * rows, rows_c = (double)R * 2 * rows;
     const double tri_pts = (double)R * rows * useful;
     pr.run("fold_rhs", st, 0.0, rows_in * useful * sizeof(T),
-           [&] { launch_fold_rhs<T>(src, n, f, P.sc, R, src_cplx, A, st); });
+           [&] { launch_fold_rhs<T>(src, n, f, P.sc, R, src_cplx, bd, A, st); });
     pr.run(sizeof(T) == 8 ? "gemm_sine_f64" : "gemm_sine_f32", st, rows_in * gemm_row_flops,
            2.0 * rows_in * useful * sizeof(T), [&] { launch_gemm_bd<T>(A, Sf, B, (long)R * pin * rows, f, st); });
     pr.run(sizeof(T) == 8 ? "tridiag_f64" : "tridiag_f32", st, tri_pts * 22.0,
            tri_pts * (pin + 2) * sizeof(T) + 4.0 * rows * useful * sizeof(T),
-           [&] { launch_tridiag<T>(B, pin, A, fac, colc, n, f, R, st); });
+           [&] { launch_tridiag<T>(B, pin, A, fac, colc, n, f, R, bd, st); });
     pr.run(sizeof(T) == 8 ? "gemm_sine_f64" : "gemm_sine_f32", st, rows_c * gemm_row_flops,
            2.0 * rows_c * useful * sizeof(T), [&] { launch_gemm_bd<T>(A, Si, B, (long)R * 2 * rows, f, st); });
     const float* du = nullptr;
@@ -207,12 +235,12 @@ static void solve_batch_t(const APPlan& P, Workspace& ws, const SrcDesc& src, bo
         pr.run("gemm_sine_f32", st, rows_c * gemm_row_flops, 2.0 * rows_c * useful * sizeof(float),
                [&] { launch_gemm_bd<float>(Af, P.Sf32.as<float>(), Cb, (long)R * 2 * rows, f, st); });
         pr.run("tridiag_f32", st, tri_c * 22.0, tri_c * 4.0 * sizeof(float) + 4.0 * rows * useful * sizeof(float),
-               [&] { launch_tridiag<float>(Cb, 2, Af, P.fac32.as<float>(), P.colc32.as<float>(), n, f, R, st); });
+               [&] { launch_tridiag<float>(Cb, 2, Af, P.fac32.as<float>(), P.colc32.as<float>(), n, f, R, bd, st); });
         pr.run("gemm_sine_f32", st, rows_c * gemm_row_flops, 2.0 * rows_c * useful * sizeof(float),
                [&] { launch_gemm_bd<float>(Af, P.Si32.as<float>(), Cb, (long)R * 2 * rows, f, st); });
         du = Cb;
     }
-    consume(B, du);
+    consume(B, du, bd);
 }
 
 int chunk_size(const APPlan& P, int precision, size_t cap_bytes, int R) {
@@ -224,15 +252,15 @@ int chunk_size(const APPlan& P, int precision, size_t cap_bytes, int R) {
     return (int)std::min<size_t>(r, (size_t)R);
 }
 
-void solve_batch(const APPlan& P, Workspace& ws, int precision, const SrcDesc& src, bool src_cplx, int R,
-                 const std::function<void(const void*, const float*)>& consume, hipStream_t st) {
+void solve_batch(const APPlan& P, Workspace& ws, int precision, const SrcDesc& src, bool src_cplx, int R, Band bd,
+                 const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st) {
     if (R <= 0) return;
     if (precision == MDP_C128)
-        solve_batch_t<double>(P, ws, src, src_cplx, R, false, consume, st);
+        solve_batch_t<double>(P, ws, src, src_cplx, R, false, bd, consume, st);
     else if (precision == MDP_C64)
-        solve_batch_t<float>(P, ws, src, src_cplx, R, false, consume, st);
+        solve_batch_t<float>(P, ws, src, src_cplx, R, false, bd, consume, st);
     else if (precision == MDP_C64_REFINED)
-        solve_batch_t<float>(P, ws, src, src_cplx, R, true, consume, st);
+        solve_batch_t<float>(P, ws, src, src_cplx, R, true, bd, consume, st);
     else
         throw Error(MDP_ERR_ARG, "unknown precision");
 }

@@ -21,6 +21,8 @@ struct APPlan {
     DevBuf Sf64, Si64, Sf32, Si32;     // block-diagonal sine matrices (W x W)
     DevBuf fac64, fac32, colc64, colc32;  // tridiagonal LU factors per mode
     DevBuf lf64, rf64;    // the same l_m and r_m as interleaved complex [(n+1)][W] (fused projector sweep)
+    DevBuf tf64;          // twisted pivots tw_m [(n+1)][W] (sweep stopped at row m, zero right-hand side below)
+    std::vector<double> twist_ratio;   // per row m: smallest |1/tw_m| / row scale over all modes
     APPlan(int n, double h, double k);
 };
 
@@ -31,13 +33,12 @@ struct LSWork {
 
 // Packed interface matrix buffers (grow-only).
 struct PackedWork {
-    DevBuf dQ, dm, ds, doff, droff, dsub, dp, dgcol, dstart, dcols, dcoef, Ap, Gi, dzb;
+    DevBuf Ap, Gi;
 };
 
 // Interface assembly and reconstruction buffers (grow-only).
 struct CallWork {
-    DevBuf qsrc, qld, roff, cmap, coef, kcol, kval, koff, F, x;   // mdp_solve_interface
-    DevBuf rc_c, rc_w;                                          // mdp_reconstruct
+    DevBuf F, x;          // mdp_solve_interface
 };
 
 // Grow-only device workspaces of a context.
@@ -47,15 +48,18 @@ struct Workspace {
     LSWork ls;            // interface least squares
     PackedWork pk;        // block-sparse interface matrix
     CallWork cw;          // per-call temporaries
+    Staging stage;        // per-call descriptor uploads
     Profiler prof;        // optional per-launch timing
 };
 
 // Largest batch whose buffers fit in cap_bytes (at least 1, at most R).
 int chunk_size(const APPlan& P, int precision, size_t cap_bytes, int R);
 
-// Solve R auxiliary problems with right-hand sides described by src and hand
-// the folded result to consume(u, du) (see solve_batch_t).
-void solve_batch(const APPlan& P, Workspace& ws, int precision, const SrcDesc& src, bool src_cplx, int R,
-                 const std::function<void(const void*, const float*)>& consume, hipStream_t st);
+// Solve R auxiliary problems with right-hand sides described by src over the
+// rows of band bd (exact when the right-hand side vanishes outside it; the full
+// grid for a general one) and hand the folded result to consume(u, du, band)
+// (see solve_batch_t; the refined precision always solves the full grid).
+void solve_batch(const APPlan& P, Workspace& ws, int precision, const SrcDesc& src, bool src_cplx, int R, Band bd,
+                 const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st);
 
 }  // namespace mdp

@@ -13,6 +13,56 @@
 
 using namespace mdp;
 
+namespace {
+
+// Device buffers of released projectors, kept for the next builds so that a
+// rebuild allocates nothing (hipMalloc/hipFree stall the host and the device).
+// A kept buffer is handed out only to a later call, whose work is ordered after
+// every earlier call's work (same stream, or the wait in begin_call).
+struct BufPool {
+    int device = 0;
+    std::mutex mu;
+    std::vector<DevBuf> bufs;
+    size_t held = 0;
+    static constexpr size_t cap = (size_t)8 << 30;
+    // a kept buffer of at least `bytes` (at most twice that), else a new one
+    DevBuf take(size_t bytes) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            int best = -1;
+            for (int i = 0; i < (int)bufs.size(); ++i)
+                if (bufs[i].bytes >= bytes && bufs[i].bytes <= 2 * std::max<size_t>(bytes, 4096) &&
+                    (best < 0 || bufs[i].bytes < bufs[best].bytes))
+                    best = i;
+            if (best >= 0) {
+                DevBuf b = std::move(bufs[best]);
+                bufs.erase(bufs.begin() + best);
+                held -= b.bytes;
+                return b;
+            }
+        }
+        return DevBuf(bytes);
+    }
+    void give(DevBuf&& b) {
+        if (!b.p) return;
+        std::lock_guard<std::mutex> g(mu);
+        if (held + b.bytes > cap) {
+            (void)hipDeviceSynchronize();
+            b.release();
+            return;
+        }
+        held += b.bytes;
+        bufs.push_back(std::move(b));
+    }
+    ~BufPool() {
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize();
+        bufs.clear();
+    }
+};
+
+}  // namespace
+
 struct mdp_projector {
     std::atomic<int> refs{1};
     int device = 0;
@@ -23,15 +73,16 @@ struct mdp_projector {
     DevBuf E;      // n_gamma x 8M* real
     DevBuf gidx;   // (n+1)^2 node -> gamma index
     DevBuf meta;   // gamma nodes: gm, gq, side (int), then rho, t, side length (double)
-    std::vector<char> meta_host;  // host copy the upload reads from
     const int *gm = nullptr, *gq = nullptr, *gside = nullptr;
     const double *grho = nullptr, *gt = nullptr, *gslen = nullptr;
+    std::shared_ptr<BufPool> pool;   // where the buffers go on release
 };
 
 namespace {
 
 using PlanKey = std::tuple<int, double, double>;
 using ProjKey = std::tuple<double, double, int, double, int, int>;
+using GeomKey = std::tuple<double, double, int>;
 
 }  // namespace
 
@@ -40,6 +91,8 @@ struct mdp_ctx {
     std::string err;
     std::map<PlanKey, std::unique_ptr<APPlan>> plans;
     std::map<ProjKey, mdp_projector*> cache;
+    std::map<GeomKey, Geometry> geoms;   // grid sets and gamma per rectangle size and n (position-free)
+    std::shared_ptr<BufPool> pool = std::make_shared<BufPool>();
     Workspace ws;
     size_t ws_cap = (size_t)24 << 30;
     int projector_path = MDP_PATH_AUTO;
@@ -137,6 +190,15 @@ void prepare_ws(mdp_ctx* ctx, const APPlan& P, int precision, int R) {
 }
 
 
+// Rows m_lo-1..m_hi+1 of the M+ box: they hold gamma and N+, and a right-hand
+// side supported on M+ vanishes outside them, so the AP solve may stop there
+// (twisted pivot at the last row); the full grid if that pivot is too small.
+Band box_band(const APPlan& plan, const Geometry& G) {
+    const int t = G.m_hi + 1;
+    if (G.m_lo < 1 || t > G.n || !(plan.twist_ratio[t] > 1e-13)) return Band{0, G.n + 1};
+    return Band{G.m_lo - 1, G.m_hi - G.m_lo + 3};
+}
+
 // Q by the support-in / gamma-out route (FP64): per chunk of columns, the
 // ring RHS and the folded special rows, their sine GEMM, the fused sweep with
 // the gamma-row reductions, the inverse GEMM of the four full gamma rows and
@@ -145,7 +207,7 @@ void build_q_fused(mdp_ctx* ctx, const APPlan& plan, mdp_projector* P, hipStream
     const Geometry& G = P->g;
     const Fold& f = plan.f;
     const int n = G.n, W = f.W, ng = G.n_gamma, ncol = 8 * P->m_star;
-    const int nseg = fused_segments(n), rows_pad = nseg * FUSED_K, nb = W / 64;
+    const int nseg = fused_segments(G.m_lo, G.m_hi), rows_pad = nseg * FUSED_K, nb = W / 64;
     const size_t per_a = (size_t)nseg * 2 * W + (size_t)nb * rows_pad * 4;      // ckpt + thin
     const size_t per_b = (size_t)(n + 1) * 4 + (size_t)(4 + 4 + 8 + 8) * W;       // gc, spec, spec_hat, xs, us
     size_t chunk = ctx->ws_cap / ((per_a + per_b) * sizeof(double));
@@ -157,7 +219,6 @@ void build_q_fused(mdp_ctx* ctx, const APPlan& plan, mdp_projector* P, hipStream
         ctx->ws.b.reserve(need_b);
     }
     Profiler& pr = ctx->ws.prof;
-    const double elems_useful = (double)(n + 1) * (n - 1);
     const double gemm_row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
     const int box_rows = G.m_hi - G.m_lo + 3;
     for (int col0 = 0; col0 < ncol; col0 += (int)chunk) {
@@ -180,17 +241,16 @@ void build_q_fused(mdp_ctx* ctx, const APPlan& plan, mdp_projector* P, hipStream
                [&] { launch_fold_ring(src, n, f, plan.sc, R, gc, spec, st); });
         pr.run("gemm_sine_f64", st, 4.0 * R * gemm_row_flops, 2.0 * 4.0 * R * (n - 1) * 8.0,
                [&] { launch_gemm_bd<double>(spec, plan.Sf64.as<double>(), spec_hat, (long)R * 4, f, st); });
-        // algorithmic flops per column element: forward elimination 7, back substitution 10, ring transform 3
-        // (box rows), synthesis products and sums 8 (gamma rows)
+        // algorithmic flops per column element of the swept band (rows m_lo-1..m_hi+1): forward
+        // elimination 7, back substitution 10, synthesis products and sums 8; ring transform 3 (box rows)
         pr.run("ap_fused_f64", st,
-               (double)R * (elems_useful * 17.0 + (double)(G.m_hi - G.m_lo + 1) * (n - 1) * 3.0 +
-                            (double)box_rows * (n - 1) * 8.0),
+               (double)R * ((double)box_rows * (n - 1) * 25.0 + (double)(G.m_hi - G.m_lo + 1) * (n - 1) * 3.0),
                (double)R * ((G.m_hi - G.m_lo + 1) * 32.0 + 4.0 * (n - 1) * 8.0 + 8.0 * (n - 1) * 8.0 +
                             (double)box_rows * 4 * 8.0),
                [&] {
                    launch_proj_fused(gc, spec_hat, plan.Sf64.as<double>(), plan.Si64.as<double>(), f, G.m_lo,
                                      G.m_hi, G.q_lo, G.q_hi, plan.lf64.as<double>(), plan.rf64.as<double>(),
-                                     plan.colc64.as<double>(), ckpt, xs, thin, R, st);
+                                     plan.tf64.as<double>(), plan.colc64.as<double>(), ckpt, xs, thin, R, st);
                });
         pr.run("gemm_sine_f64", st, 8.0 * R * gemm_row_flops, 2.0 * 8.0 * R * (n - 1) * 8.0,
                [&] { launch_gemm_bd<double>(xs, plan.Si64.as<double>(), us, (long)R * 8, f, st); });
@@ -269,49 +329,49 @@ int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int p
             return MDP_OK;
         }
         hipStream_t st = (hipStream_t)stream;
-        Geometry g = make_geometry(sd->x0, sd->y0, sd->lx, sd->ly, sd->n);
+        // the grid sets relative to the rectangle depend on its size and n only
+        GeomKey gk{sd->lx, sd->ly, sd->n};
+        auto git = ctx->geoms.find(gk);
+        if (git == ctx->geoms.end())
+            git = ctx->geoms.emplace(gk, make_geometry(sd->x0, sd->y0, sd->lx, sd->ly, sd->n)).first;
+        Geometry g = git->second;
         APPlan& plan = get_plan(ctx, g.n, g.h, sd->k);
         std::unique_ptr<mdp_projector> P(new mdp_projector);
         P->device = ctx->device;
         P->k = sd->k;
         P->m_star = m_star;
         P->precision = precision;
+        P->pool = ctx->pool;
+        BufPool& pool = *ctx->pool;
         const int ng = g.n_gamma, ncol = 8 * m_star;
         begin_call(ctx, st);
         // gamma node lists in one upload; E and the node -> gamma map are built on the device
-        const size_t ints = ((3 * (size_t)ng + 1) / 2) * 2, meta_bytes = ints * sizeof(int) + 3 * (size_t)ng * sizeof(double);
-        P->meta_host.assign(meta_bytes, 0);
-        int* hi = reinterpret_cast<int*>(P->meta_host.data());
-        double* hd = reinterpret_cast<double*>(hi + ints);
-        std::copy(g.gm.begin(), g.gm.end(), hi);
-        std::copy(g.gq.begin(), g.gq.end(), hi + ng);
-        std::copy(g.side.begin(), g.side.end(), hi + 2 * ng);
-        std::copy(g.rho.begin(), g.rho.end(), hd);
-        std::copy(g.t.begin(), g.t.end(), hd + ng);
-        std::copy(g.slen.begin(), g.slen.end(), hd + 2 * ng);
-        P->meta.alloc(meta_bytes);
-        MDP_HIP(hipMemcpyAsync(P->meta.p, P->meta_host.data(), meta_bytes, hipMemcpyHostToDevice, st));
-        const int* di = P->meta.as<int>();
-        const double* dd = reinterpret_cast<const double*>(di + ints);
-        P->gm = di;
-        P->gq = di + ng;
-        P->gside = di + 2 * ng;
-        P->grho = dd;
-        P->gt = dd + ng;
-        P->gslen = dd + 2 * ng;
-        P->E.alloc((size_t)ng * ncol * sizeof(double));
+        HostBlob blob;
+        const size_t o_gm = blob.put(g.gm), o_gq = blob.put(g.gq), o_side = blob.put(g.side),
+                     o_rho = blob.put(g.rho), o_t = blob.put(g.t), o_slen = blob.put(g.slen);
+        P->meta = pool.take(blob.size());
+        ctx->ws.stage.copy(P->meta.p, blob, st);
+        const char* mb = P->meta.as<char>();
+        P->gm = reinterpret_cast<const int*>(mb + o_gm);
+        P->gq = reinterpret_cast<const int*>(mb + o_gq);
+        P->gside = reinterpret_cast<const int*>(mb + o_side);
+        P->grho = reinterpret_cast<const double*>(mb + o_rho);
+        P->gt = reinterpret_cast<const double*>(mb + o_t);
+        P->gslen = reinterpret_cast<const double*>(mb + o_slen);
+        P->E = pool.take((size_t)ng * ncol * sizeof(double));
         MDP_HIP(hipMemsetAsync(P->E.p, 0, (size_t)ng * ncol * sizeof(double), st));
         launch_extension(P->gside, P->grho, P->gt, P->gslen, ng, sd->k, m_star, P->E.as<double>(), st);
         const size_t nodes = (size_t)(g.n + 1) * (g.n + 1);
-        P->gidx.alloc(nodes * sizeof(int));
+        P->gidx = pool.take(nodes * sizeof(int));
         MDP_HIP(hipMemsetAsync(P->gidx.p, 0xff, nodes * sizeof(int), st));   // -1 everywhere
         launch_gamma_index(P->gm, P->gq, ng, g.n, P->gidx.as<int>(), st);
-        P->Q.alloc((size_t)ng * ncol * 2 * sizeof(double));
+        P->Q = pool.take((size_t)ng * ncol * 2 * sizeof(double));
         P->g = std::move(g);
         const Geometry& G = P->g;
 
         if (precision == MDP_C128 && ctx->projector_path == MDP_PATH_AUTO &&
-            fused_projector_supported(plan.f, G.m_lo, G.m_hi, G.q_lo, G.q_hi)) {
+            fused_projector_supported(plan.f, G.m_lo, G.m_hi, G.q_lo, G.q_hi) &&
+            plan.twist_ratio[G.m_hi + 1] > 1e-13) {
             build_q_fused(ctx, plan, P.get(), st);
             end_call(ctx, st);
             mdp_projector* raw = P.release();
@@ -336,15 +396,15 @@ int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int p
             const int* gqd = P->gq;
             const int n = G.n;
             const Fold f = plan.f;
-            solve_batch(plan, ctx->ws, precision, src, false, R,
-                        [&](const void* u, const float* du) {
+            solve_batch(plan, ctx->ws, precision, src, false, R, box_band(plan, G),
+                        [&](const void* u, const float* du, Band bd) {
                             ctx->ws.prof.run("gather_q", st, 0.0, (double)ng * R * 16.0 * 2.0, [&] {
                                 if (precision == MDP_C128)
-                                    launch_gather_q<double>((const double*)u, du, n, f, gmd, gqd, ng, R, Qd, ng, col0,
-                                                            st);
+                                    launch_gather_q<double>((const double*)u, du, n, f, bd, gmd, gqd, ng, R, Qd, ng,
+                                                            col0, st);
                                 else
-                                    launch_gather_q<float>((const float*)u, du, n, f, gmd, gqd, ng, R, Qd, ng, col0,
-                                                           st);
+                                    launch_gather_q<float>((const float*)u, du, n, f, bd, gmd, gqd, ng, R, Qd, ng,
+                                                           col0, st);
                             });
                         },
                         st);
@@ -370,7 +430,11 @@ void mdp_projector_release(mdp_projector* P) {
     if (!P) return;
     if (P->refs.fetch_sub(1) == 1) {
         (void)hipSetDevice(P->device);
-        (void)hipDeviceSynchronize();
+        // the buffers go back to the context's pool (freed with it)
+        P->pool->give(std::move(P->Q));
+        P->pool->give(std::move(P->E));
+        P->pool->give(std::move(P->gidx));
+        P->pool->give(std::move(P->meta));
         delete P;
     }
 }
@@ -485,25 +549,47 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             }
             koff[i + 1] = (int)kcol.size();
         }
-        begin_call(ctx, st);
+        // the full coefficient vectors from the unknowns: c[e] = known[e] + coef[e] x[src[e]]
+        const int nce = n_sub * 8 * M;
+        std::vector<int> esrc(nce, -1);
+        std::vector<double2> ecoef(nce, double2{0.0, 0.0}), eknown(nce, double2{0.0, 0.0});
+        auto E = [&](int i, int kind, int s, int j) { return (size_t)i * 8 * M + kind * 4 * M + s * M + j; };
+        for (size_t b = 0; b < blocks.size(); ++b) {
+            const Block& B = blocks[b];
+            for (int j = 0; j < M; ++j) {
+                if (B.type == 2) {
+                    const size_t e = E(B.c[0].sub, 0, B.c[0].side, j);
+                    esrc[e] = (int)(b * M + j);
+                    ecoef[e] = double2{1.0, 0.0};
+                    continue;
+                }
+                for (const Contrib& ct : B.c) {
+                    const size_t e = E(ct.sub, ct.kind, ct.side, j);
+                    esrc[e] = (int)(b * M + j);
+                    ecoef[e] = ct.coef;
+                }
+            }
+        }
+        for (int i = 0; i < n_sub; ++i)
+            for (int s = 0; s < 4; ++s) {
+                const mdp_side& sd_ = sides[4 * i + s];
+                if (sd_.kind != 0) continue;
+                const double a = sd_.alpha, b = sd_.beta;
+                for (int j = 0; j < M; ++j) {
+                    const double2 d{sd_.d[j].re, sd_.d[j].im};
+                    if (b == 0.0) eknown[E(i, 0, s, j)] = double2{d.x / a, d.y / a};
+                    else if (a == 0.0) eknown[E(i, 1, s, j)] = double2{d.x / b, d.y / b};
+                    else {   // c1 = d/beta - (alpha/beta) c0
+                        const size_t e = E(i, 1, s, j);
+                        esrc[e] = esrc[E(i, 0, s, j)];
+                        ecoef[e] = double2{-a / b, 0.0};
+                        eknown[e] = double2{d.x / b, d.y / b};
+                    }
+                }
+            }
         std::vector<const double2*> qsrc(n_sub);
         std::vector<int> qld(n_sub);
         for (int i = 0; i < n_sub; ++i) { qsrc[i] = P[i]->Q.as<const double2>(); qld[i] = P[i]->g.n_gamma; }
-        CallWork& cw = ctx->ws.cw;
-        DevBuf &d_qsrc = cw.qsrc, &d_qld = cw.qld, &d_roff = cw.roff, &d_cmap = cw.cmap, &d_coef = cw.coef,
-               &d_kcol = cw.kcol, &d_kval = cw.kval, &d_koff = cw.koff, &F = cw.F, &x = cw.x;
-        upload_ws(d_qsrc, qsrc, st);
-        upload_ws(d_qld, qld, st);
-        upload_ws(d_roff, row_off, st);
-        upload_ws(d_cmap, colmap, st);
-        upload_ws(d_coef, coefs, st);
-        upload_ws(d_kcol, kcol, st);
-        upload_ws(d_kval, kval, st);
-        upload_ws(d_koff, koff, st);
-        ensure(F, (size_t)m * sizeof(double2));
-        ensure(x, (size_t)ncol * sizeof(double2));
-        launch_known_rhs(d_qsrc.as<const double2* const>(), d_qld.as<int>(), n_sub, d_roff.as<int>(), m,
-                         d_kcol.as<int>(), d_kval.as<double2>(), d_koff.as<int>(), F.as<double2>(), st);
         // block-sparse description: subdomain i's rows touch only the unknown blocks with a contribution from i
         PackedHost ph;
         ph.n_sub = n_sub;
@@ -545,6 +631,26 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             off += (long)qld[i] * si;
         }
         ph.total_pc = (int)ph.pc_sub.size();
+
+        begin_call(ctx, st);
+        CallWork& cw = ctx->ws.cw;
+        DevBuf &F = cw.F, &x = cw.x;
+        ensure(F, (size_t)m * sizeof(double2));
+        ensure(x, (size_t)ncol * sizeof(double2));
+        // every table of the call in one upload
+        HostBlob blob;
+        const size_t o_qsrc = blob.put(qsrc), o_qld = blob.put(qld), o_roff = blob.put(row_off),
+                     o_cmap = blob.put(colmap), o_coef = blob.put(coefs), o_kcol = blob.put(kcol),
+                     o_kval = blob.put(kval), o_koff = blob.put(koff), o_esrc = blob.put(esrc),
+                     o_ecoef = blob.put(ecoef), o_eknown = blob.put(eknown);
+        const PackedTables tabs = ls_packed_tables(ctx->ws, ph, blob);
+        const char* img = ctx->ws.stage.upload(blob, st);
+        auto dq = reinterpret_cast<const double2* const*>(img + o_qsrc);
+        auto dld = reinterpret_cast<const int*>(img + o_qld);
+        auto droff = reinterpret_cast<const int*>(img + o_roff);
+        launch_known_rhs(dq, dld, n_sub, droff, m, reinterpret_cast<const int*>(img + o_kcol),
+                         reinterpret_cast<const double2*>(img + o_kval), reinterpret_cast<const int*>(img + o_koff),
+                         F.as<double2>(), st);
         LSResult r;
         {
             // the whole least-squares solve as one profiled span (it synchronises internally)
@@ -555,13 +661,13 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             // algorithmic work of the least squares: a Householder QR of the m x ncol matrix
             const double qr_flops = 8.0 * ((double)m * ncol * ncol - (double)ncol * ncol * ncol / 3.0);
             bool fallback = false;
-            r = ls_solve_packed(ctx->ws, ph, F.as<double2>(), x.as<double2>(), cond_estimate_out != nullptr, st,
-                                &fallback);
+            r = ls_solve_packed(ctx->ws, ph, img, tabs, F.as<double2>(), x.as<double2>(), cond_estimate_out != nullptr,
+                                st, &fallback);
             if (fallback) {
                 // dense Cholesky-QR passes on the assembled matrix
                 DevBuf Qbar((size_t)m * ncol * sizeof(double2));
-                launch_assemble_qbar(d_qsrc.as<const double2* const>(), d_qld.as<int>(), n_sub, d_roff.as<int>(), m,
-                                     d_cmap.as<int4>(), d_coef.as<double2>(), ncol, Qbar.as<double2>(), m, st);
+                launch_assemble_qbar(dq, dld, n_sub, droff, m, reinterpret_cast<const int4*>(img + o_cmap),
+                                     reinterpret_cast<const double2*>(img + o_coef), ncol, Qbar.as<double2>(), m, st);
                 r = ls_solve(ctx->ws, Qbar.as<double2>(), F.as<double2>(), m, ncol, x.as<double2>(),
                              cond_estimate_out != nullptr, st);
                 MDP_HIP(hipStreamSynchronize(st));
@@ -571,40 +677,11 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
                 pr.recs.push_back({"interface_ls", a, b, qr_flops, (double)m * ncol * 16.0});
             }
         }
-        // expand the unknowns to the full coefficient vectors (column order of Q)
-        std::vector<double2> hx(ncol);
-        MDP_HIP(hipMemcpyAsync(hx.data(), x.p, ncol * sizeof(double2), hipMemcpyDeviceToHost, st));
-        MDP_HIP(hipStreamSynchronize(st));
-        std::vector<double2> c((size_t)n_sub * 8 * M, double2{0.0, 0.0});
-        auto C = [&](int i, int kind, int s, int j) -> double2& { return c[(size_t)i * 8 * M + kind * 4 * M + s * M + j]; };
-        for (size_t b = 0; b < blocks.size(); ++b) {
-            const Block& B = blocks[b];
-            for (int j = 0; j < M; ++j) {
-                double2 v = hx[b * M + j];
-                if (B.type == 2) { C(B.c[0].sub, 0, B.c[0].side, j) = v; continue; }
-                for (const Contrib& ct : B.c) {
-                    double2 w = ct.coef;
-                    C(ct.sub, ct.kind, ct.side, j) = double2{w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x};
-                }
-            }
-        }
-        for (int i = 0; i < n_sub; ++i)
-            for (int s = 0; s < 4; ++s) {
-                const mdp_side& sd_ = sides[4 * i + s];
-                if (sd_.kind != 0) continue;
-                const double a = sd_.alpha, b = sd_.beta;
-                for (int j = 0; j < M; ++j) {
-                    double2 d{sd_.d[j].re, sd_.d[j].im};
-                    if (b == 0.0) C(i, 0, s, j) = double2{d.x / a, d.y / a};
-                    else if (a == 0.0) C(i, 1, s, j) = double2{d.x / b, d.y / b};
-                    else {
-                        double2 c0 = C(i, 0, s, j);
-                        C(i, 1, s, j) = double2{d.x / b - (a / b) * c0.x, d.y / b - (a / b) * c0.y};
-                    }
-                }
-            }
-        MDP_HIP(hipMemcpyAsync(c_out, c.data(), c.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-        MDP_HIP(hipStreamSynchronize(st));
+        // known and solved coefficients into the caller's vector (column order of Q), on the stream
+        launch_expand_coeffs(nce, reinterpret_cast<const int*>(img + o_esrc),
+                             reinterpret_cast<const double2*>(img + o_ecoef),
+                             reinterpret_cast<const double2*>(img + o_eknown), x.as<double2>(),
+                             reinterpret_cast<double2*>(c_out), st);
         end_call(ctx, st);
         if (rel_residual_out) *rel_residual_out = r.rel_residual;
         if (cond_estimate_out) *cond_estimate_out = r.cond;
@@ -624,57 +701,66 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
             if (!P[i]) throw Error(MDP_ERR_ARG, "null projector");
             off[i + 1] = off[i] + (long)(P[i]->g.n + 1) * (P[i]->g.n + 1);
         }
-        begin_call(ctx, st);
         // group subdomains by projector: one batched solve per distinct projector
+        std::vector<std::vector<int>> groups;
         std::vector<bool> done(n_sub, false);
         for (int i = 0; i < n_sub; ++i) {
             if (done[i]) continue;
-            const mdp_projector* Pi = P[i];
             std::vector<int> grp;
             for (int j = i; j < n_sub; ++j)
-                if (P[j] == Pi) { grp.push_back(j); done[j] = true; }
+                if (P[j] == P[i]) { grp.push_back(j); done[j] = true; }
+            groups.push_back(std::move(grp));
+        }
+        // per batch entry: the subdomain (its coefficients in c) and its grid's offset in u_out
+        std::vector<int> cidx;
+        std::vector<long> goff;
+        for (const auto& grp : groups)
+            for (int i : grp) { cidx.push_back(i); goff.push_back(off[i]); }
+        begin_call(ctx, st);
+        HostBlob blob;
+        const size_t o_cidx = blob.put(cidx), o_goff = blob.put(goff);
+        const char* img = ctx->ws.stage.upload(blob, st);
+        // u_out holds the density w (zero off gamma), then u = w - G(L w |M+) in place
+        MDP_HIP(hipMemsetAsync(u_out, 0, (size_t)off[n_sub] * sizeof(mdp_c128), st));
+        double* uo = reinterpret_cast<double*>(u_out);
+        size_t e0 = 0;
+        for (const auto& grp : groups) {
+            const mdp_projector* Pi = P[grp[0]];
             const Geometry& G = Pi->g;
             const int n = G.n, ng = G.n_gamma, ncol = 8 * Pi->m_star, R = (int)grp.size();
-            const long npts = (long)(n + 1) * (n + 1);
             APPlan& plan = get_plan(ctx, n, G.h, Pi->k);
-            DevBuf& cb = ctx->ws.cw.rc_c;
-            DevBuf& wb = ctx->ws.cw.rc_w;
-            ensure(cb, (size_t)R * ncol * sizeof(mdp_c128));
-            ensure(wb, (size_t)R * npts * sizeof(mdp_c128));
-            for (int r = 0; r < R; ++r)
-                MDP_HIP(hipMemcpyAsync(cb.as<mdp_c128>() + (size_t)r * ncol, c + (size_t)grp[r] * ncol,
-                                       ncol * sizeof(mdp_c128), hipMemcpyDeviceToDevice, st));
-            MDP_HIP(hipMemsetAsync(wb.p, 0, (size_t)R * npts * sizeof(mdp_c128), st));
-            launch_extend_density(Pi->E.as<double>(), ng, ncol, cb.as<double>(), R, Pi->gm, Pi->gq, Pi->gside, n,
-                                  wb.as<double>(), npts, st);
+            const int* ci = reinterpret_cast<const int*>(img + o_cidx) + e0;
+            const long* go = reinterpret_cast<const long*>(img + o_goff) + e0;
+            launch_extend_density(Pi->E.as<double>(), ng, ncol, reinterpret_cast<const double*>(c), ci, R, Pi->gm,
+                                  Pi->gq, Pi->gside, n, uo, 0, go, st);
             const int chunk = chunk_size(plan, Pi->precision, ctx->ws_cap, R);
             prepare_ws(ctx, plan, Pi->precision, chunk);
             for (int r0 = 0; r0 < R; r0 += chunk) {
                 const int Rc = std::min(chunk, R - r0);
                 SrcDesc src{};
                 src.kind = Src::STENCIL_GRID;
-                src.grid = wb.as<double>() + 2 * (size_t)r0 * npts;
-                src.grid_stride = npts;
+                src.grid = uo;
+                src.goff = go + r0;
                 src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
-                double* w = wb.as<double>() + 2 * (size_t)r0 * npts;
                 const Fold f = plan.f;
                 const int prec = Pi->precision;
-                solve_batch(plan, ctx->ws, prec, src, true, Rc,
-                            [&](const void* u, const float* du) {
-                                // u_out = w - G(L w |M+), written in place over w
-                                ctx->ws.prof.run("unfold_grid", st, 0.0, (double)Rc * npts * 16.0 * 3.0, [&] {
+                const Band rows = box_band(plan, G);
+                solve_batch(plan, ctx->ws, prec, src, true, Rc, rows,
+                            [&](const void* u, const float* du, Band bd) {
+                                // u_out = w - G(L w |M+) on the band, in place (zero on the other rows)
+                                ctx->ws.prof.run("unfold_grid", st, 0.0, (double)Rc * rows.nr * (n + 1) * 16.0 * 3.0,
+                                                 [&] {
                                     if (prec == MDP_C128)
-                                        launch_unfold_grid<double>((const double*)u, du, n, f, Rc, w, npts, w, npts,
-                                                                   st);
+                                        launch_unfold_grid<double>((const double*)u, du, n, f, bd, rows, Rc, uo, 0, uo,
+                                                                   0, go + r0, st);
                                     else
-                                        launch_unfold_grid<float>((const float*)u, du, n, f, Rc, w, npts, w, npts, st);
+                                        launch_unfold_grid<float>((const float*)u, du, n, f, bd, rows, Rc, uo, 0, uo, 0,
+                                                                  go + r0, st);
                                 });
                             },
                             st);
             }
-            for (int r = 0; r < R; ++r)
-                MDP_HIP(hipMemcpyAsync(u_out + off[grp[r]], wb.as<mdp_c128>() + (size_t)r * npts,
-                                       npts * sizeof(mdp_c128), hipMemcpyDeviceToDevice, st));
+            e0 += grp.size();
         }
         end_call(ctx, st);
         return MDP_OK;
@@ -704,12 +790,15 @@ int mdp_ap_solve(mdp_ctx* ctx, int n, double h, double k, int precision, int bat
             src.grid_stride = npts;
             double* out = reinterpret_cast<double*>(u) + 2 * (size_t)b0 * npts;
             const Fold f = plan.f;
-            solve_batch(plan, ctx->ws, precision, src, true, R,
-                        [&](const void* uu, const float* du) {
+            const Band all{0, n + 1};
+            solve_batch(plan, ctx->ws, precision, src, true, R, all,
+                        [&](const void* uu, const float* du, Band bd) {
                             if (precision == MDP_C128)
-                                launch_unfold_grid<double>((const double*)uu, du, n, f, R, nullptr, 0, out, npts, st);
+                                launch_unfold_grid<double>((const double*)uu, du, n, f, bd, all, R, nullptr, 0, out,
+                                                           npts, nullptr, st);
                             else
-                                launch_unfold_grid<float>((const float*)uu, du, n, f, R, nullptr, 0, out, npts, st);
+                                launch_unfold_grid<float>((const float*)uu, du, n, f, bd, all, R, nullptr, 0, out,
+                                                          npts, nullptr, st);
                         },
                         st);
         }

@@ -289,7 +289,8 @@ __device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double
     int bad = 0;
     for (int sb = 0; sb < 4; ++sb) {
         const int b0 = 16 * sb;
-        // ---- F: 16x16 diagonal block by wavefront 0
+        // ---- F: 16x16 diagonal block by wavefront 0 (steps unrolled: the lanes that publish
+        // column k and row k of X are known at compile time up to the lane index)
         if (wave == 0) {
             double mr[4], mi[4];
 #pragma unroll
@@ -299,58 +300,58 @@ __device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double
                 mr[q] = v.x;
                 mi[q] = v.y;
             }
-            for (int k4 = 0; k4 < 4; ++k4) {
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int k = 4 * k4 + kk;
-                    if (g == k4) {            // column k of the block (all rows; only rows > k are used)
-                        s.Ls[k][r] = make_double2(mr[kk], mi[kk]);
-                        if (r == k) s.piv[k] = mr[kk];
-                    }
-                    // the pivot straight from its lane (row k, column group k4)
-                    const int pl = k + 16 * k4;
-                    const double dk = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mr[kk]), pl),
-                                                       __builtin_amdgcn_readlane(__double2loint(mr[kk]), pl));
-                    if (r == k) {             // row k of X (columns < k are used)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) s.Xr[k][4 * g + q] = make_double2(mr[q], mi[q]);
-                    }
-                    double d = dk;
-                    if (!(d > 0.0)) {
-                        if (!bad) bad = b0 + k + 1;
-                        d = 1.0;
-                    }
-                    const double dinv = recip1(d);
-                    wave_sync();
-                    const double2 cl = s.Ls[k][r];
-                    const bool live = r > k;
-                    const double lr = live ? cl.x * dinv : 0.0, li = live ? cl.y * dinv : 0.0;
-                    // v_j: both candidates loaded, then selected (no divergent branches)
-                    double2 cs[4], xs[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        cs[q] = s.Ls[k][4 * g + q];
-                        xs[q] = s.Xr[k][4 * g + q];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int j = 4 * g + q;
-                        const double vx = (j > k) ? cs[q].x : ((j < k) ? xs[q].x : d + 1.0);
-                        const double vy = (j > k) ? -cs[q].y : ((j < k) ? xs[q].y : 0.0);
-                        mr[q] = fma(-lr, vx, fma(li, vy, mr[q]));
-                        mi[q] = fma(-lr, vy, fma(-li, vx, mi[q]));
+            for (int k = 0; k < 16; ++k) {
+                const int kk = k & 3, k4 = k >> 2, pl = k + 16 * k4;
+                const double ckr = mr[kk], cki = mi[kk];
+                // Ls[k][r] = column k; Xr[k][j] = v_j (conj of column k below the pivot, d_k + 1
+                // at the pivot, row k of X left of it)
+                if (g == k4) {
+                    s.Ls[k][r] = make_double2(ckr, cki);
+                    const double dv = unit_if_bad(ckr);
+                    if (r > k) s.Xr[k][r] = make_double2(ckr, -cki);
+                    if (r == k) {
+                        s.Xr[k][k] = make_double2(dv + 1.0, 0.0);
+                        s.piv[k] = dv;
                     }
                 }
+                if (r == k) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (4 * g + q < k) s.Xr[k][4 * g + q] = make_double2(mr[q], mi[q]);
+                }
+                // the pivot straight from its lane (row k, column group k4)
+                const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ckr), pl),
+                                                  __builtin_amdgcn_readlane(__double2loint(ckr), pl));
+                const bool ok = d > 0.0;
+                bad = (bad == 0 && !ok) ? b0 + k + 1 : bad;
+                const double dd = ok ? d : 1.0;
+                // 1/d_k = r0 (1 + e) to full precision (one Newton step on the estimate r0)
+                const double r0 = __builtin_amdgcn_rcp(dd);
+                const double e = fma(-dd, r0, 1.0);
+                wave_sync();
+                const double2 cl = s.Ls[k][r];
+                double2 w[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w[q] = s.Xr[k][4 * g + q];
+                const double tr = cl.x * r0, ti = cl.y * r0;
+                const bool live = r > k;
+                const double lr = live ? fma(tr, e, tr) : 0.0, li = live ? fma(ti, e, ti) : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    mr[q] = fma(-lr, w[q].x, fma(li, w[q].y, mr[q]));
+                    mi[q] = fma(-lr, w[q].y, fma(-li, w[q].x, mi[q]));
+                }
             }
+            wave_sync();
             // L_ss into S, L_ss^{-1} into Z (lower parts; upper part of the Z block stays zero)
             const double pr = s.piv[r];
-            const double sdr = sqrt(pr > 0.0 ? pr : 1.0), rdr = recip(sdr);
+            const double sdr = sqrt(pr), rdr = recip(sdr);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int c = 4 * g + q;
                 if (c < r) {
-                    const double pc = s.piv[c];
-                    const double sc = recip(sqrt(pc > 0.0 ? pc : 1.0));
+                    const double sc = recip(sqrt(s.piv[c]));
                     const double2 lv = s.Ls[c][r];
                     s.S[b0 + r][b0 + c] = make_double2(lv.x * sc, lv.y * sc);
                     s.Z[b0 + r][b0 + c] = make_double2(mr[q] * rdr, mi[q] * rdr);
@@ -986,6 +987,23 @@ __global__ void known_rhs_kernel(const double2* const* __restrict__ Qsrc, const 
     if (r < total_rows && part == 0) F[r] = make_double2(-sr, -si);
 }
 
+// Full coefficient vectors from the least-squares unknowns:
+// c[e] = known[e] + coef[e] x[src[e]] (src[e] < 0: known value only).
+__global__ void expand_coeffs_kernel(int n, const int* __restrict__ src, const double2* __restrict__ coef,
+                                     const double2* __restrict__ known, const double2* __restrict__ x,
+                                     double2* __restrict__ c) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double2 v = known[e];
+    const int s = src[e];
+    if (s >= 0) {
+        const double2 w = coef[e], u = x[s];
+        v.x += w.x * u.x - w.y * u.y;
+        v.y += w.x * u.y + w.y * u.x;
+    }
+    c[e] = v;
+}
+
 __global__ void col_norms_kernel(const double2* __restrict__ A, int m, int lda, double* __restrict__ out) {
     const int c = blockIdx.x;
     __shared__ double red[256];
@@ -1117,6 +1135,13 @@ void launch_known_rhs(const double2* const* Qsrc, const int* qld, int n_sub, con
     if (total_rows <= 0) return;
     hipLaunchKernelGGL(known_rhs_kernel, dim3(blocks), dim3(256), 0, st, Qsrc, qld, n_sub, row_off, kcol, kval, koff,
                        F);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_expand_coeffs(int n, const int* src, const double2* coef, const double2* known, const double2* x,
+                          double2* c, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(expand_coeffs_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, src, coef, known, x, c);
     MDP_HIP(hipGetLastError());
 }
 

@@ -223,13 +223,6 @@ LSResult ls_solve(Workspace& ws, double2* A, const double2* F, int m, int nc, do
 // does not contract.
 namespace {
 
-template <class T>
-void upload_async(DevBuf& d, const std::vector<T>& v, hipStream_t st) {
-    const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
-    grow(d, bytes);
-    if (!v.empty()) MDP_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
-}
-
 struct PackedFlags {
     int info;
     int badcol;
@@ -239,27 +232,11 @@ struct PackedFlags {
 
 }  // namespace
 
-LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, double2* x_out, bool want_cond,
-                         hipStream_t st, bool* fallback) {
-    LSResult res{};
-    *fallback = false;
+PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob) {
     PackedWork& w = ws.pk;
-    const int nc = h.nc, n_sub = h.n_sub, npc = h.total_pc;
+    const int nc = h.nc, n_sub = h.n_sub;
     long mtot = 0, ptot = 0;
     for (int i = 0; i < n_sub; ++i) { mtot += h.m[i]; ptot += (long)h.m[i] * h.s[i]; }
-    // descriptors (tiny; the copies are ordered on the stream before the kernels)
-    std::vector<const double2*> q(h.Q);
-    upload_async(w.dQ, q, st);
-    upload_async(w.dm, h.m, st);
-    upload_async(w.ds, h.s, st);
-    upload_async(w.doff, h.off, st);
-    upload_async(w.droff, h.roff, st);
-    upload_async(w.dsub, h.pc_sub, st);
-    upload_async(w.dp, h.pc_p, st);
-    upload_async(w.dgcol, h.pc_gcol, st);
-    upload_async(w.dstart, h.pc_start, st);
-    upload_async(w.dcols, h.pc_cols, st);
-    upload_async(w.dcoef, h.pc_coef, st);
     grow(w.Ap, (size_t)ptot * sizeof(double2));
     grow(w.Gi, (size_t)h.max_s * h.max_s * sizeof(double2));
     LSWork& lw = ws.ls;
@@ -270,17 +247,65 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
     grow(lw.T, nn * sizeof(double2));
     grow(lw.vec, (size_t)(6 * nc + 2 * mtot) * sizeof(double2));
     grow(lw.norms, 2 * (size_t)nc * sizeof(double));
-    grow(lw.flags, sizeof(PackedFlags));
-    PackedDevice d{w.dQ.as<const double2* const>(), w.dm.as<int>(), w.doff.as<long>(), w.ds.as<int>(),
-                   w.dsub.as<int>(), w.dp.as<int>(), w.dgcol.as<int>(), w.dcols.as<int4>(), w.dcoef.as<double2>(),
-                   w.droff.as<long>(), w.dstart.as<int>()};
+    grow(lw.flags, 64);
+    PackedTables t{};
+    t.Q = blob.put(h.Q);
+    t.m = blob.put(h.m);
+    t.s = blob.put(h.s);
+    t.off = blob.put(h.off);
+    t.roff = blob.put(h.roff);
+    t.sub = blob.put(h.pc_sub);
+    t.p = blob.put(h.pc_p);
+    t.gcol = blob.put(h.pc_gcol);
+    t.start = blob.put(h.pc_start);
+    t.cols = blob.put(h.pc_cols);
+    t.coef = blob.put(h.pc_coef);
+    // all subdomains' A_i^* A_i in one split-K launch (reduced and scattered in a second)
+    int max_m = 0, tiles = 0;
+    for (int i = 0; i < n_sub; ++i) {
+        max_m = std::max(max_m, h.m[i]);
+        tiles += ((h.s[i] + 31) / 32) * ((h.s[i] + 31) / 32);
+    }
+    const int nsplit = std::max(1, std::min(std::min(2048 / std::max(tiles, 1), std::max(1, max_m / 128)), 64));
+    std::vector<ZBatch> zb(n_sub);
+    double2* Ap = w.Ap.as<double2>();
+    long poff = 0;
+    for (int i = 0; i < n_sub; ++i) {
+        int kchunk = (h.m[i] + nsplit - 1) / nsplit;
+        kchunk = std::max(16, (kchunk + 15) / 16 * 16);
+        zb[i] = ZBatch{Ap + h.off[i], h.s[i], h.m[i], kchunk, h.pc_start[i], poff};
+        poff += (long)nsplit * h.s[i] * h.s[i];
+    }
+    grow(ws.zg, (size_t)std::max(poff, 1L) * sizeof(double2));
+    t.zb = blob.put(zb);
+    t.nsplit = nsplit;
+    return t;
+}
+
+LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, const PackedTables& tb,
+                         const double2* F, double2* x_out, bool want_cond, hipStream_t st, bool* fallback) {
+    LSResult res{};
+    *fallback = false;
+    PackedWork& w = ws.pk;
+    const int nc = h.nc, n_sub = h.n_sub, npc = h.total_pc;
+    long mtot = 0;
+    for (int i = 0; i < n_sub; ++i) mtot += h.m[i];
+    LSWork& lw = ws.ls;
+    const size_t nn = (size_t)nc * nc;
+    auto at = [&](size_t off) { return image + off; };
+    PackedDevice d{reinterpret_cast<const double2* const*>(at(tb.Q)), reinterpret_cast<const int*>(at(tb.m)),
+                   reinterpret_cast<const long*>(at(tb.off)), reinterpret_cast<const int*>(at(tb.s)),
+                   reinterpret_cast<const int*>(at(tb.sub)), reinterpret_cast<const int*>(at(tb.p)),
+                   reinterpret_cast<const int*>(at(tb.gcol)), reinterpret_cast<const int4*>(at(tb.cols)),
+                   reinterpret_cast<const double2*>(at(tb.coef)), reinterpret_cast<const long*>(at(tb.roff)),
+                   reinterpret_cast<const int*>(at(tb.start))};
     double2* Ap = w.Ap.as<double2>();
     double* norms2 = lw.norms.as<double>();
     double* norms = norms2 + nc;
     double2* y = lw.vec.as<double2>();
     double2* t = y + nc;
-    double2* x = t + nc;
-    double2* dx = x + nc;
+    double2* x = x_out;   // the solution is refined in place
+    double2* dx = t + 2 * nc;
     double2* v1 = dx + nc;
     double2* v2 = v1 + nc;
     double2* r = v2 + nc;
@@ -298,32 +323,17 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
     launch_packed_scale(d, npc, h.max_m, Ap, norms, st);
     // Gram matrix
     MDP_HIP(hipMemsetAsync(G, 0, nn * sizeof(double2), st));
-    std::vector<ZBatch> zb(n_sub);   // descriptors; alive until the stream is synchronised below
     {
-        // all subdomains' A_i^* A_i in one split-K launch, reduced and scattered in a second
-        int max_m = 0, tiles = 0;
-        for (int i = 0; i < n_sub; ++i) {
-            max_m = std::max(max_m, h.m[i]);
-            tiles += ((h.s[i] + 31) / 32) * ((h.s[i] + 31) / 32);
-        }
-        int nsplit = std::max(1, std::min(std::min(2048 / std::max(tiles, 1), std::max(1, max_m / 128)), 64));
-        long poff = 0;
-        for (int i = 0; i < n_sub; ++i) {
-            int kchunk = (h.m[i] + nsplit - 1) / nsplit;
-            kchunk = std::max(16, (kchunk + 15) / 16 * 16);
-            zb[i] = ZBatch{Ap + h.off[i], h.s[i], h.m[i], kchunk, h.pc_start[i], poff};
-            poff += (long)nsplit * h.s[i] * h.s[i];
-        }
-        upload_async(w.dzb, zb, st);
-        grow(ws.zg, (size_t)std::max(poff, 1L) * sizeof(double2));
+        int max_m = 0;
         double gram_flops = 0.0, gram_bytes = 0.0;
         for (int i = 0; i < n_sub; ++i) {
+            max_m = std::max(max_m, h.m[i]);
             gram_flops += 4.0 * h.m[i] * (double)h.s[i] * (h.s[i] + 1);   // lower half of A_i^* A_i
             gram_bytes += 16.0 * h.m[i] * (double)h.s[i];
         }
         ws.prof.run("gram", st, gram_flops, gram_bytes, [&] {
-            launch_gram_batched(w.dzb.as<ZBatch>(), n_sub, h.max_s, max_m, nsplit, ws.zg.as<double2>(),
-                                w.dgcol.as<int>(), G, nc, st);
+            launch_gram_batched(reinterpret_cast<const ZBatch*>(at(tb.zb)), n_sub, h.max_s, max_m, tb.nsplit,
+                                ws.zg.as<double2>(), d.pc_gcol, G, nc, st);
         });
     }
     cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof);
@@ -362,13 +372,22 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
         if (hf.badcol & 1) throw Error(MDP_ERR_SINGULAR, "zero column in the interface matrix");
     };
     auto converged = [&]() { return !hf.info && hf.dx2 <= 1e-22 * hf.x2; };
+    // the residual norms of the refined solution go to the host with the convergence data
+    auto residual_norms = [&]() {
+        residual();
+        MDP_HIP(hipMemsetAsync(&fl->r2, 0, 2 * sizeof(double), st));   // r2 and f2 (adjacent)
+        launch_znorm2((int)mtot, r, &fl->r2, st);
+        launch_znorm2((int)mtot, F, &fl->f2, st);
+    };
     refine(2);
+    residual_norms();
     read_flags();
     if (!hf.info && !converged()) {
         // slower contraction (larger cond): continue while the corrections shrink
         double prev = hf.dx2;
         for (int round = 0; round < 3 && !converged(); ++round) {
             refine(2);
+            residual_norms();
             read_flags();
             if (!(hf.dx2 < 0.25 * prev)) break;   // not contracting: hand over
             prev = hf.dx2;
@@ -382,14 +401,9 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, d
         *fallback = true;
         return res;
     }
-    residual();
-    launch_znorm2((int)mtot, r, &fl->r2, st);
-    launch_znorm2((int)mtot, F, &fl->f2, st);
-    read_flags();
     res.passes = 1;
     res.rel_residual = std::sqrt(hf.r2) / (hf.f2 > 0 ? std::sqrt(hf.f2) : 1.0);
     launch_scale_cols(x, 1, nc, 1, norms, 1, st);
-    MDP_HIP(hipMemcpyAsync(x_out, x, nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
     if (want_cond) {
         // cond(Qbar_eq)^2 = lambda_max(G) lambda_max(G^{-1}); G v = L (L^* v), G^{-1} v = Linv^* (Linv v)
         std::vector<double2> hv(nc);

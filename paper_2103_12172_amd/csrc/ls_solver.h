@@ -34,11 +34,23 @@ struct PackedHost {
 void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
                           hipStream_t st, Profiler* pr = nullptr);
 
+// Device tables of the packed solve: offsets into a caller's upload image.
+struct PackedTables {
+    size_t Q, m, s, off, roff, sub, p, gcol, start, cols, coef, zb;
+    int nsplit;
+};
+
+// Grow the workspaces for h and append the packed solve's tables to blob.
+PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob);
+
 // Corrected semi-normal equations on the packed matrix; F is the stacked
-// right-hand side (device).  Sets *fallback (and returns) when the Cholesky of
-// the Gram matrix breaks down or the refinement does not contract.
-LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const double2* F, double2* x_out, bool want_cond,
-                         hipStream_t st, bool* fallback);
+// right-hand side (device), `image` the device copy of the blob that holds the
+// tables t.  x_out (device) receives the solution.  Synchronises the stream
+// once in the common case (convergence check and residual norms together).
+// Sets *fallback (and returns) when the Cholesky of the Gram matrix breaks
+// down or the refinement does not contract.
+LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, const PackedTables& t,
+                         const double2* F, double2* x_out, bool want_cond, hipStream_t st, bool* fallback);
 
 // min ||A x - F||_2 for A (m x nc, column-major, ld m, device; overwritten) and
 // F (m, device); x_out (nc, device).

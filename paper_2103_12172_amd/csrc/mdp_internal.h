@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -58,6 +60,94 @@ struct DevBuf {
     void reserve(size_t b) { if (b > bytes) alloc(b); }
     void release() { if (p) (void)hipFree(p); p = nullptr; bytes = 0; }
     template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ----------------------------------------------------------------- descriptor uploads
+// The small host-built tables of one call (descriptors, index maps) are packed
+// into one byte image, each item 256-byte aligned, and moved to the device by
+// a single asynchronous copy from pinned host memory: copies from pageable
+// memory are staged synchronously by the runtime, one round trip per table.
+class HostBlob {
+public:
+    template <class T>
+    size_t put(const T* p, size_t n) {
+        const size_t off = (data_.size() + 255) / 256 * 256;
+        data_.resize(off + std::max<size_t>(n, 1) * sizeof(T), 0);
+        if (n) std::memcpy(data_.data() + off, p, n * sizeof(T));
+        return off;
+    }
+    template <class T>
+    size_t put(const std::vector<T>& v) { return put(v.data(), v.size()); }
+    size_t size() const { return data_.size(); }
+    const char* data() const { return data_.data(); }
+
+private:
+    std::vector<char> data_;
+};
+
+// Pinned host staging buffers and a grow-only device image for per-call tables.
+// A pinned slot is rewritten only after the copy out of it has completed (its
+// event); several slots rotate so that the host rarely waits for a copy queued
+// behind earlier work.  The device image is rewritten by a copy ordered on the
+// stream after every earlier call's kernels.
+struct Staging {
+    struct Slot {
+        void* host = nullptr;
+        size_t cap = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    };
+    static constexpr int kSlots = 8;
+    Slot slot[kSlots];
+    int next = 0;
+    DevBuf image;
+    Staging() = default;
+    Staging(const Staging&) = delete;
+    Staging& operator=(const Staging&) = delete;
+    ~Staging() {
+        for (Slot& s : slot) {
+            if (s.pending) (void)hipEventSynchronize(s.done);
+            if (s.host) (void)hipHostFree(s.host);
+            if (s.done) (void)hipEventDestroy(s.done);
+        }
+    }
+    // copy b to the device address dst on st
+    void copy(void* dst, const HostBlob& b, hipStream_t st) {
+        if (!b.size()) return;
+        // a slot whose last copy has completed, else the next one in turn (waited for)
+        int pick = -1;
+        for (int i = 0; i < kSlots && pick < 0; ++i) {
+            Slot& c = slot[(next + i) % kSlots];
+            if (!c.pending || hipEventQuery(c.done) == hipSuccess) pick = (next + i) % kSlots;
+        }
+        if (pick < 0) pick = next;
+        next = (pick + 1) % kSlots;
+        Slot& s = slot[pick];
+        if (!s.done) MDP_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+        if (s.pending) MDP_HIP(hipEventSynchronize(s.done));
+        s.pending = false;
+        if (b.size() > s.cap) {
+            const size_t want = std::max<size_t>({b.size(), 2 * s.cap, (size_t)1 << 16});
+            if (s.host) MDP_HIP(hipHostFree(s.host));
+            s.host = nullptr;
+            s.cap = 0;
+            MDP_HIP(hipHostMalloc(&s.host, want, hipHostMallocDefault));
+            s.cap = want;
+        }
+        std::memcpy(s.host, b.data(), b.size());
+        MDP_HIP(hipMemcpyAsync(dst, s.host, b.size(), hipMemcpyHostToDevice, st));
+        MDP_HIP(hipEventRecord(s.done, st));
+        s.pending = true;
+    }
+    // the device image, grown (after the device has drained) to at least b's size, with b copied in
+    char* upload(const HostBlob& b, hipStream_t st) {
+        if (b.size() > image.bytes) {
+            MDP_HIP(hipDeviceSynchronize());
+            image.reserve(std::max(b.size(), 2 * image.bytes));
+        }
+        copy(image.p, b, st);
+        return image.as<char>();
+    }
 };
 
 // ----------------------------------------------------------------- per-launch profiler
@@ -163,6 +253,7 @@ struct SrcDesc {
     Src kind;
     const double* grid;   // GRID / STENCIL_GRID: complex interleaved grids, (n+1)^2 each, stride grid_stride (complex elems)
     long grid_stride;
+    const long* goff;     // optional: grid b starts at goff[b] (complex elements) instead of b * grid_stride
     const double* E;      // STENCIL_E: column-major |gamma| x ncols real
     int ldE;
     int col0;             // STENCIL_E: first column of this batch
@@ -170,37 +261,46 @@ struct SrcDesc {
     int m_lo, m_hi, q_lo, q_hi;  // M+ box (STENCIL_*)
 };
 
+// Rows r0..r0+nr-1 of the AP grid held by a folded batch buffer (all n+1 rows for a full solve).
+struct Band {
+    int r0, nr;
+};
+
 template <class T>
-void launch_fold_rhs(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, bool cplx, T* out,
+void launch_fold_rhs(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, bool cplx, Band bd, T* out,
                      hipStream_t st);
 template <class T>
 void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st);
+// fac: planes l.re, l.im, r.re, r.im, tw.re, tw.im, each (n+1) x W
 template <class T>
 void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* colc, int n, const Fold& f, int R,
-                    hipStream_t st);
+                    Band bd, hipStream_t st);
 void launch_residual(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, EndRowCoef ec, int R, bool cplx_src,
                      const float* u32, float* r_out, hipStream_t st);
 template <class T>
-void launch_gather_q(const T* u, const float* du, int n, const Fold& f, const int* gm, const int* gq, int ng, int R,
-                     double* Q, int ldq, int col0, hipStream_t st);
+void launch_gather_q(const T* u, const float* du, int n, const Fold& f, Band bd, const int* gm, const int* gq, int ng,
+                     int R, double* Q, int ldq, int col0, hipStream_t st);
 template <class T>
-void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, int R, const double* w, long w_stride,
-                        double* out, long out_stride, hipStream_t st);
+// out = w - u (w given) or u on the grid rows `rows` (inside the buffer's band bd); grid b of w and
+// out starts at boff[b] (complex elements) when boff is set, else at b * stride
+void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, Band bd, Band rows, int R, const double* w,
+                        long w_stride, double* out, long out_stride, const long* boff, hipStream_t st);
 // w_b(gamma_i) = sum over the Dirichlet and Neumann columns of gamma_i's side of E(i, col) c_b(col)
-void launch_extend_density(const double* E, int ng, int ncol, const double* c, int R, const int* gm,
-                           const int* gq, const int* gside, int n, double* w, long w_stride, hipStream_t st);
+void launch_extend_density(const double* E, int ng, int ncol, const double* c, const int* cidx, int R, const int* gm,
+                           const int* gq, const int* gside, int n, double* w, long w_stride, const long* woff,
+                           hipStream_t st);
 
 // projector build, support-in / gamma-out form (FP64)
 constexpr int FUSED_K = 8;   // rows per recomputed segment of the fused tridiagonal sweep
 bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi);
-int fused_segments(int n);   // segments of FUSED_K rows covering m = 0..n
+int fused_segments(int m_lo, int m_hi);   // segments of FUSED_K rows covering m = m_lo-1..m_hi+1
 // gc: [R][n+1][4] ring table, spec: [R][4][W] folded special rows
 void launch_fold_ring(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, double* gc, double* spec,
                       hipStream_t st);
-// lf, rf: [(n+1)][W] interleaved complex Thomas factors l_m and r_m = 1/d_m
+// lf, rf, tf: [(n+1)][W] interleaved complex Thomas factors l_m, r_m = 1/d_m and twisted pivots tw_m
 void launch_proj_fused(const double* gc, const double* spec_hat, const double* Sf, const double* Si, const Fold& f,
-                       int m_lo, int m_hi, int q_lo, int q_hi, const double* lf, const double* rf, const double* colc,
-                       double* ckpt, double* xs, double* thin, int R, hipStream_t st);
+                       int m_lo, int m_hi, int q_lo, int q_hi, const double* lf, const double* rf, const double* tf,
+                       const double* colc, double* ckpt, double* xs, double* thin, int R, hipStream_t st);
 void launch_gather_q_fused(const double* us, const double* thin, const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi,
                            const int* gm, const int* gq, int ng, int R, double* Q, int ldq, int col0, hipStream_t st);
 
@@ -223,6 +323,9 @@ void launch_chol_update(double2* G, int nc, int kb, int nbk, const double2* L, c
                         hipStream_t st);
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
                           const int4* colmap, const double2* coefs, int ncol, double2* Qbar, int ldq, hipStream_t st);
+// c[e] = known[e] + coef[e] x[src[e]] (src[e] < 0: known value only), e < n
+void launch_expand_coeffs(int n, const int* src, const double2* coef, const double2* known, const double2* x,
+                          double2* c, hipStream_t st);
 void launch_known_rhs(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
                       const int* kcol, const double2* kval, const int* koff, double2* F, hipStream_t st);
 void launch_col_norms(const double2* A, int m, int n, int lda, double* out, hipStream_t st);
