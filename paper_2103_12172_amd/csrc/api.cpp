@@ -515,6 +515,38 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             }
         }
         const int ncol = (int)blocks.size() * M;
+        // Column order of the unknowns: each subdomain's private unknowns (its boundary sides, which no
+        // other subdomain's rows touch, so the Gram matrix vanishes between different subdomains' private
+        // columns) in slices of at most 64 columns, slice l of every subdomain side by side forming
+        // Cholesky step l (its diagonal sub-blocks do not couple), then the interface unknowns in 64-column
+        // steps.  perm maps the column b*M + j of block b to its place in that order.
+        std::vector<int> perm(ncol);
+        CholPlan chol_steps;
+        {
+            std::vector<std::vector<int>> priv(n_sub);
+            std::vector<int> shared;
+            for (size_t b = 0; b < blocks.size(); ++b)
+                for (int j = 0; j < M; ++j) {
+                    if (blocks[b].type != 3) priv[blocks[b].c[0].sub].push_back((int)b * M + j);
+                    else shared.push_back((int)b * M + j);
+                }
+            size_t levels = 0;
+            for (const auto& v : priv) levels = std::max(levels, (v.size() + 63) / 64);
+            int next = 0;
+            for (size_t l = 0; l < levels; ++l) {
+                std::vector<int> widths;
+                for (const auto& v : priv) {
+                    const size_t lo = 64 * l, hi = std::min(v.size(), lo + 64);
+                    if (lo >= hi) continue;
+                    for (size_t e = lo; e < hi; ++e) perm[v[e]] = next++;
+                    widths.push_back((int)(hi - lo));
+                }
+                chol_steps.push_back(widths);
+            }
+            const int kb0 = next;
+            for (int c : shared) perm[c] = next++;
+            for (int kb = kb0; kb < ncol; kb += 64) chol_steps.push_back({std::min(64, ncol - kb)});
+        }
         std::vector<int> row_off(n_sub + 1, 0);
         for (int i = 0; i < n_sub; ++i) row_off[i + 1] = row_off[i] + P[i]->g.n_gamma;
         const int m = row_off[n_sub];
@@ -525,7 +557,7 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
         for (size_t b = 0; b < blocks.size(); ++b) {
             for (const Contrib& c : blocks[b].c) {
                 for (int j = 0; j < M; ++j) {
-                    const size_t idx = (size_t)c.sub * ncol + b * M + j;
+                    const size_t idx = (size_t)c.sub * ncol + perm[b * M + j];
                     const int qcol = c.kind * 4 * M + c.side * M + j;
                     if (colmap[idx].x < 0) { colmap[idx].x = qcol; coefs[2 * idx] = c.coef; }
                     else { colmap[idx].y = qcol; coefs[2 * idx + 1] = c.coef; }
@@ -559,13 +591,13 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             for (int j = 0; j < M; ++j) {
                 if (B.type == 2) {
                     const size_t e = E(B.c[0].sub, 0, B.c[0].side, j);
-                    esrc[e] = (int)(b * M + j);
+                    esrc[e] = perm[b * M + j];
                     ecoef[e] = double2{1.0, 0.0};
                     continue;
                 }
                 for (const Contrib& ct : B.c) {
                     const size_t e = E(ct.sub, ct.kind, ct.side, j);
-                    esrc[e] = (int)(b * M + j);
+                    esrc[e] = perm[b * M + j];
                     ecoef[e] = ct.coef;
                 }
             }
@@ -594,6 +626,7 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
         PackedHost ph;
         ph.n_sub = n_sub;
         ph.nc = ncol;
+        ph.steps = chol_steps;
         ph.Q = qsrc;
         ph.m = qld;
         long off = 0;
@@ -618,7 +651,7 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
                     }
                     ph.pc_sub.push_back(i);
                     ph.pc_p.push_back(si);
-                    ph.pc_gcol.push_back((int)b * M + j);
+                    ph.pc_gcol.push_back(perm[b * M + j]);
                     ph.pc_cols.push_back(cm);
                     ph.pc_coef.push_back(w0);
                     ph.pc_coef.push_back(w1);
@@ -658,8 +691,9 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             hipEvent_t a = nullptr, b = nullptr;
             const bool span = pr.wants("interface_ls");
             if (span) { a = pr.get(); b = pr.get(); MDP_HIP(hipEventRecord(a, st)); }
-            // algorithmic work of the least squares: a Householder QR of the m x ncol matrix
-            const double qr_flops = 8.0 * ((double)m * ncol * ncol - (double)ncol * ncol * ncol / 3.0);
+            // algorithmic work of the least squares: the semi-normal path's own count, or a Householder QR
+            // of the m x ncol matrix for the dense fallback
+            double ls_flops = 8.0 * ((double)m * ncol * ncol - (double)ncol * ncol * ncol / 3.0);
             bool fallback = false;
             r = ls_solve_packed(ctx->ws, ph, img, tabs, F.as<double2>(), x.as<double2>(), cond_estimate_out != nullptr,
                                 st, &fallback);
@@ -671,10 +705,12 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
                 r = ls_solve(ctx->ws, Qbar.as<double2>(), F.as<double2>(), m, ncol, x.as<double2>(),
                              cond_estimate_out != nullptr, st);
                 MDP_HIP(hipStreamSynchronize(st));
+            } else {
+                ls_flops = r.flops;
             }
             if (span) {
                 MDP_HIP(hipEventRecord(b, st));
-                pr.recs.push_back({"interface_ls", a, b, qr_flops, (double)m * ncol * 16.0});
+                pr.recs.push_back({"interface_ls", a, b, ls_flops, (double)m * ncol * 16.0});
             }
         }
         // known and solved coefficients into the caller's vector (column order of Q), on the stream

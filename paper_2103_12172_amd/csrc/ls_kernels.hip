@@ -275,7 +275,7 @@ __device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;   // tile row, column group (columns 4g..4g+3)
     for (int e = tid; e < 64 * 64; e += blockDim.x) {
-        const int i = e >> 6, j = e & 63;
+        const int i = e & 63, j = e >> 6;   // consecutive threads: consecutive rows of a column
         double2 v = make_double2(0.0, 0.0);
         if (j <= i) {
             if (i < nb) v = G[i + (long)j * ldg];
@@ -426,7 +426,7 @@ __device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double
     const int first = bad_s;
     if (Lout || Zout) {
         for (int e = tid; e < 64 * 64; e += blockDim.x) {
-            const int i = e >> 6, j = e & 63;
+            const int i = e & 63, j = e >> 6;
             if (i >= nb || j > i) continue;
             if (Lout) Lout[i + (long)j * ldl] = s.S[i][j];
             if (Zout) Zout[i + (long)j * ldz] = s.Z[i][j];
@@ -436,36 +436,42 @@ __device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double
 }
 
 // Block step of the blocked Cholesky factorisation and inverse of an order-nc
-// Hermitian positive definite matrix (G, lower triangle, ld nc), diagonal
-// block kb..kb+nbk-1.  Z = L^{-1} is built block row by block row:
-// W(i,j) accumulates -sum_l L(i,l) Z(l,j) over the eliminated blocks l, and
-// Z(k,j) = Z(k,k) W(k,j) once block row k's W is complete.
-// Workgroup roles (256 threads each, every one refactors the diagonal block
-// into LDS first):
-//   block 0:                     L(k,k), Z(k,k) to memory, breakdown to *info;
-//   blocks 1..np (32-row slabs): L(i,k) = G(i,k) Z(k,k)^*;
-//   the rest (32-column slabs j0 < kb): Z(k,j) = Z(k,k) W(k,j).
+// Hermitian positive definite matrix (G, lower triangle, ld nc).  The step's
+// columns kb..r0-1 (r0 = kb + sp.wtot) form nq diagonal sub-blocks q,
+// columns kb + off[q] .. kb + off[q+1] - 1 (at most 64 each), that do not
+// couple (G vanishes between them, so L and L^{-1} do too): each is factored
+// on its own.  Z = L^{-1} is built block row by block row: W(i,j) accumulates
+// -sum_l L(i,l) Z(l,j) over the eliminated columns l, and Z(q,j) = Z(q,q) W(q,j)
+// once block row q's W is complete.
+// Workgroups: per sub-block q, roles (256 threads each, every one refactors
+// the sub-block's diagonal block into LDS first):
+//   role 0:                      L(q,q), Z(q,q) to memory, breakdown to *info;
+//   roles 1..np (32-row slabs of the rows r0..nc-1): L(i,q) = G(i,q) Z(q,q)^*;
+//   the rest (32-column slabs j0 < kb): Z(q,j) = Z(q,q) W(q,j).
 // The slab operand is staged in the (no longer needed) S part of the LDS.
 // (one workgroup per CU by its LDS, so all 512 registers of a lane are allowed)
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-chol_panel_kernel(const double2* __restrict__ G, int nc, int kb, int nbk, double shift, double2* __restrict__ L,
-                  double2* __restrict__ Z, const double2* __restrict__ W, int* info, int np) {
+chol_panel_kernel(const double2* __restrict__ G, int nc, CholStepDev sp, double shift, double2* __restrict__ L,
+                  double2* __restrict__ Z, const double2* __restrict__ W, int* info, int np, int nz) {
     __shared__ CholLds s;
-    const int role = blockIdx.x, tid = threadIdx.x;
-    const long dk = kb + (long)kb * nc;
+    const int roles = 1 + np + nz;
+    const int q = blockIdx.x / roles, role = blockIdx.x - q * roles, tid = threadIdx.x;
+    const int kb = sp.kb, r0 = sp.kb + sp.wtot;
+    const int kq = kb + sp.off[q], nbq = sp.off[q + 1] - sp.off[q];
+    const long dk = kq + (long)kq * nc;
     const bool diag = role == 0;
-    const int bad = chol64_lds(G + dk, nc, nbk, shift, s, diag ? L + dk : nullptr, nc, diag ? Z + dk : nullptr, nc);
+    const int bad = chol64_lds(G + dk, nc, nbq, shift, s, diag ? L + dk : nullptr, nc, diag ? Z + dk : nullptr, nc);
     if (diag) {
-        if (tid == 0 && bad && info) atomicCAS(info, 0, kb + bad);
+        if (tid == 0 && bad && info) atomicCAS(info, 0, kq + bad);
         return;
     }
     const int tr = tid >> 4, tc = tid & 15;   // 16 x 16 threads
     if (role <= np) {
-        // rows i0..i0+31: S[r][k] = G(i0 + r, kb + k); thread rows 2tr + {0,1}, columns 4tc + {0..3}
-        const int i0 = kb + nbk + 32 * (role - 1);
+        // rows i0..i0+31: S[r][k] = G(i0 + r, kq + k); thread rows 2tr + {0,1}, columns 4tc + {0..3}
+        const int i0 = r0 + 32 * (role - 1);
         for (int e = tid; e < 32 * 64; e += 256) {
-            const int rr = e >> 6, k = e & 63, i = i0 + rr;
-            s.S[rr][k] = (i < nc && k < nbk) ? G[i + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
+            const int rr = e & 31, k = e >> 5, i = i0 + rr;   // consecutive threads: consecutive rows
+            s.S[rr][k] = (i < nc && k < nbq) ? G[i + (long)(kq + k) * nc] : make_double2(0.0, 0.0);
         }
         __syncthreads();
         double ar[2][4] = {}, ai[2][4] = {};
@@ -495,17 +501,17 @@ chol_panel_kernel(const double2* __restrict__ G, int nc, int kb, int nbk, double
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int c = 4 * tc + b;
-                if (i < nc && c < nbk) L[i + (long)(kb + c) * nc] = make_double2(ar[a][b], ai[a][b]);
+                if (i < nc && c < nbq) L[i + (long)(kq + c) * nc] = make_double2(ar[a][b], ai[a][b]);
             }
         }
         return;
     }
-    // columns j0..j0+31 of block row k of Z: S[k][c] = W(kb + k, j0 + c); thread rows 4tr + {0..3},
+    // columns j0..j0+31 (< kb) of block row q of Z: S[k][c] = W(kq + k, j0 + c); thread rows 4tr + {0..3},
     // columns 2tc + {0,1}
     const int j0 = 32 * (role - 1 - np);
     for (int e = tid; e < 64 * 32; e += 256) {
         const int k = e >> 5, c = e & 31;
-        s.S[k][c] = (k < nbk) ? W[kb + k + (long)(j0 + c) * nc] : make_double2(0.0, 0.0);
+        s.S[k][c] = (k < nbq && j0 + c < kb) ? W[kq + k + (long)(j0 + c) * nc] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     double zr[4][2] = {}, zi[4][2] = {};
@@ -532,24 +538,27 @@ chol_panel_kernel(const double2* __restrict__ G, int nc, int kb, int nbk, double
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int rr = 4 * tr + a;
-        if (rr >= nbk) continue;
+        if (rr >= nbq) continue;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) Z[kb + rr + (long)(j0 + 2 * tc + b) * nc] = make_double2(zr[a][b], zi[a][b]);
+        for (int b = 0; b < 2; ++b) {
+            const int j = j0 + 2 * tc + b;
+            if (j < kb) Z[kq + rr + (long)j * nc] = make_double2(zr[a][b], zi[a][b]);
+        }
     }
 }
 
-// Update after the block step kb..kb+nbk-1 (r0 = kb + nbk): 32 x 32 tiles of
+// Update after the block step kb..r0-1 (r0 = kb + wtot): 32 x 32 tiles of
 //   the trailing Schur complement  G(i,j) -= sum_k L(i,k) conj(L(j,k)),  r0 <= j <= i (tile-wise lower),
 //   the inverse accumulation       W(i,j) -= sum_k L(i,k) Z(k,j),        i >= r0, j < r0,
-// k over the block's columns (for j in the block, Z(k,j) is the block's own
-// inverse and W starts from zero).  Both operands staged in LDS; 2 x 2 entries
-// per thread.
+// k over the step's columns in chunks of 64 (for j in the step, Z(k,j) is the
+// step's own block-diagonal inverse and W starts from zero).  Both operands
+// staged in LDS; 2 x 2 entries per thread.
 __global__ void __launch_bounds__(256)
-chol_update_kernel(double2* __restrict__ G, int nc, int kb, int nbk, const double2* __restrict__ L,
+chol_update_kernel(double2* __restrict__ G, int nc, int kb, int wtot, const double2* __restrict__ L,
                    const double2* __restrict__ Z, double2* __restrict__ W, int ntr) {
-    __shared__ double2 A[64][33];   // A[k][r] = L(i0 + r, kb + k)
-    __shared__ double2 B[64][33];   // B[k][c] = conj(L(j0 + c, kb + k)) or Z(kb + k, j0 + c)
-    const int r0 = kb + nbk, tid = threadIdx.x;
+    __shared__ double2 A[64][33];   // A[k][r] = L(i0 + r, k0 + k)
+    __shared__ double2 B[64][33];   // B[k][c] = conj(L(j0 + c, k0 + k)) or Z(k0 + k, j0 + c)
+    const int r0 = kb + wtot, tid = threadIdx.x;
     int t = blockIdx.x, i0, j0;
     bool trail;
     const int ntri = ntr * (ntr + 1) / 2;
@@ -565,39 +574,43 @@ chol_update_kernel(double2* __restrict__ G, int nc, int kb, int nbk, const doubl
         j0 = 32 * (t / ntr);
         trail = false;
     }
-    for (int e = tid; e < 64 * 32; e += 256) {
-        const int k = e >> 5, r = e & 31;
-        const int i = i0 + r, j = j0 + r;
-        const bool kin = k < nbk;
-        A[k][r] = (kin && i < nc) ? L[i + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
-        if (trail) {
-            const double2 v = (kin && j < nc) ? L[j + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
-            B[k][r] = make_double2(v.x, -v.y);
-        } else {
-            B[k][r] = kin ? Z[kb + k + (long)j * nc] : make_double2(0.0, 0.0);
-        }
-    }
-    __syncthreads();
     const int tr = tid >> 4, tc = tid & 15;
     double cr[2][2] = {}, ci[2][2] = {};
-    for (int k0 = 0; k0 < 64; k0 += 4) {
-        double2 a[4][2], b[4][2];   // one round of operands loaded before any arithmetic
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                a[kk][u] = A[k0 + kk][2 * tr + u];
-                b[kk][u] = B[k0 + kk][2 * tc + u];
+    for (int k0 = kb; k0 < r0; k0 += 64) {
+        const int kn = min(64, r0 - k0);
+        if (k0 > kb) __syncthreads();   // the previous chunk's operands are consumed
+        for (int e = tid; e < 64 * 32; e += 256) {
+            const int k = e >> 5, r = e & 31;
+            const int i = i0 + r, j = j0 + r;
+            const bool kin = k < kn;
+            A[k][r] = (kin && i < nc) ? L[i + (long)(k0 + k) * nc] : make_double2(0.0, 0.0);
+            if (trail) {
+                const double2 v = (kin && j < nc) ? L[j + (long)(k0 + k) * nc] : make_double2(0.0, 0.0);
+                B[k][r] = make_double2(v.x, -v.y);
+            } else {
+                B[k][r] = (kin && j < r0) ? Z[k0 + k + (long)j * nc] : make_double2(0.0, 0.0);
             }
+        }
+        __syncthreads();
+        for (int kk0 = 0; kk0 < 64; kk0 += 4) {
+            double2 a[4][2], b[4][2];   // one round of operands loaded before any arithmetic
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
+            for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int v = 0; v < 2; ++v) {
-                    cr[u][v] = fma(a[kk][u].x, b[kk][v].x, fma(-a[kk][u].y, b[kk][v].y, cr[u][v]));
-                    ci[u][v] = fma(a[kk][u].x, b[kk][v].y, fma(a[kk][u].y, b[kk][v].x, ci[u][v]));
+                for (int u = 0; u < 2; ++u) {
+                    a[kk][u] = A[kk0 + kk][2 * tr + u];
+                    b[kk][u] = B[kk0 + kk][2 * tc + u];
                 }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        cr[u][v] = fma(a[kk][u].x, b[kk][v].x, fma(-a[kk][u].y, b[kk][v].y, cr[u][v]));
+                        ci[u][v] = fma(a[kk][u].x, b[kk][v].y, fma(a[kk][u].y, b[kk][v].x, ci[u][v]));
+                    }
+        }
     }
     double2* C = trail ? G : W;
 #pragma unroll
@@ -607,7 +620,7 @@ chol_update_kernel(double2* __restrict__ G, int nc, int kb, int nbk, const doubl
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
             const int j = j0 + 2 * tc + v;
-            if (j >= nc || (trail && j > i)) continue;
+            if (j >= nc || (trail && j > i) || (!trail && j >= r0)) continue;
             double2 c = C[i + (long)j * nc];
             c.x -= cr[u][v];
             c.y -= ci[u][v];
@@ -908,23 +921,16 @@ __global__ void gram_scatter_kernel(const ZBatch* __restrict__ zb, const double2
         sr += v.x;
         si += v.y;
     }
+    // G(g1, g2) = A_p1^* A_p2 into the lower triangle: the conjugate at (g2, g1) when the global
+    // order of the two columns is the reverse of the local one
     const int* gcol = gcol_all + e.gcol_off;
-    double* o = reinterpret_cast<double*>(G + gcol[p1] + (long)gcol[p2] * ldg);
+    const int g1 = gcol[p1], g2 = gcol[p2];
+    double* o = reinterpret_cast<double*>(g1 >= g2 ? G + g1 + (long)g2 * ldg : G + g2 + (long)g1 * ldg);
     atomicAdd(&o[0], sr);
-    atomicAdd(&o[1], si);
+    atomicAdd(&o[1], g1 >= g2 ? si : -si);
 }
 
 // G(gcol(p1), gcol(p2)) += Gi(p1, p2) for the packed columns of one subdomain
-__global__ void scatter_gram_kernel(const double2* __restrict__ Gi, int s, const int* __restrict__ gcol, double2* G,
-                                    int ldg) {
-    const int p1 = blockIdx.x * blockDim.x + threadIdx.x, p2 = blockIdx.y;
-    if (p1 >= s) return;
-    const double2 v = Gi[p1 + (long)p2 * s];
-    double2* o = G + gcol[p1] + (long)gcol[p2] * ldg;
-    o->x += v.x;
-    o->y += v.y;
-}
-
 // y += x (complex vectors)
 __global__ void zaxpy1_kernel(int n, const double2* __restrict__ x, double2* y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1099,28 +1105,30 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
     }
 }
 
-void launch_chol_panel(const double2* G, int nc, int kb, int nbk, double shift, double2* L, double2* Z,
+void launch_chol_panel(const double2* G, int nc, const CholStepDev& sp, double shift, double2* L, double2* Z,
                        const double2* W, int* info, hipStream_t st) {
-    if (nbk < 1 || nbk > 64 || kb < 0 || kb % 64 || kb + nbk > nc) throw Error(MDP_ERR_ARG, "bad Cholesky block");
-    const int rest = nc - kb - nbk;
-    if (rest > 0 && nbk != 64) throw Error(MDP_ERR_ARG, "only the last Cholesky block may be short");
-    const int np = (rest + 31) / 32, nz = kb / 32;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(1 + np + nz), dim3(256), 0, st, G, nc, kb, nbk, shift, L, Z, W, info,
-                       np);
+    if (sp.nq < 1 || sp.nq > CholStepDev::kMaxQ || sp.kb < 0 || sp.off[0] != 0 || sp.off[sp.nq] != sp.wtot ||
+        sp.kb + sp.wtot > nc)
+        throw Error(MDP_ERR_ARG, "bad Cholesky step");
+    for (int q = 0; q < sp.nq; ++q)
+        if (sp.off[q + 1] - sp.off[q] < 1 || sp.off[q + 1] - sp.off[q] > 64)
+            throw Error(MDP_ERR_ARG, "Cholesky sub-block width must be 1..64");
+    const int rest = nc - sp.kb - sp.wtot;
+    const int np = (rest + 31) / 32, nz = (sp.kb + 31) / 32;
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(sp.nq * (1 + np + nz)), dim3(256), 0, st, G, nc, sp, shift, L, Z, W,
+                       info, np, nz);
     MDP_HIP(hipGetLastError());
 }
-
-void launch_chol_update(double2* G, int nc, int kb, int nbk, const double2* L, const double2* Z, double2* W,
+void launch_chol_update(double2* G, int nc, int kb, int wtot, const double2* L, const double2* Z, double2* W,
                         hipStream_t st) {
-    const int rest = nc - kb - nbk;
+    const int rest = nc - kb - wtot;
     if (rest <= 0) return;
     const int np = (rest + 31) / 32;
-    const int nw = (kb + nbk) / 32;   // W column tiles, the diagonal block's included
+    const int nw = (kb + wtot + 31) / 32;   // W column tiles, the step's own columns included
     const int tiles = np * (np + 1) / 2 + np * nw;
-    hipLaunchKernelGGL(chol_update_kernel, dim3(tiles), dim3(256), 0, st, G, nc, kb, nbk, L, Z, W, np);
+    hipLaunchKernelGGL(chol_update_kernel, dim3(tiles), dim3(256), 0, st, G, nc, kb, wtot, L, Z, W, np);
     MDP_HIP(hipGetLastError());
 }
-
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
                           const int4* colmap, const double2* coefs, int ncol, double2* Qbar, int ldq, hipStream_t st) {
     dim3 grid(std::max(1, std::min((total_rows + 255) / 256, 1024)), ncol);
@@ -1226,12 +1234,6 @@ void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int
     (void)max_k;
     hipLaunchKernelGGL(gram_scatter_kernel, dim3((unsigned)(((long)max_n * max_n + 255) / 256), nb), dim3(256), 0, st,
                        zb_dev, P, nsplit, gcol, G, ldg);
-    MDP_HIP(hipGetLastError());
-}
-
-void launch_scatter_gram(const double2* Gi, int s, const int* gcol, double2* G, int ldg, hipStream_t st) {
-    dim3 grid((s + 255) / 256, s);
-    hipLaunchKernelGGL(scatter_gram_kernel, grid, dim3(256), 0, st, Gi, s, gcol, G, ldg);
     MDP_HIP(hipGetLastError());
 }
 

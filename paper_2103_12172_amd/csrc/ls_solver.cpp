@@ -48,31 +48,61 @@ void grow(DevBuf& b, size_t bytes) {
 
 }  // namespace
 
+CholPlan chol_plan_uniform(int nc) {
+    CholPlan p;
+    for (int kb = 0; kb < nc; kb += NB) p.push_back({std::min(NB, nc - kb)});
+    return p;
+}
+
 // Blocked Cholesky G + shift I = L L^* and Linv = L^{-1}, two launches per
-// 64-column block (diagonal factor + panel + inverse block row, then the
+// step of the plan (diagonal sub-blocks + panel + inverse block rows, then the
 // trailing and inverse updates); W (nc x nc) is the inverse's accumulator.
 // G's lower triangle is overwritten by the trailing updates.
-void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
-                          hipStream_t st, Profiler* pr) {
+double cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
+                            hipStream_t st, Profiler* pr, const CholPlan* plan) {
     MDP_HIP(hipMemsetAsync(L, 0, sizeof(double2) * (size_t)nc * nc, st));
     MDP_HIP(hipMemsetAsync(Linv, 0, sizeof(double2) * (size_t)nc * nc, st));
     MDP_HIP(hipMemsetAsync(W, 0, sizeof(double2) * (size_t)nc * nc, st));
     Profiler none;
     Profiler& p = pr ? *pr : none;
-    for (int kb = 0; kb < nc; kb += NB) {
-        const int nbk = std::min(NB, nc - kb);
-        const double b = nbk, rest = nc - kb - nbk;
-        // algorithmic flops (complex = 4 real multiply-adds): Cholesky and triangular inverse of
-        // the diagonal block (4/3 b^3 each), the panel of L (8 rest b^2), the block row of Z (8 kb b^2);
-        // then the trailing update (4 rest^2 b, lower half) and the inverse accumulation (8 rest (kb+b) b)
-        p.run("chol_panel", st, 8.0 / 3.0 * b * b * b + 8.0 * rest * b * b + 8.0 * kb * b * b,
-              16.0 * (b * b + rest * b + 2.0 * kb * b),
-              [&] { launch_chol_panel(G, nc, kb, nbk, shift, L, Linv, W, info_dev, st); });
-        if (rest > 0)
-            p.run("chol_update", st, 4.0 * rest * rest * b + 8.0 * rest * (kb + b) * b,
-                  16.0 * (rest * rest + 2.0 * rest * b + 2.0 * rest * (kb + b)),
-                  [&] { launch_chol_update(G, nc, kb, nbk, L, Linv, W, st); });
+    const CholPlan uniform = plan ? CholPlan{} : chol_plan_uniform(nc);
+    const CholPlan& steps = plan ? *plan : uniform;
+    int kb = 0;
+    double total = 0.0;
+    for (const std::vector<int>& widths : steps) {
+        // a step with more sub-blocks than one launch takes is split (the sub-blocks do not couple)
+        for (size_t q0 = 0; q0 < widths.size(); q0 += CholStepDev::kMaxQ) {
+            CholStepDev sp{};
+            sp.kb = kb;
+            sp.nq = (int)std::min<size_t>(CholStepDev::kMaxQ, widths.size() - q0);
+            sp.off[0] = 0;
+            double panel_flops = 0.0, panel_bytes = 0.0;
+            for (int q = 0; q < sp.nq; ++q) sp.off[q + 1] = sp.off[q] + widths[q0 + q];
+            sp.wtot = sp.off[sp.nq];
+            if (sp.wtot < 1 || kb + sp.wtot > nc) throw Error(MDP_ERR_ARG, "Cholesky plan does not cover the matrix");
+            const double wt = sp.wtot, rest = nc - kb - sp.wtot;
+            for (int q = 0; q < sp.nq; ++q) {
+                // algorithmic flops (complex = 4 real multiply-adds): Cholesky and triangular inverse of the
+                // diagonal sub-block (4/3 b^3 each), its panel of L (8 rest b^2), its block row of Z (8 kb b^2)
+                const double b = widths[q0 + q];
+                panel_flops += 8.0 / 3.0 * b * b * b + 8.0 * rest * b * b + 8.0 * kb * b * b;
+                panel_bytes += 16.0 * (b * b + rest * b + 2.0 * kb * b);
+            }
+            p.run("chol_panel", st, panel_flops, panel_bytes,
+                  [&] { launch_chol_panel(G, nc, sp, shift, L, Linv, W, info_dev, st); });
+            total += panel_flops;
+            // then the trailing update (4 rest^2 w, lower half) and the inverse accumulation (8 rest (kb+w) w)
+            if (rest > 0) {
+                const double uf = 4.0 * rest * rest * wt + 8.0 * rest * (kb + wt) * wt;
+                p.run("chol_update", st, uf, 16.0 * (rest * rest + 2.0 * rest * wt + 2.0 * rest * (kb + wt)),
+                      [&] { launch_chol_update(G, nc, kb, sp.wtot, L, Linv, W, st); });
+                total += uf;
+            }
+            kb += sp.wtot;
+        }
     }
+    if (kb != nc) throw Error(MDP_ERR_ARG, "Cholesky plan does not cover the matrix");
+    return total;
 }
 
 LSResult ls_solve(Workspace& ws, double2* A, const double2* F, int m, int nc, double2* x_out, bool want_cond,
@@ -336,15 +366,27 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
                                 ws.zg.as<double2>(), d.pc_gcol, G, nc, st);
         });
     }
-    cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof);
+    const double chol_flops = cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof,
+                                                   h.steps.empty() ? nullptr : &h.steps);
+    // algorithmic flops: Gram (lower half), factor + inverse, and per normal solve (A^* v plus two
+    // triangular products) or residual (A x): 8 flops per complex multiply-add
+    double packed_cmacs = 0.0, gram_cmacs = 0.0;
+    for (int i = 0; i < n_sub; ++i) {
+        packed_cmacs += (double)h.m[i] * h.s[i];
+        gram_cmacs += 0.5 * (double)h.m[i] * h.s[i] * (h.s[i] + 1);
+    }
+    const double solve_flops = 8.0 * (packed_cmacs + (double)nc * nc), resid_flops = 8.0 * packed_cmacs;
+    int n_solves = 0, n_resid = 0;
     // c = R^{-1} R^{-*} Qbar^* F, R^{-1} = Linv^*, R^{-*} = Linv
     auto normal_solve = [&](const double2* rhs_rows, double2* out) {
+        ++n_solves;
         MDP_HIP(hipMemsetAsync(y, 0, nc * sizeof(double2), st));
         launch_packed_ahx(d, npc, Ap, rhs_rows, ONE, y, st);
         launch_zgemm('N', 'N', nc, 1, nc, ONE, Linv, nc, y, nc, ZERO, t, nc, ws.zg, st);
         launch_zgemm('C', 'N', nc, 1, nc, ONE, Linv, nc, t, nc, ZERO, out, nc, ws.zg, st);
     };
     auto residual = [&]() {   // r = F - Qbar x (stacked rows)
+        ++n_resid;
         MDP_HIP(hipMemcpyAsync(r, F, mtot * sizeof(double2), hipMemcpyDeviceToDevice, st));
         launch_packed_ax(d, n_sub, h.max_m, h.max_s, Ap, x, MONE, r, st);
     };
@@ -403,6 +445,7 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     }
     res.passes = 1;
     res.rel_residual = std::sqrt(hf.r2) / (hf.f2 > 0 ? std::sqrt(hf.f2) : 1.0);
+    res.flops = 8.0 * gram_cmacs + chol_flops + n_solves * solve_flops + n_resid * resid_flops;
     launch_scale_cols(x, 1, nc, 1, norms, 1, st);
     if (want_cond) {
         // cond(Qbar_eq)^2 = lambda_max(G) lambda_max(G^{-1}); G v = L (L^* v), G^{-1} v = Linv^* (Linv v)

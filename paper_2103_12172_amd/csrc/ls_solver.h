@@ -12,13 +12,20 @@ struct LSResult {
     double cond = 0.0;          // estimate of cond_2 of the column-equilibrated A (0 if not requested)
     bool shifted = false;       // the shifted first pass was needed
     int passes = 0;
+    double flops = 0.0;         // algorithmic flops of the method's steps (semi-normal path)
 };
 
 // Host description of the block-sparse interface matrix: subdomain i's rows
 // form the dense block A_i (m_i x s_i); packed column pc is coefA Q_i(:, colA)
 // + coefB Q_i(:, colB) and column pc_gcol[pc] of Qbar.
+// Steps of the blocked Cholesky: each step lists the widths (1..64) of its
+// mutually uncoupled diagonal sub-blocks, in column order.
+using CholPlan = std::vector<std::vector<int>>;
+CholPlan chol_plan_uniform(int nc);   // one 64-column block per step
+
 struct PackedHost {
     int n_sub = 0, nc = 0, total_pc = 0, max_m = 0, max_s = 0;
+    CholPlan steps;   // empty: one 64-column block per step
     std::vector<const double2*> Q;
     std::vector<int> m, s, pc_sub, pc_p, pc_gcol, pc_start;
     std::vector<long> off, roff;
@@ -31,8 +38,11 @@ struct PackedHost {
 // L and Linv (nc x nc, ld nc) get zero upper triangles; W is nc x nc scratch;
 // a breakdown sets *info_dev (first failing pivot, 1-based) if it is zero.
 // Per-launch timing goes to *pr when it is set and enabled.
-void cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
-                          hipStream_t st, Profiler* pr = nullptr);
+// The steps follow `plan` (default: one 64-column block per step); sub-blocks of
+// one step must not couple (G vanishes between them).
+// Returns the algorithmic flops of the factorisation and inverse as computed (dense blocks).
+double cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, int* info_dev, int nc, double shift,
+                            hipStream_t st, Profiler* pr = nullptr, const CholPlan* plan = nullptr);
 
 // Device tables of the packed solve: offsets into a caller's upload image.
 struct PackedTables {

@@ -312,14 +312,22 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
 void launch_znorm2(int m, const double2* v, double* out, hipStream_t st);
 void launch_znormalize(int n, double2* v, double* norm_out, hipStream_t st);
 void launch_scale_cols_checked(double2* A, int m, int n, int lda, const double* s, int* flags, hipStream_t st);
-// One block step (diagonal block kb..kb+nbk-1, nbk <= 64, kb a multiple of 64)
-// of the blocked Cholesky factorisation G + shift I = L L^* and of Z = L^{-1}
-// (W: nc x nc accumulator of the inverse, zero initially; L, Z zero initially):
-// the diagonal factor, the panel of L and the block row of Z, then the
-// trailing Schur update and the inverse accumulation.
-void launch_chol_panel(const double2* G, int nc, int kb, int nbk, double shift, double2* L, double2* Z,
+// One block step of the blocked Cholesky factorisation G + shift I = L L^* and
+// of Z = L^{-1} (W: nc x nc accumulator of the inverse, zero initially; L, Z
+// zero initially): columns kb .. kb+wtot-1 split into nq mutually uncoupled
+// diagonal sub-blocks, sub-block q = kb+off[q] .. kb+off[q+1]-1 (1..64 columns
+// each).  The panel launch factors the sub-blocks, the panel of L below the
+// step and the block rows of Z; the update launch applies the trailing Schur
+// update and the inverse accumulation.
+struct CholStepDev {
+    static constexpr int kMaxQ = 64;
+    int kb, nq, wtot;
+    int off[kMaxQ + 1];
+};
+void launch_chol_panel(const double2* G, int nc, const CholStepDev& sp, double shift, double2* L, double2* Z,
                        const double2* W, int* info, hipStream_t st);
-void launch_chol_update(double2* G, int nc, int kb, int nbk, const double2* L, const double2* Z, double2* W,
+// trailing Schur complement and inverse accumulation after the step kb .. kb+wtot-1
+void launch_chol_update(double2* G, int nc, int kb, int wtot, const double2* L, const double2* Z, double2* W,
                         hipStream_t st);
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
                           const int4* colmap, const double2* coefs, int ncol, double2* Qbar, int ldq, hipStream_t st);
@@ -355,7 +363,6 @@ void launch_packed_ahx(const PackedDevice& d, int total_pc, const double2* Ap, c
                        double2* y, hipStream_t st);
 void launch_packed_ax(const PackedDevice& d, int n_sub, int max_m, int max_s, const double2* Ap, const double2* x,
                       double2 alpha, double2* r, hipStream_t st);
-void launch_scatter_gram(const double2* Gi, int s, const int* gcol, double2* G, int ldg, hipStream_t st);
 // One batch entry of the Gram products A_b^* A_b (A_b: k x n, column-major, ld k):
 // its split-K partials start at P + poff, its column map at gcol + gcol_off.
 struct ZBatch {

@@ -203,9 +203,9 @@ def make_sides(sides: Sequence[Side], d_arrays: Sequence[Optional[np.ndarray]]):
     for i, (s, d) in enumerate(zip(sides, d_arrays)):
         arr[i] = s
         if d is not None:
-            buf = (C128 * len(d))(*[C128(float(v.real), float(v.imag)) for v in d])
+            buf = np.ascontiguousarray(d, dtype=np.complex128)   # same layout as C128 pairs
             keep.append(buf)
-            arr[i].d = ctypes.cast(buf, ctypes.POINTER(C128))
+            arr[i].d = buf.ctypes.data_as(ctypes.POINTER(C128))
         else:
             arr[i].d = ctypes.POINTER(C128)()
     return arr, keep
