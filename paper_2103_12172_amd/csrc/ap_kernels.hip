@@ -139,8 +139,9 @@ tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, con
         for (int u = 0; u < U; ++u) {
             const int m = m0 + u;
             if (m > t) break;
-            const T nr = fr[u] - (lr[u] * yr - li[u] * yi);   // y_{r0-1} = 0 (and l_0 = 0)
-            const T ni = fi[u] - (lr[u] * yi + li[u] * yr);
+            // y = f - l y_prev as two dependent fma per component (y_{r0-1} = 0, l_0 = 0)
+            const T nr = fma(-lr[u], yr, fma(li[u], yi, fr[u]));
+            const T ni = fma(-lr[u], yi, fma(-li[u], yr, fi[u]));
             yr = nr;
             yi = ni;
             o_re[(long)m * W] = yr;
@@ -175,10 +176,15 @@ tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, con
         for (int u = U - 1; u >= 0; --u) {
             const int m = m0 + u;
             if (m > t) continue;
-            const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);   // x_{t+1} does not enter (xr = 0)
-            const T tr = fr[u] - (sr * xr - si * xi), ti = fi[u] - (sr * xi + si * xr);
-            xr = lr[u] * tr - li[u] * ti;
-            xi = lr[u] * ti + li[u] * tr;
+            // x = rr (y - s x_next) = p - q x_next with p = rr y, q = rr s off the dependency chain
+            // (x_{t+1} does not enter: xr = 0 there)
+            const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);
+            const T ppr = fma(lr[u], fr[u], -(li[u] * fi[u])), ppi = fma(lr[u], fi[u], li[u] * fr[u]);
+            const T qr = fma(lr[u], sr, -(li[u] * si)), qi = fma(lr[u], si, li[u] * sr);
+            const T nxr = fma(-qr, xr, fma(qi, xi, ppr));
+            const T nxi = fma(-qr, xi, fma(-qi, xr, ppi));
+            xr = nxr;
+            xi = nxi;
             o_re[(long)m * W] = xr;
             o_im[(long)m * W] = xi;
         }
@@ -267,8 +273,8 @@ tridiag_part_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (g0 + u > me) break;
-                const T nr = vr[u] + (kr[u] * yr - ki[u] * yi), ni = vi[u] + (kr[u] * yi + ki[u] * yr);
-                const T qr = kr[u] * fr - ki[u] * fi, qi = kr[u] * fi + ki[u] * fr;
+                const T nr = fma(kr[u], yr, fma(-ki[u], yi, vr[u])), ni = fma(kr[u], yi, fma(ki[u], yr, vi[u]));
+                const T qr = fma(kr[u], fr, -(ki[u] * fi)), qi = fma(kr[u], fi, ki[u] * fr);
                 yr = nr; yi = ni; fr = qr; fi = qi;
                 o_re[(long)(g0 + u) * W] = yr;
                 o_im[(long)(g0 + u) * W] = yi;
@@ -297,10 +303,10 @@ tridiag_part_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (g0 + u > me) break;
-                const T qr = kr[u] * fr - ki[u] * fi, qi = kr[u] * fi + ki[u] * fr;
+                const T qr = fma(kr[u], fr, -(ki[u] * fi)), qi = fma(kr[u], fi, ki[u] * fr);
                 fr = qr; fi = qi;
-                o_re[(long)(g0 + u) * W] = vr[u] + (fr * Yr - fi * Yi);
-                o_im[(long)(g0 + u) * W] = vi[u] + (fr * Yi + fi * Yr);
+                o_re[(long)(g0 + u) * W] = fma(fr, Yr, fma(-fi, Yi, vr[u]));
+                o_im[(long)(g0 + u) * W] = fma(fr, Yi, fma(fi, Yr, vi[u]));
             }
         }
     }
@@ -314,12 +320,14 @@ tridiag_part_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out
             for (int u = U - 1; u >= 0; --u) {
                 const int m = g0 + u;
                 if (m > me) continue;
+                // x = p - q x_next with p = rr y, q = rr s (off the dependency chain); psi *= -q
                 const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);
-                const T tr = vr[u] - (sr * xr - si * xi), ti = vi[u] - (sr * xi + si * xr);
-                xr = kr[u] * tr - ki[u] * ti;
-                xi = kr[u] * ti + ki[u] * tr;
-                const T qr = -(kr[u] * sr - ki[u] * si), qi = -(kr[u] * si + ki[u] * sr);
-                const T hr = qr * gr - qi * gi, hi = qr * gi + qi * gr;
+                const T ppr = fma(kr[u], vr[u], -(ki[u] * vi[u])), ppi = fma(kr[u], vi[u], ki[u] * vr[u]);
+                const T qr = fma(kr[u], sr, -(ki[u] * si)), qi = fma(kr[u], si, ki[u] * sr);
+                const T nxr = fma(-qr, xr, fma(qi, xi, ppr));
+                const T nxi = fma(-qr, xi, fma(-qi, xr, ppi));
+                xr = nxr; xi = nxi;
+                const T hr = fma(-qr, gr, qi * gi), hi = fma(-qr, gi, -(qi * gr));
                 gr = hr; gi = hi;
                 o_re[(long)m * W] = xr;
                 o_im[(long)m * W] = xi;
@@ -350,11 +358,11 @@ tridiag_part_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out
                 const int m = g0 + u;
                 if (m > me) continue;
                 const T sr = (m == 0) ? s0r : a, si = (m == 0) ? s0i : T(0);
-                const T qr = -(kr[u] * sr - ki[u] * si), qi = -(kr[u] * si + ki[u] * sr);
-                const T hr = qr * gr - qi * gi, hi = qr * gi + qi * gr;
+                const T qr = fma(kr[u], sr, -(ki[u] * si)), qi = fma(kr[u], si, ki[u] * sr);
+                const T hr = fma(-qr, gr, qi * gi), hi = fma(-qr, gi, -(qi * gr));
                 gr = hr; gi = hi;
-                o_re[(long)m * W] = vr[u] + (gr * Xr - gi * Xi);
-                o_im[(long)m * W] = vi[u] + (gr * Xi + gi * Xr);
+                o_re[(long)m * W] = fma(gr, Xr, fma(-gi, Xi, vr[u]));
+                o_im[(long)m * W] = fma(gr, Xi, fma(gi, Xr, vi[u]));
             }
         }
     }
@@ -855,7 +863,7 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
     const double s2 = Sf[(long)(base + rg.q_lo) * W + c];
     const double t1 = Si[(long)c * W + base + rg.q_lo - 2];
     const double t2 = Si[(long)c * W + base + rg.q_lo - 1];
-    const double a = colc[c], s0r = colc[W + c], s0i = colc[2 * W + c];
+    const double a = colc[c];
     const dv2 tw = tf[(long)t * W + c];
     const dv2* lcol = lf + c;
     const dv2* rcol = rf + c;
@@ -880,9 +888,10 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
             load_f(Ln, lcol, s + 1);
 #pragma unroll
             for (int i = 0; i < K; ++i) {
+                // y = ghat - l y as two dependent fma per component
                 const double fr = ghat(m0 + s * K + i);
-                const double nr = fr - (Lc[i].x * yr - Lc[i].y * yi);
-                const double ni = -(Lc[i].x * yi + Lc[i].y * yr);
+                const double nr = fma(-Lc[i].x, yr, fma(Lc[i].y, yi, fr));
+                const double ni = fma(-Lc[i].x, yi, -(Lc[i].y * yr));
                 yr = nr;
                 yi = ni;
             }
@@ -914,23 +923,26 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
         for (int i = 0; i < K; ++i) {
             const int m = min(m0 + s * K + i, t);
             const double fr = ghat(m);
-            const double nr = fr - (Lc[i].x * pr - Lc[i].y * pi);
-            const double ni = -(Lc[i].x * pi + Lc[i].y * pr);
+            const double nr = fma(-Lc[i].x, pr, fma(Lc[i].y, pi, fr));
+            const double ni = fma(-Lc[i].x, pi, -(Lc[i].y * pr));
             pr = nr;
             pi = ni;
             vr[i] = pr;
             vi[i] = pi;
         }
+        // x_m = r_m (y_m - a x_{m+1}) = p_m - q_m x_{m+1} with p = r y and q = r a off the
+        // dependency chain (m >= m0 >= 1: the off-diagonal is the real interior one)
 #pragma unroll
         for (int i = K - 1; i >= 0; --i) {
             const int m = m0 + s * K + i;
             if (m <= t) {
-                const double offr = (m == 0) ? s0r : a, offi = (m == 0) ? s0i : 0.0;
-                const double tr = vr[i] - (offr * xr - offi * xi);
-                const double ti = vi[i] - (offr * xi + offi * xr);
                 const dv2 rm = (m == t) ? tw : Rc[i];
-                xr = rm.x * tr - rm.y * ti;
-                xi = rm.x * ti + rm.y * tr;
+                const double ppr = fma(rm.x, vr[i], -(rm.y * vi[i])), ppi = fma(rm.x, vi[i], rm.y * vr[i]);
+                const double qr = rm.x * a, qi = rm.y * a;
+                const double nxr = fma(-qr, xr, fma(qi, xi, ppr));
+                const double nxi = fma(-qr, xi, fma(-qi, xr, ppi));
+                xr = nxr;
+                xi = nxi;
                 const int so = special_out(rg, m);
                 if (so >= 0) {
                     xs_re[(long)so * W] = xr;

@@ -515,37 +515,92 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             }
         }
         const int ncol = (int)blocks.size() * M;
-        // Column order of the unknowns: each subdomain's private unknowns (its boundary sides, which no
-        // other subdomain's rows touch, so the Gram matrix vanishes between different subdomains' private
-        // columns) in slices of at most 64 columns, slice l of every subdomain side by side forming
-        // Cholesky step l (its diagonal sub-blocks do not couple), then the interface unknowns in 64-column
-        // steps.  perm maps the column b*M + j of block b to its place in that order.
+        // Column order of the unknowns and the steps of the interface Cholesky.  The unknowns are cut into
+        // slices of at most 64 columns: each subdomain's private unknowns (its boundary sides), and the
+        // unknowns of each interface.  Two slices couple in the Gram matrix only if some subdomain's rows
+        // touch both, i.e. if they share a subdomain.  A symbolic elimination groups the slices into steps:
+        // each step takes slices that are mutually uncoupled in the current (filled) coupling graph, so that
+        // their diagonal blocks factor independently in one launch; eliminating a slice couples all its
+        // remaining neighbours.  A step takes, fewest couplings first, only slices with at most `slack` times
+        // the smallest current coupling count (eliminating a well-connected slice early fills the graph);
+        // the slack giving the fewest steps is kept.  perm maps the column b*M + j of block b to its place.
         std::vector<int> perm(ncol);
         CholPlan chol_steps;
         {
-            std::vector<std::vector<int>> priv(n_sub);
-            std::vector<int> shared;
-            for (size_t b = 0; b < blocks.size(); ++b)
-                for (int j = 0; j < M; ++j) {
-                    if (blocks[b].type != 3) priv[blocks[b].c[0].sub].push_back((int)b * M + j);
-                    else shared.push_back((int)b * M + j);
+            struct Slice { std::vector<int> cols; std::vector<int> subs; };
+            std::vector<Slice> slices;
+            std::map<std::pair<int, int>, std::vector<int>> groups;   // (sub, sub) -> columns (sub, -1: private)
+            for (size_t b = 0; b < blocks.size(); ++b) {
+                const Block& B = blocks[b];
+                int s0 = B.c[0].sub, s1 = -1;
+                for (const Contrib& c : B.c)
+                    if (c.sub != s0) s1 = c.sub;
+                auto& g = groups[{s0, s1}];
+                for (int j = 0; j < M; ++j) g.push_back((int)b * M + j);
+            }
+            for (auto& kv : groups) {
+                const std::vector<int>& cols = kv.second;
+                for (size_t lo = 0; lo < cols.size(); lo += 64) {
+                    Slice sl;
+                    sl.cols.assign(cols.begin() + lo, cols.begin() + std::min(cols.size(), lo + 64));
+                    sl.subs.push_back(kv.first.first);
+                    if (kv.first.second >= 0) sl.subs.push_back(kv.first.second);
+                    slices.push_back(std::move(sl));
                 }
-            size_t levels = 0;
-            for (const auto& v : priv) levels = std::max(levels, (v.size() + 63) / 64);
+            }
+            const int ns = (int)slices.size();
+            std::vector<std::vector<char>> adj0(ns, std::vector<char>(ns, 0));
+            for (int u = 0; u < ns; ++u)
+                for (int v = 0; v < ns; ++v)
+                    if (u != v)
+                        for (int a1 : slices[u].subs)
+                            for (int a2 : slices[v].subs)
+                                if (a1 == a2) adj0[u][v] = 1;
+            auto schedule = [&](double slack) {
+                std::vector<std::vector<int>> steps;
+                std::vector<std::vector<char>> adj = adj0;
+                std::vector<char> done(ns, 0);
+                for (int left = ns; left > 0;) {
+                    std::vector<int> order, deg(ns, 0);
+                    for (int u = 0; u < ns; ++u) {
+                        if (done[u]) continue;
+                        order.push_back(u);
+                        for (int v = 0; v < ns; ++v) deg[u] += (!done[v] && adj[u][v]);
+                    }
+                    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return deg[x] < deg[y]; });
+                    const double cap = slack * std::max(deg[order[0]], 1);
+                    std::vector<int> pick;
+                    for (int u : order) {
+                        if (deg[u] > cap) break;
+                        bool ok = true;
+                        for (int v : pick) ok = ok && !adj[u][v];
+                        if (ok) pick.push_back(u);
+                    }
+                    for (int u : pick) {   // the eliminated slice's remaining neighbours become coupled
+                        done[u] = 1;
+                        --left;
+                        for (int v = 0; v < ns; ++v)
+                            for (int w2 = 0; w2 < ns; ++w2)
+                                if (v != w2 && !done[v] && !done[w2] && adj[u][v] && adj[u][w2]) adj[v][w2] = 1;
+                    }
+                    steps.push_back(pick);
+                }
+                return steps;
+            };
+            std::vector<std::vector<int>> best;
+            for (double slack : {1.0, 1.5, 2.0, 3.0, 1e9}) {
+                auto st = schedule(slack);
+                if (best.empty() || st.size() < best.size()) best = st;
+            }
             int next = 0;
-            for (size_t l = 0; l < levels; ++l) {
+            for (const auto& step : best) {
                 std::vector<int> widths;
-                for (const auto& v : priv) {
-                    const size_t lo = 64 * l, hi = std::min(v.size(), lo + 64);
-                    if (lo >= hi) continue;
-                    for (size_t e = lo; e < hi; ++e) perm[v[e]] = next++;
-                    widths.push_back((int)(hi - lo));
+                for (int u : step) {
+                    for (int c : slices[u].cols) perm[c] = next++;
+                    widths.push_back((int)slices[u].cols.size());
                 }
                 chol_steps.push_back(widths);
             }
-            const int kb0 = next;
-            for (int c : shared) perm[c] = next++;
-            for (int kb = kb0; kb < ncol; kb += 64) chol_steps.push_back({std::min(64, ncol - kb)});
         }
         std::vector<int> row_off(n_sub + 1, 0);
         for (int i = 0; i < n_sub; ++i) row_off[i + 1] = row_off[i] + P[i]->g.n_gamma;
