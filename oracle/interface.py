@@ -1,7 +1,8 @@
 """Coupling of the subdomains and the least-squares solve.  Test infrastructure only.
 
 Follows paper Sec. 3.3-3.5:
-  * the per-subdomain systems Q^(i) c^(i) = F^(i) (F = 0 for f = 0) are stacked
+  * the per-subdomain systems Q^(i) c^(i) = F^(i) (F^(i) from the source term,
+    eq. linear_system_equations; zero for f = 0) are stacked
     block-diagonally (eqs. 2_block_system, N_block_system);
   * boundary conditions alpha c^(0) + beta c^(1) = d on every boundary side
     (eq. BC_coefficients) and interface conditions c^(0)_a = c^(0)_b,
@@ -60,14 +61,19 @@ def plan_unknowns(sides, m_star):
     return blocks
 
 
-def assemble(Qs, sides, d, m_star):
-    """Reduced system (Qbar, Fbar) from per-subdomain Q matrices and boundary coefficients d[i][s]."""
+def assemble(Qs, sides, d, m_star, F_src=None):
+    """Reduced system (Qbar, Fbar) from per-subdomain Q matrices, boundary coefficients d[i][s]
+    and the per-subdomain right-hand sides F_src[i] of the source term (None: f = 0)."""
     N = len(sides)
     rows = [Q.shape[0] for Q in Qs]
     off = np.concatenate([[0], np.cumsum(rows)])
     blocks = plan_unknowns(sides, m_star)
     Qbar = np.zeros((off[-1], len(blocks) * m_star), dtype=complex)
     Fbar = np.zeros(off[-1], dtype=complex)
+    if F_src is not None:
+        for i in range(N):
+            if F_src[i] is not None:
+                Fbar[off[i]:off[i + 1]] += F_src[i]
     for b, (_, contrib) in enumerate(blocks):
         for (i, s, kind, coef) in contrib:
             Qbar[off[i]:off[i + 1], b * m_star:(b + 1) * m_star] += coef * Qs[i][:, _cols(m_star, s, kind)]
@@ -144,8 +150,8 @@ def householder_qr_solve(A, b):
     return x, R, res
 
 
-def solve_interface(Qs, sides, d, m_star):
-    Qbar, Fbar, blocks = assemble(Qs, sides, d, m_star)
+def solve_interface(Qs, sides, d, m_star, F_src=None):
+    Qbar, Fbar, blocks = assemble(Qs, sides, d, m_star, F_src)
     x, R, res = householder_qr_solve(Qbar, Fbar)
     c = expand(x, sides, d, m_star, blocks)
     info = {"rows": Qbar.shape[0], "cols": Qbar.shape[1], "residual": res,

@@ -17,7 +17,7 @@ Geometry conventions (paper Sec. 3.3-3.4):
     side of a neighbouring subdomain (Sec. 3.3.2);
   * the auxiliary grid has n cells per direction.
 
-Test solutions (all homogeneous, f = 0):
+Test solutions of the homogeneous equation (f = 0):
   * plane wave exp(i k (x cos(theta) + y sin(theta)));
   * the piecewise plane wave of Appendix A: in strip i,
     a_i exp(i k_i x) + b_i exp(-i k_i x), amplitudes fixed by continuity of u
@@ -27,6 +27,20 @@ Test solutions (all homogeneous, f = 0):
     condition; the amplitudes here come from solving the appendix's linear
     system directly, which for two strips gives R = (k1-k2)/(k1+k2) and
     T = 2 k1/(k1+k2).
+
+Problems with a source f (eq. helmholtz, Delta u + k^2 u = f):
+  * a manufactured plane wave exp(i (a x + b y)) with a^2 + b^2 != k^2, so that
+    f = (k^2 - a^2 - b^2) u;
+  * sin^4(pi x) sin(pi y) (a test solution of Table uniform_2), f = Delta u + k^2 u
+    in closed form;
+  * the compactly supported bump of eq. source_bump with homogeneous boundary
+    data (no exact solution; grid self-convergence).  Reading: the printed
+    support x^2 + y^2 < 1/2 does not match the singular point of the exponent,
+    r^2 = 1/4; the support used is r^2 < 1/4 (the function and all its
+    derivatives vanish there, so f is smooth).
+A source is described by f(x, y) (sampled on the auxiliary grids) and its jet
+at boundary points with outward normal (nx, ny): (f, df/dn, d2f/dn2 - d2f/dtau2),
+the terms of the equation-based extension that involve f (eqs. cart_ext_2-4).
 """
 from __future__ import annotations
 
@@ -71,6 +85,8 @@ class Workload:
     precision: str = "c128"   # compute precision of the AP solves: c128 | c64 | c64r
     notes: str = ""
     extra: dict = field(default_factory=dict)
+    source: Optional[Callable] = None      # f(x, y) -> complex ndarray (None: f = 0)
+    source_jet: Optional[Callable] = None  # (x, y, nx, ny) -> (f, df/dn, d2f/dn2 - d2f/dtau2)
 
 
 # ----------------------------------------------------------------- solutions
@@ -85,6 +101,110 @@ def plane_wave(k: float, theta: float):
         return 1j * k * c * v, 1j * k * s * v
 
     return u, grad
+
+
+def manufactured_plane_wave(k: float, a: float, b: float):
+    """u = exp(i (a x + b y)) and its source f = (k^2 - a^2 - b^2) u with the jet of f."""
+    amp = k * k - a * a - b * b
+
+    def u(x, y):
+        return np.exp(1j * (a * np.asarray(x) + b * np.asarray(y)))
+
+    def grad(x, y):
+        v = u(x, y)
+        return 1j * a * v, 1j * b * v
+
+    def f(x, y):
+        return amp * u(x, y)
+
+    def jet(x, y, nx, ny):
+        v = f(x, y)
+        dn = a * nx + b * ny            # derivative along the normal: i dn
+        dt = -a * ny + b * nx           # along the tangent (-ny, nx)
+        return v, 1j * dn * v, (-dn * dn + dt * dt) * v
+
+    return u, grad, f, jet
+
+
+def sin4_solution(k: float):
+    """u = sin^4(pi x) sin(pi y), f = Delta u + k^2 u = sin(pi y) P(x) with
+    P = 3 pi^2/2 (1 - cos 4 pi x) + (k^2 - 5 pi^2)/8 (3 - 4 cos 2 pi x + cos 4 pi x)."""
+    pi = math.pi
+    c1 = 1.5 * pi * pi
+    c2 = (k * k - 5.0 * pi * pi) / 8.0
+
+    def u(x, y):
+        return (np.sin(pi * np.asarray(x)) ** 4 * np.sin(pi * np.asarray(y))).astype(complex)
+
+    def grad(x, y):
+        x, y = np.asarray(x), np.asarray(y)
+        sx = np.sin(pi * x)
+        return ((4.0 * pi * sx ** 3 * np.cos(pi * x) * np.sin(pi * y)).astype(complex),
+                (pi * sx ** 4 * np.cos(pi * y)).astype(complex))
+
+    def P(x, d=0):
+        c2x, c4x = np.cos(2 * pi * x), np.cos(4 * pi * x)
+        s2x, s4x = np.sin(2 * pi * x), np.sin(4 * pi * x)
+        if d == 0:
+            return c1 * (1.0 - c4x) + c2 * (3.0 - 4.0 * c2x + c4x)
+        if d == 1:
+            return c1 * 4 * pi * s4x + c2 * (8 * pi * s2x - 4 * pi * s4x)
+        return c1 * 16 * pi * pi * c4x + c2 * (16 * pi * pi * c2x - 16 * pi * pi * c4x)
+
+    def f(x, y):
+        x, y = np.asarray(x), np.asarray(y)
+        return (np.sin(pi * y) * P(x)).astype(complex)
+
+    def jet(x, y, nx, ny):
+        x, y = np.asarray(x, dtype=float), np.asarray(y, dtype=float)
+        sy, cy = np.sin(pi * y), np.cos(pi * y)
+        fx, fy = sy * P(x, 1), pi * cy * P(x)
+        fxx, fyy, fxy = sy * P(x, 2), -pi * pi * sy * P(x), pi * cy * P(x, 1)
+        tx, ty = -ny, nx
+        fn = nx * fx + ny * fy
+        fnn = nx * nx * fxx + 2 * nx * ny * fxy + ny * ny * fyy
+        ftt = tx * tx * fxx + 2 * tx * ty * fxy + ty * ty * fyy
+        return f(x, y), fn.astype(complex), (fnn - ftt).astype(complex)
+
+    return u, grad, f, jet
+
+
+def bump_source(x0: float = 0.0, y0: float = 0.0):
+    """f = exp(-1/(1/4 - r^2)) for r^2 = (x-x0)^2 + (y-y0)^2 < 1/4, else 0 (eq. source_bump,
+    support read as r^2 < 1/4), with its jet: f_x = f * dE/dx for the exponent E = -1/(1/4 - r^2)."""
+
+    def f(x, y):
+        x, y = np.asarray(x, dtype=float), np.asarray(y, dtype=float)
+        r2 = (x - x0) ** 2 + (y - y0) ** 2
+        out = np.zeros(np.broadcast(x, y).shape, dtype=complex)
+        inside = r2 < 0.25
+        d = 0.25 - r2[inside] if np.ndim(r2) else 0.25 - r2
+        if np.ndim(r2):
+            out[inside] = np.exp(-1.0 / d)
+            return out
+        return complex(np.exp(-1.0 / d)) if inside else 0j
+
+    def jet(x, y, nx, ny):
+        x, y = np.asarray(x, dtype=float), np.asarray(y, dtype=float)
+        X, Y = x - x0, y - y0
+        r2 = X * X + Y * Y
+        inside = r2 < 0.25
+        d = np.where(inside, 0.25 - r2, 1.0)
+        e = np.where(inside, np.exp(-1.0 / d), 0.0)
+        # E = -1/d, dE/dx = -2X/d^2, d2E/dx2 = -2/d^2 - 8X^2/d^3, d2E/dxdy = -8XY/d^3
+        Ex, Ey = -2 * X / d ** 2, -2 * Y / d ** 2
+        Exx = -2 / d ** 2 - 8 * X * X / d ** 3
+        Eyy = -2 / d ** 2 - 8 * Y * Y / d ** 3
+        Exy = -8 * X * Y / d ** 3
+        fx, fy = e * Ex, e * Ey
+        fxx, fyy, fxy = e * (Exx + Ex * Ex), e * (Eyy + Ey * Ey), e * (Exy + Ex * Ey)
+        tx, ty = -ny, nx
+        fn = nx * fx + ny * fy
+        fnn = nx * nx * fxx + 2 * nx * ny * fxy + ny * ny * fyy
+        ftt = tx * tx * fxx + 2 * tx * ty * fxy + ty * ty * fyy
+        return e.astype(complex), fn.astype(complex), (fnn - ftt).astype(complex)
+
+    return f, jet
 
 
 def piecewise_amplitudes(interfaces: List[float], ks: List[float]) -> Tuple[np.ndarray, np.ndarray]:
@@ -283,6 +403,45 @@ def config_paper_jump(n: int = 64, k1: float = 5.0, k2: float = 13.0, m_star: in
     subs, sides = grid_topology(2, 1, -1.0, -1.0, 2.0, 2.0, [k1, k2], n, lambda ix, iy, s: (1.0, 0.0))
     u, g, a, b = piecewise_plane_wave([1.0], [k1, k2])
     return Workload("paper_jump_%g_%g_n%d" % (k1, k2, n), subs, sides, m_star, u, g, "c128")
+
+
+def config_paper_sin4(n: int = 64, k: float = 13.0, m_star: int = 40) -> Workload:
+    """Two squares of side 2 (interface at x = 1), Robin alpha = beta = 1, the
+    inhomogeneous test solution sin^4(pi x) sin(pi y) of Table uniform_2."""
+    subs, sides = grid_topology(2, 1, -1.0, -1.0, 2.0, 2.0, [k, k], n, lambda ix, iy, s: (1.0, 1.0))
+    u, g, f, jet = sin4_solution(k)
+    return Workload("paper_sin4_n%d" % n, subs, sides, m_star, u, g, "c128", source=f, source_jet=jet,
+                    notes="2 squares of side 2, k=%g, n=%d, M*=%d, Robin 1/1, u = sin^4(pi x) sin(pi y)"
+                    % (k, n, m_star))
+
+
+def config_source_plane(n: int = 64, k: float = 10.0, m_star: int = 16, a: float = 6.0, b: float = 5.0) -> Workload:
+    """The 2x1 rectangles of two_rect with the manufactured wave exp(i(a x + b y)),
+    a^2 + b^2 != k^2, and its source; Dirichlet data."""
+    subs, sides = grid_topology(2, 1, 0.0, 0.0, 0.5, 1.0, [k, k], n, lambda ix, iy, s: (1.0, 0.0))
+    u, g, f, jet = manufactured_plane_wave(k, a, b)
+    return Workload("source_plane_n%d" % n, subs, sides, m_star, u, g, "c128", source=f, source_jet=jet,
+                    notes="2x1 rectangles, k=%g, n=%d, M*=%d, Dirichlet, u = exp(i(%gx+%gy)) with its source"
+                    % (k, n, m_star, a, b))
+
+
+def config_bump(n: int = 128, k: float = 20.0, m_star: int = 32) -> Workload:
+    """2x2 squares of side 0.5 with the bump source centred at the cross-point
+    (0.5, 0.5) and homogeneous Dirichlet data; no exact solution (exact = 0 is
+    only a placeholder for the boundary data)."""
+    subs, sides = grid_topology(2, 2, 0.0, 0.0, 0.5, 0.5, [k] * 4, n, lambda ix, iy, s: (1.0, 0.0))
+    f, jet = bump_source(0.5, 0.5)
+
+    def zero(x, y):
+        return np.zeros(np.broadcast(np.asarray(x), np.asarray(y)).shape, dtype=complex)
+
+    def zero_grad(x, y):
+        z = zero(x, y)
+        return z, z
+
+    return Workload("bump_n%d" % n, subs, sides, m_star, zero, zero_grad, "c128", source=f, source_jet=jet,
+                    notes="2x2 squares, k=%g, n=%d, M*=%d, Dirichlet 0, bump source at the cross-point"
+                    % (k, n, m_star))
 
 
 WORKLOADS = {
