@@ -3,15 +3,17 @@
  * Method of Difference Potentials (MDP) applied to non-overlapping domain
  * decomposition of the Helmholtz equation
  *     Delta u + k^2 u = f  in Omega,   alpha u + beta du/dn = phi  on dOmega
- * (North, Tsynkov & Turkel, Sec. 3, eq. helmholtz_physical), here with f = 0.
+ * (North, Tsynkov & Turkel, Sec. 3, eq. helmholtz_physical).
  *
  * The three calls follow the algorithm summary of Sec. 3.5:
  *   step 1b  mdp_build_projector  -- Q^(i) = [(P_gamma - I) Ex Psi_j], one
  *                                    auxiliary-problem (AP) solve per column;
  *   step 2   mdp_solve_interface  -- boundary and interface conditions
  *                                    eliminated in coefficient space, least
- *                                    squares for the coefficients c;
- *   step 3   mdp_reconstruct      -- u = P_{N+} Ex(c) on each subdomain.
+ *                                    squares for the coefficients c (with
+ *                                    step 1c, the source's right-hand side F,
+ *                                    when a source f is given);
+ *   step 3   mdp_reconstruct      -- u = P_{N+} Ex(c) (+ G B f) on each subdomain.
  * mdp_ap_solve exposes G^(h), the AP solve itself (Sec. 3.2.1), on a batch of
  * right-hand sides.
  *
@@ -139,6 +141,37 @@ int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int p
 int mdp_projector_info(const mdp_projector* P, int* n_gamma, const int** gamma_mq,
                        const mdp_c128** q_dev);
 
+/* Foot points of gamma for the source data of mdp_source: for gamma node i
+ * (order of mdp_projector_info) on side s of the rectangle sd (the subdomain
+ * the projector serves; it may sit anywhere), xy_out[2i], xy_out[2i+1] is the
+ * point of the side's line at the node's side parameter (the node projected
+ * onto the line, not clamped to the side) and side_out[i] = s (0 bottom,
+ * 1 top, 2 left, 3 right; outward normal of that side).  Host arrays of
+ * 2*n_gamma doubles and n_gamma ints; side_out may be NULL.
+ * Errors: MDP_ERR_ARG (null pointers, sd of another size). */
+int mdp_projector_gamma_feet(const mdp_projector* P, const mdp_subdomain* sd, double* xy_out, int* side_out);
+
+/* Host helper: the auxiliary grid of the rectangle sd (Sec. 3.2.1; the square
+ * of side 1.1*max(lx, ly) centred on it, n = sd->n cells per direction): node
+ * (m, q) sits at (xa + m h, ya + q h).  Errors: MDP_ERR_ARG (null pointers,
+ * non-positive or non-finite sizes, n odd or < 8). */
+int mdp_ap_grid(const mdp_subdomain* sd, double* xa, double* ya, double* h);
+
+/* Source f of Delta u + k^2 u = f on one subdomain (eq. helmholtz; Sec. 3.5
+ * step 1c).  Device arrays, caller-owned, complex128:
+ *   f    f at every node of the subdomain's auxiliary grid, (n+1)^2, index
+ *        m*(n+1)+q (only the nodes of N+ are read), for the scheme's
+ *        right-hand side B^(h) f (eq. rhs_g);
+ *   jet  3*n_gamma: at the foot point of gamma node i (mdp_projector_gamma_feet),
+ *        jet[i] = f, jet[n_gamma+i] = df/dn (outward normal),
+ *        jet[2*n_gamma+i] = d2f/dn2 - d2f/dtau2, for the inhomogeneous part of
+ *        the extension Ex^(I) f (eqs. cart_ext_2-4, extension_split).
+ * A NULL f marks a subdomain without source. */
+typedef struct {
+    const mdp_c128* f;
+    const mdp_c128* jet;
+} mdp_source;
+
 /* Drop one reference; the projector is freed with its last reference (the
  * context's cache holds one of its own until mdp_destroy). NULL is a no-op. */
 void mdp_projector_release(mdp_projector* P);
@@ -151,7 +184,10 @@ void mdp_projector_release(mdp_projector* P);
  * (eq. transmission_coefficients) are resolved by elimination (Sec. 3.3.3),
  * giving the reduced system Qbar c = Fbar with sum|gamma_i| rows and
  * 4*n_sub*M* columns, which is solved in the least-squares sense (steps
- * 2b-2c) in FP64 on the device.
+ * 2b-2c) in FP64 on the device.  sources (host, n_sub entries, or NULL for
+ * f = 0 everywhere) add each subdomain's right-hand side
+ * F = (I - P_gamma) Ex^(I) f - Tr G^(h) B^(h) f (eq. linear_system_equations;
+ * step 1c, one AP solve per subdomain with a source) to Fbar.
  * c_out (device, caller-owned, 8M* complex per subdomain, subdomain-major, each
  * in the column order of Q) receives every coefficient, known and solved.
  * rel_residual_out (host, may be NULL) = ||Qbar c - Fbar|| / ||Fbar||;
@@ -164,12 +200,16 @@ void mdp_projector_release(mdp_projector* P);
  * alpha = beta = 0, M* or rectangle different from the projectors', null d),
  * MDP_ERR_NONFINITE, MDP_ERR_SINGULAR (the factor of Qbar broke down), MDP_ERR_OOM, MDP_ERR_HIP. */
 int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs,
-                        const mdp_projector* const* P, const mdp_side* sides, int m_star, void* stream,
-                        mdp_c128* c_out, double* rel_residual_out, double* cond_estimate_out);
+                        const mdp_projector* const* P, const mdp_side* sides, int m_star,
+                        const mdp_source* sources, void* stream, mdp_c128* c_out, double* rel_residual_out,
+                        double* cond_estimate_out);
 
 /* Step 3 of Sec. 3.5 for n_sub subdomains: xi_gamma = Ex(sum_j c_j Psi_j) and
  * u = P_{N+} xi_gamma = w - G^(h)(L^(h) w |_{M+}) (eqs. Potential_def,
- * potential_solution_homo).  c (device) holds 8M* coefficients per subdomain
+ * potential_solution_homo); with sources (host, n_sub entries, or NULL),
+ * xi_gamma also holds Ex^(I) f and u = P_{N+} xi_gamma + G^(h) B^(h) f =
+ * w - G^(h)((L^(h) w - B^(h) f) |_{M+}) (eq. potential_solution).  c (device)
+ * holds 8M* coefficients per subdomain
  * as written by mdp_solve_interface; u_out (device, caller-owned) receives
  * subdomain i's grid function at offset sum_{l<i} (n_l+1)^2 (complex); it is
  * the solution on N+, the difference potential at the other nodes of the grid
@@ -178,7 +218,7 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs,
  * Subdomains sharing a projector are solved in one batch.
  * Errors: MDP_ERR_ARG, MDP_ERR_OOM, MDP_ERR_HIP. */
 int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P,
-                    const mdp_c128* c, void* stream, mdp_c128* u_out);
+                    const mdp_c128* c, const mdp_source* sources, void* stream, mdp_c128* u_out);
 
 /* G^(h) of Sec. 3.2.1 on `batch` right-hand sides: solves the discrete AP
  * (eq. discrete_AP: the compact scheme at interior nodes, u = 0 on q = 0, n,

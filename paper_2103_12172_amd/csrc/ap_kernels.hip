@@ -53,12 +53,24 @@ struct SrcEval {
         C64 c = wgrid(b, m, q);
         return {sc.c0 * c.re + sc.ce * e.re + sc.cc * k.re, sc.c0 * c.im + sc.ce * e.im + sc.cc * k.im};
     }
+    // B^(h) f at an M+ node (eq. rhs_g) from entry b's source grid
+    __device__ inline C64 bsource(const double* fg, int m, int q) const {
+        auto at = [&](int mm, int qq) -> C64 {
+            const double* p = fg + 2 * ((long)mm * (n + 1) + qq);
+            return {p[0], p[1]};
+        };
+        const C64 c = at(m, q);
+        const C64 e = cadd(cadd(at(m + 1, q), at(m - 1, q)), cadd(at(m, q + 1), at(m, q - 1)));
+        return {c.re + (e.re - 4.0 * c.re) / 12.0, c.im + (e.im - 4.0 * c.im) / 12.0};
+    }
     // right-hand side g(m, q) of the AP at an interior node (zero on the end rows)
     __device__ inline C64 rhs(int b, int m, int q) const {
         if (m <= 0 || m >= n || q <= 0 || q >= n) return {0.0, 0.0};
         if (d.kind == Src::GRID) return wgrid(b, m, q);
         if (!in_mplus(m, q)) return {0.0, 0.0};
-        return stencil(b, m, q);
+        C64 v = stencil(b, m, q);
+        if (d.kind == Src::STENCIL_GRID && d.fsrc && d.fsrc[b]) v = csub(v, bsource(d.fsrc[b], m, q));
+        return v;
     }
 };
 
@@ -536,6 +548,47 @@ __global__ void extend_density_kernel(const double* __restrict__ E, int ng, int 
     o[1] = im;
 }
 
+// Inhomogeneous part of the extension (eqs. general_extension, cart_ext_2-4, extension_split):
+// at gamma node i of entry b, rho^2/2 f + rho^3/6 df/dn + rho^4/24 (d2f/dn2 - d2f/dtau2 - k^2 f)
+// from the entry's jet (f, df/dn, d2f/dn2 - d2f/dtau2 at the node's foot point).
+__global__ void source_extension_kernel(const double* __restrict__ rho, const int* __restrict__ gm,
+                                        const int* __restrict__ gq, int ng, int n, double k,
+                                        const double* const* __restrict__ jet, double* w,
+                                        const long* __restrict__ woff, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    const double* J = jet[b];
+    if (i >= ng || !J) return;
+    const double r = rho[i], r2 = r * r;
+    const double f0r = J[2 * i], f0i = J[2 * i + 1];
+    const double fnr = J[2 * (ng + i)], fni = J[2 * (ng + i) + 1];
+    const double ftr = J[2 * (2 * ng + i)], fti = J[2 * (2 * ng + i) + 1];
+    const double a = 0.5 * r2, bb = r2 * r / 6.0, c = r2 * r2 / 24.0;
+    const double vr = a * f0r + bb * fnr + c * (ftr - k * k * f0r);
+    const double vi = a * f0i + bb * fni + c * (fti - k * k * f0i);
+    double* o = w + 2 * (woff[b] + (long)gm[i] * (n + 1) + gq[i]);
+    if (accumulate) {
+        o[0] += vr;
+        o[1] += vi;
+    } else {
+        o[0] = vr;
+        o[1] = vi;
+    }
+}
+
+// F[foff[b] + i] += u_b(gamma_i): the trace of an AP solution added to a right-hand side
+template <class T>
+__global__ void gather_add_kernel(const T* __restrict__ u, Fold f, Band bd, const int* __restrict__ gm,
+                                  const int* __restrict__ gq, int ng, double* F, const long* __restrict__ foff) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= ng) return;
+    const C64 v = unfold_c(u, f, bd, b, gm[i], gq[i]);
+    double* o = F + 2 * (foff[b] + i);
+    o[0] += v.re;
+    o[1] += v.im;
+}
+
 // Extension matrix E = Ex Psi (Sec. 3.2.3-3.2.4, eqs. general_extension,
 // cartesian_extension, Psi_def): column-major |gamma| x 8M*, zero outside the
 // node's side.  For gamma node i on side s, at signed distance rho from the
@@ -674,6 +727,32 @@ void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, Band 
                        out_stride, boff);
     MDP_HIP(hipGetLastError());
 }
+
+void launch_source_extension(const double* rho, const int* gm, const int* gq, int ng, int n, double k,
+                             const double* const* jet, int R, double* w, const long* woff, bool accumulate,
+                             hipStream_t st) {
+    check_batch(R);
+    if (ng <= 0 || R <= 0) return;
+    dim3 grid((ng + 255) / 256, R);
+    hipLaunchKernelGGL(source_extension_kernel, grid, dim3(256), 0, st, rho, gm, gq, ng, n, k, jet, w, woff,
+                       accumulate ? 1 : 0);
+    MDP_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_gather_add(const T* u, int n, const Fold& f, Band bd, const int* gm, const int* gq, int ng, int R,
+                       double* F, const long* foff, hipStream_t st) {
+    check_batch(R);
+    check_band(bd, n);
+    if (ng <= 0 || R <= 0) return;
+    dim3 grid((ng + 255) / 256, R);
+    hipLaunchKernelGGL(gather_add_kernel<T>, grid, dim3(256), 0, st, u, f, bd, gm, gq, ng, F, foff);
+    MDP_HIP(hipGetLastError());
+}
+template void launch_gather_add<double>(const double*, int, const Fold&, Band, const int*, const int*, int, int,
+                                        double*, const long*, hipStream_t);
+template void launch_gather_add<float>(const float*, int, const Fold&, Band, const int*, const int*, int, int,
+                                       double*, const long*, hipStream_t);
 
 void launch_extend_density(const double* E, int ng, int ncol, const double* c, const int* cidx, int R, const int* gm,
                            const int* gq, const int* gside, int n, double* w, long w_stride, const long* woff,

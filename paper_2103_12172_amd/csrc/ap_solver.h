@@ -39,6 +39,7 @@ struct PackedWork {
 // Interface assembly and reconstruction buffers (grow-only).
 struct CallWork {
     DevBuf F, x;          // mdp_solve_interface
+    DevBuf srcw;          // mdp_solve_interface: densities Ex^(I) f of the source right-hand sides
 };
 
 // Grow-only device workspaces of a context.

@@ -426,6 +426,41 @@ int mdp_projector_info(const mdp_projector* P, int* n_gamma, const int** gamma_m
     return MDP_OK;
 }
 
+int mdp_ap_grid(const mdp_subdomain* sd, double* xa, double* ya, double* h) {
+    if (!sd || !xa || !ya || !h) return MDP_ERR_ARG;
+    try {
+        const Geometry g = make_geometry(sd->x0, sd->y0, sd->lx, sd->ly, sd->n);
+        *xa = g.xa;
+        *ya = g.ya;
+        *h = g.h;
+        return MDP_OK;
+    } catch (const Error& e) {
+        return e.code;
+    }
+}
+
+int mdp_projector_gamma_feet(const mdp_projector* P, const mdp_subdomain* sd, double* xy_out, int* side_out) {
+    if (!P || !sd || !xy_out) return MDP_ERR_ARG;
+    const Geometry& g = P->g;
+    if (sd->lx != g.lx || sd->ly != g.ly) return MDP_ERR_ARG;
+    for (int i = 0; i < g.n_gamma; ++i) {
+        const int s = g.side[i];
+        const double t = g.t[i];
+        double x, y;
+        if (s == 0 || s == 1) {
+            x = sd->x0 + 0.5 * (t + 1.0) * sd->lx;
+            y = (s == 0) ? sd->y0 : sd->y0 + sd->ly;
+        } else {
+            y = sd->y0 + 0.5 * (t + 1.0) * sd->ly;
+            x = (s == 2) ? sd->x0 : sd->x0 + sd->lx;
+        }
+        xy_out[2 * i] = x;
+        xy_out[2 * i + 1] = y;
+        if (side_out) side_out[i] = s;
+    }
+    return MDP_OK;
+}
+
 void mdp_projector_release(mdp_projector* P) {
     if (!P) return;
     if (P->refs.fetch_sub(1) == 1) {
@@ -461,8 +496,8 @@ void side_segment(const mdp_subdomain& sd, int s, double* seg) {
 }  // namespace
 
 int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, const mdp_projector* const* P,
-                        const mdp_side* sides, int m_star, void* stream, mdp_c128* c_out, double* rel_residual_out,
-                        double* cond_estimate_out) {
+                        const mdp_side* sides, int m_star, const mdp_source* sources, void* stream, mdp_c128* c_out,
+                        double* rel_residual_out, double* cond_estimate_out) {
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
     return guarded(ctx, [&]() -> int {
         if (n_sub < 1 || !subs || !P || !sides || !c_out) throw Error(MDP_ERR_ARG, "null or empty arguments");
@@ -720,17 +755,47 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
         }
         ph.total_pc = (int)ph.pc_sub.size();
 
+        // step 1c: subdomains with a source, grouped by projector (one batched AP solve per group)
+        struct SrcGroup { const mdp_projector* P; int R; size_t e0; };
+        std::vector<SrcGroup> src_groups;
+        std::vector<const double*> s_f, s_jet;
+        std::vector<long> s_goff, s_foff;
+        long srcw_elems = 0;
+        if (sources) {
+            std::vector<bool> used(n_sub, false);
+            for (int i = 0; i < n_sub; ++i) {
+                if (!sources[i].f || used[i]) continue;
+                SrcGroup sg{P[i], 0, s_f.size()};
+                const long npts = (long)(P[i]->g.n + 1) * (P[i]->g.n + 1);
+                for (int j = i; j < n_sub; ++j) {
+                    if (P[j] != P[i] || !sources[j].f) continue;
+                    if (!sources[j].jet) throw Error(MDP_ERR_ARG, "source without its boundary jet");
+                    used[j] = true;
+                    s_f.push_back(reinterpret_cast<const double*>(sources[j].f));
+                    s_jet.push_back(reinterpret_cast<const double*>(sources[j].jet));
+                    s_goff.push_back(srcw_elems);
+                    s_foff.push_back(row_off[j]);
+                    srcw_elems += npts;
+                    ++sg.R;
+                }
+                src_groups.push_back(sg);
+            }
+        }
+
         begin_call(ctx, st);
         CallWork& cw = ctx->ws.cw;
         DevBuf &F = cw.F, &x = cw.x;
         ensure(F, (size_t)m * sizeof(double2));
         ensure(x, (size_t)ncol * sizeof(double2));
+        if (srcw_elems) ensure(cw.srcw, (size_t)srcw_elems * sizeof(double2));
         // every table of the call in one upload
         HostBlob blob;
         const size_t o_qsrc = blob.put(qsrc), o_qld = blob.put(qld), o_roff = blob.put(row_off),
                      o_cmap = blob.put(colmap), o_coef = blob.put(coefs), o_kcol = blob.put(kcol),
                      o_kval = blob.put(kval), o_koff = blob.put(koff), o_esrc = blob.put(esrc),
                      o_ecoef = blob.put(ecoef), o_eknown = blob.put(eknown);
+        const size_t o_sf = blob.put(s_f), o_sjet = blob.put(s_jet), o_sgoff = blob.put(s_goff),
+                     o_sfoff = blob.put(s_foff);
         const PackedTables tabs = ls_packed_tables(ctx->ws, ph, blob);
         const char* img = ctx->ws.stage.upload(blob, st);
         auto dq = reinterpret_cast<const double2* const*>(img + o_qsrc);
@@ -739,6 +804,48 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
         launch_known_rhs(dq, dld, n_sub, droff, m, reinterpret_cast<const int*>(img + o_kcol),
                          reinterpret_cast<const double2*>(img + o_kval), reinterpret_cast<const int*>(img + o_koff),
                          F.as<double2>(), st);
+        // F^(i) = Tr G((L w_I - B f)|M+) with w_I = Ex^(I) f on gamma (eq. linear_system_equations:
+        // (I - P_gamma) Ex^(I) f = Tr G(L w_I|M+)), added to subdomain i's rows of Fbar
+        for (const SrcGroup& sg : src_groups) {
+            const mdp_projector* Pi = sg.P;
+            const Geometry& G = Pi->g;
+            const int n = G.n, ng = G.n_gamma;
+            const long npts = (long)(n + 1) * (n + 1);
+            APPlan& plan = get_plan(ctx, n, G.h, Pi->k);
+            double* wb = cw.srcw.as<double>();
+            const long* go = reinterpret_cast<const long*>(img + o_sgoff) + sg.e0;
+            const long* fo = reinterpret_cast<const long*>(img + o_sfoff) + sg.e0;
+            const double* const* fs = reinterpret_cast<const double* const*>(img + o_sf) + sg.e0;
+            const double* const* js = reinterpret_cast<const double* const*>(img + o_sjet) + sg.e0;
+            MDP_HIP(hipMemsetAsync(wb + 2 * s_goff[sg.e0], 0, (size_t)sg.R * npts * sizeof(double2), st));
+            launch_source_extension(Pi->grho, Pi->gm, Pi->gq, ng, n, Pi->k, js, sg.R, wb, go, false, st);
+            const int chunk = chunk_size(plan, Pi->precision, ctx->ws_cap, sg.R);
+            prepare_ws(ctx, plan, Pi->precision, chunk);
+            const Fold f = plan.f;
+            const int prec = Pi->precision;
+            for (int r0 = 0; r0 < sg.R; r0 += chunk) {
+                const int Rc = std::min(chunk, sg.R - r0);
+                SrcDesc src{};
+                src.kind = Src::STENCIL_GRID;
+                src.grid = wb;
+                src.goff = go + r0;
+                src.fsrc = fs + r0;
+                src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
+                solve_batch(plan, ctx->ws, prec, src, true, Rc, box_band(plan, G),
+                            [&](const void* u, const float* du, Band bd) {
+                                double* Fd = reinterpret_cast<double*>(F.p);
+                                if (prec == MDP_C128)
+                                    launch_gather_add<double>((const double*)u, n, f, bd, Pi->gm, Pi->gq, ng, Rc, Fd,
+                                                              fo + r0, st);
+                                else
+                                    launch_gather_add<float>((const float*)u, n, f, bd, Pi->gm, Pi->gq, ng, Rc, Fd,
+                                                             fo + r0, st);
+                                if (du)   // the FP32 correction of a refined solve
+                                    launch_gather_add<float>(du, n, f, bd, Pi->gm, Pi->gq, ng, Rc, Fd, fo + r0, st);
+                            },
+                            st);
+            }
+        }
         LSResult r;
         {
             // the whole least-squares solve as one profiled span (it synchronises internally)
@@ -781,8 +888,8 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
 }
 
 // ---------------------------------------------------------------------------- step 3
-int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, const mdp_c128* c, void* stream,
-                    mdp_c128* u_out) {
+int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, const mdp_c128* c,
+                    const mdp_source* sources, void* stream, mdp_c128* u_out) {
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
     return guarded(ctx, [&]() -> int {
         if (n_sub < 1 || !P || !c || !u_out) throw Error(MDP_ERR_ARG, "null or empty arguments");
@@ -802,14 +909,22 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
                 if (P[j] == P[i]) { grp.push_back(j); done[j] = true; }
             groups.push_back(std::move(grp));
         }
-        // per batch entry: the subdomain (its coefficients in c) and its grid's offset in u_out
+        // per batch entry: the subdomain (its coefficients in c), its grid's offset in u_out and its source
         std::vector<int> cidx;
         std::vector<long> goff;
+        std::vector<const double*> sf, sjet;
         for (const auto& grp : groups)
-            for (int i : grp) { cidx.push_back(i); goff.push_back(off[i]); }
+            for (int i : grp) {
+                cidx.push_back(i);
+                goff.push_back(off[i]);
+                const bool has = sources && sources[i].f;
+                if (has && !sources[i].jet) throw Error(MDP_ERR_ARG, "source without its boundary jet");
+                sf.push_back(has ? reinterpret_cast<const double*>(sources[i].f) : nullptr);
+                sjet.push_back(has ? reinterpret_cast<const double*>(sources[i].jet) : nullptr);
+            }
         begin_call(ctx, st);
         HostBlob blob;
-        const size_t o_cidx = blob.put(cidx), o_goff = blob.put(goff);
+        const size_t o_cidx = blob.put(cidx), o_goff = blob.put(goff), o_sf = blob.put(sf), o_sjet = blob.put(sjet);
         const char* img = ctx->ws.stage.upload(blob, st);
         // u_out holds the density w (zero off gamma), then u = w - G(L w |M+) in place
         MDP_HIP(hipMemsetAsync(u_out, 0, (size_t)off[n_sub] * sizeof(mdp_c128), st));
@@ -824,6 +939,14 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
             const long* go = reinterpret_cast<const long*>(img + o_goff) + e0;
             launch_extend_density(Pi->E.as<double>(), ng, ncol, reinterpret_cast<const double*>(c), ci, R, Pi->gm,
                                   Pi->gq, Pi->gside, n, uo, 0, go, st);
+            // xi_gamma also holds Ex^(I) f where there is a source (eq. extension_split)
+            bool any_src = false;
+            for (size_t e = e0; e < e0 + grp.size(); ++e) any_src = any_src || sf[e];
+            const double* const* fs = reinterpret_cast<const double* const*>(img + o_sf) + e0;
+            if (any_src)
+                launch_source_extension(Pi->grho, Pi->gm, Pi->gq, ng, n, Pi->k,
+                                        reinterpret_cast<const double* const*>(img + o_sjet) + e0, R, uo, go, true,
+                                        st);
             const int chunk = chunk_size(plan, Pi->precision, ctx->ws_cap, R);
             prepare_ws(ctx, plan, Pi->precision, chunk);
             for (int r0 = 0; r0 < R; r0 += chunk) {
@@ -832,6 +955,7 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
                 src.kind = Src::STENCIL_GRID;
                 src.grid = uo;
                 src.goff = go + r0;
+                src.fsrc = any_src ? fs + r0 : nullptr;   // right-hand side L w - B f (eq. potential_solution)
                 src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
                 const Fold f = plan.f;
                 const int prec = Pi->precision;

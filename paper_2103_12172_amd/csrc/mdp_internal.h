@@ -254,6 +254,8 @@ struct SrcDesc {
     const double* grid;   // GRID / STENCIL_GRID: complex interleaved grids, (n+1)^2 each, stride grid_stride (complex elems)
     long grid_stride;
     const long* goff;     // optional: grid b starts at goff[b] (complex elements) instead of b * grid_stride
+    const double* const* fsrc;   // STENCIL_GRID, optional: per entry b the source f on the grid (complex,
+                                 // (n+1)^2) or null; the right-hand side becomes L w - B f on M+
     const double* E;      // STENCIL_E: column-major |gamma| x ncols real
     int ldE;
     int col0;             // STENCIL_E: first column of this batch
@@ -285,6 +287,15 @@ template <class T>
 // out starts at boff[b] (complex elements) when boff is set, else at b * stride
 void launch_unfold_grid(const T* u, const float* du, int n, const Fold& f, Band bd, Band rows, int R, const double* w,
                         long w_stride, double* out, long out_stride, const long* boff, hipStream_t st);
+// w_b(gamma_i) (+)= Ex^(I) f = rho^2/2 f + rho^3/6 df/dn + rho^4/24 (d2f/dn2 - d2f/dtau2 - k^2 f) from the
+// jet of entry b (3 x ng complex, null: entry skipped); grid b of w at woff[b] (complex elements)
+void launch_source_extension(const double* rho, const int* gm, const int* gq, int ng, int n, double k,
+                             const double* const* jet, int R, double* w, const long* woff, bool accumulate,
+                             hipStream_t st);
+// F[foff[b] + i] += u_b(gamma_i) (u in folded band layout, complex F)
+template <class T>
+void launch_gather_add(const T* u, int n, const Fold& f, Band bd, const int* gm, const int* gq, int ng, int R,
+                       double* F, const long* foff, hipStream_t st);
 // w_b(gamma_i) = sum over the Dirichlet and Neumann columns of gamma_i's side of E(i, col) c_b(col)
 void launch_extend_density(const double* E, int ng, int ncol, const double* c, const int* cidx, int R, const int* gm,
                            const int* gq, const int* gside, int n, double* w, long w_stride, const long* woff,

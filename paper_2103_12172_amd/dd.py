@@ -3,7 +3,9 @@
 Argument marshalling only: boundary data are sampled from the workload at the
 library's Chebyshev points, turned into coefficients by the library, and the
 projector build, interface least squares and reconstruction all run in
-libmdp on the GPU.
+libmdp on the GPU.  A workload with a source f is sampled on each auxiliary
+grid (for B^(h) f) and, with its normal derivatives, at the foot points of
+gamma (for Ex^(I) f) that the library reports.
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ class DDResult:
     cond: Optional[float]
     offsets: List[int]   # start of each subdomain's grid in u
     projectors: List[object]
+    sources: Optional[list] = None   # device (f, jet) per subdomain, kept alive with the result
 
 
 def subdomain_structs(w: wl.Workload) -> List[mdp.Subdomain]:
@@ -52,21 +55,44 @@ def build_projectors(ctx, w: wl.Workload, precision, stream=None) -> List[object
     return out
 
 
+def source_tensors(ctx, w: wl.Workload, projectors) -> Optional[list]:
+    """Per subdomain (f on its auxiliary grid, jet of f at the foot points of gamma) as device tensors."""
+    import torch
+    if w.source is None:
+        return None
+    dev = "cuda:%d" % ctx.device
+    out = []
+    for s, P in zip(subdomain_structs(w), projectors):
+        xa, ya, h = mdp.mdp_ap_grid(s)
+        nodes = np.arange(s.n + 1)
+        X, Y = np.meshgrid(xa + nodes * h, ya + nodes * h, indexing="ij")
+        f = np.ascontiguousarray(np.asarray(w.source(X, Y), dtype=np.complex128).reshape(-1))
+        xy, side = mdp.mdp_projector_gamma_feet(P, s)
+        normals = np.array([wl.outward_normal(int(v)) for v in side]).reshape(-1, 2)
+        jet = np.concatenate([np.asarray(v, dtype=np.complex128).reshape(-1)
+                              for v in w.source_jet(xy[:, 0], xy[:, 1], normals[:, 0], normals[:, 1])])
+        out.append((torch.from_numpy(f).to(dev), torch.from_numpy(jet).to(dev)))
+    return out
+
+
 def dd_solve(ctx, w: wl.Workload, precision=None, stream=None, projectors=None, sides=None,
-             want_cond: bool = True) -> DDResult:
+             want_cond: bool = True, sources=None) -> DDResult:
     import torch
     precision = precision or w.precision
     subs = subdomain_structs(w)
     projectors = projectors or build_projectors(ctx, w, precision, stream)
     if sides is None:
         sides = side_structs(w, w.m_star)
+    if sources is None and w.source is not None:
+        sources = source_tensors(ctx, w, projectors)
     dev = "cuda:%d" % ctx.device
     N = len(subs)
     c = torch.empty(N * 8 * w.m_star, dtype=torch.complex128, device=dev)
-    rel, cond = mdp.mdp_solve_interface(ctx, subs, projectors, sides[0], sides[1], w.m_star, c, stream, want_cond)
+    rel, cond = mdp.mdp_solve_interface(ctx, subs, projectors, sides[0], sides[1], w.m_star, c, stream, want_cond,
+                                        sources)
     offs = [0]
     for sd in w.subdomains:
         offs.append(offs[-1] + (sd.n + 1) ** 2)
     u = torch.empty(offs[-1], dtype=torch.complex128, device=dev)
-    mdp.mdp_reconstruct(ctx, projectors, c, u, stream)
-    return DDResult(u, c, rel, cond, offs, projectors)
+    mdp.mdp_reconstruct(ctx, projectors, c, u, stream, sources)
+    return DDResult(u, c, rel, cond, offs, projectors, sources)

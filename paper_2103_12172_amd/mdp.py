@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "MDP_OK", -1: "MDP_ERR_ARG", -2: "MDP_ERR_HIP", -3: "MDP_ERR_
 EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector", "mdp_projector_info",
             "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
             "mdp_cheb_coeffs", "mdp_version", "mdp_cache_clear", "mdp_profile_enable", "mdp_profile_report",
-            "mdp_set_projector_path", "mdp_profile_select"]
+            "mdp_set_projector_path", "mdp_profile_select", "mdp_projector_gamma_feet", "mdp_ap_grid"]
 MDP_PATH_AUTO, MDP_PATH_DENSE = 0, 1
 PROJECTOR_PATHS = {"auto": MDP_PATH_AUTO, "dense": MDP_PATH_DENSE}
 
@@ -44,6 +44,10 @@ class C128(ctypes.Structure):
 class Subdomain(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("lx", ctypes.c_double),
                 ("ly", ctypes.c_double), ("k", ctypes.c_double), ("n", ctypes.c_int)]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p), ("jet", ctypes.c_void_p)]
 
 
 class Side(ctypes.Structure):
@@ -76,9 +80,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mdp_projector_release.argtypes = [vp]
     lib.mdp_projector_release.restype = None
     lib.mdp_solve_interface.argtypes = [vp, ip, ctypes.POINTER(Subdomain), ctypes.POINTER(vp), ctypes.POINTER(Side),
-                                        ip, vp, vp, ctypes.POINTER(dp), ctypes.POINTER(dp)]
+                                        ip, ctypes.POINTER(Source), vp, vp, ctypes.POINTER(dp), ctypes.POINTER(dp)]
     lib.mdp_solve_interface.restype = ip
-    lib.mdp_reconstruct.argtypes = [vp, ip, ctypes.POINTER(vp), vp, vp, vp]
+    lib.mdp_reconstruct.argtypes = [vp, ip, ctypes.POINTER(vp), vp, ctypes.POINTER(Source), vp, vp]
+    lib.mdp_projector_gamma_feet.argtypes = [vp, ctypes.POINTER(Subdomain), ctypes.POINTER(dp), ctypes.POINTER(ip)]
+    lib.mdp_projector_gamma_feet.restype = ip
+    lib.mdp_ap_grid.argtypes = [ctypes.POINTER(Subdomain), ctypes.POINTER(dp), ctypes.POINTER(dp), ctypes.POINTER(dp)]
+    lib.mdp_ap_grid.restype = ip
     lib.mdp_reconstruct.restype = ip
     lib.mdp_ap_solve.argtypes = [vp, ip, dp, dp, ip, ip, vp, vp, vp]
     lib.mdp_ap_solve.restype = ip
@@ -211,26 +219,66 @@ def make_sides(sides: Sequence[Side], d_arrays: Sequence[Optional[np.ndarray]]):
     return arr, keep
 
 
+def make_sources(sources):
+    """mdp_source array from per-subdomain (f, jet) device tensors or None (None overall: no source)."""
+    if sources is None:
+        return None
+    arr = (Source * len(sources))()
+    for i, src in enumerate(sources):
+        if src is None:
+            arr[i].f, arr[i].jet = None, None
+        else:
+            f, jet = src
+            arr[i].f, arr[i].jet = f.data_ptr(), jet.data_ptr()
+    return arr
+
+
 def mdp_solve_interface(ctx: Context, subs: Sequence[Subdomain], projectors: Sequence[Projector], sides,
-                        d_arrays, m_star: int, c_out, stream=None, want_cond: bool = True):
+                        d_arrays, m_star: int, c_out, stream=None, want_cond: bool = True, sources=None):
+    """sources: None or, per subdomain, None or (f, jet) complex128 device tensors (see mdp_source)."""
     n = len(subs)
     sub_arr = (Subdomain * n)(*subs)
     parr = (ctypes.c_void_p * n)(*[p.handle.value for p in projectors])
     side_arr, keep = make_sides(sides, d_arrays)
+    src_arr = make_sources(sources)
     rel = ctypes.c_double()
     cond = ctypes.c_double()
-    ctx.check(ctx.lib.mdp_solve_interface(ctx.handle, n, sub_arr, parr, side_arr, m_star,
+    ctx.check(ctx.lib.mdp_solve_interface(ctx.handle, n, sub_arr, parr, side_arr, m_star, src_arr,
                                           ctypes.c_void_p(_stream_ptr(stream)), ctypes.c_void_p(c_out.data_ptr()),
                                           ctypes.byref(rel), ctypes.byref(cond) if want_cond else None))
     del keep
     return rel.value, (cond.value if want_cond else None)
 
 
-def mdp_reconstruct(ctx: Context, projectors: Sequence[Projector], c, u_out, stream=None):
+def mdp_reconstruct(ctx: Context, projectors: Sequence[Projector], c, u_out, stream=None, sources=None):
     n = len(projectors)
     parr = (ctypes.c_void_p * n)(*[p.handle.value for p in projectors])
-    ctx.check(ctx.lib.mdp_reconstruct(ctx.handle, n, parr, ctypes.c_void_p(c.data_ptr()),
+    ctx.check(ctx.lib.mdp_reconstruct(ctx.handle, n, parr, ctypes.c_void_p(c.data_ptr()), make_sources(sources),
                                       ctypes.c_void_p(_stream_ptr(stream)), ctypes.c_void_p(u_out.data_ptr())))
+
+
+def mdp_projector_gamma_feet(P: "Projector", sub: Subdomain):
+    """(xy [n_gamma, 2], side [n_gamma]) foot points of gamma on the rectangle sub."""
+    lib = load()
+    ng = ctypes.c_int()
+    P.ctx.check(lib.mdp_projector_info(P.handle, ctypes.byref(ng), None, None))
+    xy = np.zeros((ng.value, 2))
+    side = np.zeros(ng.value, dtype=np.int32)
+    rc = lib.mdp_projector_gamma_feet(P.handle, ctypes.byref(sub), xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      side.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_projector_gamma_feet")
+    return xy, side
+
+
+def mdp_ap_grid(sub: Subdomain):
+    """(xa, ya, h) of the auxiliary grid of the rectangle sub."""
+    lib = load()
+    xa, ya, h = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    rc = lib.mdp_ap_grid(ctypes.byref(sub), ctypes.byref(xa), ctypes.byref(ya), ctypes.byref(h))
+    if rc != MDP_OK:
+        raise MdpError(rc, "mdp_ap_grid")
+    return xa.value, ya.value, h.value
 
 
 def mdp_ap_solve(ctx: Context, n: int, h: float, k: float, precision, g, u, stream=None):

@@ -61,3 +61,15 @@ def test_create_without_device_fails_loudly():
     rc = lib.mdp_create(ctypes.byref(h), 0)
     assert rc == mdp.MDP_ERR_NODEVICE
     assert b"device" in lib.mdp_last_error(None)
+
+
+def test_ap_grid_helper_follows_the_documented_grid():
+    """mdp_ap_grid (host): the square of side 1.1 max(lx, ly) centred on the rectangle,
+    n cells; odd n is rejected."""
+    sub = mdp.Subdomain(0.25, -1.0, 0.5, 2.0, 10.0, 64)
+    xa, ya, h = mdp.mdp_ap_grid(sub)
+    L = 1.1 * 2.0
+    assert abs(h - L / 64) < 1e-15
+    assert abs(xa - (0.5 - L / 2)) < 1e-14 and abs(ya - (0.0 - L / 2)) < 1e-14
+    with pytest.raises(mdp.MdpError):
+        mdp.mdp_ap_grid(mdp.Subdomain(0.0, 0.0, 1.0, 1.0, 10.0, 63))
