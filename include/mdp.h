@@ -75,6 +75,25 @@ typedef enum {
     MDP_PATH_DENSE = 1
 } mdp_projector_path;
 
+/* How mdp_solve_interface solves the reduced least-squares system (steps 2b-2c
+ * of Sec. 3.5).  Both use the normal equations of the column-equilibrated Qbar
+ * with iterative refinement against the true residual (corrected semi-normal
+ * equations); they differ in how the Gram matrix Qbar^* Qbar is factored.
+ * MDP_IFACE_AUTO: dense up to 4096 unknowns, multifrontal above.
+ * MDP_IFACE_DENSE: one dense blocked Cholesky of the Gram matrix and its inverse
+ *   (order 4 n_sub M*; memory and work grow with its square and cube), with a
+ *   Cholesky-QR fallback on the assembled Qbar for ill-conditioned systems.
+ * MDP_IFACE_MULTIFRONTAL: nested dissection over the subdomain layout: the
+ *   subdomains are halved recursively along the longer extent of their centres;
+ *   each tree node eliminates the unknowns shared by its two halves (a dense
+ *   partial Cholesky of its front) and passes the Schur complement on the
+ *   unknowns it shares with the rest to its parent.  No dense fallback. */
+typedef enum {
+    MDP_IFACE_AUTO = 0,
+    MDP_IFACE_DENSE = 1,
+    MDP_IFACE_MULTIFRONTAL = 2
+} mdp_interface_path;
+
 /* One subdomain: the rectangle [x0, x0+lx] x [y0, y0+ly] with constant
  * wavenumber k (Sec. 3.1 assumes k constant on every subdomain).  Its
  * auxiliary domain is the square of side 1.1*max(lx, ly) centred on it, with
@@ -111,6 +130,10 @@ void mdp_destroy(mdp_ctx* ctx);
 /* Select the projector route of later mdp_build_projector calls on ctx
  * (projectors already cached are not rebuilt).  Errors: MDP_ERR_ARG. */
 int mdp_set_projector_path(mdp_ctx* ctx, int path);
+
+/* Select the interface least-squares route (mdp_interface_path) of later
+ * mdp_solve_interface calls on ctx.  Errors: MDP_ERR_ARG. */
+int mdp_set_interface_path(mdp_ctx* ctx, int path);
 
 /* Message of the last failure on ctx (or of the last mdp_create failure when
  * ctx is NULL).  Valid until the next call on the same context. */

@@ -33,7 +33,8 @@ struct LSWork {
 
 // Packed interface matrix buffers (grow-only).
 struct PackedWork {
-    DevBuf Ap, Gi;
+    DevBuf Ap;
+    DevBuf mf;            // multifrontal factor arena
 };
 
 // Interface assembly and reconstruction buffers (grow-only).

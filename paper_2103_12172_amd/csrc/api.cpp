@@ -96,6 +96,7 @@ struct mdp_ctx {
     Workspace ws;
     size_t ws_cap = (size_t)24 << 30;
     int projector_path = MDP_PATH_AUTO;
+    int interface_path = MDP_IFACE_AUTO;
     hipEvent_t last = nullptr;   // end of the previous call's work (workspaces are shared)
     hipStream_t last_stream = nullptr;
     bool have_last = false;
@@ -307,6 +308,14 @@ int mdp_set_projector_path(mdp_ctx* ctx, int path) {
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
     if (path != MDP_PATH_AUTO && path != MDP_PATH_DENSE) return fail(ctx, MDP_ERR_ARG, "unknown projector path");
     ctx->projector_path = path;
+    return MDP_OK;
+}
+
+int mdp_set_interface_path(mdp_ctx* ctx, int path) {
+    if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
+    if (path != MDP_IFACE_AUTO && path != MDP_IFACE_DENSE && path != MDP_IFACE_MULTIFRONTAL)
+        return fail(ctx, MDP_ERR_ARG, "unknown interface path");
+    ctx->interface_path = path;
     return MDP_OK;
 }
 
@@ -550,6 +559,8 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             }
         }
         const int ncol = (int)blocks.size() * M;
+        const bool multifrontal = ctx->interface_path == MDP_IFACE_MULTIFRONTAL ||
+                                  (ctx->interface_path == MDP_IFACE_AUTO && ncol > 4096 && n_sub > 1);
         // Column order of the unknowns and the steps of the interface Cholesky.  The unknowns are cut into
         // slices of at most 64 columns: each subdomain's private unknowns (its boundary sides), and the
         // unknowns of each interface.  Two slices couple in the Gram matrix only if some subdomain's rows
@@ -561,7 +572,10 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
         // the slack giving the fewest steps is kept.  perm maps the column b*M + j of block b to its place.
         std::vector<int> perm(ncol);
         CholPlan chol_steps;
-        {
+        if (multifrontal) {
+            // the elimination tree orders the columns itself
+            for (int c = 0; c < ncol; ++c) perm[c] = c;
+        } else {
             struct Slice { std::vector<int> cols; std::vector<int> subs; };
             std::vector<Slice> slices;
             std::map<std::pair<int, int>, std::vector<int>> groups;   // (sub, sub) -> columns (sub, -1: private)
@@ -641,10 +655,10 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
         for (int i = 0; i < n_sub; ++i) row_off[i + 1] = row_off[i] + P[i]->g.n_gamma;
         const int m = row_off[n_sub];
         if (m < ncol) throw Error(MDP_ERR_ARG, "fewer gamma rows than unknowns");
-        // column map per (subdomain, Qbar column)
-        std::vector<int4> colmap((size_t)n_sub * ncol, int4{-1, -1, 0, 0});
-        std::vector<double2> coefs((size_t)n_sub * ncol * 2, double2{0.0, 0.0});
-        for (size_t b = 0; b < blocks.size(); ++b) {
+        // column map per (subdomain, Qbar column): the dense route's fallback assembles Qbar from it
+        std::vector<int4> colmap(multifrontal ? 0 : (size_t)n_sub * ncol, int4{-1, -1, 0, 0});
+        std::vector<double2> coefs(multifrontal ? 0 : (size_t)n_sub * ncol * 2, double2{0.0, 0.0});
+        for (size_t b = 0; b < blocks.size() && !multifrontal; ++b) {
             for (const Contrib& c : blocks[b].c) {
                 for (int j = 0; j < M; ++j) {
                     const size_t idx = (size_t)c.sub * ncol + perm[b * M + j];
@@ -754,6 +768,16 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             off += (long)qld[i] * si;
         }
         ph.total_pc = (int)ph.pc_sub.size();
+        if (multifrontal) {
+            for (int i = 0; i < n_sub; ++i) {
+                ph.cx.push_back(sd[i].x0 + 0.5 * sd[i].lx);
+                ph.cy.push_back(sd[i].y0 + 0.5 * sd[i].ly);
+            }
+            ph.mf = mf_plan(ph);
+            if (ph.mf.lds_fwd > 4096 || ph.mf.lds_bwd > 4096)
+                throw Error(MDP_ERR_ARG, "interface front too large for the multifrontal solve");
+            ph.multifrontal = true;
+        }
 
         // step 1c: subdomains with a source, grouped by projector (one batched AP solve per group)
         struct SrcGroup { const mdp_projector* P; int R; size_t e0; };
@@ -859,6 +883,9 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             bool fallback = false;
             r = ls_solve_packed(ctx->ws, ph, img, tabs, F.as<double2>(), x.as<double2>(), cond_estimate_out != nullptr,
                                 st, &fallback);
+            if (fallback && multifrontal)
+                throw Error(MDP_ERR_SINGULAR, "interface least squares: the multifrontal Gram factor broke down or "
+                                              "the refinement did not converge");
             if (fallback) {
                 // dense Cholesky-QR passes on the assembled matrix
                 DevBuf Qbar((size_t)m * ncol * sizeof(double2));

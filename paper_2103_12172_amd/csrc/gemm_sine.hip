@@ -201,10 +201,15 @@ void launch_cfg(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t
 template <class T>
 void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st) {
     if (M <= 0) return;
-    if (f.P1 % 128 == 0 && f.P2 % 128 == 0)
+    // 128 x 128 tiles when they give enough workgroups to fill the chip (256 CUs), 64 x 64 otherwise
+    // (short batches: a few thousand rows)
+    const long big = ((M + 127) / 128) * (f.W / 128);
+    if (f.P1 % 128 == 0 && f.P2 % 128 == 0 && big >= 512)
         launch_cfg<T, 128, 128, 2, 2>(A, B, C, M, f, st);
-    else
+    else if (f.P1 % 128 == 0 && f.P2 % 128 == 0 && big >= 256)
         launch_cfg<T, 128, 64, 4, 1>(A, B, C, M, f, st);
+    else
+        launch_cfg<T, 64, 64, 2, 2>(A, B, C, M, f, st);
 }
 
 template void launch_gemm_bd<double>(const double*, const double*, double*, long, const Fold&, hipStream_t);

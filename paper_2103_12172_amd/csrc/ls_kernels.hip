@@ -1232,6 +1232,7 @@ void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int
                        0L, 0, 1, zb_dev);
     MDP_HIP(hipGetLastError());
     (void)max_k;
+    if (!G) return;   // the partials are used as they are (multifrontal leaves)
     hipLaunchKernelGGL(gram_scatter_kernel, dim3((unsigned)(((long)max_n * max_n + 255) / 256), nb), dim3(256), 0, st,
                        zb_dev, P, nsplit, gcol, G, ldg);
     MDP_HIP(hipGetLastError());
@@ -1250,6 +1251,178 @@ void launch_diag_range(const double2* L, int n, int ld, double* out, hipStream_t
 void launch_fill(double* p, long n, double v, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(256), 0, st, p, n, v);
+    MDP_HIP(hipGetLastError());
+}
+
+
+// ---------------------------------------------------------------------------
+// Multifrontal Cholesky of the interface Gram matrix (elimination tree over
+// the subdomains).  Fronts are assembled by gathering: each entry of a node's
+// front is the sum of at most two children's contribution entries (or one entry
+// of a leaf's Gram block), so no two threads write one entry.
+
+__global__ void __launch_bounds__(256)
+mf_assemble_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
+                   const double2* __restrict__ P, double2* __restrict__ arena) {
+    const MFNodeDev nd = nodes[list[blockIdx.y]];
+    const int f = nd.f, e = nd.e;
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)f * f) return;
+    const int a = (int)(t % f), c = (int)(t / f);   // row a, column c
+    if (a < e && c >= e) return;                    // F12 = F21^* is not kept
+    double2 v = make_double2(0.0, 0.0);
+    if (nd.leaf) {
+        const int* sp = reinterpret_cast<const int*>(img + nd.spos);
+        int p1 = sp[a], p2 = sp[c];
+        const bool cj = p1 < p2;   // the partials hold the lower triangle (p1 >= p2)
+        if (cj) { const int q = p1; p1 = p2; p2 = q; }
+        const double2* q = P + nd.poff + p1 + (long)p2 * nd.n;
+        for (int k = 0; k < nd.nsplit; ++k) {
+            const double2 w = q[k * nd.pstride];
+            v.x += w.x;
+            v.y += w.y;
+        }
+        if (cj) v.y = -v.y;
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int* inv = reinterpret_cast<const int*>(img + (kk ? nd.inv1 : nd.inv0));
+            const int ia = inv[a], ic = inv[c];
+            if (ia < 0 || ic < 0) continue;
+            const MFNodeDev& kd = nodes[kk ? nd.kid1 : nd.kid0];
+            const double2 w = arena[kd.Y + (long)(kd.e + ic) * kd.b + ia];
+            v.x += w.x;
+            v.y += w.y;
+        }
+    }
+    if (a < e) arena[nd.X + a + (long)c * e] = v;
+    else arena[nd.Y + (a - e) + (long)c * nd.b] = v;
+}
+
+__device__ inline double2 wave_sum2(double2 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    return v;
+}
+
+// One workgroup per node: w = (y at the eliminated columns, 0) + the children's
+// contributions at their front positions (children in turn), z = Linv w_e,
+// cw = w_b - L21 z.
+__global__ void __launch_bounds__(256)
+mf_forward_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
+                  double2* __restrict__ arena, const double2* __restrict__ y) {
+    extern __shared__ double2 mf_sh[];
+    const MFNodeDev nd = nodes[list[blockIdx.x]];
+    const int e = nd.e, b = nd.b, f = nd.f, tid = threadIdx.x;
+    double2* w = mf_sh;
+    double2* zs = mf_sh + f;
+    const int* idx = reinterpret_cast<const int*>(img + nd.idx);
+    for (int a = tid; a < f; a += 256) w[a] = (a < e) ? y[idx[a]] : make_double2(0.0, 0.0);
+    __syncthreads();
+    if (!nd.leaf) {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const MFNodeDev& kd = nodes[kk ? nd.kid1 : nd.kid0];
+            const int* kp = reinterpret_cast<const int*>(img + (kk ? nd.kpos1 : nd.kpos0));
+            const double2* cwk = arena + kd.cw;
+            for (int r = tid; r < kd.b; r += 256) {
+                const double2 u = cwk[r];
+                w[kp[r]].x += u.x;
+                w[kp[r]].y += u.y;
+            }
+            __syncthreads();
+        }
+    }
+    const double2* Li = arena + nd.Linv;
+    double2* z = arena + nd.z;
+    for (int i = tid; i < e; i += 256) {
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j <= i; ++j) {
+            const double2 l = Li[i + (long)j * e], u = w[j];
+            sr += l.x * u.x - l.y * u.y;
+            si += l.x * u.y + l.y * u.x;
+        }
+        z[i] = make_double2(sr, si);
+        zs[i] = make_double2(sr, si);
+    }
+    __syncthreads();
+    const double2* L21 = arena + nd.L21;
+    double2* cw = arena + nd.cw;
+    for (int r = tid; r < b; r += 256) {
+        double sr = w[e + r].x, si = w[e + r].y;
+        for (int j = 0; j < e; ++j) {
+            const double2 l = L21[r + (long)j * b], u = zs[j];
+            sr -= l.x * u.x - l.y * u.y;
+            si -= l.x * u.y + l.y * u.x;
+        }
+        cw[r] = make_double2(sr, si);
+    }
+}
+
+// One workgroup per node: xb = x at the boundary columns, t = z - L21^* xb,
+// x at the eliminated columns = Linv^* t.  A wavefront per column of L21 and per
+// row of Linv^* (lanes along contiguous memory).
+__global__ void __launch_bounds__(256)
+mf_backward_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
+                   const double2* __restrict__ arena, double2* __restrict__ x) {
+    extern __shared__ double2 mf_sh[];
+    const MFNodeDev nd = nodes[list[blockIdx.x]];
+    const int e = nd.e, b = nd.b, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    double2* xb = mf_sh;
+    double2* t = mf_sh + b;
+    const int* idx = reinterpret_cast<const int*>(img + nd.idx);
+    for (int r = tid; r < b; r += 256) xb[r] = x[idx[e + r]];
+    __syncthreads();
+    const double2* L21 = arena + nd.L21;
+    const double2* z = arena + nd.z;
+    for (int j = wave; j < e; j += 4) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int r = lane; r < b; r += 64) {
+            const double2 l = L21[r + (long)j * b], u = xb[r];   // conj(l) u
+            s.x += l.x * u.x + l.y * u.y;
+            s.y += l.x * u.y - l.y * u.x;
+        }
+        s = wave_sum2(s);
+        if (lane == 0) t[j] = make_double2(z[j].x - s.x, z[j].y - s.y);
+    }
+    __syncthreads();
+    const double2* Li = arena + nd.Linv;
+    for (int i = wave; i < e; i += 4) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int j = i + lane; j < e; j += 64) {
+            const double2 l = Li[j + (long)i * e], u = t[j];   // conj(Linv(j, i)) t_j
+            s.x += l.x * u.x + l.y * u.y;
+            s.y += l.x * u.y - l.y * u.x;
+        }
+        s = wave_sum2(s);
+        if (lane == 0) x[idx[i]] = s;
+    }
+}
+
+void launch_mf_assemble(const MFNodeDev* nodes, const int* list, int count, int max_f, const char* img,
+                        const double2* P, double2* arena, hipStream_t st) {
+    if (count <= 0 || max_f <= 0) return;
+    const unsigned bx = (unsigned)(((long)max_f * max_f + 255) / 256);
+    hipLaunchKernelGGL(mf_assemble_kernel, dim3(bx, count), dim3(256), 0, st, nodes, list, img, P, arena);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_mf_forward(const MFNodeDev* nodes, const int* list, int count, int lds_elems, const char* img,
+                       double2* arena, const double2* y, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(mf_forward_kernel, dim3(count), dim3(256), (size_t)std::max(lds_elems, 1) * sizeof(double2),
+                       st, nodes, list, img, arena, y);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_mf_backward(const MFNodeDev* nodes, const int* list, int count, int lds_elems, const char* img,
+                        const double2* arena, double2* x, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(mf_backward_kernel, dim3(count), dim3(256), (size_t)std::max(lds_elems, 1) * sizeof(double2),
+                       st, nodes, list, img, arena, x);
     MDP_HIP(hipGetLastError());
 }
 

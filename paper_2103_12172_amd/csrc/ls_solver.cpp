@@ -17,8 +17,12 @@
 // the device once, at the end (and once more when the shift is needed).
 #include "ls_solver.h"
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
+#include <functional>
+#include <limits>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -262,19 +266,165 @@ struct PackedFlags {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Multifrontal route (many subdomains).  The Gram matrix sum_i A_i^* A_i couples
+// two unknowns only when one subdomain touches both, so with the unknowns of
+// each half of the subdomains eliminated before those of the interfaces between
+// the halves (nested dissection over the subdomain layout) the Cholesky factor
+// keeps the block structure of the tree: each node holds the dense partial
+// factorisation of its front (its eliminated columns and the columns it shares
+// with subdomains outside it), and passes the Schur complement on the shared
+// columns to its parent.
+MFHost mf_plan(const PackedHost& h) {
+    MFHost t;
+    const int ns = h.n_sub, nc = h.nc;
+    if ((int)h.cx.size() != ns || (int)h.cy.size() != ns) throw Error(MDP_ERR_ARG, "subdomain centres missing");
+    // subdomains touching each column (at most two)
+    std::vector<std::array<int, 2>> touch(nc, std::array<int, 2>{-1, -1});
+    std::vector<std::vector<int>> subcols(ns);
+    for (int pc = 0; pc < h.total_pc; ++pc) {
+        const int g = h.pc_gcol[pc], s = h.pc_sub[pc];
+        std::array<int, 2>& tt = touch[g];
+        if (tt[0] < 0 || tt[0] == s) tt[0] = s;
+        else if (tt[1] < 0 || tt[1] == s) tt[1] = s;
+        else throw Error(MDP_ERR_ARG, "an interface unknown touches more than two subdomains");
+        subcols[s].push_back(g);
+    }
+    for (auto& v : subcols) {
+        std::sort(v.begin(), v.end());
+        if (std::adjacent_find(v.begin(), v.end()) != v.end())
+            throw Error(MDP_ERR_ARG, "a subdomain holds one unknown twice");
+    }
+    // the tree: halves along the longer extent of the centres, one subdomain per leaf
+    std::vector<int> order(ns), parent, depth, leaf_of(ns, -1);
+    for (int i = 0; i < ns; ++i) order[i] = i;
+    std::vector<MFHost::Node>& nodes = t.nodes;
+    std::function<int(int, int, int)> build = [&](int lo, int hi, int dep) -> int {
+        const int v = (int)nodes.size();
+        nodes.emplace_back();
+        parent.push_back(-1);
+        depth.push_back(dep);
+        if (hi - lo == 1) {
+            nodes[v].sub = order[lo];
+            leaf_of[order[lo]] = v;
+            return v;
+        }
+        double x0 = std::numeric_limits<double>::infinity(), x1 = -x0, y0 = x0, y1 = -x0;
+        for (int i = lo; i < hi; ++i) {
+            x0 = std::min(x0, h.cx[order[i]]); x1 = std::max(x1, h.cx[order[i]]);
+            y0 = std::min(y0, h.cy[order[i]]); y1 = std::max(y1, h.cy[order[i]]);
+        }
+        const bool byx = (x1 - x0) >= (y1 - y0);
+        std::stable_sort(order.begin() + lo, order.begin() + hi, [&](int a, int b) {
+            return byx ? std::make_pair(h.cx[a], h.cy[a]) < std::make_pair(h.cx[b], h.cy[b])
+                       : std::make_pair(h.cy[a], h.cx[a]) < std::make_pair(h.cy[b], h.cx[b]);
+        });
+        const int mid = lo + (hi - lo) / 2;
+        const int k0 = build(lo, mid, dep + 1);
+        const int k1 = build(mid, hi, dep + 1);
+        parent[k0] = parent[k1] = v;
+        nodes[v].kid[0] = k0;
+        nodes[v].kid[1] = k1;
+        nodes[v].height = 1 + std::max(nodes[k0].height, nodes[k1].height);
+        return v;
+    };
+    build(0, ns, 0);
+    const int nn = (int)nodes.size();
+    auto lca = [&](int a, int b) {
+        while (depth[a] > depth[b]) a = parent[a];
+        while (depth[b] > depth[a]) b = parent[b];
+        while (a != b) { a = parent[a]; b = parent[b]; }
+        return a;
+    };
+    std::vector<std::vector<int>> elim(nn), bnd(nn);
+    for (int g = 0; g < nc; ++g) {
+        if (touch[g][0] < 0) throw Error(MDP_ERR_ARG, "an unknown touches no subdomain");
+        const int v = touch[g][1] < 0 ? leaf_of[touch[g][0]] : lca(leaf_of[touch[g][0]], leaf_of[touch[g][1]]);
+        elim[v].push_back(g);
+    }
+    // boundary columns, children before parents (nodes were created parents first)
+    std::vector<int> posg(nc, -1), pgl(nc, -1);
+    for (int v = nn - 1; v >= 0; --v) {
+        MFHost::Node& nd = nodes[v];
+        std::vector<int> cand;
+        if (nd.sub >= 0) {
+            cand = subcols[nd.sub];
+        } else {
+            const std::vector<int>&a = bnd[nd.kid[0]], &b = bnd[nd.kid[1]];
+            std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(cand));
+        }
+        std::set_difference(cand.begin(), cand.end(), elim[v].begin(), elim[v].end(), std::back_inserter(bnd[v]));
+        if (cand.size() != bnd[v].size() + elim[v].size()) throw Error(MDP_ERR_ARG, "inconsistent elimination tree");
+        nd.e = (int)elim[v].size();
+        nd.b = (int)bnd[v].size();
+        nd.idx = elim[v];
+        nd.idx.insert(nd.idx.end(), bnd[v].begin(), bnd[v].end());
+        const int f = nd.e + nd.b;
+        for (int a = 0; a < f; ++a) posg[nd.idx[a]] = a;
+        if (nd.sub >= 0) {
+            const int s = nd.sub;
+            for (int p = 0; p < h.s[s]; ++p) pgl[h.pc_gcol[h.pc_start[s] + p]] = p;
+            nd.spos.resize(f);
+            for (int a = 0; a < f; ++a) nd.spos[a] = pgl[nd.idx[a]];
+            for (int p = 0; p < h.s[s]; ++p) pgl[h.pc_gcol[h.pc_start[s] + p]] = -1;
+        } else {
+            for (int c = 0; c < 2; ++c) {
+                const std::vector<int>& kb = bnd[nd.kid[c]];
+                nd.kpos[c].resize(kb.size());
+                nd.inv[c].assign(f, -1);
+                for (size_t r = 0; r < kb.size(); ++r) {
+                    const int a = posg[kb[r]];
+                    if (a < 0) throw Error(MDP_ERR_ARG, "inconsistent elimination tree");
+                    nd.kpos[c][r] = a;
+                    nd.inv[c][a] = (int)r;
+                }
+            }
+        }
+        for (int a = 0; a < f; ++a) posg[nd.idx[a]] = -1;
+        if (nd.height >= (int)t.by_height.size()) t.by_height.resize(nd.height + 1);
+        t.by_height[nd.height].push_back(v);
+        t.max_f = std::max(t.max_f, f);
+        t.max_e = std::max(t.max_e, nd.e);
+        t.lds_fwd = std::max(t.lds_fwd, f + nd.e);
+        t.lds_bwd = std::max(t.lds_bwd, nd.b + nd.e);
+    }
+    if (nodes[0].b != 0) throw Error(MDP_ERR_ARG, "inconsistent elimination tree");
+    // factor arena: per node F11 (e^2), the rest of the front (b f), Linv (e^2), L21 (b e), z (e), cw (b)
+    size_t off = 0;
+    auto take = [&](size_t n) { const size_t o = off; off += (n + 15) / 16 * 16; return o; };
+    for (MFHost::Node& nd : nodes) {
+        const size_t e = nd.e, b = nd.b;
+        nd.X = take(e * e);
+        nd.Y = take(b * (e + b));
+        nd.Linv = take(e * e);
+        nd.L21 = take(b * e);
+        nd.z = take(e);
+        nd.cw = take(b);
+    }
+    t.arena = off;
+    return t;
+}
+
 PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob) {
     PackedWork& w = ws.pk;
     const int nc = h.nc, n_sub = h.n_sub;
     long mtot = 0, ptot = 0;
     for (int i = 0; i < n_sub; ++i) { mtot += h.m[i]; ptot += (long)h.m[i] * h.s[i]; }
     grow(w.Ap, (size_t)ptot * sizeof(double2));
-    grow(w.Gi, (size_t)h.max_s * h.max_s * sizeof(double2));
     LSWork& lw = ws.ls;
-    const size_t nn = (size_t)nc * nc;
-    grow(lw.G, nn * sizeof(double2));
-    grow(lw.L, nn * sizeof(double2));
-    grow(lw.Linv[0], nn * sizeof(double2));
-    grow(lw.T, nn * sizeof(double2));
+    if (h.multifrontal) {
+        // the factor arena; the scratch of the per-node Cholesky (order <= max_e)
+        const size_t ee = (size_t)h.mf.max_e * h.mf.max_e;
+        grow(w.mf, std::max<size_t>(h.mf.arena, 1) * sizeof(double2));
+        grow(lw.L, std::max<size_t>(ee, 1) * sizeof(double2));
+        grow(lw.T, std::max<size_t>(ee, 1) * sizeof(double2));
+    } else {
+        const size_t nn = (size_t)nc * nc;
+        grow(lw.G, nn * sizeof(double2));
+        grow(lw.L, nn * sizeof(double2));
+        grow(lw.Linv[0], nn * sizeof(double2));
+        grow(lw.T, nn * sizeof(double2));
+    }
     grow(lw.vec, (size_t)(6 * nc + 2 * mtot) * sizeof(double2));
     grow(lw.norms, 2 * (size_t)nc * sizeof(double));
     grow(lw.flags, 64);
@@ -309,6 +459,45 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
     grow(ws.zg, (size_t)std::max(poff, 1L) * sizeof(double2));
     t.zb = blob.put(zb);
     t.nsplit = nsplit;
+    if (h.multifrontal) {
+        const MFHost& mf = h.mf;
+        std::vector<MFNodeDev> nd(mf.nodes.size());
+        for (size_t v = 0; v < mf.nodes.size(); ++v) {
+            const MFHost::Node& a = mf.nodes[v];
+            MFNodeDev& o = nd[v];
+            o.e = a.e;
+            o.b = a.b;
+            o.f = a.e + a.b;
+            o.leaf = a.sub >= 0;
+            o.idx = (long)blob.put(a.idx);
+            o.X = (long)a.X; o.Y = (long)a.Y; o.Linv = (long)a.Linv; o.L21 = (long)a.L21;
+            o.z = (long)a.z; o.cw = (long)a.cw;
+            o.kid0 = a.kid[0];
+            o.kid1 = a.kid[1];
+            if (o.leaf) {
+                const ZBatch& z = zb[a.sub];
+                o.n = z.n;
+                o.nsplit = nsplit;
+                o.pstride = (long)z.n * z.n;
+                o.poff = z.poff;
+                o.spos = (long)blob.put(a.spos);
+            } else {
+                o.inv0 = (long)blob.put(a.inv[0]);
+                o.inv1 = (long)blob.put(a.inv[1]);
+                o.kpos0 = (long)blob.put(a.kpos[0]);
+                o.kpos1 = (long)blob.put(a.kpos[1]);
+            }
+        }
+        t.mf_nodes = blob.put(nd);
+        std::vector<int> lists;
+        t.mf_list_off.clear();
+        for (const auto& hv : mf.by_height) {
+            t.mf_list_off.push_back(lists.size());
+            lists.insert(lists.end(), hv.begin(), hv.end());
+        }
+        t.mf_list_off.push_back(lists.size());
+        t.mf_lists = blob.put(lists);
+    }
     return t;
 }
 
@@ -340,9 +529,13 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     double2* v2 = v1 + nc;
     double2* r = v2 + nc;
     PackedFlags* fl = lw.flags.as<PackedFlags>();
-    double2* G = lw.G.as<double2>();
+    const bool mfr = h.multifrontal;
+    double2* G = mfr ? nullptr : lw.G.as<double2>();
     double2* L = lw.L.as<double2>();
-    double2* Linv = lw.Linv[0].as<double2>();
+    double2* Linv = mfr ? nullptr : lw.Linv[0].as<double2>();
+    const MFNodeDev* mf_nodes = mfr ? reinterpret_cast<const MFNodeDev*>(at(tb.mf_nodes)) : nullptr;
+    const int* mf_lists = mfr ? reinterpret_cast<const int*>(at(tb.mf_lists)) : nullptr;
+    double2* arena = mfr ? w.mf.as<double2>() : nullptr;
 
     MDP_HIP(hipMemsetAsync(fl, 0, sizeof(PackedFlags), st));
     // packed blocks, equilibrated columns
@@ -351,8 +544,8 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     launch_packed_colnorm2(d, npc, Ap, norms2, st);
     launch_finalize_norms(nc, norms2, norms, &fl->badcol, st);
     launch_packed_scale(d, npc, h.max_m, Ap, norms, st);
-    // Gram matrix
-    MDP_HIP(hipMemsetAsync(G, 0, nn * sizeof(double2), st));
+    // Gram matrix (multifrontal: the per-subdomain blocks stay apart)
+    if (!mfr) MDP_HIP(hipMemsetAsync(G, 0, nn * sizeof(double2), st));
     {
         int max_m = 0;
         double gram_flops = 0.0, gram_bytes = 0.0;
@@ -366,8 +559,60 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
                                 ws.zg.as<double2>(), d.pc_gcol, G, nc, st);
         });
     }
-    const double chol_flops = cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof,
-                                                   h.steps.empty() ? nullptr : &h.steps);
+    double chol_flops = 0.0;
+    if (!mfr) {
+        chol_flops = cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof,
+                                          h.steps.empty() ? nullptr : &h.steps);
+    } else {
+        // children before parents: assemble every front of one height, then factor each node's
+        // eliminated block (Cholesky and inverse), L21 = F21 L11^{-*}, and its contribution
+        // F22 - L21 L21^* in place
+        const MFHost& mf = h.mf;
+        for (size_t hh = 0; hh < mf.by_height.size(); ++hh) {
+            const std::vector<int>& lv = mf.by_height[hh];
+            int mxf = 0;
+            double abytes = 0.0;
+            for (int v : lv) {
+                const int f = mf.nodes[v].e + mf.nodes[v].b;
+                mxf = std::max(mxf, f);
+                abytes += 32.0 * f * f;
+            }
+            ws.prof.run("mf_assemble", st, 0.0, abytes, [&] {
+                launch_mf_assemble(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)lv.size(), mxf, image,
+                                   ws.zg.as<double2>(), arena, st);
+            });
+            for (int v : lv) {
+                const MFHost::Node& nd = mf.nodes[v];
+                if (nd.e == 0) continue;
+                chol_flops += cholesky_and_inverse(arena + nd.X, L, arena + nd.Linv, lw.T.as<double2>(), &fl->info,
+                                                   nd.e, 0.0, st, &ws.prof, nullptr);
+                if (nd.b == 0) continue;
+                const double e = nd.e, b = nd.b;
+                ws.prof.run("mf_gemm", st, 8.0 * b * e * e, 16.0 * (2.0 * b * e + e * e), [&] {
+                    launch_zgemm('N', 'C', nd.b, nd.e, nd.e, ONE, arena + nd.Y, nd.b, arena + nd.Linv, nd.e, ZERO,
+                                 arena + nd.L21, nd.b, ws.zg, st, 2);
+                });
+                ws.prof.run("mf_gemm", st, 8.0 * b * b * e, 16.0 * (2.0 * b * e + 2.0 * b * b), [&] {
+                    launch_zgemm('N', 'C', nd.b, nd.b, nd.e, MONE, arena + nd.L21, nd.b, arena + nd.L21, nd.b, ONE,
+                                 arena + nd.Y + (size_t)nd.e * nd.b, nd.b, ws.zg, st);
+                });
+                chol_flops += 8.0 * b * e * e + 8.0 * b * b * e;
+            }
+        }
+    }
+    // G^{-1} y (multifrontal): forward through the tree, children first, then back from the root
+    auto mf_solve = [&](const double2* yv, double2* out) {
+        const MFHost& mf = h.mf;
+        const int H = (int)mf.by_height.size();
+        ws.prof.run("mf_solve", st, 0.0, 0.0, [&] {
+            for (int hh = 0; hh < H; ++hh)
+                launch_mf_forward(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.lds_fwd,
+                                  image, arena, yv, st);
+            for (int hh = H - 1; hh >= 0; --hh)
+                launch_mf_backward(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(),
+                                   mf.lds_bwd, image, arena, out, st);
+        });
+    };
     // algorithmic flops: Gram (lower half), factor + inverse, and per normal solve (A^* v plus two
     // triangular products) or residual (A x): 8 flops per complex multiply-add
     double packed_cmacs = 0.0, gram_cmacs = 0.0;
@@ -375,13 +620,22 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
         packed_cmacs += (double)h.m[i] * h.s[i];
         gram_cmacs += 0.5 * (double)h.m[i] * h.s[i] * (h.s[i] + 1);
     }
-    const double solve_flops = 8.0 * (packed_cmacs + (double)nc * nc), resid_flops = 8.0 * packed_cmacs;
+    double tri_cmacs = (double)nc * nc;   // two triangular products with Linv (dense)
+    if (mfr) {
+        tri_cmacs = 0.0;
+        for (const MFHost::Node& nd : h.mf.nodes) tri_cmacs += (double)nd.e * nd.e + 2.0 * nd.b * nd.e;
+    }
+    const double solve_flops = 8.0 * (packed_cmacs + tri_cmacs), resid_flops = 8.0 * packed_cmacs;
     int n_solves = 0, n_resid = 0;
     // c = R^{-1} R^{-*} Qbar^* F, R^{-1} = Linv^*, R^{-*} = Linv
     auto normal_solve = [&](const double2* rhs_rows, double2* out) {
         ++n_solves;
         MDP_HIP(hipMemsetAsync(y, 0, nc * sizeof(double2), st));
         launch_packed_ahx(d, npc, Ap, rhs_rows, ONE, y, st);
+        if (mfr) {
+            mf_solve(y, out);
+            return;
+        }
         launch_zgemm('N', 'N', nc, 1, nc, ONE, Linv, nc, y, nc, ZERO, t, nc, ws.zg, st);
         launch_zgemm('C', 'N', nc, 1, nc, ONE, Linv, nc, t, nc, ZERO, out, nc, ws.zg, st);
     };
@@ -455,7 +709,17 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
             MDP_HIP(hipMemcpyAsync(v1, hv.data(), nc * sizeof(double2), hipMemcpyHostToDevice, st));
             launch_znormalize(nc, v1, &fl->pw[which], st);
             for (int it = 0; it < 16; ++it) {
-                if (which == 0) {
+                if (mfr) {
+                    if (which == 0) {   // G v = A^* (A v)
+                        MDP_HIP(hipMemsetAsync(r, 0, mtot * sizeof(double2), st));
+                        launch_packed_ax(d, n_sub, h.max_m, h.max_s, Ap, v1, ONE, r, st);
+                        MDP_HIP(hipMemsetAsync(v1, 0, nc * sizeof(double2), st));
+                        launch_packed_ahx(d, npc, Ap, r, ONE, v1, st);
+                    } else {
+                        MDP_HIP(hipMemcpyAsync(v2, v1, nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+                        mf_solve(v2, v1);
+                    }
+                } else if (which == 0) {
                     launch_zgemm('C', 'N', nc, 1, nc, ONE, L, nc, v1, nc, ZERO, v2, nc, ws.zg, st);
                     launch_zgemm('N', 'N', nc, 1, nc, ONE, L, nc, v2, nc, ZERO, v1, nc, ws.zg, st);
                 } else {

@@ -23,8 +23,32 @@ struct LSResult {
 using CholPlan = std::vector<std::vector<int>>;
 CholPlan chol_plan_uniform(int nc);   // one 64-column block per step
 
+// Elimination tree of the multifrontal Cholesky: subdomains split in halves
+// along the longer extent of their centres, down to one subdomain per leaf; a
+// column is eliminated at the lowest node whose subdomains hold every subdomain
+// that touches it (nested dissection: a node eliminates the interfaces between
+// its two halves).
+struct MFHost {
+    struct Node {
+        int e = 0, b = 0, sub = -1, kid[2] = {-1, -1}, height = 0;
+        std::vector<int> idx;      // front position -> global column (eliminated first, then boundary)
+        std::vector<int> kpos[2];  // child's boundary position -> front position
+        std::vector<int> inv[2];   // front position -> child's boundary position, or -1
+        std::vector<int> spos;     // leaf: front position -> column of its subdomain's Gram block
+        size_t X = 0, Y = 0, Linv = 0, L21 = 0, z = 0, cw = 0;   // arena offsets (complex entries)
+    };
+    std::vector<Node> nodes;
+    std::vector<std::vector<int>> by_height;   // nodes of each height (leaves: 0)
+    int max_f = 0, max_e = 0, lds_fwd = 0, lds_bwd = 0;
+    size_t arena = 0;                          // complex entries of the factor arena
+    double flops = 0.0;                        // partial factorisations (complex, 8 per multiply-add)
+};
+
 struct PackedHost {
     int n_sub = 0, nc = 0, total_pc = 0, max_m = 0, max_s = 0;
+    std::vector<double> cx, cy;   // subdomain centres (elimination tree of the multifrontal route)
+    bool multifrontal = false;
+    MFHost mf;
     CholPlan steps;   // empty: one 64-column block per step
     std::vector<const double2*> Q;
     std::vector<int> m, s, pc_sub, pc_p, pc_gcol, pc_start;
@@ -48,7 +72,12 @@ double cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, i
 struct PackedTables {
     size_t Q, m, s, off, roff, sub, p, gcol, start, cols, coef, zb;
     int nsplit;
+    size_t mf_nodes, mf_lists;            // multifrontal: node table, node lists by height
+    std::vector<size_t> mf_list_off;      // start of each height's list (entries)
 };
+
+// Symbolic phase of the multifrontal route (h.pc_* and h.cx, h.cy set).
+MFHost mf_plan(const PackedHost& h);
 
 // Grow the workspaces for h and append the packed solve's tables to blob.
 PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob);

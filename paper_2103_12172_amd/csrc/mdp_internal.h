@@ -387,6 +387,36 @@ struct ZBatch {
 void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int nsplit, double2* P, const int* gcol,
                          double2* G, int ldg, hipStream_t st);
 void launch_zaxpy1(int n, const double2* x, double2* y, hipStream_t st);
+// Multifrontal Cholesky of the interface Gram matrix: one node of the
+// elimination tree.  Its front holds e eliminated columns, then b boundary
+// columns (global indices idx[0..f-1], f = e + b).  A leaf assembles its
+// subdomain's Gram block (split-K partials at P + poff, order n, nsplit splits of
+// pstride entries; spos maps front positions to the block's columns); an inner
+// node assembles its two children's contribution blocks (inv0/inv1 map front
+// positions to a child's boundary positions, -1 if absent; kpos0/kpos1 map the
+// child's boundary positions to front positions).  Int tables are byte offsets
+// into the call's device image; X, Y, Linv, L21, z, cw are element offsets into
+// the factor arena: X = F11 (e x e), Y = rows e..f-1 of the front (b x f, ld b,
+// the contribution block F22 - L21 L21^* in its columns e..f-1 once factored),
+// Linv = L11^{-1}, L21 (b x e), z (forward solve, e), cw (forward contribution, b).
+struct MFNodeDev {
+    int e, b, f, leaf;
+    int n, nsplit;
+    long pstride, poff;
+    long spos, inv0, inv1, kpos0, kpos1, idx;
+    int kid0, kid1;
+    long X, Y, Linv, L21, z, cw;
+};
+// all fronts of the nodes list[0..count-1] (max_f: their largest order)
+void launch_mf_assemble(const MFNodeDev* nodes, const int* list, int count, int max_f, const char* img,
+                        const double2* P, double2* arena, hipStream_t st);
+// forward substitution of the listed nodes: z = Linv (y_e + children), cw = w_b - L21 z
+void launch_mf_forward(const MFNodeDev* nodes, const int* list, int count, int lds_elems, const char* img,
+                       double2* arena, const double2* y, hipStream_t st);
+// back substitution of the listed nodes: x_e = Linv^* (z - L21^* x_b)
+void launch_mf_backward(const MFNodeDev* nodes, const int* list, int count, int lds_elems, const char* img,
+                        const double2* arena, double2* x, hipStream_t st);
+
 void launch_diag_range(const double2* L, int n, int ld, double* out, hipStream_t st);
 
 }  // namespace mdp

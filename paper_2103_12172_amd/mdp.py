@@ -26,9 +26,10 @@ STATUS_NAMES = {0: "MDP_OK", -1: "MDP_ERR_ARG", -2: "MDP_ERR_HIP", -3: "MDP_ERR_
 EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector", "mdp_projector_info",
             "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
             "mdp_cheb_coeffs", "mdp_version", "mdp_cache_clear", "mdp_profile_enable", "mdp_profile_report",
-            "mdp_set_projector_path", "mdp_profile_select", "mdp_projector_gamma_feet", "mdp_ap_grid"]
+            "mdp_set_projector_path", "mdp_set_interface_path", "mdp_profile_select", "mdp_projector_gamma_feet", "mdp_ap_grid"]
 MDP_PATH_AUTO, MDP_PATH_DENSE = 0, 1
 PROJECTOR_PATHS = {"auto": MDP_PATH_AUTO, "dense": MDP_PATH_DENSE}
+INTERFACE_PATHS = {"auto": 0, "dense": 1, "multifrontal": 2}
 
 
 class MdpError(RuntimeError):
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mdp_profile_select.restype = ip
     lib.mdp_set_projector_path.argtypes = [vp, ip]
     lib.mdp_set_projector_path.restype = ip
+    lib.mdp_set_interface_path.argtypes = [vp, ip]
+    lib.mdp_set_interface_path.restype = ip
     lib.mdp_cache_clear.argtypes = [vp]
     lib.mdp_cache_clear.restype = ip
     lib.mdp_profile_enable.argtypes = [vp, ip]
@@ -316,6 +319,13 @@ def mdp_set_projector_path(ctx: Context, path):
     """Route of later projector builds: "auto" (fused support-in / gamma-out
     sweep for complex128) or "dense" (full AP solves + gather)."""
     ctx.check(ctx.lib.mdp_set_projector_path(ctx.handle, PROJECTOR_PATHS.get(path, path)))
+
+
+def mdp_set_interface_path(ctx: Context, path):
+    """Route of later interface solves: "auto" (dense up to 4096 unknowns),
+    "dense" (dense Gram Cholesky) or "multifrontal" (nested dissection over the
+    subdomain layout)."""
+    ctx.check(ctx.lib.mdp_set_interface_path(ctx.handle, INTERFACE_PATHS.get(path, path)))
 
 
 def mdp_profile_enable(ctx: Context, enable: bool = True):

@@ -87,6 +87,7 @@ class Workload:
     extra: dict = field(default_factory=dict)
     source: Optional[Callable] = None      # f(x, y) -> complex ndarray (None: f = 0)
     source_jet: Optional[Callable] = None  # (x, y, nx, ny) -> (f, df/dn, d2f/dn2 - d2f/dtau2)
+    has_exact: bool = True                  # exact() is the solution (False: boundary data only)
 
 
 # ----------------------------------------------------------------- solutions
@@ -425,10 +426,10 @@ def config_source_plane(n: int = 64, k: float = 10.0, m_star: int = 16, a: float
                     % (k, n, m_star, a, b))
 
 
-def config_bump(n: int = 128, k: float = 20.0, m_star: int = 32) -> Workload:
-    """2x2 squares of side 0.5 with the bump source centred at the cross-point
-    (0.5, 0.5) and homogeneous Dirichlet data; no exact solution (exact = 0 is
-    only a placeholder for the boundary data)."""
+def config_bump(n: int = 256, k: float = 50.0, m_star: int = 32) -> Workload:
+    """2x2 squares of side 0.5 (the cross-point layout) with the bump source
+    centred at the cross-point (0.5, 0.5) and homogeneous Dirichlet data; no
+    exact solution (exact = 0 only gives the zero boundary data)."""
     subs, sides = grid_topology(2, 2, 0.0, 0.0, 0.5, 0.5, [k] * 4, n, lambda ix, iy, s: (1.0, 0.0))
     f, jet = bump_source(0.5, 0.5)
 
@@ -440,14 +441,44 @@ def config_bump(n: int = 128, k: float = 20.0, m_star: int = 32) -> Workload:
         return z, z
 
     return Workload("bump_n%d" % n, subs, sides, m_star, zero, zero_grad, "c128", source=f, source_jet=jet,
+                    has_exact=False,
                     notes="2x2 squares, k=%g, n=%d, M*=%d, Dirichlet 0, bump source at the cross-point"
                     % (k, n, m_star))
+
+
+def config_uneven(nx: int = 16, ny: int = 16, n_choices=(128, 256, 384, 512), k_range=(20.0, 80.0),
+                  m_star: int = 32, seed: int = 4, k_data: float = 50.0, theta: float = math.pi / 6) -> Workload:
+    """Unit square as nx x ny equal squares with uneven AP grids and wavenumbers:
+    every subdomain's n drawn uniformly from n_choices, then every k uniformly
+    from k_range (one generator, all n first); Dirichlet data of the plane wave
+    exp(i k_data (x cos theta + y sin theta)) on the outer sides.  The plane wave
+    solves none of the subdomain equations, so there is no exact solution."""
+    rng = np.random.default_rng(seed)
+    N = nx * ny
+    ns = [int(v) for v in rng.choice(np.asarray(n_choices), size=N)]
+    ks = [float(v) for v in rng.uniform(k_range[0], k_range[1], size=N)]
+    subs, sides = grid_topology(nx, ny, 0.0, 0.0, 1.0 / nx, 1.0 / ny, ks, ns, lambda ix, iy, s: (1.0, 0.0))
+    u, g = plane_wave(k_data, theta)
+    w = Workload("uneven_%dx%d" % (nx, ny), subs, sides, m_star, u, g, "c128", has_exact=False,
+                 notes="%dx%d squares, n in %s, k in U[%g,%g] (seed %d), M*=%d, Dirichlet data of the plane "
+                 "wave k=%g at theta=%.4f" % (nx, ny, list(n_choices), k_range[0], k_range[1], seed, m_star,
+                                               k_data, theta))
+    w.extra["ns"], w.extra["ks"] = ns, ks
+    return w
+
+
+def config_uneven_small(seed: int = 4) -> Workload:
+    """The uneven layout at a size the oracle solves in seconds: 3x3 squares,
+    n in {32, 48, 64}, k in U[5, 15], M* = 8, plane wave k = 10."""
+    return config_uneven(3, 3, (32, 48, 64), (5.0, 15.0), 8, seed, 10.0)
 
 
 WORKLOADS = {
     "two_rect": config_two_rect,
     "cross_point": config_cross_point,
     "transmission": config_transmission,
+    "bump": config_bump,
+    "uneven": config_uneven,
 }
 
 
