@@ -156,6 +156,19 @@ const char* mdp_last_error(const mdp_ctx* ctx);
 int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int precision,
                         void* stream, mdp_projector** out);
 
+/* Step 1b for `count` subdomains at once (sds: host array), e.g. every
+ * subdomain of a layout with uneven n and k: out[i] (host array of count
+ * handles) receives subdomain i's projector, exactly as count calls of
+ * mdp_build_projector would (same cache, same reference counts; subdomains
+ * with equal (lx, ly, n, k) share one build).  On the MDP_PATH_AUTO route the
+ * columns of every projector not yet cached run through the fused sweep
+ * together: one launch per stage over all of them, the sine GEMMs one launch
+ * per distinct n.  On failure no handle is returned (out[] is zeroed) and the
+ * projectors built by the call stay in the cache.  Errors: as
+ * mdp_build_projector, plus MDP_ERR_ARG for count < 1. */
+int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int m_star, int precision,
+                         void* stream, mdp_projector** out);
+
 /* Read-only view of a projector.  n_gamma = |gamma|; gamma_mq (host, 2*n_gamma
  * ints) lists gamma nodes as (m, q) pairs in increasing lexicographic (m, q)
  * order; q_dev (device, n_gamma x 8M* complex, column-major, leading

@@ -831,9 +831,26 @@ __device__ inline int special_out(const RingGeom& r, int m) {
 // non-special box row (zero on the special rows and outside the box);
 // spec[b][s][W] = folded special input row s.
 // Work item t of RHS b: t <= n a gc row, otherwise one folded special entry.
+// The job of global column b (jobs sorted by b0; uniform over the workgroup).
+__device__ inline int find_job(const FusedJob* __restrict__ jobs, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].b0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(256)
-fold_ring_kernel(SrcEval ev, Fold f, RingGeom rg, double* __restrict__ gc, double* __restrict__ spec) {
-    const int n = f.n, p = f.p, W = f.W, b = blockIdx.y;
+fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs) {
+    const FusedJob& J = jobs[find_job(jobs, njobs, blockIdx.y)];
+    const Fold f = J.f;
+    const RingGeom rg{J.src.m_lo, J.src.m_hi, J.src.q_lo, J.src.q_hi};
+    const SrcEval ev{J.src, f.n, J.sc};
+    double* __restrict__ gc = J.gc;
+    double* __restrict__ spec = J.spec;
+    const int n = f.n, p = f.p, W = f.W, b = blockIdx.y - J.b0;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t <= n) {
         const int m = t;
@@ -915,15 +932,27 @@ __device__ inline int special_slot(const RingGeom& r, int m) {
 // LDS: the wave's ring pairs of rows m0..t and the 4 special-row values per lane.
 template <int K>
 __global__ void __launch_bounds__(64)
-proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec_hat,
-                  const double* __restrict__ Sf, const double* __restrict__ Si, Fold f, RingGeom rg,
-                  const dv2* __restrict__ lf, const dv2* __restrict__ rf, const dv2* __restrict__ tf,
-                  const double* __restrict__ colc, double* __restrict__ ckpt, double* __restrict__ xs,
-                  double* __restrict__ thin, int nseg) {
+proj_fused_kernel(const FusedJob* __restrict__ jobs, int njobs) {
     static_assert(K % 8 == 0, "segments are reduced 8 rows at a time");
     extern __shared__ double2 lds_g[];  // [t-m0+1] ring pairs, then [5][64] special values
+    const FusedJob& J = jobs[find_job(jobs, njobs, blockIdx.y)];
+    const Fold f = J.f;
     const int n = f.n, W = f.W;
-    const int lane = threadIdx.x, wblk = blockIdx.x, b = blockIdx.y;
+    const int lane = threadIdx.x, wblk = blockIdx.x, b = blockIdx.y - J.b0;
+    if (wblk >= W / 64) return;   // a job with fewer mode columns than the widest one
+    const RingGeom rg{J.src.m_lo, J.src.m_hi, J.src.q_lo, J.src.q_hi};
+    const int nseg = J.nseg;
+    const double* __restrict__ gc = J.gc;
+    const double* __restrict__ spec_hat = J.spec_hat;
+    const double* __restrict__ Sf = J.Sf;
+    const double* __restrict__ Si = J.Si;
+    const dv2* __restrict__ lf = reinterpret_cast<const dv2*>(J.lf);
+    const dv2* __restrict__ rf = reinterpret_cast<const dv2*>(J.rf);
+    const dv2* __restrict__ tf = reinterpret_cast<const dv2*>(J.tf);
+    const double* __restrict__ colc = J.colc;
+    double* __restrict__ ckpt = J.ckpt;
+    double* __restrict__ xs = J.xs;
+    double* __restrict__ thin = J.thin;
     const int c = wblk * 64 + lane;
     const bool odd = c < f.P1;  // uniform over the wavefront (P1 is a multiple of 64)
     const int base = odd ? 0 : f.P1;
@@ -1056,13 +1085,19 @@ proj_fused_kernel(const double* __restrict__ gc, const double* __restrict__ spec
 // Q(i, col0+b) = -u(m_i, q_i): the full gamma rows from the synthesis rows us
 // ([b][plane][4][W], output of the inverse sine GEMM of xs), the others from
 // the thin partial sums (odd-mode blocks give A, even-mode blocks B).
-__global__ void gather_q_fused_kernel(const double* __restrict__ us, const double* __restrict__ thin, Fold f,
-                                      RingGeom rg, int rows_pad, const int* __restrict__ gm,
-                                      const int* __restrict__ gq, int ng, double* __restrict__ Q, int ldq,
-                                      int col0) {
+__global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njobs) {
+    const FusedJob& J = jobs[find_job(jobs, njobs, blockIdx.y)];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (i >= ng) return;
+    const int b = blockIdx.y - J.b0;
+    if (i >= J.ng) return;
+    const Fold f = J.f;
+    const RingGeom rg{J.src.m_lo, J.src.m_hi, J.src.q_lo, J.src.q_hi};
+    const double* __restrict__ us = J.us;
+    const double* __restrict__ thin = J.thin;
+    const int* __restrict__ gm = J.gm;
+    const int* __restrict__ gq = J.gq;
+    const int rows_pad = J.rows_pad, ldq = J.ldq, col0 = J.src.col0;
+    double* __restrict__ Q = J.Q;
     const int m = gm[i], q = gq[i], n = f.n, p = f.p, W = f.W;
     double vre, vim;
     const int so = special_out(rg, m);
@@ -1121,38 +1156,25 @@ bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int 
 
 int fused_segments(int m_lo, int m_hi) { return (m_hi - m_lo + 3 + FUSED_K - 1) / FUSED_K; }
 
-void launch_fold_ring(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, double* gc, double* spec,
-                      hipStream_t st) {
-    check_batch(R);
-    SrcEval ev{s, n, sc};
-    RingGeom rg{s.m_lo, s.m_hi, s.q_lo, s.q_hi};
-    const int items = n + 1 + 4 * f.W;
-    hipLaunchKernelGGL(fold_ring_kernel, dim3((items + 255) / 256, R), dim3(256), 0, st, ev, f, rg, gc, spec);
+void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_items, hipStream_t st) {
+    if (njobs <= 0 || total <= 0) return;
+    check_batch(total);
+    hipLaunchKernelGGL(fold_ring_kernel, dim3((max_items + 255) / 256, total), dim3(256), 0, st, jobs, njobs);
     MDP_HIP(hipGetLastError());
 }
 
-void launch_proj_fused(const double* gc, const double* spec_hat, const double* Sf, const double* Si, const Fold& f,
-                       int m_lo, int m_hi, int q_lo, int q_hi, const double* lf, const double* rf, const double* tf,
-                       const double* colc, double* ckpt, double* xs, double* thin, int R, hipStream_t st) {
-    check_batch(R);
-    if (!fused_projector_supported(f, m_lo, m_hi, q_lo, q_hi)) throw Error(MDP_ERR_ARG, "fused projector geometry");
-    RingGeom rg{m_lo, m_hi, q_lo, q_hi};
-    const int nseg = fused_segments(m_lo, m_hi);
-    const size_t lds = (size_t)(m_hi - m_lo + 3) * sizeof(double2) + 5 * 64 * sizeof(double);
-    hipLaunchKernelGGL(proj_fused_kernel<FUSED_K>, dim3(f.W / 64, R), dim3(64), lds, st, gc, spec_hat, Sf, Si, f, rg,
-                       reinterpret_cast<const dv2*>(lf), reinterpret_cast<const dv2*>(rf),
-                       reinterpret_cast<const dv2*>(tf), colc, ckpt, xs, thin, nseg);
+void launch_proj_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_wblk, size_t lds_bytes,
+                            hipStream_t st) {
+    if (njobs <= 0 || total <= 0) return;
+    check_batch(total);
+    hipLaunchKernelGGL(proj_fused_kernel<FUSED_K>, dim3(max_wblk, total), dim3(64), lds_bytes, st, jobs, njobs);
     MDP_HIP(hipGetLastError());
 }
 
-void launch_gather_q_fused(const double* us, const double* thin, const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi,
-                           const int* gm, const int* gq, int ng, int R, double* Q, int ldq, int col0, hipStream_t st) {
-    check_batch(R);
-    RingGeom rg{m_lo, m_hi, q_lo, q_hi};
-    const int rows_pad = fused_segments(m_lo, m_hi) * FUSED_K;
-    dim3 grid((ng + 255) / 256, R);
-    hipLaunchKernelGGL(gather_q_fused_kernel, grid, dim3(256), 0, st, us, thin, f, rg, rows_pad, gm, gq, ng, Q, ldq,
-                       col0);
+void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, hipStream_t st) {
+    if (njobs <= 0 || total <= 0) return;
+    check_batch(total);
+    hipLaunchKernelGGL(gather_q_fused_kernel, dim3((max_ng + 255) / 256, total), dim3(256), 0, st, jobs, njobs);
     MDP_HIP(hipGetLastError());
 }
 

@@ -200,65 +200,160 @@ Band box_band(const APPlan& plan, const Geometry& G) {
     return Band{G.m_lo - 1, G.m_hi - G.m_lo + 3};
 }
 
-// Q by the support-in / gamma-out route (FP64): per chunk of columns, the
-// ring RHS and the folded special rows, their sine GEMM, the fused sweep with
-// the gamma-row reductions, the inverse GEMM of the four full gamma rows and
-// the gather into Q.
-void build_q_fused(mdp_ctx* ctx, const APPlan& plan, mdp_projector* P, hipStream_t st) {
-    const Geometry& G = P->g;
-    const Fold& f = plan.f;
-    const int n = G.n, W = f.W, ng = G.n_gamma, ncol = 8 * P->m_star;
-    const int nseg = fused_segments(G.m_lo, G.m_hi), rows_pad = nseg * FUSED_K, nb = W / 64;
-    const size_t per_a = (size_t)nseg * 2 * W + (size_t)nb * rows_pad * 4;      // ckpt + thin
-    const size_t per_b = (size_t)(n + 1) * 4 + (size_t)(4 + 4 + 8 + 8) * W;       // gc, spec, spec_hat, xs, us
-    size_t chunk = ctx->ws_cap / ((per_a + per_b) * sizeof(double));
-    chunk = std::max<size_t>(1, std::min<size_t>({chunk, (size_t)65535, (size_t)ncol}));
-    const size_t need_a = chunk * per_a * sizeof(double), need_b = chunk * per_b * sizeof(double);
-    if (need_a > ctx->ws.a.bytes || need_b > ctx->ws.b.bytes) {
-        MDP_HIP(hipDeviceSynchronize());
-        ctx->ws.a.reserve(need_a);
-        ctx->ws.b.reserve(need_b);
+// A projector whose Q the fused route computes.
+struct FusedItem {
+    const APPlan* plan;
+    mdp_projector* P;
+};
+
+// Q of every item by the support-in / gamma-out route (FP64), the columns of all
+// items through each stage together.  Per batch of columns (as many as the
+// workspace holds): the ring RHS and the folded special rows, their sine GEMM
+// (one launch per n), the fused sweep with the gamma-row reductions, the inverse
+// GEMM of the four full gamma rows (one launch per n) and the gather into Q.
+void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
+    if (items.empty()) return;
+    std::stable_sort(items.begin(), items.end(),
+                     [](const FusedItem& a, const FusedItem& b) { return a.plan->n < b.plan->n; });
+    struct Per { size_t a, b; int ncol; };
+    std::vector<Per> per(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+        const Geometry& G = items[i].P->g;
+        const Fold& f = items[i].plan->f;
+        const int nseg = fused_segments(G.m_lo, G.m_hi), rows_pad = nseg * FUSED_K, nb = f.W / 64;
+        per[i].a = (size_t)nseg * 2 * f.W + (size_t)nb * rows_pad * 4;      // ckpt + thin
+        per[i].b = (size_t)(G.n + 1) * 4 + (size_t)(4 + 4 + 8 + 8) * f.W;    // gc, spec, spec_hat, xs, us
+        per[i].ncol = 8 * items[i].P->m_star;
     }
+    const size_t cap = ctx->ws_cap / sizeof(double);
     Profiler& pr = ctx->ws.prof;
-    const double gemm_row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
-    const int box_rows = G.m_hi - G.m_lo + 3;
-    for (int col0 = 0; col0 < ncol; col0 += (int)chunk) {
-        const int R = std::min((int)chunk, ncol - col0);
-        double* ckpt = ctx->ws.a.as<double>();
-        double* thin = ckpt + (size_t)R * nseg * 2 * W;
-        double* gc = ctx->ws.b.as<double>();
-        double* spec = gc + (size_t)R * (n + 1) * 4;
-        double* spec_hat = spec + (size_t)R * 4 * W;
-        double* xs = spec_hat + (size_t)R * 4 * W;
-        double* us = xs + (size_t)R * 8 * W;
-        SrcDesc src{};
-        src.kind = Src::STENCIL_E;
-        src.E = P->E.as<double>();
-        src.ldE = ng;
-        src.col0 = col0;
-        src.gidx = P->gidx.as<int>();
-        src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
-        pr.run("fold_ring", st, 0.0, (double)R * ((n + 1) * 4.0 + 4.0 * (n - 1)) * 8.0,
-               [&] { launch_fold_ring(src, n, f, plan.sc, R, gc, spec, st); });
-        pr.run("gemm_sine_f64", st, 4.0 * R * gemm_row_flops, 2.0 * 4.0 * R * (n - 1) * 8.0,
-               [&] { launch_gemm_bd<double>(spec, plan.Sf64.as<double>(), spec_hat, (long)R * 4, f, st); });
-        // algorithmic flops per column element of the swept band (rows m_lo-1..m_hi+1): forward
-        // elimination 7, back substitution 10, synthesis products and sums 8; ring transform 3 (box rows)
-        pr.run("ap_fused_f64", st,
-               (double)R * ((double)box_rows * (n - 1) * 25.0 + (double)(G.m_hi - G.m_lo + 1) * (n - 1) * 3.0),
-               (double)R * ((G.m_hi - G.m_lo + 1) * 32.0 + 4.0 * (n - 1) * 8.0 + 8.0 * (n - 1) * 8.0 +
-                            (double)box_rows * 4 * 8.0),
-               [&] {
-                   launch_proj_fused(gc, spec_hat, plan.Sf64.as<double>(), plan.Si64.as<double>(), f, G.m_lo,
-                                     G.m_hi, G.q_lo, G.q_hi, plan.lf64.as<double>(), plan.rf64.as<double>(),
-                                     plan.tf64.as<double>(), plan.colc64.as<double>(), ckpt, xs, thin, R, st);
-               });
-        pr.run("gemm_sine_f64", st, 8.0 * R * gemm_row_flops, 2.0 * 8.0 * R * (n - 1) * 8.0,
-               [&] { launch_gemm_bd<double>(xs, plan.Si64.as<double>(), us, (long)R * 8, f, st); });
-        pr.run("gather_q", st, 0.0, (double)ng * R * 16.0 * 2.0, [&] {
-            launch_gather_q_fused(us, thin, f, G.m_lo, G.m_hi, G.q_lo, G.q_hi, P->gm, P->gq, ng,
-                                  R, P->Q.as<double>(), ng, col0, st);
-        });
+    struct JobHost { size_t item; int col0, R; };
+    size_t it = 0;
+    int next_col = 0;
+    while (it < items.size()) {
+        // the next batch: whole or partial items in order, within the workspace and the grid limit
+        std::vector<JobHost> jh;
+        size_t sa = 0, sb = 0;
+        int total = 0;
+        while (it < items.size() && total < 65535) {
+            const Per& q = per[it];
+            const size_t used = sa + sb, each = q.a + q.b;
+            const size_t room = used < cap ? (cap - used) / each : 0;
+            const int R = (int)std::min<size_t>({room, (size_t)(65535 - total), (size_t)(q.ncol - next_col)});
+            if (R <= 0) break;
+            jh.push_back({it, next_col, R});
+            sa += (size_t)R * q.a;
+            sb += (size_t)R * q.b;
+            total += R;
+            next_col += R;
+            if (next_col == q.ncol) { ++it; next_col = 0; }
+        }
+        if (jh.empty()) throw Error(MDP_ERR_OOM, "workspace too small for one projector column");
+        if (sa * sizeof(double) > ctx->ws.a.bytes || sb * sizeof(double) > ctx->ws.b.bytes) {
+            MDP_HIP(hipDeviceSynchronize());
+            ctx->ws.a.reserve(std::max<size_t>(sa, 1) * sizeof(double));
+            ctx->ws.b.reserve(std::max<size_t>(sb, 1) * sizeof(double));
+        }
+        // regions: ws.b = gc | spec | spec_hat | xs | us, ws.a = ckpt | thin, each in job order
+        size_t n_gc = 0, n_sp = 0, n_x = 0, n_ck = 0;
+        for (const JobHost& j : jh) {
+            const Geometry& G = items[j.item].P->g;
+            const Fold& f = items[j.item].plan->f;
+            n_gc += (size_t)j.R * (G.n + 1) * 4;
+            n_sp += (size_t)j.R * 4 * f.W;
+            n_x += (size_t)j.R * 8 * f.W;
+            n_ck += (size_t)j.R * fused_segments(G.m_lo, G.m_hi) * 2 * f.W;
+        }
+        double* B = ctx->ws.b.as<double>();
+        double* A = ctx->ws.a.as<double>();
+        double *gc = B, *spec = gc + n_gc, *spec_hat = spec + n_sp, *xs = spec_hat + n_sp, *us = xs + n_x;
+        double *ckpt = A, *thin = ckpt + n_ck;
+        std::vector<FusedJob> jobs(jh.size());
+        int b0 = 0, max_items = 0, max_wblk = 0, max_ng = 0;
+        size_t lds = 0;
+        double fold_bytes = 0.0, sweep_flops = 0.0, sweep_bytes = 0.0, gather_bytes = 0.0;
+        for (size_t q = 0; q < jh.size(); ++q) {
+            const JobHost& j = jh[q];
+            const FusedItem& itm = items[j.item];
+            const APPlan& plan = *itm.plan;
+            const Geometry& G = itm.P->g;
+            const Fold& f = plan.f;
+            const int n = G.n, ng = G.n_gamma, R = j.R;
+            const int nseg = fused_segments(G.m_lo, G.m_hi);
+            FusedJob& J = jobs[q];
+            J.src = SrcDesc{};
+            J.src.kind = Src::STENCIL_E;
+            J.src.E = itm.P->E.as<double>();
+            J.src.ldE = ng;
+            J.src.col0 = j.col0;
+            J.src.gidx = itm.P->gidx.as<int>();
+            J.src.m_lo = G.m_lo; J.src.m_hi = G.m_hi; J.src.q_lo = G.q_lo; J.src.q_hi = G.q_hi;
+            J.sc = plan.sc;
+            J.f = f;
+            J.nseg = nseg;
+            J.rows_pad = nseg * FUSED_K;
+            J.ng = ng;
+            J.ldq = ng;
+            J.b0 = b0;
+            J.R = R;
+            J.Sf = plan.Sf64.as<double>();
+            J.Si = plan.Si64.as<double>();
+            J.lf = plan.lf64.as<double>();
+            J.rf = plan.rf64.as<double>();
+            J.tf = plan.tf64.as<double>();
+            J.colc = plan.colc64.as<double>();
+            J.gc = gc; gc += (size_t)R * (n + 1) * 4;
+            J.spec = spec; spec += (size_t)R * 4 * f.W;
+            J.spec_hat = spec_hat; spec_hat += (size_t)R * 4 * f.W;
+            J.xs = xs; xs += (size_t)R * 8 * f.W;
+            J.us = us; us += (size_t)R * 8 * f.W;
+            J.ckpt = ckpt; ckpt += (size_t)R * nseg * 2 * f.W;
+            J.thin = thin; thin += (size_t)R * (f.W / 64) * J.rows_pad * 4;
+            J.Q = itm.P->Q.as<double>();
+            J.gm = itm.P->gm;
+            J.gq = itm.P->gq;
+            b0 += R;
+            max_items = std::max(max_items, n + 1 + 4 * f.W);
+            max_wblk = std::max(max_wblk, f.W / 64);
+            max_ng = std::max(max_ng, ng);
+            lds = std::max(lds, (size_t)(G.m_hi - G.m_lo + 3) * sizeof(double2) + 5 * 64 * sizeof(double));
+            // algorithmic flops per column element of the swept band (rows m_lo-1..m_hi+1): forward
+            // elimination 7, back substitution 10, synthesis products and sums 8; ring transform 3 (box rows)
+            const int box_rows = G.m_hi - G.m_lo + 3;
+            fold_bytes += (double)R * ((n + 1) * 4.0 + 4.0 * (n - 1)) * 8.0;
+            sweep_flops += (double)R * ((double)box_rows * (n - 1) * 25.0 + (double)(G.m_hi - G.m_lo + 1) * (n - 1) * 3.0);
+            sweep_bytes += (double)R * ((G.m_hi - G.m_lo + 1) * 32.0 + 4.0 * (n - 1) * 8.0 + 8.0 * (n - 1) * 8.0 +
+                                        (double)box_rows * 4 * 8.0);
+            gather_bytes += (double)ng * R * 16.0 * 2.0;
+        }
+        HostBlob blob;
+        const size_t o_jobs = blob.put(jobs);
+        const FusedJob* dj = reinterpret_cast<const FusedJob*>(ctx->ws.stage.upload(blob, st) + o_jobs);
+        const int nj = (int)jobs.size();
+        // the sine GEMMs: one per run of jobs with the same n (their rows are consecutive)
+        auto gemms = [&](bool forward) {
+            for (size_t q0 = 0; q0 < jobs.size();) {
+                size_t q1 = q0;
+                long rows = 0;
+                while (q1 < jobs.size() && jobs[q1].f.n == jobs[q0].f.n) rows += jobs[q1++].R;
+                const Fold& f = jobs[q0].f;
+                const double row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
+                const int mult = forward ? 4 : 8;
+                pr.run("gemm_sine_f64", st, mult * rows * row_flops, 2.0 * mult * rows * (f.n - 1) * 8.0, [&] {
+                    if (forward)
+                        launch_gemm_bd<double>(jobs[q0].spec, jobs[q0].Sf, jobs[q0].spec_hat, rows * 4, f, st);
+                    else
+                        launch_gemm_bd<double>(jobs[q0].xs, jobs[q0].Si, jobs[q0].us, rows * 8, f, st);
+                });
+                q0 = q1;
+            }
+        };
+        pr.run("fold_ring", st, 0.0, fold_bytes, [&] { launch_fold_ring_jobs(dj, nj, total, max_items, st); });
+        gemms(true);
+        pr.run("ap_fused_f64", st, sweep_flops, sweep_bytes,
+               [&] { launch_proj_fused_jobs(dj, nj, total, max_wblk, lds, st); });
+        gemms(false);
+        pr.run("gather_q", st, 0.0, gather_bytes, [&] { launch_gather_q_fused_jobs(dj, nj, total, max_ng, st); });
     }
 }
 
@@ -321,110 +416,136 @@ int mdp_set_interface_path(mdp_ctx* ctx, int path) {
 
 const char* mdp_last_error(const mdp_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
+int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int m_star, int precision, void* stream,
+                         mdp_projector** out) {
+    if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
+    if (out && count > 0) std::memset(out, 0, sizeof(mdp_projector*) * count);
+    return guarded(ctx, [&]() -> int {
+        if (count < 1) throw Error(MDP_ERR_ARG, "count must be >= 1");
+        if (!sds || !out) throw Error(MDP_ERR_ARG, "null subdomain or output pointer");
+        if (m_star < 1) throw Error(MDP_ERR_ARG, "M* must be >= 1");
+        check_precision(precision);
+        for (int i = 0; i < count; ++i)
+            if (!std::isfinite(sds[i].k) || !(sds[i].k > 0)) throw Error(MDP_ERR_NONFINITE, "k must be finite and > 0");
+        hipStream_t st = (hipStream_t)stream;
+        std::vector<mdp_projector*> res(count, nullptr);
+        std::vector<FusedItem> fused;
+        std::vector<std::pair<ProjKey, mdp_projector*>> fresh;   // built by this call, not yet cached
+        bool began = false;
+        try {
+            for (int i = 0; i < count; ++i) {
+                const mdp_subdomain* sd = &sds[i];
+                ProjKey key{sd->lx, sd->ly, sd->n, sd->k, m_star, precision};
+                auto it = ctx->cache.find(key);
+                if (it != ctx->cache.end()) { res[i] = it->second; continue; }
+                bool dup = false;
+                for (auto& kv : fresh)
+                    if (kv.first == key) { res[i] = kv.second; dup = true; }
+                if (dup) continue;
+                if (!began) { begin_call(ctx, st); began = true; }
+                // the grid sets relative to the rectangle depend on its size and n only
+                GeomKey gk{sd->lx, sd->ly, sd->n};
+                auto git = ctx->geoms.find(gk);
+                if (git == ctx->geoms.end())
+                    git = ctx->geoms.emplace(gk, make_geometry(sd->x0, sd->y0, sd->lx, sd->ly, sd->n)).first;
+                Geometry g = git->second;
+                APPlan& plan = get_plan(ctx, g.n, g.h, sd->k);
+                std::unique_ptr<mdp_projector> P(new mdp_projector);
+                P->device = ctx->device;
+                P->k = sd->k;
+                P->m_star = m_star;
+                P->precision = precision;
+                P->pool = ctx->pool;
+                BufPool& pool = *ctx->pool;
+                const int ng = g.n_gamma, ncol = 8 * m_star;
+                // gamma node lists in one upload; E and the node -> gamma map are built on the device
+                HostBlob blob;
+                const size_t o_gm = blob.put(g.gm), o_gq = blob.put(g.gq), o_side = blob.put(g.side),
+                             o_rho = blob.put(g.rho), o_t = blob.put(g.t), o_slen = blob.put(g.slen);
+                P->meta = pool.take(blob.size());
+                ctx->ws.stage.copy(P->meta.p, blob, st);
+                const char* mb = P->meta.as<char>();
+                P->gm = reinterpret_cast<const int*>(mb + o_gm);
+                P->gq = reinterpret_cast<const int*>(mb + o_gq);
+                P->gside = reinterpret_cast<const int*>(mb + o_side);
+                P->grho = reinterpret_cast<const double*>(mb + o_rho);
+                P->gt = reinterpret_cast<const double*>(mb + o_t);
+                P->gslen = reinterpret_cast<const double*>(mb + o_slen);
+                P->E = pool.take((size_t)ng * ncol * sizeof(double));
+                MDP_HIP(hipMemsetAsync(P->E.p, 0, (size_t)ng * ncol * sizeof(double), st));
+                launch_extension(P->gside, P->grho, P->gt, P->gslen, ng, sd->k, m_star, P->E.as<double>(), st);
+                const size_t nodes = (size_t)(g.n + 1) * (g.n + 1);
+                P->gidx = pool.take(nodes * sizeof(int));
+                MDP_HIP(hipMemsetAsync(P->gidx.p, 0xff, nodes * sizeof(int), st));   // -1 everywhere
+                launch_gamma_index(P->gm, P->gq, ng, g.n, P->gidx.as<int>(), st);
+                P->Q = pool.take((size_t)ng * ncol * 2 * sizeof(double));
+                P->g = std::move(g);
+                const Geometry& G = P->g;
+                mdp_projector* raw = P.release();
+                fresh.push_back({key, raw});
+                res[i] = raw;
+                if (precision == MDP_C128 && ctx->projector_path == MDP_PATH_AUTO &&
+                    fused_projector_supported(plan.f, G.m_lo, G.m_hi, G.q_lo, G.q_hi) &&
+                    plan.twist_ratio[G.m_hi + 1] > 1e-13) {
+                    fused.push_back({&plan, raw});
+                    continue;
+                }
+                // dense route: full AP solves of the columns, gathered onto gamma
+                const int chunk = chunk_size(plan, precision, ctx->ws_cap, ncol);
+                prepare_ws(ctx, plan, precision, chunk);
+                for (int col0 = 0; col0 < ncol; col0 += chunk) {
+                    const int R = std::min(chunk, ncol - col0);
+                    SrcDesc src{};
+                    src.kind = Src::STENCIL_E;
+                    src.E = raw->E.as<double>();
+                    src.ldE = ng;
+                    src.col0 = col0;
+                    src.gidx = raw->gidx.as<int>();
+                    src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
+                    double* Qd = raw->Q.as<double>();
+                    const int* gmd = raw->gm;
+                    const int* gqd = raw->gq;
+                    const int n = G.n;
+                    const Fold f = plan.f;
+                    solve_batch(plan, ctx->ws, precision, src, false, R, box_band(plan, G),
+                                [&](const void* u, const float* du, Band bd) {
+                                    ctx->ws.prof.run("gather_q", st, 0.0, (double)ng * R * 16.0 * 2.0, [&] {
+                                        if (precision == MDP_C128)
+                                            launch_gather_q<double>((const double*)u, du, n, f, bd, gmd, gqd, ng, R,
+                                                                    Qd, ng, col0, st);
+                                        else
+                                            launch_gather_q<float>((const float*)u, du, n, f, bd, gmd, gqd, ng, R,
+                                                                   Qd, ng, col0, st);
+                                    });
+                                },
+                                st);
+                }
+            }
+            build_q_fused(ctx, fused, st);
+        } catch (...) {
+            // nothing built by this call is handed out; its projectors are dropped after the device drains
+            (void)hipDeviceSynchronize();
+            for (auto& kv : fresh) mdp_projector_release(kv.second);
+            throw;
+        }
+        if (began) end_call(ctx, st);
+        for (auto& kv : fresh) {
+            kv.second->refs.store(1);   // the cache's reference; the callers' follow
+            ctx->cache[kv.first] = kv.second;
+        }
+        for (int i = 0; i < count; ++i) {
+            res[i]->refs.fetch_add(1);
+            out[i] = res[i];
+        }
+        return MDP_OK;
+    });
+}
+
 int mdp_build_projector(mdp_ctx* ctx, const mdp_subdomain* sd, int m_star, int precision, void* stream,
                         mdp_projector** out) {
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
-    return guarded(ctx, [&]() -> int {
-        if (!sd || !out) throw Error(MDP_ERR_ARG, "null subdomain or output pointer");
-        *out = nullptr;
-        if (m_star < 1) throw Error(MDP_ERR_ARG, "M* must be >= 1");
-        check_precision(precision);
-        if (!std::isfinite(sd->k) || !(sd->k > 0)) throw Error(MDP_ERR_NONFINITE, "k must be finite and > 0");
-        ProjKey key{sd->lx, sd->ly, sd->n, sd->k, m_star, precision};
-        auto it = ctx->cache.find(key);
-        if (it != ctx->cache.end()) {
-            it->second->refs.fetch_add(1);
-            *out = it->second;
-            return MDP_OK;
-        }
-        hipStream_t st = (hipStream_t)stream;
-        // the grid sets relative to the rectangle depend on its size and n only
-        GeomKey gk{sd->lx, sd->ly, sd->n};
-        auto git = ctx->geoms.find(gk);
-        if (git == ctx->geoms.end())
-            git = ctx->geoms.emplace(gk, make_geometry(sd->x0, sd->y0, sd->lx, sd->ly, sd->n)).first;
-        Geometry g = git->second;
-        APPlan& plan = get_plan(ctx, g.n, g.h, sd->k);
-        std::unique_ptr<mdp_projector> P(new mdp_projector);
-        P->device = ctx->device;
-        P->k = sd->k;
-        P->m_star = m_star;
-        P->precision = precision;
-        P->pool = ctx->pool;
-        BufPool& pool = *ctx->pool;
-        const int ng = g.n_gamma, ncol = 8 * m_star;
-        begin_call(ctx, st);
-        // gamma node lists in one upload; E and the node -> gamma map are built on the device
-        HostBlob blob;
-        const size_t o_gm = blob.put(g.gm), o_gq = blob.put(g.gq), o_side = blob.put(g.side),
-                     o_rho = blob.put(g.rho), o_t = blob.put(g.t), o_slen = blob.put(g.slen);
-        P->meta = pool.take(blob.size());
-        ctx->ws.stage.copy(P->meta.p, blob, st);
-        const char* mb = P->meta.as<char>();
-        P->gm = reinterpret_cast<const int*>(mb + o_gm);
-        P->gq = reinterpret_cast<const int*>(mb + o_gq);
-        P->gside = reinterpret_cast<const int*>(mb + o_side);
-        P->grho = reinterpret_cast<const double*>(mb + o_rho);
-        P->gt = reinterpret_cast<const double*>(mb + o_t);
-        P->gslen = reinterpret_cast<const double*>(mb + o_slen);
-        P->E = pool.take((size_t)ng * ncol * sizeof(double));
-        MDP_HIP(hipMemsetAsync(P->E.p, 0, (size_t)ng * ncol * sizeof(double), st));
-        launch_extension(P->gside, P->grho, P->gt, P->gslen, ng, sd->k, m_star, P->E.as<double>(), st);
-        const size_t nodes = (size_t)(g.n + 1) * (g.n + 1);
-        P->gidx = pool.take(nodes * sizeof(int));
-        MDP_HIP(hipMemsetAsync(P->gidx.p, 0xff, nodes * sizeof(int), st));   // -1 everywhere
-        launch_gamma_index(P->gm, P->gq, ng, g.n, P->gidx.as<int>(), st);
-        P->Q = pool.take((size_t)ng * ncol * 2 * sizeof(double));
-        P->g = std::move(g);
-        const Geometry& G = P->g;
-
-        if (precision == MDP_C128 && ctx->projector_path == MDP_PATH_AUTO &&
-            fused_projector_supported(plan.f, G.m_lo, G.m_hi, G.q_lo, G.q_hi) &&
-            plan.twist_ratio[G.m_hi + 1] > 1e-13) {
-            build_q_fused(ctx, plan, P.get(), st);
-            end_call(ctx, st);
-            mdp_projector* raw = P.release();
-            raw->refs.store(2);
-            ctx->cache[key] = raw;
-            *out = raw;
-            return MDP_OK;
-        }
-        const int chunk = chunk_size(plan, precision, ctx->ws_cap, ncol);
-        prepare_ws(ctx, plan, precision, chunk);
-        for (int col0 = 0; col0 < ncol; col0 += chunk) {
-            const int R = std::min(chunk, ncol - col0);
-            SrcDesc src{};
-            src.kind = Src::STENCIL_E;
-            src.E = P->E.as<double>();
-            src.ldE = ng;
-            src.col0 = col0;
-            src.gidx = P->gidx.as<int>();
-            src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
-            double* Qd = P->Q.as<double>();
-            const int* gmd = P->gm;
-            const int* gqd = P->gq;
-            const int n = G.n;
-            const Fold f = plan.f;
-            solve_batch(plan, ctx->ws, precision, src, false, R, box_band(plan, G),
-                        [&](const void* u, const float* du, Band bd) {
-                            ctx->ws.prof.run("gather_q", st, 0.0, (double)ng * R * 16.0 * 2.0, [&] {
-                                if (precision == MDP_C128)
-                                    launch_gather_q<double>((const double*)u, du, n, f, bd, gmd, gqd, ng, R, Qd, ng,
-                                                            col0, st);
-                                else
-                                    launch_gather_q<float>((const float*)u, du, n, f, bd, gmd, gqd, ng, R, Qd, ng,
-                                                           col0, st);
-                            });
-                        },
-                        st);
-        }
-        end_call(ctx, st);
-        mdp_projector* raw = P.release();
-        raw->refs.store(2);  // one for the cache, one for the caller
-        ctx->cache[key] = raw;
-        *out = raw;
-        return MDP_OK;
-    });
+    if (!sd || !out) return fail(ctx, MDP_ERR_ARG, "null subdomain or output pointer");
+    return mdp_build_projectors(ctx, 1, sd, m_star, precision, stream, out);
 }
 
 int mdp_projector_info(const mdp_projector* P, int* n_gamma, const int** gamma_mq, const mdp_c128** q_dev) {

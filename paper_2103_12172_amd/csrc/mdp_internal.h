@@ -303,18 +303,31 @@ void launch_extend_density(const double* E, int ng, int ncol, const double* c, c
 
 // projector build, support-in / gamma-out form (FP64)
 constexpr int FUSED_K = 8;   // rows per recomputed segment of the fused tridiagonal sweep
+// One projector's columns in a batched support-in / gamma-out build: global
+// columns b0 .. b0+R-1 of the launches are its columns src.col0 .. src.col0+R-1.
+// Buffers are the job's own (column 0 of the job at the pointer); jobs of one
+// n hold consecutive spec / spec_hat / xs / us ranges so that one sine GEMM per
+// n covers them.  Layouts: gc [R][n+1][4] ring table, spec / spec_hat [R][4][W]
+// folded special rows, lf / rf / tf [(n+1)][W] interleaved complex Thomas factors
+// l_m, r_m = 1/d_m and twisted pivots, ckpt [R][nseg][2][W], xs / us
+// [R][2][4][W], thin [R][W/64][rows_pad][4].
+struct FusedJob {
+    SrcDesc src;
+    StencilCoef sc;
+    Fold f;
+    int nseg, rows_pad, ng, ldq;
+    int b0, R;
+    const double *Sf, *Si, *lf, *rf, *tf, *colc;
+    double *gc, *spec, *spec_hat, *ckpt, *xs, *thin, *us, *Q;
+    const int *gm, *gq;
+};
+// jobs: device table sorted by b0; total = sum of R; max_*: largest per-job extents
+void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_items, hipStream_t st);
+void launch_proj_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_wblk, size_t lds_bytes,
+                            hipStream_t st);
+void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, hipStream_t st);
 bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi);
 int fused_segments(int m_lo, int m_hi);   // segments of FUSED_K rows covering m = m_lo-1..m_hi+1
-// gc: [R][n+1][4] ring table, spec: [R][4][W] folded special rows
-void launch_fold_ring(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, double* gc, double* spec,
-                      hipStream_t st);
-// lf, rf, tf: [(n+1)][W] interleaved complex Thomas factors l_m, r_m = 1/d_m and twisted pivots tw_m
-void launch_proj_fused(const double* gc, const double* spec_hat, const double* Sf, const double* Si, const Fold& f,
-                       int m_lo, int m_hi, int q_lo, int q_hi, const double* lf, const double* rf, const double* tf,
-                       const double* colc, double* ckpt, double* xs, double* thin, int R, hipStream_t st);
-void launch_gather_q_fused(const double* us, const double* thin, const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi,
-                           const int* gm, const int* gq, int ng, int R, double* Q, int ldq, int col0, hipStream_t st);
-
 // interface least squares
 // tri: 0 full; 1 lower-triangle tiles of C only; 2 op(B) upper triangular (skip its zero part)
 void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const double2* A, int lda,

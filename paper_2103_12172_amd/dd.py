@@ -49,10 +49,7 @@ def side_structs(w: wl.Workload, m_star: int):
 
 
 def build_projectors(ctx, w: wl.Workload, precision, stream=None) -> List[object]:
-    out = []
-    for s in subdomain_structs(w):
-        out.append(mdp.mdp_build_projector(ctx, s, w.m_star, precision, stream))
-    return out
+    return mdp.mdp_build_projectors(ctx, subdomain_structs(w), w.m_star, precision, stream)
 
 
 def source_tensors(ctx, w: wl.Workload, projectors) -> Optional[list]:

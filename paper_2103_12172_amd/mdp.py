@@ -23,7 +23,8 @@ PRECISIONS = {"c128": MDP_C128, "c64": MDP_C64, "c64r": MDP_C64_REFINED}
 STATUS_NAMES = {0: "MDP_OK", -1: "MDP_ERR_ARG", -2: "MDP_ERR_HIP", -3: "MDP_ERR_OOM", -4: "MDP_ERR_SINGULAR",
                 -5: "MDP_ERR_NONFINITE", -6: "MDP_ERR_NODEVICE"}
 
-EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector", "mdp_projector_info",
+EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector", "mdp_build_projectors",
+            "mdp_projector_info",
             "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
             "mdp_cheb_coeffs", "mdp_version", "mdp_cache_clear", "mdp_profile_enable", "mdp_profile_report",
             "mdp_set_projector_path", "mdp_set_interface_path", "mdp_profile_select", "mdp_projector_gamma_feet", "mdp_ap_grid"]
@@ -76,6 +77,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mdp_last_error.restype = ctypes.c_char_p
     lib.mdp_build_projector.argtypes = [vp, ctypes.POINTER(Subdomain), ip, ip, vp, ctypes.POINTER(vp)]
     lib.mdp_build_projector.restype = ip
+    lib.mdp_build_projectors.argtypes = [vp, ip, ctypes.POINTER(Subdomain), ip, ip, vp, ctypes.POINTER(vp)]
+    lib.mdp_build_projectors.restype = ip
     lib.mdp_projector_info.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ctypes.POINTER(ip)), ctypes.POINTER(vp)]
     lib.mdp_projector_info.restype = ip
     lib.mdp_projector_release.argtypes = [vp]
@@ -205,6 +208,17 @@ def mdp_build_projector(ctx: Context, sd: Subdomain, m_star: int, precision, str
     ctx.check(ctx.lib.mdp_build_projector(ctx.handle, ctypes.byref(sd), m_star, prec,
                                           ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
     return Projector(ctx, h, m_star)
+
+
+def mdp_build_projectors(ctx: Context, sds: Sequence[Subdomain], m_star: int, precision, stream=None):
+    """Projectors of all subdomains in one call (batched launches over every new projector)."""
+    prec = PRECISIONS.get(precision, precision)
+    n = len(sds)
+    arr = (Subdomain * n)(*sds)
+    hs = (ctypes.c_void_p * n)()
+    ctx.check(ctx.lib.mdp_build_projectors(ctx.handle, n, arr, m_star, prec, ctypes.c_void_p(_stream_ptr(stream)),
+                                           hs))
+    return [Projector(ctx, ctypes.c_void_p(hs[i]), m_star) for i in range(n)]
 
 
 def make_sides(sides: Sequence[Side], d_arrays: Sequence[Optional[np.ndarray]]):

@@ -14,8 +14,8 @@ nested-dissection factorisation of its Gram matrix), through the C-ABI.
   oracle run at that size; the refinement's own convergence check must pass,
   the residual must be at the level of the small layout's, and for sampled
   subdomains the oracle's reconstruction from the GPU's coefficients (its
-  banded-LU AP solve of eq. potential_solution_homo) must match the GPU's
-  solution on N+.
+  own AP solve of eq. potential_solution_homo) must match the GPU's solution
+  on N+.
 """
 import numpy as np
 import pytest
@@ -114,8 +114,6 @@ def test_uneven_full_size(ctx):
     worst = 0.0
     for i in picks:
         sd = w.subdomains[i]
-        if sd.n > 256:   # the oracle's banded LU at n = 512 takes minutes: sample the smaller grids
-            continue
         g = APGrid(sd.x0, sd.y0, sd.lx, sd.ly, sd.n)
         E = extension_matrix(g, sd.k, w.m_star)
         uref = potential(g, sd.k, E @ c[i], make_solver(sd.n, g.h, sd.k))
