@@ -473,6 +473,51 @@ def config_uneven_small(seed: int = 4) -> Workload:
     return config_uneven(3, 3, (32, 48, 64), (5.0, 15.0), 8, seed, 10.0)
 
 
+def config_adjoint(nx: int = 4, ny: int = 4, n: int = 512, k2_range=(400.0, 3600.0), m_star: int = 32,
+                   seed: int = 5, k_data: float = 40.0, theta: float = math.pi / 6, bc=None) -> Workload:
+    """Unit square as nx x ny equal squares with piecewise-constant k^2 drawn
+    uniformly from k2_range (numpy default_rng(seed)); data of the plane wave
+    exp(i k_data (x cos theta + y sin theta)) on the outer sides (Dirichlet, or
+    bc(ix, iy, side) -> (alpha, beta)).  No exact solution."""
+    rng = np.random.default_rng(seed)
+    k2 = rng.uniform(k2_range[0], k2_range[1], size=nx * ny)
+    ks = [float(math.sqrt(v)) for v in k2]
+    subs, sides = grid_topology(nx, ny, 0.0, 0.0, 1.0 / nx, 1.0 / ny, ks, n, bc or (lambda ix, iy, s: (1.0, 0.0)))
+    u, g = plane_wave(k_data, theta)
+    w = Workload("adjoint_%dx%d_n%d" % (nx, ny, n), subs, sides, m_star, u, g, "c128", has_exact=False,
+                 notes="%dx%d squares, n=%d, k^2 in U[%g,%g] (seed %d), M*=%d, plane-wave data k=%g"
+                 % (nx, ny, n, k2_range[0], k2_range[1], seed, m_star, k_data))
+    w.extra["k2"] = [float(v) for v in k2]
+    return w
+
+
+def config_adjoint_small(seed: int = 5) -> Workload:
+    """The adjoint layout at a size the oracle differentiates in seconds: 2x2
+    squares, n = 24, k^2 in U[100, 400], M* = 5, plane-wave data k = 12;
+    Dirichlet on x = 0, Neumann on y = 0, Robin (1, 1/2) on x = 1 and y = 1."""
+    def bc(ix, iy, s):
+        return {LEFT: (1.0, 0.0), BOTTOM: (0.0, 1.0), RIGHT: (1.0, 0.5), TOP: (1.0, 0.5)}[s]
+    return config_adjoint(2, 2, 24, (100.0, 400.0), 5, seed, 12.0, bc=bc)
+
+
+def receiver_points(w: Workload, count: int, seed: int):
+    """count points uniform over the bounding box of the subdomains (seeded) and
+    the subdomain holding each (the first in order whose closed rectangle does)."""
+    rng = np.random.default_rng(seed)
+    x0 = min(sd.x0 for sd in w.subdomains)
+    x1 = max(sd.x0 + sd.lx for sd in w.subdomains)
+    y0 = min(sd.y0 for sd in w.subdomains)
+    y1 = max(sd.y0 + sd.ly for sd in w.subdomains)
+    pts = np.column_stack([rng.uniform(x0, x1, size=count), rng.uniform(y0, y1, size=count)])
+    owner = []
+    for x, y in pts:
+        for i, sd in enumerate(w.subdomains):
+            if sd.x0 <= x <= sd.x0 + sd.lx and sd.y0 <= y <= sd.y0 + sd.ly:
+                owner.append(i)
+                break
+    return pts, owner
+
+
 WORKLOADS = {
     "two_rect": config_two_rect,
     "cross_point": config_cross_point,
