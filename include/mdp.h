@@ -240,6 +240,29 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs,
                         const mdp_source* sources, void* stream, mdp_c128* c_out, double* rel_residual_out,
                         double* cond_estimate_out);
 
+/* Gradient of a receiver functional of the DD solve (f = 0) with respect to
+ * every subdomain's k^2 and the boundary data, by a reverse pass through the
+ * three steps of Sec. 3.5 (the conjugate-transposed AP solve of the
+ * reconstruction, the adjoint of the coefficient expansion and of the least
+ * squares, and k^2-directional derivatives of the AP solves: dA/dk^2 of the
+ * scheme of eq. FD_scheme and of the x-end rows, dE/dk^2 of the extension of
+ * eq. general_extension).  The functional is
+ *     Phi = Re sum_t conj(ubar_t) u_{sub_t}(node_t),
+ * u the reconstruction of mdp_reconstruct; for J = sum_t |u_t - u_obs_t|^2 pass
+ * ubar = 2 (u - u_obs).  Arguments as mdp_solve_interface (the interface
+ * system is solved again: nothing of an earlier call is kept); receivers (host
+ * arrays of n_rcv): subdomain index, node index m*(n+1)+q of its auxiliary grid
+ * (any node; the reconstruction is the solution on N+), complex weight ubar_t
+ * (weights of one node add).  Outputs (host): grad_k2[i] = dPhi/d(k_i^2)
+ * (n_sub doubles); grad_d[(4 i + s) M* + j] = dPhi/d(Re d) + i dPhi/d(Im d) for
+ * coefficient j of boundary side s of subdomain i (zero for interface sides).
+ * Requires complex128 projectors.  Waits for the stream.  Errors: as
+ * mdp_solve_interface, plus MDP_ERR_ARG (receiver out of range, a projector
+ * not complex128) and MDP_ERR_SINGULAR (the system needed the dense fallback). */
+int mdp_dd_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, const mdp_projector* const* P,
+                    const mdp_side* sides, int m_star, int n_rcv, const int* rcv_sub, const int* rcv_node,
+                    const mdp_c128* ubar, void* stream, double* grad_k2, mdp_c128* grad_d);
+
 /* Step 3 of Sec. 3.5 for n_sub subdomains: xi_gamma = Ex(sum_j c_j Psi_j) and
  * u = P_{N+} xi_gamma = w - G^(h)(L^(h) w |_{M+}) (eqs. Potential_def,
  * potential_solution_homo); with sources (host, n_sub entries, or NULL),

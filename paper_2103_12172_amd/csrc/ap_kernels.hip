@@ -65,6 +65,7 @@ struct SrcEval {
     }
     // right-hand side g(m, q) of the AP at an interior node (zero on the end rows)
     __device__ inline C64 rhs(int b, int m, int q) const {
+        if (d.kind == Src::GRID_ALL) return (q <= 0 || q >= n) ? C64{0.0, 0.0} : wgrid(b, m, q);
         if (m <= 0 || m >= n || q <= 0 || q >= n) return {0.0, 0.0};
         if (d.kind == Src::GRID) return wgrid(b, m, q);
         if (!in_mplus(m, q)) return {0.0, 0.0};
@@ -110,6 +111,57 @@ fold_rhs_kernel(SrcEval ev, Fold f, int planes, Band bd, T* __restrict__ out) {
 // fac planes: [0] l.re [1] l.im [2] r.re [3] r.im [4] tw.re [5] tw.im, each
 // (n+1) x W by absolute row; colc: [0] a, [1] sup0.re, [2] sup0.im.
 // y is kept in `out` between the sweeps.
+// Conjugate-transposed solve T^H x = g for every mode column c and entry b, all
+// rows m = 0..n, with the LU factors T = L U of the forward solve (L unit lower
+// bidiagonal with l_m, U upper bidiagonal with pivots d_m = 1/r_m and
+// super-diagonal s_m: s_0 = sup0, s_m = a):
+//   U^H y = g:  y_m = conj(r_m) (g_m - conj(s_{m-1}) y_{m-1}),
+//   L^H x = y:  x_n = y_n, x_m = y_m - conj(l_{m+1}) x_{m+1}.
+// y is kept in `out` between the sweeps.  FP64, one column per thread.
+__global__ void __launch_bounds__(256)
+tridiag_adj_kernel(const double* __restrict__ in, int planes_in, double* __restrict__ out,
+                   const double* __restrict__ fac, const double* __restrict__ colc, int n, int W, int R) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (c >= W || b >= R) return;
+    const long plane = (long)(n + 1) * W;
+    const double* g_re = in + (long)b * planes_in * plane + c;
+    const double* g_im = (planes_in == 2) ? g_re + plane : nullptr;
+    double* o_re = out + (long)b * 2 * plane + c;
+    double* o_im = o_re + plane;
+    const double* l_re = fac + c;
+    const double* l_im = fac + plane + c;
+    const double* r_re = fac + 2 * plane + c;
+    const double* r_im = fac + 3 * plane + c;
+    const double a = colc[c], s0r = colc[W + c], s0i = colc[2 * W + c];
+    double yr = 0.0, yi = 0.0;
+    for (int m = 0; m <= n; ++m) {
+        const long off = (long)m * W;
+        double gr = g_re[off], gi = g_im ? g_im[off] : 0.0;
+        if (m >= 1) {   // g - conj(s) y
+            const double sr = (m == 1) ? s0r : a, si = (m == 1) ? s0i : 0.0;
+            gr -= sr * yr + si * yi;
+            gi -= sr * yi - si * yr;
+        }
+        const double rr = r_re[off], ri = r_im[off];   // conj(r) g
+        yr = rr * gr + ri * gi;
+        yi = rr * gi - ri * gr;
+        o_re[off] = yr;
+        o_im[off] = yi;
+    }
+    double xr = yr, xi = yi;
+    for (int m = n - 1; m >= 0; --m) {
+        const long off = (long)m * W, offn = (long)(m + 1) * W;
+        const double lr = l_re[offn], li = l_im[offn];   // y - conj(l_{m+1}) x
+        const double nxr = o_re[off] - (lr * xr + li * xi);
+        const double nxi = o_im[off] - (lr * xi - li * xr);
+        xr = nxr;
+        xi = nxi;
+        o_re[off] = xr;
+        o_im[off] = xi;
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256)
 tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, const T* __restrict__ fac,
@@ -604,7 +656,7 @@ __global__ void gather_add_kernel(const T* __restrict__ u, Fold f, Band bd, cons
 // The other 6M* entries of the row are left as they are (the caller zeroes E).
 __global__ void extension_kernel(const int* __restrict__ side, const double* __restrict__ rho,
                                  const double* __restrict__ tpar, const double* __restrict__ slen, int ng, double k,
-                                 int M, double* __restrict__ E) {
+                                 int M, double* __restrict__ E, int deriv) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ng) return;
     const int s = side[i];
@@ -616,8 +668,14 @@ __global__ void extension_kernel(const int* __restrict__ side, const double* __r
     double prev[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // T_{j-1}^(p)
     for (int j = 0; j < M; ++j) {
         const double p0 = cur[0], p2 = sc2 * cur[2], p4 = sc4 * cur[4];
-        E[(long)(s * M + j) * ng + i] = p0 + 0.5 * r2 * (-p2 - k2 * p0) + (r4 / 24.0) * (p4 + 2.0 * k2 * p2 + k4 * p0);
-        E[(long)(4 * M + s * M + j) * ng + i] = r * p0 + (r3 / 6.0) * (-p2 - k2 * p0);
+        if (deriv) {   // d/d(k^2): -rho^2/2 psi + rho^4/24 (2 psi'' + 2 k^2 psi) and -rho^3/6 psi
+            E[(long)(s * M + j) * ng + i] = -0.5 * r2 * p0 + (r4 / 24.0) * (2.0 * p2 + 2.0 * k2 * p0);
+            E[(long)(4 * M + s * M + j) * ng + i] = -(r3 / 6.0) * p0;
+        } else {
+            E[(long)(s * M + j) * ng + i] =
+                p0 + 0.5 * r2 * (-p2 - k2 * p0) + (r4 / 24.0) * (p4 + 2.0 * k2 * p2 + k4 * p0);
+            E[(long)(4 * M + s * M + j) * ng + i] = r * p0 + (r3 / 6.0) * (-p2 - k2 * p0);
+        }
         double nxt[5];
         if (j == 0) {
             nxt[0] = t;
@@ -691,6 +749,14 @@ void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* c
         hipLaunchKernelGGL(tridiag_part_kernel<T>, grid, dim3(64 * P), 0, st, in, planes_in, out, fac, colc, n, f.W,
                            bd, P, Lseg);
     }
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_tridiag_adj(const double* in, int planes_in, double* out, const double* fac, const double* colc, int n,
+                        const Fold& f, int R, hipStream_t st) {
+    check_batch(R);
+    dim3 grid((f.W + 255) / 256, R);
+    hipLaunchKernelGGL(tridiag_adj_kernel, grid, dim3(256), 0, st, in, planes_in, out, fac, colc, n, f.W, R);
     MDP_HIP(hipGetLastError());
 }
 
@@ -1136,10 +1202,10 @@ __global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njo
 }  // namespace
 
 void launch_extension(const int* side, const double* rho, const double* t, const double* slen, int ng, double k,
-                      int m_star, double* E, hipStream_t st) {
+                      int m_star, double* E, hipStream_t st, int deriv) {
     if (ng <= 0) return;
     hipLaunchKernelGGL(extension_kernel, dim3((ng + 255) / 256), dim3(256), 0, st, side, rho, t, slen, ng, k, m_star,
-                       E);
+                       E, deriv);
     MDP_HIP(hipGetLastError());
 }
 

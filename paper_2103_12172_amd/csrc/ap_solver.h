@@ -41,6 +41,7 @@ struct PackedWork {
 struct CallWork {
     DevBuf F, x;          // mdp_solve_interface
     DevBuf srcw;          // mdp_solve_interface: densities Ex^(I) f of the source right-hand sides
+    DevBuf grad;          // mdp_dd_gradient: grids, vectors and tables of the reverse pass
 };
 
 // Grow-only device workspaces of a context.
@@ -63,5 +64,10 @@ int chunk_size(const APPlan& P, int precision, size_t cap_bytes, int R);
 // (see solve_batch_t; the refined precision always solves the full grid).
 void solve_batch(const APPlan& P, Workspace& ws, int precision, const SrcDesc& src, bool src_cplx, int R, Band bd,
                  const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st);
+
+// The conjugate-transposed solve A^{-H} (all n+1 rows, FP64) of R right-hand sides from
+// `src` (GRID or GRID_ALL); consume as for solve_batch.
+void solve_batch_adjoint(const APPlan& P, Workspace& ws, const SrcDesc& src, bool src_cplx, int R,
+                         const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st);
 
 }  // namespace mdp

@@ -625,9 +625,37 @@ void side_segment(const mdp_subdomain& sd, int s, double* seg) {
 
 }  // namespace
 
-int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, const mdp_projector* const* P,
-                        const mdp_side* sides, int m_star, const mdp_source* sources, void* stream, mdp_c128* c_out,
-                        double* rel_residual_out, double* cond_estimate_out) {
+namespace {
+
+// Receivers and outputs of a gradient call (host arrays).
+struct GradArgs {
+    int n_rcv;
+    const int* rcv_sub;
+    const int* rcv_node;
+    const mdp_c128* ubar;
+    double* grad_k2;
+    mdp_c128* grad_d;
+};
+
+// Reverse pass of Phi = Re sum_r conj(ubar_r) u_r (u the reconstruction of eq. potential_solution_homo,
+// f = 0) through the three steps of Sec. 3.5, after the interface solve left x, Fbar and the Gram factor:
+//   u_i = w_i - A_i^{-1}(L w_i |M+), w_i = E_i c_i on gamma:
+//       cbar_i = E_i^T [ubar_i - L^T (A_i^{-H} ubar_i)|M+] on gamma;
+//   c = K x + known(d):  xbar = K^* cbar;
+//   x = (Qbar^* Qbar)^{-1} Qbar^* Fbar:  z = (Qbar^* Qbar)^{-1} xbar, Fbb = Qbar z, r = Fbar - Qbar x;
+//   boundary data: dPhi/dd = (cbar_known - Q_known^* Fbb) / (alpha or beta);
+//   k_i^2: Re[ <ubar, du/dk^2>_c fixed - <Fbb_i, dQ_i c_i> + <r_i, dQ_i cz_i> ] with cz = K z, where
+//       for a density c: v = A^{-1}(L w|M+), h = -dA v + (dL w + L dw)|M+ (dw = dE c), y = A^{-1} h,
+//       dQ c = -y|gamma and du/dk^2 = dw - y.
+void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const mdp_projector* const* P,
+                        const mdp_side* sides, int M, const PackedHost& ph, const PackedTables& tabs, const char* img,
+                        const double2* F, const double2* x, const double2* c_full, const int* esrc, const double2* ecoef, const std::vector<int>& row_off, const GradArgs& ga,
+                        hipStream_t st);
+
+// The interface solve of step 2; with ga set, the reverse pass of the receiver functional follows.
+int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, const mdp_projector* const* P,
+                         const mdp_side* sides, int m_star, const mdp_source* sources, void* stream, mdp_c128* c_out,
+                         double* rel_residual_out, double* cond_estimate_out, const GradArgs* ga) {
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
     return guarded(ctx, [&]() -> int {
         if (n_sub < 1 || !subs || !P || !sides || !c_out) throw Error(MDP_ERR_ARG, "null or empty arguments");
@@ -992,6 +1020,7 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             }
         }
         LSResult r;
+        bool fallback = false;
         {
             // the whole least-squares solve as one profiled span (it synchronises internally)
             Profiler& pr = ctx->ws.prof;
@@ -1001,7 +1030,6 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
             // algorithmic work of the least squares: the semi-normal path's own count, or a Householder QR
             // of the m x ncol matrix for the dense fallback
             double ls_flops = 8.0 * ((double)m * ncol * ncol - (double)ncol * ncol * ncol / 3.0);
-            bool fallback = false;
             r = ls_solve_packed(ctx->ws, ph, img, tabs, F.as<double2>(), x.as<double2>(), cond_estimate_out != nullptr,
                                 st, &fallback);
             if (fallback && multifrontal)
@@ -1028,11 +1056,282 @@ int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, cons
                              reinterpret_cast<const double2*>(img + o_ecoef),
                              reinterpret_cast<const double2*>(img + o_eknown), x.as<double2>(),
                              reinterpret_cast<double2*>(c_out), st);
+        if (ga) {
+            if (fallback) throw Error(MDP_ERR_SINGULAR, "gradient: the interface system needed the dense fallback");
+            interface_gradient(ctx, n_sub, sd.data(), P, sides, M, ph, tabs, img, F.as<double2>(), x.as<double2>(),
+                               reinterpret_cast<const double2*>(c_out), reinterpret_cast<const int*>(img + o_esrc),
+                               reinterpret_cast<const double2*>(img + o_ecoef), row_off, *ga, st);
+        }
         end_call(ctx, st);
         if (rel_residual_out) *rel_residual_out = r.rel_residual;
         if (cond_estimate_out) *cond_estimate_out = r.cond;
         return MDP_OK;
     });
+}
+
+void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const mdp_projector* const* P,
+                        const mdp_side* sides, int M, const PackedHost& ph, const PackedTables& tabs, const char* img,
+                        const double2* F, const double2* x, const double2* c_full, const int* esrc,
+                        const double2* ecoef, const std::vector<int>& row_off, const GradArgs& ga, hipStream_t st) {
+    const int nc = ph.nc, ncol = 8 * M, nce = n_sub * ncol;
+    const long m_rows = row_off[n_sub];
+    for (int i = 0; i < n_sub; ++i)
+        if (P[i]->precision != MDP_C128) throw Error(MDP_ERR_ARG, "gradient: projectors must be complex128");
+    // grid offsets (complex elements) of every subdomain in the ubar and lambda grids
+    std::vector<long> goff(n_sub + 1, 0);
+    int max_n = 0, max_ng = 0;
+    for (int i = 0; i < n_sub; ++i) {
+        goff[i + 1] = goff[i] + (long)(P[i]->g.n + 1) * (P[i]->g.n + 1);
+        max_n = std::max(max_n, P[i]->g.n);
+        max_ng = std::max(max_ng, P[i]->g.n_gamma);
+    }
+    const long max_grid = (long)(max_n + 1) * (max_n + 1);
+    // receivers: values summed per node, grouped by subdomain
+    std::map<std::pair<int, int>, double2> acc;
+    for (int t = 0; t < ga.n_rcv; ++t) {
+        const int i = ga.rcv_sub[t], node = ga.rcv_node[t], n = P[i]->g.n;
+        if (node < 0 || node >= (n + 1) * (n + 1)) throw Error(MDP_ERR_ARG, "receiver node out of range");
+        if (!std::isfinite(ga.ubar[t].re) || !std::isfinite(ga.ubar[t].im))
+            throw Error(MDP_ERR_NONFINITE, "non-finite receiver weight");
+        double2& v = acc[{i, node}];
+        v.x += ga.ubar[t].re;
+        v.y += ga.ubar[t].im;
+    }
+    std::vector<long> r_off_all, r_node;   // ubar grid offsets; node within the subdomain's grid
+    std::vector<double2> r_val;
+    std::vector<int> r_first(n_sub + 1, 0);
+    for (const auto& kv : acc) {
+        r_off_all.push_back(goff[kv.first.first] + kv.first.second);
+        r_node.push_back(kv.first.second);
+        r_val.push_back(kv.second);
+        ++r_first[kv.first.first + 1];
+    }
+    for (int i = 0; i < n_sub; ++i) r_first[i + 1] += r_first[i];
+    // known coefficients: (subdomain, side, j) of every boundary side
+    std::vector<const double2*> kq;
+    std::vector<int> krows, kcolv, keidx;
+    std::vector<long> kroff;
+    std::vector<double> kdiv;
+    std::vector<size_t> kout;   // index into grad_d
+    for (int i = 0; i < n_sub; ++i)
+        for (int s = 0; s < 4; ++s) {
+            const mdp_side& sdd = sides[4 * i + s];
+            if (sdd.kind != 0) continue;
+            const double a = sdd.alpha, b = sdd.beta;
+            const int kind = (b == 0.0) ? 0 : 1;   // Dirichlet: c0 = d/alpha; otherwise c1 holds d/beta
+            for (int j = 0; j < M; ++j) {
+                kq.push_back(P[i]->Q.as<const double2>());
+                krows.push_back(P[i]->g.n_gamma);
+                kcolv.push_back(kind * 4 * M + s * M + j);
+                keidx.push_back(i * ncol + kind * 4 * M + s * M + j);
+                kroff.push_back(row_off[i]);
+                kdiv.push_back(b == 0.0 ? a : b);
+                kout.push_back(((size_t)i * 4 + s) * M + j);
+            }
+        }
+    const int nk = (int)kq.size();
+    std::vector<long> entry_off(2 * n_sub);   // JVP scratch offsets: entries 0 (c_full), 1 (cz)
+    HostBlob blob;
+    const size_t o_roff = blob.put(r_off_all), o_rnode = blob.put(r_node), o_rval = blob.put(r_val),
+                 o_goff = blob.put(goff), o_kq = blob.put(kq), o_krows = blob.put(krows), o_kcol = blob.put(kcolv),
+                 o_keidx = blob.put(keidx), o_kroff = blob.put(kroff), o_kdiv = blob.put(kdiv);
+    std::vector<long> two{0, max_grid};
+    const size_t o_two = blob.put(two);
+    std::vector<int> one_idx(n_sub);
+    for (int i = 0; i < n_sub; ++i) one_idx[i] = i;
+    const size_t o_idx = blob.put(one_idx);
+    // device buffers: grids ubar, lambda (all subdomains); JVP scratch (w, dw, v, h, y: 2 entries each of the
+    // largest grid); dE; wbar; vectors
+    CallWork& cw = ctx->ws.cw;
+    const long gtot = goff[n_sub];
+    size_t off = 0;
+    auto take = [&](size_t elems) { const size_t o = off; off += (elems + 15) / 16 * 16; return o; };
+    const size_t b_ubar = take(gtot), b_lam = take(gtot), b_w = take(2 * max_grid), b_dw = take(2 * max_grid),
+                 b_v = take(2 * max_grid), b_h = take(2 * max_grid), b_y = take(2 * max_grid),
+                 b_dE = take(((size_t)max_ng * ncol + 1) / 2), b_wbar = take(max_ng), b_cbar = take(nce),
+                 b_cz = take(nce), b_zero = take(nce), b_xbar = take(nc), b_xs = take(nc), b_zs = take(nc),
+                 b_z = take(nc), b_Fbb = take(m_rows), b_r = take(m_rows), b_k = take(n_sub), b_dg = take(nk),
+                 b_tab = take((blob.size() + 15) / 16);
+    ensure(cw.grad, off * sizeof(double2));
+    double2* G0 = cw.grad.as<double2>();
+    auto at = [&](size_t o) { return G0 + o; };
+    char* tab = reinterpret_cast<char*>(at(b_tab));
+    ctx->ws.stage.copy(tab, blob, st);
+    auto T = [&](size_t o) { return tab + o; };
+    const long* d_goff = reinterpret_cast<const long*>(T(o_goff));
+    const long* d_two = reinterpret_cast<const long*>(T(o_two));
+    const int* d_idx = reinterpret_cast<const int*>(T(o_idx));
+    double* ubar = reinterpret_cast<double*>(at(b_ubar));
+    double* lam = reinterpret_cast<double*>(at(b_lam));
+    Profiler& pr = ctx->ws.prof;
+    // (1) ubar grids
+    MDP_HIP(hipMemsetAsync(ubar, 0, (size_t)gtot * sizeof(double2), st));
+    launch_scatter_values(reinterpret_cast<const long*>(T(o_roff)), reinterpret_cast<const double*>(T(o_rval)),
+                          (int)r_val.size(), ubar, st);
+    // (2) per subdomain: lambda = A^{-H} ubar, wbar on gamma, cbar = E^T wbar
+    double2* cbar = at(b_cbar);
+    for (int i = 0; i < n_sub; ++i) {
+        const mdp_projector* Pi = P[i];
+        const Geometry& G = Pi->g;
+        const int n = G.n, ng = G.n_gamma;
+        APPlan& plan = get_plan(ctx, n, G.h, Pi->k);
+        SrcDesc src{};
+        src.kind = Src::GRID;
+        src.grid = ubar;
+        src.goff = d_goff + i;
+        const Fold f = plan.f;
+        prepare_ws(ctx, plan, MDP_C128, 1);
+        solve_batch_adjoint(plan, ctx->ws, src, true, 1,
+                            [&](const void* u, const float*, Band bd) {
+                                launch_unfold_grid<double>((const double*)u, nullptr, n, f, bd, bd, 1, nullptr, 0, lam,
+                                                           0, d_goff + i, st);
+                            },
+                            st);
+        pr.run("adjoint", st, 0.0, 0.0, [&] {
+            launch_gamma_adjoint(ubar, lam, d_goff + i, 1, n, plan.sc, G.m_lo, G.m_hi, G.q_lo, G.q_hi, Pi->gm, Pi->gq,
+                                 ng, reinterpret_cast<double*>(at(b_wbar)), 0, st);
+            launch_et_apply(Pi->E.as<double>(), ng, ncol, reinterpret_cast<const double*>(at(b_wbar)), 0, 1, d_idx + i,
+                            reinterpret_cast<double*>(cbar), st);
+        });
+    }
+    // (3) xbar = K^* cbar; z = D^{-1} G^{-1} D^{-1} xbar (column equilibration D of the packed matrix)
+    const double* norms = ctx->ws.ls.norms.as<double>() + nc;
+    double2* xbar = at(b_xbar);
+    double2* xs = at(b_xs);
+    double2* zs = at(b_zs);
+    double2* z = at(b_z);
+    MDP_HIP(hipMemsetAsync(xbar, 0, (size_t)nc * sizeof(double2), st));
+    launch_expand_adj(nce, esrc, ecoef, cbar, xbar, st);
+    MDP_HIP(hipMemcpyAsync(xs, xbar, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_scale_cols(xs, 1, nc, 1, norms, 1, st);
+    ls_packed_factor_solve(ctx->ws, ph, img, tabs, xs, zs, st);
+    MDP_HIP(hipMemcpyAsync(z, zs, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_scale_cols(z, 1, nc, 1, norms, 1, st);
+    // (4) Fbb = Qbar z = Ap zs; r = Fbar - Qbar x = Fbar - Ap (D x)
+    const char* pimg = img;
+    auto pat = [&](size_t o) { return pimg + o; };
+    PackedDevice d{reinterpret_cast<const double2* const*>(pat(tabs.Q)), reinterpret_cast<const int*>(pat(tabs.m)),
+                   reinterpret_cast<const long*>(pat(tabs.off)), reinterpret_cast<const int*>(pat(tabs.s)),
+                   reinterpret_cast<const int*>(pat(tabs.sub)), reinterpret_cast<const int*>(pat(tabs.p)),
+                   reinterpret_cast<const int*>(pat(tabs.gcol)), reinterpret_cast<const int4*>(pat(tabs.cols)),
+                   reinterpret_cast<const double2*>(pat(tabs.coef)), reinterpret_cast<const long*>(pat(tabs.roff)),
+                   reinterpret_cast<const int*>(pat(tabs.start))};
+    const double2* Ap = ctx->ws.pk.Ap.as<double2>();
+    double2* Fbb = at(b_Fbb);
+    double2* r = at(b_r);
+    const double2 one{1.0, 0.0}, mone{-1.0, 0.0};
+    MDP_HIP(hipMemsetAsync(Fbb, 0, (size_t)m_rows * sizeof(double2), st));
+    launch_packed_ax(d, n_sub, ph.max_m, ph.max_s, Ap, zs, one, Fbb, st);
+    MDP_HIP(hipMemcpyAsync(xs, x, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_scale_cols(xs, 1, nc, 1, norms, 0, st);
+    MDP_HIP(hipMemcpyAsync(r, F, (size_t)m_rows * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_packed_ax(d, n_sub, ph.max_m, ph.max_s, Ap, xs, mone, r, st);
+    // (5) boundary-data gradient
+    double2* dg = at(b_dg);
+    launch_data_grad(nk, reinterpret_cast<const double2* const*>(T(o_kq)), reinterpret_cast<const int*>(T(o_krows)),
+                     reinterpret_cast<const int*>(T(o_kcol)), reinterpret_cast<const long*>(T(o_kroff)),
+                     reinterpret_cast<const int*>(T(o_keidx)), reinterpret_cast<const double*>(T(o_kdiv)), cbar, Fbb,
+                     dg, st);
+    // (6) cz = K z (no known part)
+    double2* cz = at(b_cz);
+    double2* zero = at(b_zero);
+    MDP_HIP(hipMemsetAsync(zero, 0, (size_t)nce * sizeof(double2), st));
+    launch_expand_coeffs(nce, esrc, ecoef, zero, z, cz, st);
+    // (7) k^2 of every subdomain: two JVP densities (c_full, cz)
+    double* W = reinterpret_cast<double*>(at(b_w));
+    double* DW = reinterpret_cast<double*>(at(b_dw));
+    double* V = reinterpret_cast<double*>(at(b_v));
+    double* H = reinterpret_cast<double*>(at(b_h));
+    double* Y = reinterpret_cast<double*>(at(b_y));
+    double* dE = reinterpret_cast<double*>(at(b_dE));
+    double2* kres = at(b_k);
+    const StencilCoef dsc{2.0 / 3.0, 1.0 / 12.0, 0.0};
+    for (int i = 0; i < n_sub; ++i) {
+        const mdp_projector* Pi = P[i];
+        const Geometry& G = Pi->g;
+        const int n = G.n, ng = G.n_gamma;
+        APPlan& plan = get_plan(ctx, n, G.h, Pi->k);
+        const Fold f = plan.f;
+        MDP_HIP(hipMemsetAsync(dE, 0, (size_t)ng * ncol * sizeof(double), st));
+        launch_extension(Pi->gside, Pi->grho, Pi->gt, Pi->gslen, ng, Pi->k, M, dE, st, 1);
+        MDP_HIP(hipMemsetAsync(W, 0, (size_t)2 * max_grid * sizeof(double2), st));
+        MDP_HIP(hipMemsetAsync(DW, 0, (size_t)2 * max_grid * sizeof(double2), st));
+        for (int e = 0; e < 2; ++e) {
+            const double* cv = reinterpret_cast<const double*>(e == 0 ? c_full : cz);
+            launch_extend_density(Pi->E.as<double>(), ng, ncol, cv, d_idx + i, 1, Pi->gm, Pi->gq, Pi->gside, n, W, 0,
+                                  d_two + e, st);
+            launch_extend_density(dE, ng, ncol, cv, d_idx + i, 1, Pi->gm, Pi->gq, Pi->gside, n, DW, 0, d_two + e, st);
+        }
+        prepare_ws(ctx, plan, MDP_C128, 2);
+        SrcDesc sv{};
+        sv.kind = Src::STENCIL_GRID;
+        sv.grid = W;
+        sv.goff = d_two;
+        sv.m_lo = G.m_lo; sv.m_hi = G.m_hi; sv.q_lo = G.q_lo; sv.q_hi = G.q_hi;
+        const Band full{0, n + 1};
+        solve_batch(plan, ctx->ws, MDP_C128, sv, true, 2, full,
+                    [&](const void* u, const float*, Band bd) {
+                        launch_unfold_grid<double>((const double*)u, nullptr, n, f, bd, bd, 2, nullptr, 0, V, 0, d_two,
+                                                   st);
+                    },
+                    st);
+        launch_jvp_rhs(V, W, DW, d_two, 2, n, G.h, Pi->k, plan.sc, dsc, G.m_lo, G.m_hi, G.q_lo, G.q_hi, H, st);
+        SrcDesc sh{};
+        sh.kind = Src::GRID_ALL;
+        sh.grid = H;
+        sh.goff = d_two;
+        solve_batch(plan, ctx->ws, MDP_C128, sh, true, 2, full,
+                    [&](const void* u, const float*, Band bd) {
+                        launch_unfold_grid<double>((const double*)u, nullptr, n, f, bd, bd, 2, nullptr, 0, Y, 0, d_two,
+                                                   st);
+                    },
+                    st);
+        const int r0 = r_first[i], rc = r_first[i + 1] - r_first[i];
+        launch_kappa_dot(Y, Y + 2 * max_grid, DW, Pi->gm, Pi->gq, ng, n, Fbb, r, row_off[i],
+                         reinterpret_cast<const long*>(T(o_rnode)) + r0, reinterpret_cast<const double*>(T(o_rval)) + 2 * r0,
+                         rc, kres + i, st);
+    }
+    // (8) results to the host
+    std::vector<double2> hk(n_sub), hd(nk);
+    MDP_HIP(hipMemcpyAsync(hk.data(), kres, (size_t)n_sub * sizeof(double2), hipMemcpyDeviceToHost, st));
+    if (nk) MDP_HIP(hipMemcpyAsync(hd.data(), dg, (size_t)nk * sizeof(double2), hipMemcpyDeviceToHost, st));
+    MDP_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n_sub; ++i) ga.grad_k2[i] = hk[i].x;
+    std::memset(ga.grad_d, 0, sizeof(mdp_c128) * (size_t)n_sub * 4 * M);
+    for (int t = 0; t < nk; ++t) ga.grad_d[kout[t]] = mdp_c128{hd[t].x, hd[t].y};
+}
+
+}  // namespace
+
+int mdp_solve_interface(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, const mdp_projector* const* P,
+                        const mdp_side* sides, int m_star, const mdp_source* sources, void* stream, mdp_c128* c_out,
+                        double* rel_residual_out, double* cond_estimate_out) {
+    return solve_interface_impl(ctx, n_sub, subs, P, sides, m_star, sources, stream, c_out, rel_residual_out,
+                                cond_estimate_out, nullptr);
+}
+
+int mdp_dd_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, const mdp_projector* const* P,
+                    const mdp_side* sides, int m_star, int n_rcv, const int* rcv_sub, const int* rcv_node,
+                    const mdp_c128* ubar, void* stream, double* grad_k2, mdp_c128* grad_d) {
+    if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
+    if (n_sub < 1 || !grad_k2 || !grad_d || n_rcv < 0 || (n_rcv > 0 && (!rcv_sub || !rcv_node || !ubar)))
+        return fail(ctx, MDP_ERR_ARG, "null or empty gradient arguments");
+    for (int t = 0; t < n_rcv; ++t)
+        if (rcv_sub[t] < 0 || rcv_sub[t] >= n_sub) return fail(ctx, MDP_ERR_ARG, "receiver subdomain out of range");
+    GradArgs ga{n_rcv, rcv_sub, rcv_node, ubar, grad_k2, grad_d};
+    int rc = MDP_OK;
+    {
+        DevBuf c;
+        try {
+            c.alloc((size_t)n_sub * 8 * std::max(m_star, 1) * sizeof(mdp_c128));
+        } catch (const Error& e) {
+            return fail(ctx, e.code, e.what());
+        }
+        rc = solve_interface_impl(ctx, n_sub, subs, P, sides, m_star, nullptr, stream, c.as<mdp_c128>(), nullptr,
+                                  nullptr, &ga);
+        (void)hipStreamSynchronize((hipStream_t)stream);
+    }
+    return rc;
 }
 
 // ---------------------------------------------------------------------------- step 3

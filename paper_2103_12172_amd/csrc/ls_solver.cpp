@@ -736,4 +736,30 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     return res;
 }
 
+// G^{-1} v with the factor of the last ls_solve_packed on these workspaces (the Gram
+// matrix of the column-equilibrated packed matrix; out may not alias v).
+void ls_packed_factor_solve(Workspace& ws, const PackedHost& h, const char* image, const PackedTables& tb,
+                            const double2* v, double2* out, hipStream_t st) {
+    const int nc = h.nc;
+    if (h.multifrontal) {
+        const MFHost& mf = h.mf;
+        const MFNodeDev* nodes = reinterpret_cast<const MFNodeDev*>(image + tb.mf_nodes);
+        const int* lists = reinterpret_cast<const int*>(image + tb.mf_lists);
+        double2* arena = ws.pk.mf.as<double2>();
+        const int H = (int)mf.by_height.size();
+        for (int hh = 0; hh < H; ++hh)
+            launch_mf_forward(nodes, lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.lds_fwd, image,
+                              arena, v, st);
+        for (int hh = H - 1; hh >= 0; --hh)
+            launch_mf_backward(nodes, lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.lds_bwd, image,
+                               arena, out, st);
+        return;
+    }
+    LSWork& lw = ws.ls;
+    double2* t = lw.vec.as<double2>() + nc;   // the normal solve's own temporary
+    const double2* Linv = lw.Linv[0].as<double2>();
+    launch_zgemm('N', 'N', nc, 1, nc, ONE, Linv, nc, v, nc, ZERO, t, nc, ws.zg, st);
+    launch_zgemm('C', 'N', nc, 1, nc, ONE, Linv, nc, t, nc, ZERO, out, nc, ws.zg, st);
+}
+
 }  // namespace mdp

@@ -91,6 +91,11 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
 LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, const PackedTables& t,
                          const double2* F, double2* x_out, bool want_cond, hipStream_t st, bool* fallback);
 
+// G^{-1} v with the Gram factor left by the last ls_solve_packed on ws (same h, image and
+// tables; G the Gram matrix of the column-equilibrated packed matrix); out must not alias v.
+void ls_packed_factor_solve(Workspace& ws, const PackedHost& h, const char* image, const PackedTables& tb,
+                            const double2* v, double2* out, hipStream_t st);
+
 // min ||A x - F||_2 for A (m x nc, column-major, ld m, device; overwritten) and
 // F (m, device); x_out (nc, device).
 LSResult ls_solve(Workspace& ws, double2* A, const double2* F, int m, int nc, double2* x_out, bool want_cond,

@@ -222,8 +222,9 @@ Geometry make_geometry(double x0, double y0, double lx, double ly, int n);
 // Extension matrix E = Ex^(H) Psi (|gamma| x 8M*, column-major, real FP64) on
 // the device from the gamma nodes' side, rho, t and side length; E must be
 // zeroed first (only each row's own-side columns are written).
+// deriv = 1: the derivative dE/d(k^2) instead of E
 void launch_extension(const int* side, const double* rho, const double* t, const double* slen, int ng, double k,
-                      int m_star, double* E, hipStream_t st);
+                      int m_star, double* E, hipStream_t st, int deriv = 0);
 // gidx[gm[i] (n+1) + gq[i]] = i over a map filled with -1 beforehand
 void launch_gamma_index(const int* gm, const int* gq, int ng, int n, int* gidx, hipStream_t st);
 
@@ -247,7 +248,9 @@ struct EndRowCoef { double wD, wD2, wA, wA2, k; };
 struct APDevPlan;  // forward
 
 // RHS sources of an AP batch (all evaluated in FP64)
-enum class Src { GRID = 0, STENCIL_GRID = 1, STENCIL_E = 2 };
+// GRID: a given grid on the interior nodes (zero on the x-end rows); GRID_ALL:
+// a given grid on every unknown row, the x-end rows included
+enum class Src { GRID = 0, STENCIL_GRID = 1, STENCIL_E = 2, GRID_ALL = 3 };
 
 struct SrcDesc {
     Src kind;
@@ -279,6 +282,38 @@ void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* c
                     Band bd, hipStream_t st);
 void launch_residual(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, EndRowCoef ec, int R, bool cplx_src,
                      const float* u32, float* r_out, hipStream_t st);
+// conjugate-transposed tridiagonal solves T^H x = g per mode with the LU factors of T (all n+1 rows; FP64)
+void launch_tridiag_adj(const double* in, int planes_in, double* out, const double* fac, const double* colc, int n,
+                        const Fold& f, int R, hipStream_t st);
+
+// ----------------------------------------------------------------- adjoint (receiver functional)
+// grids[off[t]] = val[t] (complex), t < count; the grids are cleared beforehand
+void launch_scatter_values(const long* off, const double* val, int count, double* grids, hipStream_t st);
+// wbar_b(i) = ubar_b(gamma_i) - sum over the 3x3 neighbours r of gamma_i in M+ of c(r) lambda_b(r)
+// (the transpose of L^(h) restricted to M+, applied to lambda and read on gamma); grids at goff[b]
+void launch_gamma_adjoint(const double* ubar, const double* lambda, const long* goff, int R, int n, StencilCoef sc,
+                          int m_lo, int m_hi, int q_lo, int q_hi, const int* gm, const int* gq, int ng, double* wbar,
+                          long wbar_stride, hipStream_t st);
+// cbar_b(col) = sum_i E(i, col) wbar_b(i)  (E real |gamma| x ncol, column-major); cbar at cidx[b] * ncol
+void launch_et_apply(const double* E, int ng, int ncol, const double* wbar, long wbar_stride, int R, const int* cidx,
+                     double* cbar, hipStream_t st);
+// xbar[src[e]] += conj(coef[e]) cbar[e] (at most two contributions per unknown; xbar cleared beforehand)
+void launch_expand_adj(int n, const int* src, const double2* coef, const double2* cbar, double2* xbar, hipStream_t st);
+// out[t] = (cbar[eidx[t]] - sum_r conj(Q_t(r, kcol[t])) Fb[roff_t + r]) / div[t] for the known coefficients t
+// (Q_t the projector of entry t's subdomain, |gamma| rows, ld = rows)
+void launch_data_grad(int count, const double2* const* Q, const int* rows, const int* kcol, const long* roff,
+                      const int* eidx, const double* div, const double2* cbar, const double2* Fb, double2* out,
+                      hipStream_t st);
+// h_b = -dA v_b + (dL w_b + L dw_b)|M+ on every unknown row (dA: the derivative of the AP operator with respect to
+// k^2; dL, L: stencil weights dsc, sc); grids at goff[b]
+void launch_jvp_rhs(const double* v, const double* w, const double* dw, const long* goff, int R, int n, double h,
+                    double k, StencilCoef sc, StencilCoef dsc, int m_lo, int m_hi, int q_lo, int q_hi, double* out,
+                    hipStream_t st);
+// out[i] = sum_g [conj(Fb(r0 + g)) yf(gamma_g) - conj(r(r0 + g)) yz(gamma_g)]
+//          + sum over the receivers of the subdomain conj(ubar) (dwf - yf) at their nodes
+void launch_kappa_dot(const double* yf, const double* yz, const double* dwf, const int* gm, const int* gq, int ng,
+                      int n, const double2* Fb, const double2* r, long r0, const long* rcv_node, const double* rcv_val,
+                      int rcv_count, double2* out, hipStream_t st);
 template <class T>
 void launch_gather_q(const T* u, const float* du, int n, const Fold& f, Band bd, const int* gm, const int* gq, int ng,
                      int R, double* Q, int ldq, int col0, hipStream_t st);

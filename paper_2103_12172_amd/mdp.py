@@ -27,7 +27,8 @@ EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector"
             "mdp_projector_info",
             "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
             "mdp_cheb_coeffs", "mdp_version", "mdp_cache_clear", "mdp_profile_enable", "mdp_profile_report",
-            "mdp_set_projector_path", "mdp_set_interface_path", "mdp_profile_select", "mdp_projector_gamma_feet", "mdp_ap_grid"]
+            "mdp_set_projector_path", "mdp_set_interface_path", "mdp_profile_select", "mdp_projector_gamma_feet", "mdp_ap_grid",
+            "mdp_dd_gradient"]
 MDP_PATH_AUTO, MDP_PATH_DENSE = 0, 1
 PROJECTOR_PATHS = {"auto": MDP_PATH_AUTO, "dense": MDP_PATH_DENSE}
 INTERFACE_PATHS = {"auto": 0, "dense": 1, "multifrontal": 2}
@@ -86,6 +87,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mdp_solve_interface.argtypes = [vp, ip, ctypes.POINTER(Subdomain), ctypes.POINTER(vp), ctypes.POINTER(Side),
                                         ip, ctypes.POINTER(Source), vp, vp, ctypes.POINTER(dp), ctypes.POINTER(dp)]
     lib.mdp_solve_interface.restype = ip
+    lib.mdp_dd_gradient.argtypes = [vp, ip, ctypes.POINTER(Subdomain), ctypes.POINTER(vp), ctypes.POINTER(Side), ip,
+                                    ip, ctypes.POINTER(ip), ctypes.POINTER(ip), vp, vp, ctypes.POINTER(dp), vp]
+    lib.mdp_dd_gradient.restype = ip
     lib.mdp_reconstruct.argtypes = [vp, ip, ctypes.POINTER(vp), vp, ctypes.POINTER(Source), vp, vp]
     lib.mdp_projector_gamma_feet.argtypes = [vp, ctypes.POINTER(Subdomain), ctypes.POINTER(dp), ctypes.POINTER(ip)]
     lib.mdp_projector_gamma_feet.restype = ip
@@ -265,6 +269,29 @@ def mdp_solve_interface(ctx: Context, subs: Sequence[Subdomain], projectors: Seq
                                           ctypes.byref(rel), ctypes.byref(cond) if want_cond else None))
     del keep
     return rel.value, (cond.value if want_cond else None)
+
+
+def mdp_dd_gradient(ctx: Context, subs: Sequence[Subdomain], projectors: Sequence[Projector], sides, d_arrays,
+                    m_star: int, rcv_sub, rcv_node, ubar, stream=None):
+    """Gradient of Phi = Re sum_t conj(ubar_t) u(receiver t): (dPhi/dk^2 per subdomain,
+    dPhi/dd as complex [n_sub, 4, M*] (zero on interface sides))."""
+    n = len(subs)
+    sub_arr = (Subdomain * n)(*subs)
+    parr = (ctypes.c_void_p * n)(*[p.handle.value for p in projectors])
+    side_arr, keep = make_sides(sides, d_arrays)
+    rs = np.ascontiguousarray(rcv_sub, dtype=np.int32)
+    rn = np.ascontiguousarray(rcv_node, dtype=np.int32)
+    ub = np.ascontiguousarray(ubar, dtype=np.complex128)
+    gk = np.zeros(n, dtype=np.float64)
+    gd = np.zeros((n, 4, m_star), dtype=np.complex128)
+    ip_ = ctypes.POINTER(ctypes.c_int)
+    ctx.check(ctx.lib.mdp_dd_gradient(ctx.handle, n, sub_arr, parr, side_arr, m_star, int(rs.size),
+                                      rs.ctypes.data_as(ip_), rn.ctypes.data_as(ip_), ctypes.c_void_p(ub.ctypes.data),
+                                      ctypes.c_void_p(_stream_ptr(stream)),
+                                      gk.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ctypes.c_void_p(gd.ctypes.data)))
+    del keep
+    return gk, gd
 
 
 def mdp_reconstruct(ctx: Context, projectors: Sequence[Projector], c, u_out, stream=None, sources=None):
