@@ -50,6 +50,9 @@ ALGO = {
     "residual": ("hbm", "hbm", "bytes"),
     "gather_q": ("hbm", "hbm", "bytes"),
     "unfold_grid": ("hbm", "hbm", "bytes"),
+    "tridiag_adj": ("hbm", "hbm", "bytes"),
+    "mf_assemble": ("hbm", "hbm", "bytes"),
+    "mf_gemm": ("mfma", "f64", "flops"),
 }
 # kernel class -> (part of its rocprofv3 kernel name, source file) for the PMC traffic summaries
 KERNELS = {
@@ -294,12 +297,82 @@ def cpu_baseline_sampled(w, res, n_sample=2, seed=5):
     return cb, qerr
 
 
+def run_adjoint(args):
+    """One step = a cold DD solve of the adjoint layout (4x4 squares, n = 512, k^2 in U[400, 3600],
+    64 receivers) and the gradient of J = sum |u - u_obs|^2 with respect to the 16 k^2 and every
+    boundary coefficient; u_obs = the solve at k^2 (1 + 0.05 U[-1, 1]) (seeded), computed before timing."""
+    import numpy as np
+    import torch
+    from paper_2103_12172_amd import autodiff, dd, mdp
+    from paper_2103_12172_amd import workloads as wl
+
+    w = wl.config_adjoint()
+    N = len(w.subdomains)
+    ctx = mdp.mdp_create(0)
+    pts, own = wl.receiver_points(w, 64, 5)
+    rs, rn, _ = autodiff.snap_receivers(w, pts, own)
+    prob = autodiff.Problem(ctx, w, rs, rn)
+    k2 = torch.tensor([sd.k ** 2 for sd in w.subdomains], dtype=torch.float64)
+    _, ds = dd.side_structs(w, w.m_star)
+    d = np.zeros((N, 4, w.m_star), dtype=np.complex128)
+    for i in range(N):
+        for s_ in range(4):
+            if ds[4 * i + s_] is not None:
+                d[i, s_] = ds[4 * i + s_]
+    d = torch.tensor(d)
+    rng = np.random.default_rng(5)
+    with torch.no_grad():
+        uobs = autodiff.ReceiverValues.apply(k2 * torch.tensor(1 + 0.05 * rng.uniform(-1, 1, N)), d, prob)
+
+    def step():
+        mdp.mdp_cache_clear(ctx)
+        kk = k2.clone().requires_grad_(True)
+        dd_ = d.clone().requires_grad_(True)
+        u = autodiff.ReceiverValues.apply(kk, dd_, prob)
+        J = ((u - uobs).abs() ** 2).sum()
+        J.backward()
+        return float(J), kk.grad, dd_.grad
+
+    for it in range(max(args.warmup, 1)):
+        if it == max(args.warmup, 1) - 1 and not args.no_profile:
+            mdp.mdp_profile_select(ctx, None)
+            mdp.mdp_profile_enable(ctx, True)
+        step()
+    report = None
+    if not args.no_profile:
+        report = mdp.mdp_profile_report(ctx)
+        mdp.mdp_profile_enable(ctx, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        J, gk, gd = step()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    # AP solves per step: the forward (8M* columns per subdomain + its reconstruction) and the
+    # gradient (per subdomain one adjoint and four forward solves)
+    pts = float(sum((8 * w.m_star + 1 + 5) * (sd.n + 1) * (sd.n - 1) for sd in w.subdomains))
+    line = {"metric": "AP grid-points/s (batched compact-4 Helmholtz) + DD solve ms, FP32 vs FP64",
+            "value": pts / step_s, "unit": "AP grid-points/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+            "config": {"workload": w.notes + "; 64 receivers; step = cold forward solve + gradient of the misfit "
+                       "with respect to 16 k^2 and all boundary coefficients", "ap_points_per_step": pts},
+            "J": J, "grad_k2_max": float(gk.abs().max()), "grad_d_max": float(gd.abs().max())}
+    if report:
+        name, roof = roofline(report, "adjoint")
+        line["roofline"] = roof
+        line["kernels"] = {k: {"count": v["count"], "total_ms": round(v["total_ms"], 4)} for k, v in report.items()}
+        line["kernels_note"] = "HIP-event records of the last warm-up step"
+    print(json.dumps(line))
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cross_point", choices=["two_rect", "cross_point", "transmission", "bump", "uneven"])
+    ap.add_argument("--workload", default="cross_point", choices=["two_rect", "cross_point", "transmission", "bump", "uneven", "adjoint"])
     ap.add_argument("--precision", default="c128", help="c128 | c64 | c64r: precision of the reported value")
     ap.add_argument("--compare", default="c64r,c64", help="precisions also timed, comma-separated ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -328,6 +401,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "adjoint":
+        run_adjoint(args)
         return
     w = wl.WORKLOADS[args.workload]()
     prec = args.precision
