@@ -450,12 +450,11 @@ __device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double
 //   the rest (32-column slabs j0 < kb): Z(q,j) = Z(q,q) W(q,j).
 // The slab operand is staged in the (no longer needed) S part of the LDS.
 // (one workgroup per CU by its LDS, so all 512 registers of a lane are allowed)
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-chol_panel_kernel(const double2* __restrict__ G, int nc, CholStepDev sp, double shift, double2* __restrict__ L,
-                  double2* __restrict__ Z, const double2* __restrict__ W, int* info, int np, int nz) {
-    __shared__ CholLds s;
+__device__ inline void chol_panel_body(const double2* __restrict__ G, int nc, const CholStepDev& sp, double shift,
+                                       double2* __restrict__ L, double2* __restrict__ Z,
+                                       const double2* __restrict__ W, int* info, int np, int nz, int bx, CholLds& s) {
     const int roles = 1 + np + nz;
-    const int q = blockIdx.x / roles, role = blockIdx.x - q * roles, tid = threadIdx.x;
+    const int q = bx / roles, role = bx - q * roles, tid = threadIdx.x;
     const int kb = sp.kb, r0 = sp.kb + sp.wtot;
     const int kq = kb + sp.off[q], nbq = sp.off[q + 1] - sp.off[q];
     const long dk = kq + (long)kq * nc;
@@ -547,19 +546,44 @@ chol_panel_kernel(const double2* __restrict__ G, int nc, CholStepDev sp, double 
     }
 }
 
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+chol_panel_kernel(const double2* __restrict__ G, int nc, CholStepDev sp, double shift, double2* __restrict__ L,
+                  double2* __restrict__ Z, const double2* __restrict__ W, int* info, int np, int nz) {
+    __shared__ CholLds s;
+    chol_panel_body(G, nc, sp, shift, L, Z, W, info, np, nz, blockIdx.x, s);
+}
+
+// One Cholesky step of several matrices at once (the fronts of one elimination-tree
+// height): entry blockIdx.y factors its sub-block kb..kb+w-1; workgroups past the
+// entry's roles exit.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+chol_panel_batched_kernel(const CholBatchEntry* __restrict__ ent, int* info) {
+    __shared__ CholLds s;
+    const CholBatchEntry e = ent[blockIdx.y];
+    if ((int)blockIdx.x >= 1 + e.np + e.nz) return;
+    CholStepDev sp;
+    sp.kb = e.kb;
+    sp.nq = 1;
+    sp.wtot = e.w;
+    sp.off[0] = 0;
+    sp.off[1] = e.w;
+    chol_panel_body(e.G, e.nc, sp, 0.0, e.L, e.Z, e.W, info, e.np, e.nz, blockIdx.x, s);
+}
+
 // Update after the block step kb..r0-1 (r0 = kb + wtot): 32 x 32 tiles of
 //   the trailing Schur complement  G(i,j) -= sum_k L(i,k) conj(L(j,k)),  r0 <= j <= i (tile-wise lower),
 //   the inverse accumulation       W(i,j) -= sum_k L(i,k) Z(k,j),        i >= r0, j < r0,
 // k over the step's columns in chunks of 64 (for j in the step, Z(k,j) is the
 // step's own block-diagonal inverse and W starts from zero).  Both operands
 // staged in LDS; 2 x 2 entries per thread.
-__global__ void __launch_bounds__(256)
-chol_update_kernel(double2* __restrict__ G, int nc, int kb, int wtot, const double2* __restrict__ L,
-                   const double2* __restrict__ Z, double2* __restrict__ W, int ntr) {
+__device__ inline void chol_update_body(double2* __restrict__ G, int nc, int kb, int wtot,
+                                        const double2* __restrict__ L, const double2* __restrict__ Z,
+                                        double2* __restrict__ W, int ntr, int bx) {
     __shared__ double2 A[64][33];   // A[k][r] = L(i0 + r, k0 + k)
     __shared__ double2 B[64][33];   // B[k][c] = conj(L(j0 + c, k0 + k)) or Z(k0 + k, j0 + c)
     const int r0 = kb + wtot, tid = threadIdx.x;
-    int t = blockIdx.x, i0, j0;
+    int t = bx, i0, j0;
     bool trail;
     const int ntri = ntr * (ntr + 1) / 2;
     if (t < ntri) {
@@ -627,6 +651,22 @@ chol_update_kernel(double2* __restrict__ G, int nc, int kb, int wtot, const doub
             C[i + (long)j * nc] = c;
         }
     }
+}
+
+
+__global__ void __launch_bounds__(256)
+chol_update_kernel(double2* __restrict__ G, int nc, int kb, int wtot, const double2* __restrict__ L,
+                   const double2* __restrict__ Z, double2* __restrict__ W, int ntr) {
+    chol_update_body(G, nc, kb, wtot, L, Z, W, ntr, blockIdx.x);
+}
+
+// The update of one step of several matrices at once (entry blockIdx.y; workgroups past
+// the entry's tiles exit).
+__global__ void __launch_bounds__(256)
+chol_update_batched_kernel(const CholBatchEntry* __restrict__ ent) {
+    const CholBatchEntry e = ent[blockIdx.y];
+    if ((int)blockIdx.x >= e.tiles) return;
+    chol_update_body(e.G, e.nc, e.kb, e.w, e.L, e.Z, e.W, e.np, blockIdx.x);
 }
 
 // max and min Cholesky pivot ratio estimate: diag of L (ld) -> out[0] = max |L_ii|^2, out[1] = min |L_ii|^2
@@ -1119,6 +1159,16 @@ void launch_chol_panel(const double2* G, int nc, const CholStepDev& sp, double s
                        info, np, nz);
     MDP_HIP(hipGetLastError());
 }
+void launch_chol_panel_batched(const CholBatchEntry* ent, int count, int max_roles, int* info, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(chol_panel_batched_kernel, dim3(max_roles, count), dim3(256), 0, st, ent, info);
+    MDP_HIP(hipGetLastError());
+}
+void launch_chol_update_batched(const CholBatchEntry* ent, int count, int max_tiles, hipStream_t st) {
+    if (count <= 0 || max_tiles <= 0) return;
+    hipLaunchKernelGGL(chol_update_batched_kernel, dim3(max_tiles, count), dim3(256), 0, st, ent);
+    MDP_HIP(hipGetLastError());
+}
 void launch_chol_update(double2* G, int nc, int kb, int wtot, const double2* L, const double2* Z, double2* W,
                         hipStream_t st) {
     const int rest = nc - kb - wtot;
@@ -1265,11 +1315,10 @@ __global__ void __launch_bounds__(256)
 mf_assemble_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
                    const double2* __restrict__ P, double2* __restrict__ arena) {
     const MFNodeDev nd = nodes[list[blockIdx.y]];
-    const int f = nd.f, e = nd.e;
+    const int f = nd.f;
     const long t = blockIdx.x * 256L + threadIdx.x;
     if (t >= (long)f * f) return;
     const int a = (int)(t % f), c = (int)(t / f);   // row a, column c
-    if (a < e && c >= e) return;                    // F12 = F21^* is not kept
     double2 v = make_double2(0.0, 0.0);
     if (nd.leaf) {
         const int* sp = reinterpret_cast<const int*>(img + nd.spos);
@@ -1289,14 +1338,16 @@ mf_assemble_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ 
             const int* inv = reinterpret_cast<const int*>(img + (kk ? nd.inv1 : nd.inv0));
             const int ia = inv[a], ic = inv[c];
             if (ia < 0 || ic < 0) continue;
+            // the child's contribution block is the lower triangle of its factored front's G(e:, e:)
             const MFNodeDev& kd = nodes[kk ? nd.kid1 : nd.kid0];
-            const double2 w = arena[kd.Y + (long)(kd.e + ic) * kd.b + ia];
+            const bool lo = ia >= ic;
+            const int r = kd.e + (lo ? ia : ic), cc = kd.e + (lo ? ic : ia);
+            const double2 w = arena[kd.G + r + (long)cc * kd.f];
             v.x += w.x;
-            v.y += w.y;
+            v.y += lo ? w.y : -w.y;
         }
     }
-    if (a < e) arena[nd.X + a + (long)c * e] = v;
-    else arena[nd.Y + (a - e) + (long)c * nd.b] = v;
+    arena[nd.G + a + (long)c * f] = v;
 }
 
 __device__ inline double2 wave_sum2(double2 v) {
@@ -1308,92 +1359,147 @@ __device__ inline double2 wave_sum2(double2 v) {
     return v;
 }
 
-// One workgroup per node: w = (y at the eliminated columns, 0) + the children's
-// contributions at their front positions (children in turn), z = Linv w_e,
-// cw = w_b - L21 z.
-__global__ void __launch_bounds__(256)
-mf_forward_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
-                  double2* __restrict__ arena, const double2* __restrict__ y) {
-    extern __shared__ double2 mf_sh[];
-    const MFNodeDev nd = nodes[list[blockIdx.x]];
-    const int e = nd.e, b = nd.b, f = nd.f, tid = threadIdx.x;
-    double2* w = mf_sh;
-    double2* zs = mf_sh + f;
-    const int* idx = reinterpret_cast<const int*>(img + nd.idx);
-    for (int a = tid; a < f; a += 256) w[a] = (a < e) ? y[idx[a]] : make_double2(0.0, 0.0);
-    __syncthreads();
+// Substitutions with many workgroups per node (a node's rows or columns cut into
+// chunks), two launches per direction and height.  w(a), the front's right-hand
+// side at position a, is y at the eliminated columns plus the children's
+// contributions, gathered per position through the inverse maps.
+__device__ inline double2 mf_front_rhs(const MFNodeDev& nd, const MFNodeDev* __restrict__ nodes,
+                                       const char* __restrict__ img, const double2* __restrict__ arena,
+                                       const double2* __restrict__ y, const int* __restrict__ idx, int a) {
+    double2 v = (a < nd.e) ? y[idx[a]] : make_double2(0.0, 0.0);
     if (!nd.leaf) {
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
-            const MFNodeDev& kd = nodes[kk ? nd.kid1 : nd.kid0];
-            const int* kp = reinterpret_cast<const int*>(img + (kk ? nd.kpos1 : nd.kpos0));
-            const double2* cwk = arena + kd.cw;
-            for (int r = tid; r < kd.b; r += 256) {
-                const double2 u = cwk[r];
-                w[kp[r]].x += u.x;
-                w[kp[r]].y += u.y;
-            }
-            __syncthreads();
+            const int r = reinterpret_cast<const int*>(img + (kk ? nd.inv1 : nd.inv0))[a];
+            if (r < 0) continue;
+            const double2 u = arena[nodes[kk ? nd.kid1 : nd.kid0].cw + r];
+            v.x += u.x;
+            v.y += u.y;
         }
     }
-    const double2* Li = arena + nd.Linv;
-    double2* z = arena + nd.z;
-    for (int i = tid; i < e; i += 256) {
-        double sr = 0.0, si = 0.0;
-        for (int j = 0; j <= i; ++j) {
-            const double2 l = Li[i + (long)j * e], u = w[j];
+    return v;
+}
+
+// z(i) = sum_{j <= i} Linv(i, j) w(j) for the 64 rows of chunk blockIdx.x (lane = row; the 4
+// wavefronts split j and add their partial sums in LDS)
+__global__ void __launch_bounds__(256)
+mf_fwd_z_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
+                double2* __restrict__ arena, const double2* __restrict__ y) {
+    extern __shared__ double2 mf_sh[];
+    __shared__ double2 part[4][64];
+    const MFNodeDev nd = nodes[list[blockIdx.y]];
+    const int e = nd.e, f = nd.f, i0 = blockIdx.x * 64;
+    if (i0 >= e) return;
+    const int iend = min(e, i0 + 64), tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int* idx = reinterpret_cast<const int*>(img + nd.idx);
+    for (int a = tid; a < iend; a += 256) mf_sh[a] = mf_front_rhs(nd, nodes, img, arena, y, idx, a);
+    __syncthreads();
+    const int i = i0 + lane;
+    const double2* Li = arena + nd.Z;
+    double sr = 0.0, si = 0.0;
+    if (i < iend) {
+        const int q = (i + 4) / 4;   // j = 0..i split in four ranges
+        const int j0 = wave * q, j1 = min(i + 1, j0 + q);
+        for (int j = j0; j < j1; ++j) {
+            const double2 l = Li[i + (long)j * f], u = mf_sh[j];
             sr += l.x * u.x - l.y * u.y;
             si += l.x * u.y + l.y * u.x;
         }
-        z[i] = make_double2(sr, si);
-        zs[i] = make_double2(sr, si);
     }
+    part[wave][lane] = make_double2(sr, si);
     __syncthreads();
-    const double2* L21 = arena + nd.L21;
-    double2* cw = arena + nd.cw;
-    for (int r = tid; r < b; r += 256) {
-        double sr = w[e + r].x, si = w[e + r].y;
-        for (int j = 0; j < e; ++j) {
-            const double2 l = L21[r + (long)j * b], u = zs[j];
-            sr -= l.x * u.x - l.y * u.y;
-            si -= l.x * u.y + l.y * u.x;
+    if (wave == 0 && i < iend) {
+        double2 zz = part[0][lane];
+        for (int k = 1; k < 4; ++k) {
+            zz.x += part[k][lane].x;
+            zz.y += part[k][lane].y;
         }
-        cw[r] = make_double2(sr, si);
+        arena[nd.z + i] = zz;
     }
 }
 
-// One workgroup per node: xb = x at the boundary columns, t = z - L21^* xb,
-// x at the eliminated columns = Linv^* t.  A wavefront per column of L21 and per
-// row of Linv^* (lanes along contiguous memory).
+// cw(r) = w(e + r) - sum_j L21(r, j) z(j) for the 64 rows of chunk blockIdx.x
 __global__ void __launch_bounds__(256)
-mf_backward_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
-                   const double2* __restrict__ arena, double2* __restrict__ x) {
+mf_fwd_cw_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
+                 double2* __restrict__ arena, const double2* __restrict__ y) {
     extern __shared__ double2 mf_sh[];
-    const MFNodeDev nd = nodes[list[blockIdx.x]];
-    const int e = nd.e, b = nd.b, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    double2* xb = mf_sh;
-    double2* t = mf_sh + b;
+    __shared__ double2 part[4][64];
+    const MFNodeDev nd = nodes[list[blockIdx.y]];
+    const int e = nd.e, b = nd.b, f = nd.f, r0 = blockIdx.x * 64;
+    if (r0 >= b) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int* idx = reinterpret_cast<const int*>(img + nd.idx);
-    for (int r = tid; r < b; r += 256) xb[r] = x[idx[e + r]];
+    for (int j = tid; j < e; j += 256) mf_sh[j] = arena[nd.z + j];
     __syncthreads();
-    const double2* L21 = arena + nd.L21;
-    const double2* z = arena + nd.z;
-    for (int j = wave; j < e; j += 4) {
+    const int r = r0 + lane;
+    const double2* L21 = arena + nd.L + e;
+    double sr = 0.0, si = 0.0;
+    if (r < b) {
+        const int q = (e + 3) / 4, j0 = wave * q, j1 = min(e, j0 + q);
+        for (int j = j0; j < j1; ++j) {
+            const double2 l = L21[r + (long)j * f], u = mf_sh[j];
+            sr += l.x * u.x - l.y * u.y;
+            si += l.x * u.y + l.y * u.x;
+        }
+    }
+    part[wave][lane] = make_double2(sr, si);
+    __syncthreads();
+    if (wave == 0 && r < b) {
+        double2 v = mf_front_rhs(nd, nodes, img, arena, y, idx, e + r);
+        for (int k = 0; k < 4; ++k) {
+            v.x -= part[k][lane].x;
+            v.y -= part[k][lane].y;
+        }
+        arena[nd.cw + r] = v;
+    }
+}
+
+// t(j) = z(j) - sum_r conj(L21(r, j)) x(idx(e + r)) for the 16 columns of chunk blockIdx.x (a
+// wavefront per column, lanes along the column); t overwrites z
+__global__ void __launch_bounds__(256)
+mf_bwd_t_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
+                double2* __restrict__ arena, const double2* __restrict__ x) {
+    extern __shared__ double2 mf_sh[];
+    const MFNodeDev nd = nodes[list[blockIdx.y]];
+    const int e = nd.e, b = nd.b, f = nd.f, c0 = blockIdx.x * 16;
+    if (c0 >= e) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int* idx = reinterpret_cast<const int*>(img + nd.idx);
+    for (int r = tid; r < b; r += 256) mf_sh[r] = x[idx[e + r]];
+    __syncthreads();
+    const double2* L21 = arena + nd.L + e;
+    for (int j = c0 + wave; j < min(e, c0 + 16); j += 4) {
         double2 s = make_double2(0.0, 0.0);
         for (int r = lane; r < b; r += 64) {
-            const double2 l = L21[r + (long)j * b], u = xb[r];   // conj(l) u
+            const double2 l = L21[r + (long)j * f], u = mf_sh[r];   // conj(l) u
             s.x += l.x * u.x + l.y * u.y;
             s.y += l.x * u.y - l.y * u.x;
         }
         s = wave_sum2(s);
-        if (lane == 0) t[j] = make_double2(z[j].x - s.x, z[j].y - s.y);
+        if (lane == 0) {
+            const double2 z = arena[nd.z + j];
+            arena[nd.z + j] = make_double2(z.x - s.x, z.y - s.y);
+        }
     }
+}
+
+// x(idx(i)) = sum_{j >= i} conj(Linv(j, i)) t(j) for the 16 rows of chunk blockIdx.x
+__global__ void __launch_bounds__(256)
+mf_bwd_x_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
+                const double2* __restrict__ arena, double2* __restrict__ x) {
+    extern __shared__ double2 mf_sh[];
+    const MFNodeDev nd = nodes[list[blockIdx.y]];
+    const int e = nd.e, f = nd.f, c0 = blockIdx.x * 16;
+    if (c0 >= e) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int* idx = reinterpret_cast<const int*>(img + nd.idx);
+    for (int j = c0 + tid; j < e; j += 256) mf_sh[j - c0] = arena[nd.z + j];
     __syncthreads();
-    const double2* Li = arena + nd.Linv;
-    for (int i = wave; i < e; i += 4) {
+    const double2* Li = arena + nd.Z;
+    for (int i = c0 + wave; i < min(e, c0 + 16); i += 4) {
         double2 s = make_double2(0.0, 0.0);
         for (int j = i + lane; j < e; j += 64) {
-            const double2 l = Li[j + (long)i * e], u = t[j];   // conj(Linv(j, i)) t_j
+            const double2 l = Li[j + (long)i * f], u = mf_sh[j - c0];   // conj(Linv(j, i)) t_j
             s.x += l.x * u.x + l.y * u.y;
             s.y += l.x * u.y - l.y * u.x;
         }
@@ -1402,27 +1508,31 @@ mf_backward_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ 
     }
 }
 
+void launch_mf_solve(const MFNodeDev* nodes, const int* list, int count, int max_e, int max_b, bool forward,
+                     const char* img, double2* arena, const double2* in, double2* out, hipStream_t st) {
+    if (count <= 0) return;
+    const size_t lds_e = (size_t)std::max(max_e, 1) * sizeof(double2), lds_b = (size_t)std::max(max_b, 1) * sizeof(double2);
+    if (forward) {
+        if (max_e > 0)
+            hipLaunchKernelGGL(mf_fwd_z_kernel, dim3((max_e + 63) / 64, count), dim3(256), lds_e, st, nodes, list, img,
+                               arena, in);
+        if (max_b > 0)
+            hipLaunchKernelGGL(mf_fwd_cw_kernel, dim3((max_b + 63) / 64, count), dim3(256), lds_e, st, nodes, list,
+                               img, arena, in);
+    } else if (max_e > 0) {
+        hipLaunchKernelGGL(mf_bwd_t_kernel, dim3((max_e + 15) / 16, count), dim3(256), lds_b, st, nodes, list, img,
+                           arena, (const double2*)out);
+        hipLaunchKernelGGL(mf_bwd_x_kernel, dim3((max_e + 15) / 16, count), dim3(256), lds_e, st, nodes, list, img,
+                           (const double2*)arena, out);
+    }
+    MDP_HIP(hipGetLastError());
+}
+
 void launch_mf_assemble(const MFNodeDev* nodes, const int* list, int count, int max_f, const char* img,
                         const double2* P, double2* arena, hipStream_t st) {
     if (count <= 0 || max_f <= 0) return;
     const unsigned bx = (unsigned)(((long)max_f * max_f + 255) / 256);
     hipLaunchKernelGGL(mf_assemble_kernel, dim3(bx, count), dim3(256), 0, st, nodes, list, img, P, arena);
-    MDP_HIP(hipGetLastError());
-}
-
-void launch_mf_forward(const MFNodeDev* nodes, const int* list, int count, int lds_elems, const char* img,
-                       double2* arena, const double2* y, hipStream_t st) {
-    if (count <= 0) return;
-    hipLaunchKernelGGL(mf_forward_kernel, dim3(count), dim3(256), (size_t)std::max(lds_elems, 1) * sizeof(double2),
-                       st, nodes, list, img, arena, y);
-    MDP_HIP(hipGetLastError());
-}
-
-void launch_mf_backward(const MFNodeDev* nodes, const int* list, int count, int lds_elems, const char* img,
-                        const double2* arena, double2* x, hipStream_t st) {
-    if (count <= 0) return;
-    hipLaunchKernelGGL(mf_backward_kernel, dim3(count), dim3(256), (size_t)std::max(lds_elems, 1) * sizeof(double2),
-                       st, nodes, list, img, arena, x);
     MDP_HIP(hipGetLastError());
 }
 

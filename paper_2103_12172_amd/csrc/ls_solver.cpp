@@ -385,21 +385,58 @@ MFHost mf_plan(const PackedHost& h) {
         t.by_height[nd.height].push_back(v);
         t.max_f = std::max(t.max_f, f);
         t.max_e = std::max(t.max_e, nd.e);
-        t.lds_fwd = std::max(t.lds_fwd, f + nd.e);
-        t.lds_bwd = std::max(t.lds_bwd, nd.b + nd.e);
+        t.lds_fwd = std::max(t.lds_fwd, nd.e);   // the substitutions stage e or b values in LDS
+        t.lds_bwd = std::max(t.lds_bwd, nd.b);
     }
     if (nodes[0].b != 0) throw Error(MDP_ERR_ARG, "inconsistent elimination tree");
-    // factor arena: per node F11 (e^2), the rest of the front (b f), Linv (e^2), L21 (b e), z (e), cw (b)
+    // factor arena: every front G (f x f), then per height the L, Z, W (f x e each) of its nodes
+    // (cleared together before the height's steps), then the solve vectors z (e) and cw (b)
     size_t off = 0;
     auto take = [&](size_t n) { const size_t o = off; off += (n + 15) / 16 * 16; return o; };
+    for (MFHost::Node& nd : nodes) nd.G = take((size_t)(nd.e + nd.b) * (nd.e + nd.b));
+    for (const auto& hv : t.by_height) {
+        int me = 0, mb = 0;
+        for (int v : hv) { me = std::max(me, nodes[v].e); mb = std::max(mb, nodes[v].b); }
+        t.h_max_e.push_back(me);
+        t.h_max_b.push_back(mb);
+        t.lzw.push_back(off);
+        for (int v : hv) {
+            MFHost::Node& nd = nodes[v];
+            const size_t fe = (size_t)(nd.e + nd.b) * nd.e;
+            nd.L = take(fe);
+            nd.Z = take(fe);
+            nd.W = take(fe);
+        }
+    }
+    t.lzw.push_back(off);
     for (MFHost::Node& nd : nodes) {
-        const size_t e = nd.e, b = nd.b;
-        nd.X = take(e * e);
-        nd.Y = take(b * (e + b));
-        nd.Linv = take(e * e);
-        nd.L21 = take(b * e);
-        nd.z = take(e);
-        nd.cw = take(b);
+        nd.z = take(nd.e);
+        nd.cw = take(nd.b);
+    }
+    // batched steps: panel s of every front of a height with more than 64 s eliminated columns
+    for (size_t hh = 0; hh < t.by_height.size(); ++hh) {
+        int max_e = 0;
+        for (int v : t.by_height[hh]) max_e = std::max(max_e, nodes[v].e);
+        for (int kb = 0; kb < max_e; kb += 64) {
+            MFHost::Step sp{(int)hh, (int)t.entry_node.size(), 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+            for (int v : t.by_height[hh]) {
+                const MFHost::Node& nd = nodes[v];
+                if (nd.e <= kb) continue;
+                const int f = nd.e + nd.b, w = std::min(64, nd.e - kb), rest = f - kb - w;
+                const int np = (rest + 31) / 32, nz = (kb + 31) / 32, nw = (kb + w + 31) / 32;
+                t.entry_node.push_back(v);
+                t.entry_kb.push_back(kb);
+                ++sp.count;
+                sp.max_roles = std::max(sp.max_roles, 1 + np + nz);
+                sp.max_tiles = std::max(sp.max_tiles, np * (np + 1) / 2 + np * nw);
+                const double W_ = w, R_ = rest, K_ = kb;
+                sp.panel_flops += 8.0 / 3.0 * W_ * W_ * W_ + 8.0 * R_ * W_ * W_ + 8.0 * K_ * W_ * W_;
+                sp.panel_bytes += 16.0 * (W_ * W_ + R_ * W_ + 2.0 * K_ * W_);
+                sp.update_flops += 4.0 * R_ * R_ * W_ + 8.0 * R_ * (K_ + W_) * W_;
+                sp.update_bytes += 16.0 * (R_ * R_ + 2.0 * R_ * W_ + 2.0 * R_ * (K_ + W_));
+            }
+            t.steps.push_back(sp);
+        }
     }
     t.arena = off;
     return t;
@@ -413,11 +450,8 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
     grow(w.Ap, (size_t)ptot * sizeof(double2));
     LSWork& lw = ws.ls;
     if (h.multifrontal) {
-        // the factor arena; the scratch of the per-node Cholesky (order <= max_e)
-        const size_t ee = (size_t)h.mf.max_e * h.mf.max_e;
+        // the factor arena
         grow(w.mf, std::max<size_t>(h.mf.arena, 1) * sizeof(double2));
-        grow(lw.L, std::max<size_t>(ee, 1) * sizeof(double2));
-        grow(lw.T, std::max<size_t>(ee, 1) * sizeof(double2));
     } else {
         const size_t nn = (size_t)nc * nc;
         grow(lw.G, nn * sizeof(double2));
@@ -470,7 +504,7 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
             o.f = a.e + a.b;
             o.leaf = a.sub >= 0;
             o.idx = (long)blob.put(a.idx);
-            o.X = (long)a.X; o.Y = (long)a.Y; o.Linv = (long)a.Linv; o.L21 = (long)a.L21;
+            o.G = (long)a.G; o.L = (long)a.L; o.Z = (long)a.Z; o.W = (long)a.W;
             o.z = (long)a.z; o.cw = (long)a.cw;
             o.kid0 = a.kid[0];
             o.kid1 = a.kid[1];
@@ -497,6 +531,16 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
         }
         t.mf_list_off.push_back(lists.size());
         t.mf_lists = blob.put(lists);
+        double2* arena = w.mf.as<double2>();
+        std::vector<CholBatchEntry> ent(mf.entry_node.size());
+        for (size_t q = 0; q < ent.size(); ++q) {
+            const MFHost::Node& a = mf.nodes[mf.entry_node[q]];
+            const int f = a.e + a.b, kb = mf.entry_kb[q], wd = std::min(64, a.e - kb), rest = f - kb - wd;
+            const int np = (rest + 31) / 32, nw = (kb + wd + 31) / 32;
+            ent[q] = CholBatchEntry{arena + a.G, arena + a.L, arena + a.Z, arena + a.W, f, kb, wd, np, (kb + 31) / 32,
+                                    np * (np + 1) / 2 + np * nw};
+        }
+        t.mf_steps = blob.put(ent);
     }
     return t;
 }
@@ -564,10 +608,13 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
         chol_flops = cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof,
                                           h.steps.empty() ? nullptr : &h.steps);
     } else {
-        // children before parents: assemble every front of one height, then factor each node's
-        // eliminated block (Cholesky and inverse), L21 = F21 L11^{-*}, and its contribution
-        // F22 - L21 L21^* in place
+        // children before parents: assemble every front of one height, then factor the first e columns
+        // of all its fronts together, one batched panel and one batched update launch per 64 columns
+        // (the panel rows below the eliminated block are L21, the trailing update leaves
+        // F22 - L21 L21^* in G(e:, e:))
         const MFHost& mf = h.mf;
+        const CholBatchEntry* ent = reinterpret_cast<const CholBatchEntry*>(image + tb.mf_steps);
+        size_t si = 0;
         for (size_t hh = 0; hh < mf.by_height.size(); ++hh) {
             const std::vector<int>& lv = mf.by_height[hh];
             int mxf = 0;
@@ -577,26 +624,21 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
                 mxf = std::max(mxf, f);
                 abytes += 32.0 * f * f;
             }
+            if (mf.lzw[hh + 1] > mf.lzw[hh])
+                MDP_HIP(hipMemsetAsync(arena + mf.lzw[hh], 0, (mf.lzw[hh + 1] - mf.lzw[hh]) * sizeof(double2), st));
             ws.prof.run("mf_assemble", st, 0.0, abytes, [&] {
                 launch_mf_assemble(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)lv.size(), mxf, image,
                                    ws.zg.as<double2>(), arena, st);
             });
-            for (int v : lv) {
-                const MFHost::Node& nd = mf.nodes[v];
-                if (nd.e == 0) continue;
-                chol_flops += cholesky_and_inverse(arena + nd.X, L, arena + nd.Linv, lw.T.as<double2>(), &fl->info,
-                                                   nd.e, 0.0, st, &ws.prof, nullptr);
-                if (nd.b == 0) continue;
-                const double e = nd.e, b = nd.b;
-                ws.prof.run("mf_gemm", st, 8.0 * b * e * e, 16.0 * (2.0 * b * e + e * e), [&] {
-                    launch_zgemm('N', 'C', nd.b, nd.e, nd.e, ONE, arena + nd.Y, nd.b, arena + nd.Linv, nd.e, ZERO,
-                                 arena + nd.L21, nd.b, ws.zg, st, 2);
+            for (; si < mf.steps.size() && mf.steps[si].height == (int)hh; ++si) {
+                const MFHost::Step& sp = mf.steps[si];
+                ws.prof.run("chol_panel", st, sp.panel_flops, sp.panel_bytes, [&] {
+                    launch_chol_panel_batched(ent + sp.entry0, sp.count, sp.max_roles, &fl->info, st);
                 });
-                ws.prof.run("mf_gemm", st, 8.0 * b * b * e, 16.0 * (2.0 * b * e + 2.0 * b * b), [&] {
-                    launch_zgemm('N', 'C', nd.b, nd.b, nd.e, MONE, arena + nd.L21, nd.b, arena + nd.L21, nd.b, ONE,
-                                 arena + nd.Y + (size_t)nd.e * nd.b, nd.b, ws.zg, st);
+                ws.prof.run("chol_update", st, sp.update_flops, sp.update_bytes, [&] {
+                    launch_chol_update_batched(ent + sp.entry0, sp.count, sp.max_tiles, st);
                 });
-                chol_flops += 8.0 * b * e * e + 8.0 * b * b * e;
+                chol_flops += sp.panel_flops + sp.update_flops;
             }
         }
     }
@@ -606,11 +648,11 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
         const int H = (int)mf.by_height.size();
         ws.prof.run("mf_solve", st, 0.0, 0.0, [&] {
             for (int hh = 0; hh < H; ++hh)
-                launch_mf_forward(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.lds_fwd,
-                                  image, arena, yv, st);
+                launch_mf_solve(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.h_max_e[hh],
+                                mf.h_max_b[hh], true, image, arena, yv, nullptr, st);
             for (int hh = H - 1; hh >= 0; --hh)
-                launch_mf_backward(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(),
-                                   mf.lds_bwd, image, arena, out, st);
+                launch_mf_solve(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.h_max_e[hh],
+                                mf.h_max_b[hh], false, image, arena, nullptr, out, st);
         });
     };
     // algorithmic flops: Gram (lower half), factor + inverse, and per normal solve (A^* v plus two
@@ -748,11 +790,11 @@ void ls_packed_factor_solve(Workspace& ws, const PackedHost& h, const char* imag
         double2* arena = ws.pk.mf.as<double2>();
         const int H = (int)mf.by_height.size();
         for (int hh = 0; hh < H; ++hh)
-            launch_mf_forward(nodes, lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.lds_fwd, image,
-                              arena, v, st);
+            launch_mf_solve(nodes, lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.h_max_e[hh],
+                            mf.h_max_b[hh], true, image, arena, v, nullptr, st);
         for (int hh = H - 1; hh >= 0; --hh)
-            launch_mf_backward(nodes, lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.lds_bwd, image,
-                               arena, out, st);
+            launch_mf_solve(nodes, lists + tb.mf_list_off[hh], (int)mf.by_height[hh].size(), mf.h_max_e[hh],
+                            mf.h_max_b[hh], false, image, arena, nullptr, out, st);
         return;
     }
     LSWork& lw = ws.ls;

@@ -35,11 +35,21 @@ struct MFHost {
         std::vector<int> kpos[2];  // child's boundary position -> front position
         std::vector<int> inv[2];   // front position -> child's boundary position, or -1
         std::vector<int> spos;     // leaf: front position -> column of its subdomain's Gram block
-        size_t X = 0, Y = 0, Linv = 0, L21 = 0, z = 0, cw = 0;   // arena offsets (complex entries)
+        size_t G = 0, L = 0, Z = 0, W = 0, z = 0, cw = 0;   // arena offsets (complex entries)
+    };
+    // one batched Cholesky step: 64-column panel s of every front of one height with e > 64 s
+    struct Step {
+        int height, entry0, count, max_roles, max_tiles;
+        double panel_flops, update_flops, panel_bytes, update_bytes;
     };
     std::vector<Node> nodes;
     std::vector<std::vector<int>> by_height;   // nodes of each height (leaves: 0)
-    int max_f = 0, max_e = 0, lds_fwd = 0, lds_bwd = 0;
+    std::vector<size_t> lzw;                   // per height: arena range [lzw[h], lzw[h+1]) of its L, Z, W
+    std::vector<int> h_max_e, h_max_b;         // per height: largest eliminated and boundary counts
+    std::vector<Step> steps;                   // heights in order, panels in order within a height
+    std::vector<int> entry_node;               // node of every step entry
+    std::vector<int> entry_kb;                 // first column of every step entry's panel
+    int max_f = 0, max_e = 0, lds_fwd = 0, lds_bwd = 0;   // largest front, e; LDS entries of the substitutions
     size_t arena = 0;                          // complex entries of the factor arena
     double flops = 0.0;                        // partial factorisations (complex, 8 per multiply-add)
 };
@@ -72,7 +82,7 @@ double cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, i
 struct PackedTables {
     size_t Q, m, s, off, roff, sub, p, gcol, start, cols, coef, zb;
     int nsplit;
-    size_t mf_nodes, mf_lists;            // multifrontal: node table, node lists by height
+    size_t mf_nodes, mf_lists, mf_steps;  // multifrontal: node table, node lists by height, step entries
     std::vector<size_t> mf_list_off;      // start of each height's list (entries)
 };
 

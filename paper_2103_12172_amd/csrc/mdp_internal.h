@@ -362,6 +362,35 @@ void launch_proj_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_
                             hipStream_t st);
 void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, hipStream_t st);
 bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi);
+
+// One plan's entries in a batched FP64 band solve across plans (the reconstruction of
+// subdomains with different n and k): global entries b0 .. b0+R-1 are the job's entries
+// 0 .. R-1.  Right-hand side src (entry b's grid at src.goff[b]); rows bd; batch buffers A, B
+// ([b][2][bd.nr][W], the job's own regions; jobs of one n hold consecutive regions so one
+// sine GEMM per n covers them); the density step reads E (|gamma| x ncol), the gamma lists
+// and the coefficient vector cidx[b] of c, and writes entry b's grid at src.goff[b].
+struct SolveJob {
+    SrcDesc src;
+    StencilCoef sc;
+    Fold f;
+    Band bd;
+    int b0, R;
+    double *A, *B;
+    const double *fac, *colc;
+    const double* E;
+    int ng, ncol;
+    const int *gm, *gq, *gside, *cidx;
+};
+// w_b(gamma) = E c_b on the entries' grids (cleared beforehand); c: every subdomain's coefficients
+void launch_extend_density_jobs(const SolveJob* jobs, int njobs, int total, int max_ng, double* grids,
+                                const double* c, hipStream_t st);
+// the folded right-hand sides of every entry into its job's A
+void launch_fold_rhs_jobs(const SolveJob* jobs, int njobs, int total, int max_w, int max_nr, hipStream_t st);
+// the mode solves of every entry, B -> A
+void launch_tridiag_jobs(const SolveJob* jobs, int njobs, int total, int max_w, hipStream_t st);
+// grid_b = w_b - u_b on the band rows, in place (u from the job's B)
+void launch_unfold_jobs(const SolveJob* jobs, int njobs, int total, int max_n, int max_nr, double* grids,
+                        hipStream_t st);
 int fused_segments(int m_lo, int m_hi);   // segments of FUSED_K rows covering m = m_lo-1..m_hi+1
 // interface least squares
 // tri: 0 full; 1 lower-triangle tiles of C only; 2 op(B) upper triangular (skip its zero part)
@@ -385,6 +414,16 @@ struct CholStepDev {
 };
 void launch_chol_panel(const double2* G, int nc, const CholStepDev& sp, double shift, double2* L, double2* Z,
                        const double2* W, int* info, hipStream_t st);
+// One matrix's share of a batched Cholesky step: sub-block kb..kb+w-1 of the order-nc matrix G
+// (ld nc), its factor L, the inverse Z and the inverse's accumulator W (ld nc, columns < the
+// eliminated count); np = ceil((nc-kb-w)/32) row slabs, nz = ceil(kb/32) Z slabs, tiles of the
+// update = np(np+1)/2 + np ceil((kb+w)/32).
+struct CholBatchEntry {
+    double2 *G, *L, *Z, *W;
+    int nc, kb, w, np, nz, tiles;
+};
+void launch_chol_panel_batched(const CholBatchEntry* ent, int count, int max_roles, int* info, hipStream_t st);
+void launch_chol_update_batched(const CholBatchEntry* ent, int count, int max_tiles, hipStream_t st);
 // trailing Schur complement and inverse accumulation after the step kb .. kb+wtot-1
 void launch_chol_update(double2* G, int nc, int kb, int wtot, const double2* L, const double2* Z, double2* W,
                         hipStream_t st);
@@ -443,27 +482,28 @@ void launch_zaxpy1(int n, const double2* x, double2* y, hipStream_t st);
 // node assembles its two children's contribution blocks (inv0/inv1 map front
 // positions to a child's boundary positions, -1 if absent; kpos0/kpos1 map the
 // child's boundary positions to front positions).  Int tables are byte offsets
-// into the call's device image; X, Y, Linv, L21, z, cw are element offsets into
-// the factor arena: X = F11 (e x e), Y = rows e..f-1 of the front (b x f, ld b,
-// the contribution block F22 - L21 L21^* in its columns e..f-1 once factored),
-// Linv = L11^{-1}, L21 (b x e), z (forward solve, e), cw (forward contribution, b).
+// into the call's device image; G, L, Z, W, z, cw are element offsets into the
+// factor arena: G the front (f x f, ld f), factored in place over its first e
+// columns (afterwards its lower block G(e:, e:) is the contribution
+// F22 - L21 L21^*); L (f x e, ld f) the factor's columns, L21 = its rows e..f-1;
+// Z (ld f) holds L11^{-1}; W the inverse's accumulator; z (e) and cw (b) the
+// forward solve's values and contribution.
 struct MFNodeDev {
     int e, b, f, leaf;
     int n, nsplit;
     long pstride, poff;
     long spos, inv0, inv1, kpos0, kpos1, idx;
     int kid0, kid1;
-    long X, Y, Linv, L21, z, cw;
+    long G, L, Z, W, z, cw;
 };
 // all fronts of the nodes list[0..count-1] (max_f: their largest order)
 void launch_mf_assemble(const MFNodeDev* nodes, const int* list, int count, int max_f, const char* img,
                         const double2* P, double2* arena, hipStream_t st);
-// forward substitution of the listed nodes: z = Linv (y_e + children), cw = w_b - L21 z
-void launch_mf_forward(const MFNodeDev* nodes, const int* list, int count, int lds_elems, const char* img,
-                       double2* arena, const double2* y, hipStream_t st);
-// back substitution of the listed nodes: x_e = Linv^* (z - L21^* x_b)
-void launch_mf_backward(const MFNodeDev* nodes, const int* list, int count, int lds_elems, const char* img,
-                        const double2* arena, double2* x, hipStream_t st);
+// substitutions of the listed nodes (one tree height; max_e, max_b over them): forward
+// (in = y): z = Linv w_e, cw = w_b - L21 z; backward (out = x, read at the boundary
+// columns, written at the eliminated ones): t = z - L21^* x_b, x_e = Linv^* t
+void launch_mf_solve(const MFNodeDev* nodes, const int* list, int count, int max_e, int max_b, bool forward,
+                     const char* img, double2* arena, const double2* in, double2* out, hipStream_t st);
 
 void launch_diag_range(const double2* L, int n, int ld, double* out, hipStream_t st);
 
