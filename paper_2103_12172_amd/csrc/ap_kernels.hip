@@ -79,12 +79,9 @@ struct SrcEval {
 // out row (b, m): block 1 col c = q-1 (q = 1..p):   e_q = g_q + g_{n-q} (e_p = g_p)
 //                 block 2 col c = P1+q-1 (q < p):   o_q = g_q - g_{n-q}
 template <class T>
-__global__ void __launch_bounds__(256)
-fold_rhs_kernel(SrcEval ev, Fold f, int planes, Band bd, T* __restrict__ out) {
+__device__ inline void fold_rhs_body(const SrcEval& ev, const Fold& f, int planes, Band bd, T* __restrict__ out, int c,
+                                     int m, int b) {
     const int n = f.n, p = f.p, W = f.W;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = bd.r0 + blockIdx.y, b = blockIdx.z;
-    if (c >= W) return;
     C64 v = {0.0, 0.0};
     if (c < f.P1) {
         const int q = c + 1;
@@ -97,6 +94,14 @@ fold_rhs_kernel(SrcEval ev, Fold f, int planes, Band bd, T* __restrict__ out) {
     const long o = (((long)b * planes) * bd.nr + (m - bd.r0)) * W + c;
     out[o] = (T)v.re;
     if (planes == 2) out[o + (long)bd.nr * W] = (T)v.im;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+fold_rhs_kernel(SrcEval ev, Fold f, int planes, Band bd, T* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= f.W) return;
+    fold_rhs_body<T>(ev, f, planes, bd, out, c, bd.r0 + blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------------ tridiagonal solve per mode
@@ -134,41 +139,86 @@ tridiag_adj_kernel(const double* __restrict__ in, int planes_in, double* __restr
     const double* r_re = fac + 2 * plane + c;
     const double* r_im = fac + 3 * plane + c;
     const double a = colc[c], s0r = colc[W + c], s0i = colc[2 * W + c];
-    double yr = 0.0, yi = 0.0;
-    for (int m = 0; m <= n; ++m) {
-        const long off = (long)m * W;
-        double gr = g_re[off], gi = g_im ? g_im[off] : 0.0;
-        if (m >= 1) {   // g - conj(s) y
-            const double sr = (m == 1) ? s0r : a, si = (m == 1) ? s0i : 0.0;
-            gr -= sr * yr + si * yi;
-            gi -= sr * yi - si * yr;
+    // rows in groups of U with the next group's loads in flight
+    constexpr int U = 8;
+    double gr[U], gi[U], rr[U], ri[U], ngr[U], ngi[U], nrr[U], nri[U];
+    auto load_fwd = [&](int m0, double* Gr, double* Gi, double* Rr, double* Ri) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long off = (long)min(m0 + u, n) * W;
+            Gr[u] = g_re[off];
+            Gi[u] = g_im ? g_im[off] : 0.0;
+            Rr[u] = r_re[off];
+            Ri[u] = r_im[off];
         }
-        const double rr = r_re[off], ri = r_im[off];   // conj(r) g
-        yr = rr * gr + ri * gi;
-        yi = rr * gi - ri * gr;
-        o_re[off] = yr;
-        o_im[off] = yi;
+    };
+    double yr = 0.0, yi = 0.0;
+    load_fwd(0, gr, gi, rr, ri);
+    for (int m0 = 0; m0 <= n; m0 += U) {
+        if (m0 + U <= n) load_fwd(m0 + U, ngr, ngi, nrr, nri);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int m = m0 + u;
+            if (m > n) break;
+            double xr_ = gr[u], xi_ = gi[u];
+            if (m >= 1) {   // g - conj(s) y
+                const double sr = (m == 1) ? s0r : a, si = (m == 1) ? s0i : 0.0;
+                xr_ -= sr * yr + si * yi;
+                xi_ -= sr * yi - si * yr;
+            }
+            yr = rr[u] * xr_ + ri[u] * xi_;   // conj(r) (g - conj(s) y)
+            yi = rr[u] * xi_ - ri[u] * xr_;
+            o_re[(long)m * W] = yr;
+            o_im[(long)m * W] = yi;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            gr[u] = ngr[u];
+            gi[u] = ngi[u];
+            rr[u] = nrr[u];
+            ri[u] = nri[u];
+        }
     }
+    // x_n = y_n; x_m = y_m - conj(l_{m+1}) x_{m+1}, rows n-1..0 in groups of U
     double xr = yr, xi = yi;
-    for (int m = n - 1; m >= 0; --m) {
-        const long off = (long)m * W, offn = (long)(m + 1) * W;
-        const double lr = l_re[offn], li = l_im[offn];   // y - conj(l_{m+1}) x
-        const double nxr = o_re[off] - (lr * xr + li * xi);
-        const double nxi = o_im[off] - (lr * xi - li * xr);
-        xr = nxr;
-        xi = nxi;
-        o_re[off] = xr;
-        o_im[off] = xi;
+    auto load_bwd = [&](int mtop, double* Yr, double* Yi, double* Lr, double* Li) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int m = max(mtop - u, 0);
+            Yr[u] = o_re[(long)m * W];
+            Yi[u] = o_im[(long)m * W];
+            Lr[u] = l_re[(long)(m + 1) * W];
+            Li[u] = l_im[(long)(m + 1) * W];
+        }
+    };
+    load_bwd(n - 1, gr, gi, rr, ri);
+    for (int mtop = n - 1; mtop >= 0; mtop -= U) {
+        if (mtop - U >= 0) load_bwd(mtop - U, ngr, ngi, nrr, nri);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int m = mtop - u;
+            if (m < 0) break;
+            const double nxr = gr[u] - (rr[u] * xr + ri[u] * xi);
+            const double nxi = gi[u] - (rr[u] * xi - ri[u] * xr);
+            xr = nxr;
+            xi = nxi;
+            o_re[(long)m * W] = xr;
+            o_im[(long)m * W] = xi;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            gr[u] = ngr[u];
+            gi[u] = ngi[u];
+            rr[u] = nrr[u];
+            ri[u] = nri[u];
+        }
     }
 }
 
 template <class T>
-__global__ void __launch_bounds__(256)
-tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, const T* __restrict__ fac,
-               const T* __restrict__ colc, int n, int W, int R, Band bd) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (c >= W || b >= R) return;
+__device__ inline void tridiag_body(const T* __restrict__ in, int planes_in, T* __restrict__ out,
+                                    const T* __restrict__ fac, const T* __restrict__ colc, int n, int W, Band bd,
+                                    int c, int b) {
     const int r0 = bd.r0, t = bd.r0 + bd.nr - 1;
     const long plane = (long)bd.nr * W, fplane = (long)(n + 1) * W;
     const T* fin_re = in + (long)b * planes_in * plane + c - (long)r0 * W;   // indexed by absolute row
@@ -260,6 +310,16 @@ tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, con
             li[u] = nli[u];
         }
     }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+tridiag_kernel(const T* __restrict__ in, int planes_in, T* __restrict__ out, const T* __restrict__ fac,
+               const T* __restrict__ colc, int n, int W, int R, Band bd) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (c >= W || b >= R) return;
+    tridiag_body<T>(in, planes_in, out, fac, colc, n, W, bd, c, b);
 }
 
 // The same solve cut into P row segments, one wavefront each (64 columns per
@@ -552,13 +612,10 @@ __global__ void gather_q_kernel(const T* __restrict__ u, const float* __restrict
 // out_b(m, q) = w_b(m, q) + alpha * u_b(m, q) on the rows out_r0 + blockIdx.y (inside the
 // buffer's band bd; w optional; complex interleaved FP64)
 template <class T>
-__global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f, Band bd,
-                                   int out_r0, double alpha, const double* w, long w_stride, double* out,
-                                   long out_stride, const long* __restrict__ boff) {
+__device__ inline void unfold_body(const T* __restrict__ u, const float* __restrict__ du, const Fold& f, Band bd,
+                                   double alpha, const double* w, long w_stride, double* out, long out_stride,
+                                   const long* __restrict__ boff, int m, int q, int b) {
     const int n = f.n;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = out_r0 + blockIdx.y, b = blockIdx.z;
-    if (q > n) return;
     const long node = (long)m * (n + 1) + q;
     C64 v = unfold_c(u, f, bd, b, m, q);
     if (du) v = cadd(v, unfold_c(du, f, bd, b, m, q));
@@ -573,16 +630,23 @@ __global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restr
     o[1] = im;
 }
 
+template <class T>
+__global__ void unfold_grid_kernel(const T* __restrict__ u, const float* __restrict__ du, Fold f, Band bd,
+                                   int out_r0, double alpha, const double* w, long w_stride, double* out,
+                                   long out_stride, const long* __restrict__ boff) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > f.n) return;
+    unfold_body<T>(u, du, f, bd, alpha, w, w_stride, out, out_stride, boff, out_r0 + blockIdx.y, q, blockIdx.z);
+}
+
 // ------------------------------------------------------------------ density on gamma for reconstruction
 // w_b(gamma_i) = sum_col E(i, col) c_b(col)  (E real, c complex); w is pre-zeroed elsewhere.
-__global__ void extend_density_kernel(const double* __restrict__ E, int ng, int ncol, const double* __restrict__ c,
-                                      const int* __restrict__ cidx, const int* __restrict__ gm,
-                                      const int* __restrict__ gq, const int* __restrict__ gside, int n, double* w,
-                                      long w_stride, const long* __restrict__ woff) {
+__device__ inline void extend_density_body(const double* __restrict__ E, int ng, int ncol,
+                                           const double* __restrict__ c, const int* __restrict__ cidx,
+                                           const int* __restrict__ gm, const int* __restrict__ gq,
+                                           const int* __restrict__ gside, int n, double* w, long w_stride,
+                                           const long* __restrict__ woff, int i, int b) {
     // row i of E is nonzero only in its side's Dirichlet and Neumann columns
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (i >= ng) return;
     const int M = ncol / 8, s = gside[i];
     double re = 0.0, im = 0.0;
     const double* cb = c + 2 * (long)(cidx ? cidx[b] : b) * ncol;
@@ -598,6 +662,15 @@ __global__ void extend_density_kernel(const double* __restrict__ E, int ng, int 
     double* o = w + 2 * ((woff ? woff[b] : (long)b * w_stride) + (long)gm[i] * (n + 1) + gq[i]);
     o[0] = re;
     o[1] = im;
+}
+
+__global__ void extend_density_kernel(const double* __restrict__ E, int ng, int ncol, const double* __restrict__ c,
+                                      const int* __restrict__ cidx, const int* __restrict__ gm,
+                                      const int* __restrict__ gq, const int* __restrict__ gside, int n, double* w,
+                                      long w_stride, const long* __restrict__ woff) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ng) return;
+    extend_density_body(E, ng, ncol, c, cidx, gm, gq, gside, n, w, w_stride, woff, i, blockIdx.y);
 }
 
 // Inhomogeneous part of the extension (eqs. general_extension, cart_ext_2-4, extension_split):
@@ -1199,6 +1272,51 @@ __global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njo
     o[1] = -vim;
 }
 
+// ------------------------------------------------------------------ batched solves across plans
+__device__ inline int find_solve_job(const SolveJob* __restrict__ jobs, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].b0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void extend_density_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs, double* grids,
+                                           const double* __restrict__ c) {
+    const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.y)];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= J.ng) return;
+    extend_density_body(J.E, J.ng, J.ncol, c, J.cidx, J.gm, J.gq, J.gside, J.f.n, grids, 0, J.src.goff, i,
+                        blockIdx.y - J.b0);
+}
+
+__global__ void __launch_bounds__(256)
+fold_rhs_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs) {
+    const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.z)];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= J.f.W || (int)blockIdx.y >= J.bd.nr) return;
+    const SrcEval ev{J.src, J.f.n, J.sc};
+    fold_rhs_body<double>(ev, J.f, 2, J.bd, J.A, c, J.bd.r0 + blockIdx.y, blockIdx.z - J.b0);
+}
+
+__global__ void __launch_bounds__(256)
+tridiag_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs) {
+    const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.y)];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= J.f.W) return;
+    tridiag_body<double>(J.B, 2, J.A, J.fac, J.colc, J.f.n, J.f.W, J.bd, c, blockIdx.y - J.b0);
+}
+
+__global__ void unfold_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs, double* grids) {
+    const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.z)];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > J.f.n || (int)blockIdx.y >= J.bd.nr) return;
+    unfold_body<double>(J.B, nullptr, J.f, J.bd, -1.0, grids, 0, grids, 0, J.src.goff, J.bd.r0 + blockIdx.y, q,
+                        blockIdx.z - J.b0);
+}
+
 }  // namespace
 
 void launch_extension(const int* side, const double* rho, const double* t, const double* slen, int ng, double k,
@@ -1221,6 +1339,38 @@ bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int 
 }
 
 int fused_segments(int m_lo, int m_hi) { return (m_hi - m_lo + 3 + FUSED_K - 1) / FUSED_K; }
+
+void launch_extend_density_jobs(const SolveJob* jobs, int njobs, int total, int max_ng, double* grids,
+                                const double* c, hipStream_t st) {
+    if (njobs <= 0 || total <= 0 || max_ng <= 0) return;
+    check_batch(total);
+    hipLaunchKernelGGL(extend_density_jobs_kernel, dim3((max_ng + 255) / 256, total), dim3(256), 0, st, jobs, njobs,
+                       grids, c);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_fold_rhs_jobs(const SolveJob* jobs, int njobs, int total, int max_w, int max_nr, hipStream_t st) {
+    if (njobs <= 0 || total <= 0) return;
+    check_batch(total);
+    hipLaunchKernelGGL(fold_rhs_jobs_kernel, dim3((max_w + 255) / 256, max_nr, total), dim3(256), 0, st, jobs, njobs);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_tridiag_jobs(const SolveJob* jobs, int njobs, int total, int max_w, hipStream_t st) {
+    if (njobs <= 0 || total <= 0) return;
+    check_batch(total);
+    hipLaunchKernelGGL(tridiag_jobs_kernel, dim3((max_w + 255) / 256, total), dim3(256), 0, st, jobs, njobs);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_unfold_jobs(const SolveJob* jobs, int njobs, int total, int max_n, int max_nr, double* grids,
+                        hipStream_t st) {
+    if (njobs <= 0 || total <= 0) return;
+    check_batch(total);
+    hipLaunchKernelGGL(unfold_jobs_kernel, dim3((max_n + 1 + 255) / 256, max_nr, total), dim3(256), 0, st, jobs, njobs,
+                       grids);
+    MDP_HIP(hipGetLastError());
+}
 
 void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_items, hipStream_t st) {
     if (njobs <= 0 || total <= 0) return;

@@ -42,6 +42,7 @@ struct CallWork {
     DevBuf F, x;          // mdp_solve_interface
     DevBuf srcw;          // mdp_solve_interface: densities Ex^(I) f of the source right-hand sides
     DevBuf grad;          // mdp_dd_gradient: grids, vectors and tables of the reverse pass
+    DevBuf jobs;          // job tables of batched launches across plans
 };
 
 // Grow-only device workspaces of a context.

@@ -66,6 +66,7 @@ struct BufPool {
 struct mdp_projector {
     std::atomic<int> refs{1};
     int device = 0;
+    unsigned long long serial = 0;   // unique per build in its context (the interface factor's key)
     Geometry g;
     double k = 0.0;
     int m_star = 0, precision = 0;
@@ -97,6 +98,10 @@ struct mdp_ctx {
     size_t ws_cap = (size_t)24 << 30;
     int projector_path = MDP_PATH_AUTO;
     int interface_path = MDP_IFACE_AUTO;
+    unsigned long long next_serial = 1;
+    // key of the interface system whose Gram factor the workspaces hold (projector builds, side
+    // kinds and coefficients, M*, route); empty when none is valid
+    std::vector<double> iface_key;
     hipEvent_t last = nullptr;   // end of the previous call's work (workspaces are shared)
     hipStream_t last_stream = nullptr;
     bool have_last = false;
@@ -452,6 +457,7 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                 APPlan& plan = get_plan(ctx, g.n, g.h, sd->k);
                 std::unique_ptr<mdp_projector> P(new mdp_projector);
                 P->device = ctx->device;
+                P->serial = ctx->next_serial++;
                 P->k = sd->k;
                 P->m_star = m_star;
                 P->precision = precision;
@@ -1019,6 +1025,23 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
                             st);
             }
         }
+        // the system matrix depends on the projectors, the side kinds and coefficients and the route only:
+        // when they match the last factored system, its Gram factor is reused (new data or sources change
+        // the right-hand side alone; Sec. 3.5 factors Qbar once)
+        std::vector<double> key;
+        key.push_back((double)m_star);
+        key.push_back(multifrontal ? 1.0 : 0.0);
+        for (int i = 0; i < n_sub; ++i) {
+            key.push_back((double)P[i]->serial);
+            for (int s = 0; s < 4; ++s) {
+                const mdp_side& q = sides[4 * i + s];
+                key.push_back((double)q.kind);
+                key.push_back(q.kind == 0 ? q.alpha : (double)q.nbr);
+                key.push_back(q.kind == 0 ? q.beta : (double)q.nbr_side);
+            }
+        }
+        const bool reuse = !ctx->iface_key.empty() && ctx->iface_key == key;
+        ctx->iface_key.clear();   // set again below once this call's factor is in place
         LSResult r;
         bool fallback = false;
         {
@@ -1031,7 +1054,7 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
             // of the m x ncol matrix for the dense fallback
             double ls_flops = 8.0 * ((double)m * ncol * ncol - (double)ncol * ncol * ncol / 3.0);
             r = ls_solve_packed(ctx->ws, ph, img, tabs, F.as<double2>(), x.as<double2>(), cond_estimate_out != nullptr,
-                                st, &fallback);
+                                st, &fallback, reuse);
             if (fallback && multifrontal)
                 throw Error(MDP_ERR_SINGULAR, "interface least squares: the multifrontal Gram factor broke down or "
                                               "the refinement did not converge");
@@ -1045,6 +1068,7 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
                 MDP_HIP(hipStreamSynchronize(st));
             } else {
                 ls_flops = r.flops;
+                ctx->iface_key = key;
             }
             if (span) {
                 MDP_HIP(hipEventRecord(b, st));
@@ -1356,6 +1380,17 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
                 if (P[j] == P[i]) { grp.push_back(j); done[j] = true; }
             groups.push_back(std::move(grp));
         }
+        // groups of one n next to each other (the batched route's sine GEMMs go per n)
+        std::stable_sort(groups.begin(), groups.end(), [&](const std::vector<int>& a, const std::vector<int>& b) {
+            return P[a[0]]->g.n < P[b[0]]->g.n;
+        });
+        bool any_source = false, all_c128 = true;
+        for (int i = 0; i < n_sub; ++i) {
+            any_source = any_source || (sources && sources[i].f);
+            all_c128 = all_c128 && P[i]->precision == MDP_C128;
+        }
+        // several distinct projectors, complex128, no source: every group's solve in the same launches
+        const bool batched = groups.size() > 1 && all_c128 && !any_source;
         // per batch entry: the subdomain (its coefficients in c), its grid's offset in u_out and its source
         std::vector<int> cidx;
         std::vector<long> goff;
@@ -1376,6 +1411,95 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
         // u_out holds the density w (zero off gamma), then u = w - G(L w |M+) in place
         MDP_HIP(hipMemsetAsync(u_out, 0, (size_t)off[n_sub] * sizeof(mdp_c128), st));
         double* uo = reinterpret_cast<double*>(u_out);
+        if (batched) {
+            Profiler& pr = ctx->ws.prof;
+            std::vector<SolveJob> jobs;
+            std::vector<const APPlan*> plans;
+            size_t elems = 0, e = 0;
+            int total = 0, max_ng = 0, max_w = 0, max_nr = 0, max_n = 0;
+            double rhs_bytes = 0.0, tri_pts = 0.0, unfold_bytes = 0.0;
+            for (const auto& grp : groups) {
+                const mdp_projector* Pi = P[grp[0]];
+                const Geometry& G = Pi->g;
+                const APPlan& plan = get_plan(ctx, G.n, G.h, Pi->k);
+                const Band bd = box_band(plan, G);
+                SolveJob J{};
+                J.src.kind = Src::STENCIL_GRID;
+                J.src.grid = uo;
+                J.src.goff = reinterpret_cast<const long*>(img + o_goff) + e;
+                J.src.m_lo = G.m_lo; J.src.m_hi = G.m_hi; J.src.q_lo = G.q_lo; J.src.q_hi = G.q_hi;
+                J.sc = plan.sc;
+                J.f = plan.f;
+                J.bd = bd;
+                J.b0 = total;
+                J.R = (int)grp.size();
+                J.A = reinterpret_cast<double*>(elems);   // offsets for now, pointers below
+                J.fac = plan.fac64.as<double>();
+                J.colc = plan.colc64.as<double>();
+                J.E = Pi->E.as<double>();
+                J.ng = G.n_gamma;
+                J.ncol = 8 * Pi->m_star;
+                J.gm = Pi->gm; J.gq = Pi->gq; J.gside = Pi->gside;
+                J.cidx = reinterpret_cast<const int*>(img + o_cidx) + e;
+                jobs.push_back(J);
+                plans.push_back(&plan);
+                elems += (size_t)J.R * 2 * bd.nr * plan.f.W;
+                total += J.R;
+                e += grp.size();
+                max_ng = std::max(max_ng, G.n_gamma);
+                max_w = std::max(max_w, plan.f.W);
+                max_nr = std::max(max_nr, bd.nr);
+                max_n = std::max(max_n, G.n);
+                rhs_bytes += (double)J.R * 2 * bd.nr * (G.n - 1) * 8.0;
+                tri_pts += (double)J.R * bd.nr * (G.n - 1);
+                unfold_bytes += (double)J.R * bd.nr * (G.n + 1) * 16.0 * 3.0;
+            }
+            if (elems * sizeof(double) > ctx->ws.a.bytes || elems * sizeof(double) > ctx->ws.b.bytes) {
+                MDP_HIP(hipDeviceSynchronize());
+                ctx->ws.a.reserve(elems * sizeof(double));
+                ctx->ws.b.reserve(elems * sizeof(double));
+            }
+            for (SolveJob& J : jobs) {
+                const size_t o = reinterpret_cast<size_t>(J.A);
+                J.A = ctx->ws.a.as<double>() + o;
+                J.B = ctx->ws.b.as<double>() + o;
+            }
+            HostBlob jb;
+            const size_t o_jobs = jb.put(jobs);
+            ensure(ctx->ws.cw.jobs, jb.size());
+            ctx->ws.stage.copy(ctx->ws.cw.jobs.p, jb, st);
+            const SolveJob* dj = reinterpret_cast<const SolveJob*>(ctx->ws.cw.jobs.as<char>() + o_jobs);
+            const int nj = (int)jobs.size();
+            auto gemms = [&](bool forward) {
+                for (size_t q0 = 0; q0 < jobs.size();) {
+                    size_t q1 = q0;
+                    long rows = 0;
+                    while (q1 < jobs.size() && jobs[q1].f.n == jobs[q0].f.n) {
+                        rows += (long)jobs[q1].R * 2 * jobs[q1].bd.nr;
+                        ++q1;
+                    }
+                    const Fold& f = jobs[q0].f;
+                    const double row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
+                    pr.run("gemm_sine_f64", st, rows * row_flops, 2.0 * rows * (f.n - 1) * 8.0, [&] {
+                        if (forward)
+                            launch_gemm_bd<double>(jobs[q0].A, plans[q0]->Sf64.as<double>(), jobs[q0].B, rows, f, st);
+                        else
+                            launch_gemm_bd<double>(jobs[q0].A, plans[q0]->Si64.as<double>(), jobs[q0].B, rows, f, st);
+                    });
+                    q0 = q1;
+                }
+            };
+            launch_extend_density_jobs(dj, nj, total, max_ng, uo, reinterpret_cast<const double*>(c), st);
+            pr.run("fold_rhs", st, 0.0, rhs_bytes, [&] { launch_fold_rhs_jobs(dj, nj, total, max_w, max_nr, st); });
+            gemms(true);
+            pr.run("tridiag_f64", st, tri_pts * 22.0, tri_pts * 4.0 * 8.0,
+                   [&] { launch_tridiag_jobs(dj, nj, total, max_w, st); });
+            gemms(false);
+            pr.run("unfold_grid", st, 0.0, unfold_bytes,
+                   [&] { launch_unfold_jobs(dj, nj, total, max_n, max_nr, uo, st); });
+            end_call(ctx, st);
+            return MDP_OK;
+        }
         size_t e0 = 0;
         for (const auto& grp : groups) {
             const mdp_projector* Pi = P[grp[0]];

@@ -546,7 +546,8 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
 }
 
 LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, const PackedTables& tb,
-                         const double2* F, double2* x_out, bool want_cond, hipStream_t st, bool* fallback) {
+                         const double2* F, double2* x_out, bool want_cond, hipStream_t st, bool* fallback,
+                         bool reuse) {
     LSResult res{};
     *fallback = false;
     PackedWork& w = ws.pk;
@@ -582,63 +583,65 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     double2* arena = mfr ? w.mf.as<double2>() : nullptr;
 
     MDP_HIP(hipMemsetAsync(fl, 0, sizeof(PackedFlags), st));
-    // packed blocks, equilibrated columns
-    launch_assemble_packed(d, npc, h.max_m, Ap, st);
-    MDP_HIP(hipMemsetAsync(norms2, 0, nc * sizeof(double), st));
-    launch_packed_colnorm2(d, npc, Ap, norms2, st);
-    launch_finalize_norms(nc, norms2, norms, &fl->badcol, st);
-    launch_packed_scale(d, npc, h.max_m, Ap, norms, st);
-    // Gram matrix (multifrontal: the per-subdomain blocks stay apart)
-    if (!mfr) MDP_HIP(hipMemsetAsync(G, 0, nn * sizeof(double2), st));
-    {
-        int max_m = 0;
-        double gram_flops = 0.0, gram_bytes = 0.0;
-        for (int i = 0; i < n_sub; ++i) {
-            max_m = std::max(max_m, h.m[i]);
-            gram_flops += 4.0 * h.m[i] * (double)h.s[i] * (h.s[i] + 1);   // lower half of A_i^* A_i
-            gram_bytes += 16.0 * h.m[i] * (double)h.s[i];
-        }
-        ws.prof.run("gram", st, gram_flops, gram_bytes, [&] {
-            launch_gram_batched(reinterpret_cast<const ZBatch*>(at(tb.zb)), n_sub, h.max_s, max_m, tb.nsplit,
-                                ws.zg.as<double2>(), d.pc_gcol, G, nc, st);
-        });
-    }
     double chol_flops = 0.0;
-    if (!mfr) {
-        chol_flops = cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof,
-                                          h.steps.empty() ? nullptr : &h.steps);
-    } else {
-        // children before parents: assemble every front of one height, then factor the first e columns
-        // of all its fronts together, one batched panel and one batched update launch per 64 columns
-        // (the panel rows below the eliminated block are L21, the trailing update leaves
-        // F22 - L21 L21^* in G(e:, e:))
-        const MFHost& mf = h.mf;
-        const CholBatchEntry* ent = reinterpret_cast<const CholBatchEntry*>(image + tb.mf_steps);
-        size_t si = 0;
-        for (size_t hh = 0; hh < mf.by_height.size(); ++hh) {
-            const std::vector<int>& lv = mf.by_height[hh];
-            int mxf = 0;
-            double abytes = 0.0;
-            for (int v : lv) {
-                const int f = mf.nodes[v].e + mf.nodes[v].b;
-                mxf = std::max(mxf, f);
-                abytes += 32.0 * f * f;
+    if (!reuse) {
+        // packed blocks, equilibrated columns
+        launch_assemble_packed(d, npc, h.max_m, Ap, st);
+        MDP_HIP(hipMemsetAsync(norms2, 0, nc * sizeof(double), st));
+        launch_packed_colnorm2(d, npc, Ap, norms2, st);
+        launch_finalize_norms(nc, norms2, norms, &fl->badcol, st);
+        launch_packed_scale(d, npc, h.max_m, Ap, norms, st);
+        // Gram matrix (multifrontal: the per-subdomain blocks stay apart)
+        if (!mfr) MDP_HIP(hipMemsetAsync(G, 0, nn * sizeof(double2), st));
+        {
+            int max_m = 0;
+            double gram_flops = 0.0, gram_bytes = 0.0;
+            for (int i = 0; i < n_sub; ++i) {
+                max_m = std::max(max_m, h.m[i]);
+                gram_flops += 4.0 * h.m[i] * (double)h.s[i] * (h.s[i] + 1);   // lower half of A_i^* A_i
+                gram_bytes += 16.0 * h.m[i] * (double)h.s[i];
             }
-            if (mf.lzw[hh + 1] > mf.lzw[hh])
-                MDP_HIP(hipMemsetAsync(arena + mf.lzw[hh], 0, (mf.lzw[hh + 1] - mf.lzw[hh]) * sizeof(double2), st));
-            ws.prof.run("mf_assemble", st, 0.0, abytes, [&] {
-                launch_mf_assemble(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)lv.size(), mxf, image,
-                                   ws.zg.as<double2>(), arena, st);
+            ws.prof.run("gram", st, gram_flops, gram_bytes, [&] {
+                launch_gram_batched(reinterpret_cast<const ZBatch*>(at(tb.zb)), n_sub, h.max_s, max_m, tb.nsplit,
+                                    ws.zg.as<double2>(), d.pc_gcol, G, nc, st);
             });
-            for (; si < mf.steps.size() && mf.steps[si].height == (int)hh; ++si) {
-                const MFHost::Step& sp = mf.steps[si];
-                ws.prof.run("chol_panel", st, sp.panel_flops, sp.panel_bytes, [&] {
-                    launch_chol_panel_batched(ent + sp.entry0, sp.count, sp.max_roles, &fl->info, st);
+        }
+        if (!mfr) {
+            chol_flops = cholesky_and_inverse(G, L, Linv, lw.T.as<double2>(), &fl->info, nc, 0.0, st, &ws.prof,
+                                              h.steps.empty() ? nullptr : &h.steps);
+        } else {
+            // children before parents: assemble every front of one height, then factor the first e columns
+            // of all its fronts together, one batched panel and one batched update launch per 64 columns
+            // (the panel rows below the eliminated block are L21, the trailing update leaves
+            // F22 - L21 L21^* in G(e:, e:))
+            const MFHost& mf = h.mf;
+            const CholBatchEntry* ent = reinterpret_cast<const CholBatchEntry*>(image + tb.mf_steps);
+            size_t si = 0;
+            for (size_t hh = 0; hh < mf.by_height.size(); ++hh) {
+                const std::vector<int>& lv = mf.by_height[hh];
+                int mxf = 0;
+                double abytes = 0.0;
+                for (int v : lv) {
+                    const int f = mf.nodes[v].e + mf.nodes[v].b;
+                    mxf = std::max(mxf, f);
+                    abytes += 32.0 * f * f;
+                }
+                if (mf.lzw[hh + 1] > mf.lzw[hh])
+                    MDP_HIP(hipMemsetAsync(arena + mf.lzw[hh], 0, (mf.lzw[hh + 1] - mf.lzw[hh]) * sizeof(double2), st));
+                ws.prof.run("mf_assemble", st, 0.0, abytes, [&] {
+                    launch_mf_assemble(mf_nodes, mf_lists + tb.mf_list_off[hh], (int)lv.size(), mxf, image,
+                                       ws.zg.as<double2>(), arena, st);
                 });
-                ws.prof.run("chol_update", st, sp.update_flops, sp.update_bytes, [&] {
-                    launch_chol_update_batched(ent + sp.entry0, sp.count, sp.max_tiles, st);
-                });
-                chol_flops += sp.panel_flops + sp.update_flops;
+                for (; si < mf.steps.size() && mf.steps[si].height == (int)hh; ++si) {
+                    const MFHost::Step& sp = mf.steps[si];
+                    ws.prof.run("chol_panel", st, sp.panel_flops, sp.panel_bytes, [&] {
+                        launch_chol_panel_batched(ent + sp.entry0, sp.count, sp.max_roles, &fl->info, st);
+                    });
+                    ws.prof.run("chol_update", st, sp.update_flops, sp.update_bytes, [&] {
+                        launch_chol_update_batched(ent + sp.entry0, sp.count, sp.max_tiles, st);
+                    });
+                    chol_flops += sp.panel_flops + sp.update_flops;
+                }
             }
         }
     }
@@ -741,7 +744,7 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     }
     res.passes = 1;
     res.rel_residual = std::sqrt(hf.r2) / (hf.f2 > 0 ? std::sqrt(hf.f2) : 1.0);
-    res.flops = 8.0 * gram_cmacs + chol_flops + n_solves * solve_flops + n_resid * resid_flops;
+    res.flops = (reuse ? 0.0 : 8.0 * gram_cmacs) + chol_flops + n_solves * solve_flops + n_resid * resid_flops;
     launch_scale_cols(x, 1, nc, 1, norms, 1, st);
     if (want_cond) {
         // cond(Qbar_eq)^2 = lambda_max(G) lambda_max(G^{-1}); G v = L (L^* v), G^{-1} v = Linv^* (Linv v)

@@ -98,8 +98,11 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
 // once in the common case (convergence check and residual norms together).
 // Sets *fallback (and returns) when the Cholesky of the Gram matrix breaks
 // down or the refinement does not contract.
+// reuse: the workspaces still hold the equilibrated packed matrix and the Gram factor of the
+// same system (only F differs from the call that built them): assembly and factorisation are skipped.
 LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, const PackedTables& t,
-                         const double2* F, double2* x_out, bool want_cond, hipStream_t st, bool* fallback);
+                         const double2* F, double2* x_out, bool want_cond, hipStream_t st, bool* fallback,
+                         bool reuse = false);
 
 // G^{-1} v with the Gram factor left by the last ls_solve_packed on ws (same h, image and
 // tables; G the Gram matrix of the column-equilibrated packed matrix); out must not alias v.
