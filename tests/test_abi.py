@@ -50,6 +50,9 @@ def test_argument_errors_without_device():
     assert lib.mdp_cheb_points(0, None) == mdp.MDP_ERR_ARG
     assert lib.mdp_set_projector_path(None, 0) == mdp.MDP_ERR_ARG
     assert lib.mdp_cache_clear(None) == mdp.MDP_ERR_ARG
+    assert lib.mdp_set_interface_path(None, 0) == mdp.MDP_ERR_ARG
+    assert lib.mdp_build_projectors(None, 1, None, 8, 0, None, None) == mdp.MDP_ERR_ARG
+    assert lib.mdp_dd_gradient(None, 1, None, None, None, 8, 0, None, None, None, None, None, None) == mdp.MDP_ERR_ARG
 
 
 def test_create_without_device_fails_loudly():
