@@ -131,6 +131,14 @@ void mdp_destroy(mdp_ctx* ctx);
  * (projectors already cached are not rebuilt).  Errors: MDP_ERR_ARG. */
 int mdp_set_projector_path(mdp_ctx* ctx, int path);
 
+/* Autotuning of the sine transform's GEMM (enable != 0): the first GEMM of every
+ * (precision, n, number of rows within a factor of two) times each eligible
+ * tile shape (128x128, 128x64, 64x64 workgroup tiles) on its own operands and
+ * keeps the fastest for later calls; the first call waits for its stream.
+ * The choice is process-wide; results change only by rounding.  Errors:
+ * MDP_ERR_ARG (ctx == NULL). */
+int mdp_set_autotune(mdp_ctx* ctx, int enable);
+
 /* Select the interface least-squares route (mdp_interface_path) of later
  * mdp_solve_interface calls on ctx.  Errors: MDP_ERR_ARG. */
 int mdp_set_interface_path(mdp_ctx* ctx, int path);

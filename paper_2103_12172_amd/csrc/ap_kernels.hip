@@ -123,12 +123,9 @@ fold_rhs_kernel(SrcEval ev, Fold f, int planes, Band bd, T* __restrict__ out) {
 //   U^H y = g:  y_m = conj(r_m) (g_m - conj(s_{m-1}) y_{m-1}),
 //   L^H x = y:  x_n = y_n, x_m = y_m - conj(l_{m+1}) x_{m+1}.
 // y is kept in `out` between the sweeps.  FP64, one column per thread.
-__global__ void __launch_bounds__(256)
-tridiag_adj_kernel(const double* __restrict__ in, int planes_in, double* __restrict__ out,
-                   const double* __restrict__ fac, const double* __restrict__ colc, int n, int W, int R) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (c >= W || b >= R) return;
+__device__ inline void tridiag_adj_body(const double* __restrict__ in, int planes_in, double* __restrict__ out,
+                                        const double* __restrict__ fac, const double* __restrict__ colc, int n, int W,
+                                        int c, int b) {
     const long plane = (long)(n + 1) * W;
     const double* g_re = in + (long)b * planes_in * plane + c;
     const double* g_im = (planes_in == 2) ? g_re + plane : nullptr;
@@ -825,14 +822,6 @@ void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* c
     MDP_HIP(hipGetLastError());
 }
 
-void launch_tridiag_adj(const double* in, int planes_in, double* out, const double* fac, const double* colc, int n,
-                        const Fold& f, int R, hipStream_t st) {
-    check_batch(R);
-    dim3 grid((f.W + 255) / 256, R);
-    hipLaunchKernelGGL(tridiag_adj_kernel, grid, dim3(256), 0, st, in, planes_in, out, fac, colc, n, f.W, R);
-    MDP_HIP(hipGetLastError());
-}
-
 void launch_residual(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, EndRowCoef ec, int R, bool,
                      const float* u32, float* r_out, hipStream_t st) {
     check_batch(R);
@@ -1306,15 +1295,20 @@ tridiag_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs) {
     const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.y)];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= J.f.W) return;
-    tridiag_body<double>(J.B, 2, J.A, J.fac, J.colc, J.f.n, J.f.W, J.bd, c, blockIdx.y - J.b0);
+    if (J.adjoint) tridiag_adj_body(J.B, 2, J.A, J.fac, J.colc, J.f.n, J.f.W, c, blockIdx.y - J.b0);
+    else tridiag_body<double>(J.B, 2, J.A, J.fac, J.colc, J.f.n, J.f.W, J.bd, c, blockIdx.y - J.b0);
 }
 
 __global__ void unfold_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs, double* grids) {
     const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.z)];
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q > J.f.n || (int)blockIdx.y >= J.bd.nr) return;
-    unfold_body<double>(J.B, nullptr, J.f, J.bd, -1.0, grids, 0, grids, 0, J.src.goff, J.bd.r0 + blockIdx.y, q,
-                        blockIdx.z - J.b0);
+    if (J.out)   // the solution itself into separate grids
+        unfold_body<double>(J.B, nullptr, J.f, J.bd, 1.0, nullptr, 0, J.out, 0, J.ooff, J.bd.r0 + blockIdx.y, q,
+                            blockIdx.z - J.b0);
+    else         // w - u in place
+        unfold_body<double>(J.B, nullptr, J.f, J.bd, -1.0, grids, 0, grids, 0, J.src.goff, J.bd.r0 + blockIdx.y, q,
+                            blockIdx.z - J.b0);
 }
 
 }  // namespace

@@ -243,34 +243,6 @@ static void solve_batch_t(const APPlan& P, Workspace& ws, const SrcDesc& src, bo
     consume(B, du, bd);
 }
 
-void solve_batch_adjoint(const APPlan& P, Workspace& ws, const SrcDesc& src, bool src_cplx, int R,
-                         const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st) {
-    if (R <= 0) return;
-    // A^{-H} = S T^{-H} (2/n) S: the forward transform, the conjugate-transposed mode solves, the synthesis
-    const Fold& f = P.f;
-    const int n = P.n;
-    const Band bd{0, n + 1};
-    const size_t elems = (size_t)R * 2 * (n + 1) * f.W;
-    ws.a.reserve(elems * sizeof(double));
-    ws.b.reserve(elems * sizeof(double));
-    double* A = ws.a.as<double>();
-    double* B = ws.b.as<double>();
-    const int pin = src_cplx ? 2 : 1;
-    Profiler& pr = ws.prof;
-    const double useful = (double)(n - 1);
-    const double gemm_row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
-    const double rows_in = (double)R * pin * (n + 1), rows_c = (double)R * 2 * (n + 1);
-    pr.run("fold_rhs", st, 0.0, rows_in * useful * 8.0,
-           [&] { launch_fold_rhs<double>(src, n, f, P.sc, R, src_cplx, bd, A, st); });
-    pr.run("gemm_sine_f64", st, rows_in * gemm_row_flops, 2.0 * rows_in * useful * 8.0,
-           [&] { launch_gemm_bd<double>(A, P.Sf64.as<double>(), B, (long)R * pin * (n + 1), f, st); });
-    pr.run("tridiag_adj", st, (double)R * (n + 1) * useful * 22.0, (double)R * (n + 1) * useful * (pin + 4) * 8.0,
-           [&] { launch_tridiag_adj(B, pin, A, P.fac64.as<double>(), P.colc64.as<double>(), n, f, R, st); });
-    pr.run("gemm_sine_f64", st, rows_c * gemm_row_flops, 2.0 * rows_c * useful * 8.0,
-           [&] { launch_gemm_bd<double>(A, P.Si64.as<double>(), B, (long)R * 2 * (n + 1), f, st); });
-    consume(B, nullptr, bd);
-}
-
 int chunk_size(const APPlan& P, int precision, size_t cap_bytes, int R) {
     const size_t elem = (precision == MDP_C128) ? 8 : 4;
     const size_t per_rhs = 2 * (size_t)(P.n + 1) * P.f.W * elem * (precision == MDP_C64_REFINED ? 3 : 2);

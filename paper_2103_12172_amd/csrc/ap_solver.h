@@ -66,9 +66,4 @@ int chunk_size(const APPlan& P, int precision, size_t cap_bytes, int R);
 void solve_batch(const APPlan& P, Workspace& ws, int precision, const SrcDesc& src, bool src_cplx, int R, Band bd,
                  const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st);
 
-// The conjugate-transposed solve A^{-H} (all n+1 rows, FP64) of R right-hand sides from
-// `src` (GRID or GRID_ALL); consume as for solve_batch.
-void solve_batch_adjoint(const APPlan& P, Workspace& ws, const SrcDesc& src, bool src_cplx, int R,
-                         const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st);
-
 }  // namespace mdp

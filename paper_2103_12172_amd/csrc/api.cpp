@@ -362,6 +362,70 @@ void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
     }
 }
 
+// Band solves of several plans' entries in one launch per stage: jobs in order of n (their
+// A and B regions are assigned here, back to back, so one sine GEMM per n covers a run of
+// jobs), job.b0 set by the caller.  Fold (job.src), forward GEMMs, mode solves (or their
+// conjugate transposes), inverse GEMMs, unfold into job.out or in place (w - u into `grids`).
+void batched_band_solve(mdp_ctx* ctx, std::vector<SolveJob>& jobs, const std::vector<const APPlan*>& plans,
+                        double* grids, hipStream_t st) {
+    if (jobs.empty()) return;
+    Profiler& pr = ctx->ws.prof;
+    size_t elems = 0;
+    int total = 0, max_w = 0, max_nr = 0, max_n = 0;
+    double rhs_bytes = 0.0, tri_pts = 0.0, unfold_bytes = 0.0;
+    for (SolveJob& J : jobs) {
+        J.A = reinterpret_cast<double*>(elems);   // offsets for now
+        elems += (size_t)J.R * 2 * J.bd.nr * J.f.W;
+        total += J.R;
+        max_w = std::max(max_w, J.f.W);
+        max_nr = std::max(max_nr, J.bd.nr);
+        max_n = std::max(max_n, J.f.n);
+        rhs_bytes += (double)J.R * 2 * J.bd.nr * (J.f.n - 1) * 8.0;
+        tri_pts += (double)J.R * J.bd.nr * (J.f.n - 1);
+        unfold_bytes += (double)J.R * J.bd.nr * (J.f.n + 1) * 16.0 * 3.0;
+    }
+    if (elems * sizeof(double) > ctx->ws.a.bytes || elems * sizeof(double) > ctx->ws.b.bytes) {
+        MDP_HIP(hipDeviceSynchronize());
+        ctx->ws.a.reserve(elems * sizeof(double));
+        ctx->ws.b.reserve(elems * sizeof(double));
+    }
+    for (SolveJob& J : jobs) {
+        const size_t o = reinterpret_cast<size_t>(J.A);
+        J.A = ctx->ws.a.as<double>() + o;
+        J.B = ctx->ws.b.as<double>() + o;
+    }
+    HostBlob jb;
+    const size_t o_jobs = jb.put(jobs);
+    ensure(ctx->ws.cw.jobs, jb.size());
+    ctx->ws.stage.copy(ctx->ws.cw.jobs.p, jb, st);
+    const SolveJob* dj = reinterpret_cast<const SolveJob*>(ctx->ws.cw.jobs.as<char>() + o_jobs);
+    const int nj = (int)jobs.size();
+    auto gemms = [&](bool forward) {
+        for (size_t q0 = 0; q0 < jobs.size();) {
+            size_t q1 = q0;
+            long rows = 0;
+            while (q1 < jobs.size() && jobs[q1].f.n == jobs[q0].f.n) {
+                rows += (long)jobs[q1].R * 2 * jobs[q1].bd.nr;
+                ++q1;
+            }
+            const Fold& f = jobs[q0].f;
+            const double row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
+            pr.run("gemm_sine_f64", st, rows * row_flops, 2.0 * rows * (f.n - 1) * 8.0, [&] {
+                launch_gemm_bd<double>(jobs[q0].A, (forward ? plans[q0]->Sf64 : plans[q0]->Si64).as<double>(),
+                                       jobs[q0].B, rows, f, st);
+            });
+            q0 = q1;
+        }
+    };
+    pr.run("fold_rhs", st, 0.0, rhs_bytes, [&] { launch_fold_rhs_jobs(dj, nj, total, max_w, max_nr, st); });
+    gemms(true);
+    const bool adj = jobs[0].adjoint != 0;
+    pr.run(adj ? "tridiag_adj" : "tridiag_f64", st, tri_pts * 22.0, tri_pts * 4.0 * 8.0,
+           [&] { launch_tridiag_jobs(dj, nj, total, max_w, st); });
+    gemms(false);
+    pr.run("unfold_grid", st, 0.0, unfold_bytes, [&] { launch_unfold_jobs(dj, nj, total, max_n, max_nr, grids, st); });
+}
+
 }  // namespace
 
 extern "C" {
@@ -408,6 +472,12 @@ int mdp_set_projector_path(mdp_ctx* ctx, int path) {
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
     if (path != MDP_PATH_AUTO && path != MDP_PATH_DENSE) return fail(ctx, MDP_ERR_ARG, "unknown projector path");
     ctx->projector_path = path;
+    return MDP_OK;
+}
+
+int mdp_set_autotune(mdp_ctx* ctx, int enable) {
+    if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
+    set_gemm_autotune(enable);
     return MDP_OK;
 }
 
@@ -1103,13 +1173,11 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
         if (P[i]->precision != MDP_C128) throw Error(MDP_ERR_ARG, "gradient: projectors must be complex128");
     // grid offsets (complex elements) of every subdomain in the ubar and lambda grids
     std::vector<long> goff(n_sub + 1, 0);
-    int max_n = 0, max_ng = 0;
+    int max_ng = 0;
     for (int i = 0; i < n_sub; ++i) {
         goff[i + 1] = goff[i] + (long)(P[i]->g.n + 1) * (P[i]->g.n + 1);
-        max_n = std::max(max_n, P[i]->g.n);
         max_ng = std::max(max_ng, P[i]->g.n_gamma);
     }
-    const long max_grid = (long)(max_n + 1) * (max_n + 1);
     // receivers: values summed per node, grouped by subdomain
     std::map<std::pair<int, int>, double2> acc;
     for (int t = 0; t < ga.n_rcv; ++t) {
@@ -1159,23 +1227,48 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
     const size_t o_roff = blob.put(r_off_all), o_rnode = blob.put(r_node), o_rval = blob.put(r_val),
                  o_goff = blob.put(goff), o_kq = blob.put(kq), o_krows = blob.put(krows), o_kcol = blob.put(kcolv),
                  o_keidx = blob.put(keidx), o_kroff = blob.put(kroff), o_kdiv = blob.put(kdiv);
-    std::vector<long> two{0, max_grid};
-    const size_t o_two = blob.put(two);
     std::vector<int> one_idx(n_sub);
     for (int i = 0; i < n_sub; ++i) one_idx[i] = i;
     const size_t o_idx = blob.put(one_idx);
-    // device buffers: grids ubar, lambda (all subdomains); JVP scratch (w, dw, v, h, y: 2 entries each of the
-    // largest grid); dE; wbar; vectors
+    // subdomains in order of n (the batched solves' GEMMs go per n)
+    std::vector<int> ord(n_sub);
+    for (int i = 0; i < n_sub; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return P[a]->g.n < P[b]->g.n; });
+    // JVP grids: two entries per subdomain (densities c and cz) at goff2[2i + e]; dE per subdomain at de_off[i];
+    // the two coefficient sets [c | cz] side by side (entry (i, e) reads vector i + e n_sub)
+    std::vector<long> goff2(2 * n_sub), de_off(n_sub + 1, 0);
+    std::vector<int> cidx2(2 * n_sub);
+    for (int i = 0; i < n_sub; ++i) {
+        const long gs = (long)(P[i]->g.n + 1) * (P[i]->g.n + 1);
+        goff2[2 * i] = 2 * goff[i];
+        goff2[2 * i + 1] = 2 * goff[i] + gs;
+        cidx2[2 * i] = i;
+        cidx2[2 * i + 1] = n_sub + i;
+        de_off[i + 1] = de_off[i] + (long)P[i]->g.n_gamma * ncol;
+    }
+    // the job-table form of these index arrays follows the job order (ord)
+    std::vector<long> goff2_o, goff_o;
+    std::vector<int> cidx2_o;
+    for (int i : ord) {
+        goff2_o.push_back(goff2[2 * i]);
+        goff2_o.push_back(goff2[2 * i + 1]);
+        cidx2_o.push_back(cidx2[2 * i]);
+        cidx2_o.push_back(cidx2[2 * i + 1]);
+        goff_o.push_back(goff[i]);
+    }
+    const size_t o_g2 = blob.put(goff2_o), o_c2 = blob.put(cidx2_o), o_go = blob.put(goff_o),
+                 o_g2s = blob.put(goff2);
+    // device buffers: grids ubar, lambda; JVP grids w, dw, v, h, y (two per subdomain); dE; wbar; vectors
     CallWork& cw = ctx->ws.cw;
     const long gtot = goff[n_sub];
     size_t off = 0;
     auto take = [&](size_t elems) { const size_t o = off; off += (elems + 15) / 16 * 16; return o; };
-    const size_t b_ubar = take(gtot), b_lam = take(gtot), b_w = take(2 * max_grid), b_dw = take(2 * max_grid),
-                 b_v = take(2 * max_grid), b_h = take(2 * max_grid), b_y = take(2 * max_grid),
-                 b_dE = take(((size_t)max_ng * ncol + 1) / 2), b_wbar = take(max_ng), b_cbar = take(nce),
-                 b_cz = take(nce), b_zero = take(nce), b_xbar = take(nc), b_xs = take(nc), b_zs = take(nc),
-                 b_z = take(nc), b_Fbb = take(m_rows), b_r = take(m_rows), b_k = take(n_sub), b_dg = take(nk),
-                 b_tab = take((blob.size() + 15) / 16);
+    const size_t b_ubar = take(gtot), b_lam = take(gtot), b_w = take(2 * gtot), b_dw = take(2 * gtot),
+                 b_v = take(2 * gtot), b_h = take(2 * gtot), b_y = take(2 * gtot),
+                 b_dE = take(((size_t)de_off[n_sub] + 1) / 2), b_wbar = take(max_ng), b_cbar = take(nce),
+                 b_cc = take(2 * (size_t)nce), b_zero = take(nce), b_xbar = take(nc), b_xs = take(nc),
+                 b_zs = take(nc), b_z = take(nc), b_Fbb = take(m_rows), b_r = take(m_rows), b_k = take(n_sub),
+                 b_dg = take(nk), b_tab = take((blob.size() + 15) / 16);
     ensure(cw.grad, off * sizeof(double2));
     double2* G0 = cw.grad.as<double2>();
     auto at = [&](size_t o) { return G0 + o; };
@@ -1183,8 +1276,11 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
     ctx->ws.stage.copy(tab, blob, st);
     auto T = [&](size_t o) { return tab + o; };
     const long* d_goff = reinterpret_cast<const long*>(T(o_goff));
-    const long* d_two = reinterpret_cast<const long*>(T(o_two));
     const int* d_idx = reinterpret_cast<const int*>(T(o_idx));
+    const long* d_g2 = reinterpret_cast<const long*>(T(o_g2));
+    const int* d_c2 = reinterpret_cast<const int*>(T(o_c2));
+    const long* d_go = reinterpret_cast<const long*>(T(o_go));
+    const long* d_g2s = reinterpret_cast<const long*>(T(o_g2s));   // subdomain order
     double* ubar = reinterpret_cast<double*>(at(b_ubar));
     double* lam = reinterpret_cast<double*>(at(b_lam));
     Profiler& pr = ctx->ws.prof;
@@ -1192,30 +1288,44 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
     MDP_HIP(hipMemsetAsync(ubar, 0, (size_t)gtot * sizeof(double2), st));
     launch_scatter_values(reinterpret_cast<const long*>(T(o_roff)), reinterpret_cast<const double*>(T(o_rval)),
                           (int)r_val.size(), ubar, st);
-    // (2) per subdomain: lambda = A^{-H} ubar, wbar on gamma, cbar = E^T wbar
+    // (2) lambda = A^{-H} ubar for every subdomain in one batched solve; then per subdomain wbar on gamma
+    // and cbar = E^T wbar
+    std::vector<const APPlan*> plans(n_sub);
+    for (int i = 0; i < n_sub; ++i) plans[i] = &get_plan(ctx, P[i]->g.n, P[i]->g.h, P[i]->k);
+    {
+        std::vector<SolveJob> jobs;
+        std::vector<const APPlan*> jp;
+        for (int q = 0; q < n_sub; ++q) {
+            const int i = ord[q];
+            const APPlan& plan = *plans[i];
+            SolveJob J{};
+            J.src.kind = Src::GRID;
+            J.src.grid = ubar;
+            J.src.goff = d_go + q;
+            J.sc = plan.sc;
+            J.f = plan.f;
+            J.bd = Band{0, plan.n + 1};
+            J.b0 = q;
+            J.R = 1;
+            J.fac = plan.fac64.as<double>();
+            J.colc = plan.colc64.as<double>();
+            J.adjoint = 1;
+            J.out = lam;
+            J.ooff = d_go + q;
+            jobs.push_back(J);
+            jp.push_back(&plan);
+        }
+        batched_band_solve(ctx, jobs, jp, nullptr, st);
+    }
     double2* cbar = at(b_cbar);
     for (int i = 0; i < n_sub; ++i) {
         const mdp_projector* Pi = P[i];
         const Geometry& G = Pi->g;
-        const int n = G.n, ng = G.n_gamma;
-        APPlan& plan = get_plan(ctx, n, G.h, Pi->k);
-        SrcDesc src{};
-        src.kind = Src::GRID;
-        src.grid = ubar;
-        src.goff = d_goff + i;
-        const Fold f = plan.f;
-        prepare_ws(ctx, plan, MDP_C128, 1);
-        solve_batch_adjoint(plan, ctx->ws, src, true, 1,
-                            [&](const void* u, const float*, Band bd) {
-                                launch_unfold_grid<double>((const double*)u, nullptr, n, f, bd, bd, 1, nullptr, 0, lam,
-                                                           0, d_goff + i, st);
-                            },
-                            st);
         pr.run("adjoint", st, 0.0, 0.0, [&] {
-            launch_gamma_adjoint(ubar, lam, d_goff + i, 1, n, plan.sc, G.m_lo, G.m_hi, G.q_lo, G.q_hi, Pi->gm, Pi->gq,
-                                 ng, reinterpret_cast<double*>(at(b_wbar)), 0, st);
-            launch_et_apply(Pi->E.as<double>(), ng, ncol, reinterpret_cast<const double*>(at(b_wbar)), 0, 1, d_idx + i,
-                            reinterpret_cast<double*>(cbar), st);
+            launch_gamma_adjoint(ubar, lam, d_goff + i, 1, G.n, plans[i]->sc, G.m_lo, G.m_hi, G.q_lo, G.q_hi,
+                                 Pi->gm, Pi->gq, G.n_gamma, reinterpret_cast<double*>(at(b_wbar)), 0, st);
+            launch_et_apply(Pi->E.as<double>(), G.n_gamma, ncol, reinterpret_cast<const double*>(at(b_wbar)), 0, 1,
+                            d_idx + i, reinterpret_cast<double*>(cbar), st);
         });
     }
     // (3) xbar = K^* cbar; z = D^{-1} G^{-1} D^{-1} xbar (column equilibration D of the packed matrix)
@@ -1256,12 +1366,14 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
                      reinterpret_cast<const int*>(T(o_kcol)), reinterpret_cast<const long*>(T(o_kroff)),
                      reinterpret_cast<const int*>(T(o_keidx)), reinterpret_cast<const double*>(T(o_kdiv)), cbar, Fbb,
                      dg, st);
-    // (6) cz = K z (no known part)
-    double2* cz = at(b_cz);
+    // (6) the two density sets side by side: [c | cz], cz = K z (no known part)
+    double2* cc = at(b_cc);
     double2* zero = at(b_zero);
+    MDP_HIP(hipMemcpyAsync(cc, c_full, (size_t)nce * sizeof(double2), hipMemcpyDeviceToDevice, st));
     MDP_HIP(hipMemsetAsync(zero, 0, (size_t)nce * sizeof(double2), st));
-    launch_expand_coeffs(nce, esrc, ecoef, zero, z, cz, st);
-    // (7) k^2 of every subdomain: two JVP densities (c_full, cz)
+    launch_expand_coeffs(nce, esrc, ecoef, zero, z, cc + nce, st);
+    // (7) k^2 of every subdomain, both densities of all subdomains in the same launches:
+    //     w = E c, dw = dE c; v = A^{-1}(L w|M+); h = -dA v + (dL w + L dw)|M+; y = A^{-1} h
     double* W = reinterpret_cast<double*>(at(b_w));
     double* DW = reinterpret_cast<double*>(at(b_dw));
     double* V = reinterpret_cast<double*>(at(b_v));
@@ -1270,50 +1382,73 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
     double* dE = reinterpret_cast<double*>(at(b_dE));
     double2* kres = at(b_k);
     const StencilCoef dsc{2.0 / 3.0, 1.0 / 12.0, 0.0};
-    for (int i = 0; i < n_sub; ++i) {
-        const mdp_projector* Pi = P[i];
-        const Geometry& G = Pi->g;
-        const int n = G.n, ng = G.n_gamma;
-        APPlan& plan = get_plan(ctx, n, G.h, Pi->k);
-        const Fold f = plan.f;
-        MDP_HIP(hipMemsetAsync(dE, 0, (size_t)ng * ncol * sizeof(double), st));
-        launch_extension(Pi->gside, Pi->grho, Pi->gt, Pi->gslen, ng, Pi->k, M, dE, st, 1);
-        MDP_HIP(hipMemsetAsync(W, 0, (size_t)2 * max_grid * sizeof(double2), st));
-        MDP_HIP(hipMemsetAsync(DW, 0, (size_t)2 * max_grid * sizeof(double2), st));
-        for (int e = 0; e < 2; ++e) {
-            const double* cv = reinterpret_cast<const double*>(e == 0 ? c_full : cz);
-            launch_extend_density(Pi->E.as<double>(), ng, ncol, cv, d_idx + i, 1, Pi->gm, Pi->gq, Pi->gside, n, W, 0,
-                                  d_two + e, st);
-            launch_extend_density(dE, ng, ncol, cv, d_idx + i, 1, Pi->gm, Pi->gq, Pi->gside, n, DW, 0, d_two + e, st);
+    MDP_HIP(hipMemsetAsync(dE, 0, (size_t)de_off[n_sub] * sizeof(double), st));
+    MDP_HIP(hipMemsetAsync(W, 0, (size_t)2 * gtot * sizeof(double2), st));
+    MDP_HIP(hipMemsetAsync(DW, 0, (size_t)2 * gtot * sizeof(double2), st));
+    for (int i = 0; i < n_sub; ++i)
+        launch_extension(P[i]->gside, P[i]->grho, P[i]->gt, P[i]->gslen, P[i]->g.n_gamma, P[i]->k, M, dE + de_off[i],
+                         st, 1);
+    auto jvp_jobs = [&](Src kind, const double* grid, double* out, bool density_dE) {
+        std::vector<SolveJob> jobs;
+        std::vector<const APPlan*> jp;
+        for (int q = 0; q < n_sub; ++q) {
+            const int i = ord[q];
+            const mdp_projector* Pi = P[i];
+            const Geometry& G = Pi->g;
+            const APPlan& plan = *plans[i];
+            SolveJob J{};
+            J.src.kind = kind;
+            J.src.grid = grid;
+            J.src.goff = d_g2 + 2 * q;
+            J.src.m_lo = G.m_lo; J.src.m_hi = G.m_hi; J.src.q_lo = G.q_lo; J.src.q_hi = G.q_hi;
+            J.sc = plan.sc;
+            J.f = plan.f;
+            J.bd = Band{0, plan.n + 1};
+            J.b0 = 2 * q;
+            J.R = 2;
+            J.fac = plan.fac64.as<double>();
+            J.colc = plan.colc64.as<double>();
+            J.E = density_dE ? dE + de_off[i] : Pi->E.as<double>();
+            J.ng = G.n_gamma;
+            J.ncol = ncol;
+            J.gm = Pi->gm; J.gq = Pi->gq; J.gside = Pi->gside;
+            J.cidx = d_c2 + 2 * q;
+            J.out = out;
+            J.ooff = d_g2 + 2 * q;
+            jobs.push_back(J);
+            jp.push_back(&plan);
         }
-        prepare_ws(ctx, plan, MDP_C128, 2);
-        SrcDesc sv{};
-        sv.kind = Src::STENCIL_GRID;
-        sv.grid = W;
-        sv.goff = d_two;
-        sv.m_lo = G.m_lo; sv.m_hi = G.m_hi; sv.q_lo = G.q_lo; sv.q_hi = G.q_hi;
-        const Band full{0, n + 1};
-        solve_batch(plan, ctx->ws, MDP_C128, sv, true, 2, full,
-                    [&](const void* u, const float*, Band bd) {
-                        launch_unfold_grid<double>((const double*)u, nullptr, n, f, bd, bd, 2, nullptr, 0, V, 0, d_two,
-                                                   st);
-                    },
-                    st);
-        launch_jvp_rhs(V, W, DW, d_two, 2, n, G.h, Pi->k, plan.sc, dsc, G.m_lo, G.m_hi, G.q_lo, G.q_hi, H, st);
-        SrcDesc sh{};
-        sh.kind = Src::GRID_ALL;
-        sh.grid = H;
-        sh.goff = d_two;
-        solve_batch(plan, ctx->ws, MDP_C128, sh, true, 2, full,
-                    [&](const void* u, const float*, Band bd) {
-                        launch_unfold_grid<double>((const double*)u, nullptr, n, f, bd, bd, 2, nullptr, 0, Y, 0, d_two,
-                                                   st);
-                    },
-                    st);
+        return std::make_pair(jobs, jp);
+    };
+    // densities w (E) and dw (dE) of both coefficient sets
+    for (int which = 0; which < 2; ++which) {
+        auto jj = jvp_jobs(Src::STENCIL_GRID, nullptr, nullptr, which == 1);
+        HostBlob jb;
+        const size_t o_j = jb.put(jj.first);
+        ensure(cw.jobs, jb.size());
+        ctx->ws.stage.copy(cw.jobs.p, jb, st);
+        launch_extend_density_jobs(reinterpret_cast<const SolveJob*>(cw.jobs.as<char>() + o_j), n_sub, 2 * n_sub,
+                                   max_ng, which == 0 ? W : DW, reinterpret_cast<const double*>(cc), st);
+    }
+    {
+        auto jj = jvp_jobs(Src::STENCIL_GRID, W, V, false);
+        batched_band_solve(ctx, jj.first, jj.second, nullptr, st);
+    }
+    for (int i = 0; i < n_sub; ++i) {
+        const Geometry& G = P[i]->g;
+        launch_jvp_rhs(V, W, DW, d_g2s + 2 * i, 2, G.n, G.h, P[i]->k, plans[i]->sc, dsc, G.m_lo, G.m_hi, G.q_lo,
+                       G.q_hi, H, st);
+    }
+    {
+        auto jj = jvp_jobs(Src::GRID_ALL, H, Y, false);
+        batched_band_solve(ctx, jj.first, jj.second, nullptr, st);
+    }
+    for (int i = 0; i < n_sub; ++i) {
+        const Geometry& G = P[i]->g;
         const int r0 = r_first[i], rc = r_first[i + 1] - r_first[i];
-        launch_kappa_dot(Y, Y + 2 * max_grid, DW, Pi->gm, Pi->gq, ng, n, Fbb, r, row_off[i],
-                         reinterpret_cast<const long*>(T(o_rnode)) + r0, reinterpret_cast<const double*>(T(o_rval)) + 2 * r0,
-                         rc, kres + i, st);
+        launch_kappa_dot(Y + 2 * goff2[2 * i], Y + 2 * goff2[2 * i + 1], DW + 2 * goff2[2 * i], P[i]->gm, P[i]->gq,
+                         G.n_gamma, G.n, Fbb, r, row_off[i], reinterpret_cast<const long*>(T(o_rnode)) + r0,
+                         reinterpret_cast<const double*>(T(o_rval)) + 2 * r0, rc, kres + i, st);
     }
     // (8) results to the host
     std::vector<double2> hk(n_sub), hd(nk);
@@ -1412,17 +1547,14 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
         MDP_HIP(hipMemsetAsync(u_out, 0, (size_t)off[n_sub] * sizeof(mdp_c128), st));
         double* uo = reinterpret_cast<double*>(u_out);
         if (batched) {
-            Profiler& pr = ctx->ws.prof;
             std::vector<SolveJob> jobs;
             std::vector<const APPlan*> plans;
-            size_t elems = 0, e = 0;
-            int total = 0, max_ng = 0, max_w = 0, max_nr = 0, max_n = 0;
-            double rhs_bytes = 0.0, tri_pts = 0.0, unfold_bytes = 0.0;
+            size_t e = 0;
+            int total = 0, max_ng = 0;
             for (const auto& grp : groups) {
                 const mdp_projector* Pi = P[grp[0]];
                 const Geometry& G = Pi->g;
                 const APPlan& plan = get_plan(ctx, G.n, G.h, Pi->k);
-                const Band bd = box_band(plan, G);
                 SolveJob J{};
                 J.src.kind = Src::STENCIL_GRID;
                 J.src.grid = uo;
@@ -1430,10 +1562,9 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
                 J.src.m_lo = G.m_lo; J.src.m_hi = G.m_hi; J.src.q_lo = G.q_lo; J.src.q_hi = G.q_hi;
                 J.sc = plan.sc;
                 J.f = plan.f;
-                J.bd = bd;
+                J.bd = box_band(plan, G);
                 J.b0 = total;
                 J.R = (int)grp.size();
-                J.A = reinterpret_cast<double*>(elems);   // offsets for now, pointers below
                 J.fac = plan.fac64.as<double>();
                 J.colc = plan.colc64.as<double>();
                 J.E = Pi->E.as<double>();
@@ -1443,60 +1574,20 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
                 J.cidx = reinterpret_cast<const int*>(img + o_cidx) + e;
                 jobs.push_back(J);
                 plans.push_back(&plan);
-                elems += (size_t)J.R * 2 * bd.nr * plan.f.W;
                 total += J.R;
                 e += grp.size();
                 max_ng = std::max(max_ng, G.n_gamma);
-                max_w = std::max(max_w, plan.f.W);
-                max_nr = std::max(max_nr, bd.nr);
-                max_n = std::max(max_n, G.n);
-                rhs_bytes += (double)J.R * 2 * bd.nr * (G.n - 1) * 8.0;
-                tri_pts += (double)J.R * bd.nr * (G.n - 1);
-                unfold_bytes += (double)J.R * bd.nr * (G.n + 1) * 16.0 * 3.0;
             }
-            if (elems * sizeof(double) > ctx->ws.a.bytes || elems * sizeof(double) > ctx->ws.b.bytes) {
-                MDP_HIP(hipDeviceSynchronize());
-                ctx->ws.a.reserve(elems * sizeof(double));
-                ctx->ws.b.reserve(elems * sizeof(double));
+            // the densities first (the table goes up with the solve's; the density step reads the same fields)
+            {
+                HostBlob jb;
+                const size_t o_j = jb.put(jobs);
+                ensure(ctx->ws.cw.jobs, jb.size());
+                ctx->ws.stage.copy(ctx->ws.cw.jobs.p, jb, st);
+                launch_extend_density_jobs(reinterpret_cast<const SolveJob*>(ctx->ws.cw.jobs.as<char>() + o_j),
+                                           (int)jobs.size(), total, max_ng, uo, reinterpret_cast<const double*>(c), st);
             }
-            for (SolveJob& J : jobs) {
-                const size_t o = reinterpret_cast<size_t>(J.A);
-                J.A = ctx->ws.a.as<double>() + o;
-                J.B = ctx->ws.b.as<double>() + o;
-            }
-            HostBlob jb;
-            const size_t o_jobs = jb.put(jobs);
-            ensure(ctx->ws.cw.jobs, jb.size());
-            ctx->ws.stage.copy(ctx->ws.cw.jobs.p, jb, st);
-            const SolveJob* dj = reinterpret_cast<const SolveJob*>(ctx->ws.cw.jobs.as<char>() + o_jobs);
-            const int nj = (int)jobs.size();
-            auto gemms = [&](bool forward) {
-                for (size_t q0 = 0; q0 < jobs.size();) {
-                    size_t q1 = q0;
-                    long rows = 0;
-                    while (q1 < jobs.size() && jobs[q1].f.n == jobs[q0].f.n) {
-                        rows += (long)jobs[q1].R * 2 * jobs[q1].bd.nr;
-                        ++q1;
-                    }
-                    const Fold& f = jobs[q0].f;
-                    const double row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
-                    pr.run("gemm_sine_f64", st, rows * row_flops, 2.0 * rows * (f.n - 1) * 8.0, [&] {
-                        if (forward)
-                            launch_gemm_bd<double>(jobs[q0].A, plans[q0]->Sf64.as<double>(), jobs[q0].B, rows, f, st);
-                        else
-                            launch_gemm_bd<double>(jobs[q0].A, plans[q0]->Si64.as<double>(), jobs[q0].B, rows, f, st);
-                    });
-                    q0 = q1;
-                }
-            };
-            launch_extend_density_jobs(dj, nj, total, max_ng, uo, reinterpret_cast<const double*>(c), st);
-            pr.run("fold_rhs", st, 0.0, rhs_bytes, [&] { launch_fold_rhs_jobs(dj, nj, total, max_w, max_nr, st); });
-            gemms(true);
-            pr.run("tridiag_f64", st, tri_pts * 22.0, tri_pts * 4.0 * 8.0,
-                   [&] { launch_tridiag_jobs(dj, nj, total, max_w, st); });
-            gemms(false);
-            pr.run("unfold_grid", st, 0.0, unfold_bytes,
-                   [&] { launch_unfold_jobs(dj, nj, total, max_n, max_nr, uo, st); });
+            batched_band_solve(ctx, jobs, plans, uo, st);
             end_call(ctx, st);
             return MDP_OK;
         }

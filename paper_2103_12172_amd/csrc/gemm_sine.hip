@@ -18,6 +18,11 @@
 // M tile run on the same XCD and share the A rows in that XCD's L2.
 #include <type_traits>
 
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "mdp_internal.h"
 
 namespace mdp {
@@ -196,7 +201,59 @@ void launch_cfg(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t
     MDP_HIP(hipGetLastError());
 }
 
+// Tile shapes: 0 = 128 x 128, 1 = 128 x 64, 2 = 64 x 64.
+template <class T>
+void launch_shape(int shape, const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st) {
+    if (shape == 0) launch_cfg<T, 128, 128, 2, 2>(A, B, C, M, f, st);
+    else if (shape == 1) launch_cfg<T, 128, 64, 4, 1>(A, B, C, M, f, st);
+    else launch_cfg<T, 64, 64, 2, 2>(A, B, C, M, f, st);
+}
+
+// Autotuner: the tile shape of every (precision, n, rows within a factor of two), picked at
+// first use by timing each eligible shape on the call's own operands (3 launches each after
+// one warm-up, HIP events on the call's stream; the chosen shape runs last, so C holds its
+// product).  The shapes block the same sums differently: results agree to rounding.
+std::atomic<int> g_autotune{0};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tuned;
+
+template <class T>
+int tuned_shape(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st, int fallback) {
+    const bool wide = f.P1 % 128 == 0 && f.P2 % 128 == 0;
+    if (!wide) return 2;
+    int lg = 0;
+    while ((2L << lg) <= M) ++lg;
+    const auto key = std::make_tuple((int)sizeof(T), f.n, lg);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) return it->second;
+    }
+    hipEvent_t e0, e1;
+    MDP_HIP(hipEventCreate(&e0));
+    MDP_HIP(hipEventCreate(&e1));
+    int best = fallback;
+    float best_ms = 1e30f;
+    for (int shape = 0; shape < 3; ++shape) {
+        launch_shape<T>(shape, A, B, C, M, f, st);
+        MDP_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r) launch_shape<T>(shape, A, B, C, M, f, st);
+        MDP_HIP(hipEventRecord(e1, st));
+        MDP_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        MDP_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = shape; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[key] = best;
+    return best;
+}
+
 }  // namespace
+
+void set_gemm_autotune(int on) { g_autotune.store(on ? 1 : 0); }
 
 template <class T>
 void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st) {
@@ -204,12 +261,9 @@ void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStre
     // 128 x 128 tiles when they give enough workgroups to fill the chip (256 CUs), 64 x 64 otherwise
     // (short batches: a few thousand rows)
     const long big = ((M + 127) / 128) * (f.W / 128);
-    if (f.P1 % 128 == 0 && f.P2 % 128 == 0 && big >= 512)
-        launch_cfg<T, 128, 128, 2, 2>(A, B, C, M, f, st);
-    else if (f.P1 % 128 == 0 && f.P2 % 128 == 0 && big >= 256)
-        launch_cfg<T, 128, 64, 4, 1>(A, B, C, M, f, st);
-    else
-        launch_cfg<T, 64, 64, 2, 2>(A, B, C, M, f, st);
+    const bool wide = f.P1 % 128 == 0 && f.P2 % 128 == 0;
+    const int shape = (wide && big >= 512) ? 0 : (wide && big >= 256) ? 1 : 2;
+    launch_shape<T>(g_autotune.load() ? tuned_shape<T>(A, B, C, M, f, st, shape) : shape, A, B, C, M, f, st);
 }
 
 template void launch_gemm_bd<double>(const double*, const double*, double*, long, const Fold&, hipStream_t);

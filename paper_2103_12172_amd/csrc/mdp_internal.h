@@ -276,15 +276,14 @@ void launch_fold_rhs(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int
                      hipStream_t st);
 template <class T>
 void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st);
+// process-wide: pick the sine GEMM's tile shape per (precision, n, rows) by timing at first use
+void set_gemm_autotune(int on);
 // fac: planes l.re, l.im, r.re, r.im, tw.re, tw.im, each (n+1) x W
 template <class T>
 void launch_tridiag(const T* in, int planes_in, T* out, const T* fac, const T* colc, int n, const Fold& f, int R,
                     Band bd, hipStream_t st);
 void launch_residual(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, EndRowCoef ec, int R, bool cplx_src,
                      const float* u32, float* r_out, hipStream_t st);
-// conjugate-transposed tridiagonal solves T^H x = g per mode with the LU factors of T (all n+1 rows; FP64)
-void launch_tridiag_adj(const double* in, int planes_in, double* out, const double* fac, const double* colc, int n,
-                        const Fold& f, int R, hipStream_t st);
 
 // ----------------------------------------------------------------- adjoint (receiver functional)
 // grids[off[t]] = val[t] (complex), t < count; the grids are cleared beforehand
@@ -380,6 +379,9 @@ struct SolveJob {
     const double* E;
     int ng, ncol;
     const int *gm, *gq, *gside, *cidx;
+    int adjoint;          // 1: conjugate-transposed mode solves (all rows)
+    double* out;          // set: the solution into these grids (entry b at ooff[b]); null: w - u in place
+    const long* ooff;
 };
 // w_b(gamma) = E c_b on the entries' grids (cleared beforehand); c: every subdomain's coefficients
 void launch_extend_density_jobs(const SolveJob* jobs, int njobs, int total, int max_ng, double* grids,
@@ -388,7 +390,7 @@ void launch_extend_density_jobs(const SolveJob* jobs, int njobs, int total, int 
 void launch_fold_rhs_jobs(const SolveJob* jobs, int njobs, int total, int max_w, int max_nr, hipStream_t st);
 // the mode solves of every entry, B -> A
 void launch_tridiag_jobs(const SolveJob* jobs, int njobs, int total, int max_w, hipStream_t st);
-// grid_b = w_b - u_b on the band rows, in place (u from the job's B)
+// grid_b = w_b - u_b on the band rows, in place, or (job.out set) out_b = u_b (u from the job's B)
 void launch_unfold_jobs(const SolveJob* jobs, int njobs, int total, int max_n, int max_nr, double* grids,
                         hipStream_t st);
 int fused_segments(int m_lo, int m_hi);   // segments of FUSED_K rows covering m = m_lo-1..m_hi+1

@@ -51,6 +51,7 @@ def test_argument_errors_without_device():
     assert lib.mdp_set_projector_path(None, 0) == mdp.MDP_ERR_ARG
     assert lib.mdp_cache_clear(None) == mdp.MDP_ERR_ARG
     assert lib.mdp_set_interface_path(None, 0) == mdp.MDP_ERR_ARG
+    assert lib.mdp_set_autotune(None, 1) == mdp.MDP_ERR_ARG
     assert lib.mdp_build_projectors(None, 1, None, 8, 0, None, None) == mdp.MDP_ERR_ARG
     assert lib.mdp_dd_gradient(None, 1, None, None, None, 8, 0, None, None, None, None, None, None) == mdp.MDP_ERR_ARG
 
