@@ -691,7 +691,7 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     };
     normal_solve(F, x);
     // refinement steps; the last correction's norm and the solution's norm are
-    // measured so the host can judge convergence (each step contracts the error
+    // measured so the host can decide on convergence (each step contracts the error
     // by about cond(Qbar)^2 u)
     auto refine = [&](int steps) {
         for (int it = 0; it < steps; ++it) {
