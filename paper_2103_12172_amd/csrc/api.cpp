@@ -1349,17 +1349,16 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
                    reinterpret_cast<const int*>(pat(tabs.sub)), reinterpret_cast<const int*>(pat(tabs.p)),
                    reinterpret_cast<const int*>(pat(tabs.gcol)), reinterpret_cast<const int4*>(pat(tabs.cols)),
                    reinterpret_cast<const double2*>(pat(tabs.coef)), reinterpret_cast<const long*>(pat(tabs.roff)),
-                   reinterpret_cast<const int*>(pat(tabs.start))};
+                   reinterpret_cast<const int*>(pat(tabs.start)), reinterpret_cast<const int*>(pat(tabs.gc_start)),
+                   reinterpret_cast<const int*>(pat(tabs.gc_list))};
     const double2* Ap = ctx->ws.pk.Ap.as<double2>();
     double2* Fbb = at(b_Fbb);
     double2* r = at(b_r);
     const double2 one{1.0, 0.0}, mone{-1.0, 0.0};
-    MDP_HIP(hipMemsetAsync(Fbb, 0, (size_t)m_rows * sizeof(double2), st));
-    launch_packed_ax(d, n_sub, ph.max_m, ph.max_s, Ap, zs, one, Fbb, st);
+    launch_packed_axpy(d, n_sub, ph.max_m, Ap, zs, one, nullptr, Fbb, nullptr, nullptr, st);
     MDP_HIP(hipMemcpyAsync(xs, x, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
     launch_scale_cols(xs, 1, nc, 1, norms, 0, st);
-    MDP_HIP(hipMemcpyAsync(r, F, (size_t)m_rows * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    launch_packed_ax(d, n_sub, ph.max_m, ph.max_s, Ap, xs, mone, r, st);
+    launch_packed_axpy(d, n_sub, ph.max_m, Ap, xs, mone, F, r, nullptr, nullptr, st);
     // (5) boundary-data gradient
     double2* dg = at(b_dg);
     launch_data_grad(nk, reinterpret_cast<const double2* const*>(T(o_kq)), reinterpret_cast<const int*>(T(o_krows)),

@@ -692,15 +692,16 @@ __global__ void diag_range_kernel(const double2* __restrict__ L, int n, int ld, 
 }
 
 // y = alpha op(A) x + beta y, op = conjugate transpose: one workgroup per output
-// entry j (a length-m dot product of column j), A column-major m x n.
+// entry j (a length-m dot product of column j), A column-major m x n; lower: A is
+// lower triangular, so column j starts at row j.
 __global__ void __launch_bounds__(256)
 zgemv_c_kernel(int m, const double2* __restrict__ A, int lda, const double2* __restrict__ x, double2* y,
-               double2 alpha, double2 beta) {
+               double2 alpha, double2 beta, int lower) {
     const int j = blockIdx.x;
     __shared__ double rr[256], ri[256];
     double sr = 0.0, si = 0.0;
     const double2* col = A + (long)j * lda;
-    for (int i = threadIdx.x; i < m; i += 256) {
+    for (int i = (lower ? j : 0) + threadIdx.x; i < m; i += 256) {
         const double2 a = col[i], v = x[i];
         sr += a.x * v.x + a.y * v.y;
         si += a.x * v.y - a.y * v.x;
@@ -742,6 +743,36 @@ zgemv_n_kernel(int m, int n, const double2* __restrict__ A, int lda, const doubl
     }
     atomicAdd(&y[2 * i], alpha.x * sr - alpha.y * si);
     atomicAdd(&y[2 * i + 1], alpha.x * si + alpha.y * sr);
+}
+
+// y = alpha A x (A column-major m x n, y overwritten); lower: A is lower triangular
+// (row i reads columns j <= i only).  16 rows x 16 column groups per workgroup; the
+// groups' partial sums are added in a fixed order (no atomics).
+__global__ void __launch_bounds__(256)
+zgemv_n_set_kernel(int m, int n, const double2* __restrict__ A, int lda, const double2* __restrict__ x,
+                   double2* __restrict__ y, double2 alpha, int lower) {
+    __shared__ double2 part[16][17];
+    const int tr = threadIdx.x & 15, cg = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + tr;
+    const int jend = lower ? min(n, i + 1) : n;
+    double sr = 0.0, si = 0.0;
+    if (i < m) {
+        const double2* a = A + i;
+#pragma unroll 4
+        for (int j = cg; j < jend; j += 16) {
+            const double2 av = a[(long)j * lda], v = x[j];
+            sr = fma(av.x, v.x, fma(-av.y, v.y, sr));
+            si = fma(av.x, v.y, fma(av.y, v.x, si));
+        }
+    }
+    part[cg][tr] = make_double2(sr, si);
+    __syncthreads();
+    if (cg == 0 && i < m) {
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) { ar += part[q][tr].x; ai += part[q][tr].y; }
+        y[i] = make_double2(alpha.x * ar - alpha.y * ai, alpha.x * ai + alpha.y * ar);
+    }
 }
 
 // y = beta y; beta = 0 overwrites y with zeros without reading it (y may hold
@@ -914,6 +945,129 @@ __global__ void __launch_bounds__(256) packed_ahx_kernel(PackedDesc d, const dou
         const int g = d.pc_gcol[pc];
         atomicAdd(&y[2 * g], alpha.x * rr[0] - alpha.y * ri[0]);
         atomicAdd(&y[2 * g + 1], alpha.x * ri[0] + alpha.y * rr[0]);
+    }
+}
+
+// y[g] = sum over the packed columns p of global column g (gc_list[gc_start[g] ..
+// gc_start[g+1]-1]) of A_i(:, p)^* v_i: one workgroup per global column, y overwritten,
+// every sum in a fixed order (no atomics).
+__global__ void __launch_bounds__(256) packed_ahx_set_kernel(PackedDesc d, const double2* __restrict__ Ap,
+                                                             const double2* __restrict__ v,
+                                                             const int* __restrict__ gc_start,
+                                                             const int* __restrict__ gc_list,
+                                                             double2* __restrict__ y) {
+    const int g = blockIdx.x;
+    __shared__ double rr[256], ri[256];
+    double sr = 0.0, si = 0.0;
+    for (int e = gc_start[g]; e < gc_start[g + 1]; ++e) {
+        const int pc = gc_list[e];
+        const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
+        const double2* col = Ap + d.off[i] + (long)p * m;
+        const double2* vi = v + d.roff[i];
+        for (int r = threadIdx.x; r < m; r += 256) {
+            const double2 a = col[r], b = vi[r];
+            sr = fma(a.x, b.x, fma(a.y, b.y, sr));
+            si = fma(a.x, b.y, fma(-a.y, b.x, si));
+        }
+    }
+    rr[threadIdx.x] = sr;
+    ri[threadIdx.x] = si;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) { rr[threadIdx.x] += rr[threadIdx.x + w]; ri[threadIdx.x] += ri[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) y[g] = make_double2(rr[0], ri[0]);
+}
+
+// out_i = F_i + alpha A_i x(gcol of its columns) (F null: alpha A_i x) for the rows of
+// subdomain i = blockIdx.y: 32 rows x 8 column groups per workgroup, the groups'
+// partial sums added in a fixed order (no atomics).  norms (if set): norms[0] +=
+// ||out||^2, norms[1] += ||F||^2 over the rows (accumulators zeroed by an earlier
+// kernel).  clr (if set): clr[0] = clr[1] = 0, by the first workgroup (the
+// accumulators of a later kernel).
+__global__ void __launch_bounds__(256) packed_axpy_kernel(PackedDesc d, const double2* __restrict__ Ap,
+                                                          const double2* __restrict__ x,
+                                                          const int* __restrict__ pc_start, double2 alpha,
+                                                          const double2* __restrict__ F, double2* __restrict__ out,
+                                                          double* norms, double* clr) {
+    const int i = blockIdx.y;
+    if (clr && blockIdx.x == 0 && i == 0 && threadIdx.x == 0) { clr[0] = 0.0; clr[1] = 0.0; }
+    const int m = d.m[i], s = d.s[i];
+    if ((int)blockIdx.x * 32 >= m) return;   // the whole workgroup
+    const int tr = threadIdx.x & 31, cg = threadIdx.x >> 5;
+    const int row = blockIdx.x * 32 + tr;
+    __shared__ double2 part[8][33];
+    __shared__ double nrm[2][32];
+    double sr = 0.0, si = 0.0;
+    if (row < m) {
+        const double2* A = Ap + d.off[i] + row;
+        const int* gc = d.pc_gcol + pc_start[i];
+#pragma unroll 4
+        for (int c = cg; c < s; c += 8) {
+            const double2 a = A[(long)c * m], v = x[gc[c]];
+            sr = fma(a.x, v.x, fma(-a.y, v.y, sr));
+            si = fma(a.x, v.y, fma(a.y, v.x, si));
+        }
+    }
+    part[cg][tr] = make_double2(sr, si);
+    __syncthreads();
+    if (cg == 0) {
+        double rn = 0.0, fn = 0.0;
+        if (row < m) {
+            double ar = 0.0, ai = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) { ar += part[q][tr].x; ai += part[q][tr].y; }
+            const long o = d.roff[i] + row;
+            const double2 f = F ? F[o] : make_double2(0.0, 0.0);
+            const double2 res = make_double2(f.x + alpha.x * ar - alpha.y * ai, f.y + alpha.x * ai + alpha.y * ar);
+            out[o] = res;
+            rn = res.x * res.x + res.y * res.y;
+            fn = f.x * f.x + f.y * f.y;
+        }
+        nrm[0][tr] = rn;
+        nrm[1][tr] = fn;
+    }
+    if (!norms) return;   // uniform over the workgroup
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double a = 0.0;
+        for (int q = 0; q < 32; ++q) a += nrm[threadIdx.x][q];
+        atomicAdd(&norms[threadIdx.x], a);
+    }
+}
+
+// x += dx; norms (if set): norms[0] += ||x||^2 of the updated x, norms[1] += ||dx||^2
+// (accumulators zeroed by an earlier kernel); clr (if set): clr[0] = clr[1] = 0 by the
+// first workgroup.
+__global__ void __launch_bounds__(256) zaxpy_norms_kernel(int n, const double2* __restrict__ dx,
+                                                          double2* __restrict__ x, double* norms, double* clr) {
+    if (clr && blockIdx.x == 0 && threadIdx.x == 0) { clr[0] = 0.0; clr[1] = 0.0; }
+    __shared__ double red[2][256];
+    double xn = 0.0, dn = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const double2 d = dx[i];
+        double2 v = x[i];
+        v.x += d.x;
+        v.y += d.y;
+        x[i] = v;
+        xn += v.x * v.x + v.y * v.y;
+        dn += d.x * d.x + d.y * d.y;
+    }
+    if (!norms) return;   // uniform over the grid
+    red[0][threadIdx.x] = xn;
+    red[1][threadIdx.x] = dn;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&norms[0], red[0][0]);
+        atomicAdd(&norms[1], red[1][0]);
     }
 }
 
@@ -1096,8 +1250,10 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
     if (n == 1 && tri == 0) {   // matrix-vector products
         if (opB != 'N') throw Error(MDP_ERR_ARG, "gemv with a transposed vector");
         if (opA == 'C')
-            hipLaunchKernelGGL(zgemv_c_kernel, dim3(m), dim3(256), 0, st, k, A, lda, B, C, alpha, beta);
-        else {
+            hipLaunchKernelGGL(zgemv_c_kernel, dim3(m), dim3(256), 0, st, k, A, lda, B, C, alpha, beta, 0);
+        else if (beta.x == 0.0 && beta.y == 0.0) {
+            hipLaunchKernelGGL(zgemv_n_set_kernel, dim3((m + 15) / 16), dim3(256), 0, st, m, k, A, lda, B, C, alpha, 0);
+        } else {
             if (!(beta.x == 1.0 && beta.y == 0.0))
                 hipLaunchKernelGGL(zscale_kernel, dim3((m + 255) / 256), dim3(256), 0, st, m, C, beta);
             hipLaunchKernelGGL(zgemv_n_kernel, dim3((m + 255) / 256, (k + 63) / 64), dim3(256), 0, st, m, k, A, lda,
@@ -1285,6 +1441,39 @@ void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int
     if (!G) return;   // the partials are used as they are (multifrontal leaves)
     hipLaunchKernelGGL(gram_scatter_kernel, dim3((unsigned)(((long)max_n * max_n + 255) / 256), nb), dim3(256), 0, st,
                        zb_dev, P, nsplit, gcol, G, ldg);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_trmv_lower(char op, int n, const double2* A, int lda, const double2* x, double2* y, hipStream_t st) {
+    if (n <= 0) return;
+    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+    if (op == 'C')
+        hipLaunchKernelGGL(zgemv_c_kernel, dim3(n), dim3(256), 0, st, n, A, lda, x, y, one, zero, 1);
+    else
+        hipLaunchKernelGGL(zgemv_n_set_kernel, dim3((n + 15) / 16), dim3(256), 0, st, n, n, A, lda, x, y, one, 1);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_packed_ahx_set(const PackedDevice& d, int nc, const double2* Ap, const double2* v, double2* y,
+                           hipStream_t st) {
+    if (nc <= 0) return;
+    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
+    hipLaunchKernelGGL(packed_ahx_set_kernel, dim3(nc), dim3(256), 0, st, pd, Ap, v, d.gc_start, d.gc_list, y);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_packed_axpy(const PackedDevice& d, int n_sub, int max_m, const double2* Ap, const double2* x,
+                        double2 alpha, const double2* F, double2* out, double* norms, double* clr, hipStream_t st) {
+    if (n_sub <= 0 || max_m <= 0) return;
+    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
+    hipLaunchKernelGGL(packed_axpy_kernel, dim3((max_m + 31) / 32, n_sub), dim3(256), 0, st, pd, Ap, x, d.pc_start,
+                       alpha, F, out, norms, clr);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_zaxpy_norms(int n, const double2* dx, double2* x, double* norms, double* clr, hipStream_t st) {
+    const int g = std::max(1, std::min(256, (n + 255) / 256));
+    hipLaunchKernelGGL(zaxpy_norms_kernel, dim3(g), dim3(256), 0, st, n, dx, x, norms, clr);
     MDP_HIP(hipGetLastError());
 }
 

@@ -474,6 +474,15 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
     t.start = blob.put(h.pc_start);
     t.cols = blob.put(h.pc_cols);
     t.coef = blob.put(h.pc_coef);
+    {
+        std::vector<int> gs(nc + 1, 0), gl(h.total_pc);
+        for (int pc = 0; pc < h.total_pc; ++pc) ++gs[h.pc_gcol[pc] + 1];
+        for (int g = 0; g < nc; ++g) gs[g + 1] += gs[g];
+        std::vector<int> fill(gs.begin(), gs.end() - 1);
+        for (int pc = 0; pc < h.total_pc; ++pc) gl[fill[h.pc_gcol[pc]]++] = pc;
+        t.gc_start = blob.put(gs);
+        t.gc_list = blob.put(gl);
+    }
     // all subdomains' A_i^* A_i in one split-K launch (reduced and scattered in a second)
     int max_m = 0, tiles = 0;
     for (int i = 0; i < n_sub; ++i) {
@@ -562,7 +571,8 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
                    reinterpret_cast<const int*>(at(tb.sub)), reinterpret_cast<const int*>(at(tb.p)),
                    reinterpret_cast<const int*>(at(tb.gcol)), reinterpret_cast<const int4*>(at(tb.cols)),
                    reinterpret_cast<const double2*>(at(tb.coef)), reinterpret_cast<const long*>(at(tb.roff)),
-                   reinterpret_cast<const int*>(at(tb.start))};
+                   reinterpret_cast<const int*>(at(tb.start)), reinterpret_cast<const int*>(at(tb.gc_start)),
+                   reinterpret_cast<const int*>(at(tb.gc_list))};
     double2* Ap = w.Ap.as<double2>();
     double* norms2 = lw.norms.as<double>();
     double* norms = norms2 + nc;
@@ -673,37 +683,36 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     const double solve_flops = 8.0 * (packed_cmacs + tri_cmacs), resid_flops = 8.0 * packed_cmacs;
     int n_solves = 0, n_resid = 0;
     // c = R^{-1} R^{-*} Qbar^* F, R^{-1} = Linv^*, R^{-*} = Linv
+    // (every product below overwrites its output and sums in a fixed order, so the
+    // sequence needs no clearing launches and repeats bit for bit)
     auto normal_solve = [&](const double2* rhs_rows, double2* out) {
         ++n_solves;
-        MDP_HIP(hipMemsetAsync(y, 0, nc * sizeof(double2), st));
-        launch_packed_ahx(d, npc, Ap, rhs_rows, ONE, y, st);
+        launch_packed_ahx_set(d, nc, Ap, rhs_rows, y, st);
         if (mfr) {
             mf_solve(y, out);
             return;
         }
-        launch_zgemm('N', 'N', nc, 1, nc, ONE, Linv, nc, y, nc, ZERO, t, nc, ws.zg, st);
-        launch_zgemm('C', 'N', nc, 1, nc, ONE, Linv, nc, t, nc, ZERO, out, nc, ws.zg, st);
+        launch_trmv_lower('N', nc, Linv, nc, y, t, st);
+        launch_trmv_lower('C', nc, Linv, nc, t, out, st);
     };
-    auto residual = [&]() {   // r = F - Qbar x (stacked rows)
+    // r = F - Qbar x (stacked rows); norms: ||r||^2, ||F||^2 into r2, f2; clr: accumulators to zero
+    auto residual = [&](double* norms, double* clr) {
         ++n_resid;
-        MDP_HIP(hipMemcpyAsync(r, F, mtot * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        launch_packed_ax(d, n_sub, h.max_m, h.max_s, Ap, x, MONE, r, st);
+        launch_packed_axpy(d, n_sub, h.max_m, Ap, x, MONE, F, r, norms, clr, st);
     };
     normal_solve(F, x);
     // refinement steps; the last correction's norm and the solution's norm are
     // measured so the host can decide on convergence (each step contracts the error
-    // by about cond(Qbar)^2 u)
+    // by about cond(Qbar)^2 u).  The last step's residual launch clears x2 and dx2
+    // (adjacent), its update accumulates them and clears r2 and f2 (adjacent) for
+    // the residual norms that follow.
     auto refine = [&](int steps) {
         for (int it = 0; it < steps; ++it) {
-            residual();
+            const bool last = it == steps - 1;
+            residual(nullptr, last ? &fl->x2 : nullptr);
             normal_solve(r, dx);
-            if (it == steps - 1) {
-                MDP_HIP(hipMemsetAsync(&fl->x2, 0, 2 * sizeof(double), st));   // x2 and dx2 (adjacent)
-                launch_znorm2(nc, dx, &fl->dx2, st);
-            }
-            launch_zaxpy1(nc, dx, x, st);
+            launch_zaxpy_norms(nc, dx, x, last ? &fl->x2 : nullptr, last ? &fl->r2 : nullptr, st);
         }
-        launch_znorm2(nc, x, &fl->x2, st);
     };
     PackedFlags hf{};
     auto read_flags = [&]() {
@@ -714,12 +723,7 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     };
     auto converged = [&]() { return !hf.info && hf.dx2 <= 1e-22 * hf.x2; };
     // the residual norms of the refined solution go to the host with the convergence data
-    auto residual_norms = [&]() {
-        residual();
-        MDP_HIP(hipMemsetAsync(&fl->r2, 0, 2 * sizeof(double), st));   // r2 and f2 (adjacent)
-        launch_znorm2((int)mtot, r, &fl->r2, st);
-        launch_znorm2((int)mtot, F, &fl->f2, st);
-    };
+    auto residual_norms = [&]() { residual(&fl->r2, nullptr); };
     refine(2);
     residual_norms();
     read_flags();
@@ -803,8 +807,8 @@ void ls_packed_factor_solve(Workspace& ws, const PackedHost& h, const char* imag
     LSWork& lw = ws.ls;
     double2* t = lw.vec.as<double2>() + nc;   // the normal solve's own temporary
     const double2* Linv = lw.Linv[0].as<double2>();
-    launch_zgemm('N', 'N', nc, 1, nc, ONE, Linv, nc, v, nc, ZERO, t, nc, ws.zg, st);
-    launch_zgemm('C', 'N', nc, 1, nc, ONE, Linv, nc, t, nc, ZERO, out, nc, ws.zg, st);
+    launch_trmv_lower('N', nc, Linv, nc, v, t, st);
+    launch_trmv_lower('C', nc, Linv, nc, t, out, st);
 }
 
 }  // namespace mdp

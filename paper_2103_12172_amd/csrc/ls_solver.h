@@ -81,6 +81,7 @@ double cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, i
 // Device tables of the packed solve: offsets into a caller's upload image.
 struct PackedTables {
     size_t Q, m, s, off, roff, sub, p, gcol, start, cols, coef, zb;
+    size_t gc_start, gc_list;   // global column -> its packed columns (CSR)
     int nsplit;
     size_t mf_nodes, mf_lists, mf_steps;  // multifrontal: node table, node lists by height, step entries
     std::vector<size_t> mf_list_off;      // start of each height's list (entries)

@@ -453,6 +453,8 @@ struct PackedDevice {
     const double2* pc_coef;
     const long* roff;
     const int* pc_start;   // first packed column of each subdomain
+    const int* gc_start = nullptr;   // global column g: its packed columns gc_list[gc_start[g] .. gc_start[g+1]-1]
+    const int* gc_list = nullptr;
 };
 void launch_assemble_packed(const PackedDevice& d, int total_pc, int max_m, double2* Ap, hipStream_t st);
 void launch_packed_colnorm2(const PackedDevice& d, int total_pc, const double2* Ap, double* norms2, hipStream_t st);
@@ -476,6 +478,17 @@ struct ZBatch {
 void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int nsplit, double2* P, const int* gcol,
                          double2* G, int ldg, hipStream_t st);
 void launch_zaxpy1(int n, const double2* x, double2* y, hipStream_t st);
+// y = op(A) x for lower-triangular A (n x n, ld lda), op 'N' or 'C'; y overwritten, fixed summation order.
+void launch_trmv_lower(char op, int n, const double2* A, int lda, const double2* x, double2* y, hipStream_t st);
+// y = A^* v on the packed matrix, one entry per global column (d.gc_start / d.gc_list set), y overwritten.
+void launch_packed_ahx_set(const PackedDevice& d, int nc, const double2* Ap, const double2* v, double2* y,
+                           hipStream_t st);
+// out = F + alpha A x on the stacked rows (F null: alpha A x); norms: += ||out||^2, ||F||^2; clr: two
+// accumulators of a later kernel set to zero.
+void launch_packed_axpy(const PackedDevice& d, int n_sub, int max_m, const double2* Ap, const double2* x,
+                        double2 alpha, const double2* F, double2* out, double* norms, double* clr, hipStream_t st);
+// x += dx; norms: += ||x||^2 (updated), ||dx||^2; clr as above.
+void launch_zaxpy_norms(int n, const double2* dx, double2* x, double* norms, double* clr, hipStream_t st);
 // Multifrontal Cholesky of the interface Gram matrix: one node of the
 // elimination tree.  Its front holds e eliminated columns, then b boundary
 // columns (global indices idx[0..f-1], f = e + b).  A leaf assembles its
