@@ -723,15 +723,12 @@ __global__ void gather_add_kernel(const T* __restrict__ u, Fold f, Band bd, cons
 // resp. u = 0, du/dn = psi on the side, normal derivatives replaced through the
 // equation).  T_j^(p) by the differentiated recurrence
 // T_{j+1}^(p) = 2 t T_j^(p) + 2 p T_j^(p-1) - T_{j-1}^(p), one thread per node.
-// The other 6M* entries of the row are left as they are (the caller zeroes E).
-__global__ void extension_kernel(const int* __restrict__ side, const double* __restrict__ rho,
-                                 const double* __restrict__ tpar, const double* __restrict__ slen, int ng, double k,
-                                 int M, double* __restrict__ E, int deriv) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ng) return;
-    const int s = side[i];
-    const double t = tpar[i], r = rho[i];
-    const double sc = 2.0 / slen[i], sc2 = sc * sc, sc4 = sc2 * sc2;
+// extension_row writes the 2M* entries of the node's side; extension_kernel leaves the
+// other 6M* entries of the row as they are (the caller zeroes E), geom_setup_kernel
+// writes them as zeros.
+__device__ inline void extension_row(int s, double t, double r, double slen, int ng, double k, int M,
+                                     double* __restrict__ E, int deriv, int i) {
+    const double sc = 2.0 / slen, sc2 = sc * sc, sc4 = sc2 * sc2;
     const double k2 = k * k, k4 = k2 * k2;
     const double r2 = r * r, r3 = r2 * r, r4 = r2 * r2;
     double cur[5] = {1.0, 0.0, 0.0, 0.0, 0.0};    // T_j^(p), p = 0..4
@@ -761,6 +758,47 @@ __global__ void extension_kernel(const int* __restrict__ side, const double* __r
             cur[p] = nxt[p];
         }
     }
+}
+
+__global__ void extension_kernel(const int* __restrict__ side, const double* __restrict__ rho,
+                                 const double* __restrict__ tpar, const double* __restrict__ slen, int ng, double k,
+                                 int M, double* __restrict__ E, int deriv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ng) return;
+    extension_row(side[i], tpar[i], rho[i], slen[i], ng, k, M, E, deriv, i);
+}
+
+// The per-projector set-up of one build, every projector of the call in one launch
+// (entry blockIdx.y; the x workgroups stride over the entry's work): the gamma node
+// tables copied from the call's upload into the projector's own buffer, the full
+// rows of E (zero outside the node's side), and the node -> gamma map filled with -1.
+__global__ void __launch_bounds__(256) geom_setup_kernel(const GeomJob* __restrict__ jobs) {
+    const GeomJob jb = jobs[blockIdx.y];
+    const long stride = (long)gridDim.x * blockDim.x;
+    const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned* src = reinterpret_cast<const unsigned*>(jb.src);
+    unsigned* dst = reinterpret_cast<unsigned*>(jb.meta);
+    for (long w = t0; w < jb.meta_words; w += stride) dst[w] = src[w];
+    const int M = jb.M, ng = jb.ng;
+    for (long i = t0; i < ng; i += stride) {
+        const int s = jb.side[i];
+        for (int kind = 0; kind < 2; ++kind)
+            for (int q = 0; q < 4; ++q) {
+                if (q == s) continue;
+                double* col = jb.E + (long)(kind * 4 * M + q * M) * ng + i;
+                for (int j = 0; j < M; ++j) col[(long)j * ng] = 0.0;
+            }
+        extension_row(s, jb.t[i], jb.rho[i], jb.slen[i], ng, jb.k, M, jb.E, 0, (int)i);
+    }
+    const long nodes = (long)(jb.n + 1) * (jb.n + 1);
+    for (long v = t0; v < nodes; v += stride) jb.gidx[v] = -1;
+}
+
+// gidx[gm[i] (n+1) + gq[i]] = i for every entry (after geom_setup_kernel)
+__global__ void __launch_bounds__(256) gamma_index_jobs_kernel(const GeomJob* __restrict__ jobs) {
+    const GeomJob jb = jobs[blockIdx.y];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < jb.ng; i += (long)gridDim.x * blockDim.x)
+        jb.gidx[jb.gm[i] * (jb.n + 1) + jb.gq[i]] = (int)i;
 }
 
 // gidx[gm[i] (n+1) + gq[i]] = i (the map was filled with -1)
@@ -1318,6 +1356,16 @@ void launch_extension(const int* side, const double* rho, const double* t, const
     if (ng <= 0) return;
     hipLaunchKernelGGL(extension_kernel, dim3((ng + 255) / 256), dim3(256), 0, st, side, rho, t, slen, ng, k, m_star,
                        E, deriv);
+    MDP_HIP(hipGetLastError());
+}
+
+void launch_geom_setup(const GeomJob* jobs_dev, int count, int max_nodes, hipStream_t st) {
+    if (count <= 0) return;
+    if (count > 65535) throw Error(MDP_ERR_ARG, "too many projectors for one set-up launch");
+    const unsigned gx = (unsigned)std::max(1, std::min(64, (max_nodes + 255) / 256));
+    hipLaunchKernelGGL(geom_setup_kernel, dim3(gx, count), dim3(256), 0, st, jobs_dev);
+    MDP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(gamma_index_jobs_kernel, dim3(std::min(gx, 16u), count), dim3(256), 0, st, jobs_dev);
     MDP_HIP(hipGetLastError());
 }
 

@@ -508,6 +508,14 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
         std::vector<std::pair<ProjKey, mdp_projector*>> fresh;   // built by this call, not yet cached
         bool began = false;
         try {
+            // every fresh projector's gamma tables in one upload, its set-up (tables, E, node map)
+            // in one launch pair for all of them
+            struct SetupSrc { size_t base, o_gm, o_gq, o_side, o_rho, o_t, o_slen; };
+            HostBlob setup;
+            std::vector<GeomJob> gjobs;
+            std::vector<SetupSrc> gsrc;
+            int max_nodes = 0;
+            std::vector<std::pair<mdp_projector*, APPlan*>> dense;   // the full-solve route, after the set-up
             for (int i = 0; i < count; ++i) {
                 const mdp_subdomain* sd = &sds[i];
                 ProjKey key{sd->lx, sd->ly, sd->n, sd->k, m_star, precision};
@@ -534,27 +542,40 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                 P->pool = ctx->pool;
                 BufPool& pool = *ctx->pool;
                 const int ng = g.n_gamma, ncol = 8 * m_star;
-                // gamma node lists in one upload; E and the node -> gamma map are built on the device
                 HostBlob blob;
-                const size_t o_gm = blob.put(g.gm), o_gq = blob.put(g.gq), o_side = blob.put(g.side),
-                             o_rho = blob.put(g.rho), o_t = blob.put(g.t), o_slen = blob.put(g.slen);
+                SetupSrc ss{};
+                ss.o_gm = blob.put(g.gm);
+                ss.o_gq = blob.put(g.gq);
+                ss.o_side = blob.put(g.side);
+                ss.o_rho = blob.put(g.rho);
+                ss.o_t = blob.put(g.t);
+                ss.o_slen = blob.put(g.slen);
+                if (blob.size() % 4) throw Error(MDP_ERR_ARG, "gamma tables not in 4-byte words");
+                ss.base = setup.put(blob.data(), blob.size());
                 P->meta = pool.take(blob.size());
-                ctx->ws.stage.copy(P->meta.p, blob, st);
                 const char* mb = P->meta.as<char>();
-                P->gm = reinterpret_cast<const int*>(mb + o_gm);
-                P->gq = reinterpret_cast<const int*>(mb + o_gq);
-                P->gside = reinterpret_cast<const int*>(mb + o_side);
-                P->grho = reinterpret_cast<const double*>(mb + o_rho);
-                P->gt = reinterpret_cast<const double*>(mb + o_t);
-                P->gslen = reinterpret_cast<const double*>(mb + o_slen);
+                P->gm = reinterpret_cast<const int*>(mb + ss.o_gm);
+                P->gq = reinterpret_cast<const int*>(mb + ss.o_gq);
+                P->gside = reinterpret_cast<const int*>(mb + ss.o_side);
+                P->grho = reinterpret_cast<const double*>(mb + ss.o_rho);
+                P->gt = reinterpret_cast<const double*>(mb + ss.o_t);
+                P->gslen = reinterpret_cast<const double*>(mb + ss.o_slen);
                 P->E = pool.take((size_t)ng * ncol * sizeof(double));
-                MDP_HIP(hipMemsetAsync(P->E.p, 0, (size_t)ng * ncol * sizeof(double), st));
-                launch_extension(P->gside, P->grho, P->gt, P->gslen, ng, sd->k, m_star, P->E.as<double>(), st);
                 const size_t nodes = (size_t)(g.n + 1) * (g.n + 1);
                 P->gidx = pool.take(nodes * sizeof(int));
-                MDP_HIP(hipMemsetAsync(P->gidx.p, 0xff, nodes * sizeof(int), st));   // -1 everywhere
-                launch_gamma_index(P->gm, P->gq, ng, g.n, P->gidx.as<int>(), st);
                 P->Q = pool.take((size_t)ng * ncol * 2 * sizeof(double));
+                GeomJob jb{};
+                jb.meta = P->meta.as<char>();
+                jb.meta_words = (long)(blob.size() / 4);
+                jb.ng = ng;
+                jb.n = g.n;
+                jb.M = m_star;
+                jb.k = sd->k;
+                jb.E = P->E.as<double>();
+                jb.gidx = P->gidx.as<int>();
+                gjobs.push_back(jb);
+                gsrc.push_back(ss);
+                max_nodes = std::max(max_nodes, (int)nodes);
                 P->g = std::move(g);
                 const Geometry& G = P->g;
                 mdp_projector* raw = P.release();
@@ -566,7 +587,32 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                     fused.push_back({&plan, raw});
                     continue;
                 }
+                dense.push_back({raw, &plan});
+            }
+            if (!gjobs.empty()) {
+                // the job table holds device addresses inside the upload: the image is sized first
+                const size_t o_jobs = (setup.size() + 255) / 256 * 256;
+                char* img = ctx->ws.stage.image_for(o_jobs + gjobs.size() * sizeof(GeomJob));
+                for (size_t q = 0; q < gjobs.size(); ++q) {
+                    const char* b = img + gsrc[q].base;
+                    gjobs[q].src = b;
+                    gjobs[q].gm = reinterpret_cast<const int*>(b + gsrc[q].o_gm);
+                    gjobs[q].gq = reinterpret_cast<const int*>(b + gsrc[q].o_gq);
+                    gjobs[q].side = reinterpret_cast<const int*>(b + gsrc[q].o_side);
+                    gjobs[q].rho = reinterpret_cast<const double*>(b + gsrc[q].o_rho);
+                    gjobs[q].t = reinterpret_cast<const double*>(b + gsrc[q].o_t);
+                    gjobs[q].slen = reinterpret_cast<const double*>(b + gsrc[q].o_slen);
+                }
+                if (setup.put(gjobs) != o_jobs) throw Error(MDP_ERR_ARG, "set-up table layout");
+                if (ctx->ws.stage.upload(setup, st) != img) throw Error(MDP_ERR_ARG, "set-up image moved");
+                launch_geom_setup(reinterpret_cast<const GeomJob*>(img + o_jobs), (int)gjobs.size(), max_nodes, st);
+            }
+            for (auto& dp : dense) {
                 // dense route: full AP solves of the columns, gathered onto gamma
+                mdp_projector* raw = dp.first;
+                APPlan& plan = *dp.second;
+                const Geometry& G = raw->g;
+                const int ng = G.n_gamma, ncol = 8 * m_star;
                 const int chunk = chunk_size(plan, precision, ctx->ws_cap, ncol);
                 prepare_ws(ctx, plan, precision, chunk);
                 for (int col0 = 0; col0 < ncol; col0 += chunk) {

@@ -139,14 +139,20 @@ struct Staging {
         MDP_HIP(hipEventRecord(s.done, st));
         s.pending = true;
     }
-    // the device image, grown (after the device has drained) to at least b's size, with b copied in
-    char* upload(const HostBlob& b, hipStream_t st) {
-        if (b.size() > image.bytes) {
+    // the device image, grown (after the device has drained) to hold at least `bytes`
+    // (tables that hold addresses inside the image are written after this)
+    char* image_for(size_t bytes) {
+        if (bytes > image.bytes) {
             MDP_HIP(hipDeviceSynchronize());
-            image.reserve(std::max(b.size(), 2 * image.bytes));
+            image.reserve(std::max(bytes, 2 * image.bytes));
         }
-        copy(image.p, b, st);
         return image.as<char>();
+    }
+    // the device image, grown as above to b's size, with b copied in
+    char* upload(const HostBlob& b, hipStream_t st) {
+        char* img = image_for(b.size());
+        copy(img, b, st);
+        return img;
     }
 };
 
@@ -227,6 +233,23 @@ void launch_extension(const int* side, const double* rho, const double* t, const
                       int m_star, double* E, hipStream_t st, int deriv = 0);
 // gidx[gm[i] (n+1) + gq[i]] = i over a map filled with -1 beforehand
 void launch_gamma_index(const int* gm, const int* gq, int ng, int n, int* gidx, hipStream_t st);
+// One projector's set-up in a build (device pointers): its gamma node tables are copied
+// from the call's upload (src, meta_words 4-byte words) to its own buffer (meta); E
+// (ng x 8M, column-major) and the node -> gamma map gidx ((n+1)^2) are written from the
+// uploaded tables (side, rho, t, slen, gm, gq point into the upload).
+struct GeomJob {
+    const char* src;
+    char* meta;
+    long meta_words;
+    const int *side, *gm, *gq;
+    const double *rho, *t, *slen;
+    int ng, n, M;
+    double k;
+    double* E;
+    int* gidx;
+};
+// every entry's set-up in two launches (tables, E and the -1 fill; then the gamma scatter)
+void launch_geom_setup(const GeomJob* jobs_dev, int count, int max_nodes, hipStream_t st);
 
 // ----------------------------------------------------------------- folded sine layout
 // For even n = 2p the type-I sine transform splits by the parity of the mode j:
