@@ -768,10 +768,10 @@ __global__ void extension_kernel(const int* __restrict__ side, const double* __r
     extension_row(side[i], tpar[i], rho[i], slen[i], ng, k, M, E, deriv, i);
 }
 
-// The per-projector set-up of one build, every projector of the call in one launch
-// (entry blockIdx.y; the x workgroups stride over the entry's work): the gamma node
-// tables copied from the call's upload into the projector's own buffer, the full
-// rows of E (zero outside the node's side), and the node -> gamma map filled with -1.
+// The set-up of one build in one launch (entry blockIdx.y; the x workgroups stride over
+// the entry's work): for a geometry new to the context, its gamma node tables copied
+// from the call's upload into its own buffer and its node -> gamma map filled with -1;
+// for a projector, the full rows of E (zero outside the node's side).
 __global__ void __launch_bounds__(256) geom_setup_kernel(const GeomJob* __restrict__ jobs) {
     const GeomJob jb = jobs[blockIdx.y];
     const long stride = (long)gridDim.x * blockDim.x;
@@ -779,7 +779,7 @@ __global__ void __launch_bounds__(256) geom_setup_kernel(const GeomJob* __restri
     const unsigned* src = reinterpret_cast<const unsigned*>(jb.src);
     unsigned* dst = reinterpret_cast<unsigned*>(jb.meta);
     for (long w = t0; w < jb.meta_words; w += stride) dst[w] = src[w];
-    const int M = jb.M, ng = jb.ng;
+    const int M = jb.M, ng = jb.E ? jb.ng : 0;
     for (long i = t0; i < ng; i += stride) {
         const int s = jb.side[i];
         for (int kind = 0; kind < 2; ++kind)
@@ -790,13 +790,15 @@ __global__ void __launch_bounds__(256) geom_setup_kernel(const GeomJob* __restri
             }
         extension_row(s, jb.t[i], jb.rho[i], jb.slen[i], ng, jb.k, M, jb.E, 0, (int)i);
     }
+    if (!jb.gidx) return;
     const long nodes = (long)(jb.n + 1) * (jb.n + 1);
     for (long v = t0; v < nodes; v += stride) jb.gidx[v] = -1;
 }
 
-// gidx[gm[i] (n+1) + gq[i]] = i for every entry (after geom_setup_kernel)
+// gidx[gm[i] (n+1) + gq[i]] = i for every entry with a node map (after geom_setup_kernel)
 __global__ void __launch_bounds__(256) gamma_index_jobs_kernel(const GeomJob* __restrict__ jobs) {
     const GeomJob jb = jobs[blockIdx.y];
+    if (!jb.gidx) return;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < jb.ng; i += (long)gridDim.x * blockDim.x)
         jb.gidx[jb.gm[i] * (jb.n + 1) + jb.gq[i]] = (int)i;
 }

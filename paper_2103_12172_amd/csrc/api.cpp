@@ -63,20 +63,36 @@ struct BufPool {
 
 }  // namespace
 
+// The grid sets and gamma of one rectangle size and n with their device tables, shared
+// by every projector of that geometry whatever its k (the tables are uploaded, and the
+// node map written, by the first build that needs them).
+struct GeomShared {
+    Geometry g;
+    DevBuf meta;   // gamma nodes: gm, gq, side (int), then rho, t, side length (double)
+    DevBuf gidx;   // (n+1)^2 node -> gamma index, -1 off gamma
+    const int *gm = nullptr, *gq = nullptr, *gside = nullptr;
+    const double *grho = nullptr, *gt = nullptr, *gslen = nullptr;
+    bool on_device = false;
+    explicit GeomShared(Geometry&& geo) : g(std::move(geo)) {}
+};
+
 struct mdp_projector {
     std::atomic<int> refs{1};
     int device = 0;
     unsigned long long serial = 0;   // unique per build in its context (the interface factor's key)
-    Geometry g;
+    std::shared_ptr<GeomShared> geo;
+    const Geometry& g;
     double k = 0.0;
     int m_star = 0, precision = 0;
     DevBuf Q;      // n_gamma x 8M* complex, column-major
     DevBuf E;      // n_gamma x 8M* real
-    DevBuf gidx;   // (n+1)^2 node -> gamma index
-    DevBuf meta;   // gamma nodes: gm, gq, side (int), then rho, t, side length (double)
+    const int* gidx = nullptr;   // the geometry's node map and gamma tables (device)
     const int *gm = nullptr, *gq = nullptr, *gside = nullptr;
     const double *grho = nullptr, *gt = nullptr, *gslen = nullptr;
     std::shared_ptr<BufPool> pool;   // where the buffers go on release
+    explicit mdp_projector(std::shared_ptr<GeomShared> s)
+        : geo(std::move(s)), g(geo->g), gidx(geo->gidx.as<int>()), gm(geo->gm), gq(geo->gq), gside(geo->gside),
+          grho(geo->grho), gt(geo->gt), gslen(geo->gslen) {}
 };
 
 namespace {
@@ -92,7 +108,7 @@ struct mdp_ctx {
     std::string err;
     std::map<PlanKey, std::unique_ptr<APPlan>> plans;
     std::map<ProjKey, mdp_projector*> cache;
-    std::map<GeomKey, Geometry> geoms;   // grid sets and gamma per rectangle size and n (position-free)
+    std::map<GeomKey, std::shared_ptr<GeomShared>> geoms;   // per rectangle size and n (position-free)
     std::shared_ptr<BufPool> pool = std::make_shared<BufPool>();
     Workspace ws;
     size_t ws_cap = (size_t)24 << 30;
@@ -291,7 +307,7 @@ void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
             J.src.E = itm.P->E.as<double>();
             J.src.ldE = ng;
             J.src.col0 = j.col0;
-            J.src.gidx = itm.P->gidx.as<int>();
+            J.src.gidx = itm.P->gidx;
             J.src.m_lo = G.m_lo; J.src.m_hi = G.m_hi; J.src.q_lo = G.q_lo; J.src.q_hi = G.q_hi;
             J.sc = plan.sc;
             J.f = f;
@@ -508,12 +524,12 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
         std::vector<std::pair<ProjKey, mdp_projector*>> fresh;   // built by this call, not yet cached
         bool began = false;
         try {
-            // every fresh projector's gamma tables in one upload, its set-up (tables, E, node map)
-            // in one launch pair for all of them
-            struct SetupSrc { size_t base, o_gm, o_gq, o_side, o_rho, o_t, o_slen; };
+            // the gamma tables of geometries new to the context in one upload; E of every fresh
+            // projector and the new geometries' node maps in one launch pair
+            struct SetupSrc { GeomShared* geo; size_t base, o_gm, o_gq, o_side, o_rho, o_t, o_slen; };
             HostBlob setup;
-            std::vector<GeomJob> gjobs;
-            std::vector<SetupSrc> gsrc;
+            std::vector<SetupSrc> gnew;                     // geometries uploaded by this call
+            std::vector<std::pair<mdp_projector*, int>> ejobs;   // projector, its geometry in gnew (-1: resident)
             int max_nodes = 0;
             std::vector<std::pair<mdp_projector*, APPlan*>> dense;   // the full-solve route, after the set-up
             for (int i = 0; i < count; ++i) {
@@ -530,10 +546,43 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                 GeomKey gk{sd->lx, sd->ly, sd->n};
                 auto git = ctx->geoms.find(gk);
                 if (git == ctx->geoms.end())
-                    git = ctx->geoms.emplace(gk, make_geometry(sd->x0, sd->y0, sd->lx, sd->ly, sd->n)).first;
-                Geometry g = git->second;
-                APPlan& plan = get_plan(ctx, g.n, g.h, sd->k);
-                std::unique_ptr<mdp_projector> P(new mdp_projector);
+                    git = ctx->geoms
+                              .emplace(gk, std::make_shared<GeomShared>(
+                                               make_geometry(sd->x0, sd->y0, sd->lx, sd->ly, sd->n)))
+                              .first;
+                GeomShared& gs = *git->second;
+                int gi = -1;
+                if (!gs.on_device) {
+                    for (size_t q = 0; q < gnew.size(); ++q)
+                        if (gnew[q].geo == &gs) gi = (int)q;
+                    if (gi < 0) {
+                        const Geometry& g = gs.g;
+                        HostBlob blob;
+                        SetupSrc ss{&gs, 0, 0, 0, 0, 0, 0, 0};
+                        ss.o_gm = blob.put(g.gm);
+                        ss.o_gq = blob.put(g.gq);
+                        ss.o_side = blob.put(g.side);
+                        ss.o_rho = blob.put(g.rho);
+                        ss.o_t = blob.put(g.t);
+                        ss.o_slen = blob.put(g.slen);
+                        if (blob.size() % 4) throw Error(MDP_ERR_ARG, "gamma tables not in 4-byte words");
+                        ss.base = setup.put(blob.data(), blob.size());
+                        gs.meta.alloc(blob.size());
+                        const char* mb = gs.meta.as<char>();
+                        gs.gm = reinterpret_cast<const int*>(mb + ss.o_gm);
+                        gs.gq = reinterpret_cast<const int*>(mb + ss.o_gq);
+                        gs.gside = reinterpret_cast<const int*>(mb + ss.o_side);
+                        gs.grho = reinterpret_cast<const double*>(mb + ss.o_rho);
+                        gs.gt = reinterpret_cast<const double*>(mb + ss.o_t);
+                        gs.gslen = reinterpret_cast<const double*>(mb + ss.o_slen);
+                        gs.gidx.alloc((size_t)(g.n + 1) * (g.n + 1) * sizeof(int));
+                        max_nodes = std::max(max_nodes, (g.n + 1) * (g.n + 1));
+                        gi = (int)gnew.size();
+                        gnew.push_back(ss);
+                    }
+                }
+                APPlan& plan = get_plan(ctx, gs.g.n, gs.g.h, sd->k);
+                std::unique_ptr<mdp_projector> P(new mdp_projector(git->second));
                 P->device = ctx->device;
                 P->serial = ctx->next_serial++;
                 P->k = sd->k;
@@ -541,45 +590,14 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                 P->precision = precision;
                 P->pool = ctx->pool;
                 BufPool& pool = *ctx->pool;
-                const int ng = g.n_gamma, ncol = 8 * m_star;
-                HostBlob blob;
-                SetupSrc ss{};
-                ss.o_gm = blob.put(g.gm);
-                ss.o_gq = blob.put(g.gq);
-                ss.o_side = blob.put(g.side);
-                ss.o_rho = blob.put(g.rho);
-                ss.o_t = blob.put(g.t);
-                ss.o_slen = blob.put(g.slen);
-                if (blob.size() % 4) throw Error(MDP_ERR_ARG, "gamma tables not in 4-byte words");
-                ss.base = setup.put(blob.data(), blob.size());
-                P->meta = pool.take(blob.size());
-                const char* mb = P->meta.as<char>();
-                P->gm = reinterpret_cast<const int*>(mb + ss.o_gm);
-                P->gq = reinterpret_cast<const int*>(mb + ss.o_gq);
-                P->gside = reinterpret_cast<const int*>(mb + ss.o_side);
-                P->grho = reinterpret_cast<const double*>(mb + ss.o_rho);
-                P->gt = reinterpret_cast<const double*>(mb + ss.o_t);
-                P->gslen = reinterpret_cast<const double*>(mb + ss.o_slen);
+                const int ng = gs.g.n_gamma, ncol = 8 * m_star;
                 P->E = pool.take((size_t)ng * ncol * sizeof(double));
-                const size_t nodes = (size_t)(g.n + 1) * (g.n + 1);
-                P->gidx = pool.take(nodes * sizeof(int));
                 P->Q = pool.take((size_t)ng * ncol * 2 * sizeof(double));
-                GeomJob jb{};
-                jb.meta = P->meta.as<char>();
-                jb.meta_words = (long)(blob.size() / 4);
-                jb.ng = ng;
-                jb.n = g.n;
-                jb.M = m_star;
-                jb.k = sd->k;
-                jb.E = P->E.as<double>();
-                jb.gidx = P->gidx.as<int>();
-                gjobs.push_back(jb);
-                gsrc.push_back(ss);
-                max_nodes = std::max(max_nodes, (int)nodes);
-                P->g = std::move(g);
+                max_nodes = std::max(max_nodes, ng);
                 const Geometry& G = P->g;
                 mdp_projector* raw = P.release();
                 fresh.push_back({key, raw});
+                ejobs.push_back({raw, gi});
                 res[i] = raw;
                 if (precision == MDP_C128 && ctx->projector_path == MDP_PATH_AUTO &&
                     fused_projector_supported(plan.f, G.m_lo, G.m_hi, G.q_lo, G.q_hi) &&
@@ -589,23 +607,52 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                 }
                 dense.push_back({raw, &plan});
             }
-            if (!gjobs.empty()) {
+            if (!ejobs.empty()) {
                 // the job table holds device addresses inside the upload: the image is sized first
+                std::vector<GeomJob> jobs;
                 const size_t o_jobs = (setup.size() + 255) / 256 * 256;
-                char* img = ctx->ws.stage.image_for(o_jobs + gjobs.size() * sizeof(GeomJob));
-                for (size_t q = 0; q < gjobs.size(); ++q) {
-                    const char* b = img + gsrc[q].base;
-                    gjobs[q].src = b;
-                    gjobs[q].gm = reinterpret_cast<const int*>(b + gsrc[q].o_gm);
-                    gjobs[q].gq = reinterpret_cast<const int*>(b + gsrc[q].o_gq);
-                    gjobs[q].side = reinterpret_cast<const int*>(b + gsrc[q].o_side);
-                    gjobs[q].rho = reinterpret_cast<const double*>(b + gsrc[q].o_rho);
-                    gjobs[q].t = reinterpret_cast<const double*>(b + gsrc[q].o_t);
-                    gjobs[q].slen = reinterpret_cast<const double*>(b + gsrc[q].o_slen);
+                char* img =
+                    ctx->ws.stage.image_for(o_jobs + (gnew.size() + ejobs.size()) * sizeof(GeomJob));
+                auto tables = [&](GeomJob& jb, const SetupSrc& ss) {
+                    const char* b = img + ss.base;
+                    jb.gm = reinterpret_cast<const int*>(b + ss.o_gm);
+                    jb.gq = reinterpret_cast<const int*>(b + ss.o_gq);
+                    jb.side = reinterpret_cast<const int*>(b + ss.o_side);
+                    jb.rho = reinterpret_cast<const double*>(b + ss.o_rho);
+                    jb.t = reinterpret_cast<const double*>(b + ss.o_t);
+                    jb.slen = reinterpret_cast<const double*>(b + ss.o_slen);
+                };
+                for (const SetupSrc& ss : gnew) {   // tables to the geometry's buffer, its node map
+                    GeomJob jb{};
+                    tables(jb, ss);
+                    jb.src = img + ss.base;
+                    jb.meta = ss.geo->meta.as<char>();
+                    jb.meta_words = (long)(ss.geo->meta.bytes / 4);
+                    jb.ng = ss.geo->g.n_gamma;
+                    jb.n = ss.geo->g.n;
+                    jb.gidx = ss.geo->gidx.as<int>();
+                    jobs.push_back(jb);
                 }
-                if (setup.put(gjobs) != o_jobs) throw Error(MDP_ERR_ARG, "set-up table layout");
+                for (const auto& ej : ejobs) {   // E of each fresh projector
+                    const mdp_projector* P = ej.first;
+                    GeomJob jb{};
+                    if (ej.second >= 0) {
+                        tables(jb, gnew[ej.second]);   // the geometry arrives with this call
+                    } else {
+                        jb.gm = P->gm; jb.gq = P->gq; jb.side = P->gside;
+                        jb.rho = P->grho; jb.t = P->gt; jb.slen = P->gslen;
+                    }
+                    jb.ng = P->g.n_gamma;
+                    jb.n = P->g.n;
+                    jb.M = m_star;
+                    jb.k = P->k;
+                    jb.E = P->E.as<double>();
+                    jobs.push_back(jb);
+                }
+                if (setup.put(jobs) != o_jobs) throw Error(MDP_ERR_ARG, "set-up table layout");
                 if (ctx->ws.stage.upload(setup, st) != img) throw Error(MDP_ERR_ARG, "set-up image moved");
-                launch_geom_setup(reinterpret_cast<const GeomJob*>(img + o_jobs), (int)gjobs.size(), max_nodes, st);
+                launch_geom_setup(reinterpret_cast<const GeomJob*>(img + o_jobs), (int)jobs.size(), max_nodes, st);
+                for (const SetupSrc& ss : gnew) ss.geo->on_device = true;
             }
             for (auto& dp : dense) {
                 // dense route: full AP solves of the columns, gathered onto gamma
@@ -622,7 +669,7 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                     src.E = raw->E.as<double>();
                     src.ldE = ng;
                     src.col0 = col0;
-                    src.gidx = raw->gidx.as<int>();
+                    src.gidx = raw->gidx;
                     src.m_lo = G.m_lo; src.m_hi = G.m_hi; src.q_lo = G.q_lo; src.q_hi = G.q_hi;
                     double* Qd = raw->Q.as<double>();
                     const int* gmd = raw->gm;
@@ -720,8 +767,6 @@ void mdp_projector_release(mdp_projector* P) {
         // the buffers go back to the context's pool (freed with it)
         P->pool->give(std::move(P->Q));
         P->pool->give(std::move(P->E));
-        P->pool->give(std::move(P->gidx));
-        P->pool->give(std::move(P->meta));
         delete P;
     }
 }

@@ -233,10 +233,11 @@ void launch_extension(const int* side, const double* rho, const double* t, const
                       int m_star, double* E, hipStream_t st, int deriv = 0);
 // gidx[gm[i] (n+1) + gq[i]] = i over a map filled with -1 beforehand
 void launch_gamma_index(const int* gm, const int* gq, int ng, int n, int* gidx, hipStream_t st);
-// One projector's set-up in a build (device pointers): its gamma node tables are copied
-// from the call's upload (src, meta_words 4-byte words) to its own buffer (meta); E
-// (ng x 8M, column-major) and the node -> gamma map gidx ((n+1)^2) are written from the
-// uploaded tables (side, rho, t, slen, gm, gq point into the upload).
+// One entry of a build's set-up (device pointers).  A geometry new to the context:
+// meta_words 4-byte words of gamma node tables copied from the call's upload (src) to
+// its buffer (meta), and its node -> gamma map gidx ((n+1)^2) written from gm, gq.
+// A projector: E (ng x 8M, column-major) from side, rho, t, slen and k.  Fields of
+// the other kind are zero / null.
 struct GeomJob {
     const char* src;
     char* meta;
