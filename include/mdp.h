@@ -217,7 +217,10 @@ typedef struct {
 } mdp_source;
 
 /* Drop one reference; the projector is freed with its last reference (the
- * context's cache holds one of its own until mdp_destroy). NULL is a no-op. */
+ * context's cache holds one of its own until mdp_destroy or mdp_cache_clear).
+ * Its device buffers go back to the context, whose later calls reuse them in
+ * stream order after its earlier calls: device work of the caller's own that
+ * reads Q must have completed when the last reference goes.  NULL is a no-op. */
 void mdp_projector_release(mdp_projector* P);
 
 /* Step 2 of Sec. 3.5.  subs (host, n_sub) are the subdomains; P[i] is
@@ -308,8 +311,9 @@ int mdp_cheb_coeffs(int m_star, const mdp_c128* samples, mdp_c128* d);
 
 /* Drop the context's own reference to every cached projector (projectors the
  * caller still holds stay valid) so that the next mdp_build_projector
- * recomputes Q.  AP plans (sine matrices, per-mode tridiagonal factors) and
- * workspaces are kept.  Errors: MDP_ERR_ARG (ctx == NULL). */
+ * recomputes Q.  AP plans (sine matrices, per-mode tridiagonal factors),
+ * geometries and workspaces are kept.  Does not wait for the device.
+ * Errors: MDP_ERR_ARG (ctx == NULL). */
 int mdp_cache_clear(mdp_ctx* ctx);
 
 /* Per-launch profiling of the context's kernels: while enabled, every kernel

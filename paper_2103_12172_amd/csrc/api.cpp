@@ -103,6 +103,30 @@ using GeomKey = std::tuple<double, double, int>;
 
 }  // namespace
 
+namespace {
+
+// Offsets of the interface solve's tables in its upload.
+struct IfaceOffs {
+    size_t qsrc, qld, roff, cmap, coef, kcol, kval, koff, esrc, ecoef, eknown, sf, sjet, sgoff, sfoff;
+};
+
+// The host side of the last interface solve without sources (packed description, elimination tree and the
+// device tables of both), kept for the next call with the same layout, side kinds and coefficients and M*.
+// The tables hold workspace addresses (the packed matrix, the factor arena): they are valid while those
+// buffers are the ones recorded here.
+struct IfaceCache {
+    bool valid = false;
+    std::vector<double> key;
+    PackedHost ph;
+    HostBlob blob;
+    PackedTables tabs{};
+    IfaceOffs o{};
+    const void* ap = nullptr;
+    const void* mf = nullptr;
+};
+
+}  // namespace
+
 struct mdp_ctx {
     int device = 0;
     std::string err;
@@ -118,6 +142,7 @@ struct mdp_ctx {
     // key of the interface system whose Gram factor the workspaces hold (projector builds, side
     // kinds and coefficients, M*, route); empty when none is valid
     std::vector<double> iface_key;
+    IfaceCache icache;
     hipEvent_t last = nullptr;   // end of the previous call's work (workspaces are shared)
     hipStream_t last_stream = nullptr;
     bool have_last = false;
@@ -1042,8 +1067,28 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
         std::vector<const double2*> qsrc(n_sub);
         std::vector<int> qld(n_sub);
         for (int i = 0; i < n_sub; ++i) { qsrc[i] = P[i]->Q.as<const double2>(); qld[i] = P[i]->g.n_gamma; }
+        // The host side below (packed description, elimination tree, tables) depends on the layout, the side
+        // kinds and coefficients and M* only: it is kept from the last call of the same structure (without
+        // sources), whose tables then get this call's projector addresses and boundary data.
+        bool has_src = false;
+        for (int i = 0; sources && i < n_sub; ++i) has_src = has_src || sources[i].f != nullptr;
+        std::vector<double> skey{(double)M, multifrontal ? 1.0 : 0.0, (double)n_sub};
+        for (int i = 0; i < n_sub; ++i) {
+            skey.insert(skey.end(), {sd[i].x0, sd[i].y0, sd[i].lx, sd[i].ly, (double)sd[i].n, (double)qld[i]});
+            for (int s = 0; s < 4; ++s) {
+                const mdp_side& q = sides[4 * i + s];
+                skey.insert(skey.end(), {(double)q.kind, q.kind == 0 ? q.alpha : (double)q.nbr,
+                                         q.kind == 0 ? q.beta : (double)q.nbr_side});
+            }
+        }
+        IfaceCache& ic = ctx->icache;
+        const bool plan_hit = !has_src && ic.valid && ic.key == skey && ic.ap == ctx->ws.pk.Ap.p &&
+                              ic.mf == ctx->ws.pk.mf.p;
+        if (!plan_hit) ic.valid = false;
         // block-sparse description: subdomain i's rows touch only the unknown blocks with a contribution from i
-        PackedHost ph;
+        PackedHost ph_new;
+        if (!plan_hit) {
+        PackedHost& ph = ph_new;
         ph.n_sub = n_sub;
         ph.nc = ncol;
         ph.steps = chol_steps;
@@ -1094,6 +1139,7 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
                 throw Error(MDP_ERR_ARG, "interface front too large for the multifrontal solve");
             ph.multifrontal = true;
         }
+        }
 
         // step 1c: subdomains with a source, grouped by projector (one batched AP solve per group)
         struct SrcGroup { const mdp_projector* P; int R; size_t e0; };
@@ -1129,14 +1175,39 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
         ensure(x, (size_t)ncol * sizeof(double2));
         if (srcw_elems) ensure(cw.srcw, (size_t)srcw_elems * sizeof(double2));
         // every table of the call in one upload
-        HostBlob blob;
-        const size_t o_qsrc = blob.put(qsrc), o_qld = blob.put(qld), o_roff = blob.put(row_off),
-                     o_cmap = blob.put(colmap), o_coef = blob.put(coefs), o_kcol = blob.put(kcol),
-                     o_kval = blob.put(kval), o_koff = blob.put(koff), o_esrc = blob.put(esrc),
-                     o_ecoef = blob.put(ecoef), o_eknown = blob.put(eknown);
-        const size_t o_sf = blob.put(s_f), o_sjet = blob.put(s_jet), o_sgoff = blob.put(s_goff),
-                     o_sfoff = blob.put(s_foff);
-        const PackedTables tabs = ls_packed_tables(ctx->ws, ph, blob);
+        HostBlob blob_new;
+        PackedTables tabs_new{};
+        IfaceOffs o_new{};
+        if (!plan_hit) {
+            HostBlob& blob = blob_new;
+            o_new = IfaceOffs{blob.put(qsrc), blob.put(qld), blob.put(row_off), blob.put(colmap), blob.put(coefs),
+                              blob.put(kcol), blob.put(kval), blob.put(koff), blob.put(esrc), blob.put(ecoef),
+                              blob.put(eknown), blob.put(s_f), blob.put(s_jet), blob.put(s_goff), blob.put(s_foff)};
+            tabs_new = ls_packed_tables(ctx->ws, ph_new, blob);
+            if (!has_src) {
+                ic.key = skey;
+                ic.ph = std::move(ph_new);
+                ic.blob = std::move(blob_new);
+                ic.tabs = tabs_new;
+                ic.o = o_new;
+                ic.ap = ctx->ws.pk.Ap.p;
+                ic.mf = ctx->ws.pk.mf.p;
+                ic.valid = true;
+            }
+        } else {   // this call's projectors and known coefficients into the kept tables
+            ic.ph.Q = qsrc;
+            ic.blob.put_at(ic.o.qsrc, qsrc);
+            ic.blob.put_at(ic.tabs.Q, qsrc);
+            ic.blob.put_at(ic.o.kval, kval);
+            ic.blob.put_at(ic.o.eknown, eknown);
+        }
+        const PackedHost& ph = ic.valid ? ic.ph : ph_new;
+        const HostBlob& blob = ic.valid ? ic.blob : blob_new;
+        const PackedTables& tabs = ic.valid ? ic.tabs : tabs_new;
+        const IfaceOffs& O = ic.valid ? ic.o : o_new;
+        const size_t o_qsrc = O.qsrc, o_qld = O.qld, o_roff = O.roff, o_cmap = O.cmap, o_coef = O.coef,
+                     o_kcol = O.kcol, o_kval = O.kval, o_koff = O.koff, o_esrc = O.esrc, o_ecoef = O.ecoef,
+                     o_eknown = O.eknown, o_sf = O.sf, o_sjet = O.sjet, o_sgoff = O.sgoff, o_sfoff = O.sfoff;
         const char* img = ctx->ws.stage.upload(blob, st);
         auto dq = reinterpret_cast<const double2* const*>(img + o_qsrc);
         auto dld = reinterpret_cast<const int*>(img + o_qld);
@@ -1778,7 +1849,7 @@ int mdp_ap_solve(mdp_ctx* ctx, int n, double h, double k, int precision, int bat
 int mdp_cache_clear(mdp_ctx* ctx) {
     if (!ctx) return MDP_ERR_ARG;
     return guarded(ctx, [&]() -> int {
-        MDP_HIP(hipDeviceSynchronize());
+        // released buffers are reused only by later calls, in stream order after this context's work
         for (auto& kv : ctx->cache) mdp_projector_release(kv.second);
         ctx->cache.clear();
         return MDP_OK;

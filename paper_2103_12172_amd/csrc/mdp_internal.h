@@ -80,6 +80,12 @@ public:
     size_t put(const std::vector<T>& v) { return put(v.data(), v.size()); }
     size_t size() const { return data_.size(); }
     const char* data() const { return data_.data(); }
+    // rewrite v at an offset an earlier put of the same size returned
+    template <class T>
+    void put_at(size_t off, const std::vector<T>& v) {
+        if (off + v.size() * sizeof(T) > data_.size()) throw Error(MDP_ERR_ARG, "table rewrite out of range");
+        if (!v.empty()) std::memcpy(data_.data() + off, v.data(), v.size() * sizeof(T));
+    }
 
 private:
     std::vector<char> data_;

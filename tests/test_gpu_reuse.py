@@ -50,3 +50,32 @@ def test_factor_reused_for_new_data(ctx, path):
     print("%s: reused factor vs fresh solve, c rel diff %.3e (residuals %.3e / %.3e)"
           % (path, err, r2.rel_residual, r3.rel_residual))
     assert err < 1e-12 * max(1.0, (r3.cond or 1.0) / 100.0)
+
+
+@pytest.mark.parametrize("path", ["dense", "multifrontal"])
+def test_host_tables_kept_across_projectors_and_data(ctx, path):
+    """The host side of the interface solve (packed description, elimination tree, device tables) is kept for
+    the next call of the same layout; that call's projector addresses and boundary data go into the kept
+    tables.  One layout at two wavenumbers (other projectors) and two plane waves, alternating with another
+    layout, every solve against the same solve in a fresh context."""
+    wa1 = wl.config_cross_point(n=64, k=20.0, m_star=16, seed=2)
+    wa2 = wl.config_cross_point(n=64, k=23.0, m_star=16, seed=7)
+    wb = wl.config_two_rect(n=64, k=10.0, m_star=16)
+    mdp.mdp_set_interface_path(ctx, path)
+    got = []
+    try:
+        for w in (wa1, wb, wa2, wa1, wa2):
+            got.append(dd.dd_solve(ctx, w, "c128").c.cpu().numpy())
+    finally:
+        mdp.mdp_set_interface_path(ctx, "auto")
+    for w, c in zip((wa1, wb, wa2, wa1, wa2), got):
+        fresh = mdp.mdp_create(0)
+        try:
+            mdp.mdp_set_interface_path(fresh, path)
+            ref = dd.dd_solve(fresh, w, "c128").c.cpu().numpy()
+            torch.cuda.synchronize()
+        finally:
+            fresh.close()
+        err = float(np.abs(c - ref).max() / np.abs(ref).max())
+        print("%s k=%.0f: kept tables vs fresh context, c rel diff %.3e" % (path, w.subdomains[0].k, err))
+        assert err < 1e-12
