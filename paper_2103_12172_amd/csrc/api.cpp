@@ -121,6 +121,8 @@ struct IfaceCache {
     HostBlob blob;
     PackedTables tabs{};
     IfaceOffs o{};
+    size_t dyn_end = 0;   // the per-call part (projector addresses, known coefficients) is blob[0, dyn_end)
+    DevBuf image;         // the device copy of blob
     const void* ap = nullptr;
     const void* mf = nullptr;
 };
@@ -1180,35 +1182,55 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
         IfaceOffs o_new{};
         if (!plan_hit) {
             HostBlob& blob = blob_new;
-            o_new = IfaceOffs{blob.put(qsrc), blob.put(qld), blob.put(row_off), blob.put(colmap), blob.put(coefs),
-                              blob.put(kcol), blob.put(kval), blob.put(koff), blob.put(esrc), blob.put(ecoef),
-                              blob.put(eknown), blob.put(s_f), blob.put(s_jet), blob.put(s_goff), blob.put(s_foff)};
+            // the per-call part first (one contiguous range to rewrite when the tables are kept)
+            o_new.qsrc = blob.put(qsrc);
+            o_new.kval = blob.put(kval);
+            o_new.eknown = blob.put(eknown);
+            const size_t dyn_end = blob.size();
+            o_new.qld = blob.put(qld);
+            o_new.roff = blob.put(row_off);
+            o_new.cmap = blob.put(colmap);
+            o_new.coef = blob.put(coefs);
+            o_new.kcol = blob.put(kcol);
+            o_new.koff = blob.put(koff);
+            o_new.esrc = blob.put(esrc);
+            o_new.ecoef = blob.put(ecoef);
+            o_new.sf = blob.put(s_f);
+            o_new.sjet = blob.put(s_jet);
+            o_new.sgoff = blob.put(s_goff);
+            o_new.sfoff = blob.put(s_foff);
             tabs_new = ls_packed_tables(ctx->ws, ph_new, blob);
+            tabs_new.Q = o_new.qsrc;   // the same projector addresses, kept in the per-call part
             if (!has_src) {
                 ic.key = skey;
                 ic.ph = std::move(ph_new);
                 ic.blob = std::move(blob_new);
                 ic.tabs = tabs_new;
                 ic.o = o_new;
+                ic.dyn_end = dyn_end;
                 ic.ap = ctx->ws.pk.Ap.p;
                 ic.mf = ctx->ws.pk.mf.p;
+                if (ic.image.bytes < ic.blob.size()) {
+                    MDP_HIP(hipDeviceSynchronize());   // earlier calls may still read the old copy
+                    ic.image.alloc(ic.blob.size());
+                }
+                ctx->ws.stage.copy(ic.image.p, ic.blob, st);
                 ic.valid = true;
             }
-        } else {   // this call's projectors and known coefficients into the kept tables
+        } else {   // this call's projectors and known coefficients into the kept tables and their device copy
             ic.ph.Q = qsrc;
             ic.blob.put_at(ic.o.qsrc, qsrc);
-            ic.blob.put_at(ic.tabs.Q, qsrc);
             ic.blob.put_at(ic.o.kval, kval);
             ic.blob.put_at(ic.o.eknown, eknown);
+            ctx->ws.stage.copy(ic.image.p, ic.blob.data(), ic.dyn_end, st);
         }
         const PackedHost& ph = ic.valid ? ic.ph : ph_new;
-        const HostBlob& blob = ic.valid ? ic.blob : blob_new;
         const PackedTables& tabs = ic.valid ? ic.tabs : tabs_new;
         const IfaceOffs& O = ic.valid ? ic.o : o_new;
         const size_t o_qsrc = O.qsrc, o_qld = O.qld, o_roff = O.roff, o_cmap = O.cmap, o_coef = O.coef,
                      o_kcol = O.kcol, o_kval = O.kval, o_koff = O.koff, o_esrc = O.esrc, o_ecoef = O.ecoef,
                      o_eknown = O.eknown, o_sf = O.sf, o_sjet = O.sjet, o_sgoff = O.sgoff, o_sfoff = O.sfoff;
-        const char* img = ctx->ws.stage.upload(blob, st);
+        const char* img = ic.valid ? ic.image.as<const char>() : ctx->ws.stage.upload(blob_new, st);
         auto dq = reinterpret_cast<const double2* const*>(img + o_qsrc);
         auto dld = reinterpret_cast<const int*>(img + o_qld);
         auto droff = reinterpret_cast<const int*>(img + o_roff);

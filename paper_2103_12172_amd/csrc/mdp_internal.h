@@ -118,8 +118,10 @@ struct Staging {
         }
     }
     // copy b to the device address dst on st
-    void copy(void* dst, const HostBlob& b, hipStream_t st) {
-        if (!b.size()) return;
+    void copy(void* dst, const HostBlob& b, hipStream_t st) { copy(dst, b.data(), b.size(), st); }
+    // copy n bytes at src (host) to the device address dst on st
+    void copy(void* dst, const char* src, size_t n, hipStream_t st) {
+        if (!n) return;
         // a slot whose last copy has completed, else the next one in turn (waited for)
         int pick = -1;
         for (int i = 0; i < kSlots && pick < 0; ++i) {
@@ -132,16 +134,16 @@ struct Staging {
         if (!s.done) MDP_HIP(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
         if (s.pending) MDP_HIP(hipEventSynchronize(s.done));
         s.pending = false;
-        if (b.size() > s.cap) {
-            const size_t want = std::max<size_t>({b.size(), 2 * s.cap, (size_t)1 << 16});
+        if (n > s.cap) {
+            const size_t want = std::max<size_t>({n, 2 * s.cap, (size_t)1 << 16});
             if (s.host) MDP_HIP(hipHostFree(s.host));
             s.host = nullptr;
             s.cap = 0;
             MDP_HIP(hipHostMalloc(&s.host, want, hipHostMallocDefault));
             s.cap = want;
         }
-        std::memcpy(s.host, b.data(), b.size());
-        MDP_HIP(hipMemcpyAsync(dst, s.host, b.size(), hipMemcpyHostToDevice, st));
+        std::memcpy(s.host, src, n);
+        MDP_HIP(hipMemcpyAsync(dst, s.host, n, hipMemcpyHostToDevice, st));
         MDP_HIP(hipEventRecord(s.done, st));
         s.pending = true;
     }
