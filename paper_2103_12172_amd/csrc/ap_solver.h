@@ -27,8 +27,30 @@ struct APPlan {
 };
 
 // Least-squares buffers (grow-only).
+// Pinned host memory for small device-to-host reads (grow-only; every read is
+// followed by a wait for its stream, so a regrowth never frees memory a copy uses).
+struct HostPinned {
+    void* p = nullptr;
+    size_t bytes = 0;
+    HostPinned() = default;
+    HostPinned(const HostPinned&) = delete;
+    HostPinned& operator=(const HostPinned&) = delete;
+    ~HostPinned() { if (p) (void)hipHostFree(p); }
+    void* get(size_t b) {
+        if (b > bytes) {
+            if (p) MDP_HIP(hipHostFree(p));
+            p = nullptr;
+            bytes = 0;
+            MDP_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+            bytes = b;
+        }
+        return p;
+    }
+};
+
 struct LSWork {
     DevBuf G, L, Linv[3], T, A0, Aq, vec, norms, flags;
+    HostPinned hflags;   // the flags' host copy
 };
 
 // Packed interface matrix buffers (grow-only).

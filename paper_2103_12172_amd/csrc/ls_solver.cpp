@@ -715,9 +715,11 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
         }
     };
     PackedFlags hf{};
+    PackedFlags* hpin = static_cast<PackedFlags*>(lw.hflags.get(sizeof(PackedFlags)));
     auto read_flags = [&]() {
-        MDP_HIP(hipMemcpyAsync(&hf, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
+        MDP_HIP(hipMemcpyAsync(hpin, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
         MDP_HIP(hipStreamSynchronize(st));
+        hf = *hpin;
         if (hf.badcol & 2) throw Error(MDP_ERR_NONFINITE, "non-finite entry in the interface matrix");
         if (hf.badcol & 1) throw Error(MDP_ERR_SINGULAR, "zero column in the interface matrix");
     };
@@ -778,8 +780,9 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
                 launch_znormalize(nc, v1, &fl->pw[which], st);
             }
         }
-        MDP_HIP(hipMemcpyAsync(&hf, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
+        MDP_HIP(hipMemcpyAsync(hpin, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
         MDP_HIP(hipStreamSynchronize(st));
+        hf = *hpin;
         res.cond = std::sqrt(hf.pw[0] * hf.pw[1]);
     }
     return res;
