@@ -274,16 +274,29 @@ __device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double
                           double2* __restrict__ Lout, int ldl, double2* __restrict__ Zout, int ldz) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;   // tile row, column group (columns 4g..4g+3)
-    for (int e = tid; e < 64 * 64; e += blockDim.x) {
+    // the block into LDS: all of a thread's loads are issued before the first is waited for
+    // (a rolled loop would wait for each load in turn)
+    auto entry = [&](int e, double2 v) {
         const int i = e & 63, j = e >> 6;   // consecutive threads: consecutive rows of a column
-        double2 v = make_double2(0.0, 0.0);
         if (j <= i) {
-            if (i < nb) v = G[i + (long)j * ldg];
-            else if (i == j) v = make_double2(1.0, 0.0);
+            if (i >= nb && i == j) v = make_double2(1.0, 0.0);
             if (i == j && i < nb) v.x += shift;
         }
         s.S[i][j] = v;
         s.Z[i][j] = make_double2(0.0, 0.0);
+    };
+    auto load = [&](int e) {
+        const int i = e & 63, j = e >> 6;
+        return (j <= i && i < nb) ? G[i + (long)j * ldg] : make_double2(0.0, 0.0);
+    };
+    if (blockDim.x == 256) {
+        double2 v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = load(tid + 256 * u);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) entry(tid + 256 * u, v[u]);
+    } else {
+        for (int e = tid; e < 64 * 64; e += blockDim.x) entry(e, load(e));
     }
     __syncthreads();
     int bad = 0;
@@ -468,9 +481,18 @@ __device__ inline void chol_panel_body(const double2* __restrict__ G, int nc, co
     if (role <= np) {
         // rows i0..i0+31: S[r][k] = G(i0 + r, kq + k); thread rows 2tr + {0,1}, columns 4tc + {0..3}
         const int i0 = r0 + 32 * (role - 1);
-        for (int e = tid; e < 32 * 64; e += 256) {
-            const int rr = e & 31, k = e >> 5, i = i0 + rr;   // consecutive threads: consecutive rows
-            s.S[rr][k] = (i < nc && k < nbq) ? G[i + (long)(kq + k) * nc] : make_double2(0.0, 0.0);
+        {
+            double2 v[8];   // every load issued before the first wait
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = tid + 256 * u, rr = e & 31, k = e >> 5, i = i0 + rr;   // consecutive threads: rows
+                v[u] = (i < nc && k < nbq) ? G[i + (long)(kq + k) * nc] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = tid + 256 * u;
+                s.S[e & 31][e >> 5] = v[u];
+            }
         }
         __syncthreads();
         double ar[2][4] = {}, ai[2][4] = {};
@@ -508,9 +530,18 @@ __device__ inline void chol_panel_body(const double2* __restrict__ G, int nc, co
     // columns j0..j0+31 (< kb) of block row q of Z: S[k][c] = W(kq + k, j0 + c); thread rows 4tr + {0..3},
     // columns 2tc + {0,1}
     const int j0 = 32 * (role - 1 - np);
-    for (int e = tid; e < 64 * 32; e += 256) {
-        const int k = e >> 5, c = e & 31;
-        s.S[k][c] = (k < nbq && j0 + c < kb) ? W[kq + k + (long)(j0 + c) * nc] : make_double2(0.0, 0.0);
+    {
+        double2 v[8];   // every load issued before the first wait
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u, k = e >> 5, c = e & 31;
+            v[u] = (k < nbq && j0 + c < kb) ? W[kq + k + (long)(j0 + c) * nc] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;
+            s.S[e >> 5][e & 31] = v[u];
+        }
     }
     __syncthreads();
     double zr[4][2] = {}, zi[4][2] = {};
@@ -602,18 +633,27 @@ __device__ inline void chol_update_body(double2* __restrict__ G, int nc, int kb,
     double cr[2][2] = {}, ci[2][2] = {};
     for (int k0 = kb; k0 < r0; k0 += 64) {
         const int kn = min(64, r0 - k0);
-        if (k0 > kb) __syncthreads();   // the previous chunk's operands are consumed
-        for (int e = tid; e < 64 * 32; e += 256) {
-            const int k = e >> 5, r = e & 31;
+        // both operands' loads of the chunk issued before the first wait
+        double2 av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u, k = e >> 5, r = e & 31;
             const int i = i0 + r, j = j0 + r;
             const bool kin = k < kn;
-            A[k][r] = (kin && i < nc) ? L[i + (long)(k0 + k) * nc] : make_double2(0.0, 0.0);
+            av[u] = (kin && i < nc) ? L[i + (long)(k0 + k) * nc] : make_double2(0.0, 0.0);
             if (trail) {
                 const double2 v = (kin && j < nc) ? L[j + (long)(k0 + k) * nc] : make_double2(0.0, 0.0);
-                B[k][r] = make_double2(v.x, -v.y);
+                bv[u] = make_double2(v.x, -v.y);
             } else {
-                B[k][r] = (kin && j < r0) ? Z[k0 + k + (long)j * nc] : make_double2(0.0, 0.0);
+                bv[u] = (kin && j < r0) ? Z[k0 + k + (long)j * nc] : make_double2(0.0, 0.0);
             }
+        }
+        if (k0 > kb) __syncthreads();   // the previous chunk's operands are consumed
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u, k = e >> 5, r = e & 31;
+            A[k][r] = av[u];
+            B[k][r] = bv[u];
         }
         __syncthreads();
         for (int kk0 = 0; kk0 < 64; kk0 += 4) {
