@@ -477,7 +477,6 @@ __device__ inline void chol_panel_body(const double2* __restrict__ G, int nc, co
         if (tid == 0 && bad && info) atomicCAS(info, 0, kq + bad);
         return;
     }
-    const int tr = tid >> 4, tc = tid & 15;   // 16 x 16 threads
     if (role <= np) {
         // rows i0..i0+31: S[r][k] = G(i0 + r, kq + k); thread rows 2tr + {0,1}, columns 4tc + {0..3}
         const int i0 = r0 + 32 * (role - 1);
@@ -495,36 +494,34 @@ __device__ inline void chol_panel_body(const double2* __restrict__ G, int nc, co
             }
         }
         __syncthreads();
-        double ar[2][4] = {}, ai[2][4] = {};
-        for (int k0 = 0; k0 < 64; k0 += 2) {
-            double2 gv[2][2], zv[2][4];   // L(i,c) = sum_k G(i,k) conj(Z(c,k)); operands of 2 k first
+        // L(i,c) = sum_k G(i,k) conj(Z(c,k)) on the matrix cores: 32 x 64 as 2 x 4 tiles of 16 x 16,
+        // two per wavefront (tile row wave >> 1, tile columns 2 (wave & 1) + {0, 1}); A operand
+        // lane (row lane & 15, k lane >> 4), B operand lane (k lane >> 4, column lane & 15), result
+        // rows (lane >> 4) + 4 r of each tile
+        const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
+        const int ti = wv >> 1;
+        d4 cr[2], ci[2];
 #pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
+        for (int t = 0; t < 2; ++t) { cr[t] = d4{0, 0, 0, 0}; ci[t] = d4{0, 0, 0, 0}; }
+#pragma unroll 4
+        for (int k0 = 0; k0 < 64; k0 += 4) {
+            const double2 a = s.S[16 * ti + lr][k0 + lk];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) gv[kk][a] = s.S[2 * tr + a][k0 + kk];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) zv[kk][b] = s.Z[4 * tc + b][k0 + kk];
-            }
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-#pragma unroll
-                    for (int a = 0; a < 2; ++a) {
-                        const double2 g = gv[kk][a], z = zv[kk][b];
-                        ar[a][b] = fma(g.x, z.x, fma(g.y, z.y, ar[a][b]));
-                        ai[a][b] = fma(g.y, z.x, fma(-g.x, z.y, ai[a][b]));
-                    }
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int i = i0 + 2 * tr + a;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int c = 4 * tc + b;
-                if (i < nc && c < nbq) L[i + (long)(kq + c) * nc] = make_double2(ar[a][b], ai[a][b]);
+            for (int t = 0; t < 2; ++t) {
+                const double2 z = s.Z[16 * (2 * (wv & 1) + t) + lr][k0 + lk];   // B = conj(Z)^T
+                cr[t] = mfma64(a.x, z.x, cr[t]);
+                cr[t] = mfma64(a.y, z.y, cr[t]);
+                ci[t] = mfma64(-a.x, z.y, ci[t]);
+                ci[t] = mfma64(a.y, z.x, ci[t]);
             }
         }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + 16 * ti + lk + 4 * r, c = 16 * (2 * (wv & 1) + t) + lr;
+                if (i < nc && c < nbq) L[i + (long)(kq + c) * nc] = make_double2(cr[t][r], ci[t][r]);
+            }
         return;
     }
     // columns j0..j0+31 (< kb) of block row q of Z: S[k][c] = W(kq + k, j0 + c); thread rows 4tr + {0..3},
@@ -544,37 +541,32 @@ __device__ inline void chol_panel_body(const double2* __restrict__ G, int nc, co
         }
     }
     __syncthreads();
-    double zr[4][2] = {}, zi[4][2] = {};
-    for (int k0 = 0; k0 < 64; k0 += 2) {
-        double2 wv[2][2], zv[2][4];   // operands of 2 k first
+    // Z(q, j) = Z(q,q) W(q, j) on the matrix cores: 64 x 32 as 4 x 2 tiles of 16 x 16, two per
+    // wavefront (tile rows 2 (wave >> 1) + {0, 1}, tile column wave & 1); layouts as above
+    const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
+    const int tj = wv & 1;
+    d4 cr[2], ci[2];
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
+    for (int t = 0; t < 2; ++t) { cr[t] = d4{0, 0, 0, 0}; ci[t] = d4{0, 0, 0, 0}; }
+#pragma unroll 4
+    for (int k0 = 0; k0 < 64; k0 += 4) {
+        const double2 w = s.S[k0 + lk][16 * tj + lr];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) wv[kk][b] = s.S[k0 + kk][2 * tc + b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) zv[kk][a] = s.Z[4 * tr + a][k0 + kk];
-        }
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const double2 z = zv[kk][a], w = wv[kk][b];
-                    zr[a][b] = fma(z.x, w.x, fma(-z.y, w.y, zr[a][b]));
-                    zi[a][b] = fma(z.x, w.y, fma(z.y, w.x, zi[a][b]));
-                }
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int rr = 4 * tr + a;
-        if (rr >= nbq) continue;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int j = j0 + 2 * tc + b;
-            if (j < kb) Z[kq + rr + (long)j * nc] = make_double2(zr[a][b], zi[a][b]);
+        for (int t = 0; t < 2; ++t) {
+            const double2 z = s.Z[16 * (2 * (wv >> 1) + t) + lr][k0 + lk];
+            cr[t] = mfma64(z.x, w.x, cr[t]);
+            cr[t] = mfma64(-z.y, w.y, cr[t]);
+            ci[t] = mfma64(z.x, w.y, ci[t]);
+            ci[t] = mfma64(z.y, w.x, ci[t]);
         }
     }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rr = 16 * (2 * (wv >> 1) + t) + lk + 4 * r, j = j0 + 16 * tj + lr;
+            if (rr < nbq && j < kb) Z[kq + rr + (long)j * nc] = make_double2(cr[t][r], ci[t][r]);
+        }
 }
 
 
@@ -629,8 +621,12 @@ __device__ inline void chol_update_body(double2* __restrict__ G, int nc, int kb,
         j0 = 32 * (t / ntr);
         trail = false;
     }
-    const int tr = tid >> 4, tc = tid & 15;
-    double cr[2][2] = {}, ci[2][2] = {};
+    // the 32 x 32 tile on the matrix cores: one 16 x 16 quarter per wavefront (rows 16 (wave >> 1),
+    // columns 16 (wave & 1)); A operand lane (row lane & 15, k lane >> 4), B operand lane (k lane >> 4,
+    // column lane & 15), result rows (lane >> 4) + 4 r
+    const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
+    const int ti = wv >> 1, tj = wv & 1;
+    d4 cr = d4{0, 0, 0, 0}, ci = d4{0, 0, 0, 0};
     for (int k0 = kb; k0 < r0; k0 += 64) {
         const int kn = min(64, r0 - k0);
         // both operands' loads of the chunk issued before the first wait
@@ -656,40 +652,29 @@ __device__ inline void chol_update_body(double2* __restrict__ G, int nc, int kb,
             B[k][r] = bv[u];
         }
         __syncthreads();
+#pragma unroll 4
         for (int kk0 = 0; kk0 < 64; kk0 += 4) {
-            double2 a[4][2], b[4][2];   // one round of operands loaded before any arithmetic
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    a[kk][u] = A[kk0 + kk][2 * tr + u];
-                    b[kk][u] = B[kk0 + kk][2 * tc + u];
-                }
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int v = 0; v < 2; ++v) {
-                        cr[u][v] = fma(a[kk][u].x, b[kk][v].x, fma(-a[kk][u].y, b[kk][v].y, cr[u][v]));
-                        ci[u][v] = fma(a[kk][u].x, b[kk][v].y, fma(a[kk][u].y, b[kk][v].x, ci[u][v]));
-                    }
+            const double2 a = A[kk0 + lk][16 * ti + lr], b = B[kk0 + lk][16 * tj + lr];
+            cr = mfma64(a.x, b.x, cr);
+            cr = mfma64(-a.y, b.y, cr);
+            ci = mfma64(a.x, b.y, ci);
+            ci = mfma64(a.y, b.x, ci);
         }
     }
     double2* C = trail ? G : W;
+    const int j = j0 + 16 * tj + lr;
+    bool ok[4];
+    double2 cv[4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int i = i0 + 2 * tr + u;
-        if (i >= nc) continue;
+    for (int r = 0; r < 4; ++r) {   // every load before the first wait
+        const int i = i0 + 16 * ti + lk + 4 * r;
+        ok[r] = i < nc && j < nc && !(trail && j > i) && !(!trail && j >= r0);
+        cv[r] = ok[r] ? C[i + (long)j * nc] : make_double2(0.0, 0.0);
+    }
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int j = j0 + 2 * tc + v;
-            if (j >= nc || (trail && j > i) || (!trail && j >= r0)) continue;
-            double2 c = C[i + (long)j * nc];
-            c.x -= cr[u][v];
-            c.y -= ci[u][v];
-            C[i + (long)j * nc] = c;
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * ti + lk + 4 * r;
+        if (ok[r]) C[i + (long)j * nc] = make_double2(cv[r].x - cr[r], cv[r].y - ci[r]);
     }
 }
 
