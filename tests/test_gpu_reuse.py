@@ -79,3 +79,18 @@ def test_host_tables_kept_across_projectors_and_data(ctx, path):
         err = float(np.abs(c - ref).max() / np.abs(ref).max())
         print("%s k=%.0f: kept tables vs fresh context, c rel diff %.3e" % (path, w.subdomains[0].k, err))
         assert err < 1e-12
+
+
+def test_interface_solve_repeats_bit_for_bit(ctx):
+    """The dense route's factorisation and refinement sum in a fixed order (no atomics in any product):
+    the same DD solve twice, projectors rebuilt in between, gives identical coefficients."""
+    w = wl.config_cross_point(n=64, k=20.0, m_star=16, seed=3)
+    mdp.mdp_set_interface_path(ctx, "dense")
+    try:
+        mdp.mdp_cache_clear(ctx)
+        c1 = dd.dd_solve(ctx, w, "c128").c.cpu().numpy()
+        mdp.mdp_cache_clear(ctx)
+        c2 = dd.dd_solve(ctx, w, "c128").c.cpu().numpy()
+    finally:
+        mdp.mdp_set_interface_path(ctx, "auto")
+    assert np.array_equal(c1, c2)
