@@ -803,13 +803,6 @@ __global__ void __launch_bounds__(256) gamma_index_jobs_kernel(const GeomJob* __
         jb.gidx[jb.gm[i] * (jb.n + 1) + jb.gq[i]] = (int)i;
 }
 
-// gidx[gm[i] (n+1) + gq[i]] = i (the map was filled with -1)
-__global__ void gamma_index_kernel(const int* __restrict__ gm, const int* __restrict__ gq, int ng, int n,
-                                   int* __restrict__ gidx) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ng) gidx[gm[i] * (n + 1) + gq[i]] = i;
-}
-
 inline unsigned grid_for(long total, int block = 256) {
     long g = (total + block - 1) / block;
     if (g > 1 << 20) g = 1 << 20;
@@ -1368,12 +1361,6 @@ void launch_geom_setup(const GeomJob* jobs_dev, int count, int max_nodes, hipStr
     hipLaunchKernelGGL(geom_setup_kernel, dim3(gx, count), dim3(256), 0, st, jobs_dev);
     MDP_HIP(hipGetLastError());
     hipLaunchKernelGGL(gamma_index_jobs_kernel, dim3(std::min(gx, 16u), count), dim3(256), 0, st, jobs_dev);
-    MDP_HIP(hipGetLastError());
-}
-
-void launch_gamma_index(const int* gm, const int* gq, int ng, int n, int* gidx, hipStream_t st) {
-    if (ng <= 0) return;
-    hipLaunchKernelGGL(gamma_index_kernel, dim3((ng + 255) / 256), dim3(256), 0, st, gm, gq, ng, n, gidx);
     MDP_HIP(hipGetLastError());
 }
 

@@ -1149,13 +1149,6 @@ __global__ void gram_scatter_kernel(const ZBatch* __restrict__ zb, const double2
     atomicAdd(&o[1], g1 >= g2 ? si : -si);
 }
 
-// G(gcol(p1), gcol(p2)) += Gi(p1, p2) for the packed columns of one subdomain
-// y += x (complex vectors)
-__global__ void zaxpy1_kernel(int n, const double2* __restrict__ x, double2* y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) { y[i].x += x[i].x; y[i].y += x[i].y; }
-}
-
 // Qbar(r, c) for rows of subdomain s: sum of up to two weighted columns of Q_s.
 // colmap[s*ncol + c] = (colA, colB, -, -) with -1 = absent; coefs likewise (2 per entry).
 __global__ void assemble_qbar_kernel(const double2* const* __restrict__ Qsrc, const int* __restrict__ qld, int n_sub,
@@ -1499,11 +1492,6 @@ void launch_packed_axpy(const PackedDevice& d, int n_sub, int max_m, const doubl
 void launch_zaxpy_norms(int n, const double2* dx, double2* x, double* norms, double* clr, hipStream_t st) {
     const int g = std::max(1, std::min(256, (n + 255) / 256));
     hipLaunchKernelGGL(zaxpy_norms_kernel, dim3(g), dim3(256), 0, st, n, dx, x, norms, clr);
-    MDP_HIP(hipGetLastError());
-}
-
-void launch_zaxpy1(int n, const double2* x, double2* y, hipStream_t st) {
-    hipLaunchKernelGGL(zaxpy1_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, x, y);
     MDP_HIP(hipGetLastError());
 }
 

@@ -239,8 +239,6 @@ Geometry make_geometry(double x0, double y0, double lx, double ly, int n);
 // deriv = 1: the derivative dE/d(k^2) instead of E
 void launch_extension(const int* side, const double* rho, const double* t, const double* slen, int ng, double k,
                       int m_star, double* E, hipStream_t st, int deriv = 0);
-// gidx[gm[i] (n+1) + gq[i]] = i over a map filled with -1 beforehand
-void launch_gamma_index(const int* gm, const int* gq, int ng, int n, int* gidx, hipStream_t st);
 // One entry of a build's set-up (device pointers).  A geometry new to the context:
 // meta_words 4-byte words of gamma node tables copied from the call's upload (src) to
 // its buffer (meta), and its node -> gamma map gidx ((n+1)^2) written from gm, gq.
@@ -509,7 +507,6 @@ struct ZBatch {
 // nsplit * sum_b n_b^2 partial entries; G must hold the other contributions or zero.
 void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int nsplit, double2* P, const int* gcol,
                          double2* G, int ldg, hipStream_t st);
-void launch_zaxpy1(int n, const double2* x, double2* y, hipStream_t st);
 // y = op(A) x for lower-triangular A (n x n, ld lda), op 'N' or 'C'; y overwritten, fixed summation order.
 void launch_trmv_lower(char op, int n, const double2* A, int lda, const double2* x, double2* y, hipStream_t st);
 // y = A^* v on the packed matrix, one entry per global column (d.gc_start / d.gc_list set), y overwritten.
