@@ -14,8 +14,10 @@ one AP solve per subdomain for its right-hand side), plus the per-kernel
 roofline of the dominant kernel (HIP events around the dominant class's
 launches in a second pass over the same number of steps; the step time comes
 from the pass without events) and the CPU oracle timed on the same workload.
-Workloads: cross_point (default), transmission, two_rect, and bump (the
-cross-point layout with a source term).
+Workloads: uneven (default: the 16x16 layout of squares with AP grids drawn from
+{128, 256, 384, 512} and k from U[20, 80], the largest single-GPU configuration),
+cross_point, transmission, two_rect, bump (the cross-point layout with a source
+term) and adjoint (a cold solve plus the gradient of a receiver misfit).
 """
 from __future__ import annotations
 
@@ -33,6 +35,8 @@ PEAKS = {  # MI355X published peaks
     "hbm": 8000.0,          # GB/s
     "f64": 78.6,            # TFLOP/s: FP64 MFMA; FP64 vector = 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
     "f32": 157.3,           # TFLOP/s (MFMA)
+    "f32v": 157.3,          # TFLOP/s: FP32 vector = 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz x 2 (packed
+                            # dual-issue; this build issues unpacked FP32, i.e. at most half of it)
 }
 ALGO = {
     # kernel class -> (bound, peak key, what "achieved" counts)
@@ -40,6 +44,7 @@ ALGO = {
     "gemm_sine_f32": ("mfma", "f32", "flops"),
     "interface_ls": ("mfma", "f64", "flops"),
     "ap_fused_f64": ("alu", "f64", "flops"),
+    "ap_fused_f32": ("alu", "f32v", "flops"),
     "chol_panel": ("alu", "f64", "flops"),
     "chol_update": ("alu", "f64", "flops"),
     "gram": ("mfma", "f64", "flops"),
@@ -56,7 +61,8 @@ ALGO = {
 }
 # kernel class -> (part of its rocprofv3 kernel name, source file) for the PMC traffic summaries
 KERNELS = {
-    "ap_fused_f64": ("proj_fused_kernel", "paper_2103_12172_amd/csrc/ap_kernels.hip"),
+    "ap_fused_f64": ("proj_sweep_kernel<double", "paper_2103_12172_amd/csrc/proj_sweep.hip"),
+    "ap_fused_f32": ("proj_sweep_kernel<float", "paper_2103_12172_amd/csrc/proj_sweep.hip"),
     "chol_panel": ("chol_panel_kernel", "paper_2103_12172_amd/csrc/ls_kernels.hip"),
     "tridiag_f64": ("tridiag_kernel<double>", "paper_2103_12172_amd/csrc/ap_kernels.hip"),
     "gemm_sine_f64": ("gemm_bd_kernel<double", "paper_2103_12172_amd/csrc/gemm_sine.hip"),
@@ -242,15 +248,60 @@ def warm_ms(ctx, w, prec, sides, reps=5, sources=None):
 
 
 
-def cpu_baseline(w, pts, min_seconds=10.0, max_reps=3):
-    """The CPU oracle, as it stands, on the same workload: full DD solves repeated
-    until about min_seconds of CPU work (at most max_reps)."""
-    from oracle import solve as osolve
+def _oracle_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def _host_info():
+    """Core count and model of the host CPU the oracle runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return {"nproc": nproc, "cpu_model": model}
+
+
+def _oracle_columns(sd, m_star, cols):
+    """The oracle's projector columns `cols` of subdomain sd (one AP solve each); returns
+    (seconds, AP grid points)."""
+    import numpy as np
+    from oracle.grid import APGrid
+    from oracle.projector import build_projector
+    from oracle.scheme import make_solver
+    t0 = time.perf_counter()
+    g = APGrid(sd.x0, sd.y0, sd.lx, sd.ly, sd.n)
+    Q = build_projector(g, sd.k, m_star, make_solver(sd.n, g.h, sd.k), cols=np.asarray(cols))
+    return time.perf_counter() - t0, float(len(cols)) * (sd.n + 1) * (sd.n - 1), Q
+
+
+def _single_thread(sd, m_star, ncols):
+    """The oracle restricted to one thread on ncols projector columns of sd: AP grid points/s."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        dt, pts, _ = _oracle_columns(sd, m_star, list(range(ncols)))
+    return {"value": pts / dt, "unit": "AP grid-points/s", "cores": 1,
+            "sample": "%d projector columns of one subdomain (n = %d), %.2f s" % (ncols, sd.n, dt)}
+
+
+def cpu_baseline(w, pts, min_seconds=10.0, max_reps=3):
+    """The CPU oracle, as it stands, on the same workload: full DD solves repeated
+    until about min_seconds of CPU work (at most max_reps), on every core BLAS and
+    LAPACK use; and on one thread, a bounded sample of projector columns."""
+    from oracle import solve as osolve
+    threads = _oracle_threads()
     reps, total, ores = 0, 0.0, None
     while reps < max_reps and (reps == 0 or total < min_seconds):
         t0 = time.perf_counter()
@@ -258,42 +309,41 @@ def cpu_baseline(w, pts, min_seconds=10.0, max_reps=3):
         total += time.perf_counter() - t0
         reps += 1
     dt = total / reps
-    return ores, {"value": pts / dt, "unit": "AP grid-points/s", "cores": int(threads), "kind": "oracle",
-                  "sample": "%d full cold DD solve(s) of the same workload (every projector column by the separable "
-                            "sine + LAPACK banded tridiagonal route, Householder least squares, reconstruction), "
-                            "%.2f s each" % (reps, dt)}
+    cb = {"value": pts / dt, "unit": "AP grid-points/s", "cores": int(threads), "kind": "oracle",
+          "sample": "%d full cold DD solve(s) of the same workload (every projector column by the separable "
+                    "sine + LAPACK banded tridiagonal route, Householder least squares, reconstruction), "
+                    "%.2f s each" % (reps, dt)}
+    cb.update(_host_info())
+    cb["single_thread"] = _single_thread(w.subdomains[0], w.m_star, 32)
+    return ores, cb
 
 
-def cpu_baseline_sampled(w, res, n_sample=2, seed=5):
+def cpu_baseline_sampled(w, res, seed=5):
     """The CPU oracle on a bounded sample of a layout too large for a full oracle
-    solve: the projectors Q of n_sample seeded subdomains with the smallest grids
-    (every column an AP solve), timed; and those Q against the GPU's."""
-    from oracle.grid import APGrid
-    from oracle.projector import build_projector
-    from oracle.scheme import make_solver
+    solve: every projector column of one seeded subdomain per distinct n (all
+    cores), and a few columns of the smallest one on one thread; the sampled Q
+    against the GPU's."""
     import numpy as np
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    threads = _oracle_threads()
     rng = np.random.default_rng(seed)
-    n_min = min(sd.n for sd in w.subdomains)
-    cand = [i for i, sd in enumerate(w.subdomains) if sd.n == n_min]
-    picks = sorted(rng.choice(cand, size=min(n_sample, len(cand)), replace=False).tolist())
+    picks = []
+    for n in sorted({sd.n for sd in w.subdomains}):
+        cand = [i for i, sd in enumerate(w.subdomains) if sd.n == n]
+        picks.append(int(rng.choice(cand)))
     pts, total, qerr = 0.0, 0.0, 0.0
     for i in picks:
         sd = w.subdomains[i]
-        t0 = time.perf_counter()
-        g = APGrid(sd.x0, sd.y0, sd.lx, sd.ly, sd.n)
-        Q = build_projector(g, sd.k, w.m_star, make_solver(sd.n, g.h, sd.k))
-        total += time.perf_counter() - t0
-        pts += 8 * w.m_star * (sd.n + 1) * (sd.n - 1)
+        dt, p, Q = _oracle_columns(sd, w.m_star, list(range(8 * w.m_star)))
+        total += dt
+        pts += p
         qg = res.projectors[i].q_tensor().cpu().numpy()
         qerr = max(qerr, float(np.abs(qg - Q).max() / np.abs(Q).max()))
     cb = {"value": pts / total, "unit": "AP grid-points/s", "cores": int(threads), "kind": "oracle",
-          "sample": "projectors Q of subdomains %s (n = %d, %d AP solves each by the separable sine + LAPACK banded "
-                    "tridiagonal route), %.2f s in all" % (picks, n_min, 8 * w.m_star, total)}
+          "sample": "projectors Q of subdomains %s (n = %s, %d AP solves each by the separable sine + LAPACK "
+                    "banded tridiagonal route), %.2f s in all" % (picks, [w.subdomains[i].n for i in picks],
+                                                                  8 * w.m_star, total)}
+    cb.update(_host_info())
+    cb["single_thread"] = _single_thread(w.subdomains[picks[0]], w.m_star, 64)
     return cb, qerr
 
 
@@ -372,7 +422,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cross_point", choices=["two_rect", "cross_point", "transmission", "bump", "uneven", "adjoint"])
+    ap.add_argument("--workload", default="uneven", choices=["two_rect", "cross_point", "transmission", "bump", "uneven", "adjoint"])
     ap.add_argument("--precision", default="c128", help="c128 | c64 | c64r: precision of the reported value")
     ap.add_argument("--compare", default="c64r,c64", help="precisions also timed, comma-separated ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -61,7 +61,7 @@ typedef enum {
 
 /* How mdp_build_projector computes Q.  Both routes give the same Q up to
  * rounding order.
- * MDP_PATH_AUTO: for MDP_C128, the support-in / gamma-out route: the
+ * MDP_PATH_AUTO: for MDP_C128 and MDP_C64, the support-in / gamma-out route: the
  *   right-hand side L^(h) w |_{M+} lives on the two outer rings of M+ and
  *   only Tr_gamma of the AP solution is needed (eq. def_Pgamma), so only the
  *   four dense RHS rows and the four full gamma rows go through the sine
@@ -131,13 +131,31 @@ void mdp_destroy(mdp_ctx* ctx);
  * (projectors already cached are not rebuilt).  Errors: MDP_ERR_ARG. */
 int mdp_set_projector_path(mdp_ctx* ctx, int path);
 
-/* Autotuning of the sine transform's GEMM (enable != 0): the first GEMM of every
- * (precision, n, number of rows within a factor of two) times each eligible
- * tile shape (128x128, 128x64, 64x64 workgroup tiles) on its own operands and
- * keeps the fastest for later calls; the first call waits for its stream.
- * The choice is process-wide; results change only by rounding.  Errors:
- * MDP_ERR_ARG (ctx == NULL). */
+/* Autotuning (enable != 0) of the sine transform's GEMM and of the fused
+ * projector sweep: the first GEMM of every (precision, n, number of rows within
+ * a factor of two) times each eligible tile shape (128x128, 128x64, 64x64
+ * workgroup tiles) on its own operands, and the first fused sweep of every
+ * (precision, widest n, batch size within a factor of two) times 1, 2 and 4
+ * mode columns per lane (see mdp_set_fused_schedule; a schedule set there
+ * takes precedence), each keeping the fastest for later calls; a first call
+ * waits for its stream.  The choices are process-wide; results change only by
+ * rounding.  Errors: MDP_ERR_ARG (ctx == NULL). */
 int mdp_set_autotune(mdp_ctx* ctx, int enable);
+
+/* Schedule of the fused projector sweep (the MDP_PATH_AUTO route of
+ * mdp_build_projector(s), complex128 and complex64) for later builds on ctx:
+ * cols_per_lane = 1, 2 or 4 mode columns swept side by side by each lane of a
+ * wavefront (independent recurrences; one load of a factor row serves them all),
+ * or 0 (the default) to choose per batch of columns: two when the batch has
+ * enough columns to keep about two wavefronts per SIMD busy, else one; with
+ * mdp_set_autotune on, the fastest of 1, 2 and 4 measured at first use per
+ * (precision, widest n, batch size within a factor of two).  Results change
+ * only by rounding (the synthesis sums of a row are added in another order).
+ * Errors: MDP_ERR_ARG (ctx NULL or another value). */
+int mdp_set_fused_schedule(mdp_ctx* ctx, int cols_per_lane);
+
+/* Columns per lane the last fused projector build on ctx used (0: none yet, or ctx NULL). */
+int mdp_fused_schedule_used(const mdp_ctx* ctx);
 
 /* Select the interface least-squares route (mdp_interface_path) of later
  * mdp_solve_interface calls on ctx.  Errors: MDP_ERR_ARG. */

@@ -1003,16 +1003,19 @@ __device__ inline int find_job(const FusedJob* __restrict__ jobs, int njobs, int
     return lo;
 }
 
+// Grid: nbx workgroups per column, flattened (column-major) into blockIdx.x.
+template <class T>
 __global__ void __launch_bounds__(256)
-fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs) {
-    const FusedJob& J = jobs[find_job(jobs, njobs, blockIdx.y)];
+fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs, int nbx) {
+    const int gcol = blockIdx.x / nbx, bx = blockIdx.x - gcol * nbx;
+    const FusedJob& J = jobs[find_job(jobs, njobs, gcol)];
     const Fold f = J.f;
     const RingGeom rg{J.src.m_lo, J.src.m_hi, J.src.q_lo, J.src.q_hi};
     const SrcEval ev{J.src, f.n, J.sc};
-    double* __restrict__ gc = J.gc;
-    double* __restrict__ spec = J.spec;
-    const int n = f.n, p = f.p, W = f.W, b = blockIdx.y - J.b0;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    T* __restrict__ gc = reinterpret_cast<T*>(J.gc);
+    T* __restrict__ spec = reinterpret_cast<T*>(J.spec);
+    const int n = f.n, p = f.p, W = f.W, b = gcol - J.b0;
+    const int t = bx * blockDim.x + threadIdx.x;
     if (t <= n) {
         const int m = t;
         double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
@@ -1022,11 +1025,11 @@ fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs) {
             v2 = ev.rhs(b, m, rg.q_hi - 1).re;
             v3 = ev.rhs(b, m, rg.q_hi).re;
         }
-        double* o = gc + ((long)b * (n + 1) + m) * 4;
-        o[0] = v0 + v3;
-        o[1] = v1 + v2;
-        o[2] = v0 - v3;
-        o[3] = v1 - v2;
+        T* o = gc + ((long)b * (n + 1) + m) * 4;
+        o[0] = (T)(v0 + v3);
+        o[1] = (T)(v1 + v2);
+        o[2] = (T)(v0 - v3);
+        o[3] = (T)(v1 - v2);
         return;
     }
     const int i = t - (n + 1);
@@ -1042,219 +1045,23 @@ fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs) {
         const int q = c - f.P1 + 1;
         if (q < p) v = ev.rhs(b, m, q).re - ev.rhs(b, m, n - q).re;
     }
-    spec[((long)b * 4 + s) * W + c] = v;
-}
-
-// One step of a butterfly reduce-scatter over the wavefront: the lanes with
-// `bit` set keep the upper half of v[0..2H), the others the lower half, and
-// each adds its partner's copy of the half it keeps.
-template <int H>
-__device__ inline void reduce_half(double* v, int lane, int bit) {
-    const bool hi = (lane & bit) != 0;
-#pragma unroll
-    for (int j = 0; j < H; ++j) {
-        const double keep = hi ? v[H + j] : v[j];
-        const double send = hi ? v[j] : v[H + j];
-        v[j] = keep + __shfl_xor(send, bit, 64);
-    }
-}
-
-// Sums over the 64 lanes of the 32 values v[i*4 + t] (8 rows x 4 products);
-// afterwards lanes 2j and 2j+1 hold the total of value j in v[0].
-__device__ inline void reduce_32(double* v, int lane) {
-    reduce_half<16>(v, lane, 32);
-    reduce_half<8>(v, lane, 16);
-    reduce_half<4>(v, lane, 8);
-    reduce_half<2>(v, lane, 4);
-    reduce_half<1>(v, lane, 2);
-    v[0] += __shfl_xor(v[0], 1, 64);
-}
-
-typedef double dv2 __attribute__((ext_vector_type(2)));
-
-// Index of the special input row m (0..3), 4 for any other row.
-__device__ inline int special_slot(const RingGeom& r, int m) {
-    const int s = special_in(r, m);
-    return s < 0 ? 4 : s;
-}
-
-// One wavefront per (64 consecutive folded mode columns, right-hand side b).
-// Per column c (sine mode j): forward transform of the RHS rows, Thomas
-// elimination (y_m = ghat_m - l_m y_{m-1}, x_m = r_m (y_m - s_m x_{m+1})),
-// then per row the synthesis partial sums x_m(c) * sin(pi j q / n) at
-// q = q_lo-1, q_lo (into thin) and the full gamma rows into xs.
-// Only the rows m0 = m_lo-1 .. t = m_hi+1 are swept: the right-hand side is
-// zero outside the box, so y vanishes above it, and below it the homogeneous
-// rows are eliminated from the bottom in advance (twisted factorisation at
-// row t: x_t = tw_t y_t with tw_t = 1/(d'_t - s_t sub_{t+1}/e_{t+1}), e the
-// pivots of the bottom-up elimination).
-// gc[b][n+1][4] ring table, lf/rf/tf[(n+1)][W] complex factors l_m, r_m, tw_m,
-// ckpt[b][seg][2][W], xs[b][2][4][W], thin[b][wblk][nseg*K][4] (rows from m0).
-// LDS: the wave's ring pairs of rows m0..t and the 4 special-row values per lane.
-template <int K>
-__global__ void __launch_bounds__(64)
-proj_fused_kernel(const FusedJob* __restrict__ jobs, int njobs) {
-    static_assert(K % 8 == 0, "segments are reduced 8 rows at a time");
-    extern __shared__ double2 lds_g[];  // [t-m0+1] ring pairs, then [5][64] special values
-    const FusedJob& J = jobs[find_job(jobs, njobs, blockIdx.y)];
-    const Fold f = J.f;
-    const int n = f.n, W = f.W;
-    const int lane = threadIdx.x, wblk = blockIdx.x, b = blockIdx.y - J.b0;
-    if (wblk >= W / 64) return;   // a job with fewer mode columns than the widest one
-    const RingGeom rg{J.src.m_lo, J.src.m_hi, J.src.q_lo, J.src.q_hi};
-    const int nseg = J.nseg;
-    const double* __restrict__ gc = J.gc;
-    const double* __restrict__ spec_hat = J.spec_hat;
-    const double* __restrict__ Sf = J.Sf;
-    const double* __restrict__ Si = J.Si;
-    const dv2* __restrict__ lf = reinterpret_cast<const dv2*>(J.lf);
-    const dv2* __restrict__ rf = reinterpret_cast<const dv2*>(J.rf);
-    const dv2* __restrict__ tf = reinterpret_cast<const dv2*>(J.tf);
-    const double* __restrict__ colc = J.colc;
-    double* __restrict__ ckpt = J.ckpt;
-    double* __restrict__ xs = J.xs;
-    double* __restrict__ thin = J.thin;
-    const int c = wblk * 64 + lane;
-    const bool odd = c < f.P1;  // uniform over the wavefront (P1 is a multiple of 64)
-    const int base = odd ? 0 : f.P1;
-    const int m0 = rg.m_lo - 1, t = rg.m_hi + 1;
-    double* lds_sp = reinterpret_cast<double*>(lds_g + (t - m0 + 1));
-    {
-        const double* g = gc + (long)b * (n + 1) * 4 + (odd ? 0 : 2);
-        for (int m = m0 + lane; m <= t; m += 64)
-            lds_g[m - m0] = make_double2(g[(long)m * 4], g[(long)m * 4 + 1]);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) lds_sp[s * 64 + lane] = spec_hat[((long)b * 4 + s) * W + c];
-        lds_sp[4 * 64 + lane] = 0.0;
-    }
-    __syncthreads();
-    const double s1 = Sf[(long)(base + rg.q_lo - 1) * W + c];
-    const double s2 = Sf[(long)(base + rg.q_lo) * W + c];
-    const double t1 = Si[(long)c * W + base + rg.q_lo - 2];
-    const double t2 = Si[(long)c * W + base + rg.q_lo - 1];
-    const double a = colc[c];
-    const dv2 tw = tf[(long)t * W + c];
-    const dv2* lcol = lf + c;
-    const dv2* rcol = rf + c;
-    double* ck = ckpt + (long)b * nseg * 2 * W + c;
-
-    auto ghat = [&](int m) -> double {
-        const double2 g = lds_g[m - m0];
-        return g.x * s1 + g.y * s2 + lds_sp[special_slot(rg, m) * 64 + lane];
-    };
-    // factor rows of segment s (rows past t read row t; their results are unused)
-    auto load_f = [&](dv2* F, const dv2* col, int s) {
-#pragma unroll
-        for (int i = 0; i < K; ++i) F[i] = col[(long)min(m0 + s * K + i, t) * W];
-    };
-
-    // forward elimination from row m0 (y_{m0-1} = 0), checkpointing y at the end of every full segment
-    double yr = 0.0, yi = 0.0;
-    {
-        dv2 Lc[K], Ln[K];
-        load_f(Lc, lcol, 0);
-        for (int s = 0; s < nseg - 1; ++s) {
-            load_f(Ln, lcol, s + 1);
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-                // y = ghat - l y as two dependent fma per component
-                const double fr = ghat(m0 + s * K + i);
-                const double nr = fma(-Lc[i].x, yr, fma(Lc[i].y, yi, fr));
-                const double ni = fma(-Lc[i].x, yi, -(Lc[i].y * yr));
-                yr = nr;
-                yi = ni;
-            }
-            ck[(long)s * 2 * W] = yr;
-            ck[(long)(s * 2 + 1) * W] = yi;
-#pragma unroll
-            for (int i = 0; i < K; ++i) Lc[i] = Ln[i];
-        }
-    }
-
-    // back substitution segment by segment: recompute the segment's y from
-    // the checkpoint before it, then walk back through it (x_t = tw_t y_t)
-    double xr = 0.0, xi = 0.0;
-    double* xs_re = xs + (long)b * 8 * W + c;
-    double* xs_im = xs_re + 4 * W;
-    double* th = thin + ((long)b * (W / 64) + wblk) * ((long)nseg * K) * 4;
-    dv2 Lc[K], Ln[K], Rc[K];
-    load_f(Lc, lcol, nseg - 1);
-    for (int s = nseg - 1; s >= 0; --s) {
-        double pr = 0.0, pi = 0.0;
-        load_f(Rc, rcol, s);
-        if (s > 0) {
-            pr = ck[(long)(s - 1) * 2 * W];
-            pi = ck[(long)((s - 1) * 2 + 1) * W];
-            load_f(Ln, lcol, s - 1);
-        }
-        double vr[K], vi[K];
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int m = min(m0 + s * K + i, t);
-            const double fr = ghat(m);
-            const double nr = fma(-Lc[i].x, pr, fma(Lc[i].y, pi, fr));
-            const double ni = fma(-Lc[i].x, pi, -(Lc[i].y * pr));
-            pr = nr;
-            pi = ni;
-            vr[i] = pr;
-            vi[i] = pi;
-        }
-        // x_m = r_m (y_m - a x_{m+1}) = p_m - q_m x_{m+1} with p = r y and q = r a off the
-        // dependency chain (m >= m0 >= 1: the off-diagonal is the real interior one)
-#pragma unroll
-        for (int i = K - 1; i >= 0; --i) {
-            const int m = m0 + s * K + i;
-            if (m <= t) {
-                const dv2 rm = (m == t) ? tw : Rc[i];
-                const double ppr = fma(rm.x, vr[i], -(rm.y * vi[i])), ppi = fma(rm.x, vi[i], rm.y * vr[i]);
-                const double qr = rm.x * a, qi = rm.y * a;
-                const double nxr = fma(-qr, xr, fma(qi, xi, ppr));
-                const double nxi = fma(-qr, xi, fma(-qi, xr, ppi));
-                xr = nxr;
-                xi = nxi;
-                const int so = special_out(rg, m);
-                if (so >= 0) {
-                    xs_re[(long)so * W] = xr;
-                    xs_im[(long)so * W] = xi;
-                }
-                vr[i] = xr;
-                vi[i] = xi;
-            } else {
-                vr[i] = 0.0;
-                vi[i] = 0.0;
-            }
-        }
-        // synthesis partial sums of the gamma rows of this segment
-#pragma unroll
-        for (int h8 = 0; h8 < K; h8 += 8) {
-            double v[32];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                v[4 * i + 0] = vr[h8 + i] * t1;
-                v[4 * i + 1] = vi[h8 + i] * t1;
-                v[4 * i + 2] = vr[h8 + i] * t2;
-                v[4 * i + 3] = vi[h8 + i] * t2;
-            }
-            reduce_32(v, lane);
-            if ((lane & 1) == 0) th[(long)(s * K + h8) * 4 + (lane >> 1)] = v[0];
-        }
-#pragma unroll
-        for (int i = 0; i < K; ++i) Lc[i] = Ln[i];
-    }
+    spec[((long)b * 4 + s) * W + c] = (T)v;
 }
 
 // Q(i, col0+b) = -u(m_i, q_i): the full gamma rows from the synthesis rows us
 // ([b][plane][4][W], output of the inverse sine GEMM of xs), the others from
 // the thin partial sums (odd-mode blocks give A, even-mode blocks B).
-__global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njobs) {
-    const FusedJob& J = jobs[find_job(jobs, njobs, blockIdx.y)];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y - J.b0;
+template <class T>
+__global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njobs, int nbx) {
+    const int gcol = blockIdx.x / nbx, bx = blockIdx.x - gcol * nbx;
+    const FusedJob& J = jobs[find_job(jobs, njobs, gcol)];
+    const int i = bx * blockDim.x + threadIdx.x;
+    const int b = gcol - J.b0;
     if (i >= J.ng) return;
     const Fold f = J.f;
     const RingGeom rg{J.src.m_lo, J.src.m_hi, J.src.q_lo, J.src.q_hi};
-    const double* __restrict__ us = J.us;
-    const double* __restrict__ thin = J.thin;
+    const T* __restrict__ us = reinterpret_cast<const T*>(J.us);
+    const T* __restrict__ thin = reinterpret_cast<const T*>(J.thin);
     const int* __restrict__ gm = J.gm;
     const int* __restrict__ gq = J.gq;
     const int rows_pad = J.rows_pad, ldq = J.ldq, col0 = J.src.col0;
@@ -1265,12 +1072,12 @@ __global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njo
     if (so >= 0) {
         double v[2];
         for (int pl = 0; pl < 2; ++pl) {
-            const double* row = us + (((long)b * 2 + pl) * 4 + so) * W;
+            const T* row = us + (((long)b * 2 + pl) * 4 + so) * W;
             double u;
             if (q <= 0 || q >= n) u = 0.0;
-            else if (q == p) u = row[p - 1];
-            else if (q < p) u = row[q - 1] + row[f.P1 + q - 1];
-            else u = row[n - q - 1] - row[f.P1 + n - q - 1];
+            else if (q == p) u = (double)row[p - 1];
+            else if (q < p) u = (double)row[q - 1] + (double)row[f.P1 + q - 1];
+            else u = (double)row[n - q - 1] - (double)row[f.P1 + n - q - 1];
             v[pl] = u;
         }
         vre = v[0];
@@ -1282,9 +1089,9 @@ __global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njo
         const int nb = W / 64, nb1 = f.P1 / 64;
         double A0 = 0.0, A1 = 0.0, B0 = 0.0, B1 = 0.0;
         for (int w = 0; w < nb; ++w) {
-            const double* t = thin + (((long)b * nb + w) * rows_pad + (m - rg.m_lo + 1)) * 4 + k2;
-            if (w < nb1) { A0 += t[0]; A1 += t[1]; }
-            else { B0 += t[0]; B1 += t[1]; }
+            const T* t = thin + (((long)b * nb + w) * rows_pad + (m - rg.m_lo + 1)) * 4 + k2;
+            if (w < nb1) { A0 += (double)t[0]; A1 += (double)t[1]; }
+            else { B0 += (double)t[0]; B1 += (double)t[1]; }
         }
         vre = A0 + sgn * B0;
         vim = A1 + sgn * B1;
@@ -1403,26 +1210,30 @@ void launch_unfold_jobs(const SolveJob* jobs, int njobs, int total, int max_n, i
     MDP_HIP(hipGetLastError());
 }
 
+static dim3 flat_grid(int per_col, int total) {
+    const long blocks = (long)per_col * total;
+    if (blocks > 0x7fffffffL) throw Error(MDP_ERR_ARG, "too many projector columns for one launch");
+    return dim3((unsigned)blocks);
+}
+
+template <class T>
 void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_items, hipStream_t st) {
     if (njobs <= 0 || total <= 0) return;
-    check_batch(total);
-    hipLaunchKernelGGL(fold_ring_kernel, dim3((max_items + 255) / 256, total), dim3(256), 0, st, jobs, njobs);
+    const int nbx = (max_items + 255) / 256;
+    hipLaunchKernelGGL(fold_ring_kernel<T>, flat_grid(nbx, total), dim3(256), 0, st, jobs, njobs, nbx);
     MDP_HIP(hipGetLastError());
 }
+template void launch_fold_ring_jobs<double>(const FusedJob*, int, int, int, hipStream_t);
+template void launch_fold_ring_jobs<float>(const FusedJob*, int, int, int, hipStream_t);
 
-void launch_proj_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_wblk, size_t lds_bytes,
-                            hipStream_t st) {
-    if (njobs <= 0 || total <= 0) return;
-    check_batch(total);
-    hipLaunchKernelGGL(proj_fused_kernel<FUSED_K>, dim3(max_wblk, total), dim3(64), lds_bytes, st, jobs, njobs);
-    MDP_HIP(hipGetLastError());
-}
-
+template <class T>
 void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, hipStream_t st) {
     if (njobs <= 0 || total <= 0) return;
-    check_batch(total);
-    hipLaunchKernelGGL(gather_q_fused_kernel, dim3((max_ng + 255) / 256, total), dim3(256), 0, st, jobs, njobs);
+    const int nbx = (max_ng + 255) / 256;
+    hipLaunchKernelGGL(gather_q_fused_kernel<T>, flat_grid(nbx, total), dim3(256), 0, st, jobs, njobs, nbx);
     MDP_HIP(hipGetLastError());
 }
+template void launch_gather_q_fused_jobs<double>(const FusedJob*, int, int, int, hipStream_t);
+template void launch_gather_q_fused_jobs<float>(const FusedJob*, int, int, int, hipStream_t);
 
 }  // namespace mdp

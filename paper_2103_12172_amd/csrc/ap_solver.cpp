@@ -182,6 +182,9 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
     upload<double>(lf64, lf);
     upload<double>(rf64, rf);
     upload<double>(tf64, tw);
+    upload<float>(lf32, lf);
+    upload<float>(rf32, rf);
+    upload<float>(tf32, tw);
     upload<float>(colc32, colc);
 }
 

@@ -139,6 +139,8 @@ struct mdp_ctx {
     Workspace ws;
     size_t ws_cap = (size_t)24 << 30;
     int projector_path = MDP_PATH_AUTO;
+    int sweep_cols = 0;        // mode columns per lane of the fused sweep (0: chosen per batch)
+    int last_sweep_cols = 0;   // what the last fused build used
     int interface_path = MDP_IFACE_AUTO;
     unsigned long long next_serial = 1;
     // key of the interface system whose Gram factor the workspaces hold (projector builds, side
@@ -181,11 +183,37 @@ int guarded(mdp_ctx* ctx, F&& f) {
 void begin_call(mdp_ctx* ctx, hipStream_t st) {
     if (ctx->have_last && ctx->last_stream != st) MDP_HIP(hipStreamWaitEvent(st, ctx->last, 0));
 }
-void end_call(mdp_ctx* ctx, hipStream_t st) {
-    MDP_HIP(hipEventRecord(ctx->last, st));
-    ctx->last_stream = st;
-    ctx->have_last = true;
-}
+
+// The device work of one call, from its first launch to its return: opening it orders the
+// call after the previous one; leaving it (normal return or an error thrown after some work
+// was queued) records the end of the queued work, so that the next call, on any stream,
+// waits for it before reusing the shared workspaces.  If the record itself fails the
+// device is drained instead.
+struct CallScope {
+    mdp_ctx* ctx = nullptr;
+    hipStream_t st = nullptr;
+    CallScope() = default;
+    CallScope(mdp_ctx* c, hipStream_t s) { open(c, s); }
+    CallScope(const CallScope&) = delete;
+    CallScope& operator=(const CallScope&) = delete;
+    void open(mdp_ctx* c, hipStream_t s) {
+        if (ctx) return;
+        begin_call(c, s);
+        ctx = c;
+        st = s;
+    }
+    bool is_open() const { return ctx != nullptr; }
+    ~CallScope() {
+        if (!ctx) return;
+        if (hipEventRecord(ctx->last, st) == hipSuccess) {
+            ctx->last_stream = st;
+            ctx->have_last = true;
+        } else {
+            (void)hipDeviceSynchronize();
+            ctx->have_last = false;
+        }
+    }
+};
 
 APPlan& get_plan(mdp_ctx* ctx, int n, double h, double k) {
     PlanKey key{n, h, k};
@@ -254,13 +282,21 @@ struct FusedItem {
     mdp_projector* P;
 };
 
-// Q of every item by the support-in / gamma-out route (FP64), the columns of all
-// items through each stage together.  Per batch of columns (as many as the
-// workspace holds): the ring RHS and the folded special rows, their sine GEMM
-// (one launch per n), the fused sweep with the gamma-row reductions, the inverse
-// GEMM of the four full gamma rows (one launch per n) and the gather into Q.
-void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
+// Mode columns per lane of the fused sweep: two (independent recurrences side by side,
+// half the factor loads per column) when that still leaves about two wavefronts per
+// SIMD of the chip, else one; or what the autotuner measured fastest for the batch.
+int sweep_lanes_cols(long waves_one_col) { return waves_one_col >= 2L * 2048 ? 2 : 1; }
+
+// Q of every item by the support-in / gamma-out route, T the arithmetic of the build
+// (double for complex128, float for complex64), the columns of all items through each
+// stage together.  Per batch of columns (as many as the workspace holds): the ring RHS
+// and the folded special rows, their sine GEMM (one launch per n), the fused sweep with
+// the gamma-row reductions, the inverse GEMM of the four full gamma rows (one launch
+// per n) and the gather into Q (FP64).
+template <class T>
+void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
     if (items.empty()) return;
+    constexpr bool f64 = sizeof(T) == 8;
     std::stable_sort(items.begin(), items.end(),
                      [](const FusedItem& a, const FusedItem& b) { return a.plan->n < b.plan->n; });
     struct Per { size_t a, b; int ncol; };
@@ -273,7 +309,7 @@ void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
         per[i].b = (size_t)(G.n + 1) * 4 + (size_t)(4 + 4 + 8 + 8) * f.W;    // gc, spec, spec_hat, xs, us
         per[i].ncol = 8 * items[i].P->m_star;
     }
-    const size_t cap = ctx->ws_cap / sizeof(double);
+    const size_t cap = ctx->ws_cap / sizeof(T);
     Profiler& pr = ctx->ws.prof;
     struct JobHost { size_t item; int col0, R; };
     size_t it = 0;
@@ -283,11 +319,11 @@ void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
         std::vector<JobHost> jh;
         size_t sa = 0, sb = 0;
         int total = 0;
-        while (it < items.size() && total < 65535) {
+        while (it < items.size()) {
             const Per& q = per[it];
             const size_t used = sa + sb, each = q.a + q.b;
             const size_t room = used < cap ? (cap - used) / each : 0;
-            const int R = (int)std::min<size_t>({room, (size_t)(65535 - total), (size_t)(q.ncol - next_col)});
+            const int R = (int)std::min<size_t>({room, (size_t)(q.ncol - next_col)});
             if (R <= 0) break;
             jh.push_back({it, next_col, R});
             sa += (size_t)R * q.a;
@@ -297,10 +333,10 @@ void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
             if (next_col == q.ncol) { ++it; next_col = 0; }
         }
         if (jh.empty()) throw Error(MDP_ERR_OOM, "workspace too small for one projector column");
-        if (sa * sizeof(double) > ctx->ws.a.bytes || sb * sizeof(double) > ctx->ws.b.bytes) {
+        if (sa * sizeof(T) > ctx->ws.a.bytes || sb * sizeof(T) > ctx->ws.b.bytes) {
             MDP_HIP(hipDeviceSynchronize());
-            ctx->ws.a.reserve(std::max<size_t>(sa, 1) * sizeof(double));
-            ctx->ws.b.reserve(std::max<size_t>(sb, 1) * sizeof(double));
+            ctx->ws.a.reserve(std::max<size_t>(sa, 1) * sizeof(T));
+            ctx->ws.b.reserve(std::max<size_t>(sb, 1) * sizeof(T));
         }
         // regions: ws.b = gc | spec | spec_hat | xs | us, ws.a = ckpt | thin, each in job order
         size_t n_gc = 0, n_sp = 0, n_x = 0, n_ck = 0;
@@ -312,13 +348,15 @@ void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
             n_x += (size_t)j.R * 8 * f.W;
             n_ck += (size_t)j.R * fused_segments(G.m_lo, G.m_hi) * 2 * f.W;
         }
-        double* B = ctx->ws.b.as<double>();
-        double* A = ctx->ws.a.as<double>();
-        double *gc = B, *spec = gc + n_gc, *spec_hat = spec + n_sp, *xs = spec_hat + n_sp, *us = xs + n_x;
-        double *ckpt = A, *thin = ckpt + n_ck;
+        T* B = ctx->ws.b.as<T>();
+        T* A = ctx->ws.a.as<T>();
+        T *gc = B, *spec = gc + n_gc, *spec_hat = spec + n_sp, *xs = spec_hat + n_sp, *us = xs + n_x;
+        T *ckpt = A, *thin = ckpt + n_ck;
+        auto dp = [](T* p) { return reinterpret_cast<double*>(p); };
+        auto cdp = [](const void* p) { return reinterpret_cast<const double*>(p); };
         std::vector<FusedJob> jobs(jh.size());
-        int b0 = 0, max_items = 0, max_wblk = 0, max_ng = 0;
-        size_t lds = 0;
+        int b0 = 0, max_items = 0, max_w = 0, max_ng = 0;
+        long waves_one_col = 0;
         double fold_bytes = 0.0, sweep_flops = 0.0, sweep_bytes = 0.0, gather_bytes = 0.0;
         for (size_t q = 0; q < jh.size(); ++q) {
             const JobHost& j = jh[q];
@@ -344,34 +382,34 @@ void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
             J.ldq = ng;
             J.b0 = b0;
             J.R = R;
-            J.Sf = plan.Sf64.as<double>();
-            J.Si = plan.Si64.as<double>();
-            J.lf = plan.lf64.as<double>();
-            J.rf = plan.rf64.as<double>();
-            J.tf = plan.tf64.as<double>();
-            J.colc = plan.colc64.as<double>();
-            J.gc = gc; gc += (size_t)R * (n + 1) * 4;
-            J.spec = spec; spec += (size_t)R * 4 * f.W;
-            J.spec_hat = spec_hat; spec_hat += (size_t)R * 4 * f.W;
-            J.xs = xs; xs += (size_t)R * 8 * f.W;
-            J.us = us; us += (size_t)R * 8 * f.W;
-            J.ckpt = ckpt; ckpt += (size_t)R * nseg * 2 * f.W;
-            J.thin = thin; thin += (size_t)R * (f.W / 64) * J.rows_pad * 4;
+            J.Sf = cdp(f64 ? plan.Sf64.p : plan.Sf32.p);
+            J.Si = cdp(f64 ? plan.Si64.p : plan.Si32.p);
+            J.lf = cdp(f64 ? plan.lf64.p : plan.lf32.p);
+            J.rf = cdp(f64 ? plan.rf64.p : plan.rf32.p);
+            J.tf = cdp(f64 ? plan.tf64.p : plan.tf32.p);
+            J.colc = cdp(f64 ? plan.colc64.p : plan.colc32.p);
+            J.gc = dp(gc); gc += (size_t)R * (n + 1) * 4;
+            J.spec = dp(spec); spec += (size_t)R * 4 * f.W;
+            J.spec_hat = dp(spec_hat); spec_hat += (size_t)R * 4 * f.W;
+            J.xs = dp(xs); xs += (size_t)R * 8 * f.W;
+            J.us = dp(us); us += (size_t)R * 8 * f.W;
+            J.ckpt = dp(ckpt); ckpt += (size_t)R * nseg * 2 * f.W;
+            J.thin = dp(thin); thin += (size_t)R * (f.W / 64) * J.rows_pad * 4;
             J.Q = itm.P->Q.as<double>();
             J.gm = itm.P->gm;
             J.gq = itm.P->gq;
             b0 += R;
             max_items = std::max(max_items, n + 1 + 4 * f.W);
-            max_wblk = std::max(max_wblk, f.W / 64);
+            max_w = std::max(max_w, f.W);
             max_ng = std::max(max_ng, ng);
-            lds = std::max(lds, (size_t)(G.m_hi - G.m_lo + 3) * sizeof(double2) + 5 * 64 * sizeof(double));
+            waves_one_col += (long)R * (f.W / 64);
             // algorithmic flops per column element of the swept band (rows m_lo-1..m_hi+1): forward
             // elimination 7, back substitution 10, synthesis products and sums 8; ring transform 3 (box rows)
             const int box_rows = G.m_hi - G.m_lo + 3;
-            fold_bytes += (double)R * ((n + 1) * 4.0 + 4.0 * (n - 1)) * 8.0;
+            fold_bytes += (double)R * ((n + 1) * 4.0 + 4.0 * (n - 1)) * sizeof(T);
             sweep_flops += (double)R * ((double)box_rows * (n - 1) * 25.0 + (double)(G.m_hi - G.m_lo + 1) * (n - 1) * 3.0);
-            sweep_bytes += (double)R * ((G.m_hi - G.m_lo + 1) * 32.0 + 4.0 * (n - 1) * 8.0 + 8.0 * (n - 1) * 8.0 +
-                                        (double)box_rows * 4 * 8.0);
+            sweep_bytes += (double)R * ((G.m_hi - G.m_lo + 1) * 4.0 + 4.0 * (n - 1) + 8.0 * (n - 1) +
+                                        (double)box_rows * 4) * sizeof(T);
             gather_bytes += (double)ng * R * 16.0 * 2.0;
         }
         HostBlob blob;
@@ -387,22 +425,35 @@ void build_q_fused(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st) {
                 const Fold& f = jobs[q0].f;
                 const double row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
                 const int mult = forward ? 4 : 8;
-                pr.run("gemm_sine_f64", st, mult * rows * row_flops, 2.0 * mult * rows * (f.n - 1) * 8.0, [&] {
+                pr.run(f64 ? "gemm_sine_f64" : "gemm_sine_f32", st, mult * rows * row_flops,
+                       2.0 * mult * rows * (f.n - 1) * sizeof(T), [&] {
                     if (forward)
-                        launch_gemm_bd<double>(jobs[q0].spec, jobs[q0].Sf, jobs[q0].spec_hat, rows * 4, f, st);
+                        launch_gemm_bd<T>(reinterpret_cast<const T*>(jobs[q0].spec),
+                                          reinterpret_cast<const T*>(jobs[q0].Sf),
+                                          reinterpret_cast<T*>(jobs[q0].spec_hat), rows * 4, f, st);
                     else
-                        launch_gemm_bd<double>(jobs[q0].xs, jobs[q0].Si, jobs[q0].us, rows * 8, f, st);
+                        launch_gemm_bd<T>(reinterpret_cast<const T*>(jobs[q0].xs),
+                                          reinterpret_cast<const T*>(jobs[q0].Si),
+                                          reinterpret_cast<T*>(jobs[q0].us), rows * 8, f, st);
                 });
                 q0 = q1;
             }
         };
-        pr.run("fold_ring", st, 0.0, fold_bytes, [&] { launch_fold_ring_jobs(dj, nj, total, max_items, st); });
+        const int L = ctx->sweep_cols > 0 ? ctx->sweep_cols : sweep_lanes_cols(waves_one_col);
+        pr.run("fold_ring", st, 0.0, fold_bytes, [&] { launch_fold_ring_jobs<T>(dj, nj, total, max_items, st); });
         gemms(true);
-        pr.run("ap_fused_f64", st, sweep_flops, sweep_bytes,
-               [&] { launch_proj_fused_jobs(dj, nj, total, max_wblk, lds, st); });
+        pr.run(f64 ? "ap_fused_f64" : "ap_fused_f32", st, sweep_flops, sweep_bytes, [&] {
+            ctx->last_sweep_cols =
+                launch_proj_sweep_jobs<T>(dj, nj, total, max_w, waves_one_col, L, ctx->sweep_cols == 0, st);
+        });
         gemms(false);
-        pr.run("gather_q", st, 0.0, gather_bytes, [&] { launch_gather_q_fused_jobs(dj, nj, total, max_ng, st); });
+        pr.run("gather_q", st, 0.0, gather_bytes, [&] { launch_gather_q_fused_jobs<T>(dj, nj, total, max_ng, st); });
     }
+}
+
+void build_q_fused(mdp_ctx* ctx, const std::vector<FusedItem>& items, int precision, hipStream_t st) {
+    if (precision == MDP_C128) build_q_fused_t<double>(ctx, items, st);
+    else build_q_fused_t<float>(ctx, items, st);
 }
 
 // Band solves of several plans' entries in one launch per stage: jobs in order of n (their
@@ -521,8 +572,19 @@ int mdp_set_projector_path(mdp_ctx* ctx, int path) {
 int mdp_set_autotune(mdp_ctx* ctx, int enable) {
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
     set_gemm_autotune(enable);
+    set_sweep_autotune(enable);
     return MDP_OK;
 }
+
+int mdp_set_fused_schedule(mdp_ctx* ctx, int cols_per_lane) {
+    if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
+    if (cols_per_lane != 0 && cols_per_lane != 1 && cols_per_lane != 2 && cols_per_lane != 4)
+        return fail(ctx, MDP_ERR_ARG, "columns per lane must be 0, 1, 2 or 4");
+    ctx->sweep_cols = cols_per_lane;
+    return MDP_OK;
+}
+
+int mdp_fused_schedule_used(const mdp_ctx* ctx) { return ctx ? ctx->last_sweep_cols : 0; }
 
 int mdp_set_interface_path(mdp_ctx* ctx, int path) {
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
@@ -549,7 +611,7 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
         std::vector<mdp_projector*> res(count, nullptr);
         std::vector<FusedItem> fused;
         std::vector<std::pair<ProjKey, mdp_projector*>> fresh;   // built by this call, not yet cached
-        bool began = false;
+        CallScope scope;
         try {
             // the gamma tables of geometries new to the context in one upload; E of every fresh
             // projector and the new geometries' node maps in one launch pair
@@ -568,7 +630,7 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                 for (auto& kv : fresh)
                     if (kv.first == key) { res[i] = kv.second; dup = true; }
                 if (dup) continue;
-                if (!began) { begin_call(ctx, st); began = true; }
+                scope.open(ctx, st);
                 // the grid sets relative to the rectangle depend on its size and n only
                 GeomKey gk{sd->lx, sd->ly, sd->n};
                 auto git = ctx->geoms.find(gk);
@@ -626,7 +688,7 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                 fresh.push_back({key, raw});
                 ejobs.push_back({raw, gi});
                 res[i] = raw;
-                if (precision == MDP_C128 && ctx->projector_path == MDP_PATH_AUTO &&
+                if ((precision == MDP_C128 || precision == MDP_C64) && ctx->projector_path == MDP_PATH_AUTO &&
                     fused_projector_supported(plan.f, G.m_lo, G.m_hi, G.q_lo, G.q_hi) &&
                     plan.twist_ratio[G.m_hi + 1] > 1e-13) {
                     fused.push_back({&plan, raw});
@@ -717,14 +779,13 @@ int mdp_build_projectors(mdp_ctx* ctx, int count, const mdp_subdomain* sds, int 
                                 st);
                 }
             }
-            build_q_fused(ctx, fused, st);
+            build_q_fused(ctx, fused, precision, st);
         } catch (...) {
             // nothing built by this call is handed out; its projectors are dropped after the device drains
             (void)hipDeviceSynchronize();
             for (auto& kv : fresh) mdp_projector_release(kv.second);
             throw;
         }
-        if (began) end_call(ctx, st);
         for (auto& kv : fresh) {
             kv.second->refs.store(1);   // the cache's reference; the callers' follow
             ctx->cache[kv.first] = kv.second;
@@ -1170,7 +1231,7 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
             }
         }
 
-        begin_call(ctx, st);
+        CallScope scope(ctx, st);
         CallWork& cw = ctx->ws.cw;
         DevBuf &F = cw.F, &x = cw.x;
         ensure(F, (size_t)m * sizeof(double2));
@@ -1340,12 +1401,15 @@ int solve_interface_impl(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, con
                                reinterpret_cast<const double2*>(c_out), reinterpret_cast<const int*>(img + o_esrc),
                                reinterpret_cast<const double2*>(img + o_ecoef), row_off, *ga, st);
         }
-        end_call(ctx, st);
         if (rel_residual_out) *rel_residual_out = r.rel_residual;
         if (cond_estimate_out) *cond_estimate_out = r.cond;
         return MDP_OK;
     });
 }
+
+// refinement steps of the gradient's normal solve (each: two products with the packed matrix and
+// one solve with the kept Gram factor)
+constexpr int kGradRefineSteps = 2;
 
 void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const mdp_projector* const* P,
                         const mdp_side* sides, int M, const PackedHost& ph, const PackedTables& tabs, const char* img,
@@ -1353,8 +1417,6 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
                         const double2* ecoef, const std::vector<int>& row_off, const GradArgs& ga, hipStream_t st) {
     const int nc = ph.nc, ncol = 8 * M, nce = n_sub * ncol;
     const long m_rows = row_off[n_sub];
-    for (int i = 0; i < n_sub; ++i)
-        if (P[i]->precision != MDP_C128) throw Error(MDP_ERR_ARG, "gradient: projectors must be complex128");
     // grid offsets (complex elements) of every subdomain in the ubar and lambda grids
     std::vector<long> goff(n_sub + 1, 0);
     int max_ng = 0;
@@ -1365,10 +1427,7 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
     // receivers: values summed per node, grouped by subdomain
     std::map<std::pair<int, int>, double2> acc;
     for (int t = 0; t < ga.n_rcv; ++t) {
-        const int i = ga.rcv_sub[t], node = ga.rcv_node[t], n = P[i]->g.n;
-        if (node < 0 || node >= (n + 1) * (n + 1)) throw Error(MDP_ERR_ARG, "receiver node out of range");
-        if (!std::isfinite(ga.ubar[t].re) || !std::isfinite(ga.ubar[t].im))
-            throw Error(MDP_ERR_NONFINITE, "non-finite receiver weight");
+        const int i = ga.rcv_sub[t], node = ga.rcv_node[t];   // checked by mdp_dd_gradient
         double2& v = acc[{i, node}];
         v.x += ga.ubar[t].re;
         v.y += ga.ubar[t].im;
@@ -1512,20 +1571,16 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
                             d_idx + i, reinterpret_cast<double*>(cbar), st);
         });
     }
-    // (3) xbar = K^* cbar; z = D^{-1} G^{-1} D^{-1} xbar (column equilibration D of the packed matrix)
+    // (3) xbar = K^* cbar; z = (Qbar^* Qbar)^{-1} xbar = D^{-1} G^{-1} D^{-1} xbar with the column
+    // equilibration D of the packed matrix Ap = Qbar D^{-1} and its Gram matrix G = Ap^* Ap (the forward
+    // call's factor), refined like the forward solve (corrected semi-normal steps): the error of one
+    // solve with the Gram factor grows like cond(Ap)^2 u, each step against the true normal residual
+    // rho = D^{-1} xbar - Ap^*(Ap zs) contracts it by about that factor again
     const double* norms = ctx->ws.ls.norms.as<double>() + nc;
     double2* xbar = at(b_xbar);
     double2* xs = at(b_xs);
     double2* zs = at(b_zs);
     double2* z = at(b_z);
-    MDP_HIP(hipMemsetAsync(xbar, 0, (size_t)nc * sizeof(double2), st));
-    launch_expand_adj(nce, esrc, ecoef, cbar, xbar, st);
-    MDP_HIP(hipMemcpyAsync(xs, xbar, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    launch_scale_cols(xs, 1, nc, 1, norms, 1, st);
-    ls_packed_factor_solve(ctx->ws, ph, img, tabs, xs, zs, st);
-    MDP_HIP(hipMemcpyAsync(z, zs, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    launch_scale_cols(z, 1, nc, 1, norms, 1, st);
-    // (4) Fbb = Qbar z = Ap zs; r = Fbar - Qbar x = Fbar - Ap (D x)
     const char* pimg = img;
     auto pat = [&](size_t o) { return pimg + o; };
     PackedDevice d{reinterpret_cast<const double2* const*>(pat(tabs.Q)), reinterpret_cast<const int*>(pat(tabs.m)),
@@ -1539,6 +1594,21 @@ void interface_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* sd, const 
     double2* Fbb = at(b_Fbb);
     double2* r = at(b_r);
     const double2 one{1.0, 0.0}, mone{-1.0, 0.0};
+    MDP_HIP(hipMemsetAsync(xbar, 0, (size_t)nc * sizeof(double2), st));
+    launch_expand_adj(nce, esrc, ecoef, cbar, xbar, st);
+    MDP_HIP(hipMemcpyAsync(xs, xbar, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_scale_cols(xs, 1, nc, 1, norms, 1, st);
+    ls_packed_factor_solve(ctx->ws, ph, img, tabs, xs, zs, st);
+    for (int step = 0; step < kGradRefineSteps; ++step) {
+        launch_packed_axpy(d, n_sub, ph.max_m, Ap, zs, one, nullptr, Fbb, nullptr, nullptr, st);   // Ap zs
+        launch_packed_ahx_set(d, nc, Ap, Fbb, z, st);                                             // Ap^* Ap zs
+        launch_zsub(nc, xs, z, z, st);                                                            // rho
+        ls_packed_factor_solve(ctx->ws, ph, img, tabs, z, xbar, st);                              // G^{-1} rho
+        launch_zaxpy_norms(nc, xbar, zs, nullptr, nullptr, st);
+    }
+    MDP_HIP(hipMemcpyAsync(z, zs, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_scale_cols(z, 1, nc, 1, norms, 1, st);
+    // (4) Fbb = Qbar z = Ap zs; r = Fbar - Qbar x = Fbar - Ap (D x)
     launch_packed_axpy(d, n_sub, ph.max_m, Ap, zs, one, nullptr, Fbb, nullptr, nullptr, st);
     MDP_HIP(hipMemcpyAsync(xs, x, (size_t)nc * sizeof(double2), hipMemcpyDeviceToDevice, st));
     launch_scale_cols(xs, 1, nc, 1, norms, 0, st);
@@ -1658,8 +1728,20 @@ int mdp_dd_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, const md
     if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
     if (n_sub < 1 || !grad_k2 || !grad_d || n_rcv < 0 || (n_rcv > 0 && (!rcv_sub || !rcv_node || !ubar)))
         return fail(ctx, MDP_ERR_ARG, "null or empty gradient arguments");
-    for (int t = 0; t < n_rcv; ++t)
+    if (!P || !subs || !sides) return fail(ctx, MDP_ERR_ARG, "null or empty gradient arguments");
+    // everything the reverse pass checks, before the forward solve queues any work
+    for (int i = 0; i < n_sub; ++i) {
+        if (!P[i]) return fail(ctx, MDP_ERR_ARG, "null projector");
+        if (P[i]->precision != MDP_C128) return fail(ctx, MDP_ERR_ARG, "gradient: projectors must be complex128");
+    }
+    for (int t = 0; t < n_rcv; ++t) {
         if (rcv_sub[t] < 0 || rcv_sub[t] >= n_sub) return fail(ctx, MDP_ERR_ARG, "receiver subdomain out of range");
+        const int n = P[rcv_sub[t]]->g.n;
+        if (rcv_node[t] < 0 || rcv_node[t] >= (n + 1) * (n + 1))
+            return fail(ctx, MDP_ERR_ARG, "receiver node out of range");
+        if (!std::isfinite(ubar[t].re) || !std::isfinite(ubar[t].im))
+            return fail(ctx, MDP_ERR_NONFINITE, "non-finite receiver weight");
+    }
     GradArgs ga{n_rcv, rcv_sub, rcv_node, ubar, grad_k2, grad_d};
     int rc = MDP_OK;
     {
@@ -1722,7 +1804,7 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
                 sf.push_back(has ? reinterpret_cast<const double*>(sources[i].f) : nullptr);
                 sjet.push_back(has ? reinterpret_cast<const double*>(sources[i].jet) : nullptr);
             }
-        begin_call(ctx, st);
+        CallScope scope(ctx, st);
         HostBlob blob;
         const size_t o_cidx = blob.put(cidx), o_goff = blob.put(goff), o_sf = blob.put(sf), o_sjet = blob.put(sjet);
         const char* img = ctx->ws.stage.upload(blob, st);
@@ -1771,7 +1853,6 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
                                            (int)jobs.size(), total, max_ng, uo, reinterpret_cast<const double*>(c), st);
             }
             batched_band_solve(ctx, jobs, plans, uo, st);
-            end_call(ctx, st);
             return MDP_OK;
         }
         size_t e0 = 0;
@@ -1822,7 +1903,6 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
             }
             e0 += grp.size();
         }
-        end_call(ctx, st);
         return MDP_OK;
     });
 }
@@ -1839,7 +1919,7 @@ int mdp_ap_solve(mdp_ctx* ctx, int n, double h, double k, int precision, int bat
         if (batch == 0) return MDP_OK;
         hipStream_t st = (hipStream_t)stream;
         const long npts = (long)(n + 1) * (n + 1);
-        begin_call(ctx, st);
+        CallScope scope(ctx, st);
         const int chunk = chunk_size(plan, precision, ctx->ws_cap, batch);
         prepare_ws(ctx, plan, precision, chunk);
         for (int b0 = 0; b0 < batch; b0 += chunk) {
@@ -1862,7 +1942,6 @@ int mdp_ap_solve(mdp_ctx* ctx, int n, double h, double k, int precision, int bat
                         },
                         st);
         }
-        end_call(ctx, st);
         return MDP_OK;
     });
 }

@@ -1495,6 +1495,21 @@ void launch_zaxpy_norms(int n, const double2* dx, double2* x, double* norms, dou
     MDP_HIP(hipGetLastError());
 }
 
+// out = a - b (complex vectors of length n; out may alias either)
+__global__ void __launch_bounds__(256) zsub_kernel(int n, const double2* a, const double2* b, double2* out) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const double2 x = a[i], y = b[i];
+        out[i] = make_double2(x.x - y.x, x.y - y.y);
+    }
+}
+
+void launch_zsub(int n, const double2* a, const double2* b, double2* out, hipStream_t st) {
+    if (n <= 0) return;
+    const int g = std::max(1, std::min(256, (n + 255) / 256));
+    hipLaunchKernelGGL(zsub_kernel, dim3(g), dim3(256), 0, st, n, a, b, out);
+    MDP_HIP(hipGetLastError());
+}
+
 void launch_diag_range(const double2* L, int n, int ld, double* out, hipStream_t st) {
     hipLaunchKernelGGL(diag_range_kernel, dim3(1), dim3(256), 0, st, L, n, ld, out);
     MDP_HIP(hipGetLastError());

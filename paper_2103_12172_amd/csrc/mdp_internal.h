@@ -365,7 +365,7 @@ void launch_extend_density(const double* E, int ng, int ncol, const double* c, c
                            const int* gq, const int* gside, int n, double* w, long w_stride, const long* woff,
                            hipStream_t st);
 
-// projector build, support-in / gamma-out form (FP64)
+// projector build, support-in / gamma-out form (FP64 or FP32 storage and arithmetic)
 constexpr int FUSED_K = 8;   // rows per recomputed segment of the fused tridiagonal sweep
 // One projector's columns in a batched support-in / gamma-out build: global
 // columns b0 .. b0+R-1 of the launches are its columns src.col0 .. src.col0+R-1.
@@ -374,7 +374,10 @@ constexpr int FUSED_K = 8;   // rows per recomputed segment of the fused tridiag
 // n covers them.  Layouts: gc [R][n+1][4] ring table, spec / spec_hat [R][4][W]
 // folded special rows, lf / rf / tf [(n+1)][W] interleaved complex Thomas factors
 // l_m, r_m = 1/d_m and twisted pivots, ckpt [R][nseg][2][W], xs / us
-// [R][2][4][W], thin [R][W/64][rows_pad][4].
+// [R][2][4][W], thin [R][W/64][rows_pad][4].  The buffers and the plan tables
+// hold elements of the build's arithmetic type (double, or float for complex64):
+// the pointers are typed double* and reinterpreted by the kernels.  Sf, Si are the
+// folded sine matrices, colc the per-column off-diagonal, in the same type.
 struct FusedJob {
     SrcDesc src;
     StencilCoef sc;
@@ -385,10 +388,20 @@ struct FusedJob {
     double *gc, *spec, *spec_hat, *ckpt, *xs, *thin, *us, *Q;
     const int *gm, *gq;
 };
-// jobs: device table sorted by b0; total = sum of R; max_*: largest per-job extents
+// jobs: device table sorted by b0; total = sum of R; max_*: largest per-job extents; T the
+// storage and arithmetic type of the build (double or float)
+template <class T>
 void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_items, hipStream_t st);
-void launch_proj_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_wblk, size_t lds_bytes,
-                            hipStream_t st);
+// the fused sweep, lanes_cols (1, 2 or 4) mode columns per lane (or, with may_tune and the sweep
+// autotuner on, the fastest of the three for this kind of batch), max_w the widest job's W,
+// waves_one_col the batch's wavefront count at one column per lane; returns the columns per lane
+// it used
+template <class T>
+int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, int max_w, long waves_one_col, int lanes_cols,
+                           bool may_tune, hipStream_t st);
+// process-wide: pick the fused sweep's columns per lane by timing at first use
+void set_sweep_autotune(int on);
+template <class T>
 void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, hipStream_t st);
 bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi);
 
@@ -516,6 +529,8 @@ void launch_packed_ahx_set(const PackedDevice& d, int nc, const double2* Ap, con
 // accumulators of a later kernel set to zero.
 void launch_packed_axpy(const PackedDevice& d, int n_sub, int max_m, const double2* Ap, const double2* x,
                         double2 alpha, const double2* F, double2* out, double* norms, double* clr, hipStream_t st);
+// out = a - b (out may alias a or b)
+void launch_zsub(int n, const double2* a, const double2* b, double2* out, hipStream_t st);
 // x += dx; norms: += ||x||^2 (updated), ||dx||^2; clr as above.
 void launch_zaxpy_norms(int n, const double2* dx, double2* x, double* norms, double* clr, hipStream_t st);
 // Multifrontal Cholesky of the interface Gram matrix: one node of the

@@ -28,7 +28,7 @@ EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector"
             "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
             "mdp_cheb_coeffs", "mdp_version", "mdp_cache_clear", "mdp_profile_enable", "mdp_profile_report",
             "mdp_set_projector_path", "mdp_set_interface_path", "mdp_profile_select", "mdp_projector_gamma_feet", "mdp_ap_grid",
-            "mdp_dd_gradient", "mdp_set_autotune"]
+            "mdp_dd_gradient", "mdp_set_autotune", "mdp_set_fused_schedule", "mdp_fused_schedule_used"]
 MDP_PATH_AUTO, MDP_PATH_DENSE = 0, 1
 PROJECTOR_PATHS = {"auto": MDP_PATH_AUTO, "dense": MDP_PATH_DENSE}
 INTERFACE_PATHS = {"auto": 0, "dense": 1, "multifrontal": 2}
@@ -110,6 +110,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mdp_set_interface_path.restype = ip
     lib.mdp_set_autotune.argtypes = [vp, ip]
     lib.mdp_set_autotune.restype = ip
+    lib.mdp_set_fused_schedule.argtypes = [vp, ip]
+    lib.mdp_set_fused_schedule.restype = ip
+    lib.mdp_fused_schedule_used.argtypes = [vp]
+    lib.mdp_fused_schedule_used.restype = ip
     lib.mdp_cache_clear.argtypes = [vp]
     lib.mdp_cache_clear.restype = ip
     lib.mdp_profile_enable.argtypes = [vp, ip]
@@ -372,9 +376,19 @@ def mdp_set_interface_path(ctx: Context, path):
 
 
 def mdp_set_autotune(ctx: Context, enable: bool = True):
-    """Pick the sine GEMM's tile shape per (precision, n, rows) by timing at first use (process-wide;
-    results change only by rounding)."""
+    """Pick the sine GEMM's tile shape per (precision, n, rows) and the fused sweep's columns per lane
+    per (precision, widest n, batch size) by timing at first use (process-wide; results change only by
+    rounding)."""
     ctx.check(ctx.lib.mdp_set_autotune(ctx.handle, 1 if enable else 0))
+
+
+def mdp_set_fused_schedule(ctx: Context, cols_per_lane: int = 0):
+    """Mode columns per lane of the fused projector sweep (1, 2, 4; 0 = chosen per batch)."""
+    ctx.check(ctx.lib.mdp_set_fused_schedule(ctx.handle, int(cols_per_lane)))
+
+
+def mdp_fused_schedule_used(ctx: Context) -> int:
+    return int(ctx.lib.mdp_fused_schedule_used(ctx.handle))
 
 
 def mdp_profile_enable(ctx: Context, enable: bool = True):

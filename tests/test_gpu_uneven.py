@@ -11,18 +11,20 @@ nested-dissection factorisation of its Gram matrix), through the C-ABI.
   layouts: the two factor the same Gram matrix and refine against the same
   residual, so their coefficients agree to rounding (1e-11 relative).
 * The 16x16 layout (n in {128..512}, k in U[20, 80], 65,536 AP solves): no
-  oracle run at that size; the refinement's own convergence check must pass,
-  the residual must be at the level of the small layout's, and for sampled
-  subdomains the oracle's reconstruction from the GPU's coefficients (its
-  own AP solve of eq. potential_solution_homo) must match the GPU's solution
-  on N+.
+  oracle least squares at that size (Qbar is 595,968 x 32,768).  The GPU's c
+  must satisfy the normal equations of the reduced system built from the GPU's
+  Q (checked on the host, subdomain by subdomain: every cosine between the
+  residual and a column of Qbar below 1e-12 * max(1, cond/100)); Q itself is
+  checked against the oracle per n in test_gpu_fullsize.py; and for sampled
+  subdomains the oracle's reconstruction from the GPU's coefficients (its own
+  AP solve of eq. potential_solution_homo) must match the GPU's solution on N+.
 """
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import solve as osolve
+from oracle import interface as ointerface, solve as osolve
 from oracle.extension import extension_matrix
 from oracle.grid import APGrid
 from oracle.projector import potential
@@ -97,17 +99,50 @@ def test_multifrontal_matches_dense(ctx, name):
     print("%s: multifrontal vs dense c rel diff %.3e, residuals %.3e / %.3e, cond %.3e / %.3e"
           % (w.name, err, a.rel_residual, b.rel_residual, a.cond or 0.0, b.cond or 0.0))
     assert err < 1e-11 * max(1.0, (a.cond or 1.0) / 100.0)
-    assert abs(a.rel_residual - b.rel_residual) <= 1e-6 * a.rel_residual + 1e-13
+    assert abs(a.rel_residual - b.rel_residual) <= 1e-6 * a.rel_residual
     assert b.cond and abs(np.log(b.cond / a.cond)) < 0.1
+
+
+def _normal_residual(w, projs, c):
+    """Largest cosine between the least-squares residual and a column of the reduced
+    matrix, max_b |Qbar(:, b)^* r| / (||Qbar(:, b)|| ||r||), from the GPU's Q and c on
+    the host, one subdomain at a time.  With f = 0 the residual of the reduced system
+    (Sec. 3.3.3) on subdomain i's rows is Q_i c_i (the known coefficients moved to the
+    right-hand side are part of c), and the exact least-squares solution makes every
+    such cosine zero (the normal equations Qbar^* r = 0)."""
+    M = w.m_star
+    blocks = ointerface.plan_unknowns(w.sides, M)
+    h, cn2, rn2 = [], [], 0.0
+    for i in range(len(w.subdomains)):
+        Q = projs[i].q_tensor().cpu().numpy()
+        r = Q @ c[i]
+        h.append(Q.conj().T @ r)
+        cn2.append((np.abs(Q) ** 2).sum(axis=0))
+        rn2 += float(np.vdot(r, r).real)
+    worst = 0.0
+    for _, contrib in blocks:
+        g = np.zeros(M, dtype=complex)
+        nn = np.zeros(M)
+        for (i, s, kind, coef) in contrib:
+            sl = slice(kind * 4 * M + s * M, kind * 4 * M + (s + 1) * M)
+            g += np.conj(coef) * h[i][sl]
+            nn += abs(coef) ** 2 * cn2[i][sl]
+        worst = max(worst, float((np.abs(g) / np.sqrt(nn)).max()))
+    return worst / np.sqrt(rn2)
 
 
 def test_uneven_full_size(ctx):
     """The 16x16 layout: 256 distinct (n, k) projectors, 32,768 interface unknowns."""
     w = wl.config_uneven()
     res = _solve(ctx, w, "auto")
-    assert np.isfinite(res.rel_residual) and res.rel_residual < 0.05
+    assert np.isfinite(res.rel_residual)
     assert res.cond and np.isfinite(res.cond)
     c = res.c.cpu().numpy().reshape(len(w.subdomains), 8 * w.m_star)
+    cosine = _normal_residual(w, res.projectors, c)
+    print("%s: normal-equation residual (largest cosine between r and a column) %.3e, cond %.3e, residual %.3e"
+          % (w.name, cosine, res.cond, res.rel_residual))
+    assert cosine < 1e-12 * max(1.0, res.cond / 100.0)
+    assert res.rel_residual < 1e-5   # measured 1.36e-6 (the 3x3 layout's coarser grids: 1.2e-3)
     d = osolve.boundary_coefficients(w, w.m_star)
     rng = np.random.default_rng(11)
     picks = sorted(set(rng.choice(len(w.subdomains), size=3, replace=False).tolist()) | {0})
