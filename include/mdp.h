@@ -303,7 +303,10 @@ int mdp_dd_gradient(mdp_ctx* ctx, int n_sub, const mdp_subdomain* subs, const md
  * the solution on N+, the difference potential at the other nodes of the grid
  * rows m_lo-1..m_hi+1 that hold N+ (the auxiliary solve stops at those rows:
  * its right-hand side vanishes outside them), and zero on the remaining rows.
- * Subdomains sharing a projector are solved in one batch.
+ * Subdomains sharing a projector are solved in one batch, in the projector's
+ * precision; when the subdomains use several projectors and no source is given,
+ * all their solves run in the same launches in FP64 (whatever the projectors'
+ * precision: that of a build refers to its 8M* solves per projector).
  * Errors: MDP_ERR_ARG, MDP_ERR_OOM, MDP_ERR_HIP. */
 int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P,
                     const mdp_c128* c, const mdp_source* sources, void* stream, mdp_c128* u_out);

@@ -282,10 +282,12 @@ struct FusedItem {
     mdp_projector* P;
 };
 
-// Mode columns per lane of the fused sweep: two (independent recurrences side by side,
-// half the factor loads per column) when that still leaves about two wavefronts per
-// SIMD of the chip, else one; or what the autotuner measured fastest for the batch.
-int sweep_lanes_cols(long waves_one_col) { return waves_one_col >= 2L * 2048 ? 2 : 1; }
+// Mode columns per lane of the fused sweep when none is set: complex64 takes two
+// (independent recurrences side by side, half the cross-lane reduction per column; its
+// registers still allow four wavefronts per SIMD) when that leaves about four wavefronts
+// per SIMD of the chip; complex128 takes one (two columns need about 200 VGPRs, i.e. two
+// wavefronts per SIMD, and measure slower); or what the autotuner measured fastest.
+int sweep_lanes_cols(bool f64, long waves_one_col) { return (!f64 && waves_one_col >= 2L * 4096) ? 2 : 1; }
 
 // Q of every item by the support-in / gamma-out route, T the arithmetic of the build
 // (double for complex128, float for complex64), the columns of all items through each
@@ -356,6 +358,7 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
         auto cdp = [](const void* p) { return reinterpret_cast<const double*>(p); };
         std::vector<FusedJob> jobs(jh.size());
         int b0 = 0, max_items = 0, max_w = 0, max_ng = 0;
+        long groups[3] = {0, 0, 0};
         long waves_one_col = 0;
         double fold_bytes = 0.0, sweep_flops = 0.0, sweep_bytes = 0.0, gather_bytes = 0.0;
         for (size_t q = 0; q < jh.size(); ++q) {
@@ -382,6 +385,10 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
             J.ldq = ng;
             J.b0 = b0;
             J.R = R;
+            for (int lg = 0; lg < 3; ++lg) {
+                J.g0[lg] = (int)groups[lg];
+                groups[lg] += (R + (1 << lg) - 1) >> lg;
+            }
             J.Sf = cdp(f64 ? plan.Sf64.p : plan.Sf32.p);
             J.Si = cdp(f64 ? plan.Si64.p : plan.Si32.p);
             J.lf = cdp(f64 ? plan.lf64.p : plan.lf32.p);
@@ -439,12 +446,12 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
                 q0 = q1;
             }
         };
-        const int L = ctx->sweep_cols > 0 ? ctx->sweep_cols : sweep_lanes_cols(waves_one_col);
+        const int L = ctx->sweep_cols > 0 ? ctx->sweep_cols : sweep_lanes_cols(f64, waves_one_col);
         pr.run("fold_ring", st, 0.0, fold_bytes, [&] { launch_fold_ring_jobs<T>(dj, nj, total, max_items, st); });
         gemms(true);
         pr.run(f64 ? "ap_fused_f64" : "ap_fused_f32", st, sweep_flops, sweep_bytes, [&] {
             ctx->last_sweep_cols =
-                launch_proj_sweep_jobs<T>(dj, nj, total, max_w, waves_one_col, L, ctx->sweep_cols == 0, st);
+                launch_proj_sweep_jobs<T>(dj, nj, total, groups, max_w, waves_one_col, L, ctx->sweep_cols == 0, st);
         });
         gemms(false);
         pr.run("gather_q", st, 0.0, gather_bytes, [&] { launch_gather_q_fused_jobs<T>(dj, nj, total, max_ng, st); });
@@ -1784,13 +1791,12 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P, cons
         std::stable_sort(groups.begin(), groups.end(), [&](const std::vector<int>& a, const std::vector<int>& b) {
             return P[a[0]]->g.n < P[b[0]]->g.n;
         });
-        bool any_source = false, all_c128 = true;
-        for (int i = 0; i < n_sub; ++i) {
-            any_source = any_source || (sources && sources[i].f);
-            all_c128 = all_c128 && P[i]->precision == MDP_C128;
-        }
-        // several distinct projectors, complex128, no source: every group's solve in the same launches
-        const bool batched = groups.size() > 1 && all_c128 && !any_source;
+        bool any_source = false;
+        for (int i = 0; i < n_sub; ++i) any_source = any_source || (sources && sources[i].f);
+        // several distinct projectors, no source: every group's solve in the same launches, in FP64
+        // whatever the projectors' precision (one AP solve per subdomain; the precision of a build
+        // is that of its 8M* solves per projector)
+        const bool batched = groups.size() > 1 && !any_source;
         // per batch entry: the subdomain (its coefficients in c), its grid's offset in u_out and its source
         std::vector<int> cidx;
         std::vector<long> goff;

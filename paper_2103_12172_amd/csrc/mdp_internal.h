@@ -384,6 +384,7 @@ struct FusedJob {
     Fold f;
     int nseg, rows_pad, ng, ldq;
     int b0, R;
+    int g0[3];   // first group of 1, 2, 4 consecutive columns (groups never span two jobs)
     const double *Sf, *Si, *lf, *rf, *tf, *colc;
     double *gc, *spec, *spec_hat, *ckpt, *xs, *thin, *us, *Q;
     const int *gm, *gq;
@@ -396,9 +397,11 @@ void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_i
 // autotuner on, the fastest of the three for this kind of batch), max_w the widest job's W,
 // waves_one_col the batch's wavefront count at one column per lane; returns the columns per lane
 // it used
+// groups[lg]: the number of groups of 1 << lg consecutive columns of one job over all jobs
+// (the jobs' g0[lg] are their first groups)
 template <class T>
-int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, int max_w, long waves_one_col, int lanes_cols,
-                           bool may_tune, hipStream_t st);
+int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, const long* groups, int max_w,
+                           long waves_one_col, int lanes_cols, bool may_tune, hipStream_t st);
 // process-wide: pick the fused sweep's columns per lane by timing at first use
 void set_sweep_autotune(int on);
 template <class T>

@@ -180,25 +180,64 @@ struct Lanes {
     typedef T R __attribute__((ext_vector_type(L)));       // L real values
 };
 
-// Grid: one workgroup (one wavefront) per (column, block of 64 L mode columns), the
-// block index fastest, so that consecutive workgroups, which the dispatcher deals
-// round-robin to the eight XCDs, keep one mode block per XCD when nwb divides 8 (the
-// factor rows of a block then stay in that XCD's L2).
+// LDS of one workgroup: two buffers (the segment being swept, the one being loaded) of
+// the factor rows r_m of the workgroup's 64 L mode columns (interleaved complex, row
+// after row), and of the ring rows (gA, gB of both parities) of its NW columns.
 template <class T, int L>
-__global__ void __launch_bounds__(64) proj_sweep_kernel(const FusedJob* __restrict__ jobs, int njobs, int nwb) {
+struct SweepLds {
+    static constexpr int K = FUSED_K;
+    static constexpr int row_bytes = 64 * L * 2 * (int)sizeof(T);
+    static constexpr int fac_bytes = K * row_bytes;              // one buffer of factor rows
+    static constexpr int ring_bytes_per_col = K * 4 * (int)sizeof(T);
+    static constexpr int ring_bytes = 4 * ring_bytes_per_col;    // NW <= 4 columns
+    static constexpr int bytes = 2 * (fac_bytes + ring_bytes);
+    static_assert(ring_bytes <= 1024, "a segment's ring rows are staged by one 1 KB transfer");
+    static_assert(fac_bytes % 1024 == 0, "factor rows are staged in 1 KB transfers");
+};
+
+__device__ inline void lds_dma16(const void* src, void* lds_dst) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                     (__attribute__((address_space(3))) void*)lds_dst, 16, 0, 0);
+}
+
+// Grid: one workgroup of NW wavefronts per (group of NW consecutive columns of one job,
+// block of 64 L mode columns), the block index fastest, so that consecutive
+// workgroups, which the dispatcher deals round-robin to the eight XCDs, keep one mode
+// block per XCD when nwb divides 8 (its factor rows then stay in that XCD's L2).
+// The NW wavefronts sweep their own columns through the same mode columns in step:
+// per K-row segment they read the factor rows from LDS, which the workgroup loads
+// one segment ahead with direct global-to-LDS transfers (one load of a factor row
+// serves NW columns; the only global loads a segment waits for were issued a
+// segment earlier).  A wavefront without a column (the job's last group) sweeps
+// its group's last column again and writes nothing.
+template <class T, int L>
+__global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restrict__ jobs, int njobs, int nwb,
+                                                          int lg_nw) {
     constexpr int K = FUSED_K;
     static_assert(K == 8, "a segment is reduced as 8 rows x 4 products");
+    typedef SweepLds<T, L> S;
     typedef typename Lanes<T, L>::V V;
     typedef typename Lanes<T, L>::R Rv;
-    typedef T T2 __attribute__((ext_vector_type(2)));
-    const int gcol = blockIdx.x / nwb, wblk = blockIdx.x - gcol * nwb;
-    const FusedJob& J = jobs[find_fused_job(jobs, njobs, gcol)];
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int NW = 1 << lg_nw;
+    const int grp = blockIdx.x / nwb, wblk = blockIdx.x - grp * nwb;
+    int jlo = 0, jhi = njobs - 1;   // the job holding column group grp (jobs sorted by g0)
+    while (jlo < jhi) {
+        const int mid = (jlo + jhi + 1) >> 1;
+        if (jobs[mid].g0[lg_nw] <= grp) jlo = mid;
+        else jhi = mid - 1;
+    }
+    const FusedJob& J = jobs[jlo];
     const int W = J.f.W, P1 = J.f.P1;
     const int wbase = wblk * 64 * L;
-    if (wbase >= W) return;   // a job narrower than the launch (uniform over the wavefront)
-    const int lane = threadIdx.x;
+    if (wbase >= W) return;   // a job narrower than the launch (uniform over the workgroup)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int bfirst = (grp - J.g0[lg_nw]) * NW;     // the group's first column (job-local)
+    const bool has_col = bfirst + wave < J.R;
+    const int b = min(bfirst + wave, J.R - 1);
     const int c0 = wbase + lane * L;
     const bool live = c0 < W;              // lanes past W (a last wavefront of 64 columns when L > 1)
+    const bool writes = live && has_col;
     const int cc = live ? c0 : 0;          // read column 0 there; nothing of theirs is written
     const bool odd = cc < P1;              // uniform over the lane's L columns (P1 is a multiple of 64)
     const int base = odd ? 0 : P1;
@@ -206,22 +245,15 @@ __global__ void __launch_bounds__(64) proj_sweep_kernel(const FusedJob* __restri
     const int m_lo = J.src.m_lo, m_hi = J.src.m_hi, q_lo = J.src.q_lo;
     const int m0 = m_lo - 1, t = m_hi + 1;
     const int nseg = J.nseg;
-    const int b = gcol - J.b0;
     const long LW = W;
 
     const T* __restrict__ Sf = reinterpret_cast<const T*>(J.Sf);
     const T* __restrict__ Si = reinterpret_cast<const T*>(J.Si);
     const T* __restrict__ colc = reinterpret_cast<const T*>(J.colc);
-    // factor rows: uniform row bases, the lane's vector at the 32-bit index lv (a row holds W / L
-    // lane vectors), so that loads take a scalar base and a 32-bit lane offset
-    const auto lf = gview(reinterpret_cast<const V*>(J.lf));
-    const auto rf = gview(reinterpret_cast<const V*>(J.rf));
     const T* __restrict__ tf = reinterpret_cast<const T*>(J.tf);
-    const int rowv = W / L;
-    const unsigned lv = (unsigned)(cc / L);
-    // the column's ring table: per row the pair (gA, gB) of its parity block
-    const auto ring = gview(reinterpret_cast<const T2*>(reinterpret_cast<const T*>(J.gc) + (long)b * (n + 1) * 4));
-    const unsigned rpar = odd ? 0u : 1u;
+    const char* __restrict__ rtab = reinterpret_cast<const char*>(J.rf) + (long)wbase * 2 * sizeof(T);
+    const char* __restrict__ twrow = reinterpret_cast<const char*>(J.tf) + ((long)t * LW + wbase) * 2 * sizeof(T);
+    const char* __restrict__ gring = reinterpret_cast<const char*>(J.gc);
     const T* __restrict__ spec_hat = reinterpret_cast<const T*>(J.spec_hat) + (long)b * 4 * LW + cc;
     T* __restrict__ ck = reinterpret_cast<T*>(J.ckpt) + (long)b * nseg * 2 * LW + cc;
     T* __restrict__ xs = reinterpret_cast<T*>(J.xs) + (long)b * 8 * LW + cc;
@@ -229,8 +261,8 @@ __global__ void __launch_bounds__(64) proj_sweep_kernel(const FusedJob* __restri
     T* __restrict__ th = reinterpret_cast<T*>(J.thin) + ((long)b * (W >> 6) + blk) * ((long)nseg * K) * 4;
 
     // per-column constants: the transform of the two ring entries, the synthesis at
-    // q_lo-1 and q_lo, the interior off-diagonal, the twisted pivot of row t
-    T s1[L], s2[L], t1[L], t2[L], a[L], twr[L], twi[L];
+    // q_lo-1 and q_lo, the interior off-diagonal
+    T s1[L], s2[L], t1[L], t2[L], a[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         const int c = cc + l;
@@ -239,10 +271,7 @@ __global__ void __launch_bounds__(64) proj_sweep_kernel(const FusedJob* __restri
         t1[l] = live ? Si[(long)c * LW + base + q_lo - 2] : T(0);
         t2[l] = live ? Si[(long)c * LW + base + q_lo - 1] : T(0);
         a[l] = colc[c];
-        twr[l] = tf[2 * ((long)t * LW + c)];
-        twi[l] = tf[2 * ((long)t * LW + c) + 1];
     }
-    // special input row of m: 0..3, or -1 (uniform)
     auto special_in = [&](int m) -> int {
         return (m == m_lo) ? 0 : (m == m_lo + 1) ? 1 : (m == m_hi - 1) ? 2 : (m == m_hi) ? 3 : -1;
     };
@@ -252,11 +281,51 @@ __global__ void __launch_bounds__(64) proj_sweep_kernel(const FusedJob* __restri
     // a segment holding a special row (the first, and those reaching row t - 2)
     auto general = [&](int s) { return s == 0 || m0 + s * K + K - 1 >= t - 2; };
 
-    // one elimination step of row m (rows past t are clamped to t by the caller)
-    auto eliminate = [&](auto gen_tag, int m, T* yr, T* yi) {
+    // staging of segment s into buffer sb: the factor rows r_m, m = mb..mb+K-1, of the
+    // workgroup's mode columns in 1 KB transfers shared out over the wavefronts (at row t,
+    // and the rows past it, the twisted pivot tw_t: the elimination step p = r y then gives
+    // x_t = tw_t y_t there, and the rows past t are not used), and the ring rows of the NW
+    // columns in one transfer by wavefront 0
+    char* const fac_buf = lds;
+    char* const ring_buf = lds + 2 * S::fac_bytes;
+    auto stage = [&](int s, int sb) {
+        const int mb = m0 + s * K;
+        char* fdst = fac_buf + sb * S::fac_bytes;
+        for (int ch = wave; ch < S::fac_bytes / 1024; ch += NW) {
+            const int o = ch * 1024 + lane * 16;
+            const int i = o / S::row_bytes, cb = o - i * S::row_bytes;
+            const int m = mb + i;
+            lds_dma16((m < t ? rtab + (long)m * LW * 2 * sizeof(T) : twrow) + cb, fdst + ch * 1024);
+        }
+        if (wave == 0) {
+            const int o = lane * 16;
+            if (o < NW * S::ring_bytes_per_col) {
+                const int wv = o / S::ring_bytes_per_col, rem = o - wv * S::ring_bytes_per_col;
+                const int i = rem / (4 * (int)sizeof(T)), part = rem - i * 4 * (int)sizeof(T);
+                const int bw = min(bfirst + wv, J.R - 1);
+                const int m = min(mb + i, t);
+                lds_dma16(gring + (((long)bw * (n + 1) + m) * 4) * sizeof(T) + part, ring_buf + sb * S::ring_bytes);
+            }
+        }
+    };
+    // factor row i of buffer sb for the lane's columns, and the column's ring pair of row i
+    auto fac = [&](int sb, int i) -> V {
+        return *reinterpret_cast<const V*>(fac_buf + sb * S::fac_bytes + i * S::row_bytes + lane * (2 * L * sizeof(T)));
+    };
+    auto ring = [&](int sb, int i, T& gA, T& gB) {
+        const T* r = reinterpret_cast<const T*>(ring_buf + sb * S::ring_bytes + wave * S::ring_bytes_per_col) +
+                     i * 4 + (odd ? 0 : 2);
+        gA = r[0];
+        gB = r[1];
+    };
+    // one step of the forward elimination at row m: y = ghat - a p_prev, p = r y (the staged
+    // r is tw_t at row t, so p is x_t there), in place in (pr, pi); a special input row adds
+    // its transformed values (a uniform branch: read only on those four rows)
+    auto step = [&](auto gen_tag, int sb, int i, int m, T* pr, T* pi) {
         constexpr bool GEN = decltype(gen_tag)::value;
-        const T2 g = ring[(long)m * 2 + rpar];
-        const V fl = (lf + (long)m * rowv)[lv];
+        T gA, gB;
+        ring(sb, i, gA, gB);
+        const V f = fac(sb, i);
         T sp[L];
 #pragma unroll
         for (int l = 0; l < L; ++l) sp[l] = T(0);
@@ -270,113 +339,118 @@ __global__ void __launch_bounds__(64) proj_sweep_kernel(const FusedJob* __restri
         }
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            const T gh = fma(g.x, s1[l], fma(g.y, s2[l], sp[l]));
-            const T lr = fl[2 * l], li = fl[2 * l + 1];
-            const T nr = fma(-lr, yr[l], fma(li, yi[l], gh));
-            const T ni = fma(-lr, yi[l], -(li * yr[l]));
-            yr[l] = nr;
-            yi[l] = ni;
+            const T gh = fma(gA, s1[l], fma(gB, s2[l], sp[l]));
+            const T yr = fma(-a[l], pr[l], gh);
+            const T yi = -a[l] * pi[l];
+            const T rr = f[2 * l], ri = f[2 * l + 1];
+            pr[l] = fma(rr, yr, -(ri * yi));
+            pi[l] = fma(rr, yi, ri * yr);
         }
     };
 
-    // forward elimination from row m0 (y_{m0-1} = 0), y kept at the end of every full segment
+    // forward elimination from row m0 (p_{m0-1} = 0), p kept at the end of every full segment
+    stage(0, 0);
+    __syncthreads();
     {
-        T yr[L], yi[L];
+        T pr[L], pi[L];
 #pragma unroll
-        for (int l = 0; l < L; ++l) yr[l] = yi[l] = T(0);
-        auto fwd = [&](auto gen_tag, int s) {
-#pragma unroll
-            for (int i = 0; i < K; ++i) eliminate(gen_tag, m0 + s * K + i, yr, yi);
-        };
+        for (int l = 0; l < L; ++l) pr[l] = pi[l] = T(0);
         for (int s = 0; s < nseg - 1; ++s) {
-            if (general(s)) fwd(std::true_type{}, s);
-            else fwd(std::false_type{}, s);
-            if (live) {
+            const int sb = s & 1;
+            stage(s + 1, sb ^ 1);
+            auto fwd = [&](auto gen_tag) {
+#pragma unroll
+                for (int i = 0; i < K; ++i) step(gen_tag, sb, i, m0 + s * K + i, pr, pi);
+            };
+            if (general(s)) fwd(std::true_type{});
+            else fwd(std::false_type{});
+            if (writes) {
                 Rv vr, vi;
 #pragma unroll
-                for (int l = 0; l < L; ++l) { vr[l] = yr[l]; vi[l] = yi[l]; }
+                for (int l = 0; l < L; ++l) { vr[l] = pr[l]; vi[l] = pi[l]; }
                 *reinterpret_cast<Rv*>(ck + (long)(2 * s) * LW) = vr;
                 *reinterpret_cast<Rv*>(ck + (long)(2 * s + 1) * LW) = vi;
             }
+            __syncthreads();   // buffer sb free, segment s+1 staged (the barrier waits for the transfers)
         }
     }
 
-    // back substitution segment by segment (x_{t+1} = 0, so the first row gives x_t = tw_t y_t)
+    // back substitution segment by segment (x_{t+1} = 0, so row t gives x_t = tw_t y_t):
+    // recompute the segment's p (x at row t) from the checkpoint before it, then walk back
+    // through it, x_m = p_m - r_m (a x_{m+1}), adding each row's synthesis products
     T xr[L], xi[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) xr[l] = xi[l] = T(0);
-    auto bwd = [&](auto gen_tag, int s) {
-        constexpr bool GEN = decltype(gen_tag)::value;
-        const int mb = m0 + s * K;
-        // y of the segment, recomputed from the checkpoint before it
-        T vr[K][L], vi[K][L];
-        {
-            T yr[L], yi[L];
-            if (s > 0) {
-                const Rv pr = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 2) * LW);
-                const Rv pi = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 1) * LW);
+    Rv cpr, cpi;   // the checkpoint the next segment starts from, loaded a segment ahead
+    if (nseg >= 2) {
+        cpr = *reinterpret_cast<const Rv*>(ck + (long)(2 * nseg - 4) * LW);
+        cpi = *reinterpret_cast<const Rv*>(ck + (long)(2 * nseg - 3) * LW);
+    }
+    for (int s = nseg - 1; s >= 0; --s) {
+        const int sb = s & 1;   // segment nseg-1 was staged by the forward pass's last step
+        T pr[L], pi[L];
 #pragma unroll
-                for (int l = 0; l < L; ++l) { yr[l] = pr[l]; yi[l] = pi[l]; }
-            } else {
-#pragma unroll
-                for (int l = 0; l < L; ++l) yr[l] = yi[l] = T(0);
-            }
+        for (int l = 0; l < L; ++l) {
+            pr[l] = s > 0 ? cpr[l] : T(0);
+            pi[l] = s > 0 ? cpi[l] : T(0);
+        }
+        if (s > 0) stage(s - 1, sb ^ 1);
+        if (s > 1) {
+            cpr = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 4) * LW);
+            cpi = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 3) * LW);
+        }
+        auto bwd = [&](auto gen_tag) {
+            constexpr bool GEN = decltype(gen_tag)::value;
+            const int mb = m0 + s * K;
+            T vr[K][L], vi[K][L];
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                eliminate(gen_tag, GEN ? min(mb + i, t) : mb + i, yr, yi);
+                step(gen_tag, sb, i, mb + i, pr, pi);
 #pragma unroll
-                for (int l = 0; l < L; ++l) { vr[i][l] = yr[l]; vi[i][l] = yi[l]; }
+                for (int l = 0; l < L; ++l) { vr[i][l] = pr[l]; vi[i][l] = pi[l]; }
             }
-        }
-        // walk back through the segment: x_m = r_m (y_m - a x_{m+1}) (tw_t at row t), and the
-        // row's synthesis products summed over the lane's columns
-        T acc[4 * K];
+            // read the factor rows again below rather than keep them in registers across the two
+            // walks (a compiler-level memory barrier; no instruction is emitted)
+            asm volatile("" ::: "memory");
+            T acc[4 * K];
 #pragma unroll
-        for (int i = K - 1; i >= 0; --i) {
-            const int m = mb + i;
-            acc[4 * i + 0] = acc[4 * i + 1] = acc[4 * i + 2] = acc[4 * i + 3] = T(0);
-            if (GEN && m > t) continue;
-            T rr[L], ri[L];
-            if (GEN && m == t) {
+            for (int i = K - 1; i >= 0; --i) {
+                const int m = mb + i;
+                acc[4 * i + 0] = acc[4 * i + 1] = acc[4 * i + 2] = acc[4 * i + 3] = T(0);
+                if (GEN && m > t) continue;
+                const V f = fac(sb, i);
 #pragma unroll
-                for (int l = 0; l < L; ++l) { rr[l] = twr[l]; ri[l] = twi[l]; }
-            } else {
-                const V fr = (rf + (long)m * rowv)[lv];
+                for (int l = 0; l < L; ++l) {
+                    const T sr = a[l] * xr[l], si_ = a[l] * xi[l];
+                    const T rr = f[2 * l], ri = f[2 * l + 1];
+                    xr[l] = fma(-rr, sr, fma(ri, si_, vr[i][l]));
+                    xi[l] = fma(-rr, si_, fma(-ri, sr, vi[i][l]));
+                    acc[4 * i + 0] = fma(xr[l], t1[l], acc[4 * i + 0]);
+                    acc[4 * i + 1] = fma(xi[l], t1[l], acc[4 * i + 1]);
+                    acc[4 * i + 2] = fma(xr[l], t2[l], acc[4 * i + 2]);
+                    acc[4 * i + 3] = fma(xi[l], t2[l], acc[4 * i + 3]);
+                }
+                if constexpr (GEN) {
+                    const int so = special_out(m);
+                    if (so >= 0 && writes) {
+                        Rv ore, oim;
 #pragma unroll
-                for (int l = 0; l < L; ++l) { rr[l] = fr[2 * l]; ri[l] = fr[2 * l + 1]; }
-            }
-#pragma unroll
-            for (int l = 0; l < L; ++l) {
-                const T tr = fma(-a[l], xr[l], vr[i][l]);
-                const T ti = fma(-a[l], xi[l], vi[i][l]);
-                xr[l] = fma(rr[l], tr, -(ri[l] * ti));
-                xi[l] = fma(rr[l], ti, ri[l] * tr);
-                acc[4 * i + 0] = fma(xr[l], t1[l], acc[4 * i + 0]);
-                acc[4 * i + 1] = fma(xi[l], t1[l], acc[4 * i + 1]);
-                acc[4 * i + 2] = fma(xr[l], t2[l], acc[4 * i + 2]);
-                acc[4 * i + 3] = fma(xi[l], t2[l], acc[4 * i + 3]);
-            }
-            if constexpr (GEN) {
-                const int so = special_out(m);
-                if (so >= 0 && live) {
-                    Rv ore, oim;
-#pragma unroll
-                    for (int l = 0; l < L; ++l) { ore[l] = xr[l]; oim[l] = xi[l]; }
-                    *reinterpret_cast<Rv*>(xs + (long)so * LW) = ore;
-                    *reinterpret_cast<Rv*>(xs + (long)(4 + so) * LW) = oim;
+                        for (int l = 0; l < L; ++l) { ore[l] = xr[l]; oim[l] = xi[l]; }
+                        *reinterpret_cast<Rv*>(xs + (long)so * LW) = ore;
+                        *reinterpret_cast<Rv*>(xs + (long)(4 + so) * LW) = oim;
+                    }
                 }
             }
-        }
-        GroupReduce<T, L>::run(acc, lane);
-        if (blk < (W >> 6) && GroupReduce<T, L>::writer(lane)) {
+            GroupReduce<T, L>::run(acc, lane);
+            if (has_col && blk < (W >> 6) && GroupReduce<T, L>::writer(lane)) {
 #pragma unroll
-            for (int e = 0; e < GroupReduce<T, L>::NOUT; ++e)
-                th[(long)s * K * 4 + GroupReduce<T, L>::vidx(lane, e)] = acc[e];
-        }
-    };
-    for (int s = nseg - 1; s >= 0; --s) {
-        if (general(s)) bwd(std::true_type{}, s);
-        else bwd(std::false_type{}, s);
+                for (int e = 0; e < GroupReduce<T, L>::NOUT; ++e)
+                    th[(long)s * K * 4 + GroupReduce<T, L>::vidx(lane, e)] = acc[e];
+            }
+        };
+        if (general(s)) bwd(std::true_type{});
+        else bwd(std::false_type{});
+        __syncthreads();   // buffer sb free, segment s-1 staged
     }
 }
 
@@ -384,20 +458,38 @@ __global__ void __launch_bounds__(64) proj_sweep_kernel(const FusedJob* __restri
 
 namespace {
 
-template <class T>
-void launch_cols(int L, const FusedJob* jobs, int njobs, int total, int max_w, hipStream_t st) {
-    const int nwb = (max_w + 64 * L - 1) / (64 * L);
-    const long blocks = (long)total * nwb;
+template <class T, int L>
+void launch_cl(const FusedJob* jobs, int njobs, long groups, int nwb, int lg_nw, hipStream_t st) {
+    const long blocks = groups * nwb;
     if (blocks > 0x7fffffffL) throw Error(MDP_ERR_ARG, "too many projector columns for one launch");
-    const dim3 grid((unsigned)blocks);
-    if (L == 1)
-        hipLaunchKernelGGL((proj_sweep_kernel<T, 1>), grid, dim3(64), 0, st, jobs, njobs, nwb);
-    else if (L == 2)
-        hipLaunchKernelGGL((proj_sweep_kernel<T, 2>), grid, dim3(64), 0, st, jobs, njobs, nwb);
-    else if (L == 4)
-        hipLaunchKernelGGL((proj_sweep_kernel<T, 4>), grid, dim3(64), 0, st, jobs, njobs, nwb);
-    else
-        throw Error(MDP_ERR_ARG, "columns per lane must be 1, 2 or 4");
+    constexpr int lds_bytes = SweepLds<T, L>::bytes;
+    const void* fn = reinterpret_cast<const void*>(&proj_sweep_kernel<T, L>);
+    static const bool lds_set = [fn] {   // more than 64 KB of dynamic LDS must be allowed explicitly
+        if (lds_bytes > 65536) MDP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes));
+        return true;
+    }();
+    (void)lds_set;
+    hipLaunchKernelGGL((proj_sweep_kernel<T, L>), dim3((unsigned)blocks), dim3(64 << lg_nw), lds_bytes, st, jobs, njobs,
+                       nwb, lg_nw);
+}
+
+// Wavefronts per workgroup for L columns per lane: four (one staged factor row serves four
+// columns) while that leaves at least four workgroups per CU of the chip (256 CUs), else
+// fewer (small batches: the workgroups' barriers would keep too few wavefronts busy).
+int lg_waves_per_group(long total, int max_w, int L) {
+    const long waves = total * ((max_w + 64 * L - 1) / (64 * L));
+    return waves >= 4L * 1024 ? 2 : waves >= 2L * 1024 ? 1 : 0;
+}
+
+// groups[lg] = number of column groups of 1 << lg columns over all jobs (the jobs' g0 tables)
+template <class T>
+void launch_cols(int L, const FusedJob* jobs, int njobs, int total, const long* groups, int max_w, hipStream_t st) {
+    const int lg_nw = lg_waves_per_group(total, max_w, L);
+    const int nwb = (max_w + 64 * L - 1) / (64 * L);
+    if (L == 1) launch_cl<T, 1>(jobs, njobs, groups[lg_nw], nwb, lg_nw, st);
+    else if (L == 2) launch_cl<T, 2>(jobs, njobs, groups[lg_nw], nwb, lg_nw, st);
+    else if (L == 4) launch_cl<T, 4>(jobs, njobs, groups[lg_nw], nwb, lg_nw, st);
+    else throw Error(MDP_ERR_ARG, "columns per lane must be 1, 2 or 4");
     MDP_HIP(hipGetLastError());
 }
 
@@ -416,11 +508,11 @@ std::map<std::tuple<int, int, int>, int> g_sweep_tuned;
 void set_sweep_autotune(int on) { g_sweep_tune.store(on ? 1 : 0); }
 
 template <class T>
-int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, int max_w, long waves_one_col, int lanes_cols,
-                           bool may_tune, hipStream_t st) {
+int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, const long* groups, int max_w,
+                           long waves_one_col, int lanes_cols, bool may_tune, hipStream_t st) {
     if (njobs <= 0 || total <= 0) return lanes_cols;
     if (!may_tune || !g_sweep_tune.load()) {
-        launch_cols<T>(lanes_cols, jobs, njobs, total, max_w, st);
+        launch_cols<T>(lanes_cols, jobs, njobs, total, groups, max_w, st);
         return lanes_cols;
     }
     int lg = 0;
@@ -430,7 +522,7 @@ int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, int max_w
         std::lock_guard<std::mutex> g(g_sweep_mu);
         auto it = g_sweep_tuned.find(key);
         if (it != g_sweep_tuned.end()) {
-            launch_cols<T>(it->second, jobs, njobs, total, max_w, st);
+            launch_cols<T>(it->second, jobs, njobs, total, groups, max_w, st);
             return it->second;
         }
     }
@@ -440,9 +532,9 @@ int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, int max_w
     int best = lanes_cols;
     float best_ms = 1e30f;
     for (int L : {1, 2, 4}) {
-        launch_cols<T>(L, jobs, njobs, total, max_w, st);
+        launch_cols<T>(L, jobs, njobs, total, groups, max_w, st);
         MDP_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < 2; ++r) launch_cols<T>(L, jobs, njobs, total, max_w, st);
+        for (int r = 0; r < 2; ++r) launch_cols<T>(L, jobs, njobs, total, groups, max_w, st);
         MDP_HIP(hipEventRecord(e1, st));
         MDP_HIP(hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -455,10 +547,10 @@ int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, int max_w
         std::lock_guard<std::mutex> g(g_sweep_mu);
         g_sweep_tuned[key] = best;
     }
-    launch_cols<T>(best, jobs, njobs, total, max_w, st);
+    launch_cols<T>(best, jobs, njobs, total, groups, max_w, st);
     return best;
 }
-template int launch_proj_sweep_jobs<double>(const FusedJob*, int, int, int, long, int, bool, hipStream_t);
-template int launch_proj_sweep_jobs<float>(const FusedJob*, int, int, int, long, int, bool, hipStream_t);
+template int launch_proj_sweep_jobs<double>(const FusedJob*, int, int, const long*, int, long, int, bool, hipStream_t);
+template int launch_proj_sweep_jobs<float>(const FusedJob*, int, int, const long*, int, long, int, bool, hipStream_t);
 
 }  // namespace mdp
