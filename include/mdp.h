@@ -321,6 +321,28 @@ int mdp_reconstruct(mdp_ctx* ctx, int n_sub, const mdp_projector* const* P,
 int mdp_ap_solve(mdp_ctx* ctx, int n, double h, double k, int precision, int batch,
                  const mdp_c128* g, mdp_c128* u, void* stream);
 
+/* mdp_ap_solve without any device (or pinned host) allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and result as mdp_ap_solve (results
+ * agree to rounding: the batch may be cut into chunks of another size, and the
+ * sine GEMM always takes its default tile shape); the batch buffers live in a
+ * library-owned static device array of 64 MiB per device (held by every device
+ * the library runs on until the process ends) instead of the context's
+ * workspaces; a batch larger than the array holds is solved in consecutive
+ * chunks on `stream`.  Nothing in the array has to start at zero (each solve
+ * writes every element it reads).  The plan of (n, h, k) must exist on ctx
+ * already (an earlier mdp_ap_solve with the same n, h, k, e.g. with batch 0,
+ * creates it); per-launch profiling and autotuning do not apply to this call.
+ * All calls on one device share its array: calls that overlap in time on one
+ * device race (order them on one stream, or synchronise between them).
+ * Errors: MDP_ERR_ARG (no plan for (n, h, k), null pointers, one right-hand
+ * side needing more than the 64 MiB: 32 (n+1) W bytes in complex128, 16 (n+1) W
+ * in complex64, 24 (n+1) W refined, W the folded width of n, i.e. n/2 and
+ * n/2 - 1 each rounded up to a multiple of 64: n = 1024 fits in every precision,
+ * n = 2048 only in complex64), MDP_ERR_NONFINITE, MDP_ERR_HIP. */
+int mdp_ap_solve_noalloc(mdp_ctx* ctx, int n, double h, double k, int precision, int batch, const mdp_c128* g,
+                         mdp_c128* u, void* stream);
+
 /* Host helper (Sec. 3.3.1: phi expanded in the same basis): t[i] =
  * cos(pi (i + 1/2)/M*), i = 0..M*-1, the sample points of mdp_cheb_coeffs. */
 int mdp_cheb_points(int m_star, double* t);

@@ -11,6 +11,10 @@
 //   grids        complex interleaved FP64, (n+1)^2 per function, index m*(n+1)+q.
 #include <hip/hip_complex.h>
 
+#include <map>
+#include <mutex>
+
+#include "ap_solver.h"
 #include "mdp_internal.h"
 
 namespace mdp {
@@ -1235,5 +1239,29 @@ void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int 
 }
 template void launch_gather_q_fused_jobs<double>(const FusedJob*, int, int, int, hipStream_t);
 template void launch_gather_q_fused_jobs<float>(const FusedJob*, int, int, int, hipStream_t);
+
+// ------------------------------------------------------------------ allocation-free solves
+// The batch buffers of the allocation-free AP solve: a static device array, which every
+// device the library runs on holds until the process ends.  In host code the array's
+// name stands for a host-side shadow, not a device address: host code uses only the
+// address that hipGetSymbolAddress returns for the current device (kept per device).
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+}  // namespace
+
+void* noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));   // `device` is current
+    if (e != hipSuccess || !ptr)
+        throw Error(MDP_ERR_HIP, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return ptr;
+}
 
 }  // namespace mdp

@@ -190,60 +190,91 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
 
 // One batched solve: R right-hand sides from `src` (complex if src_cplx), result
 // handed to `consume(u, du)` as folded synthesis rows in T (u) plus, for the
-// refined precision, the FP32 correction (du).
+// refined precision, the FP32 correction (du).  A, B: batch buffers of
+// R * 2 * rows * W elements of T each; C (refined only): R * 2 * rows * W floats.
+// pr null: no per-launch profiling and no GEMM autotuning (nothing is allocated).
 template <class T>
-static void solve_batch_t(const APPlan& P, Workspace& ws, const SrcDesc& src, bool src_cplx, int R, bool refine,
-                          Band bd, const std::function<void(const void*, const float*, Band)>& consume,
-                          hipStream_t st) {
+static void solve_batch_bufs(const APPlan& P, T* A, T* B, float* C, Profiler* pr, const SrcDesc& src, bool src_cplx,
+                             int R, bool refine, Band bd,
+                             const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st) {
     const Fold& f = P.f;
     const int n = P.n;
-    if (refine) bd = Band{0, n + 1};   // the FP64 residual needs every row of the AP
     const size_t rows = (size_t)bd.nr;
-    const size_t elems = (size_t)R * 2 * rows * f.W;
-    ws.a.reserve(elems * sizeof(T));
-    ws.b.reserve(elems * sizeof(T));
-    T* A = ws.a.as<T>();
-    T* B = ws.b.as<T>();
     const int pin = src_cplx ? 2 : 1;
+    const bool tune = pr != nullptr;
     const T* Sf = (const T*)(sizeof(T) == 8 ? P.Sf64.p : P.Sf32.p);
     const T* Si = (const T*)(sizeof(T) == 8 ? P.Si64.p : P.Si32.p);
     const T* fac = (const T*)(sizeof(T) == 8 ? P.fac64.p : P.fac32.p);
     const T* colc = (const T*)(sizeof(T) == 8 ? P.colc64.p : P.colc32.p);
+    auto run = [&](const char* name, double flops, double bytes, auto&& f_) {
+        if (pr) pr->run(name, st, flops, bytes, f_);
+        else f_();
+    };
 
     // algorithmic work per launch: only the p + (p-1) = n-1 useful columns of a
     // folded row count, padding does not
-    Profiler& pr = ws.prof;
     const double useful = (double)(n - 1);
     const double gemm_row_flops = 2.0 * ((double)f.p * f.p + (double)(f.p - 1) * (f.p - 1));
     const double rows_in = (double)R * pin * rows, rows_c = (double)R * 2 * rows;
     const double tri_pts = (double)R * rows * useful;
-    pr.run("fold_rhs", st, 0.0, rows_in * useful * sizeof(T),
-           [&] { launch_fold_rhs<T>(src, n, f, P.sc, R, src_cplx, bd, A, st); });
-    pr.run(sizeof(T) == 8 ? "gemm_sine_f64" : "gemm_sine_f32", st, rows_in * gemm_row_flops,
-           2.0 * rows_in * useful * sizeof(T), [&] { launch_gemm_bd<T>(A, Sf, B, (long)R * pin * rows, f, st); });
-    pr.run(sizeof(T) == 8 ? "tridiag_f64" : "tridiag_f32", st, tri_pts * 22.0,
-           tri_pts * (pin + 2) * sizeof(T) + 4.0 * rows * useful * sizeof(T),
-           [&] { launch_tridiag<T>(B, pin, A, fac, colc, n, f, R, bd, st); });
-    pr.run(sizeof(T) == 8 ? "gemm_sine_f64" : "gemm_sine_f32", st, rows_c * gemm_row_flops,
-           2.0 * rows_c * useful * sizeof(T), [&] { launch_gemm_bd<T>(A, Si, B, (long)R * 2 * rows, f, st); });
+    run("fold_rhs", 0.0, rows_in * useful * sizeof(T), [&] { launch_fold_rhs<T>(src, n, f, P.sc, R, src_cplx, bd, A, st); });
+    run(sizeof(T) == 8 ? "gemm_sine_f64" : "gemm_sine_f32", rows_in * gemm_row_flops,
+        2.0 * rows_in * useful * sizeof(T), [&] { launch_gemm_bd<T>(A, Sf, B, (long)R * pin * rows, f, st, tune); });
+    run(sizeof(T) == 8 ? "tridiag_f64" : "tridiag_f32", tri_pts * 22.0,
+        tri_pts * (pin + 2) * sizeof(T) + 4.0 * rows * useful * sizeof(T),
+        [&] { launch_tridiag<T>(B, pin, A, fac, colc, n, f, R, bd, st); });
+    run(sizeof(T) == 8 ? "gemm_sine_f64" : "gemm_sine_f32", rows_c * gemm_row_flops,
+        2.0 * rows_c * useful * sizeof(T), [&] { launch_gemm_bd<T>(A, Si, B, (long)R * 2 * rows, f, st, tune); });
     const float* du = nullptr;
     if (refine) {
         // r = g - A u in FP64 (u = the FP32 solution in B), correction solved in FP32
-        ws.c.reserve(elems * sizeof(float));
-        float* Cb = ws.c.as<float>();
         float* Af = reinterpret_cast<float*>(A);
         const double tri_c = (double)R * rows * useful;
-        pr.run("residual", st, tri_c * 9.0 * 8.0, tri_c * 2.0 * 2.0 * sizeof(float),
-               [&] { launch_residual(src, n, f, P.sc, P.ec, R, src_cplx, reinterpret_cast<const float*>(B), Af, st); });
-        pr.run("gemm_sine_f32", st, rows_c * gemm_row_flops, 2.0 * rows_c * useful * sizeof(float),
-               [&] { launch_gemm_bd<float>(Af, P.Sf32.as<float>(), Cb, (long)R * 2 * rows, f, st); });
-        pr.run("tridiag_f32", st, tri_c * 22.0, tri_c * 4.0 * sizeof(float) + 4.0 * rows * useful * sizeof(float),
-               [&] { launch_tridiag<float>(Cb, 2, Af, P.fac32.as<float>(), P.colc32.as<float>(), n, f, R, bd, st); });
-        pr.run("gemm_sine_f32", st, rows_c * gemm_row_flops, 2.0 * rows_c * useful * sizeof(float),
-               [&] { launch_gemm_bd<float>(Af, P.Si32.as<float>(), Cb, (long)R * 2 * rows, f, st); });
-        du = Cb;
+        run("residual", tri_c * 9.0 * 8.0, tri_c * 2.0 * 2.0 * sizeof(float),
+            [&] { launch_residual(src, n, f, P.sc, P.ec, R, src_cplx, reinterpret_cast<const float*>(B), Af, st); });
+        run("gemm_sine_f32", rows_c * gemm_row_flops, 2.0 * rows_c * useful * sizeof(float),
+            [&] { launch_gemm_bd<float>(Af, P.Sf32.as<float>(), C, (long)R * 2 * rows, f, st, tune); });
+        run("tridiag_f32", tri_c * 22.0, tri_c * 4.0 * sizeof(float) + 4.0 * rows * useful * sizeof(float),
+            [&] { launch_tridiag<float>(C, 2, Af, P.fac32.as<float>(), P.colc32.as<float>(), n, f, R, bd, st); });
+        run("gemm_sine_f32", rows_c * gemm_row_flops, 2.0 * rows_c * useful * sizeof(float),
+            [&] { launch_gemm_bd<float>(Af, P.Si32.as<float>(), C, (long)R * 2 * rows, f, st, tune); });
+        du = C;
     }
     consume(B, du, bd);
+}
+
+template <class T>
+static void solve_batch_t(const APPlan& P, Workspace& ws, const SrcDesc& src, bool src_cplx, int R, bool refine,
+                          Band bd, const std::function<void(const void*, const float*, Band)>& consume,
+                          hipStream_t st) {
+    if (refine) bd = Band{0, P.n + 1};   // the FP64 residual needs every row of the AP
+    const size_t elems = (size_t)R * 2 * bd.nr * P.f.W;
+    ws.a.reserve(elems * sizeof(T));
+    ws.b.reserve(elems * sizeof(T));
+    if (refine) ws.c.reserve(elems * sizeof(float));
+    solve_batch_bufs<T>(P, ws.a.as<T>(), ws.b.as<T>(), refine ? ws.c.as<float>() : nullptr, &ws.prof, src, src_cplx, R,
+                        refine, bd, consume, st);
+}
+
+size_t solve_scratch_bytes(const APPlan& P, int precision, int R) {
+    const size_t elems = (size_t)R * 2 * (P.n + 1) * P.f.W;
+    if (precision == MDP_C128) return 2 * elems * sizeof(double);
+    return 2 * elems * sizeof(float) + (precision == MDP_C64_REFINED ? elems * sizeof(float) : 0);
+}
+
+void solve_batch_scratch(const APPlan& P, int precision, void* scratch, const SrcDesc& src, bool src_cplx, int R,
+                         const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st) {
+    if (R <= 0) return;
+    const Band all{0, P.n + 1};
+    const size_t elems = (size_t)R * 2 * (P.n + 1) * P.f.W;
+    if (precision == MDP_C128) {
+        double* A = static_cast<double*>(scratch);
+        solve_batch_bufs<double>(P, A, A + elems, nullptr, nullptr, src, src_cplx, R, false, all, consume, st);
+    } else {
+        float* A = static_cast<float*>(scratch);
+        solve_batch_bufs<float>(P, A, A + elems, precision == MDP_C64_REFINED ? A + 2 * elems : nullptr, nullptr, src,
+                                src_cplx, R, precision == MDP_C64_REFINED, all, consume, st);
+    }
 }
 
 int chunk_size(const APPlan& P, int precision, size_t cap_bytes, int R) {

@@ -89,4 +89,17 @@ int chunk_size(const APPlan& P, int precision, size_t cap_bytes, int R);
 void solve_batch(const APPlan& P, Workspace& ws, int precision, const SrcDesc& src, bool src_cplx, int R, Band bd,
                  const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st);
 
+// Bytes of batch buffers a full-grid solve of R right-hand sides needs (solve_batch_scratch).
+size_t solve_scratch_bytes(const APPlan& P, int precision, int R);
+// The full-grid solve of solve_batch with its batch buffers in `scratch` (at least
+// solve_scratch_bytes bytes, device): no workspace growth, no per-launch profiling, no
+// GEMM autotuning, so nothing is allocated.
+void solve_batch_scratch(const APPlan& P, int precision, void* scratch, const SrcDesc& src, bool src_cplx, int R,
+                         const std::function<void(const void*, const float*, Band)>& consume, hipStream_t st);
+
+// The library's static device scratch array of the allocation-free entry point: its
+// size, and its address on `device` (resolved once per device; set-up call).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+void* noalloc_scratch(int device);
+
 }  // namespace mdp

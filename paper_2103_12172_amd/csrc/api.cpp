@@ -147,6 +147,7 @@ struct mdp_ctx {
     // kinds and coefficients, M*, route); empty when none is valid
     std::vector<double> iface_key;
     IfaceCache icache;
+    void* scratch = nullptr;     // this device's static scratch array (mdp_ap_solve_noalloc)
     hipEvent_t last = nullptr;   // end of the previous call's work (workspaces are shared)
     hipStream_t last_stream = nullptr;
     bool have_last = false;
@@ -553,6 +554,14 @@ int mdp_create(mdp_ctx** out, int device) {
     if (e != hipSuccess) {
         delete ctx;
         return fail(nullptr, MDP_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+    // the device address of the static scratch array of mdp_ap_solve_noalloc (with the device current)
+    try {
+        ctx->scratch = noalloc_scratch(device);
+    } catch (const Error& err) {
+        (void)hipEventDestroy(ctx->last);
+        delete ctx;
+        return fail(nullptr, err.code, err.what());
     }
     *out = ctx;
     return MDP_OK;
@@ -1947,6 +1956,55 @@ int mdp_ap_solve(mdp_ctx* ctx, int n, double h, double k, int precision, int bat
                                                           npts, nullptr, st);
                         },
                         st);
+        }
+        return MDP_OK;
+    });
+}
+
+// ---------------------------------------------------------------------------- G^(h) without allocation
+int mdp_ap_solve_noalloc(mdp_ctx* ctx, int n, double h, double k, int precision, int batch, const mdp_c128* g,
+                         mdp_c128* u, void* stream) {
+    if (!ctx) return fail(nullptr, MDP_ERR_ARG, "ctx is NULL");
+    return guarded(ctx, [&]() -> int {
+        if (batch < 0 || (batch > 0 && (!g || !u))) throw Error(MDP_ERR_ARG, "null grid pointers");
+        if (!std::isfinite(k) || !(k > 0)) throw Error(MDP_ERR_NONFINITE, "k must be finite and > 0");
+        check_precision(precision);
+        if (!ctx->scratch) throw Error(MDP_ERR_HIP, "the scratch array of this device was not resolved");
+        // the plan must exist already: creating one allocates its device tables
+        auto it = ctx->plans.find(PlanKey{n, h, k});
+        if (it == ctx->plans.end())
+            throw Error(MDP_ERR_ARG, "no plan for this (n, h, k) on the context: call mdp_ap_solve with the same "
+                                     "n, h and k first (a batch of 0 creates it)");
+        const APPlan& plan = *it->second;
+        if (batch == 0) return MDP_OK;
+        const size_t one = solve_scratch_bytes(plan, precision, 1);
+        if (one > kNoAllocScratchBytes)
+            throw Error(MDP_ERR_ARG, "n = " + std::to_string(n) + " needs " + std::to_string(one) +
+                                         " bytes of scratch per right-hand side in this precision, more than the " +
+                                         std::to_string(kNoAllocScratchBytes) + " bytes of the allocation-free solve");
+        const int chunk = (int)std::min<size_t>((size_t)batch, kNoAllocScratchBytes / one);
+        hipStream_t st = (hipStream_t)stream;
+        const long npts = (long)(n + 1) * (n + 1);
+        CallScope scope(ctx, st);
+        for (int b0 = 0; b0 < batch; b0 += chunk) {   // chunks reuse the scratch in stream order
+            const int R = std::min(chunk, batch - b0);
+            SrcDesc src{};
+            src.kind = Src::GRID;
+            src.grid = reinterpret_cast<const double*>(g) + 2 * (size_t)b0 * npts;
+            src.grid_stride = npts;
+            double* out = reinterpret_cast<double*>(u) + 2 * (size_t)b0 * npts;
+            const Fold f = plan.f;
+            const Band all{0, n + 1};
+            solve_batch_scratch(plan, precision, ctx->scratch, src, true, R,
+                                [&](const void* uu, const float* du, Band bd) {
+                                    if (precision == MDP_C128)
+                                        launch_unfold_grid<double>((const double*)uu, du, n, f, bd, all, R, nullptr, 0,
+                                                                   out, npts, nullptr, st);
+                                    else
+                                        launch_unfold_grid<float>((const float*)uu, du, n, f, bd, all, R, nullptr, 0,
+                                                                  out, npts, nullptr, st);
+                                },
+                                st);
         }
         return MDP_OK;
     });

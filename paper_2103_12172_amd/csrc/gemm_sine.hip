@@ -256,17 +256,18 @@ int tuned_shape(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t
 void set_gemm_autotune(int on) { g_autotune.store(on ? 1 : 0); }
 
 template <class T>
-void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st) {
+void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st, bool may_tune) {
     if (M <= 0) return;
     // 128 x 128 tiles when they give enough workgroups to fill the chip (256 CUs), 64 x 64 otherwise
     // (short batches: a few thousand rows)
     const long big = ((M + 127) / 128) * (f.W / 128);
     const bool wide = f.P1 % 128 == 0 && f.P2 % 128 == 0;
     const int shape = (wide && big >= 512) ? 0 : (wide && big >= 256) ? 1 : 2;
-    launch_shape<T>(g_autotune.load() ? tuned_shape<T>(A, B, C, M, f, st, shape) : shape, A, B, C, M, f, st);
+    launch_shape<T>(may_tune && g_autotune.load() ? tuned_shape<T>(A, B, C, M, f, st, shape) : shape, A, B, C, M, f,
+                    st);
 }
 
-template void launch_gemm_bd<double>(const double*, const double*, double*, long, const Fold&, hipStream_t);
-template void launch_gemm_bd<float>(const float*, const float*, float*, long, const Fold&, hipStream_t);
+template void launch_gemm_bd<double>(const double*, const double*, double*, long, const Fold&, hipStream_t, bool);
+template void launch_gemm_bd<float>(const float*, const float*, float*, long, const Fold&, hipStream_t, bool);
 
 }  // namespace mdp

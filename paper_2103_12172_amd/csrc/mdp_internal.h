@@ -304,8 +304,9 @@ struct Band {
 template <class T>
 void launch_fold_rhs(const SrcDesc& s, int n, const Fold& f, StencilCoef sc, int R, bool cplx, Band bd, T* out,
                      hipStream_t st);
+// may_tune = false: the default tile shape (the autotuner creates HIP events at first use)
 template <class T>
-void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st);
+void launch_gemm_bd(const T* A, const T* B, T* C, long M, const Fold& f, hipStream_t st, bool may_tune = true);
 // process-wide: pick the sine GEMM's tile shape per (precision, n, rows) by timing at first use
 void set_gemm_autotune(int on);
 // fac: planes l.re, l.im, r.re, r.im, tw.re, tw.im, each (n+1) x W

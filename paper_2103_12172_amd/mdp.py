@@ -28,7 +28,8 @@ EXPORTED = ["mdp_create", "mdp_destroy", "mdp_last_error", "mdp_build_projector"
             "mdp_projector_release", "mdp_solve_interface", "mdp_reconstruct", "mdp_ap_solve", "mdp_cheb_points",
             "mdp_cheb_coeffs", "mdp_version", "mdp_cache_clear", "mdp_profile_enable", "mdp_profile_report",
             "mdp_set_projector_path", "mdp_set_interface_path", "mdp_profile_select", "mdp_projector_gamma_feet", "mdp_ap_grid",
-            "mdp_dd_gradient", "mdp_set_autotune", "mdp_set_fused_schedule", "mdp_fused_schedule_used"]
+            "mdp_dd_gradient", "mdp_set_autotune", "mdp_set_fused_schedule", "mdp_fused_schedule_used",
+            "mdp_ap_solve_noalloc"]
 MDP_PATH_AUTO, MDP_PATH_DENSE = 0, 1
 PROJECTOR_PATHS = {"auto": MDP_PATH_AUTO, "dense": MDP_PATH_DENSE}
 INTERFACE_PATHS = {"auto": 0, "dense": 1, "multifrontal": 2}
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mdp_reconstruct.restype = ip
     lib.mdp_ap_solve.argtypes = [vp, ip, dp, dp, ip, ip, vp, vp, vp]
     lib.mdp_ap_solve.restype = ip
+    lib.mdp_ap_solve_noalloc.argtypes = [vp, ip, dp, dp, ip, ip, vp, vp, vp]
+    lib.mdp_ap_solve_noalloc.restype = ip
     lib.mdp_cheb_points.argtypes = [ip, ctypes.POINTER(dp)]
     lib.mdp_cheb_points.restype = ip
     lib.mdp_cheb_coeffs.argtypes = [ip, ctypes.POINTER(C128), ctypes.POINTER(C128)]
@@ -336,6 +339,16 @@ def mdp_ap_solve(ctx: Context, n: int, h: float, k: float, precision, g, u, stre
     batch = g.numel() // ((n + 1) * (n + 1))
     ctx.check(ctx.lib.mdp_ap_solve(ctx.handle, n, float(h), float(k), prec, batch, ctypes.c_void_p(g.data_ptr()),
                                    ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def mdp_ap_solve_noalloc(ctx: Context, n: int, h: float, k: float, precision, g, u, stream=None):
+    """mdp_ap_solve with the batch buffers in the library's static device scratch array (allocates
+    nothing; the plan of (n, h, k) must exist: an earlier mdp_ap_solve with those values creates it)."""
+    prec = PRECISIONS.get(precision, precision)
+    batch = g.numel() // ((n + 1) * (n + 1))
+    ctx.check(ctx.lib.mdp_ap_solve_noalloc(ctx.handle, n, float(h), float(k), prec, batch,
+                                           ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                           ctypes.c_void_p(_stream_ptr(stream))))
 
 
 def mdp_cheb_points(m_star: int) -> np.ndarray:
