@@ -1007,49 +1007,88 @@ __device__ inline int find_job(const FusedJob* __restrict__ jobs, int njobs, int
     return lo;
 }
 
-// Grid: nbx workgroups per column, flattened (column-major) into blockIdx.x.
+// One workgroup per column.  The column's density w = E(:, col) (nonzero on gamma only)
+// is spread once into LDS: the full rows m_lo-1 .. m_lo+2 and m_hi-2 .. m_hi+1 (D: the
+// neighbourhoods of the special rows) and, for every row, its values at q_lo-1, q_lo,
+// q_hi, q_hi+1 (S: on the other rows gamma holds only those four nodes), from the
+// gamma lists (coalesced reads of E, gm, gq).  The stencil L^(h) w at an M+ node then
+// reads its nine taps from LDS, in the same order as the general right-hand side.
+// LDS: 12 (n+1) doubles.
 template <class T>
 __global__ void __launch_bounds__(256)
-fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs, int nbx) {
-    const int gcol = blockIdx.x / nbx, bx = blockIdx.x - gcol * nbx;
+fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs) {
+    extern __shared__ double lds_fr[];
+    const int gcol = blockIdx.x;
     const FusedJob& J = jobs[find_job(jobs, njobs, gcol)];
     const Fold f = J.f;
     const RingGeom rg{J.src.m_lo, J.src.m_hi, J.src.q_lo, J.src.q_hi};
-    const SrcEval ev{J.src, f.n, J.sc};
     T* __restrict__ gc = reinterpret_cast<T*>(J.gc);
     T* __restrict__ spec = reinterpret_cast<T*>(J.spec);
-    const int n = f.n, p = f.p, W = f.W, b = gcol - J.b0;
-    const int t = bx * blockDim.x + threadIdx.x;
-    if (t <= n) {
-        const int m = t;
+    const int n = f.n, n1 = n + 1, p = f.p, W = f.W, b = gcol - J.b0;
+    const int m_lo = rg.m_lo, m_hi = rg.m_hi, q_lo = rg.q_lo, q_hi = rg.q_hi;
+    double* D = lds_fr;          // [8][n+1]
+    double* S = D + 8 * n1;      // [n+1][4]
+    for (int e = threadIdx.x; e < 12 * n1; e += 256) lds_fr[e] = 0.0;
+    __syncthreads();
+    const double* __restrict__ w = J.src.E + (long)(J.src.col0 + b) * J.src.ldE;
+    const int* __restrict__ gm = J.gm;
+    const int* __restrict__ gq = J.gq;
+    auto strip_col = [&](int q) { return (q == q_lo - 1) ? 0 : (q == q_lo) ? 1 : (q == q_hi) ? 2 : (q == q_hi + 1) ? 3 : -1; };
+    for (int i = threadIdx.x; i < J.ng; i += 256) {
+        const int m = gm[i], q = gq[i];
+        const double v = w[i];
+        const int r0 = m - (m_lo - 1), r1 = m - (m_hi - 2);
+        if (r0 >= 0 && r0 < 4) D[r0 * n1 + q] = v;
+        if (r1 >= 0 && r1 < 4) D[(4 + r1) * n1 + q] = v;
+        const int k = strip_col(q);
+        if (k >= 0) S[m * 4 + k] = v;
+    }
+    __syncthreads();
+    auto wv = [&](int m, int q) -> double {
+        const int r0 = m - (m_lo - 1), r1 = m - (m_hi - 2);
+        if (r0 >= 0 && r0 < 4) return D[r0 * n1 + q];
+        if (r1 >= 0 && r1 < 4) return D[(4 + r1) * n1 + q];
+        const int k = strip_col(q);
+        return k >= 0 ? S[m * 4 + k] : 0.0;
+    };
+    const StencilCoef sc = J.sc;
+    // L^(h) w at node (m, q), zero off M+ (eq. FD_scheme restricted to M+)
+    auto rhs = [&](int m, int q) -> double {
+        if (m < m_lo || m > m_hi || q < q_lo || q > q_hi) return 0.0;
+        const double ce = wv(m + 1, q) + wv(m - 1, q) + wv(m, q + 1) + wv(m, q - 1);
+        const double cc = wv(m + 1, q + 1) + wv(m - 1, q + 1) + wv(m + 1, q - 1) + wv(m - 1, q - 1);
+        return sc.c0 * wv(m, q) + sc.ce * ce + sc.cc * cc;
+    };
+    // ring table of the swept rows m_lo-1 .. m_hi+1 (zero on the special rows and outside the box)
+    for (int m = m_lo - 1 + (int)threadIdx.x; m <= m_hi + 1; m += 256) {
         double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-        if (m >= rg.m_lo && m <= rg.m_hi && special_in(rg, m) < 0) {
-            v0 = ev.rhs(b, m, rg.q_lo).re;
-            v1 = ev.rhs(b, m, rg.q_lo + 1).re;
-            v2 = ev.rhs(b, m, rg.q_hi - 1).re;
-            v3 = ev.rhs(b, m, rg.q_hi).re;
+        if (m >= m_lo && m <= m_hi && special_in(rg, m) < 0) {
+            v0 = rhs(m, q_lo);
+            v1 = rhs(m, q_lo + 1);
+            v2 = rhs(m, q_hi - 1);
+            v3 = rhs(m, q_hi);
         }
-        T* o = gc + ((long)b * (n + 1) + m) * 4;
+        T* o = gc + ((long)b * n1 + m) * 4;
         o[0] = (T)(v0 + v3);
         o[1] = (T)(v1 + v2);
         o[2] = (T)(v0 - v3);
         o[3] = (T)(v1 - v2);
-        return;
     }
-    const int i = t - (n + 1);
-    if (i >= 4 * W) return;
-    const int s = i / W, c = i - s * W;
-    const int m = (s == 0) ? rg.m_lo : (s == 1) ? rg.m_lo + 1 : (s == 2) ? rg.m_hi - 1 : rg.m_hi;
-    double v = 0.0;
-    if (c < f.P1) {
-        const int q = c + 1;
-        if (q < p) v = ev.rhs(b, m, q).re + ev.rhs(b, m, n - q).re;
-        else if (q == p) v = ev.rhs(b, m, p).re;
-    } else {
-        const int q = c - f.P1 + 1;
-        if (q < p) v = ev.rhs(b, m, q).re - ev.rhs(b, m, n - q).re;
+    // folded special input rows
+    for (int i = threadIdx.x; i < 4 * W; i += 256) {
+        const int s_ = i / W, c = i - s_ * W;
+        const int m = (s_ == 0) ? m_lo : (s_ == 1) ? m_lo + 1 : (s_ == 2) ? m_hi - 1 : m_hi;
+        double v = 0.0;
+        if (c < f.P1) {
+            const int q = c + 1;
+            if (q < p) v = rhs(m, q) + rhs(m, n - q);
+            else if (q == p) v = rhs(m, p);
+        } else {
+            const int q = c - f.P1 + 1;
+            if (q < p) v = rhs(m, q) - rhs(m, n - q);
+        }
+        spec[((long)b * 4 + s_) * W + c] = (T)v;
     }
-    spec[((long)b * 4 + s) * W + c] = (T)v;
 }
 
 // Q(i, col0+b) = -u(m_i, q_i): the full gamma rows from the synthesis rows us
@@ -1177,7 +1216,7 @@ void launch_geom_setup(const GeomJob* jobs_dev, int count, int max_nodes, hipStr
 
 bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi) {
     return q_hi == f.n - q_lo && q_lo >= 2 && q_lo <= f.p - 2 && m_lo >= 2 && m_hi <= f.n - 2 && m_hi - m_lo >= 3 &&
-           f.W % 64 == 0 && f.P1 % 64 == 0;
+           f.W % 64 == 0 && f.P1 % 64 == 0 && fold_ring_lds_bytes(f.n) <= kFoldRingMaxLds;
 }
 
 int fused_segments(int m_lo, int m_hi) { return (m_hi - m_lo + 3 + FUSED_K - 1) / FUSED_K; }
@@ -1221,10 +1260,17 @@ static dim3 flat_grid(int per_col, int total) {
 }
 
 template <class T>
-void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_items, hipStream_t st) {
+void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_n, hipStream_t st) {
     if (njobs <= 0 || total <= 0) return;
-    const int nbx = (max_items + 255) / 256;
-    hipLaunchKernelGGL(fold_ring_kernel<T>, flat_grid(nbx, total), dim3(256), 0, st, jobs, njobs, nbx);
+    const size_t lds = fold_ring_lds_bytes(max_n);
+    if (lds > kFoldRingMaxLds) throw Error(MDP_ERR_ARG, "grid too large for the fused projector route");
+    static const bool lds_set = [] {   // more than 64 KB of dynamic LDS must be allowed explicitly
+        MDP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fold_ring_kernel<T>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFoldRingMaxLds));
+        return true;
+    }();
+    (void)lds_set;
+    hipLaunchKernelGGL(fold_ring_kernel<T>, flat_grid(1, total), dim3(256), lds, st, jobs, njobs);
     MDP_HIP(hipGetLastError());
 }
 template void launch_fold_ring_jobs<double>(const FusedJob*, int, int, int, hipStream_t);

@@ -358,7 +358,7 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
         auto dp = [](T* p) { return reinterpret_cast<double*>(p); };
         auto cdp = [](const void* p) { return reinterpret_cast<const double*>(p); };
         std::vector<FusedJob> jobs(jh.size());
-        int b0 = 0, max_items = 0, max_w = 0, max_ng = 0;
+        int b0 = 0, max_n = 0, max_w = 0, max_ng = 0;
         long groups[3] = {0, 0, 0};
         long waves_one_col = 0;
         double fold_bytes = 0.0, sweep_flops = 0.0, sweep_bytes = 0.0, gather_bytes = 0.0;
@@ -407,7 +407,7 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
             J.gm = itm.P->gm;
             J.gq = itm.P->gq;
             b0 += R;
-            max_items = std::max(max_items, n + 1 + 4 * f.W);
+            max_n = std::max(max_n, n);
             max_w = std::max(max_w, f.W);
             max_ng = std::max(max_ng, ng);
             waves_one_col += (long)R * (f.W / 64);
@@ -448,7 +448,7 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
             }
         };
         const int L = ctx->sweep_cols > 0 ? ctx->sweep_cols : sweep_lanes_cols(f64, waves_one_col);
-        pr.run("fold_ring", st, 0.0, fold_bytes, [&] { launch_fold_ring_jobs<T>(dj, nj, total, max_items, st); });
+        pr.run("fold_ring", st, 0.0, fold_bytes, [&] { launch_fold_ring_jobs<T>(dj, nj, total, max_n, st); });
         gemms(true);
         pr.run(f64 ? "ap_fused_f64" : "ap_fused_f32", st, sweep_flops, sweep_bytes, [&] {
             ctx->last_sweep_cols =

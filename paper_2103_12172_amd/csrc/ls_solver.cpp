@@ -487,7 +487,7 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
     int max_m = 0, tiles = 0;
     for (int i = 0; i < n_sub; ++i) {
         max_m = std::max(max_m, h.m[i]);
-        tiles += ((h.s[i] + 31) / 32) * ((h.s[i] + 31) / 32);
+        tiles += ((h.s[i] + kGramTile - 1) / kGramTile) * ((h.s[i] + kGramTile - 1) / kGramTile);
     }
     const int nsplit = std::max(1, std::min(std::min(2048 / std::max(tiles, 1), std::max(1, max_m / 128)), 64));
     std::vector<ZBatch> zb(n_sub);
@@ -716,10 +716,14 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     };
     PackedFlags hf{};
     PackedFlags* hpin = static_cast<PackedFlags*>(lw.hflags.get(sizeof(PackedFlags)));
+    const bool verbose = std::getenv("MDP_VERBOSE") != nullptr;
     auto read_flags = [&]() {
         MDP_HIP(hipMemcpyAsync(hpin, fl, sizeof(PackedFlags), hipMemcpyDeviceToHost, st));
         MDP_HIP(hipStreamSynchronize(st));
         hf = *hpin;
+        if (verbose)
+            std::fprintf(stderr, "mdp: least squares after %d normal solves: |dx|/|x| %.3e, residual %.3e\n", n_solves,
+                         std::sqrt(hf.dx2 / (hf.x2 > 0 ? hf.x2 : 1.0)), std::sqrt(hf.r2 / (hf.f2 > 0 ? hf.f2 : 1.0)));
         if (hf.badcol & 2) throw Error(MDP_ERR_NONFINITE, "non-finite entry in the interface matrix");
         if (hf.badcol & 1) throw Error(MDP_ERR_SINGULAR, "zero column in the interface matrix");
     };

@@ -392,8 +392,13 @@ struct FusedJob {
 };
 // jobs: device table sorted by b0; total = sum of R; max_*: largest per-job extents; T the
 // storage and arithmetic type of the build (double or float)
+// the ring tables and special rows of every column (one workgroup per column; max_n the largest n)
 template <class T>
-void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_items, hipStream_t st);
+void launch_fold_ring_jobs(const FusedJob* jobs, int njobs, int total, int max_n, hipStream_t st);
+// LDS of the fold of one column of a grid with n cells (its density spread over 12 (n+1) doubles),
+// and the most a workgroup may take (the fused route needs n up to about 1700)
+inline size_t fold_ring_lds_bytes(int n) { return (size_t)12 * (n + 1) * sizeof(double); }
+constexpr size_t kFoldRingMaxLds = 160 * 1024;
 // the fused sweep, lanes_cols (1, 2 or 4) mode columns per lane (or, with may_tune and the sweep
 // autotuner on, the fastest of the three for this kind of batch), max_w the widest job's W,
 // waves_one_col the batch's wavefront count at one column per lane; returns the columns per lane
@@ -512,6 +517,8 @@ void launch_packed_ahx(const PackedDevice& d, int total_pc, const double2* Ap, c
                        double2* y, hipStream_t st);
 void launch_packed_ax(const PackedDevice& d, int n_sub, int max_m, int max_s, const double2* Ap, const double2* x,
                       double2 alpha, double2* r, hipStream_t st);
+// workgroup tile of the batched Gram products
+constexpr int kGramTile = 32;
 // One batch entry of the Gram products A_b^* A_b (A_b: k x n, column-major, ld k):
 // its split-K partials start at P + poff, its column map at gcol + gcol_off.
 struct ZBatch {
