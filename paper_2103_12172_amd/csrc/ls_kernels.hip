@@ -1,11 +1,15 @@
 // Kernels of the interface least-squares solve (complex FP64).
 //
-// The reduced system Qbar c = Fbar (paper Sec. 3.3.3-3.5) is tall and skinny
-// (sum |gamma_i| rows, 4 N M* columns).  It is factored as Qbar = Q R by
-// Cholesky-QR passes whose work is almost entirely complex GEMM on the FP64
-// matrix cores: Gram matrices, triangular inverses and the products with them.
-// Kernels here: a general complex GEMM (op N / conjugate-transpose, split-K),
-// the Cholesky + inverse of one diagonal block, and small assembly kernels.
+// The reduced system Qbar c = Fbar (Sec. 3.3.3-3.5) is tall and skinny (sum |gamma_i|
+// rows, 4 N M* columns).  It is solved by the corrected semi-normal equations: the
+// Gram matrix G = Qbar^* Qbar of the column-equilibrated packed blocks (split-K
+// complex GEMM on the FP64 matrix cores), its Cholesky factor L together with
+// L^{-1} (dense for one matrix, multifrontal over the subdomains' elimination tree
+// for many: batched panel and update launches per 64 columns), and normal solves
+// G dx = Qbar^* r with the explicit inverses, refined on the residual of the
+// packed blocks.  Kernels here: the complex GEMM and Gram batch, the blocked
+// Cholesky-with-inverse steps, the multifrontal assembly and substitutions, and the
+// packed-block products (A x, A^* y, column norms, scaling).
 #include "mdp_internal.h"
 
 namespace mdp {
