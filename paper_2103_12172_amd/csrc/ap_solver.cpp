@@ -172,19 +172,22 @@ APPlan::APPlan(int n_, double h_, double k_) : n(n_), h(h_), k(k_) {
     upload<double>(fac64, fac);
     upload<float>(fac32, fac);
     upload<double>(colc64, colc);
-    std::vector<double> lf(2 * plane), rf(2 * plane);
-    for (size_t e = 0; e < plane; ++e) {
-        lf[2 * e] = fac[e];
-        lf[2 * e + 1] = fac[plane + e];
-        rf[2 * e] = fac[2 * plane + e];
-        rf[2 * e + 1] = fac[3 * plane + e];
-    }
-    upload<double>(lf64, lf);
+    // the fused sweep's tables, in the unknowns scaled by the interior off-diagonal a of the
+    // mode (q_m = a p_m, x~_m = a x_m): a r_m on every row and a tw_m, interleaved complex
+    std::vector<double> rf(2 * plane), tf(2 * plane);
+    for (int m = 0; m <= n; ++m)
+        for (int c = 0; c < W; ++c) {
+            const size_t e = (size_t)m * W + c;
+            const double a = colc[c];
+            rf[2 * e] = a * fac[2 * plane + e];
+            rf[2 * e + 1] = a * fac[3 * plane + e];
+            tf[2 * e] = a * tw[2 * e];
+            tf[2 * e + 1] = a * tw[2 * e + 1];
+        }
     upload<double>(rf64, rf);
-    upload<double>(tf64, tw);
-    upload<float>(lf32, lf);
+    upload<double>(tf64, tf);
     upload<float>(rf32, rf);
-    upload<float>(tf32, tw);
+    upload<float>(tf32, tf);
     upload<float>(colc32, colc);
 }
 

@@ -20,9 +20,10 @@ struct APPlan {
     double min_pivot_ratio;  // smallest |pivot| / row scale over all modes (host check)
     DevBuf Sf64, Si64, Sf32, Si32;     // block-diagonal sine matrices (W x W)
     DevBuf fac64, fac32, colc64, colc32;  // tridiagonal LU factors per mode
-    DevBuf lf64, rf64;    // the same l_m and r_m as interleaved complex [(n+1)][W] (fused projector sweep)
-    DevBuf tf64;          // twisted pivots tw_m [(n+1)][W] (sweep stopped at row m, zero right-hand side below)
-    DevBuf lf32, rf32, tf32;   // FP32 copies of lf64, rf64, tf64
+    // fused projector sweep, interleaved complex [(n+1)][W], scaled by the mode's off-diagonal a:
+    DevBuf rf64;          // a r_m (r_m = 1/d'_m)
+    DevBuf tf64;          // a tw_m (twisted pivots: sweep stopped at row m, zero right-hand side below)
+    DevBuf rf32, tf32;    // FP32 copies of rf64, tf64
     std::vector<double> twist_ratio;   // per row m: smallest |1/tw_m| / row scale over all modes
     APPlan(int n, double h, double k);
 };

@@ -283,12 +283,12 @@ struct FusedItem {
     mdp_projector* P;
 };
 
-// Mode columns per lane of the fused sweep when none is set: complex64 takes two
-// (independent recurrences side by side, half the cross-lane reduction per column; its
-// registers still allow four wavefronts per SIMD) when that leaves about four wavefronts
-// per SIMD of the chip; complex128 takes one (two columns need about 200 VGPRs, i.e. two
-// wavefronts per SIMD, and measure slower); or what the autotuner measured fastest.
-int sweep_lanes_cols(bool f64, long waves_one_col) { return (!f64 && waves_one_col >= 2L * 4096) ? 2 : 1; }
+// Mode columns per lane of the fused sweep when none is set: two (independent recurrences
+// side by side, half the cross-lane reduction per column; 150 VGPRs in FP64, three
+// wavefronts per SIMD) when the batch still gives about two wavefronts per SIMD of the
+// chip at two columns per lane, else one (small batches: more wavefronts hide more
+// latency); or what the autotuner measured fastest.
+int sweep_lanes_cols(long waves_one_col) { return waves_one_col >= 2L * 4096 ? 2 : 1; }
 
 // Q of every item by the support-in / gamma-out route, T the arithmetic of the build
 // (double for complex128, float for complex64), the columns of all items through each
@@ -392,7 +392,6 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
             }
             J.Sf = cdp(f64 ? plan.Sf64.p : plan.Sf32.p);
             J.Si = cdp(f64 ? plan.Si64.p : plan.Si32.p);
-            J.lf = cdp(f64 ? plan.lf64.p : plan.lf32.p);
             J.rf = cdp(f64 ? plan.rf64.p : plan.rf32.p);
             J.tf = cdp(f64 ? plan.tf64.p : plan.tf32.p);
             J.colc = cdp(f64 ? plan.colc64.p : plan.colc32.p);
@@ -447,7 +446,7 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
                 q0 = q1;
             }
         };
-        const int L = ctx->sweep_cols > 0 ? ctx->sweep_cols : sweep_lanes_cols(f64, waves_one_col);
+        const int L = ctx->sweep_cols > 0 ? ctx->sweep_cols : sweep_lanes_cols(waves_one_col);
         pr.run("fold_ring", st, 0.0, fold_bytes, [&] { launch_fold_ring_jobs<T>(dj, nj, total, max_n, st); });
         gemms(true);
         pr.run(f64 ? "ap_fused_f64" : "ap_fused_f32", st, sweep_flops, sweep_bytes, [&] {

@@ -373,8 +373,8 @@ constexpr int FUSED_K = 8;   // rows per recomputed segment of the fused tridiag
 // Buffers are the job's own (column 0 of the job at the pointer); jobs of one
 // n hold consecutive spec / spec_hat / xs / us ranges so that one sine GEMM per
 // n covers them.  Layouts: gc [R][n+1][4] ring table, spec / spec_hat [R][4][W]
-// folded special rows, lf / rf / tf [(n+1)][W] interleaved complex Thomas factors
-// l_m, r_m = 1/d_m and twisted pivots, ckpt [R][nseg][2][W], xs / us
+// folded special rows, rf / tf [(n+1)][W] interleaved complex a r_m (r_m = 1/d'_m) and
+// a tw_m (twisted pivots), a the mode's off-diagonal, ckpt [R][nseg][2][W], xs / us
 // [R][2][4][W], thin [R][W/64][rows_pad][4].  The buffers and the plan tables
 // hold elements of the build's arithmetic type (double, or float for complex64):
 // the pointers are typed double* and reinterpreted by the kernels.  Sf, Si are the
@@ -386,7 +386,7 @@ struct FusedJob {
     int nseg, rows_pad, ng, ldq;
     int b0, R;
     int g0[3];   // first group of 1, 2, 4 consecutive columns (groups never span two jobs)
-    const double *Sf, *Si, *lf, *rf, *tf, *colc;
+    const double *Sf, *Si, *rf, *tf, *colc;
     double *gc, *spec, *spec_hat, *ckpt, *xs, *thin, *us, *Q;
     const int *gm, *gq;
 };

@@ -13,27 +13,33 @@
 // discrete_AP diagonalised by the sine transform), solved over the rows
 // m0 = m_lo - 1 .. t = m_hi + 1 only: above the box the right-hand side and so
 // the forward-eliminated y vanish, below it the rows are eliminated in advance
-// (twisted pivot tw_t).  With the LU factors l_m, r_m = 1/d'_m and the real
-// off-diagonal a of interior rows:
-//   y_m = ghat_m - l_m y_{m-1},   x_t = tw_t y_t,   x_m = r_m (y_m - a x_{m+1}).
+// (twisted pivot tw_t).  With the LU factors r_m = 1/d'_m, the twisted pivot
+// and the real interior off-diagonal a of the mode, the sweep runs in the
+// unknowns scaled by a (q_m = a r_m y_m, x~_m = a x_m), so that one complex factor
+// per row, ar_m = a r_m (a tw_t at row t), serves both directions:
+//   q_m = ar_m (ghat_m - q_{m-1}),   x~_t = q_t,   x~_m = q_m - ar_m x~_{m+1},
+// and x = x~ / a where x itself is needed.
 // Q needs the solution on gamma only (eq. def_Pgamma): the full gamma rows m0,
 // m0+1, t-1, t (x kept per mode, synthesised by a small inverse GEMM) and, on
 // every row, u at q_lo-1, q_lo and their mirrors, i.e. the synthesis sums
 //   sum_c x_m(c) S(c, q_lo-2 + base) and sum_c x_m(c) S(c, q_lo-1 + base)
-// (real and imaginary parts: four values per row and parity block).
+// (real and imaginary parts: four values per row and parity block), formed as
+// x~ times the synthesis weights over a.
 //
 // Schedule: one wavefront per (64 L consecutive folded mode columns, column b);
 // lane i sweeps the L columns c0 = wave base + i L .. c0 + L - 1 side by side
 // (independent recurrences for latency, one row of factors per load), so each
 // 64-column block of the fold (one parity) is a group of 64/L lanes.  The
-// forward elimination keeps y only at the end of every K-row segment
-// (checkpoints in HBM); the back substitution recomputes a segment's y from the
+// forward elimination keeps q only at the end of every K-row segment
+// (checkpoints in HBM); the back substitution recomputes a segment's q from the
 // checkpoint before it, walks back through it, and adds each row's four
 // synthesis products over the lane's L columns; the group then reduces the 4 K
 // sums of the segment across its lanes (a reduce-scatter: permlane swaps for
 // the lane bits 32 and 16, DPP row permutations below) and writes them.
 // Segments holding no special row (all but the first and the last one or two)
-// take a path without the special-row tests.
+// take a path without the special-row tests.  A special input row adds ar_m
+// spec_hat_m to q_m after the ring step (the same sum, and no registers held for
+// it across the step).
 #include <atomic>
 #include <map>
 #include <mutex>
@@ -231,7 +237,7 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
     const int W = J.f.W, P1 = J.f.P1;
     const int wbase = wblk * 64 * L;
     if (wbase >= W) return;   // a job narrower than the launch (uniform over the workgroup)
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int bfirst = (grp - J.g0[lg_nw]) * NW;     // the group's first column (job-local)
     const bool has_col = bfirst + wave < J.R;
     const int b = min(bfirst + wave, J.R - 1);
@@ -260,17 +266,18 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
     const int blk = (wbase >> 6) + lane / (64 / L);   // this lane group's 64-column block
     T* __restrict__ th = reinterpret_cast<T*>(J.thin) + ((long)b * (W >> 6) + blk) * ((long)nseg * K) * 4;
 
-    // per-column constants: the transform of the two ring entries, the synthesis at
-    // q_lo-1 and q_lo, the interior off-diagonal
-    T s1[L], s2[L], t1[L], t2[L], a[L];
+    // per-column constants: the transform of the two ring entries, the synthesis weights at
+    // q_lo-1 and q_lo over the interior off-diagonal a, and 1/a (zero on padding columns)
+    T s1[L], s2[L], t1[L], t2[L], ai[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         const int c = cc + l;
+        const T a = colc[c];
+        ai[l] = a != T(0) ? T(1) / a : T(0);
         s1[l] = Sf[(long)(base + q_lo - 1) * LW + c];
         s2[l] = Sf[(long)(base + q_lo) * LW + c];
-        t1[l] = live ? Si[(long)c * LW + base + q_lo - 2] : T(0);
-        t2[l] = live ? Si[(long)c * LW + base + q_lo - 1] : T(0);
-        a[l] = colc[c];
+        t1[l] = live ? Si[(long)c * LW + base + q_lo - 2] * ai[l] : T(0);
+        t2[l] = live ? Si[(long)c * LW + base + q_lo - 1] * ai[l] : T(0);
     }
     auto special_in = [&](int m) -> int {
         return (m == m_lo) ? 0 : (m == m_lo + 1) ? 1 : (m == m_hi - 1) ? 2 : (m == m_hi) ? 3 : -1;
@@ -318,86 +325,99 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
         gA = r[0];
         gB = r[1];
     };
-    // one step of the forward elimination at row m: y = ghat - a p_prev, p = r y (the staged
-    // r is tw_t at row t, so p is x_t there), in place in (pr, pi); a special input row adds
-    // its transformed values (a uniform branch: read only on those four rows)
-    auto step = [&](auto gen_tag, int sb, int i, int m, T* pr, T* pi) {
+    // one step of the forward elimination at row m: q = ar (ghat - q_prev) (the staged ar is
+    // a tw_t at row t, so q is x~_t there), in place in (qr, qi); a special input row then adds
+    // ar spec_hat (a uniform branch: read only on those four rows)
+    auto step = [&](auto gen_tag, int sb, int i, int m, T* qr, T* qi) {
         constexpr bool GEN = decltype(gen_tag)::value;
         T gA, gB;
         ring(sb, i, gA, gB);
         const V f = fac(sb, i);
-        T sp[L];
 #pragma unroll
-        for (int l = 0; l < L; ++l) sp[l] = T(0);
+        for (int l = 0; l < L; ++l) {
+            const T yr = fma(gA, s1[l], fma(gB, s2[l], -qr[l]));   // y = ghat - q_prev, yi = -qi
+            const T rr = f[2 * l], ri = f[2 * l + 1];
+            const T nr = fma(rr, yr, ri * qi[l]);
+            qi[l] = fma(ri, yr, -(rr * qi[l]));
+            qr[l] = nr;
+        }
         if constexpr (GEN) {
             const int si = special_in(m);
             if (si >= 0) {
                 const Rv v = *reinterpret_cast<const Rv*>(spec_hat + (long)si * LW);
 #pragma unroll
-                for (int l = 0; l < L; ++l) sp[l] = v[l];
+                for (int l = 0; l < L; ++l) {
+                    qr[l] = fma(f[2 * l], v[l], qr[l]);
+                    qi[l] = fma(f[2 * l + 1], v[l], qi[l]);
+                }
             }
-        }
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            const T gh = fma(gA, s1[l], fma(gB, s2[l], sp[l]));
-            const T yr = fma(-a[l], pr[l], gh);
-            const T yi = -a[l] * pi[l];
-            const T rr = f[2 * l], ri = f[2 * l + 1];
-            pr[l] = fma(rr, yr, -(ri * yi));
-            pi[l] = fma(rr, yi, ri * yr);
         }
     };
 
-    // forward elimination from row m0 (p_{m0-1} = 0), p kept at the end of every full segment
+    // forward elimination from row m0 (q_{m0-1} = 0), q kept at the end of every full segment
     stage(0, 0);
     __syncthreads();
+    Rv ckr, cki;   // the last checkpoint (q at the end of segment nseg - 2)
     {
-        T pr[L], pi[L];
+        T qr[L], qi[L];
 #pragma unroll
-        for (int l = 0; l < L; ++l) pr[l] = pi[l] = T(0);
+        for (int l = 0; l < L; ++l) qr[l] = qi[l] = T(0);
+        // the checkpoint of segment s is stored after the barrier that ends it (the barrier waits
+        // for every outstanding memory operation of the wavefront: a store issued just before it
+        // would hold it for the store's whole latency)
+        auto store_ck = [&](int s) {
+            if (writes) {
+                *reinterpret_cast<Rv*>(ck + (long)(2 * s) * LW) = ckr;
+                *reinterpret_cast<Rv*>(ck + (long)(2 * s + 1) * LW) = cki;
+            }
+        };
         for (int s = 0; s < nseg - 1; ++s) {
             const int sb = s & 1;
             stage(s + 1, sb ^ 1);
+            if (s > 0) store_ck(s - 1);
             auto fwd = [&](auto gen_tag) {
 #pragma unroll
-                for (int i = 0; i < K; ++i) step(gen_tag, sb, i, m0 + s * K + i, pr, pi);
+                for (int i = 0; i < K; ++i) step(gen_tag, sb, i, m0 + s * K + i, qr, qi);
             };
             if (general(s)) fwd(std::true_type{});
             else fwd(std::false_type{});
-            if (writes) {
-                Rv vr, vi;
 #pragma unroll
-                for (int l = 0; l < L; ++l) { vr[l] = pr[l]; vi[l] = pi[l]; }
-                *reinterpret_cast<Rv*>(ck + (long)(2 * s) * LW) = vr;
-                *reinterpret_cast<Rv*>(ck + (long)(2 * s + 1) * LW) = vi;
-            }
+            for (int l = 0; l < L; ++l) { ckr[l] = qr[l]; cki[l] = qi[l]; }
             __syncthreads();   // buffer sb free, segment s+1 staged (the barrier waits for the transfers)
         }
+        if (nseg >= 2) store_ck(nseg - 2);
     }
 
-    // back substitution segment by segment (x_{t+1} = 0, so row t gives x_t = tw_t y_t):
-    // recompute the segment's p (x at row t) from the checkpoint before it, then walk back
-    // through it, x_m = p_m - r_m (a x_{m+1}), adding each row's synthesis products
+    // back substitution segment by segment (x~_{t+1} = 0, so row t gives x~_t = q_t):
+    // recompute the segment's q from the checkpoint before it, then walk back through it,
+    // x~_m = q_m - ar_m x~_{m+1}, adding each row's synthesis products
     T xr[L], xi[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) xr[l] = xi[l] = T(0);
-    Rv cpr, cpi;   // the checkpoint the next segment starts from, loaded a segment ahead
-    if (nseg >= 2) {
-        cpr = *reinterpret_cast<const Rv*>(ck + (long)(2 * nseg - 4) * LW);
-        cpi = *reinterpret_cast<const Rv*>(ck + (long)(2 * nseg - 3) * LW);
+    Rv cqr, cqi;   // the checkpoint the next segment starts from, loaded a segment ahead
+    if (nseg >= 2) {   // the first one still in registers
+        cqr = ckr;
+        cqi = cki;
     }
+    T thv[GroupReduce<T, L>::NOUT];   // the lane's reduced synthesis sums of the last segment
+    auto store_thin = [&](int s) {
+        if (has_col && blk < (W >> 6) && GroupReduce<T, L>::writer(lane)) {
+#pragma unroll
+            for (int e = 0; e < GroupReduce<T, L>::NOUT; ++e) th[(long)s * K * 4 + GroupReduce<T, L>::vidx(lane, e)] = thv[e];
+        }
+    };
     for (int s = nseg - 1; s >= 0; --s) {
         const int sb = s & 1;   // segment nseg-1 was staged by the forward pass's last step
-        T pr[L], pi[L];
+        T qr[L], qi[L];
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            pr[l] = s > 0 ? cpr[l] : T(0);
-            pi[l] = s > 0 ? cpi[l] : T(0);
+            qr[l] = s > 0 ? cqr[l] : T(0);
+            qi[l] = s > 0 ? cqi[l] : T(0);
         }
         if (s > 0) stage(s - 1, sb ^ 1);
         if (s > 1) {
-            cpr = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 4) * LW);
-            cpi = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 3) * LW);
+            cqr = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 4) * LW);
+            cqi = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 3) * LW);
         }
         auto bwd = [&](auto gen_tag) {
             constexpr bool GEN = decltype(gen_tag)::value;
@@ -405,9 +425,9 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
             T vr[K][L], vi[K][L];
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                step(gen_tag, sb, i, mb + i, pr, pi);
+                step(gen_tag, sb, i, mb + i, qr, qi);
 #pragma unroll
-                for (int l = 0; l < L; ++l) { vr[i][l] = pr[l]; vi[i][l] = pi[l]; }
+                for (int l = 0; l < L; ++l) { vr[i][l] = qr[l]; vi[i][l] = qi[l]; }
             }
             // read the factor rows again below rather than keep them in registers across the two
             // walks (a compiler-level memory barrier; no instruction is emitted)
@@ -420,11 +440,11 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
                 if (GEN && m > t) continue;
                 const V f = fac(sb, i);
 #pragma unroll
-                for (int l = 0; l < L; ++l) {
-                    const T sr = a[l] * xr[l], si_ = a[l] * xi[l];
+                for (int l = 0; l < L; ++l) {   // x~ = q - ar x~_next
                     const T rr = f[2 * l], ri = f[2 * l + 1];
-                    xr[l] = fma(-rr, sr, fma(ri, si_, vr[i][l]));
-                    xi[l] = fma(-rr, si_, fma(-ri, sr, vi[i][l]));
+                    const T nr = fma(-rr, xr[l], fma(ri, xi[l], vr[i][l]));
+                    xi[l] = fma(-rr, xi[l], fma(-ri, xr[l], vi[i][l]));
+                    xr[l] = nr;
                     acc[4 * i + 0] = fma(xr[l], t1[l], acc[4 * i + 0]);
                     acc[4 * i + 1] = fma(xi[l], t1[l], acc[4 * i + 1]);
                     acc[4 * i + 2] = fma(xr[l], t2[l], acc[4 * i + 2]);
@@ -435,22 +455,20 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
                     if (so >= 0 && writes) {
                         Rv ore, oim;
 #pragma unroll
-                        for (int l = 0; l < L; ++l) { ore[l] = xr[l]; oim[l] = xi[l]; }
+                        for (int l = 0; l < L; ++l) { ore[l] = xr[l] * ai[l]; oim[l] = xi[l] * ai[l]; }
                         *reinterpret_cast<Rv*>(xs + (long)so * LW) = ore;
                         *reinterpret_cast<Rv*>(xs + (long)(4 + so) * LW) = oim;
                     }
                 }
             }
             GroupReduce<T, L>::run(acc, lane);
-            if (has_col && blk < (W >> 6) && GroupReduce<T, L>::writer(lane)) {
 #pragma unroll
-                for (int e = 0; e < GroupReduce<T, L>::NOUT; ++e)
-                    th[(long)s * K * 4 + GroupReduce<T, L>::vidx(lane, e)] = acc[e];
-            }
+            for (int e = 0; e < GroupReduce<T, L>::NOUT; ++e) thv[e] = acc[e];
         };
         if (general(s)) bwd(std::true_type{});
         else bwd(std::false_type{});
         __syncthreads();   // buffer sb free, segment s-1 staged
+        store_thin(s);     // after the barrier, like the checkpoints
     }
 }
 
