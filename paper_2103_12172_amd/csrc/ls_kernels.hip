@@ -1603,132 +1603,155 @@ __device__ inline double2 mf_front_rhs(const MFNodeDev& nd, const MFNodeDev* __r
     return v;
 }
 
-// z(i) = sum_{j <= i} Linv(i, j) w(j) for the 64 rows of chunk blockIdx.x (lane = row; the 4
-// wavefronts split j and add their partial sums in LDS)
+// The four substitution products are bandwidth-bound matrix-vector products with
+// the node's stored blocks (column-major, leading dimension f): many small
+// workgroups, each with several loads in flight per thread, so that every
+// height's launch spreads over the chip.
+constexpr int kMfRows = 8;                   // rows of z or cw per workgroup
+constexpr int kMfSlots = 256 / kMfRows;      // column slots of a row (threads per row)
+constexpr int kMfCols = 4;                   // columns of t or x per workgroup (a wavefront each)
+
+// acc += l * u (complex), or conj(l) * u
+__device__ inline void cmac(double& sr, double& si, double2 l, double2 u) {
+    sr = fma(l.x, u.x, fma(-l.y, u.y, sr));
+    si = fma(l.x, u.y, fma(l.y, u.x, si));
+}
+__device__ inline void cmac_conj(double& sr, double& si, double2 l, double2 u) {
+    sr = fma(l.x, u.x, fma(l.y, u.y, sr));
+    si = fma(l.x, u.y, fma(-l.y, u.x, si));
+}
+
+// sum_j M(i, j) v(j) over the columns j = slot, slot + kMfSlots, ... < jend of row i
+// (M(i, j) = Mi[j * ld], v in LDS), eight loads in flight
+__device__ inline double2 mf_row_dot(const double2* __restrict__ Mi, long ld, const double2* v, int slot, int jend) {
+    double sr = 0.0, si = 0.0;
+    int j = slot;
+    for (; j + 7 * kMfSlots < jend; j += 8 * kMfSlots) {
+        double2 l[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) l[q] = Mi[(long)(j + q * kMfSlots) * ld];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cmac(sr, si, l[q], v[j + q * kMfSlots]);
+    }
+    for (; j < jend; j += kMfSlots) cmac(sr, si, Mi[(long)j * ld], v[j]);
+    return make_double2(sr, si);
+}
+
+// the kMfSlots partial sums of each of the workgroup's kMfRows rows, added in LDS; the
+// total of row r is returned to thread r (other threads: zero)
+__device__ inline double2 mf_rows_total(double2 p, int r, int slot) {
+    __shared__ double2 part[kMfSlots][kMfRows];
+    part[slot][r] = p;
+    __syncthreads();
+    double2 t = make_double2(0.0, 0.0);
+    if (threadIdx.x < kMfRows) {
+        for (int q = 0; q < kMfSlots; ++q) {
+            t.x += part[q][threadIdx.x].x;
+            t.y += part[q][threadIdx.x].y;
+        }
+    }
+    return t;
+}
+
+// z(i) = sum_{j <= i} Linv(i, j) w(j) for the kMfRows rows of chunk blockIdx.x: thread (row
+// tid % kMfRows, slot tid / kMfRows) takes every kMfSlots-th column
 __global__ void __launch_bounds__(256)
 mf_fwd_z_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
                 double2* __restrict__ arena, const double2* __restrict__ y) {
     extern __shared__ double2 mf_sh[];
-    __shared__ double2 part[4][64];
     const MFNodeDev nd = nodes[list[blockIdx.y]];
-    const int e = nd.e, f = nd.f, i0 = blockIdx.x * 64;
+    const int e = nd.e, i0 = blockIdx.x * kMfRows;
     if (i0 >= e) return;
-    const int iend = min(e, i0 + 64), tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int iend = min(e, i0 + kMfRows), tid = threadIdx.x, r = tid % kMfRows, slot = tid / kMfRows;
     const int* idx = reinterpret_cast<const int*>(img + nd.idx);
     for (int a = tid; a < iend; a += 256) mf_sh[a] = mf_front_rhs(nd, nodes, img, arena, y, idx, a);
     __syncthreads();
-    const int i = i0 + lane;
-    const double2* Li = arena + nd.Z;
-    double sr = 0.0, si = 0.0;
-    if (i < iend) {
-        const int q = (i + 4) / 4;   // j = 0..i split in four ranges
-        const int j0 = wave * q, j1 = min(i + 1, j0 + q);
-        for (int j = j0; j < j1; ++j) {
-            const double2 l = Li[i + (long)j * f], u = mf_sh[j];
-            sr += l.x * u.x - l.y * u.y;
-            si += l.x * u.y + l.y * u.x;
-        }
-    }
-    part[wave][lane] = make_double2(sr, si);
-    __syncthreads();
-    if (wave == 0 && i < iend) {
-        double2 zz = part[0][lane];
-        for (int k = 1; k < 4; ++k) {
-            zz.x += part[k][lane].x;
-            zz.y += part[k][lane].y;
-        }
-        arena[nd.z + i] = zz;
-    }
+    const int i = i0 + r;
+    const double2 p = (i < iend) ? mf_row_dot(arena + nd.Z + i, nd.f, mf_sh, slot, i + 1) : make_double2(0.0, 0.0);
+    const double2 zz = mf_rows_total(p, r, slot);
+    if (tid < kMfRows && i0 + tid < iend) arena[nd.z + i0 + tid] = zz;
 }
 
-// cw(r) = w(e + r) - sum_j L21(r, j) z(j) for the 64 rows of chunk blockIdx.x
+// cw(r) = w(e + r) - sum_j L21(r, j) z(j) for the kMfRows rows of chunk blockIdx.x
 __global__ void __launch_bounds__(256)
 mf_fwd_cw_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
                  double2* __restrict__ arena, const double2* __restrict__ y) {
     extern __shared__ double2 mf_sh[];
-    __shared__ double2 part[4][64];
     const MFNodeDev nd = nodes[list[blockIdx.y]];
-    const int e = nd.e, b = nd.b, f = nd.f, r0 = blockIdx.x * 64;
+    const int e = nd.e, b = nd.b, r0 = blockIdx.x * kMfRows;
     if (r0 >= b) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, r = tid % kMfRows, slot = tid / kMfRows;
     const int* idx = reinterpret_cast<const int*>(img + nd.idx);
     for (int j = tid; j < e; j += 256) mf_sh[j] = arena[nd.z + j];
     __syncthreads();
-    const int r = r0 + lane;
-    const double2* L21 = arena + nd.L + e;
-    double sr = 0.0, si = 0.0;
-    if (r < b) {
-        const int q = (e + 3) / 4, j0 = wave * q, j1 = min(e, j0 + q);
-        for (int j = j0; j < j1; ++j) {
-            const double2 l = L21[r + (long)j * f], u = mf_sh[j];
-            sr += l.x * u.x - l.y * u.y;
-            si += l.x * u.y + l.y * u.x;
-        }
-    }
-    part[wave][lane] = make_double2(sr, si);
-    __syncthreads();
-    if (wave == 0 && r < b) {
-        double2 v = mf_front_rhs(nd, nodes, img, arena, y, idx, e + r);
-        for (int k = 0; k < 4; ++k) {
-            v.x -= part[k][lane].x;
-            v.y -= part[k][lane].y;
-        }
-        arena[nd.cw + r] = v;
+    const double2 p = (r0 + r < b) ? mf_row_dot(arena + nd.L + e + r0 + r, nd.f, mf_sh, slot, e) : make_double2(0.0, 0.0);
+    const double2 s = mf_rows_total(p, r, slot);
+    if (tid < kMfRows && r0 + tid < b) {
+        const double2 v = mf_front_rhs(nd, nodes, img, arena, y, idx, e + r0 + tid);
+        arena[nd.cw + r0 + tid] = make_double2(v.x - s.x, v.y - s.y);
     }
 }
 
-// t(j) = z(j) - sum_r conj(L21(r, j)) x(idx(e + r)) for the 16 columns of chunk blockIdx.x (a
+// t(j) = z(j) - sum_r conj(L21(r, j)) x(idx(e + r)) for the kMfCols columns of chunk blockIdx.x (a
 // wavefront per column, lanes along the column); t overwrites z
 __global__ void __launch_bounds__(256)
 mf_bwd_t_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
                 double2* __restrict__ arena, const double2* __restrict__ x) {
     extern __shared__ double2 mf_sh[];
     const MFNodeDev nd = nodes[list[blockIdx.y]];
-    const int e = nd.e, b = nd.b, f = nd.f, c0 = blockIdx.x * 16;
+    const int e = nd.e, b = nd.b, f = nd.f, c0 = blockIdx.x * kMfCols;
     if (c0 >= e) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int* idx = reinterpret_cast<const int*>(img + nd.idx);
     for (int r = tid; r < b; r += 256) mf_sh[r] = x[idx[e + r]];
     __syncthreads();
-    const double2* L21 = arena + nd.L + e;
-    for (int j = c0 + wave; j < min(e, c0 + 16); j += 4) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int r = lane; r < b; r += 64) {
-            const double2 l = L21[r + (long)j * f], u = mf_sh[r];   // conj(l) u
-            s.x += l.x * u.x + l.y * u.y;
-            s.y += l.x * u.y - l.y * u.x;
-        }
-        s = wave_sum2(s);
-        if (lane == 0) {
-            const double2 z = arena[nd.z + j];
-            arena[nd.z + j] = make_double2(z.x - s.x, z.y - s.y);
-        }
+    const int j = c0 + wave;
+    if (j >= e) return;
+    const double2* col = arena + nd.L + e + (long)j * f;
+    double sr = 0.0, si = 0.0;
+    int r = lane;
+    for (; r + 192 < b; r += 256) {
+        double2 l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) l[q] = col[r + 64 * q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cmac_conj(sr, si, l[q], mf_sh[r + 64 * q]);
+    }
+    for (; r < b; r += 64) cmac_conj(sr, si, col[r], mf_sh[r]);
+    const double2 s = wave_sum2(make_double2(sr, si));
+    if (lane == 0) {
+        const double2 z = arena[nd.z + j];
+        arena[nd.z + j] = make_double2(z.x - s.x, z.y - s.y);
     }
 }
 
-// x(idx(i)) = sum_{j >= i} conj(Linv(j, i)) t(j) for the 16 rows of chunk blockIdx.x
+// x(idx(i)) = sum_{j >= i} conj(Linv(j, i)) t(j) for the kMfCols rows of chunk blockIdx.x
 __global__ void __launch_bounds__(256)
 mf_bwd_x_kernel(const MFNodeDev* __restrict__ nodes, const int* __restrict__ list, const char* __restrict__ img,
                 const double2* __restrict__ arena, double2* __restrict__ x) {
     extern __shared__ double2 mf_sh[];
     const MFNodeDev nd = nodes[list[blockIdx.y]];
-    const int e = nd.e, f = nd.f, c0 = blockIdx.x * 16;
+    const int e = nd.e, f = nd.f, c0 = blockIdx.x * kMfCols;
     if (c0 >= e) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int* idx = reinterpret_cast<const int*>(img + nd.idx);
     for (int j = c0 + tid; j < e; j += 256) mf_sh[j - c0] = arena[nd.z + j];
     __syncthreads();
-    const double2* Li = arena + nd.Z;
-    for (int i = c0 + wave; i < min(e, c0 + 16); i += 4) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int j = i + lane; j < e; j += 64) {
-            const double2 l = Li[j + (long)i * f], u = mf_sh[j - c0];   // conj(Linv(j, i)) t_j
-            s.x += l.x * u.x + l.y * u.y;
-            s.y += l.x * u.y - l.y * u.x;
-        }
-        s = wave_sum2(s);
-        if (lane == 0) x[idx[i]] = s;
+    const int i = c0 + wave;
+    if (i >= e) return;
+    const double2* col = arena + nd.Z + (long)i * f;
+    double sr = 0.0, si = 0.0;
+    int j = i + lane;
+    for (; j + 192 < e; j += 256) {
+        double2 l[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) l[q] = col[j + 64 * q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cmac_conj(sr, si, l[q], mf_sh[j + 64 * q - c0]);
     }
+    for (; j < e; j += 64) cmac_conj(sr, si, col[j], mf_sh[j - c0]);
+    const double2 s = wave_sum2(make_double2(sr, si));
+    if (lane == 0) x[idx[i]] = s;
 }
 
 void launch_mf_solve(const MFNodeDev* nodes, const int* list, int count, int max_e, int max_b, bool forward,
@@ -1737,16 +1760,16 @@ void launch_mf_solve(const MFNodeDev* nodes, const int* list, int count, int max
     const size_t lds_e = (size_t)std::max(max_e, 1) * sizeof(double2), lds_b = (size_t)std::max(max_b, 1) * sizeof(double2);
     if (forward) {
         if (max_e > 0)
-            hipLaunchKernelGGL(mf_fwd_z_kernel, dim3((max_e + 63) / 64, count), dim3(256), lds_e, st, nodes, list, img,
-                               arena, in);
+            hipLaunchKernelGGL(mf_fwd_z_kernel, dim3((max_e + kMfRows - 1) / kMfRows, count), dim3(256), lds_e, st,
+                               nodes, list, img, arena, in);
         if (max_b > 0)
-            hipLaunchKernelGGL(mf_fwd_cw_kernel, dim3((max_b + 63) / 64, count), dim3(256), lds_e, st, nodes, list,
-                               img, arena, in);
+            hipLaunchKernelGGL(mf_fwd_cw_kernel, dim3((max_b + kMfRows - 1) / kMfRows, count), dim3(256), lds_e, st,
+                               nodes, list, img, arena, in);
     } else if (max_e > 0) {
-        hipLaunchKernelGGL(mf_bwd_t_kernel, dim3((max_e + 15) / 16, count), dim3(256), lds_b, st, nodes, list, img,
-                           arena, (const double2*)out);
-        hipLaunchKernelGGL(mf_bwd_x_kernel, dim3((max_e + 15) / 16, count), dim3(256), lds_e, st, nodes, list, img,
-                           (const double2*)arena, out);
+        hipLaunchKernelGGL(mf_bwd_t_kernel, dim3((max_e + kMfCols - 1) / kMfCols, count), dim3(256), lds_b, st,
+                           nodes, list, img, arena, (const double2*)out);
+        hipLaunchKernelGGL(mf_bwd_x_kernel, dim3((max_e + kMfCols - 1) / kMfCols, count), dim3(256), lds_e, st,
+                           nodes, list, img, (const double2*)arena, out);
     }
     MDP_HIP(hipGetLastError());
 }
