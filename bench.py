@@ -45,8 +45,9 @@ ALGO = {
     "interface_ls": ("mfma", "f64", "flops"),
     "ap_fused_f64": ("alu", "f64", "flops"),
     "ap_fused_f32": ("alu", "f32v", "flops"),
-    "chol_panel": ("alu", "f64", "flops"),
-    "chol_update": ("alu", "f64", "flops"),
+    "chol_diag": ("alu", "f64", "flops"),
+    "chol_panel": ("mfma", "f64", "flops"),
+    "chol_update": ("mfma", "f64", "flops"),
     "gram": ("mfma", "f64", "flops"),
     "tridiag_f64": ("hbm", "hbm", "bytes"),
     "tridiag_f32": ("hbm", "hbm", "bytes"),
@@ -63,7 +64,8 @@ ALGO = {
 KERNELS = {
     "ap_fused_f64": ("proj_sweep_kernel<double", "paper_2103_12172_amd/csrc/proj_sweep.hip"),
     "ap_fused_f32": ("proj_sweep_kernel<float", "paper_2103_12172_amd/csrc/proj_sweep.hip"),
-    "chol_panel": ("chol_panel_kernel", "paper_2103_12172_amd/csrc/ls_kernels.hip"),
+    "chol_diag": ("chol_diag_kernel", "paper_2103_12172_amd/csrc/ls_kernels.hip"),
+    "chol_panel": ("chol_slab_kernel", "paper_2103_12172_amd/csrc/ls_kernels.hip"),
     "tridiag_f64": ("tridiag_kernel<double>", "paper_2103_12172_amd/csrc/ap_kernels.hip"),
     "gemm_sine_f64": ("gemm_bd_kernel<double", "paper_2103_12172_amd/csrc/gemm_sine.hip"),
     "gemm_sine_f32": ("gemm_bd_kernel<float", "paper_2103_12172_amd/csrc/gemm_sine.hip"),

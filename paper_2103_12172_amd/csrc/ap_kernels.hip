@@ -1093,14 +1093,13 @@ fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs) {
 
 // Q(i, col0+b) = -u(m_i, q_i): the full gamma rows from the synthesis rows us
 // ([b][plane][4][W], output of the inverse sine GEMM of xs), the others from
-// the thin partial sums (odd-mode blocks give A, even-mode blocks B).
+// the thin partial sums (odd-mode blocks give A, even-mode blocks B).  One workgroup
+// per column (one job lookup), its threads over the column's gamma nodes.
 template <class T>
-__global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njobs, int nbx) {
-    const int gcol = blockIdx.x / nbx, bx = blockIdx.x - gcol * nbx;
+__global__ void __launch_bounds__(256) gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njobs) {
+    const int gcol = blockIdx.x;
     const FusedJob& J = jobs[find_job(jobs, njobs, gcol)];
-    const int i = bx * blockDim.x + threadIdx.x;
     const int b = gcol - J.b0;
-    if (i >= J.ng) return;
     const Fold f = J.f;
     const RingGeom rg{J.src.m_lo, J.src.m_hi, J.src.q_lo, J.src.q_hi};
     const T* __restrict__ us = reinterpret_cast<const T*>(J.us);
@@ -1109,7 +1108,9 @@ __global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njo
     const int* __restrict__ gq = J.gq;
     const int rows_pad = J.rows_pad, ldq = J.ldq, col0 = J.src.col0;
     double* __restrict__ Q = J.Q;
-    const int m = gm[i], q = gq[i], n = f.n, p = f.p, W = f.W;
+    const int n = f.n, p = f.p, W = f.W;
+    for (int i = threadIdx.x; i < J.ng; i += blockDim.x) {
+    const int m = gm[i], q = gq[i];
     double vre, vim;
     const int so = special_out(rg, m);
     if (so >= 0) {
@@ -1142,6 +1143,7 @@ __global__ void gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njo
     double* o = Q + 2 * ((long)(col0 + b) * ldq + i);
     o[0] = -vre;
     o[1] = -vim;
+    }
 }
 
 // ------------------------------------------------------------------ batched solves across plans
@@ -1164,13 +1166,18 @@ __global__ void extend_density_jobs_kernel(const SolveJob* __restrict__ jobs, in
                         blockIdx.y - J.b0);
 }
 
+// rows kJobRows blockIdx.x .. of entry blockIdx.y per workgroup (one job lookup), the
+// threads over the row's columns
+constexpr int kJobRows = 8;
+
 __global__ void __launch_bounds__(256)
 fold_rhs_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs) {
-    const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.z)];
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= J.f.W || (int)blockIdx.y >= J.bd.nr) return;
+    const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.y)];
     const SrcEval ev{J.src, J.f.n, J.sc};
-    fold_rhs_body<double>(ev, J.f, 2, J.bd, J.A, c, J.bd.r0 + blockIdx.y, blockIdx.z - J.b0);
+    const int r1 = min(J.bd.nr, (int)(blockIdx.x + 1) * kJobRows);
+    for (int r = blockIdx.x * kJobRows; r < r1; ++r)
+        for (int c = threadIdx.x; c < J.f.W; c += blockDim.x)
+            fold_rhs_body<double>(ev, J.f, 2, J.bd, J.A, c, J.bd.r0 + r, blockIdx.y - J.b0);
 }
 
 __global__ void __launch_bounds__(256)
@@ -1182,16 +1189,17 @@ tridiag_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs) {
     else tridiag_body<double>(J.B, 2, J.A, J.fac, J.colc, J.f.n, J.f.W, J.bd, c, blockIdx.y - J.b0);
 }
 
-__global__ void unfold_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs, double* grids) {
-    const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.z)];
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q > J.f.n || (int)blockIdx.y >= J.bd.nr) return;
-    if (J.out)   // the solution itself into separate grids
-        unfold_body<double>(J.B, nullptr, J.f, J.bd, 1.0, nullptr, 0, J.out, 0, J.ooff, J.bd.r0 + blockIdx.y, q,
-                            blockIdx.z - J.b0);
-    else         // w - u in place
-        unfold_body<double>(J.B, nullptr, J.f, J.bd, -1.0, grids, 0, grids, 0, J.src.goff, J.bd.r0 + blockIdx.y, q,
-                            blockIdx.z - J.b0);
+__global__ void __launch_bounds__(256) unfold_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs,
+                                                          double* grids) {
+    const SolveJob& J = jobs[find_solve_job(jobs, njobs, blockIdx.y)];
+    const int r1 = min(J.bd.nr, (int)(blockIdx.x + 1) * kJobRows), b = blockIdx.y - J.b0;
+    for (int r = blockIdx.x * kJobRows; r < r1; ++r)
+        for (int q = threadIdx.x; q <= J.f.n; q += blockDim.x) {
+            if (J.out)   // the solution itself into separate grids
+                unfold_body<double>(J.B, nullptr, J.f, J.bd, 1.0, nullptr, 0, J.out, 0, J.ooff, J.bd.r0 + r, q, b);
+            else         // w - u in place
+                unfold_body<double>(J.B, nullptr, J.f, J.bd, -1.0, grids, 0, grids, 0, J.src.goff, J.bd.r0 + r, q, b);
+        }
 }
 
 }  // namespace
@@ -1233,7 +1241,9 @@ void launch_extend_density_jobs(const SolveJob* jobs, int njobs, int total, int 
 void launch_fold_rhs_jobs(const SolveJob* jobs, int njobs, int total, int max_w, int max_nr, hipStream_t st) {
     if (njobs <= 0 || total <= 0) return;
     check_batch(total);
-    hipLaunchKernelGGL(fold_rhs_jobs_kernel, dim3((max_w + 255) / 256, max_nr, total), dim3(256), 0, st, jobs, njobs);
+    (void)max_w;
+    hipLaunchKernelGGL(fold_rhs_jobs_kernel, dim3((max_nr + kJobRows - 1) / kJobRows, total), dim3(256), 0, st, jobs,
+                       njobs);
     MDP_HIP(hipGetLastError());
 }
 
@@ -1248,8 +1258,9 @@ void launch_unfold_jobs(const SolveJob* jobs, int njobs, int total, int max_n, i
                         hipStream_t st) {
     if (njobs <= 0 || total <= 0) return;
     check_batch(total);
-    hipLaunchKernelGGL(unfold_jobs_kernel, dim3((max_n + 1 + 255) / 256, max_nr, total), dim3(256), 0, st, jobs, njobs,
-                       grids);
+    (void)max_n;
+    hipLaunchKernelGGL(unfold_jobs_kernel, dim3((max_nr + kJobRows - 1) / kJobRows, total), dim3(256), 0, st, jobs,
+                       njobs, grids);
     MDP_HIP(hipGetLastError());
 }
 
@@ -1279,8 +1290,8 @@ template void launch_fold_ring_jobs<float>(const FusedJob*, int, int, int, hipSt
 template <class T>
 void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, hipStream_t st) {
     if (njobs <= 0 || total <= 0) return;
-    const int nbx = (max_ng + 255) / 256;
-    hipLaunchKernelGGL(gather_q_fused_kernel<T>, flat_grid(nbx, total), dim3(256), 0, st, jobs, njobs, nbx);
+    (void)max_ng;
+    hipLaunchKernelGGL(gather_q_fused_kernel<T>, flat_grid(1, total), dim3(256), 0, st, jobs, njobs);
     MDP_HIP(hipGetLastError());
 }
 template void launch_gather_q_fused_jobs<double>(const FusedJob*, int, int, int, hipStream_t);

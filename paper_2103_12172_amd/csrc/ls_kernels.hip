@@ -274,7 +274,7 @@ __device__ inline void tile16_mac(double (&cr)[4], double (&ci)[4], FA a, FB b) 
 //  U  S(i,j) -= L(i,s) L(j,s)^* (trailing, lower) and W(i,j) -= L(i,s) Z(s,j)
 //     for the rows below (j up to the block, Z(s,s) = L_ss^{-1}).
 // P and U work on 16x16 tiles spread over the 4 wavefronts (4 entries per lane).
-__device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double shift, CholLds& s,
+__device__ __attribute__((always_inline)) int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double shift, CholLds& s,
                           double2* __restrict__ Lout, int ldl, double2* __restrict__ Zout, int ldz) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;   // tile row, column group (columns 4g..4g+3)
@@ -459,143 +459,175 @@ __device__ int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double
 // couple (G vanishes between them, so L and L^{-1} do too): each is factored
 // on its own.  Z = L^{-1} is built block row by block row: W(i,j) accumulates
 // -sum_l L(i,l) Z(l,j) over the eliminated columns l, and Z(q,j) = Z(q,q) W(q,j)
-// once block row q's W is complete.
-// Workgroups: per sub-block q, roles (256 threads each, every one refactors
-// the sub-block's diagonal block into LDS first):
-//   role 0:                      L(q,q), Z(q,q) to memory, breakdown to *info;
-//   roles 1..np (32-row slabs of the rows r0..nc-1): L(i,q) = G(i,q) Z(q,q)^*;
-//   the rest (32-column slabs j0 < kb): Z(q,j) = Z(q,q) W(q,j).
-// The slab operand is staged in the (no longer needed) S part of the LDS.
-// (one workgroup per CU by its LDS, so all 512 registers of a lane are allowed)
-__device__ inline void chol_panel_body(const double2* __restrict__ G, int nc, const CholStepDev& sp, double shift,
-                                       double2* __restrict__ L, double2* __restrict__ Z,
-                                       const double2* __restrict__ W, int* info, int np, int nz, int bx, CholLds& s) {
-    const int roles = 1 + np + nz;
-    const int q = bx / roles, role = bx - q * roles, tid = threadIdx.x;
-    const int kb = sp.kb, r0 = sp.kb + sp.wtot;
-    const int kq = kb + sp.off[q], nbq = sp.off[q + 1] - sp.off[q];
+// once block row q's W is complete.  Two launches per step before the update:
+//   diagonal: one workgroup per sub-block factors it in LDS and writes L(q,q),
+//     Z(q,q) = L(q,q)^{-1} (lower triangles; the upper ones stay zero) and the
+//     first breakdown to *info;
+//   slabs: one workgroup per 32-row slab of the rows r0..nc-1, L(i,q) =
+//     G(i,q) Z(q,q)^*, and per 32-column slab j0 < kb of block row q of Z,
+//     Z(q,j) = Z(q,q) W(q,j); Z(q,q) is read from memory (an L2-resident 64 KB
+//     block shared by the step's workgroups), so a slab workgroup needs no
+//     refactorisation and little LDS, and many fit on a CU.
+__device__ __attribute__((always_inline)) inline void chol_diag_body(const double2* __restrict__ G, int nc, int kq, int nbq, double shift,
+                                      double2* __restrict__ L, double2* __restrict__ Z, int* info, CholLds& s) {
     const long dk = kq + (long)kq * nc;
-    const bool diag = role == 0;
-    const int bad = chol64_lds(G + dk, nc, nbq, shift, s, diag ? L + dk : nullptr, nc, diag ? Z + dk : nullptr, nc);
-    if (diag) {
-        if (tid == 0 && bad && info) atomicCAS(info, 0, kq + bad);
-        return;
-    }
-    if (role <= np) {
-        // rows i0..i0+31: S[r][k] = G(i0 + r, kq + k); thread rows 2tr + {0,1}, columns 4tc + {0..3}
-        const int i0 = r0 + 32 * (role - 1);
-        {
-            double2 v[8];   // every load issued before the first wait
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = tid + 256 * u, rr = e & 31, k = e >> 5, i = i0 + rr;   // consecutive threads: rows
-                v[u] = (i < nc && k < nbq) ? G[i + (long)(kq + k) * nc] : make_double2(0.0, 0.0);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = tid + 256 * u;
-                s.S[e & 31][e >> 5] = v[u];
-            }
-        }
-        __syncthreads();
-        // L(i,c) = sum_k G(i,k) conj(Z(c,k)) on the matrix cores: 32 x 64 as 2 x 4 tiles of 16 x 16,
-        // two per wavefront (tile row wave >> 1, tile columns 2 (wave & 1) + {0, 1}); A operand
-        // lane (row lane & 15, k lane >> 4), B operand lane (k lane >> 4, column lane & 15), result
-        // rows (lane >> 4) + 4 r of each tile
-        const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
-        const int ti = wv >> 1;
+    const int bad = chol64_lds(G + dk, nc, nbq, shift, s, L + dk, nc, Z + dk, nc);
+    if (threadIdx.x == 0 && bad && info) atomicCAS(info, 0, kq + bad);
+}
+
+// Z(q,q)(r, k) of the sub-block at kq of order nbq (lower triangle; zero outside the block)
+__device__ inline double2 zqq_at(const double2* Z, int nc, int kq, int nbq, int r, int k) {
+    return (r < nbq && k <= r) ? Z[kq + r + (long)(kq + k) * nc] : make_double2(0.0, 0.0);
+}
+
+// slab role of one sub-block (kq, nbq) of the step with trailing rows from r0: roles
+// 0..np-1 are row slabs of L, the rest column slabs of block row q of Z
+__device__ __attribute__((always_inline)) inline void chol_slab_body(const double2* __restrict__ G, int nc, int kb, int r0, int kq, int nbq,
+                                      double2* __restrict__ L, double2* Z, const double2* __restrict__ W, int np,
+                                      int role) {
+    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
+    if (role < np) {
+        // L(i,c) = sum_k G(i,k) conj(Z(c,k)) on the matrix cores for the rows i0..i0+31: 32 x 64 as
+        // 2 x 4 tiles of 16 x 16, two per wavefront (tile row wave >> 1, tile columns 2 (wave & 1) +
+        // {0, 1}); A operand lane (row lane & 15, k lane >> 4), B operand lane (k lane >> 4, column
+        // lane & 15), result rows (lane >> 4) + 4 r of each tile.  Both operands straight from memory
+        // (16 consecutive rows of one column per load), four k-steps in flight.
+        const int i0 = r0 + 32 * role, ti = wv >> 1, i = i0 + 16 * ti + lr;
+        const int cb = 32 * (wv & 1);
         d4 cr[2], ci[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) { cr[t] = d4{0, 0, 0, 0}; ci[t] = d4{0, 0, 0, 0}; }
-#pragma unroll 4
-        for (int k0 = 0; k0 < 64; k0 += 4) {
-            const double2 a = s.S[16 * ti + lr][k0 + lk];
+        auto load = [&](int k0, double2* a, double2 (*z)[2]) {
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const double2 z = s.Z[16 * (2 * (wv & 1) + t) + lr][k0 + lk];   // B = conj(Z)^T
-                cr[t] = mfma64(a.x, z.x, cr[t]);
-                cr[t] = mfma64(a.y, z.y, cr[t]);
-                ci[t] = mfma64(-a.x, z.y, ci[t]);
-                ci[t] = mfma64(a.y, z.x, ci[t]);
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + 4 * u + lk;
+                a[u] = (i < nc && k < nbq) ? G[i + (long)(kq + k) * nc] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) z[u][t] = zqq_at(Z, nc, kq, nbq, cb + 16 * t + lr, k);
+            }
+        };
+        double2 a[4], z[4][2], na[4], nz[4][2];
+        load(0, a, z);
+#pragma unroll
+        for (int k0 = 0; k0 < 64; k0 += 16) {
+            if (k0 + 16 < 64) load(k0 + 16, na, nz);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {   // B = conj(Z)^T
+                    cr[t] = mfma64(a[u].x, z[u][t].x, cr[t]);
+                    cr[t] = mfma64(a[u].y, z[u][t].y, cr[t]);
+                    ci[t] = mfma64(-a[u].x, z[u][t].y, ci[t]);
+                    ci[t] = mfma64(a[u].y, z[u][t].x, ci[t]);
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = na[u];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) z[u][t] = nz[u][t];
             }
         }
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = i0 + 16 * ti + lk + 4 * r, c = 16 * (2 * (wv & 1) + t) + lr;
-                if (i < nc && c < nbq) L[i + (long)(kq + c) * nc] = make_double2(cr[t][r], ci[t][r]);
+                const int io = i0 + 16 * ti + lk + 4 * r, c = cb + 16 * t + lr;
+                if (io < nc && c < nbq) L[io + (long)(kq + c) * nc] = make_double2(cr[t][r], ci[t][r]);
             }
         return;
     }
-    // columns j0..j0+31 (< kb) of block row q of Z: S[k][c] = W(kq + k, j0 + c); thread rows 4tr + {0..3},
-    // columns 2tc + {0,1}
-    const int j0 = 32 * (role - 1 - np);
+    // columns j0..j0+31 (< kb) of block row q of Z: Sw[k][c] = W(kq + k, j0 + c), staged in LDS by
+    // coalesced loads (consecutive threads: consecutive k of one column)
+    __shared__ double2 Sw[64][33];
+    const int j0 = 32 * (role - np);
     {
         double2 v[8];   // every load issued before the first wait
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int e = tid + 256 * u, k = e >> 5, c = e & 31;
+            const int e = tid + 256 * u, k = e & 63, c = e >> 6;
             v[u] = (k < nbq && j0 + c < kb) ? W[kq + k + (long)(j0 + c) * nc] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = tid + 256 * u;
-            s.S[e >> 5][e & 31] = v[u];
+            Sw[e & 63][e >> 6] = v[u];
         }
     }
     __syncthreads();
     // Z(q, j) = Z(q,q) W(q, j) on the matrix cores: 64 x 32 as 4 x 2 tiles of 16 x 16, two per
-    // wavefront (tile rows 2 (wave >> 1) + {0, 1}, tile column wave & 1); layouts as above
-    const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
-    const int tj = wv & 1;
+    // wavefront (tile rows 2 (wave >> 1) + {0, 1}, tile column wave & 1); A operand Z(q,q) from memory
+    const int tj = wv & 1, rb = 32 * (wv >> 1);
     d4 cr[2], ci[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) { cr[t] = d4{0, 0, 0, 0}; ci[t] = d4{0, 0, 0, 0}; }
-#pragma unroll 4
-    for (int k0 = 0; k0 < 64; k0 += 4) {
-        const double2 w = s.S[k0 + lk][16 * tj + lr];
+    auto loadz = [&](int k0, double2 (*z)[2]) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const double2 z = s.Z[16 * (2 * (wv >> 1) + t) + lr][k0 + lk];
-            cr[t] = mfma64(z.x, w.x, cr[t]);
-            cr[t] = mfma64(-z.y, w.y, cr[t]);
-            ci[t] = mfma64(z.x, w.y, ci[t]);
-            ci[t] = mfma64(z.y, w.x, ci[t]);
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) z[u][t] = zqq_at(Z, nc, kq, nbq, rb + 16 * t + lr, k0 + 4 * u + lk);
+    };
+    double2 z[4][2], nzq[4][2];
+    loadz(0, z);
+#pragma unroll
+    for (int k0 = 0; k0 < 64; k0 += 16) {
+        if (k0 + 16 < 64) loadz(k0 + 16, nzq);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double2 w = Sw[k0 + 4 * u + lk][16 * tj + lr];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                cr[t] = mfma64(z[u][t].x, w.x, cr[t]);
+                cr[t] = mfma64(-z[u][t].y, w.y, cr[t]);
+                ci[t] = mfma64(z[u][t].x, w.y, ci[t]);
+                ci[t] = mfma64(z[u][t].y, w.x, ci[t]);
+            }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) z[u][t] = nzq[u][t];
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int rr = 16 * (2 * (wv >> 1) + t) + lk + 4 * r, j = j0 + 16 * tj + lr;
+            const int rr = rb + 16 * t + lk + 4 * r, j = j0 + 16 * tj + lr;
             if (rr < nbq && j < kb) Z[kq + rr + (long)j * nc] = make_double2(cr[t][r], ci[t][r]);
         }
 }
 
-
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-chol_panel_kernel(const double2* __restrict__ G, int nc, CholStepDev sp, double shift, double2* __restrict__ L,
-                  double2* __restrict__ Z, const double2* __restrict__ W, int* info, int np, int nz) {
+chol_diag_kernel(const double2* __restrict__ G, int nc, CholStepDev sp, double shift, double2* __restrict__ L,
+                 double2* __restrict__ Z, int* info) {
     __shared__ CholLds s;
-    chol_panel_body(G, nc, sp, shift, L, Z, W, info, np, nz, blockIdx.x, s);
+    const int q = blockIdx.x;
+    chol_diag_body(G, nc, sp.kb + sp.off[q], sp.off[q + 1] - sp.off[q], shift, L, Z, info, s);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+chol_slab_kernel(const double2* __restrict__ G, int nc, CholStepDev sp, double2* __restrict__ L, double2* Z,
+                 const double2* __restrict__ W, int np, int nz) {
+    const int roles = np + nz;
+    const int q = blockIdx.x / roles, role = blockIdx.x - q * roles;
+    const int kq = sp.kb + sp.off[q], nbq = sp.off[q + 1] - sp.off[q];
+    chol_slab_body(G, nc, sp.kb, sp.kb + sp.wtot, kq, nbq, L, Z, W, np, role);
 }
 
 // One Cholesky step of several matrices at once (the fronts of one elimination-tree
-// height): entry blockIdx.y factors its sub-block kb..kb+w-1; workgroups past the
-// entry's roles exit.
+// height): entry blockIdx.x (diagonal) or blockIdx.y (slabs) factors its sub-block
+// kb..kb+w-1; slab workgroups past the entry's roles exit.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-chol_panel_batched_kernel(const CholBatchEntry* __restrict__ ent, int* info) {
+chol_diag_batched_kernel(const CholBatchEntry* __restrict__ ent, int* info) {
     __shared__ CholLds s;
+    const CholBatchEntry e = ent[blockIdx.x];
+    chol_diag_body(e.G, e.nc, e.kb, e.w, 0.0, e.L, e.Z, info, s);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+chol_slab_batched_kernel(const CholBatchEntry* __restrict__ ent) {
     const CholBatchEntry e = ent[blockIdx.y];
-    if ((int)blockIdx.x >= 1 + e.np + e.nz) return;
-    CholStepDev sp;
-    sp.kb = e.kb;
-    sp.nq = 1;
-    sp.wtot = e.w;
-    sp.off[0] = 0;
-    sp.off[1] = e.w;
-    chol_panel_body(e.G, e.nc, sp, 0.0, e.L, e.Z, e.W, info, e.np, e.nz, blockIdx.x, s);
+    if ((int)blockIdx.x >= e.np + e.nz) return;
+    chol_slab_body(e.G, e.nc, e.kb, e.kb + e.w, e.kb, e.w, e.L, e.Z, e.W, e.np, blockIdx.x);
 }
 
 // Update after the block step kb..r0-1 (r0 = kb + wtot): 32 x 32 tiles of
@@ -1323,23 +1355,33 @@ void launch_zgemm(char opA, char opB, int m, int n, int k, double2 alpha, const 
     }
 }
 
-void launch_chol_panel(const double2* G, int nc, const CholStepDev& sp, double shift, double2* L, double2* Z,
-                       const double2* W, int* info, hipStream_t st) {
+void launch_chol_diag(const double2* G, int nc, const CholStepDev& sp, double shift, double2* L, double2* Z, int* info,
+                      hipStream_t st) {
     if (sp.nq < 1 || sp.nq > CholStepDev::kMaxQ || sp.kb < 0 || sp.off[0] != 0 || sp.off[sp.nq] != sp.wtot ||
         sp.kb + sp.wtot > nc)
         throw Error(MDP_ERR_ARG, "bad Cholesky step");
     for (int q = 0; q < sp.nq; ++q)
         if (sp.off[q + 1] - sp.off[q] < 1 || sp.off[q + 1] - sp.off[q] > 64)
             throw Error(MDP_ERR_ARG, "Cholesky sub-block width must be 1..64");
-    const int rest = nc - sp.kb - sp.wtot;
-    const int np = (rest + 31) / 32, nz = (sp.kb + 31) / 32;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(sp.nq * (1 + np + nz)), dim3(256), 0, st, G, nc, sp, shift, L, Z, W,
-                       info, np, nz);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(sp.nq), dim3(256), 0, st, G, nc, sp, shift, L, Z, info);
     MDP_HIP(hipGetLastError());
 }
-void launch_chol_panel_batched(const CholBatchEntry* ent, int count, int max_roles, int* info, hipStream_t st) {
+void launch_chol_slabs(const double2* G, int nc, const CholStepDev& sp, double2* L, double2* Z, const double2* W,
+                       hipStream_t st) {
+    const int rest = nc - sp.kb - sp.wtot;
+    const int np = (rest + 31) / 32, nz = (sp.kb + 31) / 32;
+    if (np + nz == 0) return;
+    hipLaunchKernelGGL(chol_slab_kernel, dim3(sp.nq * (np + nz)), dim3(256), 0, st, G, nc, sp, L, Z, W, np, nz);
+    MDP_HIP(hipGetLastError());
+}
+void launch_chol_diag_batched(const CholBatchEntry* ent, int count, int* info, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(chol_panel_batched_kernel, dim3(max_roles, count), dim3(256), 0, st, ent, info);
+    hipLaunchKernelGGL(chol_diag_batched_kernel, dim3(count), dim3(256), 0, st, ent, info);
+    MDP_HIP(hipGetLastError());
+}
+void launch_chol_slabs_batched(const CholBatchEntry* ent, int count, int max_roles, hipStream_t st) {
+    if (count <= 0 || max_roles <= 0) return;
+    hipLaunchKernelGGL(chol_slab_batched_kernel, dim3(max_roles, count), dim3(256), 0, st, ent);
     MDP_HIP(hipGetLastError());
 }
 void launch_chol_update_batched(const CholBatchEntry* ent, int count, int max_tiles, hipStream_t st) {

@@ -80,7 +80,7 @@ double cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, i
             sp.kb = kb;
             sp.nq = (int)std::min<size_t>(CholStepDev::kMaxQ, widths.size() - q0);
             sp.off[0] = 0;
-            double panel_flops = 0.0, panel_bytes = 0.0;
+            double diag_flops = 0.0, diag_bytes = 0.0, panel_flops = 0.0, panel_bytes = 0.0;
             for (int q = 0; q < sp.nq; ++q) sp.off[q + 1] = sp.off[q] + widths[q0 + q];
             sp.wtot = sp.off[sp.nq];
             if (sp.wtot < 1 || kb + sp.wtot > nc) throw Error(MDP_ERR_ARG, "Cholesky plan does not cover the matrix");
@@ -89,12 +89,17 @@ double cholesky_and_inverse(double2* G, double2* L, double2* Linv, double2* W, i
                 // algorithmic flops (complex = 4 real multiply-adds): Cholesky and triangular inverse of the
                 // diagonal sub-block (4/3 b^3 each), its panel of L (8 rest b^2), its block row of Z (8 kb b^2)
                 const double b = widths[q0 + q];
-                panel_flops += 8.0 / 3.0 * b * b * b + 8.0 * rest * b * b + 8.0 * kb * b * b;
+                diag_flops += 8.0 / 3.0 * b * b * b;
+                diag_bytes += 16.0 * 2.0 * b * b;
+                panel_flops += 8.0 * rest * b * b + 8.0 * kb * b * b;
                 panel_bytes += 16.0 * (b * b + rest * b + 2.0 * kb * b);
             }
-            p.run("chol_panel", st, panel_flops, panel_bytes,
-                  [&] { launch_chol_panel(G, nc, sp, shift, L, Linv, W, info_dev, st); });
-            total += panel_flops;
+            p.run("chol_diag", st, diag_flops, diag_bytes,
+                  [&] { launch_chol_diag(G, nc, sp, shift, L, Linv, info_dev, st); });
+            if (rest > 0 || kb > 0)
+                p.run("chol_panel", st, panel_flops, panel_bytes,
+                      [&] { launch_chol_slabs(G, nc, sp, L, Linv, W, st); });
+            total += diag_flops + panel_flops;
             // then the trailing update (4 rest^2 w, lower half) and the inverse accumulation (8 rest (kb+w) w)
             if (rest > 0) {
                 const double uf = 4.0 * rest * rest * wt + 8.0 * rest * (kb + wt) * wt;
@@ -418,7 +423,7 @@ MFHost mf_plan(const PackedHost& h) {
         int max_e = 0;
         for (int v : t.by_height[hh]) max_e = std::max(max_e, nodes[v].e);
         for (int kb = 0; kb < max_e; kb += 64) {
-            MFHost::Step sp{(int)hh, (int)t.entry_node.size(), 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+            MFHost::Step sp{(int)hh, (int)t.entry_node.size(), 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             for (int v : t.by_height[hh]) {
                 const MFHost::Node& nd = nodes[v];
                 if (nd.e <= kb) continue;
@@ -427,10 +432,12 @@ MFHost mf_plan(const PackedHost& h) {
                 t.entry_node.push_back(v);
                 t.entry_kb.push_back(kb);
                 ++sp.count;
-                sp.max_roles = std::max(sp.max_roles, 1 + np + nz);
+                sp.max_roles = std::max(sp.max_roles, np + nz);
                 sp.max_tiles = std::max(sp.max_tiles, np * (np + 1) / 2 + np * nw);
                 const double W_ = w, R_ = rest, K_ = kb;
-                sp.panel_flops += 8.0 / 3.0 * W_ * W_ * W_ + 8.0 * R_ * W_ * W_ + 8.0 * K_ * W_ * W_;
+                sp.diag_flops += 8.0 / 3.0 * W_ * W_ * W_;
+                sp.diag_bytes += 16.0 * 2.0 * W_ * W_;
+                sp.panel_flops += 8.0 * R_ * W_ * W_ + 8.0 * K_ * W_ * W_;
                 sp.panel_bytes += 16.0 * (W_ * W_ + R_ * W_ + 2.0 * K_ * W_);
                 sp.update_flops += 4.0 * R_ * R_ * W_ + 8.0 * R_ * (K_ + W_) * W_;
                 sp.update_bytes += 16.0 * (R_ * R_ + 2.0 * R_ * W_ + 2.0 * R_ * (K_ + W_));
@@ -644,13 +651,17 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
                 });
                 for (; si < mf.steps.size() && mf.steps[si].height == (int)hh; ++si) {
                     const MFHost::Step& sp = mf.steps[si];
-                    ws.prof.run("chol_panel", st, sp.panel_flops, sp.panel_bytes, [&] {
-                        launch_chol_panel_batched(ent + sp.entry0, sp.count, sp.max_roles, &fl->info, st);
+                    ws.prof.run("chol_diag", st, sp.diag_flops, sp.diag_bytes, [&] {
+                        launch_chol_diag_batched(ent + sp.entry0, sp.count, &fl->info, st);
                     });
+                    if (sp.max_roles > 0)
+                        ws.prof.run("chol_panel", st, sp.panel_flops, sp.panel_bytes, [&] {
+                            launch_chol_slabs_batched(ent + sp.entry0, sp.count, sp.max_roles, st);
+                        });
                     ws.prof.run("chol_update", st, sp.update_flops, sp.update_bytes, [&] {
                         launch_chol_update_batched(ent + sp.entry0, sp.count, sp.max_tiles, st);
                     });
-                    chol_flops += sp.panel_flops + sp.update_flops;
+                    chol_flops += sp.diag_flops + sp.panel_flops + sp.update_flops;
                 }
             }
         }

@@ -39,8 +39,8 @@ struct MFHost {
     };
     // one batched Cholesky step: 64-column panel s of every front of one height with e > 64 s
     struct Step {
-        int height, entry0, count, max_roles, max_tiles;
-        double panel_flops, update_flops, panel_bytes, update_bytes;
+        int height, entry0, count, max_roles, max_tiles;   // max_roles: slab workgroups of one entry
+        double diag_flops, panel_flops, update_flops, diag_bytes, panel_bytes, update_bytes;
     };
     std::vector<Node> nodes;
     std::vector<std::vector<int>> by_height;   // nodes of each height (leaves: 0)

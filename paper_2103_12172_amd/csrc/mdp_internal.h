@@ -466,8 +466,12 @@ struct CholStepDev {
     int kb, nq, wtot;
     int off[kMaxQ + 1];
 };
-void launch_chol_panel(const double2* G, int nc, const CholStepDev& sp, double shift, double2* L, double2* Z,
-                       const double2* W, int* info, hipStream_t st);
+// diagonal sub-blocks of a step (L(q,q), Z(q,q) = L(q,q)^{-1}, breakdown to *info), then the
+// slabs: L(i,q) for the rows below the step and the block rows Z(q,j), j < kb
+void launch_chol_diag(const double2* G, int nc, const CholStepDev& sp, double shift, double2* L, double2* Z, int* info,
+                      hipStream_t st);
+void launch_chol_slabs(const double2* G, int nc, const CholStepDev& sp, double2* L, double2* Z, const double2* W,
+                       hipStream_t st);
 // One matrix's share of a batched Cholesky step: sub-block kb..kb+w-1 of the order-nc matrix G
 // (ld nc), its factor L, the inverse Z and the inverse's accumulator W (ld nc, columns < the
 // eliminated count); np = ceil((nc-kb-w)/32) row slabs, nz = ceil(kb/32) Z slabs, tiles of the
@@ -476,7 +480,8 @@ struct CholBatchEntry {
     double2 *G, *L, *Z, *W;
     int nc, kb, w, np, nz, tiles;
 };
-void launch_chol_panel_batched(const CholBatchEntry* ent, int count, int max_roles, int* info, hipStream_t st);
+void launch_chol_diag_batched(const CholBatchEntry* ent, int count, int* info, hipStream_t st);
+void launch_chol_slabs_batched(const CholBatchEntry* ent, int count, int max_roles, hipStream_t st);
 void launch_chol_update_batched(const CholBatchEntry* ent, int count, int max_tiles, hipStream_t st);
 // trailing Schur complement and inverse accumulation after the step kb .. kb+wtot-1
 void launch_chol_update(double2* G, int nc, int kb, int wtot, const double2* L, const double2* Z, double2* W,
