@@ -630,13 +630,120 @@ chol_slab_batched_kernel(const CholBatchEntry* __restrict__ ent) {
     chol_slab_body(e.G, e.nc, e.kb, e.kb + e.w, e.kb, e.w, e.L, e.Z, e.W, e.np, blockIdx.x);
 }
 
-// Update after the block step kb..r0-1 (r0 = kb + wtot): 32 x 32 tiles of
+// Update after the block step kb..r0-1 (r0 = kb + wtot): 64 x 64 tiles of
+//   the trailing Schur complement  G(i,j) -= sum_k L(i,k) conj(L(j,k)),  r0 <= j <= i (tile-wise lower),
+//   the inverse accumulation       W(i,j) -= sum_k L(i,k) Z(k,j),        i >= r0, j < r0,
+// k over the step's columns (for j in the step, Z(k,j) is the step's own block-diagonal
+// inverse and W starts from zero).  Computed transposed on the matrix cores,
+// C^T(j,i) = sum_k B(k,j) L(i,k) with B(k,j) = conj(L(j,k)) or Z(k,j): the result lanes
+// then hold consecutive rows i of a column j, so the read-modify-write of C is
+// coalesced, and both operands come straight from memory (16 consecutive rows of one
+// column per load; Z(k,j): 4 consecutive k of 16 columns), no LDS.  Four wavefronts, each
+// a 32 x 32 quarter of the tile as 2 x 2 blocks of 16 x 16, two k-steps of loads in flight.
+__device__ __attribute__((always_inline)) inline void chol_update64_body(double2* __restrict__ G, int nc, int kb,
+                                                                       int wtot, const double2* __restrict__ L,
+                                                                       const double2* __restrict__ Z,
+                                                                       double2* __restrict__ W, int bx) {
+    constexpr int BW = 2, TILE = 64;
+    const int r0 = kb + wtot, tid = threadIdx.x;
+    const int ntr = (nc - r0 + TILE - 1) / TILE;
+    int t = bx, i0, j0;
+    bool trail;
+    const int ntri = ntr * (ntr + 1) / 2;
+    if (t < ntri) {
+        int a = 0;
+        while ((a + 1) * (a + 2) / 2 <= t) ++a;
+        i0 = r0 + TILE * a;
+        j0 = r0 + TILE * (t - a * (a + 1) / 2);
+        trail = true;
+    } else {
+        t -= ntri;
+        i0 = r0 + TILE * (t % ntr);
+        j0 = TILE * (t / ntr);
+        trail = false;
+    }
+    const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
+    const int ib = i0 + 16 * BW * (wv & 1), jb = j0 + 16 * BW * (wv >> 1);
+    d4 cr[BW][BW], ci[BW][BW];
+#pragma unroll
+    for (int x = 0; x < BW; ++x)
+#pragma unroll
+        for (int y = 0; y < BW; ++y) { cr[x][y] = d4{0, 0, 0, 0}; ci[x][y] = d4{0, 0, 0, 0}; }
+    // operands of k-step ks (k = 4 ks + lane >> 4): A' (row j = jb + 16 tj + lane & 15),
+    // B' (column i = ib + 16 ti + lane & 15)
+    auto load = [&](int ks, double2* av, double2* bv) {
+        const int k = 4 * ks + lk;
+        const bool kin = k < wtot;
+#pragma unroll
+        for (int x = 0; x < BW; ++x) {
+            const int j = jb + 16 * x + lr, i = ib + 16 * x + lr;
+            if (trail) {
+                const double2 v = (kin && j < nc) ? L[j + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
+                av[x] = make_double2(v.x, -v.y);
+            } else {
+                av[x] = (kin && j < r0) ? Z[kb + k + (long)j * nc] : make_double2(0.0, 0.0);
+            }
+            bv[x] = (kin && i < nc) ? L[i + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
+        }
+    };
+    // stages of S k-steps, the next stage's loads in flight
+    constexpr int S = 2;
+    const int nks = (wtot + 3) / 4;
+    double2 a[S][BW], b[S][BW], na[S][BW], nb[S][BW];
+#pragma unroll
+    for (int u = 0; u < S; ++u) load(u, a[u], b[u]);
+    for (int ks = 0; ks < nks; ks += S) {
+        if (ks + S < nks) {
+#pragma unroll
+            for (int u = 0; u < S; ++u) load(ks + S + u, na[u], nb[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+#pragma unroll
+            for (int x = 0; x < BW; ++x)
+#pragma unroll
+                for (int y = 0; y < BW; ++y) {   // D'(j, i) += A'(j, k) B'(k, i), complex
+                    cr[x][y] = mfma64(a[u][x].x, b[u][y].x, cr[x][y]);
+                    cr[x][y] = mfma64(-a[u][x].y, b[u][y].y, cr[x][y]);
+                    ci[x][y] = mfma64(a[u][x].x, b[u][y].y, ci[x][y]);
+                    ci[x][y] = mfma64(a[u][x].y, b[u][y].x, ci[x][y]);
+                }
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+#pragma unroll
+            for (int x = 0; x < BW; ++x) { a[u][x] = na[u][x]; b[u][x] = nb[u][x]; }
+    }
+    // result lane: rows j = jb + 16 x + (lane >> 4) + 4 r, column i = ib + 16 y + lane & 15
+    double2* C = trail ? G : W;
+#pragma unroll
+    for (int x = 0; x < BW; ++x)
+#pragma unroll
+        for (int y = 0; y < BW; ++y) {
+            const int i = ib + 16 * y + lr;
+            bool ok[4];
+            double2 cv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {   // every load before the first wait
+                const int j = jb + 16 * x + lk + 4 * r;
+                ok[r] = i < nc && (trail ? (j < nc && j <= i) : j < r0);
+                cv[r] = ok[r] ? C[i + (long)j * nc] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jb + 16 * x + lk + 4 * r;
+                if (ok[r]) C[i + (long)j * nc] = make_double2(cv[r].x - cr[x][y][r], cv[r].y - ci[x][y][r]);
+            }
+        }
+}
+
+
+// The same update in 32 x 32 tiles (small matrices: four times the workgroups) of
 //   the trailing Schur complement  G(i,j) -= sum_k L(i,k) conj(L(j,k)),  r0 <= j <= i (tile-wise lower),
 //   the inverse accumulation       W(i,j) -= sum_k L(i,k) Z(k,j),        i >= r0, j < r0,
 // k over the step's columns in chunks of 64 (for j in the step, Z(k,j) is the
 // step's own block-diagonal inverse and W starts from zero).  Both operands
 // staged in LDS; 2 x 2 entries per thread.
-__device__ inline void chol_update_body(double2* __restrict__ G, int nc, int kb, int wtot,
+__device__ __attribute__((always_inline)) inline void chol_update32_body(double2* __restrict__ G, int nc, int kb, int wtot,
                                         const double2* __restrict__ L, const double2* __restrict__ Z,
                                         double2* __restrict__ W, int ntr, int bx) {
     __shared__ double2 A[64][33];   // A[k][r] = L(i0 + r, k0 + k)
@@ -715,19 +822,23 @@ __device__ inline void chol_update_body(double2* __restrict__ G, int nc, int kb,
 }
 
 
-__global__ void __launch_bounds__(256)
+template <bool WIDE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 3 : 1)))
 chol_update_kernel(double2* __restrict__ G, int nc, int kb, int wtot, const double2* __restrict__ L,
-                   const double2* __restrict__ Z, double2* __restrict__ W, int ntr) {
-    chol_update_body(G, nc, kb, wtot, L, Z, W, ntr, blockIdx.x);
+                   const double2* __restrict__ Z, double2* __restrict__ W) {
+    if constexpr (WIDE) chol_update64_body(G, nc, kb, wtot, L, Z, W, blockIdx.x);
+    else chol_update32_body(G, nc, kb, wtot, L, Z, W, (nc - kb - wtot + 31) / 32, blockIdx.x);
 }
 
 // The update of one step of several matrices at once (entry blockIdx.y; workgroups past
 // the entry's tiles exit).
-__global__ void __launch_bounds__(256)
+template <bool WIDE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE ? 3 : 1)))
 chol_update_batched_kernel(const CholBatchEntry* __restrict__ ent) {
     const CholBatchEntry e = ent[blockIdx.y];
-    if ((int)blockIdx.x >= e.tiles) return;
-    chol_update_body(e.G, e.nc, e.kb, e.w, e.L, e.Z, e.W, e.np, blockIdx.x);
+    if ((int)blockIdx.x >= chol_update_tiles(e.nc, e.kb, e.w, WIDE ? 64 : 32)) return;
+    if constexpr (WIDE) chol_update64_body(e.G, e.nc, e.kb, e.w, e.L, e.Z, e.W, blockIdx.x);
+    else chol_update32_body(e.G, e.nc, e.kb, e.w, e.L, e.Z, e.W, e.np, blockIdx.x);
 }
 
 // max and min Cholesky pivot ratio estimate: diag of L (ld) -> out[0] = max |L_ii|^2, out[1] = min |L_ii|^2
@@ -919,38 +1030,53 @@ struct PackedDesc {
     const long* roff;          // first row of subdomain i in the stacked right-hand side
 };
 
-__global__ void assemble_packed_kernel(PackedDesc d, double2* __restrict__ Ap) {
+// packed column pc at row r: its (at most two) Q columns combined with their coefficients
+__device__ inline double2 packed_value(const PackedDesc& d, const double2* __restrict__ Q, int m, int4 cm, double2 wa,
+                                       double2 wb, int r) {
+    double2 v = make_double2(0.0, 0.0);
+    if (cm.x >= 0) {
+        const double2 q = Q[r + (long)cm.x * m];
+        v.x += wa.x * q.x - wa.y * q.y;
+        v.y += wa.x * q.y + wa.y * q.x;
+    }
+    if (cm.y >= 0) {
+        const double2 q = Q[r + (long)cm.y * m];
+        v.x += wb.x * q.x - wb.y * q.y;
+        v.y += wb.x * q.y + wb.y * q.x;
+    }
+    return v;
+}
+
+// the packed blocks, each column divided by the norm of its global column
+__global__ void assemble_packed_kernel(PackedDesc d, const double* __restrict__ norms, double2* __restrict__ Ap) {
     const int pc = blockIdx.y;
     const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
     const int4 cm = d.pc_cols[pc];
     const double2 wa = d.pc_coef[2 * pc], wb = d.pc_coef[2 * pc + 1];
+    const double f = 1.0 / norms[d.pc_gcol[pc]];
     const double2* Q = d.Q[i];
     double2* out = Ap + d.off[i] + (long)p * m;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < m; r += gridDim.x * blockDim.x) {
-        double2 v = make_double2(0.0, 0.0);
-        if (cm.x >= 0) {
-            const double2 q = Q[r + (long)cm.x * m];
-            v.x += wa.x * q.x - wa.y * q.y;
-            v.y += wa.x * q.y + wa.y * q.x;
-        }
-        if (cm.y >= 0) {
-            const double2 q = Q[r + (long)cm.y * m];
-            v.x += wb.x * q.x - wb.y * q.y;
-            v.y += wb.x * q.y + wb.y * q.x;
-        }
-        out[r] = v;
+        const double2 v = packed_value(d, Q, m, cm, wa, wb, r);
+        out[r] = make_double2(v.x * f, v.y * f);
     }
 }
 
-// norms2[gcol] += ||packed column||^2 (one workgroup per packed column)
-__global__ void __launch_bounds__(256) packed_colnorm2_kernel(PackedDesc d, const double2* __restrict__ Ap,
-                                                              double* norms2) {
+// norms2[gcol] += ||packed column||^2 from the Q columns it combines (one workgroup per
+// packed column; a global column has at most two packed columns, so the atomic sum does
+// not depend on their order)
+__global__ void __launch_bounds__(256) packed_colnorm2_kernel(PackedDesc d, double* norms2) {
     const int pc = blockIdx.x;
-    const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
-    const double2* col = Ap + d.off[i] + (long)p * m;
+    const int i = d.pc_sub[pc], m = d.m[i];
+    const int4 cm = d.pc_cols[pc];
+    const double2 wa = d.pc_coef[2 * pc], wb = d.pc_coef[2 * pc + 1];
+    const double2* Q = d.Q[i];
     __shared__ double red[256];
     double s = 0.0;
-    for (int r = threadIdx.x; r < m; r += 256) s += col[r].x * col[r].x + col[r].y * col[r].y;
+    for (int r = threadIdx.x; r < m; r += 256) {
+        const double2 v = packed_value(d, Q, m, cm, wa, wb, r);
+        s += v.x * v.x + v.y * v.y;
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -968,17 +1094,6 @@ __global__ void finalize_norms_kernel(int n, const double* __restrict__ norms2, 
     if (!(v < 1e300)) { atomicOr(flags, 2); norms[c] = 1.0; return; }
     if (!(v > 0.0)) { atomicOr(flags, 1); norms[c] = 1.0; return; }
     norms[c] = sqrt(v);
-}
-
-__global__ void packed_scale_kernel(PackedDesc d, double2* Ap, const double* __restrict__ norms) {
-    const int pc = blockIdx.y;
-    const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
-    const double f = 1.0 / norms[d.pc_gcol[pc]];
-    double2* col = Ap + d.off[i] + (long)p * m;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < m; r += gridDim.x * blockDim.x) {
-        col[r].x *= f;
-        col[r].y *= f;
-    }
 }
 
 // y[gcol] += alpha * A_i(:, p)^* v_i (one workgroup per packed column)
@@ -1384,19 +1499,24 @@ void launch_chol_slabs_batched(const CholBatchEntry* ent, int count, int max_rol
     hipLaunchKernelGGL(chol_slab_batched_kernel, dim3(max_roles, count), dim3(256), 0, st, ent);
     MDP_HIP(hipGetLastError());
 }
-void launch_chol_update_batched(const CholBatchEntry* ent, int count, int max_tiles, hipStream_t st) {
-    if (count <= 0 || max_tiles <= 0) return;
-    hipLaunchKernelGGL(chol_update_batched_kernel, dim3(max_tiles, count), dim3(256), 0, st, ent);
+// 64 x 64 tiles when they still give every CU a few workgroups, else 32 x 32
+void launch_chol_update_batched(const CholBatchEntry* ent, int count, int max_tiles64, long tiles64, int max_tiles32,
+                                hipStream_t st) {
+    if (count <= 0 || max_tiles32 <= 0) return;
+    if (tiles64 >= kUpdWideMin)
+        hipLaunchKernelGGL(chol_update_batched_kernel<true>, dim3(max_tiles64, count), dim3(256), 0, st, ent);
+    else
+        hipLaunchKernelGGL(chol_update_batched_kernel<false>, dim3(max_tiles32, count), dim3(256), 0, st, ent);
     MDP_HIP(hipGetLastError());
 }
 void launch_chol_update(double2* G, int nc, int kb, int wtot, const double2* L, const double2* Z, double2* W,
                         hipStream_t st) {
-    const int rest = nc - kb - wtot;
-    if (rest <= 0) return;
-    const int np = (rest + 31) / 32;
-    const int nw = (kb + wtot + 31) / 32;   // W column tiles, the step's own columns included
-    const int tiles = np * (np + 1) / 2 + np * nw;
-    hipLaunchKernelGGL(chol_update_kernel, dim3(tiles), dim3(256), 0, st, G, nc, kb, wtot, L, Z, W, np);
+    const int t64 = chol_update_tiles(nc, kb, wtot, 64), t32 = chol_update_tiles(nc, kb, wtot, 32);
+    if (t32 <= 0) return;
+    if (t64 >= kUpdWideMin)
+        hipLaunchKernelGGL(chol_update_kernel<true>, dim3(t64), dim3(256), 0, st, G, nc, kb, wtot, L, Z, W);
+    else
+        hipLaunchKernelGGL(chol_update_kernel<false>, dim3(t32), dim3(256), 0, st, G, nc, kb, wtot, L, Z, W);
     MDP_HIP(hipGetLastError());
 }
 void launch_assemble_qbar(const double2* const* Qsrc, const int* qld, int n_sub, const int* row_off, int total_rows,
@@ -1450,29 +1570,22 @@ void launch_scale_cols_checked(double2* A, int m, int n, int lda, const double* 
     MDP_HIP(hipGetLastError());
 }
 
-void launch_assemble_packed(const PackedDevice& d, int total_pc, int max_m, double2* Ap, hipStream_t st) {
+void launch_assemble_packed(const PackedDevice& d, int total_pc, int max_m, const double* norms, double2* Ap,
+                            hipStream_t st) {
     PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
     dim3 grid(std::max(1, std::min((max_m + 255) / 256, 64)), total_pc);
-    hipLaunchKernelGGL(assemble_packed_kernel, grid, dim3(256), 0, st, pd, Ap);
+    hipLaunchKernelGGL(assemble_packed_kernel, grid, dim3(256), 0, st, pd, norms, Ap);
     MDP_HIP(hipGetLastError());
 }
 
-void launch_packed_colnorm2(const PackedDevice& d, int total_pc, const double2* Ap, double* norms2, hipStream_t st) {
+void launch_packed_colnorm2(const PackedDevice& d, int total_pc, double* norms2, hipStream_t st) {
     PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
-    hipLaunchKernelGGL(packed_colnorm2_kernel, dim3(total_pc), dim3(256), 0, st, pd, Ap, norms2);
+    hipLaunchKernelGGL(packed_colnorm2_kernel, dim3(total_pc), dim3(256), 0, st, pd, norms2);
     MDP_HIP(hipGetLastError());
 }
 
 void launch_finalize_norms(int n, const double* norms2, double* norms, int* flags, hipStream_t st) {
     hipLaunchKernelGGL(finalize_norms_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, norms2, norms, flags);
-    MDP_HIP(hipGetLastError());
-}
-
-void launch_packed_scale(const PackedDevice& d, int total_pc, int max_m, double2* Ap, const double* norms,
-                         hipStream_t st) {
-    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
-    dim3 grid(std::max(1, std::min((max_m + 255) / 256, 64)), total_pc);
-    hipLaunchKernelGGL(packed_scale_kernel, grid, dim3(256), 0, st, pd, Ap, norms);
     MDP_HIP(hipGetLastError());
 }
 

@@ -423,17 +423,19 @@ MFHost mf_plan(const PackedHost& h) {
         int max_e = 0;
         for (int v : t.by_height[hh]) max_e = std::max(max_e, nodes[v].e);
         for (int kb = 0; kb < max_e; kb += 64) {
-            MFHost::Step sp{(int)hh, (int)t.entry_node.size(), 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            MFHost::Step sp{(int)hh, (int)t.entry_node.size(), 0, 0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             for (int v : t.by_height[hh]) {
                 const MFHost::Node& nd = nodes[v];
                 if (nd.e <= kb) continue;
                 const int f = nd.e + nd.b, w = std::min(64, nd.e - kb), rest = f - kb - w;
-                const int np = (rest + 31) / 32, nz = (kb + 31) / 32, nw = (kb + w + 31) / 32;
+                const int np = (rest + 31) / 32, nz = (kb + 31) / 32;
                 t.entry_node.push_back(v);
                 t.entry_kb.push_back(kb);
                 ++sp.count;
                 sp.max_roles = std::max(sp.max_roles, np + nz);
-                sp.max_tiles = std::max(sp.max_tiles, np * (np + 1) / 2 + np * nw);
+                sp.max_tiles64 = std::max(sp.max_tiles64, chol_update_tiles(f, kb, w, 64));
+                sp.max_tiles32 = std::max(sp.max_tiles32, chol_update_tiles(f, kb, w, 32));
+                sp.tiles64 += chol_update_tiles(f, kb, w, 64);
                 const double W_ = w, R_ = rest, K_ = kb;
                 sp.diag_flops += 8.0 / 3.0 * W_ * W_ * W_;
                 sp.diag_bytes += 16.0 * 2.0 * W_ * W_;
@@ -552,9 +554,8 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
         for (size_t q = 0; q < ent.size(); ++q) {
             const MFHost::Node& a = mf.nodes[mf.entry_node[q]];
             const int f = a.e + a.b, kb = mf.entry_kb[q], wd = std::min(64, a.e - kb), rest = f - kb - wd;
-            const int np = (rest + 31) / 32, nw = (kb + wd + 31) / 32;
-            ent[q] = CholBatchEntry{arena + a.G, arena + a.L, arena + a.Z, arena + a.W, f, kb, wd, np, (kb + 31) / 32,
-                                    np * (np + 1) / 2 + np * nw};
+            const int np = (rest + 31) / 32;
+            ent[q] = CholBatchEntry{arena + a.G, arena + a.L, arena + a.Z, arena + a.W, f, kb, wd, np, (kb + 31) / 32};
         }
         t.mf_steps = blob.put(ent);
     }
@@ -602,12 +603,11 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     MDP_HIP(hipMemsetAsync(fl, 0, sizeof(PackedFlags), st));
     double chol_flops = 0.0;
     if (!reuse) {
-        // packed blocks, equilibrated columns
-        launch_assemble_packed(d, npc, h.max_m, Ap, st);
+        // packed blocks, equilibrated columns (norms from Q, then one assembling pass)
         MDP_HIP(hipMemsetAsync(norms2, 0, nc * sizeof(double), st));
-        launch_packed_colnorm2(d, npc, Ap, norms2, st);
+        launch_packed_colnorm2(d, npc, norms2, st);
         launch_finalize_norms(nc, norms2, norms, &fl->badcol, st);
-        launch_packed_scale(d, npc, h.max_m, Ap, norms, st);
+        launch_assemble_packed(d, npc, h.max_m, norms, Ap, st);
         // Gram matrix (multifrontal: the per-subdomain blocks stay apart)
         if (!mfr) MDP_HIP(hipMemsetAsync(G, 0, nn * sizeof(double2), st));
         {
@@ -659,7 +659,8 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
                             launch_chol_slabs_batched(ent + sp.entry0, sp.count, sp.max_roles, st);
                         });
                     ws.prof.run("chol_update", st, sp.update_flops, sp.update_bytes, [&] {
-                        launch_chol_update_batched(ent + sp.entry0, sp.count, sp.max_tiles, st);
+                        launch_chol_update_batched(ent + sp.entry0, sp.count, sp.max_tiles64, sp.tiles64,
+                                                   sp.max_tiles32, st);
                     });
                     chol_flops += sp.diag_flops + sp.panel_flops + sp.update_flops;
                 }

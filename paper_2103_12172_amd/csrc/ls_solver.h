@@ -39,7 +39,9 @@ struct MFHost {
     };
     // one batched Cholesky step: 64-column panel s of every front of one height with e > 64 s
     struct Step {
-        int height, entry0, count, max_roles, max_tiles;   // max_roles: slab workgroups of one entry
+        int height, entry0, count, max_roles;   // max_roles: slab workgroups of one entry
+        int max_tiles64, max_tiles32;           // update workgroups of one entry (64 x 64, 32 x 32 tiles)
+        long tiles64;                           // 64 x 64 update tiles of all entries
         double diag_flops, panel_flops, update_flops, diag_bytes, panel_bytes, update_bytes;
     };
     std::vector<Node> nodes;

@@ -474,15 +474,23 @@ void launch_chol_slabs(const double2* G, int nc, const CholStepDev& sp, double2*
                        hipStream_t st);
 // One matrix's share of a batched Cholesky step: sub-block kb..kb+w-1 of the order-nc matrix G
 // (ld nc), its factor L, the inverse Z and the inverse's accumulator W (ld nc, columns < the
-// eliminated count); np = ceil((nc-kb-w)/32) row slabs, nz = ceil(kb/32) Z slabs, tiles of the
-// update = np(np+1)/2 + np ceil((kb+w)/32).
+// eliminated count); np = ceil((nc-kb-w)/32) row slabs, nz = ceil(kb/32) Z slabs.
+// workgroups of the update after the step kb..kb+w-1 of an order-nc matrix: tile x tile tiles
+// of the trailing lower part and of the inverse accumulation (columns < kb + w)
+__host__ __device__ inline int chol_update_tiles(int nc, int kb, int w, int tile) {
+    const int ntr = (nc - kb - w + tile - 1) / tile, nw = (kb + w + tile - 1) / tile;
+    return ntr * (ntr + 1) / 2 + ntr * nw;
+}
+// the update takes 64 x 64 tiles from this many workgroups of that size on (four per CU)
+constexpr long kUpdWideMin = 1024;
 struct CholBatchEntry {
     double2 *G, *L, *Z, *W;
-    int nc, kb, w, np, nz, tiles;
+    int nc, kb, w, np, nz;
 };
 void launch_chol_diag_batched(const CholBatchEntry* ent, int count, int* info, hipStream_t st);
 void launch_chol_slabs_batched(const CholBatchEntry* ent, int count, int max_roles, hipStream_t st);
-void launch_chol_update_batched(const CholBatchEntry* ent, int count, int max_tiles, hipStream_t st);
+void launch_chol_update_batched(const CholBatchEntry* ent, int count, int max_tiles64, long tiles64, int max_tiles32,
+                                hipStream_t st);
 // trailing Schur complement and inverse accumulation after the step kb .. kb+wtot-1
 void launch_chol_update(double2* G, int nc, int kb, int wtot, const double2* L, const double2* Z, double2* W,
                         hipStream_t st);
@@ -513,11 +521,13 @@ struct PackedDevice {
     const int* gc_start = nullptr;   // global column g: its packed columns gc_list[gc_start[g] .. gc_start[g+1]-1]
     const int* gc_list = nullptr;
 };
-void launch_assemble_packed(const PackedDevice& d, int total_pc, int max_m, double2* Ap, hipStream_t st);
-void launch_packed_colnorm2(const PackedDevice& d, int total_pc, const double2* Ap, double* norms2, hipStream_t st);
+// column equilibration of the packed blocks: norms2[g] += ||packed columns of g||^2 (read from
+// Q), norms = sqrt(norms2) (zero / non-finite raise flag bits 1 / 2), then the blocks
+// assembled with every column divided by its global column's norm
+void launch_packed_colnorm2(const PackedDevice& d, int total_pc, double* norms2, hipStream_t st);
 void launch_finalize_norms(int n, const double* norms2, double* norms, int* flags, hipStream_t st);
-void launch_packed_scale(const PackedDevice& d, int total_pc, int max_m, double2* Ap, const double* norms,
-                         hipStream_t st);
+void launch_assemble_packed(const PackedDevice& d, int total_pc, int max_m, const double* norms, double2* Ap,
+                            hipStream_t st);
 void launch_packed_ahx(const PackedDevice& d, int total_pc, const double2* Ap, const double2* v, double2 alpha,
                        double2* y, hipStream_t st);
 void launch_packed_ax(const PackedDevice& d, int n_sub, int max_m, int max_s, const double2* Ap, const double2* x,
