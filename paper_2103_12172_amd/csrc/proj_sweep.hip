@@ -193,12 +193,15 @@ template <class T, int L>
 struct SweepLds {
     static constexpr int K = FUSED_K;
     static constexpr int row_bytes = 64 * L * 2 * (int)sizeof(T);
+    static constexpr int lane_bytes = L * 2 * (int)sizeof(T);   // a lane's factors of one row
+    static constexpr int units = lane_bytes > 16 ? lane_bytes / 16 : 1;   // staged in 16-byte units
     static constexpr int fac_bytes = K * row_bytes;              // one buffer of factor rows
     static constexpr int ring_bytes_per_col = K * 4 * (int)sizeof(T);
     static constexpr int ring_bytes = 4 * ring_bytes_per_col;    // NW <= 4 columns
     static constexpr int bytes = 2 * (fac_bytes + ring_bytes);
     static_assert(ring_bytes <= 1024, "a segment's ring rows are staged by one 1 KB transfer");
     static_assert(fac_bytes % 1024 == 0, "factor rows are staged in 1 KB transfers");
+    static_assert(lane_bytes <= 16 || units * 16 == lane_bytes, "a lane's factors are whole 16-byte units");
 };
 
 __device__ inline void lds_dma16(const void* src, void* lds_dst) {
@@ -295,12 +298,19 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
     // columns in one transfer by wavefront 0
     char* const fac_buf = lds;
     char* const ring_buf = lds + 2 * S::fac_bytes;
+    // A row whose lane share exceeds 16 bytes is staged unit-major: with U 16-byte units per lane,
+    // LDS unit u * 64 + j of a row holds lane j's unit u, so that each of a lane's U reads below is
+    // contiguous over the wavefront (no LDS bank conflicts); shares of 8 or 16 bytes are read
+    // contiguously as they are.
+    constexpr int U = S::units;
+    constexpr bool unit_major = S::lane_bytes > 16;
     auto stage = [&](int s, int sb) {
         const int mb = m0 + s * K;
         char* fdst = fac_buf + sb * S::fac_bytes;
         for (int ch = wave; ch < S::fac_bytes / 1024; ch += NW) {
             const int o = ch * 1024 + lane * 16;
-            const int i = o / S::row_bytes, cb = o - i * S::row_bytes;
+            const int i = o / S::row_bytes, p = (o - i * S::row_bytes) / 16;
+            const int cb = unit_major ? ((p & 63) * U + (p >> 6)) * 16 : p * 16;   // the global unit it holds
             const int m = mb + i;
             lds_dma16((m < t ? rtab + (long)m * LW * 2 * sizeof(T) : twrow) + cb, fdst + ch * 1024);
         }
@@ -317,7 +327,18 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
     };
     // factor row i of buffer sb for the lane's columns, and the column's ring pair of row i
     auto fac = [&](int sb, int i) -> V {
-        return *reinterpret_cast<const V*>(fac_buf + sb * S::fac_bytes + i * S::row_bytes + lane * (2 * L * sizeof(T)));
+        if constexpr (!unit_major)
+            return *reinterpret_cast<const V*>(fac_buf + sb * S::fac_bytes + i * S::row_bytes + lane * S::lane_bytes);
+        typedef T Unit __attribute__((ext_vector_type(16 / sizeof(T))));
+        const char* row = fac_buf + sb * S::fac_bytes + i * S::row_bytes + lane * 16;
+        V f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const Unit x = *reinterpret_cast<const Unit*>(row + u * 64 * 16);
+#pragma unroll
+            for (int e = 0; e < (int)(16 / sizeof(T)); ++e) f[u * (16 / sizeof(T)) + e] = x[e];
+        }
+        return f;
     };
     auto ring = [&](int sb, int i, T& gA, T& gB) {
         const T* r = reinterpret_cast<const T*>(ring_buf + sb * S::ring_bytes + wave * S::ring_bytes_per_col) +
