@@ -51,8 +51,11 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
     constexpr int WT = ZBM / 2;          // wave tile (2 x 2 waves)
     constexpr int TT = WT / 16;          // 16x16 MFMA blocks per wave side
     constexpr int NL = ZBM * ZBK / 256;  // complex elements per thread per tile
-    __shared__ double Ar[2][ZBK][ZBM + 2], Ai[2][ZBK][ZBM + 2];
-    __shared__ double Br[2][ZBK][ZBN + 2], Bi[2][ZBK][ZBN + 2];
+    // operands as interleaved complex (one 16-byte read per operand and lane: a quarter-wave
+    // reads 16 consecutive entries, all 64 banks once; the row padding keeps the k-major
+    // stores conflict-free too)
+    __shared__ double2 As[2][ZBK][ZBM + 1];
+    __shared__ double2 Bs[2][ZBK][ZBN + 1];
     const int tid = threadIdx.x;
     const int mt = blockIdx.x % mtiles, nt = blockIdx.x / mtiles;
     const int kz = blockIdx.y;
@@ -102,11 +105,9 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
             int idx = tid + v * 256;
             int i, kk, j;
             if (opA == 0) { i = idx % ZBM; kk = idx / ZBM; } else { kk = idx % ZBK; i = idx / ZBK; }
-            Ar[buf][kk][i] = ra[v].x;
-            Ai[buf][kk][i] = ra[v].y;
+            As[buf][kk][i] = ra[v];
             if (opB == 0) { kk = idx % ZBK; j = idx / ZBK; } else { j = idx % ZBN; kk = idx / ZBN; }
-            Br[buf][kk][j] = rb[v].x;
-            Bi[buf][kk][j] = rb[v].y;
+            Bs[buf][kk][j] = rb[v];
         }
     };
 
@@ -124,10 +125,12 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
             double ar[TT], ai[TT], br[TT], bi[TT];
 #pragma unroll
             for (int i = 0; i < TT; ++i) {
-                ar[i] = Ar[buf][kk * 4 + lk][wm * WT + i * 16 + lr];
-                ai[i] = Ai[buf][kk * 4 + lk][wm * WT + i * 16 + lr];
-                br[i] = Br[buf][kk * 4 + lk][wn * WT + i * 16 + lr];
-                bi[i] = Bi[buf][kk * 4 + lk][wn * WT + i * 16 + lr];
+                const double2 a = As[buf][kk * 4 + lk][wm * WT + i * 16 + lr];
+                const double2 b = Bs[buf][kk * 4 + lk][wn * WT + i * 16 + lr];
+                ar[i] = a.x;
+                ai[i] = a.y;
+                br[i] = b.x;
+                bi[i] = b.y;
             }
 #pragma unroll
             for (int i = 0; i < TT; ++i)
