@@ -100,6 +100,31 @@ __device__ inline void fold_rhs_body(const SrcEval& ev, const Fold& f, int plane
     if (planes == 2) out[o + (long)bd.nr * W] = (T)v.im;
 }
 
+// Both folded entries that grid columns q and n - q feed, from one evaluation of each
+// (column j < P1 of the odd-mode block: e_q, q = j + 1; column P1 + j < W of the even-mode
+// block: o_q), and the zero padding of both blocks.
+template <class T>
+__device__ inline void fold_rhs_pair_body(const SrcEval& ev, const Fold& f, int planes, Band bd, T* __restrict__ out,
+                                          int j, int m, int b) {
+    const int n = f.n, p = f.p, W = f.W, q = j + 1;
+    C64 e = {0.0, 0.0}, o = {0.0, 0.0};
+    if (q < p) {
+        const C64 g1 = ev.rhs(b, m, q), g2 = ev.rhs(b, m, n - q);
+        e = cadd(g1, g2);
+        o = csub(g1, g2);
+    } else if (q == p) {
+        e = ev.rhs(b, m, p);
+    }
+    const long o1 = (((long)b * planes) * bd.nr + (m - bd.r0)) * W + j;
+    out[o1] = (T)e.re;
+    if (planes == 2) out[o1 + (long)bd.nr * W] = (T)e.im;
+    if (f.P1 + j < W) {
+        const long o2 = o1 + f.P1;
+        out[o2] = (T)o.re;
+        if (planes == 2) out[o2 + (long)bd.nr * W] = (T)o.im;
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256)
 fold_rhs_kernel(SrcEval ev, Fold f, int planes, Band bd, T* __restrict__ out) {
@@ -1176,8 +1201,8 @@ fold_rhs_jobs_kernel(const SolveJob* __restrict__ jobs, int njobs) {
     const SrcEval ev{J.src, J.f.n, J.sc};
     const int r1 = min(J.bd.nr, (int)(blockIdx.x + 1) * kJobRows);
     for (int r = blockIdx.x * kJobRows; r < r1; ++r)
-        for (int c = threadIdx.x; c < J.f.W; c += blockDim.x)
-            fold_rhs_body<double>(ev, J.f, 2, J.bd, J.A, c, J.bd.r0 + r, blockIdx.y - J.b0);
+        for (int j = threadIdx.x; j < J.f.P1; j += blockDim.x)
+            fold_rhs_pair_body<double>(ev, J.f, 2, J.bd, J.A, j, J.bd.r0 + r, blockIdx.y - J.b0);
 }
 
 __global__ void __launch_bounds__(256)
