@@ -19,10 +19,23 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ inline d4 mfma64(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
+// The dispatcher deals consecutive workgroups round-robin to the eight XCDs.  For a batch
+// launch (x, y = tile of a batch entry, z = entry) renumber the workgroups so that XCD x
+// runs the x-th eighth of the launch in order (a remainder keeps its place): every tile of
+// one entry then runs on the same XCD, and the tiles sharing an operand block read it
+// through one L2 (dealt as launched, every XCD would stream every entry's operands).
+__device__ inline long xcd_grouped(long lin, long total) {
+    const long per = total >> 3;
+    return lin < per * 8 ? (lin & 7) * per + (lin >> 3) : lin;
+}
+
 // C(M x N) (+)= op(A)(M x K) op(B)(K x N), column-major, op in {N, C}.
-// Workgroup tile 64 x 64, 4 waves of 32 x 32, K step 16; the K range of this
-// workgroup is [kz*kchunk, min(K, (kz+1)*kchunk)).  With split-K (nsplit > 1)
-// raw products go to P[kz] and a second kernel reduces them.
+// Workgroup tile ZBM x ZBM (32 or 64), 4 waves of ZBM/2 x ZBM/2, K step 16; the K
+// range of this workgroup is [kz*kchunk, min(K, (kz+1)*kchunk)).  With split-K
+// (nsplit > 1) raw products go to P[kz] and a second kernel reduces them.
+// Each complex product takes three real MFMA products instead of four (the 3M form:
+// ar br, ai bi and (ar + ai)(br + bi); re = P1 - P2, im = P3 - P1 - P2), normwise as
+// accurate as the four-product form up to a small constant factor.
 constexpr int ZBK = 16;
 
 // tri: 0 = full; 1 = only tiles touching the lower triangle of C are computed
@@ -36,8 +49,15 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
              const double2* __restrict__ B, int ldb, double2* __restrict__ C, int ldc, double2 alpha, double2 beta,
              int kchunk, double2* __restrict__ P, long pstride, int mtiles, int tri, const ZBatch* __restrict__ zb) {
     constexpr int ZBN = ZBM;
-    if (zb) {
-        const ZBatch e = zb[blockIdx.z];
+    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    if (zb) {   // every tile of one Gram product on one XCD
+        const long w = xcd_grouped(bx + (long)gridDim.x * (by + (long)gridDim.y * bz),
+                                   (long)gridDim.x * gridDim.y * gridDim.z);
+        bx = (int)(w % gridDim.x);
+        const long r = w / gridDim.x;
+        by = (int)(r % gridDim.y);
+        bz = (int)(r / gridDim.y);
+        const ZBatch e = zb[bz];
         A = B = e.A;
         M = N = e.n;
         K = e.k;
@@ -46,7 +66,7 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
         P += e.poff;
         pstride = (long)e.n * e.n;
         mtiles = (e.n + ZBM - 1) / ZBM;
-        if ((int)blockIdx.x >= mtiles * mtiles) return;
+        if (bx >= mtiles * mtiles) return;
     }
     constexpr int WT = ZBM / 2;          // wave tile (2 x 2 waves)
     constexpr int TT = WT / 16;          // 16x16 MFMA blocks per wave side
@@ -57,8 +77,8 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
     __shared__ double2 As[2][ZBK][ZBM + 1];
     __shared__ double2 Bs[2][ZBK][ZBN + 1];
     const int tid = threadIdx.x;
-    const int mt = blockIdx.x % mtiles, nt = blockIdx.x / mtiles;
-    const int kz = blockIdx.y;
+    const int mt = bx % mtiles, nt = bx / mtiles;
+    const int kz = by;
     const int m0 = mt * ZBM, n0 = nt * ZBN;
     if (tri == 1 && m0 + ZBM <= n0) return;
     const int kb = kz * kchunk;
@@ -67,11 +87,11 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
     const int wave = tid >> 6, lane = tid & 63, wm = wave >> 1, wn = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
 
-    d4 cr[TT][TT], ci[TT][TT];
+    d4 c1[TT][TT], c2[TT][TT], c3[TT][TT];
 #pragma unroll
     for (int i = 0; i < TT; ++i)
 #pragma unroll
-        for (int j = 0; j < TT; ++j) { cr[i][j] = d4{0, 0, 0, 0}; ci[i][j] = d4{0, 0, 0, 0}; }
+        for (int j = 0; j < TT; ++j) { c1[i][j] = d4{0, 0, 0, 0}; c2[i][j] = d4{0, 0, 0, 0}; c3[i][j] = d4{0, 0, 0, 0}; }
 
     double2 ra[NL], rb[NL];
     auto gload = [&](int k0) {
@@ -136,10 +156,9 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
             for (int i = 0; i < TT; ++i)
 #pragma unroll
                 for (int j = 0; j < TT; ++j) {
-                    cr[i][j] = mfma64(ar[i], br[j], cr[i][j]);
-                    cr[i][j] = mfma64(-ai[i], bi[j], cr[i][j]);
-                    ci[i][j] = mfma64(ar[i], bi[j], ci[i][j]);
-                    ci[i][j] = mfma64(ai[i], br[j], ci[i][j]);
+                    c1[i][j] = mfma64(ar[i], br[j], c1[i][j]);
+                    c2[i][j] = mfma64(ai[i], bi[j], c2[i][j]);
+                    c3[i][j] = mfma64(ar[i] + ai[i], br[j] + bi[j], c3[i][j]);
                 }
         }
         if (more) lstore(buf ^ 1);
@@ -155,7 +174,7 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
                 int gi = m0 + wm * WT + i * 16 + lk + 4 * r;   // f64 MFMA D rows: (lane>>4) + 4r
                 int gj = n0 + wn * WT + j * 16 + lr;
                 if (gi >= M || gj >= N) continue;
-                double vr = cr[i][j][r], vi = ci[i][j][r];
+                double vr = c1[i][j][r] - c2[i][j][r], vi = c3[i][j][r] - c1[i][j][r] - c2[i][j][r];
                 if (P) {
                     P[kz * pstride + gi + (long)gj * M] = make_double2(vr, vi);   // zero if this K range was empty
                 } else {
@@ -1611,7 +1630,7 @@ void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int
                          double2* G, int ldg, hipStream_t st) {
     if (nb <= 0) return;
     // 32 x 32 workgroup tiles: the 16x16 layout's blocks (order 256, some 3000 rows) give ~16k
-    // workgroups; 64 x 64 tiles measured 1.3x slower there (9.4 ms against 7.1 ms per launch)
+    // workgroups; 64 x 64 tiles measured 1.7x slower there (8.3 ms against 5.0 ms per launch)
     const int tile = kGramTile;
     const int mt = (max_n + tile - 1) / tile;
     const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
