@@ -1099,20 +1099,32 @@ fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs) {
         o[2] = (T)(v0 - v3);
         o[3] = (T)(v1 - v2);
     }
-    // folded special input rows
-    for (int i = threadIdx.x; i < 4 * W; i += 256) {
-        const int s_ = i / W, c = i - s_ * W;
+    // folded special input rows: the stencil of special row s reads rows m-1..m+1, all held
+    // full in D (rows m_lo-1..m_lo+2 for s = 0, 1 and m_hi-2..m_hi+1 for s = 2, 3); each pair
+    // of mirrored nodes (q, n - q) is evaluated once for its odd-mode column q - 1 (the sum)
+    // and its even-mode column P1 + q - 1 (the difference)
+    const int P1 = f.P1;
+    for (int i = threadIdx.x; i < 4 * P1; i += 256) {
+        const int s_ = i / P1, j = i - s_ * P1, q = j + 1;
         const int m = (s_ == 0) ? m_lo : (s_ == 1) ? m_lo + 1 : (s_ == 2) ? m_hi - 1 : m_hi;
-        double v = 0.0;
-        if (c < f.P1) {
-            const int q = c + 1;
-            if (q < p) v = rhs(m, q) + rhs(m, n - q);
-            else if (q == p) v = rhs(m, p);
-        } else {
-            const int q = c - f.P1 + 1;
-            if (q < p) v = rhs(m, q) - rhs(m, n - q);
+        const double* Dm = D + ((s_ < 2 ? m - (m_lo - 1) : 4 + m - (m_hi - 2)) * n1);   // row m of D
+        auto rhs_d = [&](int qq) -> double {   // rhs(m, qq) from D alone
+            if (qq < q_lo || qq > q_hi) return 0.0;
+            const double ce = Dm[n1 + qq] + Dm[-n1 + qq] + Dm[qq + 1] + Dm[qq - 1];
+            const double cc = Dm[n1 + qq + 1] + Dm[-n1 + qq + 1] + Dm[n1 + qq - 1] + Dm[-n1 + qq - 1];
+            return sc.c0 * Dm[qq] + sc.ce * ce + sc.cc * cc;
+        };
+        double ve = 0.0, vo = 0.0;
+        if (q < p) {
+            const double r1 = rhs_d(q), r2 = rhs_d(n - q);
+            vo = r1 + r2;
+            ve = r1 - r2;
+        } else if (q == p) {
+            vo = rhs_d(p);
         }
-        spec[((long)b * 4 + s_) * W + c] = (T)v;
+        T* o = spec + ((long)b * 4 + s_) * W;
+        o[j] = (T)vo;
+        if (P1 + j < W) o[P1 + j] = (T)ve;
     }
 }
 
