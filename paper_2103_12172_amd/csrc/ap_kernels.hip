@@ -1130,10 +1130,12 @@ fold_ring_kernel(const FusedJob* __restrict__ jobs, int njobs) {
 
 // Q(i, col0+b) = -u(m_i, q_i): the full gamma rows from the synthesis rows us
 // ([b][plane][4][W], output of the inverse sine GEMM of xs), the others from
-// the thin partial sums (odd-mode blocks give A, even-mode blocks B).  One workgroup
-// per column (one job lookup), its threads over the column's gamma nodes.
+// the thin partial sums (odd-mode blocks give A, even-mode blocks B; with pair_blocks the
+// sweep summed each pair of 64-column blocks 2k, 2k + 1 not straddling P1 into slot 2k).
+// One workgroup per column (one job lookup), its threads over the column's gamma nodes.
 template <class T>
-__global__ void __launch_bounds__(256) gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njobs) {
+__global__ void __launch_bounds__(256) gather_q_fused_kernel(const FusedJob* __restrict__ jobs, int njobs,
+                                                             int pair_blocks) {
     const int gcol = blockIdx.x;
     const FusedJob& J = jobs[find_job(jobs, njobs, gcol)];
     const int b = gcol - J.b0;
@@ -1170,6 +1172,7 @@ __global__ void __launch_bounds__(256) gather_q_fused_kernel(const FusedJob* __r
         const int nb = W / 64, nb1 = f.P1 / 64;
         double A0 = 0.0, A1 = 0.0, B0 = 0.0, B1 = 0.0;
         for (int w = 0; w < nb; ++w) {
+            if (pair_blocks && (w & 1) && w * 64 != f.P1) continue;   // summed into slot w - 1
             const T* t = thin + (((long)b * nb + w) * rows_pad + (m - rg.m_lo + 1)) * 4 + k2;
             if (w < nb1) { A0 += (double)t[0]; A1 += (double)t[1]; }
             else { B0 += (double)t[0]; B1 += (double)t[1]; }
@@ -1325,14 +1328,16 @@ template void launch_fold_ring_jobs<double>(const FusedJob*, int, int, int, hipS
 template void launch_fold_ring_jobs<float>(const FusedJob*, int, int, int, hipStream_t);
 
 template <class T>
-void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, hipStream_t st) {
+void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, int sweep_cols,
+                                hipStream_t st) {
     if (njobs <= 0 || total <= 0) return;
     (void)max_ng;
-    hipLaunchKernelGGL(gather_q_fused_kernel<T>, flat_grid(1, total), dim3(256), 0, st, jobs, njobs);
+    hipLaunchKernelGGL(gather_q_fused_kernel<T>, flat_grid(1, total), dim3(256), 0, st, jobs, njobs,
+                       sweep_cols == 2 ? 1 : 0);
     MDP_HIP(hipGetLastError());
 }
-template void launch_gather_q_fused_jobs<double>(const FusedJob*, int, int, int, hipStream_t);
-template void launch_gather_q_fused_jobs<float>(const FusedJob*, int, int, int, hipStream_t);
+template void launch_gather_q_fused_jobs<double>(const FusedJob*, int, int, int, int, hipStream_t);
+template void launch_gather_q_fused_jobs<float>(const FusedJob*, int, int, int, int, hipStream_t);
 
 // ------------------------------------------------------------------ allocation-free solves
 // The batch buffers of the allocation-free AP solve: a static device array, which every

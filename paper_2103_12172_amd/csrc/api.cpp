@@ -454,7 +454,8 @@ void build_q_fused_t(mdp_ctx* ctx, std::vector<FusedItem> items, hipStream_t st)
                 launch_proj_sweep_jobs<T>(dj, nj, total, groups, max_w, waves_one_col, L, ctx->sweep_cols == 0, st);
         });
         gemms(false);
-        pr.run("gather_q", st, 0.0, gather_bytes, [&] { launch_gather_q_fused_jobs<T>(dj, nj, total, max_ng, st); });
+        pr.run("gather_q", st, 0.0, gather_bytes,
+               [&] { launch_gather_q_fused_jobs<T>(dj, nj, total, max_ng, ctx->last_sweep_cols, st); });
     }
 }
 

@@ -410,8 +410,10 @@ int launch_proj_sweep_jobs(const FusedJob* jobs, int njobs, int total, const lon
                            long waves_one_col, int lanes_cols, bool may_tune, hipStream_t st);
 // process-wide: pick the fused sweep's columns per lane by timing at first use
 void set_sweep_autotune(int on);
+// sweep_cols: the columns per lane the sweep ran with (its thin-sum layout)
 template <class T>
-void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, hipStream_t st);
+void launch_gather_q_fused_jobs(const FusedJob* jobs, int njobs, int total, int max_ng, int sweep_cols,
+                                hipStream_t st);
 bool fused_projector_supported(const Fold& f, int m_lo, int m_hi, int q_lo, int q_hi);
 
 // One plan's entries in a batched FP64 band solve across plans (the reconstruction of

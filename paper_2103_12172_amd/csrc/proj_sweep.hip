@@ -421,8 +421,12 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
         cqi = cki;
     }
     T thv[GroupReduce<T, L>::NOUT];   // the lane's reduced synthesis sums of the last segment
+    // With two columns per lane a wavefront covers two 64-column blocks; unless they straddle
+    // the parity boundary P1 (both odd or both even modes, or the second past W and all zero)
+    // the wavefront adds their sums and writes them to the first block's slot only.
+    const bool pair = L == 2 && wbase + 64 != P1;
     auto store_thin = [&](int s) {
-        if (has_col && blk < (W >> 6) && GroupReduce<T, L>::writer(lane)) {
+        if (has_col && blk < (W >> 6) && GroupReduce<T, L>::writer(lane) && (!pair || lane < 32)) {
 #pragma unroll
             for (int e = 0; e < GroupReduce<T, L>::NOUT; ++e) th[(long)s * K * 4 + GroupReduce<T, L>::vidx(lane, e)] = thv[e];
         }
@@ -483,6 +487,13 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
                 }
             }
             GroupReduce<T, L>::run(acc, lane);
+            if constexpr (L == 2) {
+                if (pair) {   // lanes j and j + 32 hold the same sum of the two blocks
+                    T hi = acc[0];
+                    lane_swap<true>(acc[0], hi);
+                    acc[0] += hi;
+                }
+            }
 #pragma unroll
             for (int e = 0; e < GroupReduce<T, L>::NOUT; ++e) thv[e] = acc[e];
         };
