@@ -245,8 +245,8 @@ __device__ inline double unit_if_bad(double d) { return d > 0.0 ? d : 1.0; }
 struct CholLds {
     double2 S[64][65];     // Schur complement -> L (row-major, lower part)
     double2 Z[64][65];     // inverse accumulation -> L^{-1} (row-major, lower part, zero upper part)
-    double2 Ls[16][16];    // sub-block elimination: column k of S at step k (Ls[k][r])
-    double2 Xr[16][16];    // sub-block elimination: row k of X at step k (Xr[k][j])
+    double2 Cs[4][16];     // sub-block elimination step: column 4g + (k & 3) of row r from lane (r, g)
+    double2 Rw[4][4][16];  // sub-block elimination step: M(r, 4g + q) from lane (r, g) at Rw[q][g][r]
     double piv[16];
 };
 
@@ -289,7 +289,8 @@ __device__ inline void tile16_mac(double (&cr)[4], double (&ci)[4], FA a, FB b) 
 //     D(i,k)/d_k, M(i,j) -= Lt(i,k) v_j over one array M holding D right of the
 //     eliminated columns and the unit factor's inverse X left of them, v_j =
 //     conj(D(j,k)) for j > k, X(k,j) for j < k, d_k + 1 for j = k), with
-//     wavefront-level synchronisation only;
+//     wavefront-level synchronisation only and no branches: every lane publishes
+//     its entries each step and reads the ones it needs from the right copy;
 //  P  L(i,s) = S(i,s) L_ss^{-*} for the rows below, and Z(s,j) = L_ss^{-1} W(s,j)
 //     for the columns left of the block, W(s,j) = -sum_{l<s} L(s,l) Z(l,j) being
 //     what Z holds there;
@@ -328,10 +329,9 @@ __device__ __attribute__((always_inline)) int chol64_lds(const double2* __restri
     int bad = 0;
     for (int sb = 0; sb < 4; ++sb) {
         const int b0 = 16 * sb;
-        // ---- F: 16x16 diagonal block by wavefront 0 (steps unrolled: the lanes that publish
-        // column k and row k of X are known at compile time up to the lane index)
+        // ---- F: 16x16 diagonal block by wavefront 0 (lane (r, g) holds M(r, 4g + q), q < 4)
         if (wave == 0) {
-            double mr[4], mi[4];
+            double mr[4], mi[4], lr0[4] = {}, li0[4] = {};   // lr0: L_ss(r, 4g + q) before scaling
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int c = 4 * g + q;
@@ -342,37 +342,36 @@ __device__ __attribute__((always_inline)) int chol64_lds(const double2* __restri
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int kk = k & 3, k4 = k >> 2, pl = k + 16 * k4;
-                const double ckr = mr[kk], cki = mi[kk];
-                // Ls[k][r] = column k; Xr[k][j] = v_j (conj of column k below the pivot, d_k + 1
-                // at the pivot, row k of X left of it)
-                if (g == k4) {
-                    s.Ls[k][r] = make_double2(ckr, cki);
-                    const double dv = unit_if_bad(ckr);
-                    if (r > k) s.Xr[k][r] = make_double2(ckr, -cki);
-                    if (r == k) {
-                        s.Xr[k][k] = make_double2(dv + 1.0, 0.0);
-                        s.piv[k] = dv;
-                    }
-                }
-                if (r == k) {
+                // publish: column 4g + kk of row r (group k4's copy is column k) and the lane's row
+                // entries (row k's are read below); reads of the last step were issued before these
+                // writes, and one wavefront's LDS operations complete in order
+                s.Cs[g][r] = make_double2(mr[kk], mi[kk]);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (4 * g + q < k) s.Xr[k][4 * g + q] = make_double2(mr[q], mi[q]);
-                }
+                for (int q = 0; q < 4; ++q) s.Rw[q][g][r] = make_double2(mr[q], mi[q]);
                 // the pivot straight from its lane (row k, column group k4)
-                const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ckr), pl),
-                                                  __builtin_amdgcn_readlane(__double2loint(ckr), pl));
+                const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mr[kk]), pl),
+                                                  __builtin_amdgcn_readlane(__double2loint(mr[kk]), pl));
                 const bool ok = d > 0.0;
                 bad = (bad == 0 && !ok) ? b0 + k + 1 : bad;
                 const double dd = ok ? d : 1.0;
+                s.piv[k] = dd;   // the same value from every lane
+                lr0[kk] = g == k4 ? mr[kk] : lr0[kk];
+                li0[kk] = g == k4 ? mi[kk] : li0[kk];
                 // 1/d_k = r0 (1 + e) to full precision (one Newton step on the estimate r0)
                 const double r0 = __builtin_amdgcn_rcp(dd);
                 const double e = fma(-dd, r0, 1.0);
                 wave_sync();
-                const double2 cl = s.Ls[k][r];
+                const double2 cl = s.Cs[k4][r];
                 double2 w[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) w[q] = s.Xr[k][4 * g + q];
+                for (int q = 0; q < 4; ++q) {
+                    const int j = 4 * g + q;
+                    // v_j: conj(M(j, k)) below the pivot (column k), d_k + 1 at it, M(k, j) left of it
+                    const double2* src = j > k ? &s.Cs[k4][j] : &s.Rw[q][g][k];
+                    const double2 v = *src;
+                    w[q].x = j == k ? dd + 1.0 : v.x;
+                    w[q].y = j > k ? -v.y : j == k ? 0.0 : v.y;
+                }
                 const double tr = cl.x * r0, ti = cl.y * r0;
                 const bool live = r > k;
                 const double lr = live ? fma(tr, e, tr) : 0.0, li = live ? fma(ti, e, ti) : 0.0;
@@ -391,8 +390,7 @@ __device__ __attribute__((always_inline)) int chol64_lds(const double2* __restri
                 const int c = 4 * g + q;
                 if (c < r) {
                     const double sc = recip(sqrt(s.piv[c]));
-                    const double2 lv = s.Ls[c][r];
-                    s.S[b0 + r][b0 + c] = make_double2(lv.x * sc, lv.y * sc);
+                    s.S[b0 + r][b0 + c] = make_double2(lr0[q] * sc, li0[q] * sc);
                     s.Z[b0 + r][b0 + c] = make_double2(mr[q] * rdr, mi[q] * rdr);
                 } else if (c == r) {
                     s.S[b0 + r][b0 + r] = make_double2(sdr, 0.0);
