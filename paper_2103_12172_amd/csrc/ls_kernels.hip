@@ -684,11 +684,11 @@ __device__ __attribute__((always_inline)) inline void chol_update64_body(double2
     }
     const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
     const int ib = i0 + 16 * BW * (wv & 1), jb = j0 + 16 * BW * (wv >> 1);
-    d4 cr[BW][BW], ci[BW][BW];
+    d4 c1[BW][BW], c2[BW][BW], c3[BW][BW];   // 3M products: ar br, ai bi, (ar + ai)(br + bi)
 #pragma unroll
     for (int x = 0; x < BW; ++x)
 #pragma unroll
-        for (int y = 0; y < BW; ++y) { cr[x][y] = d4{0, 0, 0, 0}; ci[x][y] = d4{0, 0, 0, 0}; }
+        for (int y = 0; y < BW; ++y) { c1[x][y] = c2[x][y] = c3[x][y] = d4{0, 0, 0, 0}; }
     // operands of k-step ks (k = 4 ks + lane >> 4): A' (row j = jb + 16 tj + lane & 15),
     // B' (column i = ib + 16 ti + lane & 15)
     auto load = [&](int ks, double2* av, double2* bv) {
@@ -706,8 +706,9 @@ __device__ __attribute__((always_inline)) inline void chol_update64_body(double2
             bv[x] = (kin && i < nc) ? L[i + (long)(kb + k) * nc] : make_double2(0.0, 0.0);
         }
     };
-    // stages of S k-steps, the next stage's loads in flight
-    constexpr int S = 2;
+    // stages of S k-steps, the next stage's loads in flight (one: with the three 3M accumulators a
+    // second stage needs more registers than three wavefronts per SIMD leave, measured slower)
+    constexpr int S = 1;
     const int nks = (wtot + 3) / 4;
     double2 a[S][BW], b[S][BW], na[S][BW], nb[S][BW];
 #pragma unroll
@@ -723,10 +724,9 @@ __device__ __attribute__((always_inline)) inline void chol_update64_body(double2
             for (int x = 0; x < BW; ++x)
 #pragma unroll
                 for (int y = 0; y < BW; ++y) {   // D'(j, i) += A'(j, k) B'(k, i), complex
-                    cr[x][y] = mfma64(a[u][x].x, b[u][y].x, cr[x][y]);
-                    cr[x][y] = mfma64(-a[u][x].y, b[u][y].y, cr[x][y]);
-                    ci[x][y] = mfma64(a[u][x].x, b[u][y].y, ci[x][y]);
-                    ci[x][y] = mfma64(a[u][x].y, b[u][y].x, ci[x][y]);
+                    c1[x][y] = mfma64(a[u][x].x, b[u][y].x, c1[x][y]);
+                    c2[x][y] = mfma64(a[u][x].y, b[u][y].y, c2[x][y]);
+                    c3[x][y] = mfma64(a[u][x].x + a[u][x].y, b[u][y].x + b[u][y].y, c3[x][y]);
                 }
 #pragma unroll
         for (int u = 0; u < S; ++u)
@@ -751,7 +751,8 @@ __device__ __attribute__((always_inline)) inline void chol_update64_body(double2
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = jb + 16 * x + lk + 4 * r;
-                if (ok[r]) C[i + (long)j * nc] = make_double2(cv[r].x - cr[x][y][r], cv[r].y - ci[x][y][r]);
+                const double pr = c1[x][y][r] - c2[x][y][r], pi = c3[x][y][r] - c1[x][y][r] - c2[x][y][r];
+                if (ok[r]) C[i + (long)j * nc] = make_double2(cv[r].x - pr, cv[r].y - pi);
             }
         }
 }
@@ -789,7 +790,7 @@ __device__ __attribute__((always_inline)) inline void chol_update32_body(double2
     // column lane & 15), result rows (lane >> 4) + 4 r
     const int wv = tid >> 6, ln = tid & 63, lr = ln & 15, lk = ln >> 4;
     const int ti = wv >> 1, tj = wv & 1;
-    d4 cr = d4{0, 0, 0, 0}, ci = d4{0, 0, 0, 0};
+    d4 c1 = d4{0, 0, 0, 0}, c2 = c1, c3 = c1;   // 3M products: ar br, ai bi, (ar + ai)(br + bi)
     for (int k0 = kb; k0 < r0; k0 += 64) {
         const int kn = min(64, r0 - k0);
         // both operands' loads of the chunk issued before the first wait
@@ -818,10 +819,9 @@ __device__ __attribute__((always_inline)) inline void chol_update32_body(double2
 #pragma unroll 4
         for (int kk0 = 0; kk0 < 64; kk0 += 4) {
             const double2 a = A[kk0 + lk][16 * ti + lr], b = B[kk0 + lk][16 * tj + lr];
-            cr = mfma64(a.x, b.x, cr);
-            cr = mfma64(-a.y, b.y, cr);
-            ci = mfma64(a.x, b.y, ci);
-            ci = mfma64(a.y, b.x, ci);
+            c1 = mfma64(a.x, b.x, c1);
+            c2 = mfma64(a.y, b.y, c2);
+            c3 = mfma64(a.x + a.y, b.x + b.y, c3);
         }
     }
     double2* C = trail ? G : W;
@@ -837,7 +837,8 @@ __device__ __attribute__((always_inline)) inline void chol_update32_body(double2
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = i0 + 16 * ti + lk + 4 * r;
-        if (ok[r]) C[i + (long)j * nc] = make_double2(cv[r].x - cr[r], cv[r].y - ci[r]);
+        const double pr = c1[r] - c2[r], pi = c3[r] - c1[r] - c2[r];
+        if (ok[r]) C[i + (long)j * nc] = make_double2(cv[r].x - pr, cv[r].y - pi);
     }
 }
 
