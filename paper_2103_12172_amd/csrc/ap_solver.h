@@ -52,6 +52,7 @@ struct HostPinned {
 
 struct LSWork {
     DevBuf G, L, Linv[3], T, A0, Aq, vec, norms, flags;
+    DevBuf rp;           // refinement: per 32-row slab partial sums of A^* r (packed route)
     HostPinned hflags;   // the flags' host copy
 };
 

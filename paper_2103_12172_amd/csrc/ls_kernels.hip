@@ -1677,12 +1677,201 @@ void launch_zaxpy_norms(int n, const double2* dx, double2* x, double* norms, dou
     MDP_HIP(hipGetLastError());
 }
 
+// One refinement pass over the packed matrix: the residual r = F - A_i x of the 32 rows of slab
+// blockIdx.x of subdomain i = blockIdx.y (as packed_axpy_kernel with alpha = -1; r stays in LDS),
+// then the slab's share of A_i^* r for every packed column c of the subdomain,
+// P[(pc_start[i] + c) * ms + slab] (the slab's rows were just read: the second read hits the
+// caches).  clr as in packed_axpy_kernel.
+__global__ void __launch_bounds__(256) packed_resid_ahx_kernel(PackedDesc d, const double2* __restrict__ Ap,
+                                                               const double2* __restrict__ x,
+                                                               const int* __restrict__ pc_start,
+                                                               const double2* __restrict__ F,
+                                                               double2* __restrict__ P, int ms, double* clr) {
+    const int i = blockIdx.y;
+    if (clr && blockIdx.x == 0 && i == 0 && threadIdx.x == 0) { clr[0] = 0.0; clr[1] = 0.0; }
+    const int m = d.m[i], s = d.s[i];
+    const int row0 = blockIdx.x * 32;
+    if (row0 >= m) return;   // the whole workgroup
+    const int tr = threadIdx.x & 31, cg = threadIdx.x >> 5;
+    const int row = row0 + tr;
+    __shared__ double2 part[8][33];
+    __shared__ double2 rs[32];
+    const double2* __restrict__ Ai = Ap + d.off[i];
+    double sr = 0.0, si = 0.0;
+    if (row < m) {
+        const double2* A = Ai + row;
+        const int* gc = d.pc_gcol + pc_start[i];
+#pragma unroll 4
+        for (int c = cg; c < s; c += 8) {
+            const double2 a = A[(long)c * m], v = x[gc[c]];
+            sr = fma(a.x, v.x, fma(-a.y, v.y, sr));
+            si = fma(a.x, v.y, fma(a.y, v.x, si));
+        }
+    }
+    part[cg][tr] = make_double2(sr, si);
+    __syncthreads();
+    if (cg == 0) {
+        double2 res = make_double2(0.0, 0.0);
+        if (row < m) {
+            double ar = 0.0, ai = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) { ar += part[q][tr].x; ai += part[q][tr].y; }
+            const double2 f = F[d.roff[i] + row];
+            res = make_double2(f.x - ar, f.y - ai);
+        }
+        rs[tr] = res;
+    }
+    __syncthreads();
+    const int nr = min(32, m - row0);
+    double2* __restrict__ Pi = P + (long)pc_start[i] * ms + blockIdx.x;
+    for (int c = threadIdx.x; c < s; c += 256) {
+        const double2* col = Ai + (long)c * m + row0;
+        double pr = 0.0, pi = 0.0;
+        if (nr == 32) {
+#pragma unroll 8
+            for (int k = 0; k < 32; ++k) {
+                const double2 a = col[k], b = rs[k];
+                pr = fma(a.x, b.x, fma(a.y, b.y, pr));
+                pi = fma(a.x, b.y, fma(-a.y, b.x, pi));
+            }
+        } else {
+            for (int k = 0; k < nr; ++k) {
+                const double2 a = col[k], b = rs[k];
+                pr = fma(a.x, b.x, fma(a.y, b.y, pr));
+                pi = fma(a.x, b.y, fma(-a.y, b.x, pi));
+            }
+        }
+        Pi[(long)c * ms] = make_double2(pr, pi);
+    }
+}
+
+// The same pass for subdomains of at most 256 packed columns, every entry of the slab read once:
+// thread t holds rows (t & 7) + 8 q (q < 4) of columns 8 (t >> 3) .. +7 of the 32 x 256 slab in
+// registers (eight consecutive lanes read 128 consecutive bytes of a column); the row sums (over the 32 column groups) and, once r is known, the
+// column sums (over the 8 row groups) are added in LDS in a fixed order.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) packed_resid_ahx_reg_kernel(PackedDesc d, const double2* __restrict__ Ap,
+                                                                   const double2* __restrict__ x,
+                                                                   const int* __restrict__ pc_start,
+                                                                   const double2* __restrict__ F,
+                                                                   double2* __restrict__ P, int ms, double* clr) {
+    const int i = blockIdx.y;
+    if (clr && blockIdx.x == 0 && i == 0 && threadIdx.x == 0) { clr[0] = 0.0; clr[1] = 0.0; }
+    const int m = d.m[i], s = d.s[i];
+    const int row0 = blockIdx.x * 32;
+    if (row0 >= m) return;   // the whole workgroup
+    const int t = threadIdx.x, rg = t & 7, cq = t >> 3;
+    __shared__ double2 red1[32][33];   // [column group][row]
+    __shared__ double2 red2[8][257];   // [row group][column]
+    __shared__ double2 rs[32];
+    const double2* __restrict__ Ai = Ap + d.off[i];
+    const int* __restrict__ gc = d.pc_gcol + pc_start[i];
+    double2 a[8][4], xv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int c = 8 * cq + j;
+        const bool cin = c < s;
+        xv[j] = cin ? x[gc[c]] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = row0 + rg + 8 * q;
+            a[j][q] = (cin && row < m) ? Ai[row + (long)c * m] : make_double2(0.0, 0.0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {   // the block's share of (A x)(row)
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sr = fma(a[j][q].x, xv[j].x, fma(-a[j][q].y, xv[j].y, sr));
+            si = fma(a[j][q].x, xv[j].y, fma(a[j][q].y, xv[j].x, si));
+        }
+        red1[cq][rg + 8 * q] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (t < 32) {
+        double2 res = make_double2(0.0, 0.0);
+        if (row0 + t < m) {
+            double ar = 0.0, ai = 0.0;
+            for (int g = 0; g < 32; ++g) { ar += red1[g][t].x; ai += red1[g][t].y; }
+            const double2 f = F[d.roff[i] + row0 + t];
+            res = make_double2(f.x - ar, f.y - ai);
+        }
+        rs[t] = res;
+    }
+    __syncthreads();
+    double2 rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rv[q] = rs[rg + 8 * q];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {   // the block's share of (A^* r)(column)
+        double pr = 0.0, pi = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pr = fma(a[j][q].x, rv[q].x, fma(a[j][q].y, rv[q].y, pr));
+            pi = fma(a[j][q].x, rv[q].y, fma(-a[j][q].y, rv[q].x, pi));
+        }
+        red2[rg][8 * cq + j] = make_double2(pr, pi);
+    }
+    __syncthreads();
+    if (t < s) {
+        double pr = 0.0, pi = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) { pr += red2[g][t].x; pi += red2[g][t].y; }
+        P[((long)pc_start[i] + t) * ms + blockIdx.x] = make_double2(pr, pi);
+    }
+}
+
+// y[g] = sum over the packed columns pc of global column g (gc_list[gc_start[g] ..
+// gc_start[g+1]-1]) and over the slabs of their subdomain of the partials P[pc * ms + slab]:
+// one wavefront per global column, lanes over the slabs, a fixed summation order; y overwritten.
+__global__ void __launch_bounds__(256) packed_ahx_partials_kernel(PackedDesc d, const double2* __restrict__ P, int ms,
+                                                                  const int* __restrict__ gc_start,
+                                                                  const int* __restrict__ gc_list, int nc,
+                                                                  double2* __restrict__ y) {
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (g >= nc) return;   // the whole wavefront
+    double sr = 0.0, si = 0.0;
+    for (int e = gc_start[g]; e < gc_start[g + 1]; ++e) {
+        const int pc = gc_list[e];
+        const int ns = (d.m[d.pc_sub[pc]] + 31) / 32;
+        for (int q = lane; q < ns; q += 64) {
+            const double2 v = P[(long)pc * ms + q];
+            sr += v.x;
+            si += v.y;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sr += __shfl_xor(sr, o);
+        si += __shfl_xor(si, o);
+    }
+    if (lane == 0) y[g] = make_double2(sr, si);
+}
+
 // out = a - b (complex vectors of length n; out may alias either)
 __global__ void __launch_bounds__(256) zsub_kernel(int n, const double2* a, const double2* b, double2* out) {
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const double2 x = a[i], y = b[i];
         out[i] = make_double2(x.x - y.x, x.y - y.y);
     }
+}
+
+void launch_packed_resid_ahx(const PackedDevice& d, int n_sub, int max_m, int max_s, int nc, const double2* Ap,
+                             const double2* x, const double2* F, double2* P, double2* y, double* clr,
+                             hipStream_t st) {
+    if (n_sub <= 0 || max_m <= 0 || nc <= 0) return;
+    PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
+    const int ms = packed_slabs(max_m);
+    if (max_s <= 256)
+        hipLaunchKernelGGL(packed_resid_ahx_reg_kernel, dim3(ms, n_sub), dim3(256), 0, st, pd, Ap, x, d.pc_start, F,
+                           P, ms, clr);
+    else
+        hipLaunchKernelGGL(packed_resid_ahx_kernel, dim3(ms, n_sub), dim3(256), 0, st, pd, Ap, x, d.pc_start, F, P,
+                           ms, clr);
+    MDP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(packed_ahx_partials_kernel, dim3((nc + 3) / 4), dim3(256), 0, st, pd, P, ms, d.gc_start,
+                       d.gc_list, nc, y);
+    MDP_HIP(hipGetLastError());
 }
 
 void launch_zsub(int n, const double2* a, const double2* b, double2* out, hipStream_t st) {

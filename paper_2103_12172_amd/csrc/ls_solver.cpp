@@ -471,6 +471,7 @@ PackedTables ls_packed_tables(Workspace& ws, const PackedHost& h, HostBlob& blob
     grow(lw.vec, (size_t)(6 * nc + 2 * mtot) * sizeof(double2));
     grow(lw.norms, 2 * (size_t)nc * sizeof(double));
     grow(lw.flags, 64);
+    grow(lw.rp, std::max<size_t>((size_t)h.total_pc * packed_slabs(h.max_m), 1) * sizeof(double2));
     PackedTables t{};
     t.Q = blob.put(h.Q);
     t.m = blob.put(h.m);
@@ -697,15 +698,18 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     // c = R^{-1} R^{-*} Qbar^* F, R^{-1} = Linv^*, R^{-*} = Linv
     // (every product below overwrites its output and sums in a fixed order, so the
     // sequence needs no clearing launches and repeats bit for bit)
-    auto normal_solve = [&](const double2* rhs_rows, double2* out) {
-        ++n_solves;
-        launch_packed_ahx_set(d, nc, Ap, rhs_rows, y, st);
+    auto apply_inverse = [&](double2* out) {   // out = G^{-1} y
         if (mfr) {
             mf_solve(y, out);
             return;
         }
         launch_trmv_lower('N', nc, Linv, nc, y, t, st);
         launch_trmv_lower('C', nc, Linv, nc, t, out, st);
+    };
+    auto normal_solve = [&](const double2* rhs_rows, double2* out) {
+        ++n_solves;
+        launch_packed_ahx_set(d, nc, Ap, rhs_rows, y, st);
+        apply_inverse(out);
     };
     // r = F - Qbar x (stacked rows); norms: ||r||^2, ||F||^2 into r2, f2; clr: accumulators to zero
     auto residual = [&](double* norms, double* clr) {
@@ -718,11 +722,15 @@ LSResult ls_solve_packed(Workspace& ws, const PackedHost& h, const char* image, 
     // by about cond(Qbar)^2 u).  The last step's residual launch clears x2 and dx2
     // (adjacent), its update accumulates them and clears r2 and f2 (adjacent) for
     // the residual norms that follow.
+    // A refinement step's residual and its product A^* r come from one pass over the packed matrix.
     auto refine = [&](int steps) {
         for (int it = 0; it < steps; ++it) {
             const bool last = it == steps - 1;
-            residual(nullptr, last ? &fl->x2 : nullptr);
-            normal_solve(r, dx);
+            ++n_resid;
+            ++n_solves;
+            launch_packed_resid_ahx(d, n_sub, h.max_m, h.max_s, nc, Ap, x, F, lw.rp.as<double2>(), y,
+                                    last ? &fl->x2 : nullptr, st);
+            apply_inverse(dx);
             launch_zaxpy_norms(nc, dx, x, last ? &fl->x2 : nullptr, last ? &fl->r2 : nullptr, st);
         }
     };

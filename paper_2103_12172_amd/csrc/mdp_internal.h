@@ -557,6 +557,15 @@ void launch_packed_ahx_set(const PackedDevice& d, int nc, const double2* Ap, con
 // accumulators of a later kernel set to zero.
 void launch_packed_axpy(const PackedDevice& d, int n_sub, int max_m, const double2* Ap, const double2* x,
                         double2 alpha, const double2* F, double2* out, double* norms, double* clr, hipStream_t st);
+// One pass over the packed matrix for a refinement step: r = F - A x on the stacked rows (kept on
+// chip, not written) and its products A^* r, as per 32-row slab partial sums in P (packed column
+// pc, slab q at P[pc * ms + q], ms = ceil(max_m / 32)); then y = A^* r, one entry per global
+// column, the partials summed in a fixed order.  max_s: the most packed columns of a subdomain
+// (up to 256 the slab stays in registers between the two products).  clr as in launch_packed_axpy.
+inline int packed_slabs(int max_m) { return (max_m + 31) / 32; }
+void launch_packed_resid_ahx(const PackedDevice& d, int n_sub, int max_m, int max_s, int nc, const double2* Ap,
+                             const double2* x, const double2* F, double2* P, double2* y, double* clr,
+                             hipStream_t st);
 // out = a - b (out may alias a or b)
 void launch_zsub(int n, const double2* a, const double2* b, double2* out, hipStream_t st);
 // x += dx; norms: += ||x||^2 (updated), ||dx||^2; clr as above.
