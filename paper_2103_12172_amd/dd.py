@@ -45,7 +45,7 @@ def side_structs(w: wl.Workload, m_star: int):
             st.nbr, st.nbr_side = sd.nbr, sd.nbr_side
             sides.append(st)
             ds.append(mdp.mdp_cheb_coeffs(wl.boundary_samples(w, i, s, t)) if sd.kind == wl.BOUNDARY else None)
-    return sides, ds
+    return (mdp.Side * len(sides))(*sides), ds
 
 
 def build_projectors(ctx, w: wl.Workload, precision, stream=None) -> List[object]:

@@ -234,19 +234,38 @@ def mdp_build_projectors(ctx: Context, sds: Sequence[Subdomain], m_star: int, pr
     return [Projector(ctx, ctypes.c_void_p(hs[i]), m_star) for i in range(n)]
 
 
+# numpy view of an mdp_side array (the same field offsets), for setting the d pointers in one step
+_SIDE_DT = np.dtype({"names": ["kind", "alpha", "beta", "d", "nbr", "nbr_side"],
+                     "formats": [np.int32, np.float64, np.float64, np.uintp, np.int32, np.int32],
+                     "offsets": [Side.kind.offset, Side.alpha.offset, Side.beta.offset, Side.d.offset,
+                                 Side.nbr.offset, Side.nbr_side.offset],
+                     "itemsize": ctypes.sizeof(Side)})
+
+
 def make_sides(sides: Sequence[Side], d_arrays: Sequence[Optional[np.ndarray]]):
-    """Side structs with their boundary coefficient arrays attached (kept alive by the returned holder)."""
-    arr = (Side * len(sides))()
-    keep = []
-    for i, (s, d) in enumerate(zip(sides, d_arrays)):
-        arr[i] = s
-        if d is not None:
-            buf = np.ascontiguousarray(d, dtype=np.complex128)   # same layout as C128 pairs
-            keep.append(buf)
-            arr[i].d = buf.ctypes.data_as(ctypes.POINTER(C128))
-        else:
-            arr[i].d = ctypes.POINTER(C128)()
-    return arr, keep
+    """Side structs with their boundary coefficient arrays attached (kept alive by the returned holder).
+    A ctypes array of Side (as dd.side_structs returns) is copied in one move; the boundary
+    coefficients go into one contiguous buffer whose pieces the d pointers address."""
+    if len(d_arrays) != len(sides):
+        raise ValueError("one coefficient entry (array or None) per side")
+    n = len(sides)
+    arr = (Side * n)()
+    if isinstance(sides, ctypes.Array) and sides._type_ is Side:
+        ctypes.memmove(arr, sides, ctypes.sizeof(arr))
+    else:
+        for i, s in enumerate(sides):
+            arr[i] = s
+    rec = np.frombuffer(arr, dtype=_SIDE_DT)
+    rec["d"] = 0
+    idx = [i for i, d in enumerate(d_arrays) if d is not None]
+    if not idx:
+        return arr, []
+    bufs = [np.ascontiguousarray(d_arrays[i], dtype=np.complex128).reshape(-1) for i in idx]   # C128 pairs
+    flat = np.concatenate(bufs)
+    offs = np.zeros(len(bufs), dtype=np.uint64)
+    np.cumsum([b.size for b in bufs[:-1]], out=offs[1:])
+    rec["d"][idx] = np.uint64(flat.ctypes.data) + np.uint64(16) * offs
+    return arr, [flat]
 
 
 def make_sources(sources):

@@ -77,3 +77,28 @@ def test_ap_grid_helper_follows_the_documented_grid():
     assert abs(xa - (0.5 - L / 2)) < 1e-14 and abs(ya - (0.0 - L / 2)) < 1e-14
     with pytest.raises(mdp.MdpError):
         mdp.mdp_ap_grid(mdp.Subdomain(0.0, 0.0, 1.0, 1.0, 10.0, 63))
+
+
+def test_side_marshalling_array_and_list_agree():
+    """make_sides: the one-move copy of a ctypes Side array and the per-side path for a list give
+    the same structs, and each boundary side's d pointer addresses its own coefficients."""
+    from paper_2103_12172_amd import dd, workloads as wl
+    w = wl.config_cross_point(n=128, m_star=16)
+    sides, ds = dd.side_structs(w, w.m_star)
+    a1, keep1 = mdp.make_sides(sides, ds)
+    a2, keep2 = mdp.make_sides([sides[i] for i in range(len(sides))], ds)
+    assert ctypes.sizeof(a1) == ctypes.sizeof(a2)
+    nb = 0
+    for i in range(len(sides)):
+        for f in ("kind", "alpha", "beta", "nbr", "nbr_side"):
+            assert getattr(a1[i], f) == getattr(a2[i], f) == getattr(sides[i], f)
+        if ds[i] is None:
+            assert not a1[i].d and not a2[i].d
+            continue
+        nb += 1
+        for a in (a1, a2):
+            got = np.array([complex(a[i].d[j].re, a[i].d[j].im) for j in range(w.m_star)])
+            assert np.array_equal(got, np.asarray(ds[i], dtype=np.complex128))
+    assert nb > 0
+    with pytest.raises(ValueError):
+        mdp.make_sides(sides, ds[:-1])
