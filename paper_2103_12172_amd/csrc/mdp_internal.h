@@ -94,8 +94,12 @@ private:
 // Pinned host staging buffers and a grow-only device image for per-call tables.
 // A pinned slot is rewritten only after the copy out of it has completed (its
 // event); several slots rotate so that the host rarely waits for a copy queued
-// behind earlier work.  The device image is rewritten by a copy ordered on the
-// stream after every earlier call's kernels.
+// behind earlier work, and a copy takes a free slot that is already large enough
+// when there is one.  A slot that must grow keeps its old buffer until the
+// context is destroyed: freeing pinned memory synchronises the device, which
+// would make the host wait for all queued work in the middle of a call.  The
+// device image is rewritten by a copy ordered on the stream after every earlier
+// call's kernels.
 struct Staging {
     struct Slot {
         void* host = nullptr;
@@ -106,6 +110,7 @@ struct Staging {
     static constexpr int kSlots = 8;
     Slot slot[kSlots];
     int next = 0;
+    std::vector<void*> retired;   // outgrown slot buffers, freed with the context
     DevBuf image;
     Staging() = default;
     Staging(const Staging&) = delete;
@@ -116,18 +121,25 @@ struct Staging {
             if (s.host) (void)hipHostFree(s.host);
             if (s.done) (void)hipEventDestroy(s.done);
         }
+        for (void* p : retired) (void)hipHostFree(p);
     }
     // copy b to the device address dst on st
     void copy(void* dst, const HostBlob& b, hipStream_t st) { copy(dst, b.data(), b.size(), st); }
     // copy n bytes at src (host) to the device address dst on st
     void copy(void* dst, const char* src, size_t n, hipStream_t st) {
         if (!n) return;
-        // a slot whose last copy has completed, else the next one in turn (waited for)
-        int pick = -1;
-        for (int i = 0; i < kSlots && pick < 0; ++i) {
-            Slot& c = slot[(next + i) % kSlots];
-            if (!c.pending || hipEventQuery(c.done) == hipSuccess) pick = (next + i) % kSlots;
+        // a free slot (its last copy completed) large enough, else any free slot, else the next
+        // one in turn (waited for)
+        int pick = -1, fit = -1;
+        for (int i = 0; i < kSlots; ++i) {
+            const int k = (next + i) % kSlots;
+            Slot& c = slot[k];
+            if (c.pending && hipEventQuery(c.done) != hipSuccess) continue;
+            c.pending = false;
+            if (pick < 0) pick = k;
+            if (c.cap >= n) { fit = k; break; }
         }
+        if (fit >= 0) pick = fit;
         if (pick < 0) pick = next;
         next = (pick + 1) % kSlots;
         Slot& s = slot[pick];
@@ -135,11 +147,11 @@ struct Staging {
         if (s.pending) MDP_HIP(hipEventSynchronize(s.done));
         s.pending = false;
         if (n > s.cap) {
-            const size_t want = std::max<size_t>({n, 2 * s.cap, (size_t)1 << 16});
-            if (s.host) MDP_HIP(hipHostFree(s.host));
-            s.host = nullptr;
-            s.cap = 0;
-            MDP_HIP(hipHostMalloc(&s.host, want, hipHostMallocDefault));
+            const size_t want = std::max<size_t>({n, 2 * s.cap, (size_t)1 << 20});
+            void* h = nullptr;
+            MDP_HIP(hipHostMalloc(&h, want, hipHostMallocDefault));
+            if (s.host) retired.push_back(s.host);
+            s.host = h;
             s.cap = want;
         }
         std::memcpy(s.host, src, n);
