@@ -85,11 +85,13 @@ def dd_solve(ctx, w: wl.Workload, precision=None, stream=None, projectors=None, 
     dev = "cuda:%d" % ctx.device
     N = len(subs)
     c = torch.empty(N * 8 * w.m_star, dtype=torch.complex128, device=dev)
-    rel, cond = mdp.mdp_solve_interface(ctx, subs, projectors, sides[0], sides[1], w.m_star, c, stream, want_cond,
-                                        sources)
+    # the grids' layout and buffer before the interface solve, which returns only once its
+    # convergence test has reached the host (the reconstruction is queued right after it)
     offs = [0]
     for sd in w.subdomains:
         offs.append(offs[-1] + (sd.n + 1) ** 2)
     u = torch.empty(offs[-1], dtype=torch.complex128, device=dev)
+    rel, cond = mdp.mdp_solve_interface(ctx, subs, projectors, sides[0], sides[1], w.m_star, c, stream, want_cond,
+                                        sources)
     mdp.mdp_reconstruct(ctx, projectors, c, u, stream, sources)
     return DDResult(u, c, rel, cond, offs, projectors, sources)
