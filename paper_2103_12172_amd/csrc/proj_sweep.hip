@@ -304,15 +304,30 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
     // contiguously as they are.
     constexpr int U = S::units;
     constexpr bool unit_major = S::lane_bytes > 16;
+    // With rows of 1 KB or more, transfer ch is piece cr = ch mod (row_bytes / 1 KB) of row ch / (row_bytes
+    // / 1 KB): its row and piece are the same for the whole wavefront, so the source is a wavefront-uniform
+    // row address (kept in scalar registers) plus a per-lane offset fixed for the whole sweep: LDS unit
+    // 64 cr + lane holds global unit lane U + cr (unit-major) or 64 cr + lane.
+    const int lane_off = unit_major ? lane * U * 16 : lane * 16;
     auto stage = [&](int s, int sb) {
         const int mb = m0 + s * K;
         char* fdst = fac_buf + sb * S::fac_bytes;
-        for (int ch = wave; ch < S::fac_bytes / 1024; ch += NW) {
-            const int o = ch * 1024 + lane * 16;
-            const int i = o / S::row_bytes, p = (o - i * S::row_bytes) / 16;
-            const int cb = unit_major ? ((p & 63) * U + (p >> 6)) * 16 : p * 16;   // the global unit it holds
-            const int m = mb + i;
-            lds_dma16((m < t ? rtab + (long)m * LW * 2 * sizeof(T) : twrow) + cb, fdst + ch * 1024);
+        if constexpr (S::row_bytes >= 1024) {
+            constexpr int CPR = S::row_bytes / 1024, piece = unit_major ? 16 : 1024;
+            for (int ch = wave; ch < S::fac_bytes / 1024; ch += NW) {
+                const int i = ch / CPR, cr = ch - i * CPR;
+                const int m = mb + i;
+                const char* row = (m < t ? rtab + (long)m * LW * 2 * sizeof(T) : twrow) + cr * piece;
+                lds_dma16(row + lane_off, fdst + ch * 1024);
+            }
+        } else {
+            for (int ch = wave; ch < S::fac_bytes / 1024; ch += NW) {
+                const int o = ch * 1024 + lane * 16;
+                const int i = o / S::row_bytes, p = (o - i * S::row_bytes) / 16;
+                const int cb = unit_major ? ((p & 63) * U + (p >> 6)) * 16 : p * 16;   // the global unit it holds
+                const int m = mb + i;
+                lds_dma16((m < t ? rtab + (long)m * LW * 2 * sizeof(T) : twrow) + cb, fdst + ch * 1024);
+            }
         }
         if (wave == 0) {
             const int o = lane * 16;
