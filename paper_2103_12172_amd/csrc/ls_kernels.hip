@@ -7,9 +7,10 @@
 // L^{-1} (dense for one matrix, multifrontal over the subdomains' elimination tree
 // for many: batched panel and update launches per 64 columns), and normal solves
 // G dx = Qbar^* r with the explicit inverses, refined on the residual of the
-// packed blocks.  Kernels here: the complex GEMM and Gram batch, the blocked
-// Cholesky-with-inverse steps, the multifrontal assembly and substitutions, and the
-// packed-block products (A x, A^* y, column norms, scaling).
+// packed blocks.  Kernels here: the complex GEMM and Gram batch (three real MFMA
+// products per complex product), the blocked Cholesky-with-inverse steps, the
+// multifrontal assembly and substitutions, and the packed-block products (A x,
+// A^* y, a refinement step's residual and A^* r in one pass, column norms, assembly).
 #include "mdp_internal.h"
 
 namespace mdp {

@@ -35,7 +35,10 @@
 // checkpoint before it, walks back through it, and adds each row's four
 // synthesis products over the lane's L columns; the group then reduces the 4 K
 // sums of the segment across its lanes (a reduce-scatter: permlane swaps for
-// the lane bits 32 and 16, DPP row permutations below) and writes them.
+// the lane bits 32 and 16, DPP row permutations below) and writes them (at two
+// columns per lane, the wavefront's two blocks summed first when they share a
+// parity).  The factor rows of a segment reach LDS by direct global-to-LDS
+// transfers issued a segment ahead from wavefront-uniform row addresses.
 // Segments holding no special row (all but the first and the last one or two)
 // take a path without the special-row tests.  A special input row adds ar_m
 // spec_hat_m to q_m after the ring step (the same sum, and no registers held for
