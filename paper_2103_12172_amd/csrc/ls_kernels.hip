@@ -1069,18 +1069,30 @@ __device__ inline double2 packed_value(const PackedDesc& d, const double2* __res
     return v;
 }
 
-// the packed blocks, each column divided by the norm of its global column
-__global__ void assemble_packed_kernel(PackedDesc d, const double* __restrict__ norms, double2* __restrict__ Ap) {
+// the packed blocks, each column divided by the norm of its global column; a thread takes
+// kAsmRows rows 256 apart, all its loads issued before the first store
+constexpr int kAsmRows = 4;
+__global__ void __launch_bounds__(256) assemble_packed_kernel(PackedDesc d, const double* __restrict__ norms,
+                                                              double2* __restrict__ Ap) {
     const int pc = blockIdx.y;
     const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
+    const int r0 = blockIdx.x * 256 * kAsmRows + threadIdx.x;
+    if (r0 >= m) return;
     const int4 cm = d.pc_cols[pc];
     const double2 wa = d.pc_coef[2 * pc], wb = d.pc_coef[2 * pc + 1];
     const double f = 1.0 / norms[d.pc_gcol[pc]];
     const double2* Q = d.Q[i];
     double2* out = Ap + d.off[i] + (long)p * m;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < m; r += gridDim.x * blockDim.x) {
-        const double2 v = packed_value(d, Q, m, cm, wa, wb, r);
-        out[r] = make_double2(v.x * f, v.y * f);
+    double2 v[kAsmRows];
+#pragma unroll
+    for (int u = 0; u < kAsmRows; ++u) {
+        const int r = r0 + 256 * u;
+        v[u] = r < m ? packed_value(d, Q, m, cm, wa, wb, r) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kAsmRows; ++u) {
+        const int r = r0 + 256 * u;
+        if (r < m) out[r] = make_double2(v[u].x * f, v[u].y * f);
     }
 }
 
@@ -1095,9 +1107,15 @@ __global__ void __launch_bounds__(256) packed_colnorm2_kernel(PackedDesc d, doub
     const double2* Q = d.Q[i];
     __shared__ double red[256];
     double s = 0.0;
-    for (int r = threadIdx.x; r < m; r += 256) {
-        const double2 v = packed_value(d, Q, m, cm, wa, wb, r);
-        s += v.x * v.x + v.y * v.y;
+    for (int r0 = threadIdx.x; r0 < m; r0 += 256 * kAsmRows) {   // kAsmRows loads in flight
+        double2 v[kAsmRows];
+#pragma unroll
+        for (int u = 0; u < kAsmRows; ++u) {
+            const int r = r0 + 256 * u;
+            v[u] = r < m ? packed_value(d, Q, m, cm, wa, wb, r) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < kAsmRows; ++u) s += v[u].x * v[u].x + v[u].y * v[u].y;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -1162,6 +1180,7 @@ __global__ void __launch_bounds__(256) packed_ahx_set_kernel(PackedDesc d, const
         const int i = d.pc_sub[pc], p = d.pc_p[pc], m = d.m[i];
         const double2* col = Ap + d.off[i] + (long)p * m;
         const double2* vi = v + d.roff[i];
+#pragma unroll 4
         for (int r = threadIdx.x; r < m; r += 256) {
             const double2 a = col[r], b = vi[r];
             sr = fma(a.x, b.x, fma(a.y, b.y, sr));
@@ -1595,7 +1614,7 @@ void launch_scale_cols_checked(double2* A, int m, int n, int lda, const double* 
 void launch_assemble_packed(const PackedDevice& d, int total_pc, int max_m, const double* norms, double2* Ap,
                             hipStream_t st) {
     PackedDesc pd{d.Q, d.m, d.off, d.s, d.pc_sub, d.pc_p, d.pc_gcol, d.pc_cols, d.pc_coef, d.roff};
-    dim3 grid(std::max(1, std::min((max_m + 255) / 256, 64)), total_pc);
+    dim3 grid(std::max(1, (max_m + 256 * kAsmRows - 1) / (256 * kAsmRows)), total_pc);
     hipLaunchKernelGGL(assemble_packed_kernel, grid, dim3(256), 0, st, pd, norms, Ap);
     MDP_HIP(hipGetLastError());
 }
