@@ -191,6 +191,121 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
             }
 }
 
+// The Gram batch A_b^* A_b (A_b column-major k x n, ld k): rectangular GM x GN workgroup tiles
+// (rows i of A^*, columns j), only those touching the lower triangle; 4 waves of
+// GM/2 x GN/2 (two 16x16 MFMA blocks sharing the B fragment), K step 16 through
+// double-buffered LDS, 3M complex products.  A 64 x 32 tile moves 24 KB per K step for twice
+// the products of a 32 x 32 tile's 16 KB: the batch is bound by the L2 reads of A.
+// P[kz * n^2 + i + j n] = the split kz's products (raw, no scaling).
+template <int GM, int GN>
+__global__ void __launch_bounds__(256) gram_kernel(const ZBatch* __restrict__ zb, double2* __restrict__ P) {
+    constexpr int TM = GM / 32, TN = GN / 32;   // 16x16 blocks per wave (2 x 2 waves)
+    constexpr int NA = GM * ZBK / 256, NB = GN * ZBK / 256;
+    __shared__ double2 As[2][ZBK][GM + 1];
+    __shared__ double2 Bs[2][ZBK][GN + 1];
+    // every tile of one Gram product on one XCD
+    const long w = xcd_grouped(blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z),
+                               (long)gridDim.x * gridDim.y * gridDim.z);
+    const int bx = (int)(w % gridDim.x);
+    const long rr = w / gridDim.x;
+    const int kz = (int)(rr % gridDim.y), bz = (int)(rr / gridDim.y);
+    const ZBatch e = zb[bz];
+    const int n = e.n, K = e.k;
+    const int mtiles = (n + GM - 1) / GM, ntiles = (n + GN - 1) / GN;
+    if (bx >= mtiles * ntiles) return;
+    const int mt = bx % mtiles, nt = bx / mtiles;
+    const int m0 = mt * GM, n0 = nt * GN;
+    if (m0 + GM <= n0) return;   // above the diagonal
+    const double2* __restrict__ A = e.A;
+    P += e.poff + (long)kz * n * n;
+    const int kb = kz * e.kchunk, ke = min(K, kb + e.kchunk);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, wm = wave >> 1, wn = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    d4 c1[TM][TN], c2[TM][TN], c3[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) c1[i][j] = c2[i][j] = c3[i][j] = d4{0, 0, 0, 0};
+    double2 ra[NA], rb[NB];
+    // thread element idx: k-offset idx % 16 (16 consecutive rows of A, 256 bytes), column idx / 16
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+            const int idx = tid + v * 256, kk = idx % ZBK, i = idx / ZBK;
+            const int gi = m0 + i, gk = k0 + kk;
+            double2 a = (gi < n && gk < ke) ? A[gk + (long)gi * K] : make_double2(0.0, 0.0);
+            a.y = -a.y;   // rows of A^*
+            ra[v] = a;
+        }
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            const int idx = tid + v * 256, kk = idx % ZBK, j = idx / ZBK;
+            const int gj = n0 + j, gk = k0 + kk;
+            rb[v] = (gj < n && gk < ke) ? A[gk + (long)gj * K] : make_double2(0.0, 0.0);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+            const int idx = tid + v * 256;
+            As[buf][idx % ZBK][idx / ZBK] = ra[v];
+        }
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            const int idx = tid + v * 256;
+            Bs[buf][idx % ZBK][idx / ZBK] = rb[v];
+        }
+    };
+    if (kb < ke) {
+        gload(kb);
+        lstore(0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += ZBK) {
+        const bool more = k0 + ZBK < ke;
+        if (more) gload(k0 + ZBK);
+#pragma unroll
+        for (int kk = 0; kk < ZBK / 4; ++kk) {
+            double ar[TM], ai[TM], br[TN], bi[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const double2 a = As[buf][kk * 4 + lk][wm * (GM / 2) + i * 16 + lr];
+                ar[i] = a.x;
+                ai[i] = a.y;
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const double2 b = Bs[buf][kk * 4 + lk][wn * (GN / 2) + j * 16 + lr];
+                br[j] = b.x;
+                bi[j] = b.y;
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    c1[i][j] = mfma64(ar[i], br[j], c1[i][j]);
+                    c2[i][j] = mfma64(ai[i], bi[j], c2[i][j]);
+                    c3[i][j] = mfma64(ar[i] + ai[i], br[j] + bi[j], c3[i][j]);
+                }
+        }
+        if (more) lstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = m0 + wm * (GM / 2) + i * 16 + lk + 4 * r;   // f64 MFMA D rows: (lane>>4) + 4r
+                const int gj = n0 + wn * (GN / 2) + j * 16 + lr;
+                if (gi >= n || gj >= n) continue;
+                P[gi + (long)gj * n] = make_double2(c1[i][j][r] - c2[i][j][r], c3[i][j][r] - c1[i][j][r] - c2[i][j][r]);
+            }
+}
+
 __global__ void zgemm_reduce_kernel(int M, int N, int nsplit, const double2* __restrict__ P, long pstride,
                                     double2* __restrict__ C, int ldc, double2 alpha, double2 beta, int tri, int tile) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1648,14 +1763,22 @@ void launch_packed_ax(const PackedDevice& d, int n_sub, int max_m, int max_s, co
 void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int nsplit, double2* P, const int* gcol,
                          double2* G, int ldg, hipStream_t st) {
     if (nb <= 0) return;
-    // 32 x 32 workgroup tiles: the 16x16 layout's blocks (order 256, some 3000 rows) give ~16k
-    // workgroups; 64 x 64 tiles measured 1.7x slower there (8.3 ms against 5.0 ms per launch)
-    const int tile = kGramTile;
-    const int mt = (max_n + tile - 1) / tile;
-    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
-    hipLaunchKernelGGL(zgemm_kernel<kGramTile>, dim3(mt * mt, nsplit, nb), dim3(256), 0, st, 1, 0, 0, 0, 0,
-                       (const double2*)nullptr, 0, (const double2*)nullptr, 0, (double2*)nullptr, 0, one, zero, 0, P,
-                       0L, 0, 1, zb_dev);
+    // 32 x 32 workgroup tiles for a batch that gives every CU a few of them (the 16x16 layout's
+    // blocks, order 256 and some 3000 rows: ~9k lower tiles); 64 x 32 (gram_kernel) for smaller
+    // batches, where the longer tiles measured faster (cross-point: 0.053 against 0.063 ms)
+    // and slower on the 16x16 layout (5.1 against 4.9 ms); square 64 x 64 tiles measured 1.7x
+    // slower there
+    const int mt = (max_n + kGramTile - 1) / kGramTile;
+    const long lower32 = (long)nb * nsplit * mt * (mt + 1) / 2;
+    if (lower32 >= 2048) {
+        const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+        hipLaunchKernelGGL(zgemm_kernel<kGramTile>, dim3(mt * mt, nsplit, nb), dim3(256), 0, st, 1, 0, 0, 0, 0,
+                           (const double2*)nullptr, 0, (const double2*)nullptr, 0, (double2*)nullptr, 0, one, zero, 0,
+                           P, 0L, 0, 1, zb_dev);
+    } else {
+        const int tiles = ((max_n + 63) / 64) * ((max_n + 31) / 32);
+        hipLaunchKernelGGL((gram_kernel<64, 32>), dim3(tiles, nsplit, nb), dim3(256), 0, st, zb_dev, P);
+    }
     MDP_HIP(hipGetLastError());
     (void)max_k;
     if (!G) return;   // the partials are used as they are (multifrontal leaves)
