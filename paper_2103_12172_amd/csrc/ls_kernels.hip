@@ -348,54 +348,129 @@ __device__ inline double recip1(double d) {
     return fma(r, fma(-d, r, 1.0), r);
 }
 
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Registers of lane (r, g) = (lane & 15, lane >> 4) in the elimination of a 16x16 diagonal
+// sub-block: the whole Hermitian block, M(r, 4g + q) for q < 4.
+struct ElimRegs {
+    double mr[4], mi[4];     // M(r, 4g + q)
+    double lr0[4], li0[4];   // L_ss(r, 4g + q) before scaling: column 4g + q just before its step
+    unsigned badm;           // bit K: pivot d_K not positive (replaced by 1)
+};
+
+__device__ inline double readlane64(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
 }
 
-// pivot used by the elimination: a non-positive (or NaN) one is replaced by 1
-__device__ inline double unit_if_bad(double d) { return d > 0.0 ? d : 1.0; }
+// x of lane 16 (lane >> 4) + K, in every lane of that 16-lane row (DPP row broadcast)
+template <int K>
+__device__ inline double bcast_row16(double x) {
+    return __builtin_amdgcn_mov_dpp(x, 0x150 + K, 0xF, 0xF, false);   // one 64-bit DPP move
+}
+
+// Step K of the unscaled elimination of [D | I] (pivot d_K, Lt(i,K) = M(i,K)/d_K for the rows
+// i > K, M(i,j) -= Lt(i,K) v_j with v_j = M(K,j) for j != K, which is X(K,j) left of the pivot
+// and conj(M(j,K)) right of it, and v_K = d_K + 1, which turns column K into -Lt(.,K)).  All
+// operands come from registers: the pivot by a lane read, M(r,K) by a lane shuffle from column
+// group K >> 2, row K by a DPP broadcast from lane K of the lane's own 16-lane row.
+template <int K>
+__device__ __attribute__((always_inline)) inline void elim_step(ElimRegs& e, int r, int g) {
+    constexpr int kk = K & 3, k4 = K >> 2;
+    const double d = readlane64(e.mr[kk], K + 16 * k4);
+    const bool ok = d > 0.0;
+    e.badm |= ok ? 0u : 1u << K;
+    const double dd = ok ? d : 1.0;
+    e.lr0[kk] = g == k4 ? e.mr[kk] : e.lr0[kk];
+    e.li0[kk] = g == k4 ? e.mi[kk] : e.li0[kk];
+    if constexpr (K < 15) {   // no row lies below the last pivot
+        const double cr = __shfl(e.mr[kk], r + 16 * k4), ci = __shfl(e.mi[kk], r + 16 * k4);
+        double wr[4], wi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            wr[q] = bcast_row16<K>(e.mr[q]);
+            wi[q] = bcast_row16<K>(e.mi[q]);
+        }
+        wr[kk] = g == k4 ? dd + 1.0 : wr[kk];
+        wi[kk] = g == k4 ? 0.0 : wi[kk];
+        // 1/d_K = r0 (1 + eps) to full precision (one Newton step on the estimate r0)
+        const double r0 = __builtin_amdgcn_rcp(dd);
+        const double eps = fma(-dd, r0, 1.0);
+        const double tr = cr * r0, ti = ci * r0;
+        const bool live = r > K;
+        const double lr = live ? fma(tr, eps, tr) : 0.0, li = live ? fma(ti, eps, ti) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double xr = e.mr[q], xi = e.mi[q];
+            e.mr[q] = fma(-lr, wr[q], fma(li, wi[q], xr));
+            e.mi[q] = fma(-lr, wi[q], fma(-li, wr[q], xi));
+        }
+    }
+}
+
+template <int K>
+__device__ __attribute__((always_inline)) inline void elim_steps(ElimRegs& e, int r, int g) {
+    elim_step<K>(e, r, g);
+    if constexpr (K + 1 < 16) elim_steps<K + 1>(e, r, g);
+}
 
 // LDS of one diagonal-block factorisation (rows padded to 65 entries)
 struct CholLds {
     double2 S[64][65];     // Schur complement -> L (row-major, lower part)
     double2 Z[64][65];     // inverse accumulation -> L^{-1} (row-major, lower part, zero upper part)
-    double2 Cs[4][16];     // sub-block elimination step: column 4g + (k & 3) of row r from lane (r, g)
-    double2 Rw[4][4][16];  // sub-block elimination step: M(r, 4g + q) from lane (r, g) at Rw[q][g][r]
-    double piv[16];
+    double cs[64];         // 1/sqrt of the pivots: column scales of the diagonal 16x16 blocks of L
 };
 
-// C(16x16 tile) accumulation for lane (row lane & 15, columns 4 (lane >> 4) + q):
-// acc += sum_k A(r, k) B(k, c) with A(r,k) = a(r,k), B(k,c) = b(k,c) read through the
-// functors, k = 0..15.
+// C(16x16 tile) = sum_{k<16} A(i, k) B(k, c) on the matrix cores, A(i, k) = a(i, k) and
+// B(k, c) = b(k, c) read through the functors.  Computed transposed, C^T = B^T A^T, so that lane
+// (i, g) = (lane & 15, lane >> 4) ends with C(i, g + 4 q) in element q of cr / ci: the A operand
+// is B^T (lane (c, kq) holds B(4t + kq, c)), the B operand A^T (lane (kq, i) holds A(i, 4t + kq)).
+// Two LDS reads per lane and k-step of 4 (the vector form needs five per k); four independent
+// accumulation chains.
 template <class FA, class FB>
-__device__ inline void tile16_mac(double (&cr)[4], double (&ci)[4], FA a, FB b) {
+__device__ inline void tile16_load(double2 (&x)[4], double2 (&y)[4], FA a, FB b) {
+    const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
 #pragma unroll
-    for (int k0 = 0; k0 < 16; k0 += 4) {
-        double2 x[4], y[4][4];   // one round of operands loaded before any arithmetic
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            x[kk] = a(k0 + kk);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) y[kk][q] = b(k0 + kk, q);
-        }
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                cr[q] = fma(x[kk].x, y[kk][q].x, fma(-x[kk].y, y[kk][q].y, cr[q]));
-                ci[q] = fma(x[kk].x, y[kk][q].y, fma(x[kk].y, y[kk][q].x, ci[q]));
-            }
+    for (int t = 0; t < 4; ++t) {
+        x[t] = a(i, 4 * t + kq);
+        y[t] = b(4 * t + kq, i);
     }
 }
+__device__ inline void tile16_prod(const double2 (&x)[4], const double2 (&y)[4], d4& cr, d4& ci) {
+    d4 r1 = {0, 0, 0, 0}, r2 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0}, i2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        r1 = mfma64(y[t].x, x[t].x, r1);
+        r2 = mfma64(y[t].y, x[t].y, r2);
+        i1 = mfma64(y[t].x, x[t].y, i1);
+        i2 = mfma64(y[t].y, x[t].x, i2);
+    }
+    cr = r1 - r2;
+    ci = i1 + i2;
+}
+template <class FA, class FB>
+__device__ inline void tile16_mfma(d4& cr, d4& ci, FA a, FB b) {
+    double2 x[4], y[4];
+    tile16_load(x, y, a, b);
+    tile16_prod(x, y, cr, ci);
+}
+
+// One update tile of the factorisation's trailing step (rows padded to 65 entries):
+// O(i, c) -= sum_k A(i, k) B(k, c), A(i, k) = A[65 i + k], B(k, c) = B[sk k + sc c] conjugated
+// when cs = -1, O(i, c) = O[65 i + c].
+struct TileRef {
+    const double2* A;
+    const double2* B;
+    double2* O;
+    int sk, sc;
+    double cs;
+};
 
 // Cholesky factor and inverse of one Hermitian positive definite diagonal
-// block of order nb <= 64, by the whole workgroup (256 threads): G (lower
+// block of order nb <= 64, by a workgroup of exactly 256 threads: G (lower
 // triangle read, ld ldg) + shift I = L L^*.  On return (after a barrier) s.Z
 // holds L^{-1} row-major with zero upper triangle and s.S holds L in its lower
-// triangle (orders below 64 padded with the identity); if Lout / Zout are set,
-// L and L^{-1} are also written there (lower triangles, ld ldl / ldz).
+// triangle (orders below 64 padded with the identity), except that the strict
+// lower parts of its diagonal 16x16 blocks lack their column scales s.cs; if
+// Lout / Zout are set, L and L^{-1} are written there (lower triangles, ld ldl / ldz).
 // Returns the 1-based index of the first non-positive pivot (0 if none), the
 // same in every thread.
 //
@@ -404,169 +479,202 @@ __device__ inline void tile16_mac(double (&cr)[4], double (&ci)[4], FA a, FB b) 
 //     inverse by unscaled elimination of [D | I] (step k: pivot d_k, Lt(i,k) =
 //     D(i,k)/d_k, M(i,j) -= Lt(i,k) v_j over one array M holding D right of the
 //     eliminated columns and the unit factor's inverse X left of them, v_j =
-//     conj(D(j,k)) for j > k, X(k,j) for j < k, d_k + 1 for j = k), with
-//     wavefront-level synchronisation only and no branches: every lane publishes
-//     its entries each step and reads the ones it needs from the right copy;
+//     conj(D(j,k)) for j > k, X(k,j) for j < k, d_k + 1 for j = k), entirely in
+//     registers: each lane holds four entries of the whole Hermitian block, so
+//     v_j is row k's entry (a DPP row broadcast) and the multipliers' column
+//     comes from one of the four 16-lane rows (a lane shuffle);
 //  P  L(i,s) = S(i,s) L_ss^{-*} for the rows below, and Z(s,j) = L_ss^{-1} W(s,j)
 //     for the columns left of the block, W(s,j) = -sum_{l<s} L(s,l) Z(l,j) being
 //     what Z holds there;
 //  U  S(i,j) -= L(i,s) L(j,s)^* (trailing, lower) and W(i,j) -= L(i,s) Z(s,j)
 //     for the rows below (j up to the block, Z(s,s) = L_ss^{-1}).
-// P and U work on 16x16 tiles spread over the 4 wavefronts (4 entries per lane).
+// P and U work on 16x16 tiles spread over the 4 wavefronts, on the matrix cores.
 __device__ __attribute__((always_inline)) int chol64_lds(const double2* __restrict__ G, int ldg, int nb, double shift, CholLds& s,
                           double2* __restrict__ Lout, int ldl, double2* __restrict__ Zout, int ldz) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;   // tile row, column group (columns 4g..4g+3)
-    // the block into LDS: all of a thread's loads are issued before the first is waited for
-    // (a rolled loop would wait for each load in turn)
-    auto entry = [&](int e, double2 v) {
-        const int i = e & 63, j = e >> 6;   // consecutive threads: consecutive rows of a column
-        if (j <= i) {
-            if (i >= nb && i == j) v = make_double2(1.0, 0.0);
-            if (i == j && i < nb) v.x += shift;
+    // the shifted lower triangle (j <= i), padded with the identity beyond order nb, and zero where
+    // `use` is false; the load itself is unconditional (an entry outside reads G[0], nb >= 1), so
+    // that a thread's loads are all in flight before the first wait
+    auto gval = [&](int i, int j, bool use) {
+        const bool in = use && i < nb;
+        const double2 x = G[in ? i + (long)j * ldg : 0];
+        const double2 v = in ? x : make_double2(0.0, 0.0);
+        return !use || i != j ? v : i < nb ? make_double2(v.x + shift, v.y) : make_double2(1.0, 0.0);
+    };
+    // wavefront 0 takes its entries of the first diagonal 16x16 block straight from memory (the
+    // whole Hermitian block) and starts eliminating while the others bring the rest into LDS
+    double2 m0[4];
+    if (wave == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 4 * g + q;
+            const double2 v = gval(c <= r ? r : c, c <= r ? c : r, true);
+            m0[q] = make_double2(v.x, c <= r ? v.y : -v.y);
         }
-        s.S[i][j] = v;
-        s.Z[i][j] = make_double2(0.0, 0.0);
-    };
-    auto load = [&](int e) {
-        const int i = e & 63, j = e >> 6;
-        return (j <= i && i < nb) ? G[i + (long)j * ldg] : make_double2(0.0, 0.0);
-    };
-    if (blockDim.x == 256) {
-        double2 v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = load(tid + 256 * u);
-#pragma unroll
-        for (int u = 0; u < 16; ++u) entry(tid + 256 * u, v[u]);
-    } else {
-        for (int e = tid; e < 64 * 64; e += blockDim.x) entry(e, load(e));
     }
-    __syncthreads();
+    // L(i, j), the diagonal blocks' column scales applied
+    auto lval = [&](int i, int j) {
+        const double2 v = s.S[i][j];
+        const double c = ((i >> 4) == (j >> 4) && i != j) ? s.cs[j] : 1.0;
+        return make_double2(v.x * c, v.y * c);
+    };
+    // L's column block cb and Z's row block cb to memory by threads t0.. (nt of them): final once
+    // sub-block cb's panel step is done (later steps touch only columns / rows beyond it)
+    auto write_block = [&](int cb, int t, int nt) {
+        const int c0 = 16 * cb;
+        if (Lout)   // rows c0..63 as 16x16 tiles; consecutive threads: consecutive rows of a column
+#pragma unroll 4
+            for (int e = t; e < 256 * (4 - cb); e += nt) {
+                const int i = c0 + 16 * (e >> 8) + (e & 15), j = c0 + ((e >> 4) & 15);
+                if (i < nb && j <= i) Lout[i + (long)j * ldl] = lval(i, j);
+            }
+        if (Zout)
+#pragma unroll 4
+            for (int e = t; e < 16 * (c0 + 16); e += nt) {
+                const int i = c0 + (e & 15), j = e >> 4;
+                if (i < nb && j <= i) Zout[i + (long)j * ldz] = s.Z[i][j];
+            }
+    };
     int bad = 0;
     for (int sb = 0; sb < 4; ++sb) {
         const int b0 = 16 * sb;
-        // ---- F: 16x16 diagonal block by wavefront 0 (lane (r, g) holds M(r, 4g + q), q < 4)
+        // ---- F: 16x16 diagonal block by wavefront 0 (lane (r, g) holds M(r, 4g + q), q < 4; the
+        //      whole Hermitian block, so that row k supplies the conjugated column below the pivot)
         if (wave == 0) {
-            double mr[4], mi[4], lr0[4] = {}, li0[4] = {};   // lr0: L_ss(r, 4g + q) before scaling
+            ElimRegs e;
+            e.badm = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int c = 4 * g + q;
-                const double2 v = (c <= r) ? s.S[b0 + r][b0 + c] : make_double2(0.0, 0.0);
-                mr[q] = v.x;
-                mi[q] = v.y;
-            }
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int kk = k & 3, k4 = k >> 2, pl = k + 16 * k4;
-                // publish: column 4g + kk of row r (group k4's copy is column k) and the lane's row
-                // entries (row k's are read below); reads of the last step were issued before these
-                // writes, and one wavefront's LDS operations complete in order
-                s.Cs[g][r] = make_double2(mr[kk], mi[kk]);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) s.Rw[q][g][r] = make_double2(mr[q], mi[q]);
-                // the pivot straight from its lane (row k, column group k4)
-                const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mr[kk]), pl),
-                                                  __builtin_amdgcn_readlane(__double2loint(mr[kk]), pl));
-                const bool ok = d > 0.0;
-                bad = (bad == 0 && !ok) ? b0 + k + 1 : bad;
-                const double dd = ok ? d : 1.0;
-                s.piv[k] = dd;   // the same value from every lane
-                lr0[kk] = g == k4 ? mr[kk] : lr0[kk];
-                li0[kk] = g == k4 ? mi[kk] : li0[kk];
-                // 1/d_k = r0 (1 + e) to full precision (one Newton step on the estimate r0)
-                const double r0 = __builtin_amdgcn_rcp(dd);
-                const double e = fma(-dd, r0, 1.0);
-                wave_sync();
-                const double2 cl = s.Cs[k4][r];
-                double2 w[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int j = 4 * g + q;
-                    // v_j: conj(M(j, k)) below the pivot (column k), d_k + 1 at it, M(k, j) left of it
-                    const double2* src = j > k ? &s.Cs[k4][j] : &s.Rw[q][g][k];
-                    const double2 v = *src;
-                    w[q].x = j == k ? dd + 1.0 : v.x;
-                    w[q].y = j > k ? -v.y : j == k ? 0.0 : v.y;
+                double2 v = m0[q];
+                if (sb > 0) {
+                    v = (c <= r) ? s.S[b0 + r][b0 + c] : s.S[b0 + c][b0 + r];
+                    v.y = c <= r ? v.y : -v.y;
                 }
-                const double tr = cl.x * r0, ti = cl.y * r0;
-                const bool live = r > k;
-                const double lr = live ? fma(tr, e, tr) : 0.0, li = live ? fma(ti, e, ti) : 0.0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    mr[q] = fma(-lr, w[q].x, fma(li, w[q].y, mr[q]));
-                    mi[q] = fma(-lr, w[q].y, fma(-li, w[q].x, mi[q]));
-                }
+                e.mr[q] = v.x;
+                e.mi[q] = v.y;
+                e.lr0[q] = e.li0[q] = 0.0;
             }
-            wave_sync();
-            // L_ss into S, L_ss^{-1} into Z (lower parts; upper part of the Z block stays zero)
-            const double pr = s.piv[r];
+            elim_steps<0>(e, r, g);
+            if (bad == 0 && e.badm) bad = b0 + __builtin_ctz(e.badm) + 1;
+            // d_r: M(r, r) is left as it was at its own step, in register r & 3 of lane (r, r >> 2)
+            double dr = e.mr[0];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) dr = (r & 3) == q ? e.mr[q] : dr;
+            dr = __shfl(dr, r + 16 * (r >> 2));
+            const double pr = dr > 0.0 ? dr : 1.0;
+            // L_ss^{-1} into Z (lower part; upper part of the Z block stays zero), L_ss into S with
+            // its strict lower part unscaled (column c is scaled by 1/sqrt(d_c) on the way out)
             const double sdr = sqrt(pr), rdr = recip(sdr);
+            if (g == 0) s.cs[b0 + r] = rdr;
+            // every entry of the lane is written (no branches): the upper part of the Z block must
+            // stay zero, the upper part of the S block is never read
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int c = 4 * g + q;
-                if (c < r) {
-                    const double sc = recip(sqrt(s.piv[c]));
-                    s.S[b0 + r][b0 + c] = make_double2(lr0[q] * sc, li0[q] * sc);
-                    s.Z[b0 + r][b0 + c] = make_double2(mr[q] * rdr, mi[q] * rdr);
-                } else if (c == r) {
-                    s.S[b0 + r][b0 + r] = make_double2(sdr, 0.0);
-                    s.Z[b0 + r][b0 + r] = make_double2(rdr, 0.0);
+                const bool lo = c < r, dg = c == r;
+                s.S[b0 + r][b0 + c] = make_double2(dg ? sdr : e.lr0[q], dg ? 0.0 : e.li0[q]);
+                s.Z[b0 + r][b0 + c] = make_double2(lo ? e.mr[q] * rdr : dg ? rdr : 0.0, lo ? e.mi[q] * rdr : 0.0);
+            }
+        } else if (sb == 0) {
+            // the rest of the block into LDS (S and Z but their first diagonal 16x16 blocks, which
+            // wavefront 0 writes after its elimination), every load issued before the first wait
+            constexpr int NT = 192, NU = (64 * 64 + NT - 1) / NT;
+            double2 v[NU];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int e = tid - 64 + NT * u, i = e & 63, j = e >> 6;   // consecutive rows of a column
+                v[u] = gval(i, j, e < 64 * 64 && j <= i && i >= 16);
+            }
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int e = tid - 64 + NT * u, i = e & 63, j = e >> 6;
+                if (e < 64 * 64 && (i >= 16 || j >= 16)) {
+                    s.S[i][j] = v[u];
+                    s.Z[i][j] = make_double2(0.0, 0.0);
                 }
             }
+        } else {
+            write_block(sb - 1, tid - 64, blockDim.x - 64);   // while wavefront 0 eliminates
         }
         __syncthreads();
         // ---- P: panel below (tiles it = sb+1..3) and Z row block (tiles jt = 0..sb-1), into registers
         const int np = 3 - sb, ntp = np + sb;
-        double pr_[4] = {}, pi_[4] = {};
+        d4 pr_ = {0, 0, 0, 0}, pi_ = {0, 0, 0, 0};
         int pt = -1;
         for (int t = wave; t < ntp; t += 4) pt = t;   // each wavefront owns at most one tile (ntp <= 3)
         if (pt >= 0) {
             if (pt < np) {
                 const int i0 = b0 + 16 * (pt + 1);
-                tile16_mac(pr_, pi_, [&](int k) { return s.S[i0 + r][b0 + k]; },
-                           [&](int k, int q) { const double2 z = s.Z[b0 + 4 * g + q][b0 + k];
-                                               return make_double2(z.x, -z.y); });
+                tile16_mfma(pr_, pi_, [&](int i, int k) { return s.S[i0 + i][b0 + k]; },
+                            [&](int k, int c) { const double2 z = s.Z[b0 + c][b0 + k];
+                                                return make_double2(z.x, -z.y); });
             } else {
                 const int j0 = 16 * (pt - np);
-                tile16_mac(pr_, pi_, [&](int k) { return s.Z[b0 + r][b0 + k]; },
-                           [&](int k, int q) { return s.Z[b0 + k][j0 + 4 * g + q]; });
+                tile16_mfma(pr_, pi_, [&](int i, int k) { return s.Z[b0 + i][b0 + k]; },
+                            [&](int k, int c) { return s.Z[b0 + k][j0 + c]; });
             }
         }
         __syncthreads();
         if (pt >= 0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (pt < np) s.S[b0 + 16 * (pt + 1) + r][b0 + 4 * g + q] = make_double2(pr_[q], pi_[q]);
-                else s.Z[b0 + r][16 * (pt - np) + 4 * g + q] = make_double2(pr_[q], pi_[q]);
+                if (pt < np) s.S[b0 + 16 * (pt + 1) + r][b0 + g + 4 * q] = make_double2(pr_[q], pi_[q]);
+                else s.Z[b0 + r][16 * (pt - np) + g + 4 * q] = make_double2(pr_[q], pi_[q]);
             }
         }
         __syncthreads();
-        // ---- U: trailing lower tiles (sb < jt <= it) and W tiles (it > sb, jt <= sb)
-        const int ntr = np * (np + 1) / 2, nw = np * (sb + 1);
-        for (int t = wave; t < ntr + nw; t += 4) {
-            double cr[4] = {}, ci[4] = {};
+        // ---- U: trailing lower tiles (sb < jt <= it) and W tiles (it > sb, jt <= sb), a
+        //      wavefront's tiles t = wave + 4u in turn, each tile's operands loaded while the
+        //      previous one is on the matrix cores (no tile reads what another one writes)
+        const int ntr = np * (np + 1) / 2, ntot = ntr + np * (sb + 1);
+        auto tile_ref = [&](int t) {
+            TileRef f;
             if (t < ntr) {
                 int a = 0;
                 while ((a + 1) * (a + 2) / 2 <= t) ++a;
                 const int it = sb + 1 + a, jt = sb + 1 + (t - a * (a + 1) / 2);
-                tile16_mac(cr, ci, [&](int k) { return s.S[16 * it + r][b0 + k]; },
-                           [&](int k, int q) { const double2 l = s.S[16 * jt + 4 * g + q][b0 + k];
-                                               return make_double2(l.x, -l.y); });
+                f = TileRef{&s.S[16 * it][b0], &s.S[16 * jt][b0], &s.S[16 * it][16 * jt], 1, 65, -1.0};
+            } else {
+                const int u = t - ntr, it = sb + 1 + u % np, jt = u / np;
+                f = TileRef{&s.S[16 * it][b0], &s.Z[b0][16 * jt], &s.Z[16 * it][16 * jt], 65, 1, 1.0};
+            }
+            return f;
+        };
+        auto ops = [&](const TileRef& f, double2 (&x)[4], double2 (&y)[4]) {
+            tile16_load(x, y, [&](int i, int k) { return f.A[65 * i + k]; },
+                        [&](int k, int c) { const double2 v = f.B[f.sk * k + f.sc * c];
+                                            return make_double2(v.x, f.cs * v.y); });
+        };
+        if (wave < ntot) {
+            int t = wave;
+            TileRef f = tile_ref(t);
+            double2 x[4], y[4];
+            ops(f, x, y);
+            while (true) {
+                const int tn = t + 4;
+                TileRef fn = f;
+                double2 xn[4], yn[4];
+                if (tn < ntot) {
+                    fn = tile_ref(tn);
+                    ops(fn, xn, yn);
+                }
+                d4 cr, ci;
+                tile16_prod(x, y, cr, ci);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    double2& o = s.S[16 * it + r][16 * jt + 4 * g + q];
+                    double2& o = f.O[65 * r + g + 4 * q];
                     o.x -= cr[q];
                     o.y -= ci[q];
                 }
-            } else {
-                const int u = t - ntr, it = sb + 1 + u % np, jt = u / np;
-                tile16_mac(cr, ci, [&](int k) { return s.S[16 * it + r][b0 + k]; },
-                           [&](int k, int q) { return s.Z[b0 + k][16 * jt + 4 * g + q]; });
+                if (tn >= ntot) break;
+                t = tn;
+                f = fn;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    double2& o = s.Z[16 * it + r][16 * jt + 4 * g + q];
-                    o.x -= cr[q];
-                    o.y -= ci[q];
+                for (int u = 0; u < 4; ++u) {
+                    x[u] = xn[u];
+                    y[u] = yn[u];
                 }
             }
         }
@@ -577,14 +685,7 @@ __device__ __attribute__((always_inline)) int chol64_lds(const double2* __restri
     if (tid == 0) bad_s = bad;
     __syncthreads();
     const int first = bad_s;
-    if (Lout || Zout) {
-        for (int e = tid; e < 64 * 64; e += blockDim.x) {
-            const int i = e & 63, j = e >> 6;
-            if (i >= nb || j > i) continue;
-            if (Lout) Lout[i + (long)j * ldl] = s.S[i][j];
-            if (Zout) Zout[i + (long)j * ldz] = s.Z[i][j];
-        }
-    }
+    write_block(3, tid, blockDim.x);
     return first;
 }
 
