@@ -193,9 +193,11 @@ zgemm_kernel(int opA, int opB, int M, int N, int K, const double2* __restrict__ 
 
 // The Gram batch A_b^* A_b (A_b column-major k x n, ld k): rectangular GM x GN workgroup tiles
 // (rows i of A^*, columns j), only those touching the lower triangle; 4 waves of
-// GM/2 x GN/2 (two 16x16 MFMA blocks sharing the B fragment), K step 16 through
-// double-buffered LDS, 3M complex products.  A 64 x 32 tile moves 24 KB per K step for twice
-// the products of a 32 x 32 tile's 16 KB: the batch is bound by the L2 reads of A.
+// GM/2 x GN/2 (two 16x16 MFMA blocks sharing the B fragment when GM = 64), K step 16 through
+// double-buffered LDS with the global loads of the two following K steps in flight (one step
+// in flight left the batch latency-bound: 5.1 against 3.9 ms on the 16x16 layout; three
+// measured slower again), 3M complex products.  32 x 32 tiles for large batches; a 64 x 32
+// tile moves 24 KB per K step for twice the products of a 32 x 32 tile's 16 KB.
 // P[kz * n^2 + i + j n] = the split kz's products (raw, no scaling).
 template <int GM, int GN>
 __global__ void __launch_bounds__(256) gram_kernel(const ZBatch* __restrict__ zb, double2* __restrict__ P) {
@@ -226,45 +228,39 @@ __global__ void __launch_bounds__(256) gram_kernel(const ZBatch* __restrict__ zb
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) c1[i][j] = c2[i][j] = c3[i][j] = d4{0, 0, 0, 0};
-    double2 ra[NA], rb[NB];
     // thread element idx: k-offset idx % 16 (16 consecutive rows of A, 256 bytes), column idx / 16
-    auto gload = [&](int k0) {
+    struct Stage {
+        double2 a[NA], b[NB];
+    };
+    auto gload = [&](int k0, Stage& g) {
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
             const int idx = tid + v * 256, kk = idx % ZBK, i = idx / ZBK;
             const int gi = m0 + i, gk = k0 + kk;
             double2 a = (gi < n && gk < ke) ? A[gk + (long)gi * K] : make_double2(0.0, 0.0);
             a.y = -a.y;   // rows of A^*
-            ra[v] = a;
+            g.a[v] = a;
         }
 #pragma unroll
         for (int v = 0; v < NB; ++v) {
             const int idx = tid + v * 256, kk = idx % ZBK, j = idx / ZBK;
             const int gj = n0 + j, gk = k0 + kk;
-            rb[v] = (gj < n && gk < ke) ? A[gk + (long)gj * K] : make_double2(0.0, 0.0);
+            g.b[v] = (gj < n && gk < ke) ? A[gk + (long)gj * K] : make_double2(0.0, 0.0);
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, const Stage& g) {
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
             const int idx = tid + v * 256;
-            As[buf][idx % ZBK][idx / ZBK] = ra[v];
+            As[buf][idx % ZBK][idx / ZBK] = g.a[v];
         }
 #pragma unroll
         for (int v = 0; v < NB; ++v) {
             const int idx = tid + v * 256;
-            Bs[buf][idx % ZBK][idx / ZBK] = rb[v];
+            Bs[buf][idx % ZBK][idx / ZBK] = g.b[v];
         }
     };
-    if (kb < ke) {
-        gload(kb);
-        lstore(0);
-    }
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = kb; k0 < ke; k0 += ZBK) {
-        const bool more = k0 + ZBK < ke;
-        if (more) gload(k0 + ZBK);
+    auto step = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < ZBK / 4; ++kk) {
             double ar[TM], ai[TM], br[TN], bi[TN];
@@ -289,9 +285,26 @@ __global__ void __launch_bounds__(256) gram_kernel(const ZBatch* __restrict__ zb
                     c3[i][j] = mfma64(ar[i] + ai[i], br[j] + bi[j], c3[i][j]);
                 }
         }
-        if (more) lstore(buf ^ 1);
+    };
+    // two K steps of global loads in flight while one is multiplied: register stages X and Y
+    // alternate (the loop body is written twice so that each stage stays in its own registers)
+    Stage X, Y;
+    if (kb < ke) gload(kb, X);
+    if (kb + ZBK < ke) gload(kb + ZBK, Y);
+    if (kb < ke) lstore(0, X);
+    __syncthreads();
+    for (int k0 = kb; k0 < ke;) {
+        if (k0 + 2 * ZBK < ke) gload(k0 + 2 * ZBK, X);
+        step(0);
+        if (k0 + ZBK < ke) lstore(1, Y);
         __syncthreads();
-        buf ^= 1;
+        k0 += ZBK;
+        if (k0 >= ke) break;
+        if (k0 + 2 * ZBK < ke) gload(k0 + 2 * ZBK, Y);
+        step(1);
+        if (k0 + ZBK < ke) lstore(0, X);
+        __syncthreads();
+        k0 += ZBK;
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -1865,17 +1878,13 @@ void launch_gram_batched(const ZBatch* zb_dev, int nb, int max_n, int max_k, int
                          double2* G, int ldg, hipStream_t st) {
     if (nb <= 0) return;
     // 32 x 32 workgroup tiles for a batch that gives every CU a few of them (the 16x16 layout's
-    // blocks, order 256 and some 3000 rows: ~9k lower tiles); 64 x 32 (gram_kernel) for smaller
-    // batches, where the longer tiles measured faster (cross-point: 0.053 against 0.063 ms)
-    // and slower on the 16x16 layout (5.1 against 4.9 ms); square 64 x 64 tiles measured 1.7x
-    // slower there
+    // blocks, order 256 and some 3000 rows: ~9k lower tiles); 64 x 32 for smaller batches, where
+    // the longer tiles measured faster (cross-point: 0.053 against 0.063 ms) and slower on the
+    // 16x16 layout; square 64 x 64 tiles measured 1.7x slower there
     const int mt = (max_n + kGramTile - 1) / kGramTile;
     const long lower32 = (long)nb * nsplit * mt * (mt + 1) / 2;
     if (lower32 >= 2048) {
-        const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
-        hipLaunchKernelGGL(zgemm_kernel<kGramTile>, dim3(mt * mt, nsplit, nb), dim3(256), 0, st, 1, 0, 0, 0, 0,
-                           (const double2*)nullptr, 0, (const double2*)nullptr, 0, (double2*)nullptr, 0, one, zero, 0,
-                           P, 0L, 0, 1, zb_dev);
+        hipLaunchKernelGGL((gram_kernel<32, 32>), dim3(mt * mt, nsplit, nb), dim3(256), 0, st, zb_dev, P);
     } else {
         const int tiles = ((max_n + 63) / 64) * ((max_n + 31) / 32);
         hipLaunchKernelGGL((gram_kernel<64, 32>), dim3(tiles, nsplit, nb), dim3(256), 0, st, zb_dev, P);
