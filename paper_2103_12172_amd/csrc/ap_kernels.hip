@@ -242,7 +242,7 @@ __device__ inline void tridiag_adj_body(const double* __restrict__ in, int plane
 }
 
 template <class T>
-__device__ inline void tridiag_body(const T* __restrict__ in, int planes_in, T* __restrict__ out,
+__device__ __attribute__((always_inline)) inline void tridiag_body(const T* __restrict__ in, int planes_in, T* __restrict__ out,
                                     const T* __restrict__ fac, const T* __restrict__ colc, int n, int W, Band bd,
                                     int c, int b) {
     const int r0 = bd.r0, t = bd.r0 + bd.nr - 1;
