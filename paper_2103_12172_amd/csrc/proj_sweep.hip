@@ -207,6 +207,12 @@ struct SweepLds {
     static_assert(lane_bytes <= 16 || units * 16 == lane_bytes, "a lane's factors are whole 16-byte units");
 };
 
+// A pointer into global memory with the address space explicit: loads and stores through it
+// are global instructions, counted by the vector memory counter only (through a generic
+// pointer they would be flat instructions, which also count against the LDS counter, so that
+// every wait for an LDS read would also wait for them).
+template <class X> using gptr = __attribute__((address_space(1))) X*;   // converted by C-style casts
+
 __device__ inline void lds_dma16(const void* src, void* lds_dst) {
     __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                      (__attribute__((address_space(3))) void*)lds_dst, 16, 0, 0);
@@ -259,18 +265,18 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
     const int nseg = J.nseg;
     const long LW = W;
 
-    const T* __restrict__ Sf = reinterpret_cast<const T*>(J.Sf);
-    const T* __restrict__ Si = reinterpret_cast<const T*>(J.Si);
-    const T* __restrict__ colc = reinterpret_cast<const T*>(J.colc);
+    const gptr<const T> Sf = (gptr<const T>)(J.Sf);
+    const gptr<const T> Si = (gptr<const T>)(J.Si);
+    const gptr<const T> colc = (gptr<const T>)(J.colc);
     const T* __restrict__ tf = reinterpret_cast<const T*>(J.tf);
     const char* __restrict__ rtab = reinterpret_cast<const char*>(J.rf) + (long)wbase * 2 * sizeof(T);
     const char* __restrict__ twrow = reinterpret_cast<const char*>(J.tf) + ((long)t * LW + wbase) * 2 * sizeof(T);
     const char* __restrict__ gring = reinterpret_cast<const char*>(J.gc);
-    const T* __restrict__ spec_hat = reinterpret_cast<const T*>(J.spec_hat) + (long)b * 4 * LW + cc;
-    T* __restrict__ ck = reinterpret_cast<T*>(J.ckpt) + (long)b * nseg * 2 * LW + cc;
-    T* __restrict__ xs = reinterpret_cast<T*>(J.xs) + (long)b * 8 * LW + cc;
+    const gptr<const T> spec_hat = (gptr<const T>)(J.spec_hat) + (long)b * 4 * LW + cc;
+    const gptr<T> ck = (gptr<T>)(J.ckpt) + (long)b * nseg * 2 * LW + cc;
+    const gptr<T> xs = (gptr<T>)(J.xs) + (long)b * 8 * LW + cc;
     const int blk = (wbase >> 6) + lane / (64 / L);   // this lane group's 64-column block
-    T* __restrict__ th = reinterpret_cast<T*>(J.thin) + ((long)b * (W >> 6) + blk) * ((long)nseg * K) * 4;
+    const gptr<T> th = (gptr<T>)(J.thin) + ((long)b * (W >> 6) + blk) * ((long)nseg * K) * 4;
 
     // per-column constants: the transform of the two ring entries, the synthesis weights at
     // q_lo-1 and q_lo over the interior off-diagonal a, and 1/a (zero on padding columns)
@@ -383,7 +389,7 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
         if constexpr (GEN) {
             const int si = special_in(m);
             if (si >= 0) {
-                const Rv v = *reinterpret_cast<const Rv*>(spec_hat + (long)si * LW);
+                const Rv v = *(gptr<const Rv>)(spec_hat + (long)si * LW);
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     qr[l] = fma(f[2 * l], v[l], qr[l]);
@@ -406,8 +412,8 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
         // would hold it for the store's whole latency)
         auto store_ck = [&](int s) {
             if (writes) {
-                *reinterpret_cast<Rv*>(ck + (long)(2 * s) * LW) = ckr;
-                *reinterpret_cast<Rv*>(ck + (long)(2 * s + 1) * LW) = cki;
+                *(gptr<Rv>)(ck + (long)(2 * s) * LW) = ckr;
+                *(gptr<Rv>)(ck + (long)(2 * s + 1) * LW) = cki;
             }
         };
         for (int s = 0; s < nseg - 1; ++s) {
@@ -459,8 +465,8 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
         }
         if (s > 0) stage(s - 1, sb ^ 1);
         if (s > 1) {
-            cqr = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 4) * LW);
-            cqi = *reinterpret_cast<const Rv*>(ck + (long)(2 * s - 3) * LW);
+            cqr = *(gptr<const Rv>)(ck + (long)(2 * s - 4) * LW);
+            cqi = *(gptr<const Rv>)(ck + (long)(2 * s - 3) * LW);
         }
         auto bwd = [&](auto gen_tag) {
             constexpr bool GEN = decltype(gen_tag)::value;
@@ -499,8 +505,8 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
                         Rv ore, oim;
 #pragma unroll
                         for (int l = 0; l < L; ++l) { ore[l] = xr[l] * ai[l]; oim[l] = xi[l] * ai[l]; }
-                        *reinterpret_cast<Rv*>(xs + (long)so * LW) = ore;
-                        *reinterpret_cast<Rv*>(xs + (long)(4 + so) * LW) = oim;
+                        *(gptr<Rv>)(xs + (long)so * LW) = ore;
+                        *(gptr<Rv>)(xs + (long)(4 + so) * LW) = oim;
                     }
                 }
             }
