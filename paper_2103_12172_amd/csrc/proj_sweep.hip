@@ -251,8 +251,12 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
     if (wbase >= W) return;   // a job narrower than the launch (uniform over the workgroup)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int bfirst = (grp - J.g0[lg_nw]) * NW;     // the group's first column (job-local)
-    const bool has_col = bfirst + wave < J.R;
-    const int b = min(bfirst + wave, J.R - 1);
+    // the job's column count in a register: read through J inside the loops it would be
+    // reloaded after every global store (which might alias the job table), and a scalar load
+    // pending there makes every wait for an LDS read a wait for all of them
+    const int R = J.R;
+    const bool has_col = bfirst + wave < R;
+    const int b = min(bfirst + wave, R - 1);
     const int c0 = wbase + lane * L;
     const bool live = c0 < W;              // lanes past W (a last wavefront of 64 columns when L > 1)
     const bool writes = live && has_col;
@@ -343,7 +347,7 @@ __global__ void __launch_bounds__(256) proj_sweep_kernel(const FusedJob* __restr
             if (o < NW * S::ring_bytes_per_col) {
                 const int wv = o / S::ring_bytes_per_col, rem = o - wv * S::ring_bytes_per_col;
                 const int i = rem / (4 * (int)sizeof(T)), part = rem - i * 4 * (int)sizeof(T);
-                const int bw = min(bfirst + wv, J.R - 1);
+                const int bw = min(bfirst + wv, R - 1);
                 const int m = min(mb + i, t);
                 lds_dma16(gring + (((long)bw * (n + 1) + m) * 4) * sizeof(T) + part, ring_buf + sb * S::ring_bytes);
             }
