@@ -354,13 +354,6 @@ __device__ inline double recip(double d) {
     return r;
 }
 
-// 1/d from the hardware estimate and one Newton step (the estimate's error is
-// squared: full FP64 accuracy for the pivots of the block factorisation)
-__device__ inline double recip1(double d) {
-    const double r = __builtin_amdgcn_rcp(d);
-    return fma(r, fma(-d, r, 1.0), r);
-}
-
 // Registers of lane (r, g) = (lane & 15, lane >> 4) in the elimination of a 16x16 diagonal
 // sub-block: the whole Hermitian block, M(r, 4g + q) for q < 4.
 struct ElimRegs {
