@@ -713,6 +713,7 @@ __device__ __attribute__((always_inline)) int chol64_lds(const double2* __restri
 //     refactorisation and little LDS, and many fit on a CU.
 __device__ __attribute__((always_inline)) inline void chol_diag_body(const double2* __restrict__ G, int nc, int kq, int nbq, double shift,
                                       double2* __restrict__ L, double2* __restrict__ Z, int* info, CholLds& s) {
+    if (nbq <= 0) return;   // an empty block (the factorisation reads element (kq, kq) unconditionally)
     const long dk = kq + (long)kq * nc;
     const int bad = chol64_lds(G + dk, nc, nbq, shift, s, L + dk, nc, Z + dk, nc);
     if (threadIdx.x == 0 && bad && info) atomicCAS(info, 0, kq + bad);
